@@ -1,0 +1,170 @@
+"""CPU oracle for generalized winding numbers -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It is independent of the GPU library
+(no shared sources, headers or constants) and implements, in plain FP64 C:
+
+* ``direct``     -- Eq. 2 with the per-triangle signed solid angle of Eq. 6,
+                    accumulated in double-double (ground truth, Sec. 6.2).
+* ``antipodal``  -- Eq. 10 / Alg. 1 with x0 = +z and exact quantised
+                    predicates with symbolic perturbation (Supp. Sec. 2.1).
+* ``chi``        -- signed crossings of the +z and -z rays (Sec. 3.2).
+* ``distance``   -- point-to-soup distance (Ericson 2005), to mask queries
+                    on or near the surface where w is undefined (Sec. 3.1).
+* ``boundary``   -- the cancelled directed boundary chain (Sec. 4.1).
+
+The C source is ``gwn_oracle.c``; ``build()`` compiles it with gcc into
+``liboracle.so`` next to it (no FP contraction, OpenMP over queries).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gwn_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_F32 = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_F64 = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_I32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_I64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_U8 = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+_VP = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (always when force=True)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        L.oracle_quant_params.argtypes = [_F32, _i64, _F64, _F64, ctypes.POINTER(_i32)]
+        L.oracle_quantize.argtypes = [_F32, _i64, _F64, _i32, _I64, _U8]
+        L.oracle_orient2d_sos.argtypes = [_i64] * 6
+        L.oracle_orient2d_sos.restype = ctypes.c_int
+        L.oracle_plane_sos.argtypes = [_I64, _I64, _I64, _I64]
+        L.oracle_plane_sos.restype = ctypes.c_int
+        L.oracle_boundary.argtypes = [_I32, _i64, ctypes.c_int, _VP, _VP, _i64]
+        L.oracle_boundary.restype = _i64
+        L.oracle_chi.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, ctypes.c_int, _I32, _I32]
+        L.oracle_antipodal.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, ctypes.c_int, _F64, _F64, _I32, _I32]
+        L.oracle_direct.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, _F64]
+        L.oracle_solid_angle.argtypes = [_F64, _F64, _F64, _F64]
+        L.oracle_solid_angle.restype = ctypes.c_double
+        L.oracle_distance.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, ctypes.c_double, _F64]
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _mesh(V, F):
+    V = np.ascontiguousarray(V, dtype=np.float32).reshape(-1, 3)
+    F = np.ascontiguousarray(F, dtype=np.int32).reshape(-1, 3)
+    return V, F
+
+
+def _pts(Q):
+    return np.ascontiguousarray(Q, dtype=np.float32).reshape(-1, 3)
+
+
+def quant_params(V):
+    """(bbox[6], lo[3], k) of the 30-bit fixed-point grid for vertex set V."""
+    V = np.ascontiguousarray(V, dtype=np.float32).reshape(-1, 3)
+    bbox = np.zeros(6)
+    lo = np.zeros(3)
+    k = _i32(0)
+    lib().oracle_quant_params(V, V.shape[0], bbox, lo, ctypes.byref(k))
+    return bbox, lo, int(k.value)
+
+
+def quantize(P, lo, k):
+    P = _pts(P)
+    q = np.zeros((P.shape[0], 3), dtype=np.int64)
+    ib = np.zeros(P.shape[0], dtype=np.uint8)
+    lib().oracle_quantize(P, P.shape[0], np.ascontiguousarray(lo, dtype=np.float64), int(k), q, ib)
+    return q, ib.astype(bool)
+
+
+def orient2d_sos(x0, y0, x1, y1, qx, qy) -> int:
+    return int(lib().oracle_orient2d_sos(int(x0), int(y0), int(x1), int(y1), int(qx), int(qy)))
+
+
+def plane_sos(p0, p1, p2, q) -> int:
+    a = [np.ascontiguousarray(v, dtype=np.int64) for v in (p0, p1, p2, q)]
+    return int(lib().oracle_plane_sos(*a))
+
+
+def boundary(F, cancel: bool = True):
+    F = np.ascontiguousarray(F, dtype=np.int32).reshape(-1, 3)
+    n = lib().oracle_boundary(F, F.shape[0], int(cancel), None, None, 0)
+    fr = np.zeros(max(n, 1), dtype=np.int32)
+    to = np.zeros(max(n, 1), dtype=np.int32)
+    lib().oracle_boundary(F, F.shape[0], int(cancel), fr.ctypes.data, to.ctypes.data, n)
+    return fr[:n], to[:n]
+
+
+def chi(V, F, Q, use_bins: bool = True):
+    """(chi along +z, chi along -z) per query, int32."""
+    V, F = _mesh(V, F)
+    Q = _pts(Q)
+    up = np.zeros(Q.shape[0], dtype=np.int32)
+    dn = np.zeros(Q.shape[0], dtype=np.int32)
+    lib().oracle_chi(V, V.shape[0], F, F.shape[0], Q, Q.shape[0], int(use_bins), up, dn)
+    return up, dn
+
+
+def antipodal(V, F, Q, cancel: bool = True, full: bool = False):
+    """O2: w per query (float64); with full=True also (S, chi_up, chi_down)."""
+    V, F = _mesh(V, F)
+    Q = _pts(Q)
+    n = Q.shape[0]
+    w = np.zeros(n)
+    S = np.zeros(n)
+    up = np.zeros(n, dtype=np.int32)
+    dn = np.zeros(n, dtype=np.int32)
+    lib().oracle_antipodal(V, V.shape[0], F, F.shape[0], Q, n, int(cancel), w, S, up, dn)
+    return (w, S, up, dn) if full else w
+
+
+def direct(V, F, Q):
+    """O1: direct sum of signed solid angles / 4 pi, double-double accumulation."""
+    V, F = _mesh(V, F)
+    Q = _pts(Q)
+    w = np.zeros(Q.shape[0])
+    lib().oracle_direct(V, V.shape[0], F, F.shape[0], Q, Q.shape[0], w)
+    return w
+
+
+def solid_angle(v0, v1, v2, p) -> float:
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (v0, v1, v2, p)]
+    return float(lib().oracle_solid_angle(*a))
+
+
+def distance(V, F, Q, cutoff: float):
+    """min(distance to the soup, cutoff) per query."""
+    V, F = _mesh(V, F)
+    Q = _pts(Q)
+    d = np.zeros(Q.shape[0])
+    lib().oracle_distance(V, V.shape[0], F, F.shape[0], Q, Q.shape[0], float(cutoff), d)
+    return d
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())

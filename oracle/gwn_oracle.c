@@ -1,0 +1,660 @@
+/*
+ * gwn_oracle.c -- CPU oracle for generalized winding numbers of triangle soups.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * headers, tables or constants with the GPU library; both implement the same
+ * published definitions independently.
+ *
+ * Contents (all arithmetic in IEEE double, compiled without FP contraction):
+ *
+ *   O1  oracle_direct      w(p) = (1/4pi) sum_T Area_{S^2_p}(T)          [Eq. 2]
+ *       per-triangle signed solid angle by the Van Oosterom-Strackee
+ *       formula [Eq. 6] written for unnormalised vectors (both atan2
+ *       arguments scaled by |a||b||c| > 0), accumulated in double-double
+ *       (the paper's accuracy study, Sec. 6.2, uses a double-double
+ *       accumulator for its ground truth).
+ *
+ *   O2  oracle_antipodal   w(p) = chi(x0) + (1/4pi) sum_{(a,b) in dM} Area(a^, b^, x1)
+ *       [Eq. 10, Alg. 1] with x0 = +z, x1 = -z (the robustness section,
+ *       Supp. Sec. 2.1, fixes d = (0,0,1)).  The boundary dM is the net
+ *       directed edge chain left after interior edges cancel (Sec. 4.1).
+ *       chi is the signed count of crossings of the +z ray, +1 when the ray
+ *       has positive dot product with the triangle normal (Sec. 3.2).
+ *       Crossing tests and the atan2 branch use exact integer predicates on
+ *       a 30-bit fixed-point copy of the input with symbolic perturbation of
+ *       the query, q_eps = q + (e1, e2, e3), 0 < e3 << e2 << e1
+ *       (Supp. Sec. 2.1).  The boundary term is the literal Alg. 1
+ *       expression on unit vectors, summed with Neumaier compensation.
+ *
+ *   O3  oracle_distance    unsigned point-to-soup distance (closest point on
+ *       a triangle by Voronoi-region classification, Ericson 2005,
+ *       "Real-Time Collision Detection", Sec. 5.1.5).  Used only to mask
+ *       queries that lie too close to the surface, where w is undefined.
+ *
+ * Readings taken where the paper is silent (each listed in the design notes):
+ *   - quantisation box: bbox expanded by 0.75 * max extent on every side,
+ *     scale 2^k with k the largest integer such that 2.5 * extent * 2^k
+ *     <= 2^30 - 1; q = rint((x - lo) * 2^k) in double.
+ *   - geometry of the boundary term for queries whose quantised x and y lie
+ *     in [0, 2^30 - 1]: x/y offsets from the quantised grid, z offset from
+ *     the raw input; the jump decisions come from the same integers.  Other
+ *     queries use raw offsets (no decision is needed there: the +z ray meets
+ *     no triangle and every boundary edge has D > 0).
+ *   - a boundary vertex whose quantised x/y coincide with the query's and
+ *     which lies above it sits on the ray; its edge terms take the limit
+ *     under the perturbation q_eps.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_QMAX ((int64_t)1073741823) /* 2^30 - 1 */
+#define OR_PI 3.14159265358979323846
+
+typedef __int128 i128;
+
+/* ------------------------------------------------------------------------ */
+/* quantisation                                                              */
+/* ------------------------------------------------------------------------ */
+
+int oracle_quant_params(const float* V, int64_t nv, double* bbox6, double* lo3, int32_t* k_out)
+{
+    double mn[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    for (int64_t i = 0; i < nv; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            double x = (double)V[3 * i + a];
+            if (i == 0 || x < mn[a]) mn[a] = x;
+            if (i == 0 || x > mx[a]) mx[a] = x;
+        }
+    }
+    double e = 0.0;
+    for (int a = 0; a < 3; ++a)
+        if (mx[a] - mn[a] > e) e = mx[a] - mn[a];
+    if (!(e > 0.0)) e = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        bbox6[a] = mn[a];
+        bbox6[3 + a] = mx[a];
+        lo3[a] = mn[a] - 0.75 * e;
+    }
+    double ext = 2.5 * e;
+    int k = 0;
+    if (ldexp(ext, 0) <= (double)OR_QMAX) {
+        while (ldexp(ext, k + 1) <= (double)OR_QMAX) ++k;
+    } else {
+        while (ldexp(ext, k) > (double)OR_QMAX) --k;
+    }
+    *k_out = k;
+    return 0;
+}
+
+static inline double or_qcoord(double x, double lo, double scale)
+{
+    return rint((x - lo) * scale);
+}
+
+/* quantise n points; returns in-box flag per point (x and y inside [0, 2^30-1]);
+ * z is clamped to [-1, 2^30]. */
+void oracle_quantize(const float* P, int64_t n, const double* lo3, int32_t k, int64_t* q_out, uint8_t* inbox)
+{
+    double scale = ldexp(1.0, k);
+    for (int64_t i = 0; i < n; ++i) {
+        double t[3];
+        for (int a = 0; a < 3; ++a) t[a] = or_qcoord((double)P[3 * i + a], lo3[a], scale);
+        int ib = (t[0] >= 0.0 && t[0] <= (double)OR_QMAX && t[1] >= 0.0 && t[1] <= (double)OR_QMAX);
+        double z = t[2];
+        if (!(z >= -1.0)) z = -1.0;
+        if (z > (double)(OR_QMAX + 1)) z = (double)(OR_QMAX + 1);
+        q_out[3 * i + 0] = ib ? (int64_t)t[0] : 0;
+        q_out[3 * i + 1] = ib ? (int64_t)t[1] : 0;
+        q_out[3 * i + 2] = (int64_t)z;
+        if (inbox) inbox[i] = (uint8_t)ib;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* exact predicates with symbolic perturbation (Supp. Sec. 2.1)              */
+/* ------------------------------------------------------------------------ */
+
+static inline int sgn64(int64_t v) { return (v > 0) - (v < 0); }
+static inline int sgn128(i128 v) { return (v > 0) - (v < 0); }
+
+/* Sign of the classification of q_eps = (qx+e1, qy+e2) against the directed
+ * edge (x0,y0)->(x1,y1): (x+e1-x0)(y0-y1) + (y+e2-y0)(x1-x0), evaluated by
+ * coefficient signs in lexicographic order: real part, e1, e2. */
+int oracle_orient2d_sos(int64_t x0, int64_t y0, int64_t x1, int64_t y1, int64_t qx, int64_t qy)
+{
+    int64_t real = (qx - x0) * (y0 - y1) + (qy - y0) * (x1 - x0);
+    if (real != 0) return sgn64(real);
+    if (y0 - y1 != 0) return sgn64(y0 - y1);
+    return sgn64(x1 - x0);
+}
+
+/* Which side of the supporting plane of triangle (p0,p1,p2) the perturbed
+ * query lies on: sign of f(q_eps) = n . (p0 - q_eps), n = (p1-p0) x (p2-p0),
+ * i.e. f - n_x e1 - n_y e2 - n_z e3 in lexicographic order. */
+int oracle_plane_sos(const int64_t* p0, const int64_t* p1, const int64_t* p2, const int64_t* q)
+{
+    int64_t ux = p1[0] - p0[0], uy = p1[1] - p0[1], uz = p1[2] - p0[2];
+    int64_t vx = p2[0] - p0[0], vy = p2[1] - p0[1], vz = p2[2] - p0[2];
+    int64_t nx = uy * vz - uz * vy;
+    int64_t ny = uz * vx - ux * vz;
+    int64_t nz = ux * vy - uy * vx;
+    i128 f = (i128)nx * (p0[0] - q[0]) + (i128)ny * (p0[1] - q[1]) + (i128)nz * (p0[2] - q[2]);
+    if (f != 0) return sgn128(f);
+    if (nx != 0) return -sgn64(nx);
+    if (ny != 0) return -sgn64(ny);
+    return -sgn64(nz);
+}
+
+/* Crossing of the vertical line through q_eps with triangle t.  Returns 0 on
+ * a miss; otherwise +1/-1 = sign s of the projected orientation, and *above
+ * tells whether the crossing lies on the +z side of the query. */
+static int or_line_hit(const int64_t* P0, const int64_t* P1, const int64_t* P2, const int64_t* q, int* above)
+{
+    int e0 = oracle_orient2d_sos(P0[0], P0[1], P1[0], P1[1], q[0], q[1]);
+    int e1 = oracle_orient2d_sos(P1[0], P1[1], P2[0], P2[1], q[0], q[1]);
+    int e2 = oracle_orient2d_sos(P2[0], P2[1], P0[0], P0[1], q[0], q[1]);
+    if (e0 == 0 || e0 != e1 || e0 != e2) return 0;
+    int64_t nz = (P1[0] - P0[0]) * (P2[1] - P0[1]) - (P1[1] - P0[1]) * (P2[0] - P0[0]);
+    int side = oracle_plane_sos(P0, P1, P2, q);
+    *above = (side == sgn64(nz));
+    return e0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* boundary chain (Sec. 4.1: interior edges cancel)                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { int64_t lo, hi; int sign; } or_edge;
+
+static int or_edge_cmp(const void* A, const void* B)
+{
+    const or_edge* a = (const or_edge*)A;
+    const or_edge* b = (const or_edge*)B;
+    if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;
+    if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;
+    return 0;
+}
+
+/* Net directed boundary of the 2-chain given by the triangles, by vertex
+ * index: for each unordered pair {u,v}, m = #(u->v) - #(v->u), emitted |m|
+ * times in the direction of its sign.  With cancel == 0 every triangle edge
+ * is emitted as is.  Writes up to cap edges; returns the total count. */
+int64_t oracle_boundary(const int32_t* F, int64_t nf, int cancel, int32_t* from, int32_t* to, int64_t cap)
+{
+    or_edge* E = (or_edge*)malloc(sizeof(or_edge) * (size_t)(3 * nf + 1));
+    int64_t ne = 0;
+    for (int64_t t = 0; t < nf; ++t) {
+        for (int c = 0; c < 3; ++c) {
+            int64_t u = F[3 * t + c], v = F[3 * t + (c + 1) % 3];
+            if (u == v) continue;
+            if (!cancel) {
+                if (ne < cap) { from[ne] = (int32_t)u; to[ne] = (int32_t)v; }
+                ++ne;
+                continue;
+            }
+            E[ne].lo = u < v ? u : v;
+            E[ne].hi = u < v ? v : u;
+            E[ne].sign = u < v ? 1 : -1;
+            ++ne;
+        }
+    }
+    if (!cancel) { free(E); return ne; }
+    qsort(E, (size_t)ne, sizeof(or_edge), or_edge_cmp);
+    int64_t nb = 0;
+    for (int64_t i = 0; i < ne;) {
+        int64_t j = i;
+        int64_t m = 0;
+        while (j < ne && E[j].lo == E[i].lo && E[j].hi == E[i].hi) { m += E[j].sign; ++j; }
+        int64_t cnt = m > 0 ? m : -m;
+        for (int64_t r = 0; r < cnt; ++r) {
+            if (nb < cap) {
+                from[nb] = (int32_t)(m > 0 ? E[i].lo : E[i].hi);
+                to[nb] = (int32_t)(m > 0 ? E[i].hi : E[i].lo);
+            }
+            ++nb;
+        }
+        i = j;
+    }
+    free(E);
+    return nb;
+}
+
+/* ------------------------------------------------------------------------ */
+/* uniform xy bins over the quantised triangles (oracle-side accelerator;    */
+/* a plain bucket grid, unrelated to any GPU structure)                      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t G;
+    int64_t x0, y0, span;      /* bin b covers [x0 + b*span/G, ...) */
+    int64_t* start;            /* G*G+1 */
+    int64_t* items;            /* triangle ids */
+} or_bins;
+
+static inline int64_t or_bin_of(const or_bins* B, int64_t v, int64_t origin)
+{
+    int64_t b = (int64_t)(((i128)(v - origin) * B->G) / B->span);
+    if (b < 0) b = 0;
+    if (b >= B->G) b = B->G - 1;
+    return b;
+}
+
+static void or_bins_build(or_bins* B, const int64_t* QV, const int32_t* F, int64_t nf)
+{
+    int64_t mnx = 0, mxx = 0, mny = 0, mxy = 0;
+    for (int64_t t = 0; t < nf; ++t)
+        for (int c = 0; c < 3; ++c) {
+            int64_t x = QV[3 * F[3 * t + c]], y = QV[3 * F[3 * t + c] + 1];
+            if ((t == 0 && c == 0) || x < mnx) mnx = x;
+            if ((t == 0 && c == 0) || x > mxx) mxx = x;
+            if ((t == 0 && c == 0) || y < mny) mny = y;
+            if ((t == 0 && c == 0) || y > mxy) mxy = y;
+        }
+    int64_t G = (int64_t)sqrt((double)nf / 2.0);
+    if (G < 1) G = 1;
+    if (G > 2048) G = 2048;
+    B->G = G;
+    B->x0 = mnx;
+    B->y0 = mny;
+    int64_t sx = mxx - mnx + 1, sy = mxy - mny + 1;
+    B->span = sx > sy ? sx : sy;
+    B->start = (int64_t*)calloc((size_t)(G * G + 1), sizeof(int64_t));
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t* fill = NULL;
+        if (pass == 1) {
+            for (int64_t i = 0; i < G * G; ++i) B->start[i + 1] += B->start[i];
+            B->items = (int64_t*)malloc(sizeof(int64_t) * (size_t)(B->start[G * G] + 1));
+            fill = (int64_t*)calloc((size_t)(G * G), sizeof(int64_t));
+        }
+        for (int64_t t = 0; t < nf; ++t) {
+            int64_t lx = 0, hx = 0, ly = 0, hy = 0;
+            for (int c = 0; c < 3; ++c) {
+                int64_t x = QV[3 * F[3 * t + c]], y = QV[3 * F[3 * t + c] + 1];
+                if (c == 0 || x < lx) lx = x;
+                if (c == 0 || x > hx) hx = x;
+                if (c == 0 || y < ly) ly = y;
+                if (c == 0 || y > hy) hy = y;
+            }
+            int64_t bx0 = or_bin_of(B, lx, B->x0), bx1 = or_bin_of(B, hx, B->x0);
+            int64_t by0 = or_bin_of(B, ly, B->y0), by1 = or_bin_of(B, hy, B->y0);
+            for (int64_t bx = bx0; bx <= bx1; ++bx)
+                for (int64_t by = by0; by <= by1; ++by) {
+                    int64_t b = bx * G + by;
+                    if (pass == 0) B->start[b + 1]++;
+                    else B->items[B->start[b] + fill[b]++] = t;
+                }
+        }
+        if (pass == 1) free(fill);
+    }
+}
+
+static void or_bins_free(or_bins* B) { free(B->start); free(B->items); }
+
+/* ------------------------------------------------------------------------ */
+/* chi: signed crossings along the vertical line through each query           */
+/* ------------------------------------------------------------------------ */
+
+static void or_quantize_vertices(const float* V, int64_t nv, const double* lo3, int32_t k, int64_t* QV)
+{
+    double scale = ldexp(1.0, k);
+    for (int64_t i = 0; i < nv; ++i)
+        for (int a = 0; a < 3; ++a) QV[3 * i + a] = (int64_t)or_qcoord((double)V[3 * i + a], lo3[a], scale);
+}
+
+static void or_chi_one(const int64_t* QV, const int32_t* F, int64_t nf, const or_bins* B,
+                       const int64_t* q, int inbox, int32_t* up, int32_t* down)
+{
+    int32_t cu = 0, cd = 0;
+    if (inbox) {
+        const int64_t* list = NULL;
+        int64_t n = nf;
+        if (B) {
+            if (q[0] < B->x0 || q[0] >= B->x0 + B->span || q[1] < B->y0 || q[1] >= B->y0 + B->span) {
+                n = 0;
+            } else {
+                int64_t b = or_bin_of(B, q[0], B->x0) * B->G + or_bin_of(B, q[1], B->y0);
+                list = B->items + B->start[b];
+                n = B->start[b + 1] - B->start[b];
+            }
+        }
+        for (int64_t ii = 0; ii < n; ++ii) {
+            int64_t t = list ? list[ii] : ii;
+            const int64_t* P0 = QV + 3 * F[3 * t];
+            const int64_t* P1 = QV + 3 * F[3 * t + 1];
+            const int64_t* P2 = QV + 3 * F[3 * t + 2];
+            int above = 0;
+            int s = or_line_hit(P0, P1, P2, q, &above);
+            if (!s) continue;
+            if (above) cu += s;
+            else cd -= s;
+        }
+    }
+    *up = cu;
+    *down = cd;
+}
+
+/* chi(+z) and chi(-z) for every query; use_bins = 0 tests every triangle. */
+void oracle_chi(const float* V, int64_t nv, const int32_t* F, int64_t nf, const float* Q, int64_t nq,
+                int use_bins, int32_t* chi_up, int32_t* chi_down)
+{
+    double bbox[6], lo[3];
+    int32_t k;
+    oracle_quant_params(V, nv, bbox, lo, &k);
+    int64_t* QV = (int64_t*)malloc(sizeof(int64_t) * (size_t)(3 * nv + 3));
+    or_quantize_vertices(V, nv, lo, k, QV);
+    or_bins B;
+    int have_bins = use_bins && nf > 0;
+    if (have_bins) or_bins_build(&B, QV, F, nf);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < nq; ++i) {
+        int64_t q[3];
+        uint8_t ib;
+        oracle_quantize(Q + 3 * i, 1, lo, k, q, &ib);
+        int32_t u, d;
+        or_chi_one(QV, F, nf, have_bins ? &B : NULL, q, ib, &u, &d);
+        chi_up[i] = u;
+        if (chi_down) chi_down[i] = d;
+    }
+    if (have_bins) or_bins_free(&B);
+    free(QV);
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2: antipodal evaluation (Eq. 10, Alg. 1)                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Alg. 1 SignedSphericalTriArea(A, B, x1) with x1 = (0,0,-1), written out:
+ * N = A . (B x x1), D = 1 + A.B + A.x1 + B.x1. Returns (N, D). */
+static inline void or_alg1_nd(const double* A, const double* B, double* N, double* D)
+{
+    const double x1[3] = {0.0, 0.0, -1.0};
+    double c[3] = {B[1] * x1[2] - B[2] * x1[1], B[2] * x1[0] - B[0] * x1[2], B[0] * x1[1] - B[1] * x1[0]};
+    *N = A[0] * c[0] + A[1] * c[1] + A[2] * c[2];
+    *D = 1.0 + (A[0] * B[0] + A[1] * B[1] + A[2] * B[2]) + (A[0] * x1[0] + A[1] * x1[1] + A[2] * x1[2]) +
+         (B[0] * x1[0] + B[1] * x1[1] + B[2] * x1[2]);
+}
+
+/* Limit of 2*atan2(N, D) for an edge whose first (first_on=1) or second
+ * endpoint lies on the +z ray, as the query moves to q_eps: that endpoint's
+ * x/y offset becomes (-e1, -e2).  o = x/y offset of the other endpoint. */
+static double or_axis_limit(int first_on, double ox, double oy)
+{
+    if (ox == 0.0 && oy == 0.0) return 0.0;
+    if (first_on) {
+        /* N ~ e1*oy - e2*ox, D ~ -e1*ox - e2*oy */
+        if (oy != 0.0) return 2.0 * atan2(oy, -ox);
+        return ox > 0.0 ? -2.0 * OR_PI : 0.0;
+    }
+    /* N ~ -e1*oy + e2*ox, D ~ -e1*ox - e2*oy */
+    if (oy != 0.0) return 2.0 * atan2(-oy, -ox);
+    return ox > 0.0 ? 2.0 * OR_PI : 0.0;
+}
+
+typedef struct {
+    const float* V;
+    const int64_t* QV;
+    const int32_t* from;
+    const int32_t* to;
+    int64_t nb;
+    double cell;
+} or_bdry;
+
+static double or_boundary_sum(const or_bdry* Bd, const float* p, const int64_t* q, int inbox)
+{
+    double s = 0.0, comp = 0.0; /* Neumaier */
+    for (int64_t e = 0; e < Bd->nb; ++e) {
+        int32_t ia = Bd->from[e], ib = Bd->to[e];
+        double ra[3], rb[3];
+        const int64_t* qa = Bd->QV + 3 * ia;
+        const int64_t* qb = Bd->QV + 3 * ib;
+        if (inbox) {
+            ra[0] = (double)(qa[0] - q[0]) * Bd->cell;
+            ra[1] = (double)(qa[1] - q[1]) * Bd->cell;
+            rb[0] = (double)(qb[0] - q[0]) * Bd->cell;
+            rb[1] = (double)(qb[1] - q[1]) * Bd->cell;
+        } else {
+            ra[0] = (double)Bd->V[3 * ia] - (double)p[0];
+            ra[1] = (double)Bd->V[3 * ia + 1] - (double)p[1];
+            rb[0] = (double)Bd->V[3 * ib] - (double)p[0];
+            rb[1] = (double)Bd->V[3 * ib + 1] - (double)p[1];
+        }
+        ra[2] = (double)Bd->V[3 * ia + 2] - (double)p[2];
+        rb[2] = (double)Bd->V[3 * ib + 2] - (double)p[2];
+        int on_a = inbox && qa[0] == q[0] && qa[1] == q[1] && ra[2] > 0.0;
+        int on_b = inbox && qb[0] == q[0] && qb[1] == q[1] && rb[2] > 0.0;
+        double term;
+        if (on_a && on_b) {
+            term = 0.0;
+        } else if (on_a) {
+            term = or_axis_limit(1, rb[0], rb[1]);
+        } else if (on_b) {
+            term = or_axis_limit(0, ra[0], ra[1]);
+        } else {
+            double la = sqrt(ra[0] * ra[0] + ra[1] * ra[1] + ra[2] * ra[2]);
+            double lb = sqrt(rb[0] * rb[0] + rb[1] * rb[1] + rb[2] * rb[2]);
+            double A[3] = {ra[0] / la, ra[1] / la, ra[2] / la};
+            double B[3] = {rb[0] / lb, rb[1] / lb, rb[2] / lb};
+            double N, D;
+            or_alg1_nd(A, B, &N, &D);
+            if (inbox && D <= 0.0) {
+                /* atan2 jumps where N changes sign with D < 0; N carries the
+                 * sign of -orient2d(a, b, q_eps), the same polynomial as the
+                 * ray-crossing edge test (Supp. Sec. 2.1). */
+                int o = oracle_orient2d_sos(qa[0], qa[1], qb[0], qb[1], q[0], q[1]);
+                if (o != 0) N = (o > 0 ? -1.0 : 1.0) * fabs(N);
+            }
+            term = 2.0 * atan2(N, D);
+        }
+        double t = s + term;
+        if (fabs(s) >= fabs(term)) comp += (s - t) + term;
+        else comp += (term - t) + s;
+        s = t;
+    }
+    return s + comp;
+}
+
+/* O2 for every query.  cancel = 0 evaluates all 3F triangle edges instead of
+ * the cancelled boundary chain.  w_out[i] = chi_up + S/(4 pi); s_out (nullable)
+ * receives S; chi_up/chi_down (nullable) the crossing counts. */
+int oracle_antipodal(const float* V, int64_t nv, const int32_t* F, int64_t nf, const float* Q, int64_t nq,
+                     int cancel, double* w_out, double* s_out, int32_t* chi_up, int32_t* chi_down)
+{
+    double bbox[6], lo[3];
+    int32_t k;
+    oracle_quant_params(V, nv, bbox, lo, &k);
+    int64_t* QV = (int64_t*)malloc(sizeof(int64_t) * (size_t)(3 * nv + 3));
+    or_quantize_vertices(V, nv, lo, k, QV);
+    int64_t nb = oracle_boundary(F, nf, cancel, NULL, NULL, 0);
+    int32_t* from = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nb + 1));
+    int32_t* to = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nb + 1));
+    oracle_boundary(F, nf, cancel, from, to, nb);
+    or_bins B;
+    int have_bins = nf > 0;
+    if (have_bins) or_bins_build(&B, QV, F, nf);
+    or_bdry Bd = {V, QV, from, to, nb, ldexp(1.0, -k)};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nq; ++i) {
+        int64_t q[3];
+        uint8_t ib;
+        oracle_quantize(Q + 3 * i, 1, lo, k, q, &ib);
+        int32_t u, d;
+        or_chi_one(QV, F, nf, have_bins ? &B : NULL, q, ib, &u, &d);
+        double S = or_boundary_sum(&Bd, Q + 3 * i, q, ib);
+        w_out[i] = (double)u + S / (4.0 * OR_PI);
+        if (s_out) s_out[i] = S;
+        if (chi_up) chi_up[i] = u;
+        if (chi_down) chi_down[i] = d;
+    }
+    if (have_bins) or_bins_free(&B);
+    free(from);
+    free(to);
+    free(QV);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O1: direct sum of signed solid angles (Eq. 2, Eq. 6), double-double sum    */
+/* ------------------------------------------------------------------------ */
+
+static inline void or_two_sum(double a, double b, double* s, double* e)
+{
+    double x = a + b;
+    double bv = x - a;
+    double av = x - bv;
+    *e = (a - av) + (b - bv);
+    *s = x;
+}
+
+/* signed solid angle of one triangle seen from p: 2 atan2(a.(b x c),
+ * |a||b||c| + (a.b)|c| + (a.c)|b| + (b.c)|a|) with a, b, c = vertices - p. */
+double oracle_solid_angle(const double* v0, const double* v1, const double* v2, const double* p)
+{
+    double a[3], b[3], c[3];
+    for (int i = 0; i < 3; ++i) { a[i] = v0[i] - p[i]; b[i] = v1[i] - p[i]; c[i] = v2[i] - p[i]; }
+    double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    double lb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    double lc = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    double bxc[3] = {b[1] * c[2] - b[2] * c[1], b[2] * c[0] - b[0] * c[2], b[0] * c[1] - b[1] * c[0]};
+    double num = a[0] * bxc[0] + a[1] * bxc[1] + a[2] * bxc[2];
+    double ab = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    double ac = a[0] * c[0] + a[1] * c[1] + a[2] * c[2];
+    double bc = b[0] * c[0] + b[1] * c[1] + b[2] * c[2];
+    double den = la * lb * lc + ab * lc + ac * lb + bc * la;
+    return 2.0 * atan2(num, den);
+}
+
+void oracle_direct(const float* V, int64_t nv, const int32_t* F, int64_t nf, const float* Q, int64_t nq, double* w_out)
+{
+    (void)nv;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < nq; ++i) {
+        double p[3] = {(double)Q[3 * i], (double)Q[3 * i + 1], (double)Q[3 * i + 2]};
+        double hi = 0.0, lo = 0.0;
+        for (int64_t t = 0; t < nf; ++t) {
+            double v[3][3];
+            for (int c = 0; c < 3; ++c)
+                for (int a = 0; a < 3; ++a) v[c][a] = (double)V[3 * F[3 * t + c] + a];
+            double om = oracle_solid_angle(v[0], v[1], v[2], p);
+            double s, e;
+            or_two_sum(hi, om, &s, &e);
+            lo += e;
+            or_two_sum(s, lo, &hi, &lo);
+        }
+        w_out[i] = (hi + lo) / (4.0 * OR_PI);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O3: unsigned distance to the soup (Ericson 2005, Sec. 5.1.5)               */
+/* ------------------------------------------------------------------------ */
+
+static double or_point_tri_dist2(const double* p, const double* a, const double* b, const double* c)
+{
+    double ab[3], ac[3], ap[3], q[3];
+    for (int i = 0; i < 3; ++i) { ab[i] = b[i] - a[i]; ac[i] = c[i] - a[i]; ap[i] = p[i] - a[i]; }
+#define DOT(u, v) ((u)[0] * (v)[0] + (u)[1] * (v)[1] + (u)[2] * (v)[2])
+    double d1 = DOT(ab, ap), d2 = DOT(ac, ap);
+    if (d1 <= 0.0 && d2 <= 0.0) { for (int i = 0; i < 3; ++i) q[i] = a[i]; goto done; }
+    {
+        double bp[3];
+        for (int i = 0; i < 3; ++i) bp[i] = p[i] - b[i];
+        double d3 = DOT(ab, bp), d4 = DOT(ac, bp);
+        if (d3 >= 0.0 && d4 <= d3) { for (int i = 0; i < 3; ++i) q[i] = b[i]; goto done; }
+        double vc = d1 * d4 - d3 * d2;
+        if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+            double v = d1 / (d1 - d3);
+            for (int i = 0; i < 3; ++i) q[i] = a[i] + v * ab[i];
+            goto done;
+        }
+        double cp[3];
+        for (int i = 0; i < 3; ++i) cp[i] = p[i] - c[i];
+        double d5 = DOT(ab, cp), d6 = DOT(ac, cp);
+        if (d6 >= 0.0 && d5 <= d6) { for (int i = 0; i < 3; ++i) q[i] = c[i]; goto done; }
+        double vb = d5 * d2 - d1 * d6;
+        if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+            double w = d2 / (d2 - d6);
+            for (int i = 0; i < 3; ++i) q[i] = a[i] + w * ac[i];
+            goto done;
+        }
+        double va = d3 * d6 - d5 * d4;
+        if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+            double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+            for (int i = 0; i < 3; ++i) q[i] = b[i] + w * (c[i] - b[i]);
+            goto done;
+        }
+        double den = va + vb + vc;
+        if (den == 0.0) { /* degenerate triangle: nearest of its vertices/edges */
+            double best = 1e300;
+            const double* P[3] = {a, b, c};
+            for (int e = 0; e < 3; ++e) {
+                const double* u = P[e];
+                const double* w = P[(e + 1) % 3];
+                double d[3] = {w[0] - u[0], w[1] - u[1], w[2] - u[2]};
+                double up[3] = {p[0] - u[0], p[1] - u[1], p[2] - u[2]};
+                double dd = DOT(d, d);
+                double t = dd > 0.0 ? DOT(up, d) / dd : 0.0;
+                if (t < 0.0) t = 0.0;
+                if (t > 1.0) t = 1.0;
+                double r[3] = {up[0] - t * d[0], up[1] - t * d[1], up[2] - t * d[2]};
+                double r2 = DOT(r, r);
+                if (r2 < best) best = r2;
+            }
+            return best;
+        }
+        double v = vb / den, w = vc / den;
+        for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i] * v + ac[i] * w;
+    }
+done:
+    {
+        double d[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+        return DOT(d, d);
+    }
+#undef DOT
+}
+
+/* distance from each query to the nearest triangle, computed exactly for
+ * triangles whose bounding box expanded by `cutoff` contains the query; the
+ * result is min(distance, cutoff) (enough to mask near-surface queries). */
+void oracle_distance(const float* V, int64_t nv, const int32_t* F, int64_t nf, const float* Q, int64_t nq,
+                     double cutoff, double* d_out)
+{
+    (void)nv;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < nq; ++i) {
+        double p[3] = {(double)Q[3 * i], (double)Q[3 * i + 1], (double)Q[3 * i + 2]};
+        double best = cutoff * cutoff;
+        for (int64_t t = 0; t < nf; ++t) {
+            double v[3][3];
+            int skip = 0;
+            for (int a = 0; a < 3 && !skip; ++a) {
+                double lo = 1e300, hi = -1e300;
+                for (int c = 0; c < 3; ++c) {
+                    double x = (double)V[3 * F[3 * t + c] + a];
+                    v[c][a] = x;
+                    if (x < lo) lo = x;
+                    if (x > hi) hi = x;
+                }
+                if (p[a] < lo - cutoff || p[a] > hi + cutoff) skip = 1;
+            }
+            if (skip) continue;
+            double d2 = or_point_tri_dist2(p, v[0], v[1], v[2]);
+            if (d2 < best) best = d2;
+        }
+        d_out[i] = sqrt(best);
+    }
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
