@@ -1,0 +1,134 @@
+/*
+ * gwn.h -- C ABI of the MI355X (gfx950) generalized-winding-number library.
+ *
+ * Computes w_M(p), the generalized winding number of a triangle soup M at
+ * query points p (Eq. 1: the signed solid angle of M seen from p over 4 pi),
+ * by the antipodal method (Eq. 10, Alg. 1):
+ *
+ *     w(p) = chi(x0) + (1/4pi) * sum_{(a,b) in dM} Area_{S^2}(a^, b^, x1)
+ *
+ * with ray direction x0 = +z and its antipode x1 = -z.  chi(x0) is the signed
+ * number of crossings of the ray from p along +z with the soup, +1 where the
+ * ray has positive dot product with the triangle normal (Sec. 3.2); dM is the
+ * directed boundary chain left after interior edges cancel (Sec. 4.1).
+ *
+ * Robustness (Supp. Sec. 2.1): every decision that can change w by an
+ * integer -- whether the ray crosses a triangle, on which side of the
+ * triangle's plane the query lies, and the branch of atan2 where a boundary
+ * edge passes over the ray -- is taken with exact integer predicates on a
+ * 30-bit fixed-point copy of the input, with the query symbolically
+ * perturbed to q + (e1, e2, e3), 0 < e3 << e2 << e1.  The crossing counts
+ * are therefore exact and deterministic for every query, including queries
+ * on the surface.
+ *
+ * Conventions shared by all calls
+ *   - All array pointers are DEVICE pointers on the current HIP device,
+ *     owned by the caller.  The library owns mesh handles and their device
+ *     memory.  `stream` is a hipStream_t (NULL = default stream); query calls
+ *     are asynchronous on it.
+ *   - Triangle (v0, v1, v2) has normal (v1 - v0) x (v2 - v0); w > 0 on the
+ *     side opposite the normal, so w = +1 inside a closed mesh whose normals
+ *     point outward.
+ *   - Strided coordinates: element i of a coordinate array X is X[i*stride]
+ *     (stride 1 for separate arrays; stride 3 with x = P, y = P+1, z = P+2
+ *     for an interleaved (n, 3) array).
+ *   - Errors never cross the ABI as exceptions; every call returns a
+ *     gwn_status and gwn_last_error() gives a message for the calling thread.
+ */
+#ifndef GWN_H
+#define GWN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GWN_OK = 0,
+    GWN_E_INVALID = 1,     /* bad argument, out-of-range index, non-finite coordinate */
+    GWN_E_OOM = 2,         /* device allocation failed */
+    GWN_E_HIP = 3,         /* a HIP runtime call failed */
+    GWN_E_UNSUPPORTED = 4  /* valid request the library does not implement */
+} gwn_status;
+
+typedef enum {
+    GWN_PREC_FP32 = 0,     /* FP32 geometry arithmetic, exact predicates, FP64 accumulation; float output */
+    GWN_PREC_FP64 = 1      /* FP64 geometry arithmetic, exact predicates; double output */
+} gwn_precision;
+
+typedef struct gwn_mesh_s* gwn_mesh;
+
+typedef struct {
+    int64_t nv, nf;          /* vertices and triangles given to gwn_build_mesh */
+    int64_t nboundary;       /* directed boundary edges after cancellation (B) */
+    int64_t nloops;          /* closed boundary loops the edges were chained into */
+    int64_t nnodes;          /* internal BVH nodes (nf - 1, or 0) */
+    int32_t bvh_depth;       /* deepest leaf of the BVH (root = 0) */
+    int32_t qshift;          /* fixed-point scale is 2^qshift */
+    double bbox[6];          /* min xyz, max xyz of the vertices */
+    double qlo[3];           /* fixed-point origin: q = rint((x - qlo) * 2^qshift) */
+    double build_ms;         /* wall time of the build */
+} gwn_mesh_info;
+
+/*
+ * gwn_build_mesh -- ingest a soup, quantise it, extract and chain the boundary,
+ * and build the BVH, all on the device (precomputation; Sec. 6.1 excludes it
+ * from query timings).
+ *
+ *   vx, vy, vz, vstride, nv : vertex coordinates (float32), strided as above.
+ *   tri                     : nf*3 int32 vertex indices, row-major.
+ *   stream                  : work is enqueued on it; the call synchronises it
+ *                             before returning (it reads back sizes).
+ *   out                     : receives the new handle (NULL on failure).
+ *
+ * Fixed-point grid: with bbox [lo, hi] and e = max extent (1 if zero), the
+ * origin is lo - 0.75 e per axis and the scale 2^k with k the largest integer
+ * such that 2.5 e 2^k <= 2^30 - 1; q = rint((x - origin) 2^k) in FP64.
+ * Boundary chain by vertex index: net multiplicity m(u,v) = #(u->v) - #(v->u),
+ * emitted |m| times; triangles with a repeated index contribute nothing.
+ * Errors: GWN_E_INVALID for nv < 0, nf < 0, null pointers with n > 0,
+ * indices outside [0, nv), non-finite coordinates or nv >= 2^31.
+ */
+gwn_status gwn_build_mesh(const float* vx, const float* vy, const float* vz, int64_t vstride, int64_t nv,
+                          const int32_t* tri, int64_t nf, void* stream, gwn_mesh* out);
+
+/* Host-side copy of the mesh's sizes and fixed-point parameters. */
+gwn_status gwn_mesh_info_get(gwn_mesh m, gwn_mesh_info* out);
+
+/* Release the handle and its device memory (NULL is a no-op). */
+gwn_status gwn_mesh_destroy(gwn_mesh m);
+
+/*
+ * gwn_query_batch -- w for nq arbitrary points (Alg. 1 per point).
+ *
+ *   qx, qy, qz, qstride, nq : query coordinates (float32), strided.
+ *   prec                    : GWN_PREC_FP32 (w_out is float*) or GWN_PREC_FP64 (double*).
+ *   w_out                   : nq results.
+ *   chi_out                 : nullable; nq int32 crossing counts along +z.
+ * nq == 0 is a no-op.  Queries on the surface get a well-defined chi; their w is
+ * not meaningful (w is undefined on M).
+ */
+gwn_status gwn_query_batch(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                           int64_t nq, int32_t prec, void* w_out, int32_t* chi_out, void* stream);
+
+/*
+ * gwn_query_grid -- w on a cell-centred regular grid, reusing one ray per
+ * (x, y) column for all its points (Sec. 4.3.1, ray reuse).
+ *
+ *   origin, spacing, dims : host arrays of 3; point (i,j,k) is
+ *                           float(origin + (idx + 0.5) * spacing) per axis,
+ *                           evaluated in FP64 then rounded once.
+ *   w_out, chi_out        : dims[0]*dims[1]*dims[2] results at (i*ny + j)*nz + k.
+ */
+gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacing, const int64_t* dims,
+                          int32_t prec, void* w_out, int32_t* chi_out, void* stream);
+
+const char* gwn_status_str(gwn_status s);
+const char* gwn_last_error(void);   /* thread-local; "" if none */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWN_H */

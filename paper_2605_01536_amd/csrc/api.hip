@@ -1,0 +1,175 @@
+// api.hip -- extern "C" entry points declared in include/gwn.h: argument
+// validation, handle lifetime and thread-local error reporting.  All compute
+// happens in the kernels of build.hip and query.hip.
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+
+#include "gwn_mesh.h"
+
+namespace gwn {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+}  // namespace gwn
+
+namespace {
+
+void release(gwn_mesh_s* m) {
+    if (!m) return;
+    (void)hipFree(m->nodes);
+    (void)hipFree(m->tris);
+    (void)hipFree(m->bverts);
+    (void)hipFree(m->loop_off);
+    delete m;
+}
+
+gwn_status check_mesh(gwn_mesh m, const char* fn) {
+    if (!m) {
+        gwn::set_error("%s: null mesh handle", fn);
+        return GWN_E_INVALID;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != m->device) {
+        gwn::set_error("%s: mesh was built on device %d, current device is %d", fn, m->device, dev);
+        return GWN_E_INVALID;
+    }
+    return GWN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gwn_status gwn_build_mesh(const float* vx, const float* vy, const float* vz, int64_t vstride, int64_t nv,
+                          const int32_t* tri, int64_t nf, void* stream, gwn_mesh* out) {
+    gwn::clear_error();
+    if (!out) {
+        gwn::set_error("gwn_build_mesh: out is null");
+        return GWN_E_INVALID;
+    }
+    *out = nullptr;
+    if (nv < 0 || nf < 0 || vstride < 1 || nv >= (1ll << 31) || nf >= (1ll << 29)) {
+        gwn::set_error("gwn_build_mesh: bad sizes nv=%lld nf=%lld vstride=%lld", (long long)nv, (long long)nf,
+                       (long long)vstride);
+        return GWN_E_INVALID;
+    }
+    if ((nv > 0 && (!vx || !vy || !vz)) || (nf > 0 && !tri)) {
+        gwn::set_error("gwn_build_mesh: null array with nonzero size");
+        return GWN_E_INVALID;
+    }
+    if (nf > 0 && nv == 0) {
+        gwn::set_error("gwn_build_mesh: triangles given without vertices");
+        return GWN_E_INVALID;
+    }
+    gwn_mesh_s* m = new (std::nothrow) gwn_mesh_s();
+    if (!m) {
+        gwn::set_error("gwn_build_mesh: host allocation failed");
+        return GWN_E_OOM;
+    }
+    gwn_status s = gwn::build_mesh(vx, vy, vz, vstride, nv, tri, nf, (hipStream_t)stream, m);
+    if (s == GWN_OK && m->depth > gwn::kLdsStack - 1) {
+        gwn::set_error("gwn_build_mesh: BVH depth %d exceeds the traversal stack", m->depth);
+        s = GWN_E_UNSUPPORTED;
+    }
+    if (s != GWN_OK) {
+        release(m);
+        return s;
+    }
+    *out = m;
+    return GWN_OK;
+}
+
+gwn_status gwn_mesh_info_get(gwn_mesh m, gwn_mesh_info* out) {
+    gwn::clear_error();
+    if (!m || !out) {
+        gwn::set_error("gwn_mesh_info_get: null argument");
+        return GWN_E_INVALID;
+    }
+    out->nv = m->nv;
+    out->nf = m->nf;
+    out->nboundary = m->nb;
+    out->nloops = m->nloops;
+    out->nnodes = m->nnodes;
+    out->bvh_depth = m->depth;
+    out->qshift = m->g.k;
+    for (int a = 0; a < 6; ++a) out->bbox[a] = m->bbox[a];
+    for (int a = 0; a < 3; ++a) out->qlo[a] = m->g.lo[a];
+    out->build_ms = m->build_ms;
+    return GWN_OK;
+}
+
+gwn_status gwn_mesh_destroy(gwn_mesh m) {
+    gwn::clear_error();
+    release(m);
+    return GWN_OK;
+}
+
+gwn_status gwn_query_batch(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride, int64_t nq,
+                           int32_t prec, void* w_out, int32_t* chi_out, void* stream) {
+    gwn::clear_error();
+    gwn_status s = check_mesh(m, "gwn_query_batch");
+    if (s != GWN_OK) return s;
+    if (nq < 0 || qstride < 1 || (prec != GWN_PREC_FP32 && prec != GWN_PREC_FP64)) {
+        gwn::set_error("gwn_query_batch: bad nq=%lld, qstride=%lld or precision %d", (long long)nq,
+                       (long long)qstride, (int)prec);
+        return GWN_E_INVALID;
+    }
+    if (nq == 0) return GWN_OK;
+    if (!qx || !qy || !qz || !w_out) {
+        gwn::set_error("gwn_query_batch: null query or output array");
+        return GWN_E_INVALID;
+    }
+    if (nq > (1ll << 40)) {
+        gwn::set_error("gwn_query_batch: nq too large");
+        return GWN_E_INVALID;
+    }
+    return gwn::query_batch(m, qx, qy, qz, qstride, nq, prec, w_out, chi_out, (hipStream_t)stream);
+}
+
+gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacing, const int64_t* dims, int32_t prec,
+                          void* w_out, int32_t* chi_out, void* stream) {
+    gwn::clear_error();
+    gwn_status s = check_mesh(m, "gwn_query_grid");
+    if (s != GWN_OK) return s;
+    if (!origin || !spacing || !dims || (prec != GWN_PREC_FP32 && prec != GWN_PREC_FP64)) {
+        gwn::set_error("gwn_query_grid: null grid description or bad precision");
+        return GWN_E_INVALID;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (dims[a] < 0 || dims[a] > (1ll << 20) || !std::isfinite(origin[a]) || !std::isfinite(spacing[a])) {
+            gwn::set_error("gwn_query_grid: bad dims/origin/spacing on axis %d", a);
+            return GWN_E_INVALID;
+        }
+    }
+    if (dims[0] * dims[1] * dims[2] == 0) return GWN_OK;
+    if (!w_out) {
+        gwn::set_error("gwn_query_grid: null output array");
+        return GWN_E_INVALID;
+    }
+    return gwn::query_grid(m, origin, spacing, dims, prec, w_out, chi_out, (hipStream_t)stream);
+}
+
+const char* gwn_status_str(gwn_status s) {
+    switch (s) {
+        case GWN_OK: return "ok";
+        case GWN_E_INVALID: return "invalid argument";
+        case GWN_E_OOM: return "out of device memory";
+        case GWN_E_HIP: return "HIP runtime error";
+        case GWN_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* gwn_last_error(void) { return gwn::g_err; }
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// gwn_mesh.h -- host-side mesh handle and internal entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <string>
+
+#include "../../include/gwn.h"
+#include "gwn_internal.h"
+
+struct gwn_mesh_s {
+    int device = 0;
+    int64_t nv = 0, nf = 0, nb = 0, nloops = 0, nnodes = 0;
+    int depth = 0;
+    double build_ms = 0.0;
+    double bbox[6] = {0, 0, 0, 0, 0, 0};
+    gwn::QGrid g{};
+    int root = gwn::kNoRoot;
+    // device memory owned by the handle
+    gwn::Node* nodes = nullptr;
+    gwn::TriQ* tris = nullptr;
+    gwn::BVert* bverts = nullptr;
+    int* loop_off = nullptr;
+
+    gwn::MeshView view() const {
+        gwn::MeshView v;
+        v.nodes = nodes;
+        v.tris = tris;
+        v.bverts = bverts;
+        v.loop_off = loop_off;
+        v.nloops = (int)nloops;
+        v.nf = (int)nf;
+        v.root = root;
+        v.pad = 0;
+        v.g = g;
+        return v;
+    }
+};
+
+namespace gwn {
+
+// thread-local error reporting shared by all translation units
+void set_error(const char* fmt, ...);
+void clear_error();
+
+gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t vstride, int64_t nv,
+                      const int32_t* tri, int64_t nf, hipStream_t stream, gwn_mesh_s* m);
+
+gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                       int64_t nq, int prec, void* w_out, int32_t* chi_out, hipStream_t stream);
+
+gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims,
+                      int prec, void* w_out, int32_t* chi_out, hipStream_t stream);
+
+// Fixed-point grid rule (host, FP64): origin = bbox_lo - 0.75 e, scale 2^k with
+// k the largest integer such that 2.5 e 2^k <= 2^30 - 1 (e = max extent, 1 if 0).
+QGrid make_qgrid(const double bbox[6]);
+
+}  // namespace gwn
+
+#define GWN_HIP_TRY(expr)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            gwn::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                           __LINE__);                                                      \
+            return e_ == hipErrorOutOfMemory ? GWN_E_OOM : GWN_E_HIP;                      \
+        }                                                                                  \
+    } while (0)

@@ -1,0 +1,422 @@
+// query.hip -- query kernels of the antipodal method (Eq. 10, Alg. 1):
+//
+//   w(p) = chi(+z) + (1/2pi) * sum over boundary edges (a,b) of atan2(N, D)
+//
+// where, with r = v - p, rho^2 = r_x^2 + r_y^2, l = |r| and
+// s = l - r_z = rho^2 / (l + r_z) (the second form for r_z > 0),
+//
+//   N = r_a,y r_b,x - r_a,x r_b,y          (= l_a l_b  A . (B x x1))
+//   D = s_a s_b + r_a,x r_b,x + r_a,y r_b,y (= l_a l_b (1 + A.B + A.x1 + B.x1))
+//
+// for x1 = -z.  Scaling both atan2 arguments by l_a l_b > 0 and writing D
+// through s (an exact algebraic rearrangement) keeps FP32 accurate when a
+// boundary vertex is close to the ray above the query.  Offsets are in
+// fixed-point cell units: x and y from the quantised grid (exact integers),
+// z from the input scaled by 2^k.  The atan2 branch where an edge passes over
+// the ray (D <= 0) takes the sign of N from the exact perturbed predicate
+// that also decides ray crossings (Supp. Sec. 2.1), so the integer jumps of
+// chi and of the boundary sum coincide.
+#include <cmath>
+
+#include "gwn_mesh.h"
+
+namespace gwn {
+namespace {
+
+constexpr double kInv2Pi = 0.15915494309189533576888376337251;  // 1 / (2 pi)
+
+template <class T>
+struct Vtx {
+    T rx, ry, rz, s;
+    int dx, dy;
+};
+
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float fatan2(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double fatan2(double y, double x) { return atan2(y, x); }
+
+// s = l - r_z, evaluated without cancellation
+template <class T>
+__device__ __forceinline__ T stereo_s(T rho2, T rz) {
+    T l = fsqrt(rho2 + rz * rz);
+    T t = l + fabs(rz);
+    return rz > (T)0 ? fdiv(rho2, t) : t;
+}
+
+// FAR = the query's quantised x or y is outside the grid: raw offsets, and no
+// exact decision is needed (no ray crossings; every edge has D > 0 there).
+template <class T, bool FAR>
+__device__ __forceinline__ Vtx<T> make_vtx(const BVert& b, int qqx, int qqy, T pxs, T pys, T pzs) {
+    Vtx<T> v;
+    v.dx = b.qx - qqx;
+    v.dy = b.qy - qqy;
+    if (FAR) {
+        v.rx = (T)b.x - pxs;
+        v.ry = (T)b.y - pys;
+    } else {
+        v.rx = (T)v.dx;
+        v.ry = (T)v.dy;
+    }
+    v.rz = (T)b.z - pzs;
+    v.s = stereo_s<T>(v.rx * v.rx + v.ry * v.ry, v.rz);
+    return v;
+}
+
+// Rare path for D <= 0: fix the sign of N from the exact predicate, or take the
+// limit under the perturbation when an endpoint lies on the +z ray (its x/y
+// offset becomes (-e1, -e2)).
+template <class T>
+__device__ __forceinline__ void exact_branch(const Vtx<T>& a, const Vtx<T>& b, T& N, T& D) {
+    const bool aon = (a.dx == 0) & (a.dy == 0) & (a.rz > (T)0);
+    const bool bon = (b.dx == 0) & (b.dy == 0) & (b.rz > (T)0);
+    if (aon && bon) {
+        N = (T)0;
+        D = (T)1;
+    } else if (aon) {          // N ~ e1 rb_y - e2 rb_x,  D ~ -e1 rb_x - e2 rb_y
+        if (b.ry != (T)0) {
+            N = b.ry;
+            D = -b.rx;
+        } else if (b.rx > (T)0) {
+            N = -(T)0;
+            D = (T)-1;
+        } else {
+            N = (T)0;
+            D = (T)1;
+        }
+    } else if (bon) {          // N ~ -e1 ra_y + e2 ra_x, D ~ -e1 ra_x - e2 ra_y
+        if (a.ry != (T)0) {
+            N = -a.ry;
+            D = -a.rx;
+        } else if (a.rx > (T)0) {
+            N = (T)0;
+            D = (T)-1;
+        } else {
+            N = (T)0;
+            D = (T)1;
+        }
+    } else {
+        const int o = orient_sos(a.dx, a.dy, b.dx, b.dy);   // N = -orient2d(a, b, q_eps)
+        if (o > 0) N = -fabs(N);
+        else if (o < 0) N = fabs(N);
+    }
+}
+
+template <class T, bool FAR>
+__device__ __forceinline__ T edge_angle(const Vtx<T>& a, const Vtx<T>& b) {
+    T N = a.ry * b.rx - a.rx * b.ry;
+    T D = a.s * b.s + (a.rx * b.rx + a.ry * b.ry);
+    if (!FAR && D <= (T)0) exact_branch<T>(a, b, N, D);
+    return fatan2(N, D);
+}
+
+// Boundary sum for one query per lane: sum over loops, FP32 partials flushed
+// to FP64 every 32 edges (FP64 throughout for T = double).
+template <class T, bool FAR>
+__device__ double boundary_sum(const MeshView& mv, int qqx, int qqy, T pxs, T pys, T pzs) {
+    double S = 0.0;
+    const BVert* __restrict__ bv = mv.bverts;
+    for (int l = 0; l < mv.nloops; ++l) {
+        const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
+        const Vtx<T> first = make_vtx<T, FAR>(bv[b0], qqx, qqy, pxs, pys, pzs);
+        Vtx<T> prev = first;
+        int j = b0 + 1;
+        while (j < b1) {
+            const int je = min(b1, j + 32);
+            T acc = (T)0;
+#pragma unroll 2
+            for (; j < je; ++j) {
+                const Vtx<T> cur = make_vtx<T, FAR>(bv[j], qqx, qqy, pxs, pys, pzs);
+                acc += edge_angle<T, FAR>(prev, cur);
+                prev = cur;
+            }
+            S += (double)acc;
+        }
+        S += (double)edge_angle<T, FAR>(prev, first);
+    }
+    return S;
+}
+
+// ---------------------------------------------------------------- chi, batch
+
+constexpr int kChiBlock = 64;
+
+__device__ __forceinline__ int leaf_up(const MeshView& mv, int t, const QPoint& q) {
+    return ray_up_hit(mv.tris[t], q.x, q.y, q.z);
+}
+
+// signed crossings of the +z ray from q: depth-first over the BVH with a
+// per-lane stack in LDS (the radix tree over 62-bit keys is at most 63 deep)
+__device__ int chi_up(const MeshView& mv, const QPoint& q, int* stk) {
+    int node = mv.root;
+    if (node == kNoRoot) return 0;
+    if (node < 0) return leaf_up(mv, ~node, q);
+    int c = 0, sp = 0;
+    while (true) {
+        const Node nd = mv.nodes[node];
+        bool hl = box_has_xy(nd.lxy.x, nd.lxy.y, nd.lxy.z, nd.lxy.w, q.x, q.y) & (q.z <= nd.z.y);
+        bool hr = box_has_xy(nd.rxy.x, nd.rxy.y, nd.rxy.z, nd.rxy.w, q.x, q.y) & (q.z <= nd.z.w);
+        const int L = nd.link.x, R = nd.link.y;
+        if (hl && L < 0) {
+            c += leaf_up(mv, ~L, q);
+            hl = false;
+        }
+        if (hr && R < 0) {
+            c += leaf_up(mv, ~R, q);
+            hr = false;
+        }
+        if (hl && hr) {
+            stk[sp * kChiBlock] = R;
+            ++sp;
+            node = L;
+        } else if (hl) {
+            node = L;
+        } else if (hr) {
+            node = R;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = stk[sp * kChiBlock];
+        }
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(kChiBlock) void k_chi_batch(MeshView mv, const float* __restrict__ qx,
+                                                         const float* __restrict__ qy, const float* __restrict__ qz,
+                                                         long long qs, long long nq, int* __restrict__ chi) {
+    __shared__ int stk[kLdsStack * kChiBlock];
+    const long long i = blockIdx.x * (long long)kChiBlock + threadIdx.x;
+    if (i >= nq) return;
+    const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
+    chi[i] = q.inbox ? chi_up(mv, q, stk + threadIdx.x) : 0;
+}
+
+// ---------------------------------------------------------------- boundary, batch
+
+template <class T>
+__global__ __launch_bounds__(256) void k_bdry_batch(MeshView mv, const float* __restrict__ qx, const float* __restrict__ qy,
+                                                    const float* __restrict__ qz, long long qs, long long nq,
+                                                    const int* __restrict__ chi, T* __restrict__ w) {
+    const long long i = blockIdx.x * 256ll + threadIdx.x;
+    const long long ii = i < nq ? i : nq - 1;
+    const float px = qx[ii * qs], py = qy[ii * qs], pz = qz[ii * qs];
+    const QPoint q = quantize_point(px, py, pz, mv.g);
+    const T sc = (T)mv.g.scale;
+    const T pxs = (T)px * sc, pys = (T)py * sc, pzs = (T)pz * sc;
+    // lanes outside the fixed-point grid (rare) take the raw-offset loop
+    const double S = q.inbox ? boundary_sum<T, false>(mv, q.x, q.y, pxs, pys, pzs)
+                             : boundary_sum<T, true>(mv, q.x, q.y, pxs, pys, pzs);
+    if (i < nq) w[i] = (T)((double)chi[i] + S * kInv2Pi);
+}
+
+// ---------------------------------------------------------------- grid (ray reuse)
+
+struct GridArgs {
+    double o[3], s[3];
+    long long nx, ny, nz;
+    long long nchunks;   // z-chunks per column
+    long long nwaves;    // columns * nchunks
+};
+
+constexpr int kGridWaves = 4;  // waves per block; one wave per (column, z-chunk)
+
+// Boundary term for ZB samples of one column: per vertex, x/y quantities are
+// shared by the samples (the column is wave-uniform), z quantities are not.
+template <class T, int ZB, bool FAR>
+__device__ __forceinline__ void grid_boundary(const MeshView& mv, int qqx, int qqy, T pxs, T pys, const T* pzs, double* S) {
+    const BVert* __restrict__ bv = mv.bverts;
+    for (int l = 0; l < mv.nloops; ++l) {
+        const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
+        Vtx<T> first[ZB], prev[ZB];
+        {
+            const BVert b = bv[b0];
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) {
+                first[r] = make_vtx<T, FAR>(b, qqx, qqy, pxs, pys, pzs[r]);
+                prev[r] = first[r];
+            }
+        }
+        int j = b0 + 1;
+        while (j < b1) {
+            const int je = min(b1, j + 32);
+            T acc[ZB];
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) acc[r] = (T)0;
+            for (; j < je; ++j) {
+                const BVert b = bv[j];
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) {
+                    const Vtx<T> cur = make_vtx<T, FAR>(b, qqx, qqy, pxs, pys, pzs[r]);
+                    acc[r] += edge_angle<T, FAR>(prev[r], cur);
+                    prev[r] = cur;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) S[r] += (double)acc[r];
+        }
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) S[r] += (double)edge_angle<T, FAR>(prev[r], first[r]);
+    }
+}
+
+// grid coordinate origin + (i + 0.5) * spacing in FP64 without contraction
+__device__ __forceinline__ float grid_coord(double o, double s, long long i) {
+    return (float)__dadd_rn(o, __dmul_rn((double)i + 0.5, s));
+}
+
+// One wave owns one (x, y) column and a chunk of 64*ZB consecutive z samples;
+// lane l holds samples l*ZB .. l*ZB+ZB-1 of the chunk.  The column's line is
+// cast once (all lanes walk the same BVH path) and every crossing is classified
+// against each sample with the exact plane predicate (Sec. 4.3.1, ray reuse).
+template <class T, int ZB>
+__global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs ga, int* __restrict__ chi_out,
+                                                          T* __restrict__ w) {
+    __shared__ int wstack[kGridWaves][kLdsStack];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const long long gw = (long long)blockIdx.x * kGridWaves + wave;
+    if (gw >= ga.nwaves) return;
+    const long long col = gw / ga.nchunks;
+    const long long chunk = gw - col * ga.nchunks;
+    const long long ci = col / ga.ny, cj = col - ci * ga.ny;
+    const float px = grid_coord(ga.o[0], ga.s[0], ci);
+    const float py = grid_coord(ga.o[1], ga.s[1], cj);
+    const long long k0 = chunk * 64 * ZB + (long long)lane * ZB;
+
+    float pz[ZB];
+    int qzr[ZB];
+    int chi[ZB];
+    const QPoint q0 = quantize_point(px, py, 0.0f, mv.g);
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        pz[r] = grid_coord(ga.o[2], ga.s[2], min(k0 + r, ga.nz - 1));
+        qzr[r] = quantize_point(px, py, pz[r], mv.g).z;
+        chi[r] = 0;
+    }
+
+    // ---- crossings along the column's vertical line, classified per sample
+    if (q0.inbox && mv.root != kNoRoot) {
+        int* stk = wstack[wave];
+        int node = mv.root;
+        int sp = 0;
+        const bool leaf_only = node < 0;
+        while (true) {
+            int hits[2];
+            int nh = 0;
+            if (leaf_only) {
+                hits[nh++] = ~node;
+            } else {
+                const Node nd = mv.nodes[node];
+                bool hl = box_has_xy(nd.lxy.x, nd.lxy.y, nd.lxy.z, nd.lxy.w, q0.x, q0.y);
+                bool hr = box_has_xy(nd.rxy.x, nd.rxy.y, nd.rxy.z, nd.rxy.w, q0.x, q0.y);
+                const int L = nd.link.x, R = nd.link.y;
+                if (hl && L < 0) { hits[nh++] = ~L; hl = false; }
+                if (hr && R < 0) { hits[nh++] = ~R; hr = false; }
+                if (hl && hr) { stk[sp++] = R; node = L; }
+                else if (hl) node = L;
+                else if (hr) node = R;
+                else node = -1;
+            }
+            for (int h = 0; h < nh; ++h) {
+                const TriQ t = mv.tris[hits[h]];
+                const int s = tri_xy_sign(t, q0.x, q0.y);
+                if (s == 0) continue;
+                const PlaneQ pl = plane_of(t, q0.x, q0.y);
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) chi[r] += plane_above(pl, qzr[r]) ? s : 0;
+            }
+            if (leaf_only) break;
+            if (node < 0) {
+                if (sp == 0) break;
+                node = stk[--sp];
+            }
+        }
+    }
+
+    // ---- boundary term
+    const T sc = (T)mv.g.scale;
+    T pzs[ZB];
+    double S[ZB];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        pzs[r] = (T)pz[r] * sc;
+        S[r] = 0.0;
+    }
+    if (q0.inbox) grid_boundary<T, ZB, false>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S);
+    else grid_boundary<T, ZB, true>(mv, 0, 0, (T)px * sc, (T)py * sc, pzs, S);
+
+    const long long base = col * ga.nz;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        const long long k = k0 + r;
+        if (k < ga.nz) {
+            w[base + k] = (T)((double)chi[r] + S[r] * kInv2Pi);
+            if (chi_out) chi_out[base + k] = chi[r];
+        }
+    }
+}
+
+template <class T>
+gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t nq,
+                        T* w, int32_t* chi_out, hipStream_t st) {
+    int* chi = chi_out;
+    if (!chi) GWN_HIP_TRY(hipMallocAsync((void**)&chi, sizeof(int) * (size_t)nq, st));
+    const MeshView mv = m->view();
+    k_chi_batch<<<(unsigned)((nq + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, qx, qy, qz, qs, nq, chi);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        k_bdry_batch<T><<<(unsigned)((nq + 255) / 256), 256, 0, st>>>(mv, qx, qy, qz, qs, nq, chi, w);
+        e = hipGetLastError();
+    }
+    if (!chi_out) (void)hipFreeAsync(chi, st);
+    GWN_HIP_TRY(e);
+    return GWN_OK;
+}
+
+template <class T, int ZB>
+gwn_status launch_grid_zb(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out, hipStream_t st) {
+    ga.nchunks = (ga.nz + 64 * ZB - 1) / (64 * ZB);
+    ga.nwaves = ga.nx * ga.ny * ga.nchunks;
+    const long long blocks = (ga.nwaves + kGridWaves - 1) / kGridWaves;
+    k_grid<T, ZB><<<(unsigned)blocks, 64 * kGridWaves, 0, st>>>(m->view(), ga, chi_out, w);
+    GWN_HIP_TRY(hipGetLastError());
+    return GWN_OK;
+}
+
+template <class T>
+gwn_status launch_grid(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out, hipStream_t st) {
+    if (ga.nz >= 64 * 8) return launch_grid_zb<T, 8>(m, ga, w, chi_out, st);
+    if (ga.nz >= 64 * 4) return launch_grid_zb<T, 4>(m, ga, w, chi_out, st);
+    if (ga.nz >= 64 * 2) return launch_grid_zb<T, 2>(m, ga, w, chi_out, st);
+    return launch_grid_zb<T, 1>(m, ga, w, chi_out, st);
+}
+
+}  // namespace
+
+gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t nq,
+                       int prec, void* w, int32_t* chi_out, hipStream_t st) {
+    if (nq == 0) return GWN_OK;
+    if (prec == GWN_PREC_FP64) return launch_batch<double>(m, qx, qy, qz, qs, nq, (double*)w, chi_out, st);
+    return launch_batch<float>(m, qx, qy, qz, qs, nq, (float*)w, chi_out, st);
+}
+
+gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims, int prec,
+                      void* w, int32_t* chi_out, hipStream_t st) {
+    GridArgs ga;
+    for (int a = 0; a < 3; ++a) {
+        ga.o[a] = origin[a];
+        ga.s[a] = spacing[a];
+    }
+    ga.nx = dims[0];
+    ga.ny = dims[1];
+    ga.nz = dims[2];
+    ga.nchunks = ga.nwaves = 0;
+    if (ga.nx == 0 || ga.ny == 0 || ga.nz == 0) return GWN_OK;
+    if (prec == GWN_PREC_FP64) return launch_grid<double>(m, ga, (double*)w, chi_out, st);
+    return launch_grid<float>(m, ga, (float*)w, chi_out, st);
+}
+
+}  // namespace gwn

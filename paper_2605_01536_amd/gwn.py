@@ -1,0 +1,148 @@
+"""Thin Python binding of the C ABI in ``include/gwn.h`` (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libgwn.so``; this module only
+passes torch device pointers, sizes and the current HIP stream through ctypes.
+If the library is missing, :func:`load` raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgwn.so")
+
+GWN_PREC_FP32 = 0
+GWN_PREC_FP64 = 1
+_PREC = {"fp32": GWN_PREC_FP32, "fp64": GWN_PREC_FP64, GWN_PREC_FP32: GWN_PREC_FP32, GWN_PREC_FP64: GWN_PREC_FP64}
+
+_lib = None
+
+
+class GwnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gwn status {status}: {msg}")
+        self.status = status
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int64), ("nf", ctypes.c_int64), ("nboundary", ctypes.c_int64),
+                ("nloops", ctypes.c_int64), ("nnodes", ctypes.c_int64), ("bvh_depth", ctypes.c_int32),
+                ("qshift", ctypes.c_int32), ("bbox", ctypes.c_double * 6), ("qlo", ctypes.c_double * 3),
+                ("build_ms", ctypes.c_double)]
+
+
+def load():
+    """Load libgwn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(python -m paper_2605_01536_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    L.gwn_build_mesh.argtypes = [vp, vp, vp, i64, i64, vp, i64, vp, ctypes.POINTER(vp)]
+    L.gwn_mesh_info_get.argtypes = [vp, ctypes.POINTER(MeshInfo)]
+    L.gwn_mesh_destroy.argtypes = [vp]
+    L.gwn_query_batch.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp, vp]
+    L.gwn_query_grid.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int64), i32, vp, vp, vp]
+    L.gwn_status_str.argtypes = [ctypes.c_int]
+    L.gwn_status_str.restype = ctypes.c_char_p
+    L.gwn_last_error.restype = ctypes.c_char_p
+    for f in ("gwn_build_mesh", "gwn_mesh_info_get", "gwn_mesh_destroy", "gwn_query_batch", "gwn_query_grid"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        L = load()
+        raise GwnError(status, L.gwn_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr()) if t is not None else 0
+
+
+class Mesh:
+    """A soup built on the device: V (nv, 3) float32 and F (nf, 3) int32 CUDA tensors."""
+
+    def __init__(self, V, F, stream=None):
+        import torch
+        L = load()
+        V = V.to(device="cuda", dtype=torch.float32).contiguous()
+        F = F.to(device="cuda", dtype=torch.int32).contiguous()
+        self._h = ctypes.c_void_p()
+        base = _ptr(V)
+        _check(L.gwn_build_mesh(base, base + 4, base + 8, 3, V.shape[0], _ptr(F), F.shape[0],
+                                _stream(stream), ctypes.byref(self._h)))
+
+    def info(self) -> dict:
+        inf = MeshInfo()
+        _check(load().gwn_mesh_info_get(self._h, ctypes.byref(inf)))
+        return {"nv": inf.nv, "nf": inf.nf, "nboundary": inf.nboundary, "nloops": inf.nloops,
+                "nnodes": inf.nnodes, "bvh_depth": inf.bvh_depth, "qshift": inf.qshift,
+                "bbox": list(inf.bbox), "qlo": list(inf.qlo), "build_ms": inf.build_ms}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().gwn_mesh_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_mesh(V, F, stream=None) -> Mesh:
+    return Mesh(V, F, stream)
+
+
+def query_batch(mesh: Mesh, Q, prec="fp32", want_chi=False, out=None, chi_out=None, stream=None):
+    """w for points Q (n, 3) float32 CUDA tensor; returns w (and chi if requested)."""
+    import torch
+    L = load()
+    p = _PREC[prec]
+    Q = Q.contiguous()
+    n = Q.shape[0]
+    if out is None:
+        out = torch.empty(n, device=Q.device, dtype=torch.float64 if p == GWN_PREC_FP64 else torch.float32)
+    if want_chi and chi_out is None:
+        chi_out = torch.empty(n, device=Q.device, dtype=torch.int32)
+    base = _ptr(Q)
+    _check(L.gwn_query_batch(mesh.handle, base, base + 4, base + 8, 3, n, p, _ptr(out),
+                             _ptr(chi_out) if chi_out is not None else None, _stream(stream)))
+    return (out, chi_out) if want_chi else out
+
+
+def query_grid(mesh: Mesh, origin, spacing, dims, prec="fp32", want_chi=False, out=None, chi_out=None, stream=None):
+    """w on the cell-centred grid origin + (idx + 0.5) * spacing, flattened z fastest."""
+    import torch
+    L = load()
+    p = _PREC[prec]
+    n = int(dims[0]) * int(dims[1]) * int(dims[2])
+    if out is None:
+        out = torch.empty(n, device="cuda", dtype=torch.float64 if p == GWN_PREC_FP64 else torch.float32)
+    if want_chi and chi_out is None:
+        chi_out = torch.empty(n, device="cuda", dtype=torch.int32)
+    o = (ctypes.c_double * 3)(*[float(x) for x in origin])
+    s = (ctypes.c_double * 3)(*[float(x) for x in spacing])
+    d = (ctypes.c_int64 * 3)(*[int(x) for x in dims])
+    _check(L.gwn_query_grid(mesh.handle, o, s, d, p, _ptr(out), _ptr(chi_out) if chi_out is not None else None,
+                            _stream(stream)))
+    return (out, chi_out) if want_chi else out

@@ -1,0 +1,30 @@
+"""Shared helpers for the test suite (inputs and comparisons only)."""
+import numpy as np
+
+import oracle as O
+
+TOL_FP32 = 1e-4   # |w_gpu - w_oracle| bound for the FP32 path
+TOL_FP64 = 1e-5   # ... and for the FP64 path
+NEAR_FRAC = 1e-4  # queries closer than this fraction of the bbox diagonal are excluded from w checks
+
+
+def diag_of(V):
+    V = np.asarray(V, np.float64)
+    return float(np.linalg.norm(V.max(0) - V.min(0)))
+
+
+def off_surface_mask(V, F, Q, frac=NEAR_FRAC):
+    cut = frac * diag_of(V)
+    return O.distance(V, F, Q, cut * 2.0) > cut
+
+
+def compare(w_gpu, chi_gpu, V, F, Q, tol, label=""):
+    """chi must match the oracle bit for bit; w within tol where defined."""
+    w_o, S, up, dn = O.antipodal(V, F, Q, full=True)
+    chi_bad = np.flatnonzero(np.asarray(chi_gpu) != up)
+    assert chi_bad.size == 0, f"{label}: chi mismatch at {chi_bad[:10]} gpu={np.asarray(chi_gpu)[chi_bad[:10]]} oracle={up[chi_bad[:10]]}"
+    m = off_surface_mask(V, F, Q)
+    err = np.abs(np.asarray(w_gpu, np.float64) - w_o)
+    e = float(err[m].max()) if m.any() else 0.0
+    assert e <= tol, f"{label}: max |w - oracle| = {e:.3e} > {tol:.1e} (n={m.sum()})"
+    return e, int(m.sum())
