@@ -50,7 +50,21 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (calibrates HBM counters) and exit")
     return ap.parse_args()
+
+
+def copy_probe(nbytes: int):
+    """A plain copy kernel of known size: reads and writes nbytes once each."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4}), flush=True)
 
 
 def main():
@@ -64,6 +78,9 @@ def main():
     from paper_2605_01536_amd import gwn, workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     t0 = time.time()
     soup, grid = W.config4(n=args.n)
     gen_s = time.time() - t0

@@ -17,6 +17,7 @@
 // that also decides ray crossings (Supp. Sec. 2.1), so the integer jumps of
 // chi and of the boundary sum coincide.
 #include <cmath>
+#include <type_traits>
 
 #include "gwn_mesh.h"
 
@@ -35,8 +36,35 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
-__device__ __forceinline__ float fatan2(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double fatan2(double y, double x) { return atan2(y, x); }
+
+// atan(t) for |t| <= 1 as t + t x Q(x), x = t^2, Q of degree 7 fitted by the
+// Remez exchange for minimax relative error (gen_atan_poly.py: 1.7e-8 in exact
+// arithmetic, 9.2e-8 max / 2e-9 mean signed when evaluated in float32).
+constexpr float kAtanQ[8] = {0.002920693f, -0.01636793f, 0.043211866f, -0.07552215f,
+                             0.106660046f, -0.14211056f, 0.19993773f, -0.33333153f};
+constexpr float kPi = 3.14159265358979f;
+constexpr float kPi2 = 1.57079632679490f;
+
+__device__ __forceinline__ float atan_unit(float t) {
+    const float x = t * t;
+    float q = kAtanQ[0];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) q = fmaf(q, x, kAtanQ[k]);
+    return fmaf(t * x, q, t);
+}
+
+// full-range atan2 built on atan_unit (octant reduction by min/max)
+__device__ __forceinline__ float atan2_full(float y, float x) {
+    const float ay = fabsf(y), ax = fabsf(x);
+    const float mx = fmaxf(ay, ax), mn = fminf(ay, ax);
+    const float t = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
+    float a = atan_unit(t);
+    a = ay > ax ? kPi2 - a : a;
+    a = x < 0.f ? kPi - a : a;
+    return copysignf(a, y);
+}
+__device__ __forceinline__ float fatan2(float y, float x) { return atan2_full(y, x); }
 
 // s = l - r_z, evaluated without cancellation
 template <class T>
@@ -110,6 +138,168 @@ __device__ __forceinline__ T edge_angle(const Vtx<T>& a, const Vtx<T>& b) {
     T D = a.s * b.s + (a.rx * b.rx + a.ry * b.ry);
     if (!FAR && D <= (T)0) exact_branch<T>(a, b, N, D);
     return fatan2(N, D);
+}
+
+// ---------------------------------------------------------------- FP32 loop
+// x/y quantities of one boundary vertex relative to the query column (shared by
+// all samples of a grid column; per lane in the batch kernel).
+struct ColV {
+    int dx, dy;
+    float rx, ry, rho2;
+};
+
+template <bool FAR>
+__device__ __forceinline__ ColV col_vtx(const BVert& b, int qqx, int qqy, float pxs, float pys) {
+    ColV c;
+    c.dx = b.qx - qqx;
+    c.dy = b.qy - qqy;
+    if (FAR) {
+        c.rx = b.x - pxs;
+        c.ry = b.y - pys;
+    } else {
+        c.rx = (float)c.dx;
+        c.ry = (float)c.dy;
+    }
+    c.rho2 = fmaf(c.rx, c.rx, c.ry * c.ry);
+    return c;
+}
+
+// s = l - r_z without cancellation
+__device__ __forceinline__ float samp_s(float rho2, float rz) {
+    const float l = __builtin_amdgcn_sqrtf(fmaf(rz, rz, rho2));
+    const float t = l + fabsf(rz);
+    return rz > 0.f ? rho2 * __builtin_amdgcn_rcpf(t) : t;
+}
+
+// Rare path of one (sample, edge): exact atan2 branch where D <= 0 (sign of N from
+// the perturbed predicate, or the perturbation limit for an endpoint on the ray),
+// then the full-range atan2.
+__device__ __forceinline__ float edge_slow(const ColV& a, const ColV& b, float rza, float rzb, float N, float D,
+                                           bool exact) {
+    if (exact && D <= 0.f) {
+        const bool aon = (a.dx == 0) & (a.dy == 0) & (rza > 0.f);
+        const bool bon = (b.dx == 0) & (b.dy == 0) & (rzb > 0.f);
+        if (aon && bon) {
+            N = 0.f;
+            D = 1.f;
+        } else if (aon) {        // N ~ e1 rb_y - e2 rb_x,  D ~ -e1 rb_x - e2 rb_y
+            if (b.ry != 0.f) { N = b.ry; D = -b.rx; }
+            else if (b.rx > 0.f) { N = -0.f; D = -1.f; }
+            else { N = 0.f; D = 1.f; }
+        } else if (bon) {        // N ~ -e1 ra_y + e2 ra_x, D ~ -e1 ra_x - e2 ra_y
+            if (a.ry != 0.f) { N = -a.ry; D = -a.rx; }
+            else if (a.rx > 0.f) { N = 0.f; D = -1.f; }
+            else { N = 0.f; D = 1.f; }
+        } else {
+            const int o = orient_sos(a.dx, a.dy, b.dx, b.dy);   // N = -orient2d(a, b, q_eps)
+            if (o > 0) N = -fabsf(N);
+            else if (o < 0) N = fabsf(N);
+        }
+    }
+    return atan2_full(N, D);
+}
+
+// One boundary edge for ZB samples.  Fast path (wave-uniform): every sample has
+// |N| < D, so atan2(N, D) = atan(N/D) with |N/D| < 1 and no branch fix-up.
+template <int ZB, bool FAR>
+__device__ __forceinline__ void edge_f32(const ColV& a, const ColV& b, const float* sa, const float* sb,
+                                         const float* rza, const float* rzb, float* acc) {
+    const float N = fmaf(a.ry, b.rx, -a.rx * b.ry);
+    const float dot = fmaf(a.rx, b.rx, a.ry * b.ry);
+    const float aN = fabsf(N);
+    float D[ZB];
+    bool slow = false;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        D[r] = fmaf(sa[r], sb[r], dot);
+        slow |= !(aN < D[r]);
+    }
+    if (__builtin_amdgcn_ballot_w64(slow) == 0ull) {
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) acc[r] += atan_unit(N * __builtin_amdgcn_rcpf(D[r]));
+    } else {
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) acc[r] += edge_slow(a, b, rza[r], rzb[r], N, D[r], !FAR);
+    }
+}
+
+// Boundary sum for ZB samples sharing one (x, y): loops of the chain, FP32
+// partials flushed into FP64 every 32 edges.
+template <int ZB, bool FAR>
+__device__ __forceinline__ void loops_f32(const MeshView& mv, int qqx, int qqy, float pxs, float pys, const float* pzs,
+                                          double* S) {
+    const BVert* __restrict__ bv = mv.bverts;
+    for (int l = 0; l < mv.nloops; ++l) {
+        const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
+        ColV cf, cp;
+        float rzf[ZB], sf[ZB], rzp[ZB], sp[ZB];
+        {
+            const BVert b = bv[b0];
+            cf = col_vtx<FAR>(b, qqx, qqy, pxs, pys);
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) {
+                rzf[r] = b.z - pzs[r];
+                sf[r] = samp_s(cf.rho2, rzf[r]);
+                rzp[r] = rzf[r];
+                sp[r] = sf[r];
+            }
+            cp = cf;
+        }
+        int j = b0 + 1;
+        while (j < b1) {
+            const int je = min(b1, j + 32);
+            float acc[ZB];
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) acc[r] = 0.f;
+            // two vertices per trip: the loop-carried vertex alternates between
+            // two register sets instead of being copied every edge
+            for (; j + 1 < je; j += 2) {
+                const BVert b1v = bv[j];
+                const ColV c1 = col_vtx<FAR>(b1v, qqx, qqy, pxs, pys);
+                float rz1[ZB], s1[ZB];
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) {
+                    rz1[r] = b1v.z - pzs[r];
+                    s1[r] = samp_s(c1.rho2, rz1[r]);
+                }
+                edge_f32<ZB, FAR>(cp, c1, sp, s1, rzp, rz1, acc);
+                const BVert b2v = bv[j + 1];
+                cp = col_vtx<FAR>(b2v, qqx, qqy, pxs, pys);
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) {
+                    rzp[r] = b2v.z - pzs[r];
+                    sp[r] = samp_s(cp.rho2, rzp[r]);
+                }
+                edge_f32<ZB, FAR>(c1, cp, s1, sp, rz1, rzp, acc);
+            }
+            if (j < je) {
+                const BVert b = bv[j];
+                const ColV cc = col_vtx<FAR>(b, qqx, qqy, pxs, pys);
+                float rzc[ZB], sc[ZB];
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) {
+                    rzc[r] = b.z - pzs[r];
+                    sc[r] = samp_s(cc.rho2, rzc[r]);
+                }
+                edge_f32<ZB, FAR>(cp, cc, sp, sc, rzp, rzc, acc);
+                cp = cc;
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) {
+                    rzp[r] = rzc[r];
+                    sp[r] = sc[r];
+                }
+                ++j;
+            }
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) S[r] += (double)acc[r];
+        }
+        float acc[ZB];
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) acc[r] = 0.f;
+        edge_f32<ZB, FAR>(cp, cf, sp, sf, rzp, rzf, acc);
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) S[r] += (double)acc[r];
+    }
 }
 
 // Boundary sum for one query per lane: sum over loops, FP32 partials flushed
@@ -207,8 +397,14 @@ __global__ __launch_bounds__(256) void k_bdry_batch(MeshView mv, const float* __
     const T sc = (T)mv.g.scale;
     const T pxs = (T)px * sc, pys = (T)py * sc, pzs = (T)pz * sc;
     // lanes outside the fixed-point grid (rare) take the raw-offset loop
-    const double S = q.inbox ? boundary_sum<T, false>(mv, q.x, q.y, pxs, pys, pzs)
-                             : boundary_sum<T, true>(mv, q.x, q.y, pxs, pys, pzs);
+    double S = 0.0;
+    if constexpr (std::is_same<T, float>::value) {
+        if (q.inbox) loops_f32<1, false>(mv, q.x, q.y, 0.f, 0.f, &pzs, &S);
+        else loops_f32<1, true>(mv, 0, 0, pxs, pys, &pzs, &S);
+    } else {
+        S = q.inbox ? boundary_sum<T, false>(mv, q.x, q.y, pxs, pys, pzs)
+                    : boundary_sum<T, true>(mv, q.x, q.y, pxs, pys, pzs);
+    }
     if (i < nq) w[i] = (T)((double)chi[i] + S * kInv2Pi);
 }
 
@@ -345,8 +541,13 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs 
         pzs[r] = (T)pz[r] * sc;
         S[r] = 0.0;
     }
-    if (q0.inbox) grid_boundary<T, ZB, false>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S);
-    else grid_boundary<T, ZB, true>(mv, 0, 0, (T)px * sc, (T)py * sc, pzs, S);
+    if constexpr (std::is_same<T, float>::value) {
+        if (q0.inbox) loops_f32<ZB, false>(mv, q0.x, q0.y, 0.f, 0.f, pzs, S);
+        else loops_f32<ZB, true>(mv, 0, 0, px * mv.g.scalef, py * mv.g.scalef, pzs, S);
+    } else {
+        if (q0.inbox) grid_boundary<T, ZB, false>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S);
+        else grid_boundary<T, ZB, true>(mv, 0, 0, (T)px * sc, (T)py * sc, pzs, S);
+    }
 
     const long long base = col * ga.nz;
 #pragma unroll
