@@ -28,19 +28,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GWN queries/sec on 1M-tri open soup at max|err|≤1e-4 vs FP64; % roofline"
 
-# VALU issue ceiling of MI355X without packed-FP32 instructions:
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-instructions/s.
-N_CU, SIMD_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
-PEAK_LANE_OPS = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_HZ
+# VALU issue ceiling of MI355X: FP32 add/mul/fma (and compares, selects,
+# 32-bit integer ops) issue at 32 lanes per clock per SIMD, i.e. one wave64
+# instruction per 2 clocks (measured on the box; this is the rate behind the
+# 157.3 TFLOP/s FP32 vector figure, which counts an FMA as 2 FLOPs):
+# 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 7.86e13 FP32 VALU slots/s.
+# sqrt and rcp were measured at ~3.1 slots each.
+N_CU, SIMD_PER_CU, LANES_PER_CLK, CLOCK_HZ = 256, 4, 32, 2.4e9
+PEAK_SLOTS = N_CU * SIMD_PER_CU * LANES_PER_CLK * CLOCK_HZ
+TRANS_SLOTS = 3
 
-# Algorithmic VALU lane-operations per (query, boundary edge) pair of the grid
-# path, with per-column x/y work amortised over the column (counted op by op in
-# the design notes: per sample and vertex 8 incl. sqrt and rcp; per sample and
-# edge 1 (D) + 22 (atan2) + 1 (branch test) + 1 (accumulate)).
-I_MIN_GRID = 33
-I_MIN_BATCH = 43
-
-
+# Minimal VALU slots per (query, boundary edge) pair on the grid path, with x/y
+# work shared by the samples of a column (one boundary vertex per edge):
+#   per sample and vertex: r_z (1), l^2 (1), sqrt, l+|r_z| (1), rcp, rho^2*rcp (1),
+#                          compare + select (2)                    = 6 + 2 trans
+#   per sample and edge:   D (1), fast-path test (1), rcp, N*rcp (1), t^2 (1),
+#                          7 polynomial FMAs, t*x (1), final FMA (1), accumulate (1)
+#                                                                  = 14 + 1 trans
+I_MIN_GRID = 6 + 14 + 3 * TRANS_SLOTS      # = 29
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,12 +121,12 @@ def main():
     roof = {
         "bound": "alu",
         "achieved": achieved / 1e12,
-        "peak": PEAK_LANE_OPS / 1e12,
-        "unit": "Tops/s (VALU lane-ops)",
-        "frac": achieved / PEAK_LANE_OPS,
+        "peak": PEAK_SLOTS / 1e12,
+        "unit": "T FP32-VALU-slots/s",
+        "frac": achieved / PEAK_SLOTS,
         "traffic": None,
         "kernel": "k_grid",
-        "ops_per_pair": I_MIN_GRID,
+        "slots_per_pair": I_MIN_GRID,
         "pairs_per_launch": pairs,
         "avg_kernel_ms": avg_kernel_s * 1e3,
     }

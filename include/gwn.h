@@ -124,6 +124,54 @@ gwn_status gwn_query_batch(gwn_mesh m, const float* qx, const float* qy, const f
 gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacing, const int64_t* dims,
                           int32_t prec, void* w_out, int32_t* chi_out, void* stream);
 
+/*
+ * Many meshes in one launch (batched workloads of uneven size).
+ *
+ * gwn_multi_create prepares a plan for nmesh built meshes whose queries are
+ * concatenated: mesh m owns queries [q_offsets[m], q_offsets[m+1]) of the
+ * strided arrays qx, qy, qz (q_offsets: host array of nmesh+1 non-decreasing
+ * values, q_offsets[0] = 0).  It splits the queries into work items (mesh,
+ * query tile), orders them (largest estimated cost first by default), and
+ * captures one HIP graph: reset of a work counter, crossing counts for every
+ * query, and a persistent kernel whose waves claim items from the counter.
+ * With opts->autotune the candidate schedules (tile size, item order, resident
+ * waves) are timed on the real inputs and the fastest is kept; with
+ * opts->tune_cache a previously stored choice for the same device and problem
+ * size class is reused (and a new choice is appended).  Tuning runs the plan,
+ * so it writes w_out / chi_out.
+ *
+ * gwn_multi_run replays the graph on `stream` (asynchronous).  The plan keeps
+ * the pointers it was created with: the caller keeps the query arrays, w_out
+ * (float, FP32 path only) and chi_out (nullable; the plan then owns a scratch
+ * buffer) alive and unchanged in size until gwn_multi_destroy.  The meshes must
+ * outlive the plan.  Errors: GWN_E_INVALID for bad arguments or meshes from
+ * another device, GWN_E_UNSUPPORTED for prec != GWN_PREC_FP32.
+ */
+typedef struct gwn_multi_s* gwn_multi;
+
+typedef struct {
+    int32_t item_queries;     /* queries per work item, rounded up to a multiple of 64; 0 = default or tuned */
+    int32_t waves_per_simd;   /* resident persistent waves per SIMD, 1..8; 0 = default or tuned */
+    int32_t order;            /* 0 = largest estimated cost first, 1 = mesh order */
+    int32_t autotune;         /* nonzero: time candidate schedules at creation and keep the fastest */
+    const char* tune_cache;   /* nullable JSON-lines file read before tuning and appended after */
+} gwn_multi_opts;
+
+typedef struct {
+    int32_t nmesh;
+    int64_t nqueries;
+    int32_t nitems, item_queries, waves_per_simd, order, grid_blocks, tuned;
+    double est_pairs;         /* sum over meshes of queries x boundary edges */
+    double tuned_ms;          /* best replay time seen by the tuner (0 if not tuned here) */
+} gwn_multi_info;
+
+gwn_status gwn_multi_create(const gwn_mesh* meshes, int32_t nmesh, const float* qx, const float* qy,
+                            const float* qz, int64_t qstride, const int64_t* q_offsets, int32_t prec, void* w_out,
+                            int32_t* chi_out, const gwn_multi_opts* opts, void* stream, gwn_multi* out);
+gwn_status gwn_multi_run(gwn_multi plan, void* stream);
+gwn_status gwn_multi_info_get(gwn_multi plan, gwn_multi_info* out);
+gwn_status gwn_multi_destroy(gwn_multi plan);
+
 const char* gwn_status_str(gwn_status s);
 const char* gwn_last_error(void);   /* thread-local; "" if none */
 

@@ -3,6 +3,7 @@
 // happens in the kernels of build.hip and query.hip.
 #include <cstdarg>
 #include <cstdio>
+#include <cmath>
 #include <new>
 
 #include "gwn_mesh.h"
@@ -157,6 +158,64 @@ gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacin
         return GWN_E_INVALID;
     }
     return gwn::query_grid(m, origin, spacing, dims, prec, w_out, chi_out, (hipStream_t)stream);
+}
+
+gwn_status gwn_multi_create(const gwn_mesh* meshes, int32_t nmesh, const float* qx, const float* qy,
+                            const float* qz, int64_t qstride, const int64_t* q_offsets, int32_t prec, void* w_out,
+                            int32_t* chi_out, const gwn_multi_opts* opts, void* stream, gwn_multi* out) {
+    gwn::clear_error();
+    if (!out || !meshes || !q_offsets || nmesh < 1 || qstride < 1) {
+        gwn::set_error("gwn_multi_create: null argument, nmesh < 1 or qstride < 1");
+        return GWN_E_INVALID;
+    }
+    *out = nullptr;
+    if (q_offsets[0] != 0) {
+        gwn::set_error("gwn_multi_create: q_offsets[0] must be 0");
+        return GWN_E_INVALID;
+    }
+    for (int m = 0; m < nmesh; ++m) {
+        gwn_status s = check_mesh(meshes[m], "gwn_multi_create");
+        if (s != GWN_OK) return s;
+        if (q_offsets[m + 1] < q_offsets[m]) {
+            gwn::set_error("gwn_multi_create: q_offsets must be non-decreasing (at mesh %d)", m);
+            return GWN_E_INVALID;
+        }
+    }
+    if (q_offsets[nmesh] > 0 && (!qx || !qy || !qz || !w_out)) {
+        gwn::set_error("gwn_multi_create: null query or output array");
+        return GWN_E_INVALID;
+    }
+    if (q_offsets[nmesh] > (1ll << 40)) {
+        gwn::set_error("gwn_multi_create: too many queries");
+        return GWN_E_INVALID;
+    }
+    return gwn::multi_create(meshes, nmesh, qx, qy, qz, qstride, q_offsets, prec, w_out, chi_out, opts,
+                             (hipStream_t)stream, out);
+}
+
+gwn_status gwn_multi_run(gwn_multi plan, void* stream) {
+    gwn::clear_error();
+    if (!plan) {
+        gwn::set_error("gwn_multi_run: null plan");
+        return GWN_E_INVALID;
+    }
+    return gwn::multi_run(plan, (hipStream_t)stream);
+}
+
+gwn_status gwn_multi_info_get(gwn_multi plan, gwn_multi_info* out) {
+    gwn::clear_error();
+    if (!plan || !out) {
+        gwn::set_error("gwn_multi_info_get: null argument");
+        return GWN_E_INVALID;
+    }
+    gwn::multi_info(plan, out);
+    return GWN_OK;
+}
+
+gwn_status gwn_multi_destroy(gwn_multi plan) {
+    gwn::clear_error();
+    gwn::multi_destroy(plan);
+    return GWN_OK;
 }
 
 const char* gwn_status_str(gwn_status s) {

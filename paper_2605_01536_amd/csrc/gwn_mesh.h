@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <new>
 #include <string>
 
 #include "../../include/gwn.h"
@@ -50,6 +51,13 @@ gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, co
 
 gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims,
                       int prec, void* w_out, int32_t* chi_out, hipStream_t stream);
+
+gwn_status multi_create(const gwn_mesh* meshes, int nmesh, const float* qx, const float* qy, const float* qz,
+                        int64_t qs, const int64_t* q_offsets, int prec, void* w_out, int32_t* chi_out,
+                        const gwn_multi_opts* opts, hipStream_t stream, gwn_multi_s** out);
+gwn_status multi_run(gwn_multi_s* p, hipStream_t stream);
+void multi_destroy(gwn_multi_s* p);
+void multi_info(const gwn_multi_s* p, gwn_multi_info* out);
 
 // Fixed-point grid rule (host, FP64): origin = bbox_lo - 0.75 e, scale 2^k with
 // k the largest integer such that 2.5 e 2^k <= 2^30 - 1 (e = max extent, 1 if 0).

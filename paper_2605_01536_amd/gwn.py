@@ -146,3 +146,74 @@ def query_grid(mesh: Mesh, origin, spacing, dims, prec="fp32", want_chi=False, o
     _check(L.gwn_query_grid(mesh.handle, o, s, d, p, _ptr(out), _ptr(chi_out) if chi_out is not None else None,
                             _stream(stream)))
     return (out, chi_out) if want_chi else out
+
+
+class MultiOpts(ctypes.Structure):
+    _fields_ = [("item_queries", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+
+
+class MultiInfo(ctypes.Structure):
+    _fields_ = [("nmesh", ctypes.c_int32), ("nqueries", ctypes.c_int64), ("nitems", ctypes.c_int32),
+                ("item_queries", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("tuned", ctypes.c_int32), ("est_pairs", ctypes.c_double),
+                ("tuned_ms", ctypes.c_double)]
+
+
+def _load_multi(L):
+    if getattr(L, "_multi_ready", False):
+        return
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    L.gwn_multi_create.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64), i32, vp,
+                                   vp, ctypes.POINTER(MultiOpts), vp, ctypes.POINTER(vp)]
+    L.gwn_multi_run.argtypes = [vp, vp]
+    L.gwn_multi_info_get.argtypes = [vp, ctypes.POINTER(MultiInfo)]
+    L.gwn_multi_destroy.argtypes = [vp]
+    for f in ("gwn_multi_create", "gwn_multi_run", "gwn_multi_info_get", "gwn_multi_destroy"):
+        getattr(L, f).restype = ctypes.c_int
+    L._multi_ready = True
+
+
+class MultiPlan:
+    """Captured multi-mesh evaluation: meshes[m] owns queries Q[offsets[m]:offsets[m+1]]."""
+
+    def __init__(self, meshes, Q, offsets, w_out=None, chi_out=None, item_queries=0, waves_per_simd=0, order=0,
+                 autotune=False, tune_cache=None, stream=None):
+        import torch
+        L = load()
+        _load_multi(L)
+        self._meshes = list(meshes)
+        self._Q = Q.contiguous()
+        n = int(offsets[-1])
+        assert self._Q.shape[0] >= n
+        self.w = w_out if w_out is not None else torch.empty(n, device=Q.device, dtype=torch.float32)
+        self.chi = chi_out
+        hs = (ctypes.c_void_p * len(self._meshes))(*[m.handle.value for m in self._meshes])
+        offs = (ctypes.c_int64 * len(offsets))(*[int(o) for o in offsets])
+        self._cache = tune_cache.encode() if tune_cache else None
+        opts = MultiOpts(int(item_queries), int(waves_per_simd), int(order), int(bool(autotune)), self._cache)
+        base = _ptr(self._Q)
+        self._h = ctypes.c_void_p()
+        _check(L.gwn_multi_create(hs, len(self._meshes), base, base + 4, base + 8, 3, offs, GWN_PREC_FP32,
+                                  _ptr(self.w), _ptr(self.chi) if self.chi is not None else None,
+                                  ctypes.byref(opts), _stream(stream), ctypes.byref(self._h)))
+
+    def run(self, stream=None):
+        _check(load().gwn_multi_run(self._h, _stream(stream)))
+        return self.w
+
+    def info(self) -> dict:
+        inf = MultiInfo()
+        _check(load().gwn_multi_info_get(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in MultiInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().gwn_multi_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

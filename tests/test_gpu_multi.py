@@ -1,0 +1,89 @@
+"""Batched multi-mesh plans (one captured graph with a persistent kernel)
+against the single-mesh path and the CPU oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_01536_amd import workloads as W
+from tests._util import TOL_FP32, compare
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _batch_of(gwn, n_mesh, seed, q_range=(200, 5000), tri_range=(100, 20000)):
+    soups, queries = W.ellipsoid_batch(seed=seed, n_mesh=n_mesh, tri_range=tri_range, q_range=q_range)
+    meshes = [gwn.Mesh(torch.from_numpy(s.V).cuda(), torch.from_numpy(s.F).cuda()) for s in soups]
+    offs = np.concatenate([[0], np.cumsum([q.shape[0] for q in queries])]).astype(np.int64)
+    Q = torch.from_numpy(np.concatenate(queries)).cuda()
+    return soups, queries, meshes, offs, Q
+
+
+def test_multi_equals_single_mesh_path_and_oracle(gwn):
+    soups, queries, meshes, offs, Q = _batch_of(gwn, 24, seed=33)
+    chi = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
+    plan = gwn.MultiPlan(meshes, Q, offs, chi_out=chi)
+    w = plan.run().clone()
+    torch.cuda.synchronize()
+    for m, s in enumerate(soups):
+        a, b = int(offs[m]), int(offs[m + 1])
+        wb, cb = gwn.query_batch(meshes[m], Q[a:b], want_chi=True)
+        assert torch.equal(cb, chi[a:b])
+        assert torch.equal(wb, w[a:b])        # same per-query arithmetic, bit for bit
+    rng = np.random.default_rng(0)
+    for m in rng.choice(len(soups), 6, replace=False):
+        a, b = int(offs[m]), int(offs[m + 1])
+        idx = rng.choice(b - a, min(300, b - a), replace=False)
+        compare(w[a:b][torch.from_numpy(idx).cuda()].cpu().numpy(), chi[a:b][torch.from_numpy(idx).cuda()].cpu().numpy(),
+                soups[m].V, soups[m].F, queries[m][idx], TOL_FP32, f"multi mesh {m}")
+
+
+@pytest.mark.parametrize("sched", [dict(item_queries=64, waves_per_simd=1, order=1),
+                                   dict(item_queries=512, waves_per_simd=8, order=0),
+                                   dict(item_queries=100, waves_per_simd=3, order=0)])
+def test_schedules_agree(gwn, sched):
+    soups, queries, meshes, offs, Q = _batch_of(gwn, 12, seed=34)
+    ref = gwn.MultiPlan(meshes, Q, offs).run().clone()
+    p = gwn.MultiPlan(meshes, Q, offs, **sched)
+    inf = p.info()
+    assert inf["item_queries"] % 64 == 0 and inf["nitems"] > 0
+    assert torch.equal(p.run(), ref)
+
+
+def test_graph_replays_with_eager_work_between(gwn):
+    soups, queries, meshes, offs, Q = _batch_of(gwn, 10, seed=35)
+    plan = gwn.MultiPlan(meshes, Q, offs)
+    first = plan.run().clone()
+    for rep in range(4):
+        plan.w.fill_(-7.0)                                   # eager work on the same buffers
+        junk = torch.randn(1 << 20, device="cuda").sum()      # unrelated eager kernels
+        torch.cuda.synchronize()
+        out = plan.run()
+        torch.cuda.synchronize()
+        assert torch.equal(out, first), f"replay {rep} differs"
+        assert float(junk) == float(junk)
+
+
+def test_autotune_and_cache(gwn, tmp_path):
+    soups, queries, meshes, offs, Q = _batch_of(gwn, 16, seed=36)
+    cache = str(tmp_path / "tune.jsonl")
+    p1 = gwn.MultiPlan(meshes, Q, offs, autotune=True, tune_cache=cache)
+    i1 = p1.info()
+    assert i1["tuned"] == 1 and i1["tuned_ms"] > 0
+    assert os.path.exists(cache) and "item_queries" in open(cache).read()
+    w1 = p1.run().clone()
+    p2 = gwn.MultiPlan(meshes, Q, offs, autotune=True, tune_cache=cache)   # served from the cache
+    i2 = p2.info()
+    assert i2["tuned"] == 1 and i2["tuned_ms"] == 0.0
+    assert (i2["item_queries"], i2["waves_per_simd"], i2["order"]) == (i1["item_queries"], i1["waves_per_simd"], i1["order"])
+    assert torch.equal(p2.run(), w1)
+
+
+def test_multi_rejects_bad_arguments(gwn):
+    soups, queries, meshes, offs, Q = _batch_of(gwn, 3, seed=37)
+    with pytest.raises(gwn.GwnError):
+        gwn.MultiPlan(meshes, Q, [1] + list(offs[1:]))
+    with pytest.raises(gwn.GwnError):
+        gwn.MultiPlan(meshes, Q, [0, 10, 5, int(offs[-1])])
