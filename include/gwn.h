@@ -172,6 +172,53 @@ gwn_status gwn_multi_run(gwn_multi plan, void* stream);
 gwn_status gwn_multi_info_get(gwn_multi plan, gwn_multi_info* out);
 gwn_status gwn_multi_destroy(gwn_multi plan);
 
+/*
+ * Learned surrogate (a Fourier-feature MLP standing in for far-field queries;
+ * not part of the paper's method, whose nearest item is its future-work remark
+ * on approximating the fractional part).
+ *
+ * Network: gamma(p) = [sin 2piGp, cos 2piGp] with G (32x3) ~ N(0, sigma^2)
+ * fixed at creation; four GELU layers 64->128->128->128->128; linear output
+ * 128->1.  Matrix products use bf16 MFMA with fp32 accumulation; Adam updates
+ * fp32 master weights.  Parameters form one flat vector of GWN_MLP_NPARAMS
+ * floats: W1 (64x128, row-major [in][out]), b1, W2, b2, W3, b3, W4, b4, W5
+ * (128), b5.  Loss: mean squared error.
+ *
+ *   gwn_mlp_get_state / gwn_mlp_set_state copy the state between the device and
+ *     HOST arrays (each nullable: theta and the Adam moments m, v of
+ *     GWN_MLP_NPARAMS floats, G of 96 floats, the step counter; step < 0 keeps
+ *     it).  They synchronise the device.  Used for checkpoints.
+ *   gwn_mlp_forward: y_out[i] = network(q_i) for n device points.
+ *   gwn_mlp_loss_grad: gradient of the loss over the n points with targets
+ *     `target` into grad_out (device, nullable) and the loss (host, nullable).
+ *   gwn_mlp_train_step: the same, then one Adam step (lr; beta1 0.9, beta2
+ *     0.999, eps 1e-8, bias-corrected).
+ *   gwn_surrogate_query: w_out = network prediction, except for points with
+ *     |prediction - 1/2| < band, which are re-evaluated by the exact FP32 path
+ *     (gwn_query_batch arithmetic) on `mesh`; fallback_out (device, nullable)
+ *     flags them and *nfallback_out (host, nullable; synchronises) counts them.
+ * The training scratch is owned by the handle and sized to the largest batch;
+ * n must be < 2^31.
+ */
+#define GWN_MLP_NPARAMS 57985
+
+typedef struct gwn_mlp_s* gwn_mlp;
+
+gwn_status gwn_mlp_create(uint64_t seed, double fourier_sigma, gwn_mlp* out);
+gwn_status gwn_mlp_destroy(gwn_mlp h);
+gwn_status gwn_mlp_get_state(gwn_mlp h, float* theta, float* adam_m, float* adam_v, float* G, int64_t* step);
+gwn_status gwn_mlp_set_state(gwn_mlp h, const float* theta, const float* adam_m, const float* adam_v,
+                             const float* G, int64_t step);
+gwn_status gwn_mlp_forward(gwn_mlp h, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                           int64_t n, float* y_out, void* stream);
+gwn_status gwn_mlp_loss_grad(gwn_mlp h, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                             const float* target, int64_t n, float* grad_out, float* loss_out, void* stream);
+gwn_status gwn_mlp_train_step(gwn_mlp h, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                              const float* target, int64_t n, float lr, float* loss_out, void* stream);
+gwn_status gwn_surrogate_query(gwn_mlp h, gwn_mesh mesh, const float* qx, const float* qy, const float* qz,
+                               int64_t qstride, int64_t n, float band, float* w_out, uint8_t* fallback_out,
+                               int64_t* nfallback_out, void* stream);
+
 const char* gwn_status_str(gwn_status s);
 const char* gwn_last_error(void);   /* thread-local; "" if none */
 

@@ -218,6 +218,104 @@ gwn_status gwn_multi_destroy(gwn_multi plan) {
     return GWN_OK;
 }
 
+static gwn_status check_points(const char* fn, const float* qx, const float* qy, const float* qz, int64_t qs,
+                               int64_t n, const void* out) {
+    if (n < 0 || n >= (1ll << 31) || qs < 1) {
+        gwn::set_error("%s: bad n=%lld or stride=%lld", fn, (long long)n, (long long)qs);
+        return GWN_E_INVALID;
+    }
+    if (n > 0 && (!qx || !qy || !qz || !out)) {
+        gwn::set_error("%s: null point or output array", fn);
+        return GWN_E_INVALID;
+    }
+    return GWN_OK;
+}
+
+static gwn_status check_mlp(gwn_mlp h, const char* fn) {
+    if (!h) {
+        gwn::set_error("%s: null handle", fn);
+        return GWN_E_INVALID;
+    }
+    return GWN_OK;
+}
+
+gwn_status gwn_mlp_create(uint64_t seed, double fourier_sigma, gwn_mlp* out) {
+    gwn::clear_error();
+    if (!out || !(fourier_sigma > 0.0) || !std::isfinite(fourier_sigma)) {
+        gwn::set_error("gwn_mlp_create: null out or bad sigma");
+        return GWN_E_INVALID;
+    }
+    *out = nullptr;
+    return gwn::mlp_create(seed, fourier_sigma, out);
+}
+
+gwn_status gwn_mlp_destroy(gwn_mlp h) {
+    gwn::clear_error();
+    gwn::mlp_release(h);
+    return GWN_OK;
+}
+
+gwn_status gwn_mlp_get_state(gwn_mlp h, float* theta, float* m, float* v, float* G, int64_t* step) {
+    gwn::clear_error();
+    gwn_status s = check_mlp(h, "gwn_mlp_get_state");
+    return s != GWN_OK ? s : gwn::mlp_get_state(h, theta, m, v, G, step);
+}
+
+gwn_status gwn_mlp_set_state(gwn_mlp h, const float* theta, const float* m, const float* v, const float* G,
+                             int64_t step) {
+    gwn::clear_error();
+    gwn_status s = check_mlp(h, "gwn_mlp_set_state");
+    return s != GWN_OK ? s : gwn::mlp_set_state(h, theta, m, v, G, step);
+}
+
+gwn_status gwn_mlp_forward(gwn_mlp h, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t n,
+                           float* y, void* stream) {
+    gwn::clear_error();
+    gwn_status s = check_mlp(h, "gwn_mlp_forward");
+    if (s == GWN_OK) s = check_points("gwn_mlp_forward", qx, qy, qz, qs, n, y);
+    return s != GWN_OK ? s : gwn::mlp_forward(h, qx, qy, qz, qs, n, y, (hipStream_t)stream);
+}
+
+gwn_status gwn_mlp_loss_grad(gwn_mlp h, const float* qx, const float* qy, const float* qz, int64_t qs,
+                             const float* target, int64_t n, float* grad_out, float* loss_out, void* stream) {
+    gwn::clear_error();
+    gwn_status s = check_mlp(h, "gwn_mlp_loss_grad");
+    if (s == GWN_OK) s = check_points("gwn_mlp_loss_grad", qx, qy, qz, qs, n, target);
+    if (s == GWN_OK && n == 0) {
+        gwn::set_error("gwn_mlp_loss_grad: empty batch");
+        s = GWN_E_INVALID;
+    }
+    return s != GWN_OK ? s : gwn::mlp_loss_grad(h, qx, qy, qz, qs, target, n, grad_out, loss_out, (hipStream_t)stream);
+}
+
+gwn_status gwn_mlp_train_step(gwn_mlp h, const float* qx, const float* qy, const float* qz, int64_t qs,
+                              const float* target, int64_t n, float lr, float* loss_out, void* stream) {
+    gwn::clear_error();
+    gwn_status s = check_mlp(h, "gwn_mlp_train_step");
+    if (s == GWN_OK) s = check_points("gwn_mlp_train_step", qx, qy, qz, qs, n, target);
+    if (s == GWN_OK && (n == 0 || !(lr >= 0.f))) {
+        gwn::set_error("gwn_mlp_train_step: empty batch or bad learning rate");
+        s = GWN_E_INVALID;
+    }
+    return s != GWN_OK ? s : gwn::mlp_train_step(h, qx, qy, qz, qs, target, n, lr, loss_out, (hipStream_t)stream);
+}
+
+gwn_status gwn_surrogate_query(gwn_mlp h, gwn_mesh mesh, const float* qx, const float* qy, const float* qz, int64_t qs,
+                               int64_t n, float band, float* w_out, uint8_t* fallback_out, int64_t* nfallback_out,
+                               void* stream) {
+    gwn::clear_error();
+    gwn_status s = check_mlp(h, "gwn_surrogate_query");
+    if (s == GWN_OK) s = check_mesh(mesh, "gwn_surrogate_query");
+    if (s == GWN_OK) s = check_points("gwn_surrogate_query", qx, qy, qz, qs, n, w_out);
+    if (s == GWN_OK && !(band >= 0.f)) {
+        gwn::set_error("gwn_surrogate_query: band must be >= 0");
+        s = GWN_E_INVALID;
+    }
+    return s != GWN_OK ? s
+                       : gwn::surrogate_query(h, mesh, qx, qy, qz, qs, n, band, w_out, fallback_out, nfallback_out,
+                                              (hipStream_t)stream);
+}
+
 const char* gwn_status_str(gwn_status s) {
     switch (s) {
         case GWN_OK: return "ok";

@@ -59,6 +59,25 @@ gwn_status multi_run(gwn_multi_s* p, hipStream_t stream);
 void multi_destroy(gwn_multi_s* p);
 void multi_info(const gwn_multi_s* p, gwn_multi_info* out);
 
+// exact FP32 batch path whose point count lives on the device (nmax bounds it)
+gwn_status query_batch_devcount(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
+                                int64_t nmax, const int* ndev, int* chi, float* w, hipStream_t st);
+
+gwn_status mlp_create(uint64_t seed, double sigma, gwn_mlp_s** out);
+void mlp_release(gwn_mlp_s* h);
+gwn_status mlp_get_state(gwn_mlp_s* h, float* theta, float* m, float* v, float* G, int64_t* step);
+gwn_status mlp_set_state(gwn_mlp_s* h, const float* theta, const float* m, const float* v, const float* G,
+                         int64_t step);
+gwn_status mlp_forward(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t n,
+                       float* y, hipStream_t st);
+gwn_status mlp_loss_grad(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs,
+                         const float* tgt, int64_t n, float* grad_out, float* loss_out, hipStream_t st);
+gwn_status mlp_train_step(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs,
+                          const float* tgt, int64_t n, float lr, float* loss_out, hipStream_t st);
+gwn_status surrogate_query(gwn_mlp_s* h, const gwn_mesh_s* mesh, const float* qx, const float* qy, const float* qz,
+                           int64_t qs, int64_t n, float band, float* w, unsigned char* mask, int64_t* nfallback,
+                           hipStream_t st);
+
 // Fixed-point grid rule (host, FP64): origin = bbox_lo - 0.75 e, scale 2^k with
 // k the largest integer such that 2.5 e 2^k <= 2^30 - 1 (e = max extent, 1 if 0).
 QGrid make_qgrid(const double bbox[6]);

@@ -1,0 +1,632 @@
+// mlp.hip -- learned surrogate for far-field winding-number queries:
+// Fourier features gamma(p) = [sin 2piGp, cos 2piGp] (G: 32x3, fixed), four
+// GELU layers 64->128->128->128->128 and a linear output 128->1.  Matrix
+// products run on MFMA (v_mfma_f32_16x16x16bf16_1k: bf16 operands, fp32
+// accumulation); FP32 master weights are updated by Adam and re-packed into
+// bf16 copies in the two layouts the kernels read.  The band query evaluates
+// the network, re-evaluates every point whose prediction lies within `band`
+// of 1/2 with the exact kernels, and scatters those results back.
+//
+// MFMA 16x16x16 operand layout (wave64): lane l holds A[l%16][4(l/16)+i] and
+// B[4(l/16)+i][l%16] (i = 0..3); the result D[4(l/16)+i][l%16] lands in
+// component i of the lane's accumulator.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "gwn_kernels.h"
+#include "gwn_mesh.h"
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+namespace gwn {
+namespace mlp {
+
+constexpr int kFreq = 32, kIn = 64, kHid = 128;
+constexpr int kNParams = 64 * 128 + 128 + 3 * (128 * 128 + 128) + 128 + 1;   // 57985
+constexpr int kOffW[5] = {0, 8320, 24832, 41344, 57856};
+constexpr int kOffB[5] = {8192, 24704, 41216, 57728, 57984};
+constexpr int kTile = 64;        // points per workgroup tile (4 waves x 16 rows)
+constexpr int kLd = 136;         // padded LDS row (bf16) for 128-wide operands
+constexpr int kLd0 = 72;         // padded LDS row for the 64-wide first layer
+constexpr int kChunk = 256;      // batch rows per weight-gradient workgroup
+constexpr int kLdC = kChunk + 4;
+constexpr int kWf = 128 * 64 + 3 * 128 * 128 + 128;   // forward bf16 copy: Wt0..Wt3 ([out][in]) + w4
+constexpr int kWb = 3 * 128 * 128;                    // backward bf16 copy: W1..W3 ([in][out])
+
+struct Dev {
+    float* master;   // kNParams
+    float* m;        // Adam first moment
+    float* v;        // Adam second moment
+    float* G;        // 96
+    unsigned short* wf;
+    unsigned short* wb;
+};
+
+struct Train {
+    unsigned short* x;   // 5 x n x 128 (x0 uses the first 64 columns)
+    float* z;            // 4 x n x 128
+    unsigned short* dz;  // 4 x n x 128
+    float* y;            // n
+    float* dy;           // n
+    float* part;         // nchunk x (kNParams + 1)   (last entry: loss partial)
+    float* grad;         // kNParams + 1
+    long long cap;
+};
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7); returns Phi(z) and
+// exp(-z^2/2) so that gelu = z Phi and gelu' = Phi + z exp(-z^2/2)/sqrt(2 pi).
+__device__ __forceinline__ void gelu_parts(float z, float& phi, float& e) {
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+    e = __builtin_amdgcn_exp2f(-x * x * 1.4426950408889634f);
+    float p = fmaf(1.061405429f, t, -1.453152027f);
+    p = fmaf(p, t, 1.421413741f);
+    p = fmaf(p, t, -0.284496736f);
+    p = fmaf(p, t, 0.254829592f);
+    p *= t;
+    const float erfa = fmaf(-p, e, 1.0f);
+    phi = 0.5f + 0.5f * copysignf(erfa, z);
+}
+__device__ __forceinline__ float gelu(float z) {
+    float phi, e;
+    gelu_parts(z, phi, e);
+    return z * phi;
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+    float phi, e;
+    gelu_parts(z, phi, e);
+    return fmaf(z * 0.39894228040143268f, e, phi);
+}
+
+// acc[t] += A(16 rows of this wave, K) x B(K, 16t..16t+15) for t = 0..7;
+// A rows come from sA (row-major, ld lda), B from sBt stored column-major as
+// [col][k] (ld ldb).
+template <int K>
+__device__ __forceinline__ void mma_rows16(const unsigned short* sA, int lda, const unsigned short* sBt, int ldb,
+                                           int arow, v4f* acc) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const v4s a = *(const v4s*)(sA + (arow + lr) * lda + k0 + 4 * lg);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const v4s b = *(const v4s*)(sBt + (16 * t + lr) * ldb + k0 + 4 * lg);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+}
+
+// Forward pass.  Every workgroup stages all bf16 weights in LDS once, then
+// walks its tiles of 64 points; each wave owns 16 rows and only ever touches
+// its own rows of the activation tile.
+template <bool TRAIN>
+__global__ __launch_bounds__(256) void k_fwd(Dev P, const float* __restrict__ qx, const float* __restrict__ qy,
+                                             const float* __restrict__ qz, long long qs, long long n,
+                                             float* __restrict__ y, Train T) {
+    __shared__ unsigned short sW0[128 * kLd0];
+    __shared__ unsigned short sW[3][128 * kLd];
+    __shared__ unsigned short sA[kTile * kLd];
+    __shared__ float sW4[128];
+    __shared__ float sB[4][128];
+    __shared__ float sG[96];
+    for (int i = threadIdx.x; i < 128 * 64; i += 256) sW0[(i >> 6) * kLd0 + (i & 63)] = P.wf[i];
+    for (int l = 0; l < 3; ++l)
+        for (int i = threadIdx.x; i < 128 * 128; i += 256) sW[l][(i >> 7) * kLd + (i & 127)] = P.wf[8192 + l * 16384 + i];
+    for (int i = threadIdx.x; i < 128; i += 256) {
+        sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
+        for (int l = 0; l < 4; ++l) sB[l][i] = P.master[kOffB[l] + i];
+    }
+    if (threadIdx.x < 96) sG[threadIdx.x] = P.G[threadIdx.x];
+    const float b4 = P.master[kOffB[4]];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int r0 = wave * 16;
+    for (long long tile = blockIdx.x; tile * kTile < n; tile += gridDim.x) {
+        const long long base = tile * kTile + r0;
+        {   // Fourier features of this wave's 16 points; lane: point lr, frequencies 8lg..8lg+7
+            const long long pi = min(base + lr, n - 1);
+            const float px = qx[pi * qs], py = qy[pi * qs], pz = qz[pi * qs];
+#pragma unroll
+            for (int f = 8 * lg; f < 8 * lg + 8; ++f) {
+                const float arg = 6.283185307179586f * fmaf(sG[3 * f], px, fmaf(sG[3 * f + 1], py, sG[3 * f + 2] * pz));
+                float s, c;
+                sincosf(arg, &s, &c);
+                const unsigned short bs = f2bf(s), bc = f2bf(c);
+                sA[(r0 + lr) * kLd + f] = bs;
+                sA[(r0 + lr) * kLd + kFreq + f] = bc;
+                if (TRAIN && base + lr < n) {
+                    T.x[(base + lr) * 128 + f] = bs;
+                    T.x[(base + lr) * 128 + kFreq + f] = bc;
+                }
+            }
+        }
+        __syncthreads();
+        v4f acc[8];
+        for (int l = 0; l < 4; ++l) {
+            if (l == 0) mma_rows16<64>(sA, kLd, sW0, kLd0, r0, acc);
+            else mma_rows16<128>(sA, kLd, sW[l - 1], kLd, r0, acc);
+            __syncthreads();   // every lane's reads of this wave's rows are done before they are overwritten
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int c = 16 * t + lr;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = r0 + 4 * lg + i;
+                    const float zz = acc[t][i] + sB[l][c];
+                    const unsigned short xb = f2bf(gelu(zz));
+                    sA[r * kLd + c] = xb;
+                    if (TRAIN && tile * kTile + r < n) {
+                        const long long row = tile * kTile + r;
+                        T.z[((long long)l * T.cap + row) * 128 + c] = zz;
+                        T.x[((long long)(l + 1) * T.cap + row) * 128 + c] = xb;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        {   // output layer: 4 lanes per row, 32 columns each
+            const int r = r0 + (lane >> 2);
+            const int c0 = (lane & 3) * 32;
+            float s = 0.f;
+#pragma unroll 8
+            for (int c = c0; c < c0 + 32; ++c) s = fmaf(bf2f(sA[r * kLd + c]), sW4[c], s);
+            s += __shfl_xor(s, 1);
+            s += __shfl_xor(s, 2);
+            const long long row = tile * kTile + r;
+            if ((lane & 3) == 0 && row < n) {
+                y[row] = s + b4;
+                if (TRAIN) T.y[row] = s + b4;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Backward pass through the activations: dy, then dz_3 .. dz_0 (bf16, row-major).
+__global__ __launch_bounds__(256) void k_bwd(Dev P, long long n, const float* __restrict__ tgt, float inv_n, Train T) {
+    __shared__ unsigned short sW[3][128 * kLd];   // W1..W3 as [in][out]
+    __shared__ unsigned short sA[kTile * kLd];
+    __shared__ float sW4[128];
+    for (int l = 0; l < 3; ++l)
+        for (int i = threadIdx.x; i < 128 * 128; i += 256) sW[l][(i >> 7) * kLd + (i & 127)] = P.wb[l * 16384 + i];
+    for (int i = threadIdx.x; i < 128; i += 256) sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int r0 = wave * 16;
+    for (long long tile = blockIdx.x; tile * kTile < n; tile += gridDim.x) {
+        // dz_3 = (dy w4) * gelu'(z_3), in the accumulator layout
+        for (int t = 0; t < 8; ++t) {
+            const int c = 16 * t + lr;
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + 4 * lg + i;
+                const long long row = tile * kTile + r;
+                float dz = 0.f;
+                if (row < n) {
+                    const float dy = 2.f * (T.y[row] - tgt[row]) * inv_n;
+                    if (t == 0 && lr == 0) T.dy[row] = dy;
+                    dz = dy * sW4[c] * gelu_grad(T.z[(3 * T.cap + row) * 128 + c]);
+                }
+                const unsigned short b = f2bf(dz);
+                sA[r * kLd + c] = b;
+                if (row < n) T.dz[(3 * T.cap + row) * 128 + c] = b;
+            }
+        }
+        __syncthreads();
+        v4f acc[8];
+        for (int l = 3; l >= 1; --l) {
+            // dx_l = dz_l W_l^T: B[k][j] = W_l[j][k] is row j of W_l ([in][out])
+            mma_rows16<128>(sA, kLd, sW[l - 1], kLd, r0, acc);
+            __syncthreads();
+            for (int t = 0; t < 8; ++t) {
+                const int c = 16 * t + lr;
+                for (int i = 0; i < 4; ++i) {
+                    const int r = r0 + 4 * lg + i;
+                    const long long row = tile * kTile + r;
+                    float dz = 0.f;
+                    if (row < n) dz = acc[t][i] * gelu_grad(T.z[((long long)(l - 1) * T.cap + row) * 128 + c]);
+                    const unsigned short b = f2bf(dz);
+                    sA[r * kLd + c] = b;
+                    if (row < n) T.dz[((long long)(l - 1) * T.cap + row) * 128 + c] = b;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Weight gradients of one layer for one chunk of rows: dW = x^T dz on MFMA,
+// db = column sums; blockIdx.y = layer (4 = output layer on the VALU).
+__global__ __launch_bounds__(256) void k_wgrad(long long n, Train T) {
+    __shared__ unsigned short sXt[128 * kLdC];
+    __shared__ unsigned short sDt[128 * kLdC];
+    const int layer = blockIdx.y;
+    const long long c0 = (long long)blockIdx.x * kChunk;
+    float* part = T.part + (long long)blockIdx.x * (kNParams + 1);
+    if (layer == 4) {
+        if (threadIdx.x < 129) {
+            float s = 0.f;
+            for (int m = 0; m < kChunk; ++m) {
+                const long long row = c0 + m;
+                if (row >= n) break;
+                const float dy = T.dy[row];
+                s += threadIdx.x < 128 ? bf2f(T.x[(4 * T.cap + row) * 128 + threadIdx.x]) * dy : dy;
+            }
+            if (threadIdx.x < 128) part[kOffW[4] + threadIdx.x] = s;
+            else part[kOffB[4]] = s;
+        } else if (threadIdx.x == 129) {   // loss partial of this chunk
+            float s = 0.f;
+            for (int m = 0; m < kChunk; ++m) {
+                const long long row = c0 + m;
+                if (row >= n) break;
+                const float d = T.dy[row];
+                s += d * d;
+            }
+            part[kNParams] = s;   // sum of dy^2; the host turns it into the loss
+        }
+        return;
+    }
+    const int kin = layer == 0 ? 64 : 128;
+    for (int idx = threadIdx.x; idx < kChunk * 128; idx += 256) {
+        const int m = idx >> 7, j = idx & 127;
+        const long long row = c0 + m;
+        const bool ok = row < n;
+        if (j < kin) sXt[j * kLdC + m] = ok ? T.x[((long long)layer * T.cap + row) * 128 + j] : (unsigned short)0;
+        sDt[j * kLdC + m] = ok ? T.dz[((long long)layer * T.cap + row) * 128 + j] : (unsigned short)0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int rows_per_wave = kin / 4;   // 16 or 32
+    for (int rt = 0; rt < rows_per_wave / 16; ++rt) {
+        const int i0 = wave * rows_per_wave + 16 * rt;
+        v4f acc[8];
+        mma_rows16<kChunk>(sXt, kLdC, sDt, kLdC, i0, acc);
+        for (int t = 0; t < 8; ++t)
+            for (int v = 0; v < 4; ++v)
+                part[kOffW[layer] + (i0 + 4 * lg + v) * 128 + 16 * t + lr] = acc[t][v];
+    }
+    if (threadIdx.x < 128) {
+        float s = 0.f;
+        for (int m = 0; m < kChunk; ++m) s += bf2f(sDt[threadIdx.x * kLdC + m]);
+        part[kOffB[layer] + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_reduce(const float* __restrict__ part, int nchunk, float* __restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > kNParams) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunk; ++c) s += part[(long long)c * (kNParams + 1) + p];
+    grad[p] = s;
+}
+
+// bf16 copies of one master parameter in the layouts the kernels read
+__device__ __forceinline__ void pack_one(const Dev& P, int p, float w) {
+    for (int l = 0; l < 4; ++l) {
+        if (p >= kOffW[l] && p < kOffB[l]) {
+            const int kin = l == 0 ? 64 : 128;
+            const int k = (p - kOffW[l]) / 128, o = (p - kOffW[l]) % 128;
+            const unsigned short b = f2bf(w);
+            P.wf[(l == 0 ? 0 : 8192 + (l - 1) * 16384) + o * kin + k] = b;
+            if (l >= 1) P.wb[(l - 1) * 16384 + k * 128 + o] = b;
+            return;
+        }
+    }
+    if (p >= kOffW[4] && p < kOffB[4]) P.wf[8192 + 3 * 16384 + (p - kOffW[4])] = f2bf(w);
+}
+
+__global__ void k_pack(Dev P) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < kNParams) pack_one(P, p, P.master[p]);
+}
+
+__global__ void k_adam(Dev P, const float* __restrict__ grad, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNParams) return;
+    const float g = grad[p];
+    const float m = b1 * P.m[p] + (1.f - b1) * g;
+    const float v = b2 * P.v[p] + (1.f - b2) * g * g;
+    P.m[p] = m;
+    P.v[p] = v;
+    const float w = P.master[p] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+    P.master[p] = w;
+    pack_one(P, p, w);
+}
+
+// ---- band fallback: compaction by ballot / mbcnt, gather, scatter
+
+__global__ void k_reset_int(int* c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+}
+
+__global__ void k_band_select(const float* __restrict__ y, long long n, float band, int* __restrict__ count,
+                              long long* __restrict__ idx, unsigned char* __restrict__ mask) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const bool f = i < n && fabsf(y[i] - 0.5f) < band;
+    if (mask && i < n) mask[i] = f ? 1 : 0;
+    const unsigned long long b = __builtin_amdgcn_ballot_w64(f);
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0 && b) base = atomicAdd(count, __popcll(b));
+    base = __shfl(base, 0);
+    if (f) {
+        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0));
+        idx[base + rank] = i;
+    }
+}
+
+__global__ void k_gather(const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
+                         long long qs, const long long* __restrict__ idx, const int* __restrict__ count,
+                         float* __restrict__ out) {
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j >= *count) return;
+    const long long i = idx[j];
+    out[3 * j] = qx[i * qs];
+    out[3 * j + 1] = qy[i * qs];
+    out[3 * j + 2] = qz[i * qs];
+}
+
+__global__ void k_scatter(const float* __restrict__ wc, const long long* __restrict__ idx, const int* __restrict__ count,
+                          float* __restrict__ w) {
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j >= *count) return;
+    w[idx[j]] = wc[j];
+}
+
+// host-side parameter initialisation: a splitmix64 stream, Box-Muller normals
+struct Rng {
+    unsigned long long s;
+    unsigned long long next() {
+        unsigned long long z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uni() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+    double normal() { return std::sqrt(-2.0 * std::log(uni())) * std::cos(6.283185307179586 * uni()); }
+};
+
+}  // namespace mlp
+}  // namespace gwn
+
+struct gwn_mlp_s {
+    int device = 0;
+    gwn::mlp::Dev d{};
+    gwn::mlp::Train t{};
+    long long step = 0;
+    float* scratch_w = nullptr;      // compacted fallback outputs
+    float* scratch_q = nullptr;      // compacted fallback coordinates
+    long long* scratch_idx = nullptr;
+    int* scratch_cnt = nullptr;
+    int* scratch_chi = nullptr;
+    long long scratch_cap = 0;
+};
+
+namespace gwn {
+
+using namespace mlp;
+
+namespace {
+
+void free_train(gwn_mlp_s* h) {
+    (void)hipFree(h->t.x);
+    (void)hipFree(h->t.z);
+    (void)hipFree(h->t.dz);
+    (void)hipFree(h->t.y);
+    (void)hipFree(h->t.dy);
+    (void)hipFree(h->t.part);
+    (void)hipFree(h->t.grad);
+    h->t = Train{};
+}
+
+gwn_status ensure_train(gwn_mlp_s* h, long long n) {
+    if (h->t.cap >= n) return GWN_OK;
+    free_train(h);
+    const long long cap = std::max<long long>(n, 1024);
+    const long long nchunk = (cap + kChunk - 1) / kChunk;
+    GWN_HIP_TRY(hipMalloc((void**)&h->t.x, sizeof(unsigned short) * 5 * cap * 128));
+    GWN_HIP_TRY(hipMalloc((void**)&h->t.z, sizeof(float) * 4 * cap * 128));
+    GWN_HIP_TRY(hipMalloc((void**)&h->t.dz, sizeof(unsigned short) * 4 * cap * 128));
+    GWN_HIP_TRY(hipMalloc((void**)&h->t.y, sizeof(float) * cap));
+    GWN_HIP_TRY(hipMalloc((void**)&h->t.dy, sizeof(float) * cap));
+    GWN_HIP_TRY(hipMalloc((void**)&h->t.part, sizeof(float) * nchunk * (kNParams + 1)));
+    GWN_HIP_TRY(hipMalloc((void**)&h->t.grad, sizeof(float) * (kNParams + 1)));
+    h->t.cap = cap;
+    return GWN_OK;
+}
+
+gwn_status ensure_scratch(gwn_mlp_s* h, long long n) {
+    if (h->scratch_cap >= n) return GWN_OK;
+    (void)hipFree(h->scratch_w);
+    (void)hipFree(h->scratch_q);
+    (void)hipFree(h->scratch_idx);
+    (void)hipFree(h->scratch_chi);
+    const long long cap = std::max<long long>(n, 1024);
+    GWN_HIP_TRY(hipMalloc((void**)&h->scratch_w, sizeof(float) * cap));
+    GWN_HIP_TRY(hipMalloc((void**)&h->scratch_q, sizeof(float) * 3 * cap));
+    GWN_HIP_TRY(hipMalloc((void**)&h->scratch_idx, sizeof(long long) * cap));
+    GWN_HIP_TRY(hipMalloc((void**)&h->scratch_chi, sizeof(int) * cap));
+    if (!h->scratch_cnt) GWN_HIP_TRY(hipMalloc((void**)&h->scratch_cnt, sizeof(int)));
+    h->scratch_cap = cap;
+    return GWN_OK;
+}
+
+int fwd_grid(long long n) {
+    const long long tiles = (n + kTile - 1) / kTile;
+    return (int)std::max<long long>(1, std::min<long long>(tiles, 1024));
+}
+
+}  // namespace
+
+void mlp_release(gwn_mlp_s* h) {
+    if (!h) return;
+    (void)hipFree(h->d.master);
+    (void)hipFree(h->d.m);
+    (void)hipFree(h->d.v);
+    (void)hipFree(h->d.G);
+    (void)hipFree(h->d.wf);
+    (void)hipFree(h->d.wb);
+    free_train(h);
+    (void)hipFree(h->scratch_w);
+    (void)hipFree(h->scratch_q);
+    (void)hipFree(h->scratch_idx);
+    (void)hipFree(h->scratch_chi);
+    (void)hipFree(h->scratch_cnt);
+    delete h;
+}
+
+gwn_status mlp_create(uint64_t seed, double sigma, gwn_mlp_s** out) {
+    gwn_mlp_s* h = new (std::nothrow) gwn_mlp_s();
+    if (!h) return GWN_E_OOM;
+    struct Guard {
+        gwn_mlp_s* h;
+        ~Guard() { if (h) mlp_release(h); }
+    } guard{h};
+    GWN_HIP_TRY(hipGetDevice(&h->device));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.master, sizeof(float) * kNParams));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.m, sizeof(float) * kNParams));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.v, sizeof(float) * kNParams));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.G, sizeof(float) * 96));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.wf, sizeof(unsigned short) * kWf));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.wb, sizeof(unsigned short) * kWb));
+    Rng r{seed};
+    std::vector<float> G(96), theta(kNParams, 0.f);
+    for (float& g : G) g = (float)(sigma * r.normal());
+    const int fan_in[5] = {64, 128, 128, 128, 128};
+    for (int l = 0; l < 5; ++l) {
+        const double a = std::sqrt(6.0 / fan_in[l]);   // uniform He-style bound
+        for (int p = kOffW[l]; p < kOffB[l]; ++p) theta[p] = (float)(a * (2.0 * r.uni() - 1.0));
+    }
+    std::vector<float> zeros(kNParams, 0.f);
+    GWN_HIP_TRY(hipMemcpy(h->d.G, G.data(), sizeof(float) * 96, hipMemcpyHostToDevice));
+    GWN_HIP_TRY(hipMemcpy(h->d.master, theta.data(), sizeof(float) * kNParams, hipMemcpyHostToDevice));
+    GWN_HIP_TRY(hipMemcpy(h->d.m, zeros.data(), sizeof(float) * kNParams, hipMemcpyHostToDevice));
+    GWN_HIP_TRY(hipMemcpy(h->d.v, zeros.data(), sizeof(float) * kNParams, hipMemcpyHostToDevice));
+    k_pack<<<(kNParams + 255) / 256, 256>>>(h->d);
+    GWN_HIP_TRY(hipGetLastError());
+    GWN_HIP_TRY(hipDeviceSynchronize());
+    guard.h = nullptr;
+    *out = h;
+    return GWN_OK;
+}
+
+gwn_status mlp_get_state(gwn_mlp_s* h, float* theta, float* m, float* v, float* G, int64_t* step) {
+    GWN_HIP_TRY(hipDeviceSynchronize());
+    if (theta) GWN_HIP_TRY(hipMemcpy(theta, h->d.master, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    if (m) GWN_HIP_TRY(hipMemcpy(m, h->d.m, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    if (v) GWN_HIP_TRY(hipMemcpy(v, h->d.v, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    if (G) GWN_HIP_TRY(hipMemcpy(G, h->d.G, sizeof(float) * 96, hipMemcpyDeviceToHost));
+    if (step) *step = h->step;
+    return GWN_OK;
+}
+
+gwn_status mlp_set_state(gwn_mlp_s* h, const float* theta, const float* m, const float* v, const float* G,
+                         int64_t step) {
+    GWN_HIP_TRY(hipDeviceSynchronize());
+    if (theta) GWN_HIP_TRY(hipMemcpy(h->d.master, theta, sizeof(float) * kNParams, hipMemcpyHostToDevice));
+    if (m) GWN_HIP_TRY(hipMemcpy(h->d.m, m, sizeof(float) * kNParams, hipMemcpyHostToDevice));
+    if (v) GWN_HIP_TRY(hipMemcpy(h->d.v, v, sizeof(float) * kNParams, hipMemcpyHostToDevice));
+    if (G) GWN_HIP_TRY(hipMemcpy(h->d.G, G, sizeof(float) * 96, hipMemcpyHostToDevice));
+    if (step >= 0) h->step = step;
+    k_pack<<<(kNParams + 255) / 256, 256>>>(h->d);
+    GWN_HIP_TRY(hipGetLastError());
+    GWN_HIP_TRY(hipDeviceSynchronize());
+    return GWN_OK;
+}
+
+gwn_status mlp_forward(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t n,
+                       float* y, hipStream_t st) {
+    if (n == 0) return GWN_OK;
+    k_fwd<false><<<fwd_grid(n), 256, 0, st>>>(h->d, qx, qy, qz, qs, n, y, Train{});
+    GWN_HIP_TRY(hipGetLastError());
+    return GWN_OK;
+}
+
+gwn_status mlp_grad(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs, const float* tgt,
+                    int64_t n, hipStream_t st) {
+    gwn_status s = ensure_train(h, n);
+    if (s != GWN_OK) return s;
+    k_fwd<true><<<fwd_grid(n), 256, 0, st>>>(h->d, qx, qy, qz, qs, n, h->t.y, h->t);
+    GWN_HIP_TRY(hipGetLastError());
+    k_bwd<<<fwd_grid(n), 256, 0, st>>>(h->d, n, tgt, 1.0f / (float)n, h->t);
+    GWN_HIP_TRY(hipGetLastError());
+    const int nchunk = (int)((n + kChunk - 1) / kChunk);
+    k_wgrad<<<dim3(nchunk, 5), 256, 0, st>>>(n, h->t);
+    GWN_HIP_TRY(hipGetLastError());
+    k_reduce<<<(kNParams + 1 + 255) / 256, 256, 0, st>>>(h->t.part, nchunk, h->t.grad);
+    GWN_HIP_TRY(hipGetLastError());
+    return GWN_OK;
+}
+
+gwn_status mlp_loss_grad(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs,
+                         const float* tgt, int64_t n, float* grad_out, float* loss_out, hipStream_t st) {
+    gwn_status s = mlp_grad(h, qx, qy, qz, qs, tgt, n, st);
+    if (s != GWN_OK) return s;
+    if (grad_out)
+        GWN_HIP_TRY(hipMemcpyAsync(grad_out, h->t.grad, sizeof(float) * kNParams, hipMemcpyDeviceToDevice, st));
+    if (loss_out) {   // sum(dy^2) = sum(4 d^2 / n^2)  ->  loss = mean(d^2) = sum(dy^2) n / 4
+        float sdy2 = 0.f;
+        GWN_HIP_TRY(hipMemcpyAsync(&sdy2, h->t.grad + kNParams, sizeof(float), hipMemcpyDeviceToHost, st));
+        GWN_HIP_TRY(hipStreamSynchronize(st));
+        *loss_out = sdy2 * (float)n / 4.0f;
+    }
+    return GWN_OK;
+}
+
+gwn_status mlp_train_step(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs,
+                          const float* tgt, int64_t n, float lr, float* loss_out, hipStream_t st) {
+    gwn_status s = mlp_loss_grad(h, qx, qy, qz, qs, tgt, n, nullptr, loss_out, st);
+    if (s != GWN_OK) return s;
+    h->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)h->step));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)h->step));
+    k_adam<<<(kNParams + 255) / 256, 256, 0, st>>>(h->d, h->t.grad, lr, b1, b2, eps, c1, c2);
+    GWN_HIP_TRY(hipGetLastError());
+    return GWN_OK;
+}
+
+gwn_status surrogate_query(gwn_mlp_s* h, const gwn_mesh_s* mesh, const float* qx, const float* qy, const float* qz,
+                           int64_t qs, int64_t n, float band, float* w, unsigned char* mask, int64_t* nfallback,
+                           hipStream_t st) {
+    if (n == 0) {
+        if (nfallback) *nfallback = 0;
+        return GWN_OK;
+    }
+    gwn_status s = ensure_scratch(h, n);
+    if (s != GWN_OK) return s;
+    s = mlp_forward(h, qx, qy, qz, qs, n, w, st);
+    if (s != GWN_OK) return s;
+    k_reset_int<<<1, 64, 0, st>>>(h->scratch_cnt);
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    k_band_select<<<nb, 256, 0, st>>>(w, n, band, h->scratch_cnt, h->scratch_idx, mask);
+    k_gather<<<nb, 256, 0, st>>>(qx, qy, qz, qs, h->scratch_idx, h->scratch_cnt, h->scratch_q);
+    GWN_HIP_TRY(hipGetLastError());
+    // exact crossing counts and boundary term on the compacted points (device count)
+    s = query_batch_devcount(mesh, h->scratch_q, h->scratch_q + 1, h->scratch_q + 2, 3, n, h->scratch_cnt,
+                             h->scratch_chi, h->scratch_w, st);
+    if (s != GWN_OK) return s;
+    k_scatter<<<nb, 256, 0, st>>>(h->scratch_w, h->scratch_idx, h->scratch_cnt, w);
+    GWN_HIP_TRY(hipGetLastError());
+    if (nfallback) {
+        int c = 0;
+        GWN_HIP_TRY(hipMemcpyAsync(&c, h->scratch_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+        GWN_HIP_TRY(hipStreamSynchronize(st));
+        *nfallback = c;
+    }
+    return GWN_OK;
+}
+
+}  // namespace gwn

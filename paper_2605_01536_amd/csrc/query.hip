@@ -39,9 +39,11 @@ __device__ double boundary_sum(const MeshView& mv, int qqx, int qqy, T pxs, T py
 
 __global__ __launch_bounds__(kChiBlock) void k_chi_batch(MeshView mv, const float* __restrict__ qx,
                                                          const float* __restrict__ qy, const float* __restrict__ qz,
-                                                         long long qs, long long nq, int* __restrict__ chi) {
+                                                         long long qs, long long nq, const int* __restrict__ ndev,
+                                                         int* __restrict__ chi) {
     __shared__ int stk[kLdsStack * kChiBlock];
     const long long i = blockIdx.x * (long long)kChiBlock + threadIdx.x;
+    if (ndev) nq = min(nq, (long long)*ndev);   // count known only on the device
     if (i >= nq) return;
     const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
     chi[i] = q.inbox ? chi_up(mv, q, stk + threadIdx.x) : 0;
@@ -52,8 +54,11 @@ __global__ __launch_bounds__(kChiBlock) void k_chi_batch(MeshView mv, const floa
 template <class T>
 __global__ __launch_bounds__(256) void k_bdry_batch(MeshView mv, const float* __restrict__ qx, const float* __restrict__ qy,
                                                     const float* __restrict__ qz, long long qs, long long nq,
-                                                    const int* __restrict__ chi, T* __restrict__ w) {
+                                                    const int* __restrict__ ndev, const int* __restrict__ chi,
+                                                    T* __restrict__ w) {
     const long long i = blockIdx.x * 256ll + threadIdx.x;
+    if (ndev) nq = min(nq, (long long)*ndev);   // count known only on the device
+    if (nq <= 0 || blockIdx.x * 256ll >= nq) return;
     const long long ii = i < nq ? i : nq - 1;
     const float px = qx[ii * qs], py = qy[ii * qs], pz = qz[ii * qs];
     const QPoint q = quantize_point(px, py, pz, mv.g);
@@ -229,10 +234,11 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
     int* chi = chi_out;
     if (!chi) GWN_HIP_TRY(hipMallocAsync((void**)&chi, sizeof(int) * (size_t)nq, st));
     const MeshView mv = m->view();
-    k_chi_batch<<<(unsigned)((nq + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, qx, qy, qz, qs, nq, chi);
+    k_chi_batch<<<(unsigned)((nq + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, qx, qy, qz, qs, nq, nullptr,
+                                                                                    chi);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
-        k_bdry_batch<T><<<(unsigned)((nq + 255) / 256), 256, 0, st>>>(mv, qx, qy, qz, qs, nq, chi, w);
+        k_bdry_batch<T><<<(unsigned)((nq + 255) / 256), 256, 0, st>>>(mv, qx, qy, qz, qs, nq, nullptr, chi, w);
         e = hipGetLastError();
     }
     if (!chi_out) (void)hipFreeAsync(chi, st);
@@ -265,6 +271,18 @@ gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, co
     if (nq == 0) return GWN_OK;
     if (prec == GWN_PREC_FP64) return launch_batch<double>(m, qx, qy, qz, qs, nq, (double*)w, chi_out, st);
     return launch_batch<float>(m, qx, qy, qz, qs, nq, (float*)w, chi_out, st);
+}
+
+gwn_status query_batch_devcount(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
+                                int64_t nmax, const int* ndev, int* chi, float* w, hipStream_t st) {
+    if (nmax == 0) return GWN_OK;
+    const MeshView mv = m->view();
+    k_chi_batch<<<(unsigned)((nmax + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, qx, qy, qz, qs, nmax, ndev,
+                                                                                      chi);
+    GWN_HIP_TRY(hipGetLastError());
+    k_bdry_batch<float><<<(unsigned)((nmax + 255) / 256), 256, 0, st>>>(mv, qx, qy, qz, qs, nmax, ndev, chi, w);
+    GWN_HIP_TRY(hipGetLastError());
+    return GWN_OK;
 }
 
 gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims, int prec,

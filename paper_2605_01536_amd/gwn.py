@@ -217,3 +217,145 @@ class MultiPlan:
             self.close()
         except Exception:
             pass
+
+
+MLP_NPARAMS = 57985
+
+
+def _load_mlp(L):
+    if getattr(L, "_mlp_ready", False):
+        return
+    vp, i64, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float
+    L.gwn_mlp_create.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(vp)]
+    L.gwn_mlp_destroy.argtypes = [vp]
+    L.gwn_mlp_get_state.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]
+    L.gwn_mlp_set_state.argtypes = [vp, vp, vp, vp, vp, i64]
+    L.gwn_mlp_forward.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp]
+    L.gwn_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, ctypes.POINTER(f32), vp]
+    L.gwn_mlp_train_step.argtypes = [vp, vp, vp, vp, i64, vp, i64, f32, ctypes.POINTER(f32), vp]
+    L.gwn_surrogate_query.argtypes = [vp, vp, vp, vp, vp, i64, i64, f32, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
+    for f in ("gwn_mlp_create", "gwn_mlp_destroy", "gwn_mlp_get_state", "gwn_mlp_set_state", "gwn_mlp_forward",
+              "gwn_mlp_loss_grad", "gwn_mlp_train_step", "gwn_surrogate_query"):
+        getattr(L, f).restype = ctypes.c_int
+    L._mlp_ready = True
+
+
+class Surrogate:
+    """Fourier-feature MLP trained and evaluated by the library's MFMA kernels."""
+
+    def __init__(self, seed: int = 0, sigma: float = 2.0):
+        L = load()
+        _load_mlp(L)
+        self._h = ctypes.c_void_p()
+        _check(L.gwn_mlp_create(int(seed), float(sigma), ctypes.byref(self._h)))
+
+    def state(self) -> dict:
+        import numpy as np
+        th = np.zeros(MLP_NPARAMS, np.float32)
+        m = np.zeros(MLP_NPARAMS, np.float32)
+        v = np.zeros(MLP_NPARAMS, np.float32)
+        G = np.zeros(96, np.float32)
+        step = ctypes.c_int64(0)
+        _check(load().gwn_mlp_get_state(self._h, th.ctypes.data, m.ctypes.data, v.ctypes.data, G.ctypes.data,
+                                        ctypes.byref(step)))
+        return {"theta": th, "m": m, "v": v, "G": G.reshape(32, 3), "step": int(step.value)}
+
+    def load_state(self, st: dict):
+        import numpy as np
+        arrs = {k: np.ascontiguousarray(st[k], np.float32).ravel() for k in ("theta", "m", "v", "G") if k in st}
+        p = {k: (arrs[k].ctypes.data if k in arrs else None) for k in ("theta", "m", "v", "G")}
+        _check(load().gwn_mlp_set_state(self._h, p["theta"], p["m"], p["v"], p["G"], int(st.get("step", -1))))
+
+    def save(self, path: str):
+        import numpy as np
+        st = self.state()
+        np.savez(path, theta=st["theta"], m=st["m"], v=st["v"], G=st["G"], step=np.int64(st["step"]))
+
+    def load(self, path: str):
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            self.load_state({"theta": z["theta"], "m": z["m"], "v": z["v"], "G": z["G"], "step": int(z["step"])})
+
+    def forward(self, Q, out=None, stream=None):
+        import torch
+        Q = Q.contiguous()
+        n = Q.shape[0]
+        if out is None:
+            out = torch.empty(n, device=Q.device, dtype=torch.float32)
+        b = _ptr(Q)
+        _check(load().gwn_mlp_forward(self._h, b, b + 4, b + 8, 3, n, _ptr(out), _stream(stream)))
+        return out
+
+    def loss_grad(self, Q, target, stream=None):
+        import torch
+        Q = Q.contiguous()
+        target = target.contiguous().float()
+        g = torch.empty(MLP_NPARAMS, device=Q.device, dtype=torch.float32)
+        loss = ctypes.c_float(0)
+        b = _ptr(Q)
+        _check(load().gwn_mlp_loss_grad(self._h, b, b + 4, b + 8, 3, _ptr(target), Q.shape[0], _ptr(g),
+                                        ctypes.byref(loss), _stream(stream)))
+        return float(loss.value), g
+
+    def train_step(self, Q, target, lr: float, want_loss: bool = True, stream=None):
+        Q = Q.contiguous()
+        target = target.contiguous().float()
+        loss = ctypes.c_float(0)
+        b = _ptr(Q)
+        _check(load().gwn_mlp_train_step(self._h, b, b + 4, b + 8, 3, _ptr(target), Q.shape[0], float(lr),
+                                         ctypes.byref(loss) if want_loss else None, _stream(stream)))
+        return float(loss.value) if want_loss else None
+
+    def query(self, mesh: Mesh, Q, band: float, out=None, want_mask: bool = False, stream=None):
+        """Prediction, with exact re-evaluation where |prediction - 1/2| < band."""
+        import torch
+        Q = Q.contiguous()
+        n = Q.shape[0]
+        if out is None:
+            out = torch.empty(n, device=Q.device, dtype=torch.float32)
+        mask = torch.empty(n, device=Q.device, dtype=torch.uint8) if want_mask else None
+        nfb = ctypes.c_int64(0)
+        b = _ptr(Q)
+        _check(load().gwn_surrogate_query(self._h, mesh.handle, b, b + 4, b + 8, 3, n, float(band), _ptr(out),
+                                          _ptr(mask) if mask is not None else None, ctypes.byref(nfb),
+                                          _stream(stream)))
+        return (out, mask, int(nfb.value)) if want_mask else (out, int(nfb.value))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().gwn_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def train_surrogate(sur: Surrogate, X, T, epochs: int = 4, batch: int = 8192, lr: float = 2e-3,
+                    lr_final: float = 1e-4, seed: int = 0, log=None):
+    """Mini-batch Adam over (X, T) with a cosine learning-rate decay; the
+    shuffling permutation comes from torch's seeded generator."""
+    import math
+
+    import torch
+    n = X.shape[0]
+    g = torch.Generator(device=X.device)
+    g.manual_seed(int(seed))
+    steps = epochs * ((n + batch - 1) // batch)
+    k = 0
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, device=X.device, generator=g)
+        for a in range(0, n, batch):
+            idx = perm[a:a + batch]
+            lr_k = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * k / max(1, steps - 1)))
+            want = (k % 200 == 0) or (k == steps - 1)
+            loss = sur.train_step(X[idx], T[idx], lr_k, want_loss=want)
+            if want:
+                losses.append((k, loss))
+                if log:
+                    log(f"step {k}/{steps} loss {loss:.4e} lr {lr_k:.2e}")
+            k += 1
+    return losses
