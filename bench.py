@@ -55,6 +55,13 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["grid", "batch", "batched", "surrogate"], default="grid",
+                    help="grid: the headline 512^3 grid on the 1M-triangle soup (default); batch: 2M points on the "
+                         "torus soup; batched: 256 soups in one persistent graph; surrogate: MLP + exact fallback")
+    ap.add_argument("--n-mesh", type=int, default=256, help="soups in the batched workload")
+    ap.add_argument("--epochs", type=int, default=16, help="surrogate training epochs")
+    ap.add_argument("--sigma", type=float, default=4.0, help="surrogate Fourier-feature scale")
+    ap.add_argument("--lr", type=float, default=2e-3, help="surrogate peak learning rate")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM counters) and exit")
     return ap.parse_args()
@@ -85,6 +92,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.workload != "grid":
+        {"batch": bench_batch, "batched": bench_batched, "surrogate": bench_surrogate}[args.workload](args)
         return
     t0 = time.time()
     soup, grid = W.config4(n=args.n)
@@ -179,6 +189,145 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _timed(fn, steps, warmup, stream):
+    """Average ms of fn() over `steps` launches bracketed by HIP events on `stream`."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps, (time.perf_counter() - t0) * 1e3 / steps
+
+
+def _emit(metric, value, unit, args, ms, config, extra=None, dtype="f32"):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": config}
+    if extra:
+        out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """2M points (1M uniform in the bbox, 1M near the surface) on the ~85k-triangle torus soup."""
+    import torch
+    from paper_2605_01536_amd import gwn, workloads as W
+    soup, Q = W.config2()
+    mesh = gwn.Mesh(torch.from_numpy(soup.V).cuda(), torch.from_numpy(soup.F).cuda())
+    info = mesh.info()
+    Qd = torch.from_numpy(Q).cuda()
+    w = torch.empty(Q.shape[0], device="cuda", dtype=torch.float64 if args.prec == "fp64" else torch.float32)
+    st = torch.cuda.current_stream()
+    ev_ms, wall_ms = _timed(lambda: gwn.query_batch(mesh, Qd, prec=args.prec, out=w, stream=st), args.steps,
+                            args.warmup, st)
+    pairs = Q.shape[0] * info["nboundary"]
+    print(f"[bench] batch {Q.shape[0]} pts B={info['nboundary']}: {wall_ms:.1f} ms, {pairs / wall_ms * 1e3:.3e} pairs/s",
+          file=sys.stderr, flush=True)
+    _emit("GWN queries/sec, arbitrary points", Q.shape[0] / (wall_ms / 1e3), "queries/s", args, wall_ms,
+          {"workload": f"torus soup ({info['nf']} tris, {info['nboundary']} boundary edges), 1M uniform + 1M "
+                       f"near-surface points", "precision": args.prec, "pairs_per_s": pairs / (ev_ms / 1e3)},
+          dtype="f32" if args.prec == "fp32" else "f64")
+
+
+def bench_batched(args):
+    """256 ellipsoid-union soups of uneven size in one captured persistent launch, against one
+    gwn_query_batch launch pair per mesh."""
+    import torch
+    from paper_2605_01536_amd import gwn, workloads as W
+    t0 = time.time()
+    soups, queries = W.config3(n_mesh=args.n_mesh)
+    print(f"[bench] generated {len(soups)} soups in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    meshes = [gwn.Mesh(torch.from_numpy(s.V).cuda(), torch.from_numpy(s.F).cuda()) for s in soups]
+    offs = np.concatenate([[0], np.cumsum([q.shape[0] for q in queries])]).astype(np.int64)
+    Q = torch.from_numpy(np.concatenate(queries)).cuda()
+    nq = int(offs[-1])
+    pairs = float(sum((offs[i + 1] - offs[i]) * meshes[i].info()["nboundary"] for i in range(len(meshes))))
+    print(f"[bench] {len(meshes)} meshes built, {nq} queries, {pairs:.3e} pairs", file=sys.stderr, flush=True)
+    st = torch.cuda.current_stream()
+    t = time.time()
+    plan = gwn.MultiPlan(meshes, Q, offs, autotune=True, stream=st)
+    tune_s = time.time() - t
+    inf = plan.info()
+    print(f"[bench] autotune {tune_s:.1f} s -> {inf}", file=sys.stderr, flush=True)
+    ev_ms, wall_ms = _timed(lambda: plan.run(stream=st), args.steps, args.warmup, st)
+    w_ref = torch.empty(nq, device="cuda")
+
+    def per_mesh():
+        for i, m in enumerate(meshes):
+            a, b = int(offs[i]), int(offs[i + 1])
+            gwn.query_batch(m, Q[a:b], out=w_ref[a:b], stream=st)
+
+    ev2, wall2 = _timed(per_mesh, max(1, args.steps // 2), 1, st)
+    same = bool(torch.equal(plan.w, w_ref))
+    print(f"[bench] graph replay {wall_ms:.1f} ms vs per-mesh launches {wall2:.1f} ms; identical={same}",
+          file=sys.stderr, flush=True)
+    _emit("GWN queries/sec, 256 soups in one persistent graph launch", nq / (wall_ms / 1e3), "queries/s", args,
+          wall_ms, {"workload": f"{len(meshes)} ellipsoid-union soups, {nq} queries, {pairs:.3e} pairs",
+                    "pairs_per_s": pairs / (ev_ms / 1e3), "schedule": inf, "autotune_s": tune_s,
+                    "per_mesh_launches_ms": wall2, "graph_speedup_vs_per_mesh": wall2 / wall_ms,
+                    "bitwise_equal_to_per_mesh": same})
+
+
+def bench_surrogate(args):
+    """Train the MLP on 10M method-generated labels of the ~500k-triangle opened-spheres soup, then
+    evaluate 16M uniform points: exact kernel vs network + exact fallback in a band around 1/2."""
+    import torch
+    from paper_2605_01536_amd import gwn, workloads as W
+    soup, Xtr, Xin = W.config5()
+    mesh = gwn.Mesh(torch.from_numpy(soup.V).cuda(), torch.from_numpy(soup.F).cuda())
+    info = mesh.info()
+    st = torch.cuda.current_stream()
+    Xt = torch.from_numpy(Xtr).cuda()
+    Xi = torch.from_numpy(Xin).cuda()
+    del Xtr, Xin
+    t = time.time()
+    Tt = gwn.query_batch(mesh, Xt)
+    torch.cuda.synchronize()
+    label_s = time.time() - t
+    sur = gwn.Surrogate(seed=0, sigma=args.sigma)
+    t = time.time()
+    losses = gwn.train_surrogate(sur, Xt, Tt, epochs=args.epochs, batch=8192, lr=args.lr, lr_final=5e-5,
+                                 log=lambda m: print("[train] " + m, file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    train_s = time.time() - t
+    n = Xi.shape[0]
+    w_ex = torch.empty(n, device="cuda")
+    ex_ev, ex_ms = _timed(lambda: gwn.query_batch(mesh, Xi, out=w_ex, stream=st), args.steps, args.warmup, st)
+    y = torch.empty(n, device="cuda")
+    nn_ev, nn_ms = _timed(lambda: sur.forward(Xi, out=y, stream=st), args.steps, args.warmup, st)
+    err_nn = (y - w_ex).abs()
+    rows = []
+    w_s = torch.empty(n, device="cuda")
+    for band in (0.1, 0.2, 0.3, 0.4, 0.45, 0.5, 0.6):
+        res = {}
+
+        def run():
+            _, res["nfb"] = sur.query(mesh, Xi, band, out=w_s, stream=st)
+
+        ev, ms = _timed(run, args.steps, 1, st)
+        e = (w_s - w_ex).abs()
+        agree = float(((w_s >= 0.5) == (w_ex >= 0.5)).float().mean())
+        rows.append({"band": band, "ms": ms, "queries_per_s": n / (ms / 1e3), "speedup_vs_exact": ex_ms / ms,
+                     "fallback_frac": res["nfb"] / n, "max_abs_err": float(e.max()),
+                     "p99_abs_err": float(torch.quantile(e[::16], 0.99)), "rms_err": float(e.pow(2).mean().sqrt()),
+                     "inside_outside_agreement": agree})
+        print(f"[bench] band {band}: {ms:.1f} ms ({ex_ms / ms:.2f}x exact), fallback {res['nfb'] / n:.3f}, "
+              f"max|err| {rows[-1]['max_abs_err']:.3e}, agree {agree:.5f}", file=sys.stderr, flush=True)
+    best = rows[2]
+    _emit("surrogate+fallback GWN queries/sec (band 0.3)", best["queries_per_s"], "queries/s", args, best["ms"],
+          {"workload": f"opened-spheres soup ({info['nf']} tris, {info['nboundary']} boundary edges), "
+                       f"train 10M / infer 16M uniform points", "exact_ms": ex_ms, "exact_queries_per_s": n / (ex_ms / 1e3),
+                       "network_only_ms": nn_ms, "network_max_abs_err": float(err_nn.max()),
+                       "network_rms_err": float(err_nn.pow(2).mean().sqrt()), "label_s": label_s, "train_s": train_s,
+                       "train_loss": losses[-1][1], "sigma": args.sigma, "epochs": args.epochs, "bands": rows})
 
 
 if __name__ == "__main__":

@@ -2,6 +2,7 @@
 // points, the boundary term per point, and the grid kernel with one ray per
 // column (the arithmetic lives in gwn_kernels.h).
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 
 #include "gwn_kernels.h"
@@ -256,8 +257,20 @@ gwn_status launch_grid_zb(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_o
     return GWN_OK;
 }
 
+// Samples per lane: more samples share more x/y work, fewer leave registers for
+// more resident waves.  GWN_GRID_SAMPLES_PER_LANE (1, 2, 4 or 8) overrides the
+// default choice, which is the largest value the column length fills.
 template <class T>
 gwn_status launch_grid(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out, hipStream_t st) {
+    if (const char* e = std::getenv("GWN_GRID_SAMPLES_PER_LANE")) {
+        switch (std::atoi(e)) {
+            case 1: return launch_grid_zb<T, 1>(m, ga, w, chi_out, st);
+            case 2: return launch_grid_zb<T, 2>(m, ga, w, chi_out, st);
+            case 4: return launch_grid_zb<T, 4>(m, ga, w, chi_out, st);
+            case 8: return launch_grid_zb<T, 8>(m, ga, w, chi_out, st);
+            default: break;
+        }
+    }
     if (ga.nz >= 64 * 8) return launch_grid_zb<T, 8>(m, ga, w, chi_out, st);
     if (ga.nz >= 64 * 4) return launch_grid_zb<T, 4>(m, ga, w, chi_out, st);
     if (ga.nz >= 64 * 2) return launch_grid_zb<T, 2>(m, ga, w, chi_out, st);
