@@ -33,7 +33,7 @@ METRIC = "GWN queries/sec on 1M-tri open soup at max|err|≤1e-4 vs FP64; % roof
 # instruction per 2 clocks (measured on the box; this is the rate behind the
 # 157.3 TFLOP/s FP32 vector figure, which counts an FMA as 2 FLOPs):
 # 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 7.86e13 FP32 VALU slots/s.
-# sqrt and rcp were measured at ~3.1 slots each.
+# sqrt and rcp were measured at 3.0 slots each (csrc/probe/valu_probe.hip).
 N_CU, SIMD_PER_CU, LANES_PER_CLK, CLOCK_HZ = 256, 4, 32, 2.4e9
 PEAK_SLOTS = N_CU * SIMD_PER_CU * LANES_PER_CLK * CLOCK_HZ
 TRANS_SLOTS = 3
@@ -59,9 +59,9 @@ def parse():
                     help="grid: the headline 512^3 grid on the 1M-triangle soup (default); batch: 2M points on the "
                          "torus soup; batched: 256 soups in one persistent graph; surrogate: MLP + exact fallback")
     ap.add_argument("--n-mesh", type=int, default=256, help="soups in the batched workload")
-    ap.add_argument("--epochs", type=int, default=16, help="surrogate training epochs")
-    ap.add_argument("--sigma", type=float, default=4.0, help="surrogate Fourier-feature scale")
-    ap.add_argument("--lr", type=float, default=2e-3, help="surrogate peak learning rate")
+    ap.add_argument("--epochs", type=int, default=32, help="surrogate training epochs")
+    ap.add_argument("--sigma", type=float, default=1.0, help="surrogate Fourier-feature scale")
+    ap.add_argument("--lr", type=float, default=1e-3, help="surrogate peak learning rate")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM counters) and exit")
     return ap.parse_args()
