@@ -55,10 +55,11 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["grid", "batch", "batched", "surrogate"], default="grid",
+    ap.add_argument("--workload", choices=["grid", "batch", "batched", "surrogate", "precision"], default="grid",
                     help="grid: the headline 512^3 grid on the 1M-triangle soup (default); batch: 2M points on the "
                          "torus soup; batched: 256 soups in one persistent graph; surrogate: MLP + exact fallback")
     ap.add_argument("--n-mesh", type=int, default=256, help="soups in the batched workload")
+    ap.add_argument("--sample", type=int, default=20000, help="oracle sample size of the precision workload")
     ap.add_argument("--epochs", type=int, default=32, help="surrogate training epochs")
     ap.add_argument("--sigma", type=float, default=1.0, help="surrogate Fourier-feature scale")
     ap.add_argument("--lr", type=float, default=1e-3, help="surrogate peak learning rate")
@@ -94,7 +95,8 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.workload != "grid":
-        {"batch": bench_batch, "batched": bench_batched, "surrogate": bench_surrogate}[args.workload](args)
+        {"batch": bench_batch, "batched": bench_batched, "surrogate": bench_surrogate,
+         "precision": bench_precision}[args.workload](args)
         return
     t0 = time.time()
     soup, grid = W.config4(n=args.n)
@@ -328,6 +330,49 @@ def bench_surrogate(args):
                        "network_only_ms": nn_ms, "network_max_abs_err": float(err_nn.max()),
                        "network_rms_err": float(err_nn.pow(2).mean().sqrt()), "label_s": label_s, "train_s": train_s,
                        "train_loss": losses[-1][1], "sigma": args.sigma, "epochs": args.epochs, "bands": rows})
+
+
+def bench_precision(args):
+    """The 512^3 grid on the 1M-triangle soup in FP32 and FP64; both compared with the FP64
+    oracle on a random sample of grid points (queries closer than 1e-4 of the diagonal to the
+    surface excluded, crossing counts compared on every sampled point)."""
+    import torch
+
+    import oracle
+    from paper_2605_01536_amd import gwn, workloads as W
+    soup, grid = W.config4(n=args.n)
+    mesh = gwn.Mesh(torch.from_numpy(soup.V).cuda(), torch.from_numpy(soup.F).cuda())
+    info = mesh.info()
+    st = torch.cuda.current_stream()
+    res = {}
+    rng = np.random.default_rng(777)
+    idx = np.sort(rng.choice(grid.n, min(args.sample, grid.n), replace=False))
+    it = torch.from_numpy(idx).cuda()
+    P = W.grid_points(grid, idx)
+    t = time.perf_counter()
+    w_o, _, chi_o, _ = oracle.antipodal(soup.V, soup.F, P, full=True)
+    oracle_s = time.perf_counter() - t
+    diag = float(np.linalg.norm(np.asarray(info["bbox"][3:]) - np.asarray(info["bbox"][:3])))
+    far = oracle.distance(soup.V, soup.F, P, 2e-4 * diag) > 1e-4 * diag
+    print(f"[bench] oracle on {len(idx)} points: {oracle_s:.1f} s", file=sys.stderr, flush=True)
+    for prec in ("fp32", "fp64"):
+        w = torch.empty(grid.n, device="cuda", dtype=torch.float64 if prec == "fp64" else torch.float32)
+        chi = torch.empty(grid.n, device="cuda", dtype=torch.int32)
+        ev, ms = _timed(lambda: gwn.query_grid(mesh, grid.origin, grid.spacing, grid.dims, prec=prec, out=w,
+                                               chi_out=chi, stream=st), args.steps, args.warmup, st)
+        e = np.abs(w[it].double().cpu().numpy() - w_o)[far]
+        chi_ok = bool(np.array_equal(chi[it].cpu().numpy(), chi_o))
+        res[prec] = {"ms": ms, "queries_per_s": grid.n / (ms / 1e3), "max_abs_err": float(e.max()),
+                     "p99_abs_err": float(np.quantile(e, 0.99)), "rms_err": float(np.sqrt(np.mean(e * e))),
+                     "chi_bit_exact": chi_ok}
+        print(f"[bench] {prec}: {ms:.1f} ms, max|err| {e.max():.3e}, chi exact {chi_ok}", file=sys.stderr, flush=True)
+        del w, chi
+        torch.cuda.empty_cache()
+    _emit("GWN queries/sec on 1M-tri open soup, FP32 vs FP64", res["fp32"]["queries_per_s"], "queries/s", args,
+          res["fp32"]["ms"], {"workload": f"opened-spheres soup ({info['nf']} tris, {info['nboundary']} boundary "
+                                          f"edges) on a {args.n}^3 grid", "sample": len(idx),
+                              "compared_off_surface": int(far.sum()), "oracle_s": oracle_s,
+                              "oracle_threads": oracle.num_threads(), "fp32": res["fp32"], "fp64": res["fp64"]})
 
 
 if __name__ == "__main__":

@@ -69,6 +69,7 @@ def lib():
         L.oracle_solid_angle.argtypes = [_F64, _F64, _F64, _F64]
         L.oracle_solid_angle.restype = ctypes.c_double
         L.oracle_distance.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, ctypes.c_double, _F64]
+        L.oracle_distance2.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, ctypes.c_double, ctypes.c_int, _F64]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -157,12 +158,12 @@ def solid_angle(v0, v1, v2, p) -> float:
     return float(lib().oracle_solid_angle(*a))
 
 
-def distance(V, F, Q, cutoff: float):
+def distance(V, F, Q, cutoff: float, use_bins: bool = True):
     """min(distance to the soup, cutoff) per query."""
     V, F = _mesh(V, F)
     Q = _pts(Q)
     d = np.zeros(Q.shape[0])
-    lib().oracle_distance(V, V.shape[0], F, F.shape[0], Q, Q.shape[0], float(cutoff), d)
+    lib().oracle_distance2(V, V.shape[0], F, F.shape[0], Q, Q.shape[0], float(cutoff), int(use_bins), d)
     return d
 
 

@@ -620,16 +620,84 @@ done:
 
 /* distance from each query to the nearest triangle, computed exactly for
  * triangles whose bounding box expanded by `cutoff` contains the query; the
- * result is min(distance, cutoff) (enough to mask near-surface queries). */
-void oracle_distance(const float* V, int64_t nv, const int32_t* F, int64_t nf, const float* Q, int64_t nq,
-                     double cutoff, double* d_out)
+ * result is min(distance, cutoff) (enough to mask near-surface queries).
+ * With use_bins != 0 the candidate triangles come from a uniform x/y bucket
+ * grid over the expanded boxes (same arithmetic, fewer candidates). */
+void oracle_distance2(const float* V, int64_t nv, const int32_t* F, int64_t nf, const float* Q, int64_t nq,
+                      double cutoff, int use_bins, double* d_out)
 {
     (void)nv;
+    int64_t G = 1;
+    double x0 = 0.0, y0 = 0.0, cw = 1.0;
+    int64_t* start = NULL;
+    int64_t* items = NULL;
+    if (use_bins && nf > 0) {
+        double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300;
+        for (int64_t i = 0; i < 3 * nf; ++i) {
+            double x = (double)V[3 * F[i]], y = (double)V[3 * F[i] + 1];
+            if (x < mnx) mnx = x;
+            if (x > mxx) mxx = x;
+            if (y < mny) mny = y;
+            if (y > mxy) mxy = y;
+        }
+        G = (int64_t)sqrt((double)nf / 2.0);
+        if (G < 1) G = 1;
+        if (G > 2048) G = 2048;
+        x0 = mnx - cutoff;
+        y0 = mny - cutoff;
+        double span = fmax(mxx - mnx, mxy - mny) + 2.0 * cutoff;
+        cw = span / (double)G;
+        if (!(cw > 0.0)) cw = 1.0;
+        start = (int64_t*)calloc((size_t)(G * G + 1), sizeof(int64_t));
+        int64_t* fill = NULL;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1) {
+                for (int64_t i = 0; i < G * G; ++i) start[i + 1] += start[i];
+                items = (int64_t*)malloc(sizeof(int64_t) * (size_t)(start[G * G] + 1));
+                fill = (int64_t*)calloc((size_t)(G * G), sizeof(int64_t));
+            }
+            for (int64_t t = 0; t < nf; ++t) {
+                double lx = 1e300, hx = -1e300, ly = 1e300, hy = -1e300;
+                for (int c = 0; c < 3; ++c) {
+                    double x = (double)V[3 * F[3 * t + c]], y = (double)V[3 * F[3 * t + c] + 1];
+                    if (x < lx) lx = x;
+                    if (x > hx) hx = x;
+                    if (y < ly) ly = y;
+                    if (y > hy) hy = y;
+                }
+                int64_t bx0 = (int64_t)floor((lx - cutoff - x0) / cw), bx1 = (int64_t)floor((hx + cutoff - x0) / cw);
+                int64_t by0 = (int64_t)floor((ly - cutoff - y0) / cw), by1 = (int64_t)floor((hy + cutoff - y0) / cw);
+                if (bx0 < 0) bx0 = 0;
+                if (by0 < 0) by0 = 0;
+                if (bx1 >= G) bx1 = G - 1;
+                if (by1 >= G) by1 = G - 1;
+                for (int64_t bx = bx0; bx <= bx1; ++bx)
+                    for (int64_t by = by0; by <= by1; ++by) {
+                        int64_t b = bx * G + by;
+                        if (pass == 0) start[b + 1]++;
+                        else items[start[b] + fill[b]++] = t;
+                    }
+            }
+        }
+        free(fill);
+    }
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < nq; ++i) {
         double p[3] = {(double)Q[3 * i], (double)Q[3 * i + 1], (double)Q[3 * i + 2]};
         double best = cutoff * cutoff;
-        for (int64_t t = 0; t < nf; ++t) {
+        const int64_t* list = NULL;
+        int64_t n = nf;
+        if (start) {
+            int64_t bx = (int64_t)floor((p[0] - x0) / cw), by = (int64_t)floor((p[1] - y0) / cw);
+            if (bx < 0 || by < 0 || bx >= G || by >= G) {
+                n = 0;
+            } else {
+                list = items + start[bx * G + by];
+                n = start[bx * G + by + 1] - start[bx * G + by];
+            }
+        }
+        for (int64_t ii = 0; ii < n; ++ii) {
+            int64_t t = list ? list[ii] : ii;
             double v[3][3];
             int skip = 0;
             for (int a = 0; a < 3 && !skip; ++a) {
@@ -648,6 +716,14 @@ void oracle_distance(const float* V, int64_t nv, const int32_t* F, int64_t nf, c
         }
         d_out[i] = sqrt(best);
     }
+    free(start);
+    free(items);
+}
+
+void oracle_distance(const float* V, int64_t nv, const int32_t* F, int64_t nf, const float* Q, int64_t nq,
+                     double cutoff, double* d_out)
+{
+    oracle_distance2(V, nv, F, nf, Q, nq, cutoff, 1, d_out);
 }
 
 int oracle_num_threads(void)

@@ -10,7 +10,8 @@ minimise the maximum *relative* error of atan:
 
 i.e. a weighted minimax fit of h with weight x / g(x).  Usage:
 
-    python gen_atan_poly.py [deg]     # prints the coefficients, highest first
+    python gen_atan_poly.py [deg]            # float32 table, coefficients highest first
+    python gen_atan_poly.py deg double       # float64 table for |t| <= tan(pi/8)
 
 The printed table is pasted into query.hip (kAtanQ); the script also reports
 the fitted error and the error of the same Horner evaluation in float32.
@@ -30,12 +31,17 @@ def g(x):
 
 
 def h(x):
+    """(atan(sqrt x)/sqrt x - 1)/x; the alternating series -1/3 + x/5 - x^2/7 + ...
+    below x = 1/4 (60 terms: error < 4^-60), the closed form above it."""
     x = np.asarray(x, dtype=np.float64)
-    out = np.full_like(x, -1.0 / 3.0)
-    big = x > 1e-4
+    out = np.empty_like(x)
+    big = x >= 0.25
     out[big] = (g(x[big]) - 1.0) / x[big]
-    xs = x[~big]   # series: atan(t)/t = 1 - x/3 + x^2/5 - x^3/7 + ...
-    out[~big] = -1.0 / 3.0 + xs / 5.0 - xs ** 2 / 7.0 + xs ** 3 / 9.0
+    xs = x[~big]
+    acc = np.zeros_like(xs)
+    for k in range(60, 0, -1):
+        acc = acc * xs + (-1.0) ** k / (2 * k + 1)
+    out[~big] = acc
     return out
 
 
@@ -43,23 +49,28 @@ def weight(x):
     return np.asarray(x, dtype=np.float64) / g(x)
 
 
-def remez(deg, iters=60, grid=200001):
+def unit_weight(x):
+    return np.ones_like(np.asarray(x, dtype=np.float64))
+
+
+def remez(deg, iters=60, grid=200001, xmax=1.0, wfun=weight):
     n = deg + 1
-    # initial reference: Chebyshev extrema mapped to (0, 1]
+    # initial reference: Chebyshev extrema mapped to (0, xmax]
     k = np.arange(n + 1)
-    ref = 0.5 - 0.5 * np.cos(np.pi * k / n)
-    ref[0] = 1e-6
-    X = np.linspace(1e-6, 1.0, grid)
+    ref = xmax * (0.5 - 0.5 * np.cos(np.pi * k / n))
+    lo = 1e-6 * xmax if wfun is weight else 0.0
+    ref[0] = max(ref[0], lo)
+    X = np.linspace(lo, xmax, grid)
     coef = None
     for _ in range(iters):
         A = np.zeros((n + 1, n + 1))
         for i, xi in enumerate(ref):
             A[i, :n] = xi ** np.arange(n)
-            A[i, n] = (-1) ** i / weight(np.array([xi]))[0]
+            A[i, n] = (-1) ** i / wfun(np.array([xi]))[0]
         rhs = h(ref)
         sol = np.linalg.solve(A, rhs)
         coef = sol[:n]
-        err = weight(X) * (np.polyval(coef[::-1], X) - h(X))
+        err = wfun(X) * (np.polyval(coef[::-1], X) - h(X))
         # new reference: one extremum per sign-alternating segment
         sgn = np.sign(err)
         idx = []
@@ -97,6 +108,30 @@ def horner_f32(coef_hi_first, t):
 
 def main():
     deg = int(sys.argv[1]) if len(sys.argv) > 1 else 7
+    if len(sys.argv) > 2 and sys.argv[2] == "double":
+        # |t| <= tan(pi/8): x = t^2 <= 3 - 2 sqrt 2
+        xmax = 3.0 - 2.0 * np.sqrt(2.0)
+        # near-minimax: interpolate h at the Chebyshev nodes of [0, xmax] and convert
+        # to powers of x (well conditioned on this short interval); atan's relative
+        # error is then <= x max|Q - h|
+        from numpy.polynomial import Chebyshev, Polynomial
+        j = np.arange(deg + 1)
+        xn = 0.5 * xmax * (1.0 - np.cos(np.pi * (j + 0.5) / (deg + 1)))
+        cheb = Chebyshev.fit(xn, h(xn), deg, domain=[0.0, xmax])
+        coef = cheb.convert(kind=Polynomial).coef
+        X = np.linspace(0.0, xmax, 200001)
+        emax = float(np.max(np.abs(np.polyval(coef[::-1], X) - h(X))))
+        hi_first = coef[::-1]
+        t = np.linspace(0.0, np.sqrt(xmax), 400001)[1:]
+        x = t * t
+        q = np.full_like(x, hi_first[0])
+        for c in hi_first[1:]:
+            q = q * x + c
+        a = t + (t * x) * q
+        rel = np.abs(a - np.arctan(t)) / np.arctan(t)
+        print(f"// degree {deg} in x = t^2 on |t| <= tan(pi/8); max |Q - h| {emax:.3e}; float64 Horner: max rel {rel.max():.3e}")
+        print(f"constexpr double kAtanQd[{deg + 1}] = {{" + ", ".join(repr(float(c)) for c in hi_first) + "};")
+        return
     coef, emax = remez(deg)
     hi_first = coef[::-1]
     t = np.linspace(0.0, 1.0, 400001)[1:]

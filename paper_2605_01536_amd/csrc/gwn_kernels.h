@@ -31,23 +31,18 @@ namespace {
 
 constexpr double kInv2Pi = 0.15915494309189533576888376337251;  // 1 / (2 pi)
 
-template <class T>
-struct Vtx {
-    T rx, ry, rz, s;
-    int dx, dy;
-};
-
-__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
-__device__ __forceinline__ double fatan2(double y, double x) { return atan2(y, x); }
-
 // atan(t) for |t| <= 1 as t + t x Q(x), x = t^2, Q of degree 7 fitted by the
 // Remez exchange for minimax relative error (gen_atan_poly.py: 1.7e-8 in exact
 // arithmetic, 9.2e-8 max / 2e-9 mean signed when evaluated in float32).
 constexpr float kAtanQ[8] = {0.002920693f, -0.01636793f, 0.043211866f, -0.07552215f,
                              0.106660046f, -0.14211056f, 0.19993773f, -0.33333153f};
+// atan(t) for |t| <= tan(pi/8) in double: Q of degree 9 interpolated at the
+// Chebyshev nodes of [0, tan^2(pi/8)] (gen_atan_poly.py 9 double: |Q - h| <=
+// 1e-15, relative error of atan <= 2e-16).
+constexpr double kAtanQd[10] = {0.02277211404923737,  -0.044850509519182694, 0.05736903901999104,
+                                -0.06649717364503759, 0.0769106629901103,    -0.09090853283150221,
+                                0.11111109664858296,  -0.14285714266729652,  0.19999999999905727,
+                                -0.33333333333333276};
 constexpr float kPi = 3.14159265358979f;
 constexpr float kPi2 = 1.57079632679490f;
 
@@ -69,224 +64,177 @@ __device__ __forceinline__ float atan2_full(float y, float x) {
     a = x < 0.f ? kPi - a : a;
     return copysignf(a, y);
 }
-__device__ __forceinline__ float fatan2(float y, float x) { return atan2_full(y, x); }
 
-// s = l - r_z, evaluated without cancellation
+// Arithmetic of the boundary loop per type.  kFast bounds |N|/D on the fast
+// path (the range of the small-argument arctangent).
 template <class T>
-__device__ __forceinline__ T stereo_s(T rho2, T rz) {
-    T l = fsqrt(rho2 + rz * rz);
-    T t = l + fabs(rz);
-    return rz > (T)0 ? fdiv(rho2, t) : t;
-}
+struct Arith;
 
-// FAR = the query's quantised x or y is outside the grid: raw offsets, and no
-// exact decision is needed (no ray crossings; every edge has D > 0 there).
-template <class T, bool FAR>
-__device__ __forceinline__ Vtx<T> make_vtx(const BVert& b, int qqx, int qqy, T pxs, T pys, T pzs) {
-    Vtx<T> v;
-    v.dx = b.qx - qqx;
-    v.dy = b.qy - qqy;
-    if (FAR) {
-        v.rx = (T)b.x - pxs;
-        v.ry = (T)b.y - pys;
-    } else {
-        v.rx = (T)v.dx;
-        v.ry = (T)v.dy;
-    }
-    v.rz = (T)b.z - pzs;
-    v.s = stereo_s<T>(v.rx * v.rx + v.ry * v.ry, v.rz);
-    return v;
-}
-
-// Rare path for D <= 0: fix the sign of N from the exact predicate, or take the
-// limit under the perturbation when an endpoint lies on the +z ray (its x/y
-// offset becomes (-e1, -e2)).
-template <class T>
-__device__ __forceinline__ void exact_branch(const Vtx<T>& a, const Vtx<T>& b, T& N, T& D) {
-    const bool aon = (a.dx == 0) & (a.dy == 0) & (a.rz > (T)0);
-    const bool bon = (b.dx == 0) & (b.dy == 0) & (b.rz > (T)0);
-    if (aon && bon) {
-        N = (T)0;
-        D = (T)1;
-    } else if (aon) {          // N ~ e1 rb_y - e2 rb_x,  D ~ -e1 rb_x - e2 rb_y
-        if (b.ry != (T)0) {
-            N = b.ry;
-            D = -b.rx;
-        } else if (b.rx > (T)0) {
-            N = -(T)0;
-            D = (T)-1;
-        } else {
-            N = (T)0;
-            D = (T)1;
-        }
-    } else if (bon) {          // N ~ -e1 ra_y + e2 ra_x, D ~ -e1 ra_x - e2 ra_y
-        if (a.ry != (T)0) {
-            N = -a.ry;
-            D = -a.rx;
-        } else if (a.rx > (T)0) {
-            N = (T)0;
-            D = (T)-1;
-        } else {
-            N = (T)0;
-            D = (T)1;
-        }
-    } else {
-        const int o = orient_sos(a.dx, a.dy, b.dx, b.dy);   // N = -orient2d(a, b, q_eps)
-        if (o > 0) N = -fabs(N);
-        else if (o < 0) N = fabs(N);
-    }
-}
-
-template <class T, bool FAR>
-__device__ __forceinline__ T edge_angle(const Vtx<T>& a, const Vtx<T>& b) {
-    T N = a.ry * b.rx - a.rx * b.ry;
-    T D = a.s * b.s + (a.rx * b.rx + a.ry * b.ry);
-    if (!FAR && D <= (T)0) exact_branch<T>(a, b, N, D);
-    return fatan2(N, D);
-}
-
-// ---------------------------------------------------------------- FP32 loop
-// x/y quantities of one boundary vertex relative to the query column (shared by
-// all samples of a grid column; per lane in the batch kernel).
-struct ColV {
-    int dx, dy;
-    float rx, ry, rho2;
+template <>
+struct Arith<float> {
+    static constexpr float kFast = 1.0f;
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float atan_small(float t) { return atan_unit(t); }
+    static __device__ __forceinline__ float atan2(float y, float x) { return atan2_full(y, x); }
 };
 
-template <bool FAR>
-__device__ __forceinline__ ColV col_vtx(const BVert& b, int qqx, int qqy, float pxs, float pys) {
-    ColV c;
+template <>
+struct Arith<double> {
+    static constexpr double kFast = 0.41421356237;   // just below tan(pi/8)
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    // hardware reciprocal refined by two Newton steps
+    static __device__ __forceinline__ double rcp(double x) {
+        double r = __builtin_amdgcn_rcp(x);
+        double e = fma(-x, r, 1.0);
+        r = fma(r, e, r);
+        e = fma(-x, r, 1.0);
+        return fma(r, e, r);
+    }
+    static __device__ __forceinline__ double atan_small(double t) {
+        const double x = t * t;
+        double q = kAtanQd[0];
+#pragma unroll
+        for (int k = 1; k < 10; ++k) q = fma(q, x, kAtanQd[k]);
+        return fma(t * x, q, t);
+    }
+    static __device__ __forceinline__ double atan2(double y, double x) { return ::atan2(y, x); }
+};
+
+// ---------------------------------------------------------------- boundary loop
+// x/y quantities of one boundary vertex relative to the query column (shared by
+// all samples of a grid column; per lane in the batch kernels).
+template <class T>
+struct ColV {
+    int dx, dy;
+    T rx, ry, rho2;
+};
+
+template <class T, bool FAR>
+__device__ __forceinline__ ColV<T> col_vtx(const BVert& b, int qqx, int qqy, T pxs, T pys) {
+    ColV<T> c;
     c.dx = b.qx - qqx;
     c.dy = b.qy - qqy;
     if (FAR) {
-        c.rx = b.x - pxs;
-        c.ry = b.y - pys;
+        c.rx = (T)b.x - pxs;
+        c.ry = (T)b.y - pys;
     } else {
-        c.rx = (float)c.dx;
-        c.ry = (float)c.dy;
+        c.rx = (T)c.dx;
+        c.ry = (T)c.dy;
     }
-    c.rho2 = fmaf(c.rx, c.rx, c.ry * c.ry);
+    c.rho2 = c.rx * c.rx + c.ry * c.ry;
     return c;
 }
 
 // s = l - r_z without cancellation
-__device__ __forceinline__ float samp_s(float rho2, float rz) {
-    const float l = __builtin_amdgcn_sqrtf(fmaf(rz, rz, rho2));
-    const float t = l + fabsf(rz);
-    return rz > 0.f ? rho2 * __builtin_amdgcn_rcpf(t) : t;
+template <class T>
+__device__ __forceinline__ T samp_s(T rho2, T rz) {
+    const T l = Arith<T>::sqrt(rz * rz + rho2);
+    const T t = l + fabs(rz);
+    return rz > (T)0 ? rho2 * Arith<T>::rcp(t) : t;
 }
 
 // Rare path of one (sample, edge): exact atan2 branch where D <= 0 (sign of N from
 // the perturbed predicate, or the perturbation limit for an endpoint on the ray),
 // then the full-range atan2.
-__device__ __forceinline__ float edge_slow(const ColV& a, const ColV& b, float rza, float rzb, float N, float D,
-                                           bool exact) {
-    if (exact && D <= 0.f) {
-        const bool aon = (a.dx == 0) & (a.dy == 0) & (rza > 0.f);
-        const bool bon = (b.dx == 0) & (b.dy == 0) & (rzb > 0.f);
+template <class T>
+__device__ __forceinline__ T edge_slow(const ColV<T>& a, const ColV<T>& b, T rza, T rzb, T N, T D, bool exact) {
+    if (exact && D <= (T)0) {
+        const bool aon = (a.dx == 0) & (a.dy == 0) & (rza > (T)0);
+        const bool bon = (b.dx == 0) & (b.dy == 0) & (rzb > (T)0);
         if (aon && bon) {
-            N = 0.f;
-            D = 1.f;
+            N = (T)0;
+            D = (T)1;
         } else if (aon) {        // N ~ e1 rb_y - e2 rb_x,  D ~ -e1 rb_x - e2 rb_y
-            if (b.ry != 0.f) { N = b.ry; D = -b.rx; }
-            else if (b.rx > 0.f) { N = -0.f; D = -1.f; }
-            else { N = 0.f; D = 1.f; }
+            if (b.ry != (T)0) { N = b.ry; D = -b.rx; }
+            else if (b.rx > (T)0) { N = -(T)0; D = (T)-1; }
+            else { N = (T)0; D = (T)1; }
         } else if (bon) {        // N ~ -e1 ra_y + e2 ra_x, D ~ -e1 ra_x - e2 ra_y
-            if (a.ry != 0.f) { N = -a.ry; D = -a.rx; }
-            else if (a.rx > 0.f) { N = 0.f; D = -1.f; }
-            else { N = 0.f; D = 1.f; }
+            if (a.ry != (T)0) { N = -a.ry; D = -a.rx; }
+            else if (a.rx > (T)0) { N = (T)0; D = (T)-1; }
+            else { N = (T)0; D = (T)1; }
         } else {
             const int o = orient_sos(a.dx, a.dy, b.dx, b.dy);   // N = -orient2d(a, b, q_eps)
-            if (o > 0) N = -fabsf(N);
-            else if (o < 0) N = fabsf(N);
+            if (o > 0) N = -fabs(N);
+            else if (o < 0) N = fabs(N);
         }
     }
-    return atan2_full(N, D);
+    return Arith<T>::atan2(N, D);
 }
 
 // One boundary edge for ZB samples.  Fast path (wave-uniform): every sample has
-// |N| < D, so atan2(N, D) = atan(N/D) with |N/D| < 1 and no branch fix-up.
-template <int ZB, bool FAR>
-__device__ __forceinline__ void edge_f32(const ColV& a, const ColV& b, const float* sa, const float* sb,
-                                         const float* rza, const float* rzb, float* acc) {
-    const float N = fmaf(a.ry, b.rx, -a.rx * b.ry);
-    const float dot = fmaf(a.rx, b.rx, a.ry * b.ry);
-    const float aN = fabsf(N);
-    float D[ZB];
+// |N| < kFast D, so atan2(N, D) = atan(N/D) with no branch fix-up.
+template <class T, int ZB, bool FAR>
+__device__ __forceinline__ void edge_step(const ColV<T>& a, const ColV<T>& b, const T* sa, const T* sb, const T* rza,
+                                          const T* rzb, T* acc) {
+    const T N = a.ry * b.rx - a.rx * b.ry;
+    const T dot = a.rx * b.rx + a.ry * b.ry;
+    const T aN = fabs(N);
+    T D[ZB];
     bool slow = false;
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {
-        D[r] = fmaf(sa[r], sb[r], dot);
-        slow |= !(aN < D[r]);
+        D[r] = sa[r] * sb[r] + dot;
+        slow |= !(aN < Arith<T>::kFast * D[r]);
     }
     if (__builtin_amdgcn_ballot_w64(slow) == 0ull) {
 #pragma unroll
-        for (int r = 0; r < ZB; ++r) acc[r] += atan_unit(N * __builtin_amdgcn_rcpf(D[r]));
+        for (int r = 0; r < ZB; ++r) acc[r] += Arith<T>::atan_small(N * Arith<T>::rcp(D[r]));
     } else {
 #pragma unroll
-        for (int r = 0; r < ZB; ++r) acc[r] += edge_slow(a, b, rza[r], rzb[r], N, D[r], !FAR);
+        for (int r = 0; r < ZB; ++r) acc[r] += edge_slow<T>(a, b, rza[r], rzb[r], N, D[r], !FAR);
     }
 }
 
-// Boundary sum for ZB samples sharing one (x, y): loops of the chain, FP32
-// partials flushed into FP64 every 32 edges.
-template <int ZB, bool FAR>
-__device__ __forceinline__ void loops_f32(const MeshView& mv, int qqx, int qqy, float pxs, float pys, const float* pzs,
-                                          double* S) {
+template <class T, int ZB, bool FAR>
+__device__ __forceinline__ void load_vertex(const BVert& b, int qqx, int qqy, T pxs, T pys, const T* pzs, ColV<T>& c,
+                                            T* rz, T* sv) {
+    c = col_vtx<T, FAR>(b, qqx, qqy, pxs, pys);
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        rz[r] = (T)b.z - pzs[r];
+        sv[r] = samp_s<T>(c.rho2, rz[r]);
+    }
+}
+
+// Boundary sum S = sum of atan2 over the chained loops for ZB samples sharing one
+// (x, y).  FP32 partials are flushed into the FP64 sum every 32 edges.
+template <class T, int ZB, bool FAR>
+__device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int qqy, T pxs, T pys, const T* pzs,
+                                               double* S) {
     const BVert* __restrict__ bv = mv.bverts;
     for (int l = 0; l < mv.nloops; ++l) {
         const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
-        ColV cf, cp;
-        float rzf[ZB], sf[ZB], rzp[ZB], sp[ZB];
-        {
-            const BVert b = bv[b0];
-            cf = col_vtx<FAR>(b, qqx, qqy, pxs, pys);
+        ColV<T> cf, cp;
+        T rzf[ZB], sf[ZB], rzp[ZB], sp[ZB];
+        load_vertex<T, ZB, FAR>(bv[b0], qqx, qqy, pxs, pys, pzs, cf, rzf, sf);
+        cp = cf;
 #pragma unroll
-            for (int r = 0; r < ZB; ++r) {
-                rzf[r] = b.z - pzs[r];
-                sf[r] = samp_s(cf.rho2, rzf[r]);
-                rzp[r] = rzf[r];
-                sp[r] = sf[r];
-            }
-            cp = cf;
+        for (int r = 0; r < ZB; ++r) {
+            rzp[r] = rzf[r];
+            sp[r] = sf[r];
         }
         int j = b0 + 1;
         while (j < b1) {
             const int je = min(b1, j + 32);
-            float acc[ZB];
+            T acc[ZB];
 #pragma unroll
-            for (int r = 0; r < ZB; ++r) acc[r] = 0.f;
+            for (int r = 0; r < ZB; ++r) acc[r] = (T)0;
             // two vertices per trip: the loop-carried vertex alternates between
             // two register sets instead of being copied every edge
             for (; j + 1 < je; j += 2) {
-                const BVert b1v = bv[j];
-                const ColV c1 = col_vtx<FAR>(b1v, qqx, qqy, pxs, pys);
-                float rz1[ZB], s1[ZB];
-#pragma unroll
-                for (int r = 0; r < ZB; ++r) {
-                    rz1[r] = b1v.z - pzs[r];
-                    s1[r] = samp_s(c1.rho2, rz1[r]);
-                }
-                edge_f32<ZB, FAR>(cp, c1, sp, s1, rzp, rz1, acc);
-                const BVert b2v = bv[j + 1];
-                cp = col_vtx<FAR>(b2v, qqx, qqy, pxs, pys);
-#pragma unroll
-                for (int r = 0; r < ZB; ++r) {
-                    rzp[r] = b2v.z - pzs[r];
-                    sp[r] = samp_s(cp.rho2, rzp[r]);
-                }
-                edge_f32<ZB, FAR>(c1, cp, s1, sp, rz1, rzp, acc);
+                ColV<T> c1;
+                T rz1[ZB], s1[ZB];
+                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pzs, c1, rz1, s1);
+                edge_step<T, ZB, FAR>(cp, c1, sp, s1, rzp, rz1, acc);
+                load_vertex<T, ZB, FAR>(bv[j + 1], qqx, qqy, pxs, pys, pzs, cp, rzp, sp);
+                edge_step<T, ZB, FAR>(c1, cp, s1, sp, rz1, rzp, acc);
             }
             if (j < je) {
-                const BVert b = bv[j];
-                const ColV cc = col_vtx<FAR>(b, qqx, qqy, pxs, pys);
-                float rzc[ZB], sc[ZB];
-#pragma unroll
-                for (int r = 0; r < ZB; ++r) {
-                    rzc[r] = b.z - pzs[r];
-                    sc[r] = samp_s(cc.rho2, rzc[r]);
-                }
-                edge_f32<ZB, FAR>(cp, cc, sp, sc, rzp, rzc, acc);
+                ColV<T> cc;
+                T rzc[ZB], sc[ZB];
+                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pzs, cc, rzc, sc);
+                edge_step<T, ZB, FAR>(cp, cc, sp, sc, rzp, rzc, acc);
                 cp = cc;
 #pragma unroll
                 for (int r = 0; r < ZB; ++r) {
@@ -298,10 +246,10 @@ __device__ __forceinline__ void loops_f32(const MeshView& mv, int qqx, int qqy, 
 #pragma unroll
             for (int r = 0; r < ZB; ++r) S[r] += (double)acc[r];
         }
-        float acc[ZB];
+        T acc[ZB];
 #pragma unroll
-        for (int r = 0; r < ZB; ++r) acc[r] = 0.f;
-        edge_f32<ZB, FAR>(cp, cf, sp, sf, rzp, rzf, acc);
+        for (int r = 0; r < ZB; ++r) acc[r] = (T)0;
+        edge_step<T, ZB, FAR>(cp, cf, sp, sf, rzp, rzf, acc);
 #pragma unroll
         for (int r = 0; r < ZB; ++r) S[r] += (double)acc[r];
     }

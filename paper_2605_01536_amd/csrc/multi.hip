@@ -78,8 +78,8 @@ __global__ __launch_bounds__(256) void k_bdry_persistent(const MeshView* __restr
             const float sc = mv.g.scalef;
             const float pzs = pz * sc;
             double S = 0.0;
-            if (q.inbox) loops_f32<1, false>(mv, q.x, q.y, 0.f, 0.f, &pzs, &S);
-            else loops_f32<1, true>(mv, 0, 0, px * sc, py * sc, &pzs, &S);
+            if (q.inbox) boundary_loops<float, 1, false>(mv, q.x, q.y, 0.f, 0.f, &pzs, &S);
+            else boundary_loops<float, 1, true>(mv, 0, 0, px * sc, py * sc, &pzs, &S);
             if (k < I.nq) w[i] = (float)((double)chi[i] + S * kInv2Pi);
         }
     }

@@ -11,33 +11,7 @@
 namespace gwn {
 namespace {
 
-// Boundary sum for one query per lane: sum over loops, FP32 partials flushed
-// to FP64 every 32 edges (FP64 throughout for T = double).
-template <class T, bool FAR>
-__device__ double boundary_sum(const MeshView& mv, int qqx, int qqy, T pxs, T pys, T pzs) {
-    double S = 0.0;
-    const BVert* __restrict__ bv = mv.bverts;
-    for (int l = 0; l < mv.nloops; ++l) {
-        const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
-        const Vtx<T> first = make_vtx<T, FAR>(bv[b0], qqx, qqy, pxs, pys, pzs);
-        Vtx<T> prev = first;
-        int j = b0 + 1;
-        while (j < b1) {
-            const int je = min(b1, j + 32);
-            T acc = (T)0;
-#pragma unroll 2
-            for (; j < je; ++j) {
-                const Vtx<T> cur = make_vtx<T, FAR>(bv[j], qqx, qqy, pxs, pys, pzs);
-                acc += edge_angle<T, FAR>(prev, cur);
-                prev = cur;
-            }
-            S += (double)acc;
-        }
-        S += (double)edge_angle<T, FAR>(prev, first);
-    }
-    return S;
-}
-
+// crossing counts of arbitrary points (per-lane LDS traversal stack)
 __global__ __launch_bounds__(kChiBlock) void k_chi_batch(MeshView mv, const float* __restrict__ qx,
                                                          const float* __restrict__ qy, const float* __restrict__ qz,
                                                          long long qs, long long nq, const int* __restrict__ ndev,
@@ -67,13 +41,8 @@ __global__ __launch_bounds__(256) void k_bdry_batch(MeshView mv, const float* __
     const T pxs = (T)px * sc, pys = (T)py * sc, pzs = (T)pz * sc;
     // lanes outside the fixed-point grid (rare) take the raw-offset loop
     double S = 0.0;
-    if constexpr (std::is_same<T, float>::value) {
-        if (q.inbox) loops_f32<1, false>(mv, q.x, q.y, 0.f, 0.f, &pzs, &S);
-        else loops_f32<1, true>(mv, 0, 0, pxs, pys, &pzs, &S);
-    } else {
-        S = q.inbox ? boundary_sum<T, false>(mv, q.x, q.y, pxs, pys, pzs)
-                    : boundary_sum<T, true>(mv, q.x, q.y, pxs, pys, pzs);
-    }
+    if (q.inbox) boundary_loops<T, 1, false>(mv, q.x, q.y, (T)0, (T)0, &pzs, &S);
+    else boundary_loops<T, 1, true>(mv, 0, 0, pxs, pys, &pzs, &S);
     if (i < nq) w[i] = (T)((double)chi[i] + S * kInv2Pi);
 }
 
@@ -87,45 +56,6 @@ struct GridArgs {
 };
 
 constexpr int kGridWaves = 4;  // waves per block; one wave per (column, z-chunk)
-
-// Boundary term for ZB samples of one column: per vertex, x/y quantities are
-// shared by the samples (the column is wave-uniform), z quantities are not.
-template <class T, int ZB, bool FAR>
-__device__ __forceinline__ void grid_boundary(const MeshView& mv, int qqx, int qqy, T pxs, T pys, const T* pzs, double* S) {
-    const BVert* __restrict__ bv = mv.bverts;
-    for (int l = 0; l < mv.nloops; ++l) {
-        const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
-        Vtx<T> first[ZB], prev[ZB];
-        {
-            const BVert b = bv[b0];
-#pragma unroll
-            for (int r = 0; r < ZB; ++r) {
-                first[r] = make_vtx<T, FAR>(b, qqx, qqy, pxs, pys, pzs[r]);
-                prev[r] = first[r];
-            }
-        }
-        int j = b0 + 1;
-        while (j < b1) {
-            const int je = min(b1, j + 32);
-            T acc[ZB];
-#pragma unroll
-            for (int r = 0; r < ZB; ++r) acc[r] = (T)0;
-            for (; j < je; ++j) {
-                const BVert b = bv[j];
-#pragma unroll
-                for (int r = 0; r < ZB; ++r) {
-                    const Vtx<T> cur = make_vtx<T, FAR>(b, qqx, qqy, pxs, pys, pzs[r]);
-                    acc[r] += edge_angle<T, FAR>(prev[r], cur);
-                    prev[r] = cur;
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < ZB; ++r) S[r] += (double)acc[r];
-        }
-#pragma unroll
-        for (int r = 0; r < ZB; ++r) S[r] += (double)edge_angle<T, FAR>(prev[r], first[r]);
-    }
-}
 
 // grid coordinate origin + (i + 0.5) * spacing in FP64 without contraction
 __device__ __forceinline__ float grid_coord(double o, double s, long long i) {
@@ -210,13 +140,8 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs 
         pzs[r] = (T)pz[r] * sc;
         S[r] = 0.0;
     }
-    if constexpr (std::is_same<T, float>::value) {
-        if (q0.inbox) loops_f32<ZB, false>(mv, q0.x, q0.y, 0.f, 0.f, pzs, S);
-        else loops_f32<ZB, true>(mv, 0, 0, px * mv.g.scalef, py * mv.g.scalef, pzs, S);
-    } else {
-        if (q0.inbox) grid_boundary<T, ZB, false>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S);
-        else grid_boundary<T, ZB, true>(mv, 0, 0, (T)px * sc, (T)py * sc, pzs, S);
-    }
+    if (q0.inbox) boundary_loops<T, ZB, false>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S);
+    else boundary_loops<T, ZB, true>(mv, 0, 0, (T)px * sc, (T)py * sc, pzs, S);
 
     const long long base = col * ga.nz;
 #pragma unroll
@@ -271,7 +196,8 @@ gwn_status launch_grid(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out,
             default: break;
         }
     }
-    if (ga.nz >= 64 * 8) return launch_grid_zb<T, 8>(m, ga, w, chi_out, st);
+    // FP64 keeps at most 4 samples per lane (8 would need ~200 VGPRs)
+    if (ga.nz >= 64 * 8 && sizeof(T) == 4) return launch_grid_zb<T, 8>(m, ga, w, chi_out, st);
     if (ga.nz >= 64 * 4) return launch_grid_zb<T, 4>(m, ga, w, chi_out, st);
     if (ga.nz >= 64 * 2) return launch_grid_zb<T, 2>(m, ga, w, chi_out, st);
     return launch_grid_zb<T, 1>(m, ga, w, chi_out, st);

@@ -357,3 +357,11 @@ def test_point_triangle_distance_closed_forms():
     assert d[2] == pytest.approx(2.0, abs=1e-7)
     assert d[3] == pytest.approx(math.sqrt(1.5 ** 2 * 2 + 1), abs=1e-6)
     assert O.distance(V, OCT_F, Q[3:], 0.1)[0] == pytest.approx(0.1)
+
+
+def test_binned_distance_equals_brute_force():
+    s, Q = W.config2(n_uniform=800, n_near=800)
+    for cut in (1e-3, 2e-2):
+        a = O.distance(s.V, s.F, Q, cut, use_bins=True)
+        b = O.distance(s.V, s.F, Q, cut, use_bins=False)
+        assert np.array_equal(a, b)
