@@ -149,21 +149,26 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         rng = np.random.default_rng(12345)
-        # size the sample to ~cpu_seconds of oracle work (calibrated on a small sample)
-        cal = rng.choice(n, 64, replace=False)
+        # size the sample to ~cpu_seconds of oracle work; the per-point cost is
+        # calibrated on two sample sizes so the one-off setup of each call cancels
         t = time.perf_counter()
-        oracle.antipodal(soup.V, soup.F, W.grid_points(grid, cal))
-        per_q = (time.perf_counter() - t) / 64
-        m = int(max(256, min(200_000, args.cpu_seconds / max(per_q, 1e-9))))
+        oracle.antipodal(soup.V, soup.F, W.grid_points(grid, rng.choice(n, 500, replace=False)))
+        t500 = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.antipodal(soup.V, soup.F, W.grid_points(grid, rng.choice(n, 4500, replace=False)))
+        t4500 = time.perf_counter() - t
+        per_q = max((t4500 - t500) / 4000.0, 1e-9)
+        m = int(max(1000, min(5_000_000, args.cpu_seconds / per_q)))
         idx = rng.choice(n, m, replace=False)
         P = W.grid_points(grid, idx)
         t = time.perf_counter()
         w_o = oracle.antipodal(soup.V, soup.F, P)
         cpu_s = time.perf_counter() - t
         diag = float(np.linalg.norm(np.asarray(info["bbox"][3:]) - np.asarray(info["bbox"][:3])))
-        far = oracle.distance(soup.V, soup.F, P, 2e-4 * diag) > 1e-4 * diag
-        wg = w[torch.from_numpy(idx).cuda()].double().cpu().numpy()
-        err = float(np.abs(wg - w_o)[far].max())
+        mc = min(m, 200_000)   # error check on the first 200k sampled points
+        far = oracle.distance(soup.V, soup.F, P[:mc], 2e-4 * diag) > 1e-4 * diag
+        wg = w[torch.from_numpy(idx[:mc]).cuda()].double().cpu().numpy()
+        err = float(np.abs(wg - w_o[:mc])[far].max())
         cpu = {"value": m / cpu_s, "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"{m} random points of the same grid, FP64 antipodal oracle, {cpu_s:.1f} s",
                "max_abs_err_vs_gpu": err, "n_compared": int(far.sum())}
@@ -350,7 +355,15 @@ def bench_precision(args):
     it = torch.from_numpy(idx).cuda()
     P = W.grid_points(grid, idx)
     t = time.perf_counter()
-    w_o, _, chi_o, _ = oracle.antipodal(soup.V, soup.F, P, full=True)
+    w_o = np.empty(len(idx))
+    chi_o = np.empty(len(idx), dtype=np.int32)
+    chunk = 25000
+    for a in range(0, len(idx), chunk):     # chunks, so that progress is printed
+        wo, _, co, _ = oracle.antipodal(soup.V, soup.F, P[a:a + chunk], full=True)
+        w_o[a:a + chunk] = wo
+        chi_o[a:a + chunk] = co
+        print(f"[oracle] {min(a + chunk, len(idx))}/{len(idx)} points, {time.perf_counter() - t:.0f} s",
+              file=sys.stderr, flush=True)
     oracle_s = time.perf_counter() - t
     diag = float(np.linalg.norm(np.asarray(info["bbox"][3:]) - np.asarray(info["bbox"][:3])))
     far = oracle.distance(soup.V, soup.F, P, 2e-4 * diag) > 1e-4 * diag
