@@ -125,6 +125,16 @@ gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacin
                           int32_t prec, void* w_out, int32_t* chi_out, void* stream);
 
 /*
+ * gwn_query_direct -- w as the direct sum of per-triangle signed solid angles
+ * (Eq. 2, each triangle's area by Eq. 6), O(F) per query, from the float
+ * vertex positions given to gwn_build_mesh.  The baseline the antipodal method
+ * is measured against, and an independent cross-check.  Arguments as in
+ * gwn_query_batch (no crossing counts).
+ */
+gwn_status gwn_query_direct(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                            int64_t nq, int32_t prec, void* w_out, void* stream);
+
+/*
  * Many meshes in one launch (batched workloads of uneven size).
  *
  * gwn_multi_create prepares a plan for nmesh built meshes whose queries are

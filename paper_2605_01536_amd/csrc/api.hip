@@ -29,6 +29,7 @@ void release(gwn_mesh_s* m) {
     if (!m) return;
     (void)hipFree(m->nodes);
     (void)hipFree(m->tris);
+    (void)hipFree(m->trif);
     (void)hipFree(m->bverts);
     (void)hipFree(m->loop_off);
     delete m;
@@ -158,6 +159,23 @@ gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacin
         return GWN_E_INVALID;
     }
     return gwn::query_grid(m, origin, spacing, dims, prec, w_out, chi_out, (hipStream_t)stream);
+}
+
+gwn_status gwn_query_direct(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                            int64_t nq, int32_t prec, void* w_out, void* stream) {
+    gwn::clear_error();
+    gwn_status s = check_mesh(m, "gwn_query_direct");
+    if (s != GWN_OK) return s;
+    if (nq < 0 || qstride < 1 || (prec != GWN_PREC_FP32 && prec != GWN_PREC_FP64)) {
+        gwn::set_error("gwn_query_direct: bad nq, stride or precision");
+        return GWN_E_INVALID;
+    }
+    if (nq == 0) return GWN_OK;
+    if (!qx || !qy || !qz || !w_out || nq > (1ll << 40)) {
+        gwn::set_error("gwn_query_direct: null array or nq too large");
+        return GWN_E_INVALID;
+    }
+    return gwn::query_direct(m, qx, qy, qz, qstride, nq, prec, w_out, (hipStream_t)stream);
 }
 
 gwn_status gwn_multi_create(const gwn_mesh* meshes, int32_t nmesh, const float* qx, const float* qy,

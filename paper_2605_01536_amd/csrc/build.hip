@@ -126,10 +126,17 @@ __global__ void k_tri_setup(const int32_t* __restrict__ tri, int64_t nf, const i
 }
 
 __global__ void k_permute_tris(const uint64_t* __restrict__ keys, int64_t nf, const TriQ* __restrict__ src,
-                               TriQ* __restrict__ dst) {
+                               TriQ* __restrict__ dst, const int32_t* __restrict__ tri, const float* __restrict__ vx,
+                               const float* __restrict__ vy, const float* __restrict__ vz, int64_t vs,
+                               float4* __restrict__ trif) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nf) return;
-    dst[i] = src[(int64_t)(keys[i] & 0xffffffffull)];
+    const int64_t t = (int64_t)(keys[i] & 0xffffffffull);
+    dst[i] = src[t];
+    for (int c = 0; c < 3; ++c) {
+        const int64_t v = tri[3 * t + c];
+        trif[3 * i + c] = make_float4(vx[v * vs], vy[v * vs], vz[v * vs], 0.f);
+    }
 }
 
 __device__ __forceinline__ int prefix_len(const uint64_t* __restrict__ keys, int n, int i, int j) {
@@ -467,7 +474,8 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
             return hipcub::DeviceRadixSort::SortKeys(tmp, bytes, keys, keys2, (int)nf, 0, 62, st);
         }));
         GWN_HIP_TRY(hipMalloc((void**)&m->tris, sizeof(TriQ) * (size_t)nf));
-        k_permute_tris<<<nblocks(nf), kThreads, 0, st>>>(keys2, nf, tq, m->tris);
+        GWN_HIP_TRY(hipMalloc((void**)&m->trif, sizeof(float4) * 3 * (size_t)nf));
+        k_permute_tris<<<nblocks(nf), kThreads, 0, st>>>(keys2, nf, tq, m->tris, tri, vx, vy, vz, vs, m->trif);
         GWN_HIP_TRY(hipGetLastError());
         if (nf >= 2) {
             m->nnodes = nf - 1;

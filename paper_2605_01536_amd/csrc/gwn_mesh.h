@@ -19,6 +19,7 @@ struct gwn_mesh_s {
     // device memory owned by the handle
     gwn::Node* nodes = nullptr;
     gwn::TriQ* tris = nullptr;
+    float4* trif = nullptr;        // float corners in Morton order (direct sum)
     gwn::BVert* bverts = nullptr;
     int* loop_off = nullptr;
 
@@ -51,6 +52,9 @@ gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, co
 
 gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims,
                       int prec, void* w_out, int32_t* chi_out, hipStream_t stream);
+
+gwn_status query_direct(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                        int64_t nq, int prec, void* w_out, hipStream_t stream);
 
 gwn_status multi_create(const gwn_mesh* meshes, int nmesh, const float* qx, const float* qy, const float* qz,
                         int64_t qs, const int64_t* q_offsets, int prec, void* w_out, int32_t* chi_out,
