@@ -9,6 +9,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 * ``antipodal``  -- Eq. 10 / Alg. 1 with x0 = +z and exact quantised
                     predicates with symbolic perturbation (Supp. Sec. 2.1).
 * ``chi``        -- signed crossings of the +z and -z rays (Sec. 3.2).
+* ``gradient``   -- grad w by Supp. Alg. 3 (boundary term only; the integer
+                    part is locally constant), any axis.
 * ``distance``   -- point-to-soup distance (Ericson 2005), to mask queries
                     on or near the surface where w is undefined (Sec. 3.1).
 * ``boundary``   -- the cancelled directed boundary chain (Sec. 4.1).
@@ -70,6 +72,7 @@ def lib():
         L.oracle_solid_angle.restype = ctypes.c_double
         L.oracle_distance.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, ctypes.c_double, _F64]
         L.oracle_distance2.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, ctypes.c_double, ctypes.c_int, _F64]
+        L.oracle_gradient.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, _F64, _F64, _F64]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -151,6 +154,19 @@ def direct(V, F, Q):
     w = np.zeros(Q.shape[0])
     lib().oracle_direct(V, V.shape[0], F, F.shape[0], Q, Q.shape[0], w)
     return w
+
+
+def gradient(V, F, Q, axis=(0.0, 0.0, 1.0), with_l1: bool = False):
+    """O4: grad w per query, (n, 3) float64, with x0 = axis normalised; with
+    with_l1=True also the per-query sum of edge-term norms / 4 pi."""
+    V, F = _mesh(V, F)
+    Q = _pts(Q)
+    a = np.asarray(axis, dtype=np.float64)
+    a = np.ascontiguousarray(a / np.linalg.norm(a))
+    g = np.zeros((Q.shape[0], 3))
+    l1 = np.zeros(Q.shape[0])
+    lib().oracle_gradient(V, V.shape[0], F, F.shape[0], Q, Q.shape[0], a, g, l1)
+    return (g, l1) if with_l1 else g
 
 
 def solid_angle(v0, v1, v2, p) -> float:

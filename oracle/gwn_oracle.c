@@ -27,6 +27,16 @@
  *       (Supp. Sec. 2.1).  The boundary term is the literal Alg. 1
  *       expression on unit vectors, summed with Neumaier compensation.
  *
+ *   O4  oracle_gradient    grad w(p) = (1/4pi) sum_{(a,b) in dM} grad Area(a^, b^, x1)
+ *       [Supp. Sec. 4, Alg. 3]: the integer part is locally constant, so
+ *       only the boundary term is differentiated.  For each boundary edge
+ *       the derivative of 2 atan2(n, d) with respect to p is taken by the
+ *       chain rule through n = x1.(r0 x r1) and
+ *       d = l0 l1 + l1 x1.r0 + l0 x1.r1 + r0.r1, with the axis x0 (x1 = -x0)
+ *       an argument: the gradient does not depend on it.  FP64 throughout,
+ *       Neumaier-compensated per component; also returns the sum of the
+ *       per-edge term norms (the scale of the rounding error).
+ *
  *   O3  oracle_distance    unsigned point-to-soup distance (closest point on
  *       a triangle by Voronoi-region classification, Ericson 2005,
  *       "Real-Time Collision Detection", Sec. 5.1.5).  Used only to mask
@@ -548,6 +558,85 @@ void oracle_direct(const float* V, int64_t nv, const int32_t* F, int64_t nf, con
         }
         w_out[i] = (hi + lo) / (4.0 * OR_PI);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O4: gradient of w (Supp. Sec. 4, Alg. 3)                                    */
+/* ------------------------------------------------------------------------ */
+
+static inline double or_dot(const double* u, const double* v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; }
+
+static inline void or_cross(const double* u, const double* v, double* out)
+{
+    out[0] = u[1] * v[2] - u[2] * v[1];
+    out[1] = u[2] * v[0] - u[0] * v[2];
+    out[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+/* Neumaier step: running sum *s with compensation *c */
+static inline void or_neumaier(double* s, double* c, double x)
+{
+    double t = *s + x;
+    if (fabs(*s) >= fabs(x)) *c += (*s - t) + x;
+    else *c += (x - t) + *s;
+    *s = t;
+}
+
+/* grad_out[3 * i ..], and l1_out[i] = sum over edges of |edge term| (may be NULL).
+ * x0: unit axis; the boundary is the cancelled chain of oracle_boundary. */
+void oracle_gradient(const float* V, int64_t nv, const int32_t* F, int64_t nf, const float* Q, int64_t nq,
+                     const double* x0, double* grad_out, double* l1_out)
+{
+    (void)nv;
+    int64_t nb = oracle_boundary(F, nf, 1, NULL, NULL, 0);
+    int32_t* from = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nb + 1));
+    int32_t* to = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nb + 1));
+    oracle_boundary(F, nf, 1, from, to, nb);
+    const double x1[3] = {-x0[0], -x0[1], -x0[2]};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nq; ++i) {
+        const double p[3] = {(double)Q[3 * i], (double)Q[3 * i + 1], (double)Q[3 * i + 2]};
+        double gs[3] = {0, 0, 0}, gc[3] = {0, 0, 0}, l1 = 0.0;
+        for (int64_t e = 0; e < nb; ++e) {
+            double r0[3], r1[3], v0[3], v1[3];
+            for (int a = 0; a < 3; ++a) {
+                r0[a] = (double)V[3 * from[e] + a] - p[a];
+                r1[a] = (double)V[3 * to[e] + a] - p[a];
+            }
+            const double l0 = sqrt(or_dot(r0, r0)), l1v = sqrt(or_dot(r1, r1));
+            for (int a = 0; a < 3; ++a) { v0[a] = r0[a] / l0; v1[a] = r1[a] / l1v; }
+            double r0xr1[3];
+            or_cross(r0, r1, r0xr1);
+            const double n = or_dot(x1, r0xr1);
+            const double d = l0 * l1v + l1v * or_dot(x1, r0) + l0 * or_dot(x1, r1) + or_dot(r0, r1);
+            /* derivatives of 2 atan2(n, d) with respect to n and d */
+            const double cn = 2.0 * d / (n * n + d * d);
+            const double cd = -2.0 * n / (n * n + d * d);
+            /* dn/dp: n = r0.(r1 x x1) = r1.(x1 x r0), and dr0/dp = dr1/dp = -I */
+            double r1xx1[3], x1xr0[3], gn[3];
+            or_cross(r1, x1, r1xx1);
+            or_cross(x1, r0, x1xr0);
+            for (int a = 0; a < 3; ++a) gn[a] = -(r1xx1[a] + x1xr0[a]);
+            /* dd/dr0 and dd/dr1; dd/dp is minus their sum */
+            const double x1v0 = or_dot(x1, v0), x1v1 = or_dot(x1, v1);
+            double gd[3];
+            for (int a = 0; a < 3; ++a) {
+                const double t1 = l1v * (x1[a] + v1[a] + (1.0 + x1v1) * v0[a]);
+                const double t2 = l0 * (x1[a] + v0[a] + (1.0 + x1v0) * v1[a]);
+                gd[a] = -(t1 + t2);
+            }
+            double term[3];
+            for (int a = 0; a < 3; ++a) {
+                term[a] = cn * gn[a] + cd * gd[a];
+                or_neumaier(&gs[a], &gc[a], term[a]);
+            }
+            l1 += sqrt(or_dot(term, term));
+        }
+        for (int a = 0; a < 3; ++a) grad_out[3 * i + a] = (gs[a] + gc[a]) / (4.0 * OR_PI);
+        if (l1_out) l1_out[i] = l1 / (4.0 * OR_PI);
+    }
+    free(from);
+    free(to);
 }
 
 /* ------------------------------------------------------------------------ */

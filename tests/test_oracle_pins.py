@@ -365,3 +365,74 @@ def test_binned_distance_equals_brute_force():
         a = O.distance(s.V, s.F, Q, cut, use_bins=True)
         b = O.distance(s.V, s.F, Q, cut, use_bins=False)
         assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- gradient (Supp. Alg. 3)
+
+def _grad_case(seed=3, n=40):
+    s = W.opened_spheres(seed=seed, n_surf=2, tris_per_surf=200)
+    rng = np.random.default_rng(seed)
+    P = rng.uniform(-1.2, 1.2, size=(n, 3))
+    P = (np.round(P * 2**16) / 2**16).astype(np.float32)      # p +- 2^-10 stays exact in float32
+    P = P[O.distance(s.V, s.F, P, 1.0) > 0.15]
+    return s.V, s.F, P
+
+
+def test_gradient_matches_finite_differences_of_direct_sum():
+    # central differences of the direct triangle sum O1 (a different formula: no
+    # boundary, no axis), Richardson-extrapolated to O(h^4)
+    V, F, P = _grad_case()
+    assert len(P) > 20
+
+    def fd(h):
+        G = np.zeros((len(P), 3))
+        for a in range(3):
+            e = np.zeros(3, np.float32)
+            e[a] = h
+            G[:, a] = (O.direct(V, F, P + e) - O.direct(V, F, P - e)) / (2 * h)
+        return G
+
+    h = 2.0 ** -10
+    G = (4 * fd(h / 2) - fd(h)) / 3
+    g = O.gradient(V, F, P)
+    assert np.abs(g).max() > 0.05
+    assert np.abs(G - g).max() < 1e-9
+
+
+def test_gradient_biot_savart_segments():
+    # grad of the solid angle bounded by a polygon is the field of a unit current
+    # along it: per straight segment (r_a x r_b)(l_a + l_b) / (l_a l_b (l_a l_b + r_a.r_b))
+    V, F, P = _grad_case(seed=5)
+    fr, to = O.boundary(F)
+    Pd = P.astype(np.float64)
+    ra = V[fr].astype(np.float64)[None] - Pd[:, None]
+    rb = V[to].astype(np.float64)[None] - Pd[:, None]
+    la, lb = np.linalg.norm(ra, axis=2), np.linalg.norm(rb, axis=2)
+    fac = (la + lb) / (la * lb * (la * lb + (ra * rb).sum(2)))
+    B = (np.cross(ra, rb) * fac[..., None]).sum(1) / (4 * np.pi)
+    g, l1 = O.gradient(V, F, P, with_l1=True)
+    # Alg. 3's per-edge terms grow where a boundary vertex lies near the axis
+    # through p and cancel in the sum; the rounding error scales with their norms
+    err = np.abs(B - g).max(1)
+    assert (err < 1e-11 * np.maximum(1.0, l1)).all()
+    assert err[l1 < 10].max() < 1e-13
+
+
+@pytest.mark.parametrize("axis", [(0, 0, -1), (1, 0, 0), (0.3, -0.5, 0.8)])
+def test_gradient_independent_of_axis(axis):
+    V, F, P = _grad_case(seed=7)
+    g0, l0 = O.gradient(V, F, P, with_l1=True)
+    g1, l1 = O.gradient(V, F, P, axis=axis, with_l1=True)
+    # per-edge terms differ between axes; their sum may not (rounding of d, whose
+    # parts can cancel, bounds the difference)
+    assert np.abs(g1 - g0).max() < 1e-11 * max(1.0, l0.max(), l1.max())
+    assert np.abs(g0).max() > 0.05
+
+
+def test_gradient_of_closed_mesh_is_zero_and_far_field_decays():
+    s, Q = W.config1()
+    assert np.abs(O.gradient(s.V, s.F, Q[:50])).max() == 0.0
+    # one triangle: |grad w| falls off like r^-3 along a ray
+    g = O.gradient(OCT_V, OCT_F, [[10, 11, 12], [20, 22, 24]])
+    ratio = np.linalg.norm(g[0]) / np.linalg.norm(g[1])
+    assert 7.0 < ratio < 9.0
