@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["grid", "batch", "batched", "surrogate", "precision"], default="grid",
+    ap.add_argument("--workload", choices=["grid", "batch", "batched", "surrogate", "precision", "gradient",
+                                                 "direct"], default="grid",
                     help="grid: the headline 512^3 grid on the 1M-triangle soup (default); batch: 2M points on the "
                          "torus soup; batched: 256 soups in one persistent graph; surrogate: MLP + exact fallback")
     ap.add_argument("--n-mesh", type=int, default=256, help="soups in the batched workload")
@@ -96,7 +97,7 @@ def main():
         return
     if args.workload != "grid":
         {"batch": bench_batch, "batched": bench_batched, "surrogate": bench_surrogate,
-         "precision": bench_precision}[args.workload](args)
+         "precision": bench_precision, "gradient": bench_gradient, "direct": bench_direct}[args.workload](args)
         return
     t0 = time.time()
     soup, grid = W.config4(n=args.n)
@@ -242,6 +243,67 @@ def bench_batch(args):
           {"workload": f"torus soup ({info['nf']} tris, {info['nboundary']} boundary edges), 1M uniform + 1M "
                        f"near-surface points", "precision": args.prec, "pairs_per_s": pairs / (ev_ms / 1e3)},
           dtype="f32" if args.prec == "fp32" else "f64")
+
+
+def bench_gradient(args):
+    """grad w (Supp. Alg. 3) at the 2M torus-soup points, beside w at the same points."""
+    import torch
+    from paper_2605_01536_amd import gwn, workloads as W
+    soup, Q = W.config2()
+    mesh = gwn.Mesh(torch.from_numpy(soup.V).cuda(), torch.from_numpy(soup.F).cuda())
+    info = mesh.info()
+    Qd = torch.from_numpy(Q).cuda()
+    dt = torch.float64 if args.prec == "fp64" else torch.float32
+    g = torch.empty((Q.shape[0], 3), device="cuda", dtype=dt)
+    w = torch.empty(Q.shape[0], device="cuda", dtype=dt)
+    st = torch.cuda.current_stream()
+    ev_g, wall_g = _timed(lambda: gwn.query_gradient(mesh, Qd, prec=args.prec, out=g, stream=st), args.steps,
+                          args.warmup, st)
+    ev_w, wall_w = _timed(lambda: gwn.query_batch(mesh, Qd, prec=args.prec, out=w, stream=st), args.steps,
+                          args.warmup, st)
+    pairs = Q.shape[0] * info["nboundary"]
+    print(f"[bench] gradient {Q.shape[0]} pts B={info['nboundary']}: {wall_g:.1f} ms ({pairs / ev_g * 1e3:.3e} "
+          f"edge terms/s); w at the same points {wall_w:.1f} ms", file=sys.stderr, flush=True)
+    _emit("GWN gradients/sec, arbitrary points", Q.shape[0] / (wall_g / 1e3), "queries/s", args, wall_g,
+          {"workload": f"torus soup ({info['nf']} tris, {info['nboundary']} boundary edges), 1M uniform + 1M "
+                       f"near-surface points", "precision": args.prec, "pairs_per_s": pairs / (ev_g / 1e3),
+           "w_ms_same_points": wall_w},
+          dtype="f32" if args.prec == "fp32" else "f64")
+
+
+def bench_direct(args):
+    """The direct per-triangle sum (the O(F) baseline) against the antipodal path on the same
+    points: a sample of the 512^3 grid on the 1M-triangle soup and of the torus-soup points."""
+    import torch
+    from paper_2605_01536_amd import gwn, workloads as W
+    rows = []
+    soup4, grid = W.config4()
+    rng = np.random.default_rng(0)
+    P4 = W.grid_points(grid, np.sort(rng.choice(grid.n, 65536, replace=False)))
+    soup2, Q2 = W.config2()
+    P2 = Q2[np.sort(rng.choice(Q2.shape[0], 131072, replace=False))]
+    st = torch.cuda.current_stream()
+    dt = torch.float64 if args.prec == "fp64" else torch.float32
+    for name, soup, P in (("opened-spheres 512^3 grid sample", soup4, P4), ("torus soup points", soup2, P2)):
+        mesh = gwn.Mesh(torch.from_numpy(soup.V).cuda(), torch.from_numpy(soup.F).cuda())
+        info = mesh.info()
+        Pd = torch.from_numpy(np.ascontiguousarray(P)).cuda()
+        w = torch.empty(P.shape[0], device="cuda", dtype=dt)
+        ev_d, wall_d = _timed(lambda: gwn.query_direct(mesh, Pd, prec=args.prec, out=w, stream=st),
+                              max(1, args.steps // 5), 1, st)
+        ev_a, wall_a = _timed(lambda: gwn.query_batch(mesh, Pd, prec=args.prec, out=w, stream=st), args.steps,
+                              args.warmup, st)
+        rows.append({"mesh": name, "tris": info["nf"], "boundary_edges": info["nboundary"], "points": P.shape[0],
+                     "direct_qps": P.shape[0] / (ev_d / 1e3),
+                     "direct_tri_pairs_per_s": P.shape[0] * info["nf"] / (ev_d / 1e3),
+                     "antipodal_qps": P.shape[0] / (ev_a / 1e3), "speedup": ev_d / ev_a})
+        print(f"[bench] direct {name}: direct {ev_d:.2f} ms, antipodal {ev_a:.2f} ms, speedup {ev_d / ev_a:.1f}x",
+              file=sys.stderr, flush=True)
+        del mesh
+    _emit("GWN queries/sec, direct triangle sum (baseline)", rows[0]["direct_qps"], "queries/s", args,
+          P4.shape[0] / rows[0]["direct_qps"] * 1e3,
+          {"workload": "direct per-triangle sum vs antipodal on the same points", "precision": args.prec,
+           "cases": rows}, dtype="f32" if args.prec == "fp32" else "f64")
 
 
 def bench_batched(args):

@@ -125,6 +125,18 @@ gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacin
                           int32_t prec, void* w_out, int32_t* chi_out, void* stream);
 
 /*
+ * gwn_query_gradient -- the gradient of w with respect to the query point
+ * (Supp. Sec. 4, Alg. 3): the crossing count is locally constant, so only the
+ * boundary-edge term is differentiated (x0 = +z; the gradient does not depend
+ * on the axis).  grad_out: device array of 3 * nq values, (dw/dx, dw/dy, dw/dz)
+ * per query, float for GWN_PREC_FP32 and double for GWN_PREC_FP64.  Queries and
+ * errors as in gwn_query_batch.  Undefined (may be inf/nan) on the boundary
+ * curve and where w is undefined.
+ */
+gwn_status gwn_query_gradient(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                              int64_t nq, int32_t prec, void* grad_out, void* stream);
+
+/*
  * gwn_query_direct -- w as the direct sum of per-triangle signed solid angles
  * (Eq. 2, each triangle's area by Eq. 6), O(F) per query, from the float
  * vertex positions given to gwn_build_mesh.  The baseline the antipodal method

@@ -161,6 +161,23 @@ gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacin
     return gwn::query_grid(m, origin, spacing, dims, prec, w_out, chi_out, (hipStream_t)stream);
 }
 
+gwn_status gwn_query_gradient(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                              int64_t nq, int32_t prec, void* grad_out, void* stream) {
+    gwn::clear_error();
+    gwn_status s = check_mesh(m, "gwn_query_gradient");
+    if (s != GWN_OK) return s;
+    if (nq < 0 || qstride < 1 || (prec != GWN_PREC_FP32 && prec != GWN_PREC_FP64)) {
+        gwn::set_error("gwn_query_gradient: bad nq, stride or precision");
+        return GWN_E_INVALID;
+    }
+    if (nq == 0) return GWN_OK;
+    if (!qx || !qy || !qz || !grad_out || nq > (1ll << 40)) {
+        gwn::set_error("gwn_query_gradient: null array or nq too large");
+        return GWN_E_INVALID;
+    }
+    return gwn::query_gradient(m, qx, qy, qz, qstride, nq, prec, grad_out, (hipStream_t)stream);
+}
+
 gwn_status gwn_query_direct(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                             int64_t nq, int32_t prec, void* w_out, void* stream) {
     gwn::clear_error();

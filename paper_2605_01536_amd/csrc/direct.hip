@@ -5,6 +5,8 @@
 // parallelisation of this sum), and an independent GPU cross-check of w.
 #include <cmath>
 
+#include <algorithm>
+
 #include "gwn_kernels.h"
 #include "gwn_mesh.h"
 
@@ -52,10 +54,15 @@ __global__ __launch_bounds__(256) void k_direct(const float4* __restrict__ trif,
 
 gwn_status query_direct(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t nq,
                         int prec, void* w, hipStream_t st) {
-    const unsigned blocks = (unsigned)((nq + 255) / 256);
-    if (prec == GWN_PREC_FP64) k_direct<double><<<blocks, 256, 0, st>>>(m->trif, m->nf, qx, qy, qz, qs, nq, (double*)w);
-    else k_direct<float><<<blocks, 256, 0, st>>>(m->trif, m->nf, qx, qy, qz, qs, nq, (float*)w);
-    GWN_HIP_TRY(hipGetLastError());
+    const int64_t chunk = max_launch_queries();
+    for (int64_t o = 0; o < nq; o += chunk) {
+        const int64_t n = std::min<int64_t>(chunk, nq - o);
+        const unsigned blocks = (unsigned)((n + 255) / 256);
+        const float *x = qx + o * qs, *y = qy + o * qs, *z = qz + o * qs;
+        if (prec == GWN_PREC_FP64) k_direct<double><<<blocks, 256, 0, st>>>(m->trif, m->nf, x, y, z, qs, n, (double*)w + o);
+        else k_direct<float><<<blocks, 256, 0, st>>>(m->trif, m->nf, x, y, z, qs, n, (float*)w + o);
+        GWN_HIP_TRY(hipGetLastError());
+    }
     return GWN_OK;
 }
 

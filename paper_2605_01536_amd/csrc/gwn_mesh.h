@@ -53,6 +53,14 @@ gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, co
 gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims,
                       int prec, void* w_out, int32_t* chi_out, hipStream_t stream);
 
+// queries per kernel launch in the one-lane-per-query paths (keeps the launch
+// within the 32-bit work-item count); larger batches take several launches.
+// GWN_MAX_LAUNCH_QUERIES (a positive multiple of 256) lowers it, for tests.
+int64_t max_launch_queries();
+
+gwn_status query_gradient(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                          int64_t nq, int prec, void* g_out, hipStream_t stream);
+
 gwn_status query_direct(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                         int64_t nq, int prec, void* w_out, hipStream_t stream);
 

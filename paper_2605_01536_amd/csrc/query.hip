@@ -5,6 +5,8 @@
 #include <cstdlib>
 #include <type_traits>
 
+#include <algorithm>
+
 #include "gwn_kernels.h"
 #include "gwn_mesh.h"
 
@@ -53,6 +55,7 @@ struct GridArgs {
     long long nx, ny, nz;
     long long nchunks;   // z-chunks per column
     long long nwaves;    // columns * nchunks
+    long long wave0;     // first wave of this launch (large grids take several)
 };
 
 constexpr int kGridWaves = 4;  // waves per block; one wave per (column, z-chunk)
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs 
     __shared__ int wstack[kGridWaves][kLdsStack];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const long long gw = (long long)blockIdx.x * kGridWaves + wave;
+    const long long gw = ga.wave0 + (long long)blockIdx.x * kGridWaves + wave;
     if (gw >= ga.nwaves) return;
     const long long col = gw / ga.nchunks;
     const long long chunk = gw - col * ga.nchunks;
@@ -160,12 +163,19 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
     int* chi = chi_out;
     if (!chi) GWN_HIP_TRY(hipMallocAsync((void**)&chi, sizeof(int) * (size_t)nq, st));
     const MeshView mv = m->view();
-    k_chi_batch<<<(unsigned)((nq + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, qx, qy, qz, qs, nq, nullptr,
-                                                                                    chi);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
-        k_bdry_batch<T><<<(unsigned)((nq + 255) / 256), 256, 0, st>>>(mv, qx, qy, qz, qs, nq, nullptr, chi, w);
+    hipError_t e = hipSuccess;
+    // one launch covers at most max_launch_queries() points (the 32-bit grid size)
+    const int64_t chunk = max_launch_queries();
+    for (int64_t o = 0; o < nq && e == hipSuccess; o += chunk) {
+        const int64_t n = std::min<int64_t>(chunk, nq - o);
+        const float *x = qx + o * qs, *y = qy + o * qs, *z = qz + o * qs;
+        k_chi_batch<<<(unsigned)((n + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, x, y, z, qs, n, nullptr,
+                                                                                       chi + o);
         e = hipGetLastError();
+        if (e == hipSuccess) {
+            k_bdry_batch<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(mv, x, y, z, qs, n, nullptr, chi + o, w + o);
+            e = hipGetLastError();
+        }
     }
     if (!chi_out) (void)hipFreeAsync(chi, st);
     GWN_HIP_TRY(e);
@@ -176,9 +186,14 @@ template <class T, int ZB>
 gwn_status launch_grid_zb(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out, hipStream_t st) {
     ga.nchunks = (ga.nz + 64 * ZB - 1) / (64 * ZB);
     ga.nwaves = ga.nx * ga.ny * ga.nchunks;
-    const long long blocks = (ga.nwaves + kGridWaves - 1) / kGridWaves;
-    k_grid<T, ZB><<<(unsigned)blocks, 64 * kGridWaves, 0, st>>>(m->view(), ga, chi_out, w);
-    GWN_HIP_TRY(hipGetLastError());
+    // at most 2^24 waves (2^30 work-items) per launch
+    const long long kMaxWaves = max_launch_queries() / 64;
+    for (long long w0 = 0; w0 < ga.nwaves; w0 += kMaxWaves) {
+        ga.wave0 = w0;
+        const long long blocks = (std::min(kMaxWaves, ga.nwaves - w0) + kGridWaves - 1) / kGridWaves;
+        k_grid<T, ZB><<<(unsigned)blocks, 64 * kGridWaves, 0, st>>>(m->view(), ga, chi_out, w);
+        GWN_HIP_TRY(hipGetLastError());
+    }
     return GWN_OK;
 }
 
@@ -205,6 +220,15 @@ gwn_status launch_grid(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out,
 
 }  // namespace
 
+int64_t max_launch_queries() {
+    int64_t n = int64_t(1) << 30;
+    if (const char* e = std::getenv("GWN_MAX_LAUNCH_QUERIES")) {
+        const long long v = std::atoll(e);
+        if (v >= 256 && v < n && v % 256 == 0) n = v;
+    }
+    return n;
+}
+
 gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t nq,
                        int prec, void* w, int32_t* chi_out, hipStream_t st) {
     if (nq == 0) return GWN_OK;
@@ -215,6 +239,10 @@ gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, co
 gwn_status query_batch_devcount(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
                                 int64_t nmax, const int* ndev, int* chi, float* w, hipStream_t st) {
     if (nmax == 0) return GWN_OK;
+    if (nmax > max_launch_queries()) {
+        set_error("surrogate fallback: more than %lld points in one call", (long long)max_launch_queries());
+        return GWN_E_INVALID;
+    }
     const MeshView mv = m->view();
     k_chi_batch<<<(unsigned)((nmax + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, qx, qy, qz, qs, nmax, ndev,
                                                                                       chi);
@@ -234,7 +262,7 @@ gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* s
     ga.nx = dims[0];
     ga.ny = dims[1];
     ga.nz = dims[2];
-    ga.nchunks = ga.nwaves = 0;
+    ga.nchunks = ga.nwaves = ga.wave0 = 0;
     if (ga.nx == 0 || ga.ny == 0 || ga.nz == 0) return GWN_OK;
     if (prec == GWN_PREC_FP64) return launch_grid<double>(m, ga, (double*)w, chi_out, st);
     return launch_grid<float>(m, ga, (float*)w, chi_out, st);

@@ -48,6 +48,8 @@ def load():
     L.gwn_query_batch.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp, vp]
     L.gwn_query_grid.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int64), i32, vp, vp, vp]
+    L.gwn_query_gradient.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp]
+    L.gwn_query_gradient.restype = ctypes.c_int
     L.gwn_query_direct.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp]
     L.gwn_query_direct.restype = ctypes.c_int
     L.gwn_status_str.argtypes = [ctypes.c_int]
@@ -130,6 +132,20 @@ def query_batch(mesh: Mesh, Q, prec="fp32", want_chi=False, out=None, chi_out=No
     _check(L.gwn_query_batch(mesh.handle, base, base + 4, base + 8, 3, n, p, _ptr(out),
                              _ptr(chi_out) if chi_out is not None else None, _stream(stream)))
     return (out, chi_out) if want_chi else out
+
+
+def query_gradient(mesh: Mesh, Q, prec="fp32", out=None, stream=None):
+    """grad w at each query point, (n, 3) float32 or float64 (Supp. Alg. 3)."""
+    import torch
+    L = load()
+    p = _PREC[prec]
+    Q = Q.contiguous()
+    n = Q.shape[0]
+    if out is None:
+        out = torch.empty((n, 3), device=Q.device, dtype=torch.float64 if p == GWN_PREC_FP64 else torch.float32)
+    base = _ptr(Q)
+    _check(L.gwn_query_gradient(mesh.handle, base, base + 4, base + 8, 3, n, p, _ptr(out), _stream(stream)))
+    return out
 
 
 def query_direct(mesh: Mesh, Q, prec="fp32", out=None, stream=None):

@@ -180,3 +180,24 @@ def test_deterministic(gwn):
     m2 = gwn.Mesh(_dev(s.V), _dev(s.F))
     assert m2.info()["nboundary"] == m.info()["nboundary"]
     assert torch.equal(gwn.query_batch(m2, Qd), a)
+
+
+def test_launch_splitting_is_invisible(gwn, monkeypatch):
+    # batches and grids larger than one launch are split; force tiny launches and
+    # compare every output bit for bit with the single-launch result
+    s = W.opened_spheres(seed=41, n_surf=4, tris_per_surf=300)
+    m = gwn.Mesh(_dev(s.V), _dev(s.F))
+    Q = _dev(np.random.default_rng(2).uniform(-1.2, 1.2, size=(5000, 3)).astype(np.float32))
+    g = W.GridSpec(origin=(-1.0, -1.0, -1.0), spacing=(0.05, 0.05, 0.01), dims=(21, 19, 600))
+
+    def run():
+        w, c = gwn.query_batch(m, Q, want_chi=True)
+        wg, cg = gwn.query_grid(m, g.origin, g.spacing, g.dims, want_chi=True)
+        return [w, c, wg, cg, gwn.query_gradient(m, Q), gwn.query_direct(m, Q[:1000])]
+
+    ref = run()
+    monkeypatch.setenv("GWN_MAX_LAUNCH_QUERIES", "768")
+    out = run()
+    torch.cuda.synchronize()
+    for a, b in zip(ref, out):
+        assert torch.equal(a, b)
