@@ -56,6 +56,7 @@
  *     under the perturbation q_eps.
  */
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -390,6 +391,24 @@ static inline void or_alg1_nd(const double* A, const double* B, double* N, doubl
          (B[0] * x1[0] + B[1] * x1[1] + B[2] * x1[2]);
 }
 
+/* D adds terms of size up to 1 that cancel when both endpoints lie nearly on
+ * the +z axis through the query (D ~ rho^2/l^2 there) or where the spherical
+ * triangle's area crosses +-pi; below this bound its double rounding error is
+ * no longer small against D, and the same expression is evaluated again in
+ * IEEE binary128 from the (exact) double offsets. */
+#define OR_ESCALATE 0x1p-10
+
+static void or_alg1_nd_q(const double* ra, const double* rb, double* N, double* D)
+{
+    __float128 A[3], B[3];
+    const __float128 la = sqrtq((__float128)ra[0] * ra[0] + (__float128)ra[1] * ra[1] + (__float128)ra[2] * ra[2]);
+    const __float128 lb = sqrtq((__float128)rb[0] * rb[0] + (__float128)rb[1] * rb[1] + (__float128)rb[2] * rb[2]);
+    for (int i = 0; i < 3; ++i) { A[i] = ra[i] / la; B[i] = rb[i] / lb; }
+    /* x1 = (0, 0, -1): B x x1 = (-B_y, B_x, 0) */
+    *N = (double)(A[0] * -B[1] + A[1] * B[0]);
+    *D = (double)(1 + (A[0] * B[0] + A[1] * B[1] + A[2] * B[2]) - A[2] - B[2]);
+}
+
 /* Limit of 2*atan2(N, D) for an edge whose first (first_on=1) or second
  * endpoint lies on the +z ray, as the query moves to q_eps: that endpoint's
  * x/y offset becomes (-e1, -e2).  o = x/y offset of the other endpoint. */
@@ -452,6 +471,7 @@ static double or_boundary_sum(const or_bdry* Bd, const float* p, const int64_t* 
             double B[3] = {rb[0] / lb, rb[1] / lb, rb[2] / lb};
             double N, D;
             or_alg1_nd(A, B, &N, &D);
+            if (fabs(D) < OR_ESCALATE) or_alg1_nd_q(ra, rb, &N, &D);
             if (inbox && D <= 0.0) {
                 /* atan2 jumps where N changes sign with D < 0; N carries the
                  * sign of -orient2d(a, b, q_eps), the same polynomial as the
@@ -582,6 +602,65 @@ static inline void or_neumaier(double* s, double* c, double x)
     *s = t;
 }
 
+/* One edge's term c_n g_n + c_d g_d of Alg. 3 in double (x1 = -x0).  Returns 0
+ * without a result when d is small against l0 l1 (see OR_ESCALATE). */
+static int or_grad_edge(const double* r0, const double* r1, const double* x1, double* term)
+{
+    double v0[3], v1[3], r0xr1[3], r1xx1[3], x1xr0[3], gn[3], gd[3];
+    const double l0 = sqrt(or_dot(r0, r0)), l1v = sqrt(or_dot(r1, r1));
+    for (int a = 0; a < 3; ++a) { v0[a] = r0[a] / l0; v1[a] = r1[a] / l1v; }
+    or_cross(r0, r1, r0xr1);
+    const double n = or_dot(x1, r0xr1);
+    const double d = l0 * l1v + l1v * or_dot(x1, r0) + l0 * or_dot(x1, r1) + or_dot(r0, r1);
+    if (fabs(d) < OR_ESCALATE * l0 * l1v) return 0;
+    /* derivatives of 2 atan2(n, d) with respect to n and d */
+    const double cn = 2.0 * d / (n * n + d * d);
+    const double cd = -2.0 * n / (n * n + d * d);
+    /* dn/dp: n = r0.(r1 x x1) = r1.(x1 x r0), and dr0/dp = dr1/dp = -I */
+    or_cross(r1, x1, r1xx1);
+    or_cross(x1, r0, x1xr0);
+    for (int a = 0; a < 3; ++a) gn[a] = -(r1xx1[a] + x1xr0[a]);
+    /* dd/dr0 and dd/dr1; dd/dp is minus their sum */
+    const double x1v0 = or_dot(x1, v0), x1v1 = or_dot(x1, v1);
+    for (int a = 0; a < 3; ++a) {
+        const double t1 = l1v * (x1[a] + v1[a] + (1.0 + x1v1) * v0[a]);
+        const double t2 = l0 * (x1[a] + v0[a] + (1.0 + x1v0) * v1[a]);
+        gd[a] = -(t1 + t2);
+    }
+    for (int a = 0; a < 3; ++a) term[a] = cn * gn[a] + cd * gd[a];
+    return 1;
+}
+
+/* The same steps in binary128. */
+static void or_grad_edge_q(const double* r0d, const double* r1d, const double* x1d, double* term)
+{
+    __float128 r0[3], r1[3], x1[3], v0[3], v1[3], gn[3], gd[3];
+    for (int a = 0; a < 3; ++a) { r0[a] = r0d[a]; r1[a] = r1d[a]; x1[a] = x1d[a]; }
+    const __float128 l0 = sqrtq(r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]);
+    const __float128 l1v = sqrtq(r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
+    for (int a = 0; a < 3; ++a) { v0[a] = r0[a] / l0; v1[a] = r1[a] / l1v; }
+    const __float128 c[3] = {r0[1] * r1[2] - r0[2] * r1[1], r0[2] * r1[0] - r0[0] * r1[2],
+                             r0[0] * r1[1] - r0[1] * r1[0]};
+    const __float128 n = x1[0] * c[0] + x1[1] * c[1] + x1[2] * c[2];
+    const __float128 x1r0 = x1[0] * r0[0] + x1[1] * r0[1] + x1[2] * r0[2];
+    const __float128 x1r1 = x1[0] * r1[0] + x1[1] * r1[1] + x1[2] * r1[2];
+    const __float128 d = l0 * l1v + l1v * x1r0 + l0 * x1r1 + (r0[0] * r1[0] + r0[1] * r1[1] + r0[2] * r1[2]);
+    const __float128 cn = 2 * d / (n * n + d * d), cd = -2 * n / (n * n + d * d);
+    const __float128 r1xx1[3] = {r1[1] * x1[2] - r1[2] * x1[1], r1[2] * x1[0] - r1[0] * x1[2],
+                                 r1[0] * x1[1] - r1[1] * x1[0]};
+    const __float128 x1xr0[3] = {x1[1] * r0[2] - x1[2] * r0[1], x1[2] * r0[0] - x1[0] * r0[2],
+                                 x1[0] * r0[1] - x1[1] * r0[0]};
+    for (int a = 0; a < 3; ++a) gn[a] = -(r1xx1[a] + x1xr0[a]);
+    const __float128 x1v0 = x1[0] * v0[0] + x1[1] * v0[1] + x1[2] * v0[2];
+    const __float128 x1v1 = x1[0] * v1[0] + x1[1] * v1[1] + x1[2] * v1[2];
+    for (int a = 0; a < 3; ++a) {
+        const __float128 t1 = l1v * (x1[a] + v1[a] + (1 + x1v1) * v0[a]);
+        const __float128 t2 = l0 * (x1[a] + v0[a] + (1 + x1v0) * v1[a]);
+        gd[a] = -(t1 + t2);
+    }
+    for (int a = 0; a < 3; ++a) term[a] = (double)(cn * gn[a] + cd * gd[a]);
+}
+
 /* grad_out[3 * i ..], and l1_out[i] = sum over edges of |edge term| (may be NULL).
  * x0: unit axis; the boundary is the cancelled chain of oracle_boundary. */
 void oracle_gradient(const float* V, int64_t nv, const int32_t* F, int64_t nf, const float* Q, int64_t nq,
@@ -598,38 +677,13 @@ void oracle_gradient(const float* V, int64_t nv, const int32_t* F, int64_t nf, c
         const double p[3] = {(double)Q[3 * i], (double)Q[3 * i + 1], (double)Q[3 * i + 2]};
         double gs[3] = {0, 0, 0}, gc[3] = {0, 0, 0}, l1 = 0.0;
         for (int64_t e = 0; e < nb; ++e) {
-            double r0[3], r1[3], v0[3], v1[3];
+            double r0[3], r1[3], term[3];
             for (int a = 0; a < 3; ++a) {
                 r0[a] = (double)V[3 * from[e] + a] - p[a];
                 r1[a] = (double)V[3 * to[e] + a] - p[a];
             }
-            const double l0 = sqrt(or_dot(r0, r0)), l1v = sqrt(or_dot(r1, r1));
-            for (int a = 0; a < 3; ++a) { v0[a] = r0[a] / l0; v1[a] = r1[a] / l1v; }
-            double r0xr1[3];
-            or_cross(r0, r1, r0xr1);
-            const double n = or_dot(x1, r0xr1);
-            const double d = l0 * l1v + l1v * or_dot(x1, r0) + l0 * or_dot(x1, r1) + or_dot(r0, r1);
-            /* derivatives of 2 atan2(n, d) with respect to n and d */
-            const double cn = 2.0 * d / (n * n + d * d);
-            const double cd = -2.0 * n / (n * n + d * d);
-            /* dn/dp: n = r0.(r1 x x1) = r1.(x1 x r0), and dr0/dp = dr1/dp = -I */
-            double r1xx1[3], x1xr0[3], gn[3];
-            or_cross(r1, x1, r1xx1);
-            or_cross(x1, r0, x1xr0);
-            for (int a = 0; a < 3; ++a) gn[a] = -(r1xx1[a] + x1xr0[a]);
-            /* dd/dr0 and dd/dr1; dd/dp is minus their sum */
-            const double x1v0 = or_dot(x1, v0), x1v1 = or_dot(x1, v1);
-            double gd[3];
-            for (int a = 0; a < 3; ++a) {
-                const double t1 = l1v * (x1[a] + v1[a] + (1.0 + x1v1) * v0[a]);
-                const double t2 = l0 * (x1[a] + v0[a] + (1.0 + x1v0) * v1[a]);
-                gd[a] = -(t1 + t2);
-            }
-            double term[3];
-            for (int a = 0; a < 3; ++a) {
-                term[a] = cn * gn[a] + cd * gd[a];
-                or_neumaier(&gs[a], &gc[a], term[a]);
-            }
+            if (!or_grad_edge(r0, r1, x1, term)) or_grad_edge_q(r0, r1, x1, term);
+            for (int a = 0; a < 3; ++a) or_neumaier(&gs[a], &gc[a], term[a]);
             l1 += sqrt(or_dot(term, term));
         }
         for (int a = 0; a < 3; ++a) grad_out[3 * i + a] = (gs[a] + gc[a]) / (4.0 * OR_PI);

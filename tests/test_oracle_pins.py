@@ -436,3 +436,38 @@ def test_gradient_of_closed_mesh_is_zero_and_far_field_decays():
     g = O.gradient(OCT_V, OCT_F, [[10, 11, 12], [20, 22, 24]])
     ratio = np.linalg.norm(g[0]) / np.linalg.norm(g[1])
     assert 7.0 < ratio < 9.0
+
+
+def _near_axis_case():
+    # queries 0.7 below boundary vertices, 1e-7..1e-6 off their vertical line:
+    # Alg. 1's D and Alg. 3's d cancel to ~(rho/l)^2 there
+    s = W.opened_spheres(seed=40, n_surf=3, tris_per_surf=300)
+    fr, _ = O.boundary(s.F)
+    rng = np.random.default_rng(0)
+    Q = []
+    for v in s.V[fr[rng.choice(len(fr), min(40, len(fr)), replace=False)]].astype(np.float64):
+        for rho in (1e-7, 3e-7, 1e-6):
+            ang = rng.uniform(0, 2 * np.pi)
+            Q.append([v[0] + rho * np.cos(ang), v[1] + rho * np.sin(ang), v[2] - 0.7])
+    Q = np.array(Q, np.float32)
+    return s.V, s.F, Q[O.distance(s.V, s.F, Q, 1.0) > 0.01]
+
+
+def test_near_axis_antipodal_matches_direct():
+    V, F, Q = _near_axis_case()
+    assert len(Q) > 60
+    assert np.abs(O.antipodal(V, F, Q) - O.direct(V, F, Q)).max() < 1e-12
+
+
+def test_near_axis_gradient_matches_biot_savart_and_other_axes():
+    V, F, Q = _near_axis_case()
+    g, l1 = O.gradient(V, F, Q, with_l1=True)
+    assert l1.max() > 1e5             # individual edge terms are huge and cancel
+    fr, to = O.boundary(F)
+    Pd = Q.astype(np.float64)
+    ra = V[fr].astype(np.float64)[None] - Pd[:, None]
+    rb = V[to].astype(np.float64)[None] - Pd[:, None]
+    la, lb = np.linalg.norm(ra, axis=2), np.linalg.norm(rb, axis=2)
+    B = (np.cross(ra, rb) * ((la + lb) / (la * lb * (la * lb + (ra * rb).sum(2))))[..., None]).sum(1) / (4 * np.pi)
+    assert np.abs(B - g).max() < 1e-8
+    assert np.abs(O.gradient(V, F, Q, axis=(0.3, 0.4, -0.5)) - g).max() < 1e-8
