@@ -125,6 +125,18 @@ gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacin
                           int32_t prec, void* w_out, int32_t* chi_out, void* stream);
 
 /*
+ * gwn_query_crossings -- both signed crossing counts of each query's vertical
+ * line (Sec. 3.2 with the perturbed exact predicates of Supp. Sec. 2.1):
+ * chi_up = chi along x0 = +z (the count gwn_query_batch uses), chi_down = chi
+ * along the antipode -z, i.e. minus the signed crossings below the query.  For
+ * a closed mesh the two are equal; in general chi_up - chi_down is the signed
+ * count over the whole line.  Either output (device int32[nq]) may be NULL, not
+ * both.  Queries and errors as in gwn_query_batch.
+ */
+gwn_status gwn_query_crossings(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                               int64_t nq, int32_t* chi_up_out, int32_t* chi_down_out, void* stream);
+
+/*
  * gwn_query_gradient -- the gradient of w with respect to the query point
  * (Supp. Sec. 4, Alg. 3): the crossing count is locally constant, so only the
  * boundary-edge term is differentiated (x0 = +z; the gradient does not depend

@@ -161,6 +161,23 @@ gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacin
     return gwn::query_grid(m, origin, spacing, dims, prec, w_out, chi_out, (hipStream_t)stream);
 }
 
+gwn_status gwn_query_crossings(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                               int64_t nq, int32_t* chi_up_out, int32_t* chi_down_out, void* stream) {
+    gwn::clear_error();
+    gwn_status s = check_mesh(m, "gwn_query_crossings");
+    if (s != GWN_OK) return s;
+    if (nq < 0 || qstride < 1) {
+        gwn::set_error("gwn_query_crossings: bad nq or stride");
+        return GWN_E_INVALID;
+    }
+    if (nq == 0) return GWN_OK;
+    if (!qx || !qy || !qz || (!chi_up_out && !chi_down_out) || nq > (1ll << 40)) {
+        gwn::set_error("gwn_query_crossings: null array (one output may be null, not both) or nq too large");
+        return GWN_E_INVALID;
+    }
+    return gwn::query_crossings(m, qx, qy, qz, qstride, nq, chi_up_out, chi_down_out, (hipStream_t)stream);
+}
+
 gwn_status gwn_query_gradient(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                               int64_t nq, int32_t prec, void* grad_out, void* stream) {
     gwn::clear_error();

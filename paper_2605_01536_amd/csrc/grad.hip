@@ -29,12 +29,14 @@ struct GVtx {
     T rx, ry, rz, l, u, s;   // offset from p, length, 1/length, l - r_z
 };
 
+// offsets in units of 2^e cells (f = 2^-e, see far_scale): each edge term is
+// homogeneous of degree -1 in the offsets, so the sum is rescaled at the end
 template <class T, bool FLIP>
-__device__ __forceinline__ GVtx<T> gvtx(const BVert& b, T pxs, T pys, T pzs) {
+__device__ __forceinline__ GVtx<T> gvtx(const BVert& b, T pxs, T pys, T pzs, T f) {
     GVtx<T> v;
-    v.rx = (T)b.x - pxs;
-    v.ry = (T)b.y - pys;
-    v.rz = FLIP ? pzs - (T)b.z : (T)b.z - pzs;
+    v.rx = fma((T)b.x, f, -pxs);
+    v.ry = fma((T)b.y, f, -pys);
+    v.rz = FLIP ? -fma((T)b.z, f, -pzs) : fma((T)b.z, f, -pzs);
     const T rho2 = v.rx * v.rx + v.ry * v.ry;
     v.l = Arith<T>::sqrt(v.rz * v.rz + rho2);
     v.u = Arith<T>::rcp(v.l);
@@ -61,19 +63,19 @@ __device__ __forceinline__ void gedge(const GVtx<T>& a, const GVtx<T>& b, T& gx,
 // Sum over all loops of the edge terms, in cell units (FP32 partials flushed
 // into FP64 every 32 edges).  FLIP: the mirrored sum for the axis x0 = -z.
 template <class T, bool FLIP>
-__device__ void grad_loops(const MeshView& mv, T pxs, T pys, T pzs, double* G) {
+__device__ void grad_loops(const MeshView& mv, T pxs, T pys, T pzs, T f, double* G) {
     const BVert* __restrict__ bv = mv.bverts;
     G[0] = G[1] = G[2] = 0.0;
     for (int l = 0; l < mv.nloops; ++l) {
         const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
-        const GVtx<T> first = gvtx<T, FLIP>(bv[b0], pxs, pys, pzs);
+        const GVtx<T> first = gvtx<T, FLIP>(bv[b0], pxs, pys, pzs, f);
         GVtx<T> prev = first;
         for (int j = b0 + 1; j <= b1; j += 32) {
             const int je = min(b1 + 1, j + 32);
             T gx = (T)0, gy = (T)0, gz = (T)0;
             for (int jj = j; jj < je; ++jj) {
                 // index b1 closes the loop back to its first vertex
-                const GVtx<T> cur = jj < b1 ? gvtx<T, FLIP>(bv[jj], pxs, pys, pzs) : first;
+                const GVtx<T> cur = jj < b1 ? gvtx<T, FLIP>(bv[jj], pxs, pys, pzs, f) : first;
                 gedge<T>(prev, cur, gx, gy, gz);
                 prev = cur;
             }
@@ -95,14 +97,15 @@ __global__ __launch_bounds__(256) void k_grad_batch(MeshView mv, const float* __
     const long long i = blockIdx.x * 256ll + threadIdx.x;
     if (blockIdx.x * 256ll >= nq) return;
     const long long ii = i < nq ? i : nq - 1;
-    const T sc = (T)mv.g.scale;
-    const T pxs = (T)qx[ii * qs] * sc, pys = (T)qy[ii * qs] * sc, pzs = (T)qz[ii * qs] * sc;
+    const float px = qx[ii * qs], py = qy[ii * qs], pz = qz[ii * qs];
+    const FarScale<T> fs = far_scale<T>(px, py, fabsf(pz), mv.g.scale);
+    const T pxs = (T)px * fs.scf, pys = (T)py * fs.scf, pzs = (T)pz * fs.scf;
     double G[3];
-    grad_loops<T, false>(mv, pxs, pys, pzs, G);
-    if (!(isfinite(G[0]) && isfinite(G[1]) && isfinite(G[2]))) grad_loops<T, true>(mv, pxs, pys, pzs, G);
+    grad_loops<T, false>(mv, pxs, pys, pzs, fs.f, G);
+    if (!(isfinite(G[0]) && isfinite(G[1]) && isfinite(G[2]))) grad_loops<T, true>(mv, pxs, pys, pzs, fs.f, G);
     if (i < nq) {
-        // sum of 2 atan2 terms over 4 pi, and the chain rule through p * 2^k
-        const double f = kInv2Pi * mv.g.scale;
+        // sum of 2 atan2 terms over 4 pi, and the chain rule through p * 2^(k-e)
+        const double f = kInv2Pi * (double)fs.scf;
         g[3 * i] = (T)(G[0] * f);
         g[3 * i + 1] = (T)(G[1] * f);
         g[3 * i + 2] = (T)(G[2] * f);

@@ -110,14 +110,34 @@ struct ColV {
     T rx, ry, rho2;
 };
 
+// Offsets of a query outside the fixed-point box are taken in units of 2^e
+// cells, e >= 0 chosen per query so that they stay below about 2^41: atan2(N, D)
+// does not change under a common positive scale of all offsets, and FP32 would
+// otherwise overflow N, D and rho^2 for queries ~1e10 mesh sizes away.  f = 2^-e
+// scales the boundary vertices (exactly), scf = 2^(k-e) the query.
+template <class T>
+struct FarScale {
+    T scf, f;
+};
+
+template <class T>
+__device__ __forceinline__ FarScale<T> far_scale(float px, float py, float pz_abs_max, double scale) {
+    const double M = fmax(fmax(fabs((double)px), fabs((double)py)), (double)pz_abs_max) * scale;
+    const int e = M > 0x1p40 ? ilogb(M) - 40 : 0;
+    FarScale<T> s;
+    s.scf = (T)ldexp(scale, -e);
+    s.f = (T)ldexp(1.0, -e);
+    return s;
+}
+
 template <class T, bool FAR>
-__device__ __forceinline__ ColV<T> col_vtx(const BVert& b, int qqx, int qqy, T pxs, T pys) {
+__device__ __forceinline__ ColV<T> col_vtx(const BVert& b, int qqx, int qqy, T pxs, T pys, T f) {
     ColV<T> c;
     c.dx = b.qx - qqx;
     c.dy = b.qy - qqy;
     if (FAR) {
-        c.rx = (T)b.x - pxs;
-        c.ry = (T)b.y - pys;
+        c.rx = fma((T)b.x, f, -pxs);
+        c.ry = fma((T)b.y, f, -pys);
     } else {
         c.rx = (T)c.dx;
         c.ry = (T)c.dy;
@@ -187,12 +207,12 @@ __device__ __forceinline__ void edge_step(const ColV<T>& a, const ColV<T>& b, co
 }
 
 template <class T, int ZB, bool FAR>
-__device__ __forceinline__ void load_vertex(const BVert& b, int qqx, int qqy, T pxs, T pys, const T* pzs, ColV<T>& c,
-                                            T* rz, T* sv) {
-    c = col_vtx<T, FAR>(b, qqx, qqy, pxs, pys);
+__device__ __forceinline__ void load_vertex(const BVert& b, int qqx, int qqy, T pxs, T pys, const T* pzs, T f,
+                                            ColV<T>& c, T* rz, T* sv) {
+    c = col_vtx<T, FAR>(b, qqx, qqy, pxs, pys, f);
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {
-        rz[r] = (T)b.z - pzs[r];
+        rz[r] = FAR ? fma((T)b.z, f, -pzs[r]) : (T)b.z - pzs[r];
         sv[r] = samp_s<T>(c.rho2, rz[r]);
     }
 }
@@ -201,13 +221,13 @@ __device__ __forceinline__ void load_vertex(const BVert& b, int qqx, int qqy, T 
 // (x, y).  FP32 partials are flushed into the FP64 sum every 32 edges.
 template <class T, int ZB, bool FAR>
 __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int qqy, T pxs, T pys, const T* pzs,
-                                               double* S) {
+                                               double* S, T f = (T)1) {
     const BVert* __restrict__ bv = mv.bverts;
     for (int l = 0; l < mv.nloops; ++l) {
         const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
         ColV<T> cf, cp;
         T rzf[ZB], sf[ZB], rzp[ZB], sp[ZB];
-        load_vertex<T, ZB, FAR>(bv[b0], qqx, qqy, pxs, pys, pzs, cf, rzf, sf);
+        load_vertex<T, ZB, FAR>(bv[b0], qqx, qqy, pxs, pys, pzs, f, cf, rzf, sf);
         cp = cf;
 #pragma unroll
         for (int r = 0; r < ZB; ++r) {
@@ -225,15 +245,15 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
             for (; j + 1 < je; j += 2) {
                 ColV<T> c1;
                 T rz1[ZB], s1[ZB];
-                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pzs, c1, rz1, s1);
+                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pzs, f, c1, rz1, s1);
                 edge_step<T, ZB, FAR>(cp, c1, sp, s1, rzp, rz1, acc);
-                load_vertex<T, ZB, FAR>(bv[j + 1], qqx, qqy, pxs, pys, pzs, cp, rzp, sp);
+                load_vertex<T, ZB, FAR>(bv[j + 1], qqx, qqy, pxs, pys, pzs, f, cp, rzp, sp);
                 edge_step<T, ZB, FAR>(c1, cp, s1, sp, rz1, rzp, acc);
             }
             if (j < je) {
                 ColV<T> cc;
                 T rzc[ZB], sc[ZB];
-                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pzs, cc, rzc, sc);
+                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pzs, f, cc, rzc, sc);
                 edge_step<T, ZB, FAR>(cp, cc, sp, sc, rzp, rzc, acc);
                 cp = cc;
 #pragma unroll
@@ -298,6 +318,55 @@ __device__ int chi_up(const MeshView& mv, const QPoint& q, int* stk) {
         }
     }
     return c;
+}
+
+// Signed crossings of the whole vertical line through q, split at q: up = the
+// sum of s over crossings above q (chi along +z), down = minus the sum over
+// crossings below it (chi along -z).  Same traversal as chi_up without the
+// z pruning.
+__device__ void chi_line(const MeshView& mv, const QPoint& q, int* stk, int& up, int& down) {
+    up = down = 0;
+    int node = mv.root;
+    if (node == kNoRoot) return;
+    auto leaf = [&](int t) {
+        const TriQ tr = mv.tris[t];
+        const int s = tri_xy_sign(tr, q.x, q.y);
+        if (s == 0) return;
+        if (plane_above(plane_of(tr, q.x, q.y), q.z)) up += s;
+        else down -= s;
+    };
+    if (node < 0) {
+        leaf(~node);
+        return;
+    }
+    int sp = 0;
+    while (true) {
+        const Node nd = mv.nodes[node];
+        bool hl = box_has_xy(nd.lxy.x, nd.lxy.y, nd.lxy.z, nd.lxy.w, q.x, q.y);
+        bool hr = box_has_xy(nd.rxy.x, nd.rxy.y, nd.rxy.z, nd.rxy.w, q.x, q.y);
+        const int L = nd.link.x, R = nd.link.y;
+        if (hl && L < 0) {
+            leaf(~L);
+            hl = false;
+        }
+        if (hr && R < 0) {
+            leaf(~R);
+            hr = false;
+        }
+        if (hl && hr) {
+            stk[sp * kChiBlock] = R;
+            ++sp;
+            node = L;
+        } else if (hl) {
+            node = L;
+        } else if (hr) {
+            node = R;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = stk[sp * kChiBlock];
+        }
+    }
 }
 
 }  // namespace

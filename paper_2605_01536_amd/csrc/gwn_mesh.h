@@ -58,6 +58,9 @@ gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* s
 // GWN_MAX_LAUNCH_QUERIES (a positive multiple of 256) lowers it, for tests.
 int64_t max_launch_queries();
 
+gwn_status query_crossings(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                           int64_t nq, int32_t* up, int32_t* down, hipStream_t stream);
+
 gwn_status query_gradient(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                           int64_t nq, int prec, void* g_out, hipStream_t stream);
 

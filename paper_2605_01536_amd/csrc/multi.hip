@@ -75,11 +75,15 @@ __global__ __launch_bounds__(256) void k_bdry_persistent(const MeshView* __restr
             const long long i = I.q0 + min(k, I.nq - 1);
             const float px = qx[i * qs], py = qy[i * qs], pz = qz[i * qs];
             const QPoint q = quantize_point(px, py, pz, mv.g);
-            const float sc = mv.g.scalef;
-            const float pzs = pz * sc;
             double S = 0.0;
-            if (q.inbox) boundary_loops<float, 1, false>(mv, q.x, q.y, 0.f, 0.f, &pzs, &S);
-            else boundary_loops<float, 1, true>(mv, 0, 0, px * sc, py * sc, &pzs, &S);
+            if (q.inbox) {
+                const float pzs = pz * mv.g.scalef;
+                boundary_loops<float, 1, false>(mv, q.x, q.y, 0.f, 0.f, &pzs, &S);
+            } else {
+                const FarScale<float> fs = far_scale<float>(px, py, fabsf(pz), mv.g.scale);
+                const float pzs = pz * fs.scf;
+                boundary_loops<float, 1, true>(mv, 0, 0, px * fs.scf, py * fs.scf, &pzs, &S, fs.f);
+            }
             if (k < I.nq) w[i] = (float)((double)chi[i] + S * kInv2Pi);
         }
     }

@@ -26,6 +26,21 @@ __global__ __launch_bounds__(kChiBlock) void k_chi_batch(MeshView mv, const floa
     chi[i] = q.inbox ? chi_up(mv, q, stk + threadIdx.x) : 0;
 }
 
+// both crossing counts of arbitrary points (the whole vertical line)
+__global__ __launch_bounds__(kChiBlock) void k_chi_line(MeshView mv, const float* __restrict__ qx,
+                                                        const float* __restrict__ qy, const float* __restrict__ qz,
+                                                        long long qs, long long nq, int* __restrict__ up,
+                                                        int* __restrict__ down) {
+    __shared__ int stk[kLdsStack * kChiBlock];
+    const long long i = blockIdx.x * (long long)kChiBlock + threadIdx.x;
+    if (i >= nq) return;
+    const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
+    int u = 0, d = 0;
+    if (q.inbox) chi_line(mv, q, stk + threadIdx.x, u, d);
+    if (up) up[i] = u;
+    if (down) down[i] = d;
+}
+
 // ---------------------------------------------------------------- boundary, batch
 
 template <class T>
@@ -39,12 +54,16 @@ __global__ __launch_bounds__(256) void k_bdry_batch(MeshView mv, const float* __
     const long long ii = i < nq ? i : nq - 1;
     const float px = qx[ii * qs], py = qy[ii * qs], pz = qz[ii * qs];
     const QPoint q = quantize_point(px, py, pz, mv.g);
-    const T sc = (T)mv.g.scale;
-    const T pxs = (T)px * sc, pys = (T)py * sc, pzs = (T)pz * sc;
     // lanes outside the fixed-point grid (rare) take the raw-offset loop
     double S = 0.0;
-    if (q.inbox) boundary_loops<T, 1, false>(mv, q.x, q.y, (T)0, (T)0, &pzs, &S);
-    else boundary_loops<T, 1, true>(mv, 0, 0, pxs, pys, &pzs, &S);
+    if (q.inbox) {
+        const T pzs = (T)pz * (T)mv.g.scale;
+        boundary_loops<T, 1, false>(mv, q.x, q.y, (T)0, (T)0, &pzs, &S);
+    } else {
+        const FarScale<T> fs = far_scale<T>(px, py, fabsf(pz), mv.g.scale);
+        const T pzs = (T)pz * fs.scf;
+        boundary_loops<T, 1, true>(mv, 0, 0, (T)px * fs.scf, (T)py * fs.scf, &pzs, &S, fs.f);
+    }
     if (i < nq) w[i] = (T)((double)chi[i] + S * kInv2Pi);
 }
 
@@ -135,16 +154,28 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs 
     }
 
     // ---- boundary term
-    const T sc = (T)mv.g.scale;
     T pzs[ZB];
     double S[ZB];
+    if (q0.inbox) {
+        const T sc = (T)mv.g.scale;
 #pragma unroll
-    for (int r = 0; r < ZB; ++r) {
-        pzs[r] = (T)pz[r] * sc;
-        S[r] = 0.0;
+        for (int r = 0; r < ZB; ++r) {
+            pzs[r] = (T)pz[r] * sc;
+            S[r] = 0.0;
+        }
+        boundary_loops<T, ZB, false>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S);
+    } else {
+        float pzm = 0.f;
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) pzm = fmaxf(pzm, fabsf(pz[r]));
+        const FarScale<T> fs = far_scale<T>(px, py, pzm, mv.g.scale);
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) {
+            pzs[r] = (T)pz[r] * fs.scf;
+            S[r] = 0.0;
+        }
+        boundary_loops<T, ZB, true>(mv, 0, 0, (T)px * fs.scf, (T)py * fs.scf, pzs, S, fs.f);
     }
-    if (q0.inbox) boundary_loops<T, ZB, false>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S);
-    else boundary_loops<T, ZB, true>(mv, 0, 0, (T)px * sc, (T)py * sc, pzs, S);
 
     const long long base = col * ga.nz;
 #pragma unroll
@@ -219,6 +250,19 @@ gwn_status launch_grid(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out,
 }
 
 }  // namespace
+
+gwn_status query_crossings(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
+                           int64_t nq, int32_t* up, int32_t* down, hipStream_t st) {
+    const MeshView mv = m->view();
+    const int64_t chunk = max_launch_queries();
+    for (int64_t o = 0; o < nq; o += chunk) {
+        const int64_t n = std::min<int64_t>(chunk, nq - o);
+        k_chi_line<<<(unsigned)((n + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(
+            mv, qx + o * qs, qy + o * qs, qz + o * qs, qs, n, up ? up + o : nullptr, down ? down + o : nullptr);
+        GWN_HIP_TRY(hipGetLastError());
+    }
+    return GWN_OK;
+}
 
 int64_t max_launch_queries() {
     int64_t n = int64_t(1) << 30;

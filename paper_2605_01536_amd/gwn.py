@@ -48,6 +48,8 @@ def load():
     L.gwn_query_batch.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp, vp]
     L.gwn_query_grid.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int64), i32, vp, vp, vp]
+    L.gwn_query_crossings.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp]
+    L.gwn_query_crossings.restype = ctypes.c_int
     L.gwn_query_gradient.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp]
     L.gwn_query_gradient.restype = ctypes.c_int
     L.gwn_query_direct.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp]
@@ -77,12 +79,40 @@ def _ptr(t) -> int:
     return int(t.data_ptr()) if t is not None else 0
 
 
+def _points(Q, name="Q"):
+    """An (n, 3) CUDA tensor as contiguous float32 (the layout the C ABI reads)."""
+    import torch
+    if not (isinstance(Q, torch.Tensor) and Q.is_cuda and Q.dim() == 2 and Q.shape[1] == 3):
+        raise ValueError(f"{name} must be an (n, 3) CUDA tensor")
+    return Q.to(torch.float32).contiguous()
+
+
+def _out(t, shape, dtype, device, name):
+    """A caller-supplied output must match exactly (the kernels write shape[0] rows);
+    None allocates one."""
+    import torch
+    shape = tuple(int(x) for x in shape)
+    if t is None:
+        return torch.empty(shape, device=device, dtype=dtype)
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+            and tuple(t.shape) == shape):
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor of shape {shape}")
+    return t
+
+
+def _wdtype(p):
+    import torch
+    return torch.float64 if p == GWN_PREC_FP64 else torch.float32
+
+
 class Mesh:
     """A soup built on the device: V (nv, 3) float32 and F (nf, 3) int32 CUDA tensors."""
 
     def __init__(self, V, F, stream=None):
         import torch
         L = load()
+        if V.dim() != 2 or V.shape[1] != 3 or F.dim() != 2 or F.shape[1] != 3:
+            raise ValueError("V must be (nv, 3) and F (nf, 3)")
         V = V.to(device="cuda", dtype=torch.float32).contiguous()
         F = F.to(device="cuda", dtype=torch.int32).contiguous()
         self._h = ctypes.c_void_p()
@@ -122,16 +152,28 @@ def query_batch(mesh: Mesh, Q, prec="fp32", want_chi=False, out=None, chi_out=No
     import torch
     L = load()
     p = _PREC[prec]
-    Q = Q.contiguous()
+    Q = _points(Q)
     n = Q.shape[0]
-    if out is None:
-        out = torch.empty(n, device=Q.device, dtype=torch.float64 if p == GWN_PREC_FP64 else torch.float32)
-    if want_chi and chi_out is None:
-        chi_out = torch.empty(n, device=Q.device, dtype=torch.int32)
+    out = _out(out, (n,), _wdtype(p), Q.device, "out")
+    if want_chi or chi_out is not None:
+        chi_out = _out(chi_out, (n,), torch.int32, Q.device, "chi_out")
     base = _ptr(Q)
     _check(L.gwn_query_batch(mesh.handle, base, base + 4, base + 8, 3, n, p, _ptr(out),
                              _ptr(chi_out) if chi_out is not None else None, _stream(stream)))
     return (out, chi_out) if want_chi else out
+
+
+def query_crossings(mesh: Mesh, Q, stream=None):
+    """(chi along +z, chi along -z) per point, int32 CUDA tensors."""
+    import torch
+    L = load()
+    Q = _points(Q)
+    n = Q.shape[0]
+    up = torch.empty(n, device=Q.device, dtype=torch.int32)
+    dn = torch.empty(n, device=Q.device, dtype=torch.int32)
+    base = _ptr(Q)
+    _check(L.gwn_query_crossings(mesh.handle, base, base + 4, base + 8, 3, n, _ptr(up), _ptr(dn), _stream(stream)))
+    return up, dn
 
 
 def query_gradient(mesh: Mesh, Q, prec="fp32", out=None, stream=None):
@@ -139,10 +181,9 @@ def query_gradient(mesh: Mesh, Q, prec="fp32", out=None, stream=None):
     import torch
     L = load()
     p = _PREC[prec]
-    Q = Q.contiguous()
+    Q = _points(Q)
     n = Q.shape[0]
-    if out is None:
-        out = torch.empty((n, 3), device=Q.device, dtype=torch.float64 if p == GWN_PREC_FP64 else torch.float32)
+    out = _out(out, (n, 3), _wdtype(p), Q.device, "out")
     base = _ptr(Q)
     _check(L.gwn_query_gradient(mesh.handle, base, base + 4, base + 8, 3, n, p, _ptr(out), _stream(stream)))
     return out
@@ -153,10 +194,9 @@ def query_direct(mesh: Mesh, Q, prec="fp32", out=None, stream=None):
     import torch
     L = load()
     p = _PREC[prec]
-    Q = Q.contiguous()
+    Q = _points(Q)
     n = Q.shape[0]
-    if out is None:
-        out = torch.empty(n, device=Q.device, dtype=torch.float64 if p == GWN_PREC_FP64 else torch.float32)
+    out = _out(out, (n,), _wdtype(p), Q.device, "out")
     base = _ptr(Q)
     _check(L.gwn_query_direct(mesh.handle, base, base + 4, base + 8, 3, n, p, _ptr(out), _stream(stream)))
     return out
@@ -167,11 +207,12 @@ def query_grid(mesh: Mesh, origin, spacing, dims, prec="fp32", want_chi=False, o
     import torch
     L = load()
     p = _PREC[prec]
+    if len(dims) != 3 or min(int(x) for x in dims) < 0:
+        raise ValueError("dims must be three non-negative sizes")
     n = int(dims[0]) * int(dims[1]) * int(dims[2])
-    if out is None:
-        out = torch.empty(n, device="cuda", dtype=torch.float64 if p == GWN_PREC_FP64 else torch.float32)
-    if want_chi and chi_out is None:
-        chi_out = torch.empty(n, device="cuda", dtype=torch.int32)
+    out = _out(out, (n,), _wdtype(p), "cuda", "out")
+    if want_chi or chi_out is not None:
+        chi_out = _out(chi_out, (n,), torch.int32, "cuda", "chi_out")
     o = (ctypes.c_double * 3)(*[float(x) for x in origin])
     s = (ctypes.c_double * 3)(*[float(x) for x in spacing])
     d = (ctypes.c_int64 * 3)(*[int(x) for x in dims])
@@ -215,11 +256,12 @@ class MultiPlan:
         L = load()
         _load_multi(L)
         self._meshes = list(meshes)
-        self._Q = Q.contiguous()
+        self._Q = _points(Q)
         n = int(offsets[-1])
-        assert self._Q.shape[0] >= n
-        self.w = w_out if w_out is not None else torch.empty(n, device=Q.device, dtype=torch.float32)
-        self.chi = chi_out
+        if len(offsets) != len(self._meshes) + 1 or self._Q.shape[0] < n:
+            raise ValueError("offsets must have nmesh + 1 entries ending at most at len(Q)")
+        self.w = _out(w_out, (n,), torch.float32, Q.device, "w_out")
+        self.chi = _out(chi_out, (n,), torch.int32, Q.device, "chi_out") if chi_out is not None else None
         hs = (ctypes.c_void_p * len(self._meshes))(*[m.handle.value for m in self._meshes])
         offs = (ctypes.c_int64 * len(offsets))(*[int(o) for o in offsets])
         self._cache = tune_cache.encode() if tune_cache else None
@@ -252,6 +294,13 @@ class MultiPlan:
 
 
 MLP_NPARAMS = 57985
+
+
+def _target(T, Q):
+    import torch
+    if not (isinstance(T, torch.Tensor) and T.is_cuda and T.dim() == 1 and T.shape[0] == Q.shape[0]):
+        raise ValueError("target must be a 1-D CUDA tensor with one value per point")
+    return T.to(torch.float32).contiguous()
 
 
 def _load_mlp(L):
@@ -310,18 +359,17 @@ class Surrogate:
 
     def forward(self, Q, out=None, stream=None):
         import torch
-        Q = Q.contiguous()
+        Q = _points(Q)
         n = Q.shape[0]
-        if out is None:
-            out = torch.empty(n, device=Q.device, dtype=torch.float32)
+        out = _out(out, (n,), torch.float32, Q.device, "out")
         b = _ptr(Q)
         _check(load().gwn_mlp_forward(self._h, b, b + 4, b + 8, 3, n, _ptr(out), _stream(stream)))
         return out
 
     def loss_grad(self, Q, target, stream=None):
         import torch
-        Q = Q.contiguous()
-        target = target.contiguous().float()
+        Q = _points(Q)
+        target = _target(target, Q)
         g = torch.empty(MLP_NPARAMS, device=Q.device, dtype=torch.float32)
         loss = ctypes.c_float(0)
         b = _ptr(Q)
@@ -330,8 +378,8 @@ class Surrogate:
         return float(loss.value), g
 
     def train_step(self, Q, target, lr: float, want_loss: bool = True, stream=None):
-        Q = Q.contiguous()
-        target = target.contiguous().float()
+        Q = _points(Q)
+        target = _target(target, Q)
         loss = ctypes.c_float(0)
         b = _ptr(Q)
         _check(load().gwn_mlp_train_step(self._h, b, b + 4, b + 8, 3, _ptr(target), Q.shape[0], float(lr),
@@ -341,10 +389,9 @@ class Surrogate:
     def query(self, mesh: Mesh, Q, band: float, out=None, want_mask: bool = False, stream=None):
         """Prediction, with exact re-evaluation where |prediction - 1/2| < band."""
         import torch
-        Q = Q.contiguous()
+        Q = _points(Q)
         n = Q.shape[0]
-        if out is None:
-            out = torch.empty(n, device=Q.device, dtype=torch.float32)
+        out = _out(out, (n,), torch.float32, Q.device, "out")
         mask = torch.empty(n, device=Q.device, dtype=torch.uint8) if want_mask else None
         nfb = ctypes.c_int64(0)
         b = _ptr(Q)

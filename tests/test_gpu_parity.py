@@ -201,3 +201,88 @@ def test_launch_splitting_is_invisible(gwn, monkeypatch):
     torch.cuda.synchronize()
     for a, b in zip(ref, out):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("case", ["tiny", "torus", "grid512", "closed"])
+def test_crossings_both_directions(gwn, case):
+    # chi along +z and along the antipode -z, bit for bit against the oracle
+    if case == "tiny":
+        rng = np.random.default_rng(77)
+        V = (np.round(rng.uniform(-1, 1, size=(150, 3)) * 16) / 16).astype(np.float32)
+        F = rng.integers(0, 150, size=(50, 3)).astype(np.int32)
+        Q = (np.round(rng.uniform(-1.2, 1.2, size=(3001, 3)) * 16) / 16).astype(np.float32)
+    elif case == "torus":
+        s, Q = W.config2(n_uniform=2000, n_near=2000)
+        V, F = s.V, s.F
+    elif case == "grid512":
+        s, g = W.config4()
+        V, F = s.V, s.F
+        Q = W.grid_points(g, np.random.default_rng(4).choice(g.n, 2000, replace=False))
+    else:
+        s, Q = W.config1()
+        V, F = s.V, s.F
+    m = gwn.Mesh(_dev(V), _dev(F))
+    up, dn = gwn.query_crossings(m, _dev(Q))
+    ou, od = O.chi(V, F, Q)
+    assert np.array_equal(up.cpu().numpy(), ou)
+    assert np.array_equal(dn.cpu().numpy(), od)
+    _, chi = gwn.query_batch(m, _dev(Q), want_chi=True)
+    assert torch.equal(chi, up)
+    if case == "closed":
+        assert torch.equal(up, dn)
+
+
+def test_binding_rejects_mismatched_tensors(gwn):
+    m = gwn.Mesh(_dev(OCT_V), _dev(OCT_F))
+    Q = torch.rand((100, 3), device="cuda")
+    with pytest.raises(ValueError):
+        gwn.query_batch(m, Q, out=torch.empty(99, device="cuda"))
+    with pytest.raises(ValueError):
+        gwn.query_batch(m, Q, prec="fp64", out=torch.empty(100, device="cuda"))
+    with pytest.raises(ValueError):
+        gwn.query_gradient(m, Q, out=torch.empty((100, 2), device="cuda"))
+    with pytest.raises(ValueError):
+        gwn.query_batch(m, torch.rand((100, 2), device="cuda"))
+    with pytest.raises(ValueError):
+        gwn.Mesh(_dev(OCT_V[:, :2].copy()), _dev(OCT_F))
+
+
+def test_batch_beyond_one_launch(gwn):
+    # 2^30 + 4099 points: the largest single launch plus a ragged second one
+    # (13 GB of points); sampled outputs around the split against the oracle
+    n = (1 << 30) + 4099
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(123)
+    Q = torch.rand((n, 3), device="cuda", generator=gen) * 3.0 - 1.0
+    m = gwn.Mesh(_dev(OCT_V), _dev(OCT_F))
+    w = torch.full((n,), float("nan"), device="cuda")
+    chi = torch.full((n,), -7, device="cuda", dtype=torch.int32)
+    gwn.query_batch(m, Q, out=w, chi_out=chi)
+    torch.cuda.synchronize()
+    assert not bool(torch.isnan(w).any()) and int(chi.min()) >= 0
+    idx = np.concatenate([np.arange((1 << 30) - 300, (1 << 30) + 300), np.arange(n - 200, n),
+                          np.random.default_rng(9).choice(n, 1000, replace=False)])
+    it = torch.from_numpy(idx).cuda()
+    P = Q[it].cpu().numpy()
+    del Q
+    compare(w[it].cpu().numpy(), chi[it].cpu().numpy(), OCT_V, OCT_F, P, TOL_FP32, "beyond-one-launch")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_astronomically_far_queries(gwn, prec):
+    # scaled coordinates overflow FP32 here; w and its gradient are ~0 there
+    s = W.opened_spheres(seed=40, n_surf=3, tris_per_surf=300)
+    # (FAR queries take offsets in units of 2^e cells; without that FP32 N, D
+    # and rho^2 overflow beyond ~1e10 mesh sizes)
+    Q = np.array([[1e35, 0, 0], [0, -1e36, 0.5], [3e38, 3e38, 3e38], [0.1, 0.2, 1e35], [0.1, 0.2, -1e35],
+                  [-2e34, 0.3, -1e37], [5e3, 1, 2], [-3e6, 2e6, 1e6], [1e11, -1e11, 0.5], [7e15, 0.1, -3e15],
+                  [0.1, 0.2, 1e12], [0.1, 0.2, -1e12]], np.float32)
+    m = gwn.Mesh(_dev(s.V), _dev(s.F))
+    w, chi = gwn.query_batch(m, _dev(Q), prec=prec, want_chi=True)
+    g = gwn.query_gradient(m, _dev(Q), prec=prec)
+    w, chi, g = w.cpu().numpy(), chi.cpu().numpy(), g.cpu().numpy()
+    up, _ = O.chi(s.V, s.F, Q)
+    assert np.array_equal(chi, up)
+    assert np.isfinite(w).all() and np.isfinite(g).all()
+    assert np.abs(w - O.direct(s.V, s.F, Q)).max() < 1e-6
+    assert np.abs(w).max() < 1e-6 and np.abs(g).max() < 1e-6
