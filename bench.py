@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["grid", "batch", "batched", "surrogate", "precision", "gradient",
-                                                 "direct"], default="grid",
+                                                 "direct", "weld"], default="grid",
                     help="grid: the headline 512^3 grid on the 1M-triangle soup (default); batch: 2M points on the "
                          "torus soup; batched: 256 soups in one persistent graph; surrogate: MLP + exact fallback")
     ap.add_argument("--n-mesh", type=int, default=256, help="soups in the batched workload")
@@ -97,7 +97,8 @@ def main():
         return
     if args.workload != "grid":
         {"batch": bench_batch, "batched": bench_batched, "surrogate": bench_surrogate,
-         "precision": bench_precision, "gradient": bench_gradient, "direct": bench_direct}[args.workload](args)
+         "precision": bench_precision, "gradient": bench_gradient, "direct": bench_direct,
+         "weld": bench_weld}[args.workload](args)
         return
     t0 = time.time()
     soup, grid = W.config4(n=args.n)
@@ -304,6 +305,41 @@ def bench_direct(args):
           P4.shape[0] / rows[0]["direct_qps"] * 1e3,
           {"workload": "direct per-triangle sum vs antipodal on the same points", "precision": args.prec,
            "cases": rows}, dtype="f32" if args.prec == "fp32" else "f64")
+
+
+def bench_weld(args):
+    """The 1.05M-triangle soup given STL-style (three private vertices per triangle): build with
+    and without welding equal positions, and w at 1M grid points through each mesh."""
+    import torch
+    from paper_2605_01536_amd import gwn, workloads as W
+    soup, grid = W.config4()
+    ex = W.explode(soup, seed=4)
+    P = torch.from_numpy(W.grid_points(grid, np.sort(np.random.default_rng(0).choice(grid.n, 1 << 20,
+                                                                                       replace=False)))).cuda()
+    Vd, Fd = torch.from_numpy(ex.V).cuda(), torch.from_numpy(ex.F).cuda()
+    st = torch.cuda.current_stream()
+    rows = {}
+    for weld in (True, False):
+        gwn.Mesh(Vd, Fd, weld=weld)          # warm-up build
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        m = gwn.Mesh(Vd, Fd, weld=weld)
+        build_ms = (time.perf_counter() - t) * 1e3
+        info = m.info()
+        w = torch.empty(P.shape[0], device="cuda")
+        ev, wall = _timed(lambda: gwn.query_batch(m, P, out=w, stream=st), 2 if weld else 1, 1, st)
+        rows["weld" if weld else "no_weld"] = {"build_ms": build_ms, "nunique": info["nunique"],
+                                               "boundary_edges": info["nboundary"], "query_ms": ev,
+                                               "queries_per_s": P.shape[0] / (ev / 1e3)}
+        rows["w_" + ("weld" if weld else "no_weld")] = w
+        print(f"[bench] weld={weld}: build {build_ms:.1f} ms, {info['nunique']} positions, "
+              f"B={info['nboundary']}, 1M points {ev:.1f} ms", file=sys.stderr, flush=True)
+        del m
+    diff = float((rows.pop("w_weld") - rows.pop("w_no_weld")).abs().max())
+    _emit("GWN queries/sec, STL-style soup with welding", rows["weld"]["queries_per_s"], "queries/s", args,
+          rows["weld"]["query_ms"], {"workload": f"opened-spheres soup exploded to {ex.nv} private vertices "
+                                                 f"({ex.nf} tris), 2^20 grid points", "cases": rows,
+                                     "max_abs_diff_weld_vs_not": diff})
 
 
 def bench_batched(args):

@@ -69,7 +69,16 @@ typedef struct {
     double bbox[6];          /* min xyz, max xyz of the vertices */
     double qlo[3];           /* fixed-point origin: q = rint((x - qlo) * 2^qshift) */
     double build_ms;         /* wall time of the build */
+    int64_t nunique;         /* distinct vertex positions after welding (nv without welding) */
 } gwn_mesh_info;
+
+typedef struct {
+    int32_t weld_positions;  /* nonzero: vertices with equal float coordinates (+0 == -0) become one
+                                index before the boundary is extracted, so a soup whose triangles
+                                carry their own vertex copies (as in STL files) still cancels its
+                                interior edges (Sec. 4.1); w is unchanged, B shrinks */
+    int32_t reserved[3];     /* zero */
+} gwn_build_opts;
 
 /*
  * gwn_build_mesh -- ingest a soup, quantise it, extract and chain the boundary,
@@ -94,6 +103,11 @@ gwn_status gwn_build_mesh(const float* vx, const float* vy, const float* vz, int
                           const int32_t* tri, int64_t nf, void* stream, gwn_mesh* out);
 
 /* Host-side copy of the mesh's sizes and fixed-point parameters. */
+/* gwn_build_mesh with options (opts may be NULL: the defaults of gwn_build_mesh). */
+gwn_status gwn_build_mesh_opts(const float* vx, const float* vy, const float* vz, int64_t vstride, int64_t nv,
+                               const int32_t* tri, int64_t nf, const gwn_build_opts* opts, void* stream,
+                               gwn_mesh* out);
+
 gwn_status gwn_mesh_info_get(gwn_mesh m, gwn_mesh_info* out);
 
 /* Release the handle and its device memory (NULL is a no-op). */

@@ -14,6 +14,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 * ``distance``   -- point-to-soup distance (Ericson 2005), to mask queries
                     on or near the surface where w is undefined (Sec. 3.1).
 * ``boundary``   -- the cancelled directed boundary chain (Sec. 4.1).
+* ``weld``       -- merge vertices with equal coordinates onto one index.
 
 The C source is ``gwn_oracle.c``; ``build()`` compiles it with gcc into
 ``liboracle.so`` next to it (no FP contraction, OpenMP over queries).
@@ -73,6 +74,8 @@ def lib():
         L.oracle_distance.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, ctypes.c_double, _F64]
         L.oracle_distance2.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, ctypes.c_double, ctypes.c_int, _F64]
         L.oracle_gradient.argtypes = [_F32, _i64, _I32, _i64, _F32, _i64, _F64, _F64, _F64]
+        L.oracle_weld.argtypes = [_F32, _i64, _I32, _i64, _I32]
+        L.oracle_weld.restype = _i64
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -167,6 +170,14 @@ def gradient(V, F, Q, axis=(0.0, 0.0, 1.0), with_l1: bool = False):
     l1 = np.zeros(Q.shape[0])
     lib().oracle_gradient(V, V.shape[0], F, F.shape[0], Q, Q.shape[0], a, g, l1)
     return (g, l1) if with_l1 else g
+
+
+def weld(V, F):
+    """(F with equal positions merged onto their smallest index, number of distinct positions)."""
+    V, F = _mesh(V, F)
+    out = np.zeros_like(F)
+    n = lib().oracle_weld(V, V.shape[0], F, F.shape[0], out)
+    return out, int(n)
 
 
 def solid_angle(v0, v1, v2, p) -> float:

@@ -581,6 +581,47 @@ void oracle_direct(const float* V, int64_t nv, const int32_t* F, int64_t nf, con
 }
 
 /* ------------------------------------------------------------------------ */
+/* Welding: equal positions become one index (the smallest)                   */
+/* ------------------------------------------------------------------------ */
+
+static const float* or_weld_V;
+
+static int or_weld_cmp(const void* A, const void* B)
+{
+    const int64_t i = *(const int64_t*)A, j = *(const int64_t*)B;
+    for (int a = 0; a < 3; ++a) {
+        const float x = or_weld_V[3 * i + a], y = or_weld_V[3 * j + a];
+        if (x < y) return -1;
+        if (x > y) return 1;
+    }
+    return (i > j) - (i < j);
+}
+
+/* F_out = F with every index replaced by the smallest index whose vertex has
+ * the same coordinates (float equality, so +0 == -0).  Returns the number of
+ * distinct positions.  Not thread-safe (qsort comparator state). */
+int64_t oracle_weld(const float* V, int64_t nv, const int32_t* F, int64_t nf, int32_t* F_out)
+{
+    int64_t* ord = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nv + 1));
+    int32_t* rep = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nv + 1));
+    for (int64_t i = 0; i < nv; ++i) ord[i] = i;
+    or_weld_V = V;
+    qsort(ord, (size_t)nv, sizeof(int64_t), or_weld_cmp);
+    int64_t distinct = 0, first = 0;
+    for (int64_t j = 0; j < nv; ++j) {
+        const int64_t i = ord[j];
+        int same = j > 0;
+        for (int a = 0; a < 3 && same; ++a) same = V[3 * i + a] == V[3 * ord[j - 1] + a];
+        if (!same) { first = i; ++distinct; }   /* sorted by index within equal positions */
+        rep[i] = (int32_t)first;
+    }
+    for (int64_t t = 0; t < 3 * nf; ++t) F_out[t] = rep[F[t]];
+    free(ord);
+    free(rep);
+    return distinct;
+}
+
+/* ------------------------------------------------------------------------ */
 /* O4: gradient of w (Supp. Sec. 4, Alg. 3)                                    */
 /* ------------------------------------------------------------------------ */
 

@@ -54,6 +54,12 @@ extern "C" {
 
 gwn_status gwn_build_mesh(const float* vx, const float* vy, const float* vz, int64_t vstride, int64_t nv,
                           const int32_t* tri, int64_t nf, void* stream, gwn_mesh* out) {
+    return gwn_build_mesh_opts(vx, vy, vz, vstride, nv, tri, nf, nullptr, stream, out);
+}
+
+gwn_status gwn_build_mesh_opts(const float* vx, const float* vy, const float* vz, int64_t vstride, int64_t nv,
+                               const int32_t* tri, int64_t nf, const gwn_build_opts* opts, void* stream,
+                               gwn_mesh* out) {
     gwn::clear_error();
     if (!out) {
         gwn::set_error("gwn_build_mesh: out is null");
@@ -78,7 +84,8 @@ gwn_status gwn_build_mesh(const float* vx, const float* vy, const float* vz, int
         gwn::set_error("gwn_build_mesh: host allocation failed");
         return GWN_E_OOM;
     }
-    gwn_status s = gwn::build_mesh(vx, vy, vz, vstride, nv, tri, nf, (hipStream_t)stream, m);
+    const bool weld = opts && opts->weld_positions;
+    gwn_status s = gwn::build_mesh(vx, vy, vz, vstride, nv, tri, nf, weld, (hipStream_t)stream, m);
     if (s == GWN_OK && m->depth > gwn::kLdsStack - 1) {
         gwn::set_error("gwn_build_mesh: BVH depth %d exceeds the traversal stack", m->depth);
         s = GWN_E_UNSUPPORTED;
@@ -107,6 +114,7 @@ gwn_status gwn_mesh_info_get(gwn_mesh m, gwn_mesh_info* out) {
     for (int a = 0; a < 6; ++a) out->bbox[a] = m->bbox[a];
     for (int a = 0; a < 3; ++a) out->qlo[a] = m->g.lo[a];
     out->build_ms = m->build_ms;
+    out->nunique = m->nunique;
     return GWN_OK;
 }
 

@@ -359,6 +359,57 @@ __global__ void k_emit_loops(const int* __restrict__ efrom, const int* __restric
     if (r == (int)i) loop_off[lid[i]] = voff[i];
 }
 
+// ---------------------------------------------------------------- welding
+// Vertices with equal float coordinates (+0 and -0 equal) become one index, the
+// smallest: sort by (x, y, z) bit patterns (stable LSD passes), find runs, map.
+
+__device__ __forceinline__ uint32_t weld_bits(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x7fffffffu) == 0u ? 0u : b;
+}
+
+__global__ void k_weld_zkeys(const float* __restrict__ vz, int64_t vs, int64_t nv, uint32_t* __restrict__ kz,
+                             int* __restrict__ idx) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    kz[i] = weld_bits(vz[i * vs]);
+    idx[i] = (int)i;
+}
+
+__global__ void k_weld_xykeys(const float* __restrict__ vx, const float* __restrict__ vy, int64_t vs, int64_t nv,
+                              const int* __restrict__ idx, uint64_t* __restrict__ kxy) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    const int64_t v = idx[j];
+    kxy[j] = ((uint64_t)weld_bits(vx[v * vs]) << 32) | weld_bits(vy[v * vs]);
+}
+
+// run start of each sorted position (0 where the position continues a run)
+__global__ void k_weld_heads(const float* __restrict__ vz, int64_t vs, int64_t nv, const uint64_t* __restrict__ kxy,
+                             const int* __restrict__ idx, int* __restrict__ head) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    bool h = j == 0;
+    if (!h) h = kxy[j] != kxy[j - 1] || weld_bits(vz[(int64_t)idx[j] * vs]) != weld_bits(vz[(int64_t)idx[j - 1] * vs]);
+    head[j] = h ? (int)j : 0;
+}
+
+__global__ void k_weld_map(const int* __restrict__ idx, const int* __restrict__ start, int64_t nv,
+                           int* __restrict__ remap, int* __restrict__ nunique) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    const int s = start[j];
+    remap[idx[j]] = idx[s];   // the stable sort keeps the smallest index first in a run
+    if (s == (int)j) atomicAdd(nunique, 1);
+}
+
+__global__ void k_weld_tris(const int32_t* __restrict__ tri, int64_t n3, const int* __restrict__ remap,
+                            int32_t* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    out[i] = remap[tri[i]];
+}
+
 template <class F>
 hipError_t cub_call(Scratch& S, F&& f) {
     size_t bytes = 0;
@@ -399,7 +450,7 @@ QGrid make_qgrid(const double bbox[6]) {
 }
 
 gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t vs, int64_t nv, const int32_t* tri,
-                      int64_t nf, hipStream_t st, gwn_mesh_s* m) {
+                      int64_t nf, bool weld, hipStream_t st, gwn_mesh_s* m) {
     auto t0 = std::chrono::steady_clock::now();
     Scratch S;
     m->nv = nv;
@@ -434,6 +485,53 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
         set_error("gwn_build_mesh: triangle index outside [0, %lld)", (long long)nv);
         return GWN_E_INVALID;
     }
+    // ---- optional welding of equal positions (the boundary is extracted by index)
+    m->nunique = nv;
+    if (weld && nv > 1 && nf > 0) {
+        uint32_t *kz = nullptr, *kz2 = nullptr;
+        uint64_t *kxy = nullptr, *kxy2 = nullptr;
+        int *idx = nullptr, *idx2 = nullptr, *idx3 = nullptr, *head = nullptr, *start = nullptr, *remap = nullptr,
+            *nuq = nullptr;
+        int32_t* triw = nullptr;
+        GWN_HIP_TRY(S.alloc(&kz, nv));
+        GWN_HIP_TRY(S.alloc(&kz2, nv));
+        GWN_HIP_TRY(S.alloc(&kxy, nv));
+        GWN_HIP_TRY(S.alloc(&kxy2, nv));
+        GWN_HIP_TRY(S.alloc(&idx, nv));
+        GWN_HIP_TRY(S.alloc(&idx2, nv));
+        GWN_HIP_TRY(S.alloc(&idx3, nv));
+        GWN_HIP_TRY(S.alloc(&head, nv));
+        GWN_HIP_TRY(S.alloc(&start, nv));
+        GWN_HIP_TRY(S.alloc(&remap, nv));
+        GWN_HIP_TRY(S.alloc(&nuq, 1));
+        GWN_HIP_TRY(S.alloc(&triw, 3 * nf));
+        GWN_HIP_TRY(hipMemsetAsync(nuq, 0, sizeof(int), st));
+        k_weld_zkeys<<<nblocks(nv), kThreads, 0, st>>>(vz, vs, nv, kz, idx);
+        GWN_HIP_TRY(hipGetLastError());
+        GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
+            return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kz, kz2, idx, idx2, (int)nv, 0, 32, st);
+        }));
+        k_weld_xykeys<<<nblocks(nv), kThreads, 0, st>>>(vx, vy, vs, nv, idx2, kxy);
+        GWN_HIP_TRY(hipGetLastError());
+        GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
+            return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kxy, kxy2, idx2, idx3, (int)nv, 0, 64, st);
+        }));
+        k_weld_heads<<<nblocks(nv), kThreads, 0, st>>>(vz, vs, nv, kxy2, idx3, head);
+        GWN_HIP_TRY(hipGetLastError());
+        GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
+            return hipcub::DeviceScan::InclusiveScan(tmp, bytes, head, start, hipcub::Max(), (int)nv, st);
+        }));
+        k_weld_map<<<nblocks(nv), kThreads, 0, st>>>(idx3, start, nv, remap, nuq);
+        GWN_HIP_TRY(hipGetLastError());
+        k_weld_tris<<<nblocks(3 * nf), kThreads, 0, st>>>(tri, 3 * nf, remap, triw);
+        GWN_HIP_TRY(hipGetLastError());
+        int hn = 0;
+        GWN_HIP_TRY(hipMemcpyAsync(&hn, nuq, sizeof(int), hipMemcpyDeviceToHost, st));
+        GWN_HIP_TRY(hipStreamSynchronize(st));
+        m->nunique = hn;
+        tri = triw;   // the rest of the build sees welded indices
+    }
+
     double bbox[6] = {0, 0, 0, 0, 0, 0};
     if (nv > 0) {
         for (int a = 0; a < 3; ++a) {

@@ -29,7 +29,11 @@ class MeshInfo(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("nf", ctypes.c_int64), ("nboundary", ctypes.c_int64),
                 ("nloops", ctypes.c_int64), ("nnodes", ctypes.c_int64), ("bvh_depth", ctypes.c_int32),
                 ("qshift", ctypes.c_int32), ("bbox", ctypes.c_double * 6), ("qlo", ctypes.c_double * 3),
-                ("build_ms", ctypes.c_double)]
+                ("build_ms", ctypes.c_double), ("nunique", ctypes.c_int64)]
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("weld_positions", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 def load():
@@ -43,6 +47,9 @@ def load():
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     L.gwn_build_mesh.argtypes = [vp, vp, vp, i64, i64, vp, i64, vp, ctypes.POINTER(vp)]
+    L.gwn_build_mesh_opts.argtypes = [vp, vp, vp, i64, i64, vp, i64, ctypes.POINTER(BuildOpts), vp,
+                                      ctypes.POINTER(vp)]
+    L.gwn_build_mesh_opts.restype = ctypes.c_int
     L.gwn_mesh_info_get.argtypes = [vp, ctypes.POINTER(MeshInfo)]
     L.gwn_mesh_destroy.argtypes = [vp]
     L.gwn_query_batch.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp, vp]
@@ -106,9 +113,10 @@ def _wdtype(p):
 
 
 class Mesh:
-    """A soup built on the device: V (nv, 3) float32 and F (nf, 3) int32 CUDA tensors."""
+    """A soup built on the device: V (nv, 3) float32 and F (nf, 3) int32 CUDA tensors.
+    weld=True merges vertices with equal positions before the boundary is extracted."""
 
-    def __init__(self, V, F, stream=None):
+    def __init__(self, V, F, stream=None, weld: bool = False):
         import torch
         L = load()
         if V.dim() != 2 or V.shape[1] != 3 or F.dim() != 2 or F.shape[1] != 3:
@@ -117,15 +125,16 @@ class Mesh:
         F = F.to(device="cuda", dtype=torch.int32).contiguous()
         self._h = ctypes.c_void_p()
         base = _ptr(V)
-        _check(L.gwn_build_mesh(base, base + 4, base + 8, 3, V.shape[0], _ptr(F), F.shape[0],
-                                _stream(stream), ctypes.byref(self._h)))
+        opts = BuildOpts(int(bool(weld)))
+        _check(L.gwn_build_mesh_opts(base, base + 4, base + 8, 3, V.shape[0], _ptr(F), F.shape[0],
+                                     ctypes.byref(opts), _stream(stream), ctypes.byref(self._h)))
 
     def info(self) -> dict:
         inf = MeshInfo()
         _check(load().gwn_mesh_info_get(self._h, ctypes.byref(inf)))
         return {"nv": inf.nv, "nf": inf.nf, "nboundary": inf.nboundary, "nloops": inf.nloops,
                 "nnodes": inf.nnodes, "bvh_depth": inf.bvh_depth, "qshift": inf.qshift,
-                "bbox": list(inf.bbox), "qlo": list(inf.qlo), "build_ms": inf.build_ms}
+                "bbox": list(inf.bbox), "qlo": list(inf.qlo), "build_ms": inf.build_ms, "nunique": inf.nunique}
 
     @property
     def handle(self):
@@ -143,8 +152,8 @@ class Mesh:
             pass
 
 
-def build_mesh(V, F, stream=None) -> Mesh:
-    return Mesh(V, F, stream)
+def build_mesh(V, F, stream=None, weld: bool = False) -> Mesh:
+    return Mesh(V, F, stream, weld=weld)
 
 
 def query_batch(mesh: Mesh, Q, prec="fp32", want_chi=False, out=None, chi_out=None, stream=None):

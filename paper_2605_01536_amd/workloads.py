@@ -310,6 +310,16 @@ def ellipsoid_batch(seed: int = 3, n_mesh: int = 256, tri_range=(1_000, 200_000)
 # the five named configurations
 # ----------------------------------------------------------------------------
 
+def explode(soup: Soup, seed: int | None = None) -> Soup:
+    """The same triangles with three private vertex copies each, as an STL file
+    stores them (no shared indices); with a seed, the triangle order is shuffled."""
+    V = soup.V[soup.F.reshape(-1)].astype(np.float32)
+    F = np.arange(V.shape[0], dtype=np.int32).reshape(-1, 3)
+    if seed is not None:
+        F = F[np.random.default_rng(seed).permutation(F.shape[0])]
+    return Soup(V, np.ascontiguousarray(F))
+
+
 def config1(n_query: int = 10_000):
     """Closed icosphere, 1280 triangles, uniform queries in [-1.5, 1.5]^3 (seed 1)."""
     rng = np.random.default_rng(1)

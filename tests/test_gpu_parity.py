@@ -286,3 +286,24 @@ def test_astronomically_far_queries(gwn, prec):
     assert np.isfinite(w).all() and np.isfinite(g).all()
     assert np.abs(w - O.direct(s.V, s.F, Q)).max() < 1e-6
     assert np.abs(w).max() < 1e-6 and np.abs(g).max() < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_welded_exploded_soup(gwn, prec):
+    # STL-style input: every triangle with its own vertices; welding on the
+    # device recovers the indexed boundary, and w / chi match the oracle
+    s = W.opened_spheres(seed=42, n_surf=5, tris_per_surf=600)
+    e = W.explode(s, seed=3)
+    e.V[::7] = np.where(e.V[::7] == 0, np.float32(-0.0), e.V[::7])      # signed zeros weld too
+    Fw, n = O.weld(e.V, e.F)
+    mw = gwn.Mesh(_dev(e.V), _dev(e.F), weld=True)
+    info = mw.info()
+    assert info["nunique"] == n
+    assert info["nboundary"] == len(O.boundary(Fw)[0]) == len(O.boundary(s.F)[0])
+    m0 = gwn.Mesh(_dev(e.V), _dev(e.F))
+    assert m0.info()["nboundary"] == 3 * s.nf and m0.info()["nunique"] == e.V.shape[0]
+    Q = np.random.default_rng(8).uniform(-1.1, 1.1, size=(2500, 3)).astype(np.float32)
+    w, chi = gwn.query_batch(mw, _dev(Q), prec=prec, want_chi=True)
+    compare(w.cpu().numpy(), chi.cpu().numpy(), e.V, e.F, Q, TOL_FP32 if prec == "fp32" else TOL_FP64, "welded")
+    w0 = gwn.query_batch(m0, _dev(Q), prec=prec).cpu().numpy()
+    assert np.abs(w0 - w.cpu().numpy()).max() < (1e-4 if prec == "fp32" else 1e-9)

@@ -471,3 +471,22 @@ def test_near_axis_gradient_matches_biot_savart_and_other_axes():
     B = (np.cross(ra, rb) * ((la + lb) / (la * lb * (la * lb + (ra * rb).sum(2))))[..., None]).sum(1) / (4 * np.pi)
     assert np.abs(B - g).max() < 1e-8
     assert np.abs(O.gradient(V, F, Q, axis=(0.3, 0.4, -0.5)) - g).max() < 1e-8
+
+
+def test_weld_restores_the_indexed_boundary():
+    # an exploded soup (private vertex copies per triangle) has every edge on the
+    # boundary; welding equal positions gives back the indexed mesh's chain
+    s = W.opened_spheres(seed=40, n_surf=3, tris_per_surf=300)
+    e = W.explode(s, seed=1)
+    assert len(O.boundary(e.F)[0]) == 3 * s.nf
+    Fw, n = O.weld(e.V, e.F)
+    assert n == len(np.unique(s.V[np.unique(s.F)], axis=0))
+    key = lambda V, fr, to: sorted(map(tuple, np.concatenate([V[fr], V[to]], axis=1).tolist()))
+    assert key(e.V, *O.boundary(Fw)) == key(s.V, *O.boundary(s.F))
+    Q = np.random.default_rng(2).uniform(-1.2, 1.2, size=(300, 3)).astype(np.float32)
+    w0, w1 = O.antipodal(s.V, s.F, Q), O.antipodal(e.V, Fw, Q)
+    assert np.abs(w0 - w1).max() < 1e-12
+    # +0 and -0 are one position
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [-0.0, 0, -0.0]], np.float32)
+    Fz, n = O.weld(V, np.array([[0, 1, 2], [3, 2, 1]], np.int32))
+    assert n == 3 and Fz[1].tolist() == [0, 2, 1]
