@@ -59,6 +59,13 @@ gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* s
 // GWN_MAX_LAUNCH_QUERIES (a positive multiple of 256) lowers it, for tests.
 int64_t max_launch_queries();
 
+// Morton order of the points' quantised x, y for the crossing traversal (perm is
+// stream-ordered device memory the caller frees with hipFreeAsync).
+// GWN_ORDER_QUERIES=0/1 overrides the size heuristic.
+bool want_xy_order(const gwn_mesh_s* m, int64_t n);
+gwn_status xy_order(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride, int64_t n,
+                    int** perm, hipStream_t stream);
+
 gwn_status query_crossings(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                            int64_t nq, int32_t* up, int32_t* down, hipStream_t stream);
 

@@ -14,26 +14,105 @@ namespace gwn {
 namespace {
 
 // crossing counts of arbitrary points (per-lane LDS traversal stack)
+// perm (nullable): lane j handles point perm[j] (a traversal order)
 __global__ __launch_bounds__(kChiBlock) void k_chi_batch(MeshView mv, const float* __restrict__ qx,
                                                          const float* __restrict__ qy, const float* __restrict__ qz,
                                                          long long qs, long long nq, const int* __restrict__ ndev,
-                                                         int* __restrict__ chi) {
+                                                         const int* __restrict__ perm, int* __restrict__ chi) {
     __shared__ int stk[kLdsStack * kChiBlock];
-    const long long i = blockIdx.x * (long long)kChiBlock + threadIdx.x;
+    const long long j = blockIdx.x * (long long)kChiBlock + threadIdx.x;
     if (ndev) nq = min(nq, (long long)*ndev);   // count known only on the device
-    if (i >= nq) return;
+    if (j >= nq) return;
+    const long long i = perm ? (long long)perm[j] : j;
     const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
     chi[i] = q.inbox ? chi_up(mv, q, stk + threadIdx.x) : 0;
+}
+
+constexpr int kGridWaves = 4;  // waves per block in the wave-per-task kernels
+
+// Crossing counts of Morton-ordered points, one wave-uniform traversal per wave:
+// the wave descends into a child when the line of ANY of its lanes meets the
+// child's box (ballot), nodes and triangles arrive by scalar loads, and each lane
+// applies its own exact leaf test.  Neighbouring lines share almost their whole
+// path, so the wave walks about one path instead of 64 divergent ones.  UP: the
+// +z ray only (z-pruned); otherwise both directions of the whole line.
+template <bool UP>
+__global__ __launch_bounds__(64 * kGridWaves) void k_chi_wave(MeshView mv, const float* __restrict__ qx,
+                                                             const float* __restrict__ qy,
+                                                             const float* __restrict__ qz, long long qs, long long nq,
+                                                             const int* __restrict__ perm, int* __restrict__ up,
+                                                             int* __restrict__ down) {
+    __shared__ int wstack[kGridWaves][kLdsStack];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const long long j = ((long long)blockIdx.x * kGridWaves + wave) * 64 + (threadIdx.x & 63);
+    if ((long long)(blockIdx.x * kGridWaves + wave) * 64 >= nq) return;   // whole wave past the end
+    const bool valid = j < nq;
+    const long long i = perm[valid ? j : nq - 1];
+    const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
+    const bool act = valid && q.inbox;
+    int u = 0, d = 0;
+    auto leaf = [&](int t) {
+        const TriQ tr = mv.tris[t];
+        const int s = tri_xy_sign(tr, q.x, q.y);
+        if (s == 0) return;
+        if (plane_above(plane_of(tr, q.x, q.y), q.z)) u += s;
+        else d -= s;
+    };
+    int node = mv.root;
+    if (__builtin_amdgcn_ballot_w64(act) != 0ull && node != kNoRoot) {
+        if (node < 0) {
+            if (act) leaf(~node);
+        } else {
+            int* stk = wstack[wave];
+            int sp = 0;
+            while (true) {
+                const Node nd = mv.nodes[node];
+                const bool ml = act && box_has_xy(nd.lxy.x, nd.lxy.y, nd.lxy.z, nd.lxy.w, q.x, q.y) &&
+                                (!UP || q.z <= nd.z.y);
+                const bool mr = act && box_has_xy(nd.rxy.x, nd.rxy.y, nd.rxy.z, nd.rxy.w, q.x, q.y) &&
+                                (!UP || q.z <= nd.z.w);
+                bool hl = __builtin_amdgcn_ballot_w64(ml) != 0ull;
+                bool hr = __builtin_amdgcn_ballot_w64(mr) != 0ull;
+                const int L = nd.link.x, R = nd.link.y;
+                if (hl && L < 0) {
+                    if (ml) leaf(~L);
+                    hl = false;
+                }
+                if (hr && R < 0) {
+                    if (mr) leaf(~R);
+                    hr = false;
+                }
+                if (hl && hr) {
+                    stk[sp++] = R;   // every lane stores the same value
+                    node = L;
+                } else if (hl) {
+                    node = L;
+                } else if (hr) {
+                    node = R;
+                } else {
+                    if (sp == 0) break;
+                    --sp;
+                    node = stk[sp];
+                }
+                node = __builtin_amdgcn_readfirstlane(node);
+            }
+        }
+    }
+    if (valid) {
+        if (up) up[i] = u;
+        if (down) down[i] = d;
+    }
 }
 
 // both crossing counts of arbitrary points (the whole vertical line)
 __global__ __launch_bounds__(kChiBlock) void k_chi_line(MeshView mv, const float* __restrict__ qx,
                                                         const float* __restrict__ qy, const float* __restrict__ qz,
-                                                        long long qs, long long nq, int* __restrict__ up,
-                                                        int* __restrict__ down) {
+                                                        long long qs, long long nq, const int* __restrict__ perm,
+                                                        int* __restrict__ up, int* __restrict__ down) {
     __shared__ int stk[kLdsStack * kChiBlock];
-    const long long i = blockIdx.x * (long long)kChiBlock + threadIdx.x;
-    if (i >= nq) return;
+    const long long j = blockIdx.x * (long long)kChiBlock + threadIdx.x;
+    if (j >= nq) return;
+    const long long i = perm ? (long long)perm[j] : j;
     const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
     int u = 0, d = 0;
     if (q.inbox) chi_line(mv, q, stk + threadIdx.x, u, d);
@@ -77,7 +156,6 @@ struct GridArgs {
     long long wave0;     // first wave of this launch (large grids take several)
 };
 
-constexpr int kGridWaves = 4;  // waves per block; one wave per (column, z-chunk)
 
 // grid coordinate origin + (i + 0.5) * spacing in FP64 without contraction
 __device__ __forceinline__ float grid_coord(double o, double s, long long i) {
@@ -200,9 +278,20 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
     for (int64_t o = 0; o < nq && e == hipSuccess; o += chunk) {
         const int64_t n = std::min<int64_t>(chunk, nq - o);
         const float *x = qx + o * qs, *y = qy + o * qs, *z = qz + o * qs;
-        k_chi_batch<<<(unsigned)((n + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, x, y, z, qs, n, nullptr,
-                                                                                       chi + o);
+        int* perm = nullptr;
+        if (want_xy_order(m, n) && xy_order(m, x, y, z, qs, n, &perm, st) != GWN_OK) {
+            if (!chi_out) (void)hipFreeAsync(chi, st);
+            return GWN_E_HIP;   // xy_order has set the message
+        }
+        if (perm) {
+            k_chi_wave<true><<<(unsigned)((n + 64 * kGridWaves - 1) / (64 * kGridWaves)), 64 * kGridWaves, 0, st>>>(
+                mv, x, y, z, qs, n, perm, chi + o, nullptr);
+        } else {
+            k_chi_batch<<<(unsigned)((n + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, x, y, z, qs, n,
+                                                                                           nullptr, nullptr, chi + o);
+        }
         e = hipGetLastError();
+        if (perm) (void)hipFreeAsync(perm, st);
         if (e == hipSuccess) {
             k_bdry_batch<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(mv, x, y, z, qs, n, nullptr, chi + o, w + o);
             e = hipGetLastError();
@@ -257,9 +346,22 @@ gwn_status query_crossings(const gwn_mesh_s* m, const float* qx, const float* qy
     const int64_t chunk = max_launch_queries();
     for (int64_t o = 0; o < nq; o += chunk) {
         const int64_t n = std::min<int64_t>(chunk, nq - o);
-        k_chi_line<<<(unsigned)((n + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(
-            mv, qx + o * qs, qy + o * qs, qz + o * qs, qs, n, up ? up + o : nullptr, down ? down + o : nullptr);
-        GWN_HIP_TRY(hipGetLastError());
+        const float *x = qx + o * qs, *y = qy + o * qs, *z = qz + o * qs;
+        int* perm = nullptr;
+        if (want_xy_order(m, n)) {
+            const gwn_status so = xy_order(m, x, y, z, qs, n, &perm, st);
+            if (so != GWN_OK) return so;
+        }
+        if (perm) {
+            k_chi_wave<false><<<(unsigned)((n + 64 * kGridWaves - 1) / (64 * kGridWaves)), 64 * kGridWaves, 0, st>>>(
+                mv, x, y, z, qs, n, perm, up ? up + o : nullptr, down ? down + o : nullptr);
+        } else {
+            k_chi_line<<<(unsigned)((n + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(
+                mv, x, y, z, qs, n, nullptr, up ? up + o : nullptr, down ? down + o : nullptr);
+        }
+        const hipError_t e = hipGetLastError();
+        if (perm) (void)hipFreeAsync(perm, st);
+        GWN_HIP_TRY(e);
     }
     return GWN_OK;
 }
@@ -289,7 +391,7 @@ gwn_status query_batch_devcount(const gwn_mesh_s* m, const float* qx, const floa
     }
     const MeshView mv = m->view();
     k_chi_batch<<<(unsigned)((nmax + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, qx, qy, qz, qs, nmax, ndev,
-                                                                                      chi);
+                                                                                      nullptr, chi);
     GWN_HIP_TRY(hipGetLastError());
     k_bdry_batch<float><<<(unsigned)((nmax + 255) / 256), 256, 0, st>>>(mv, qx, qy, qz, qs, nmax, ndev, chi, w);
     GWN_HIP_TRY(hipGetLastError());

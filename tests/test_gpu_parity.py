@@ -307,3 +307,38 @@ def test_welded_exploded_soup(gwn, prec):
     compare(w.cpu().numpy(), chi.cpu().numpy(), e.V, e.F, Q, TOL_FP32 if prec == "fp32" else TOL_FP64, "welded")
     w0 = gwn.query_batch(m0, _dev(Q), prec=prec).cpu().numpy()
     assert np.abs(w0 - w.cpu().numpy()).max() < (1e-4 if prec == "fp32" else 1e-9)
+
+
+def test_traversal_order_is_invisible(gwn, monkeypatch):
+    # Morton-ordered traversal of the crossing kernels changes which lane handles
+    # which point, never a result
+    s, g = W.config4()
+    m = gwn.Mesh(_dev(s.V), _dev(s.F))
+    P = _dev(W.grid_points(g, np.random.default_rng(5).choice(g.n, 70001, replace=False)))
+    out = {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("GWN_ORDER_QUERIES", flag)
+        w, c = gwn.query_batch(m, P, want_chi=True)
+        up, dn = gwn.query_crossings(m, P)
+        out[flag] = (w, c, up, dn)
+    for a, b in zip(out["0"], out["1"]):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_wave_traversal_small_meshes(gwn, monkeypatch, seed):
+    # the ordered, wave-uniform crossing traversal forced on small soups (a single
+    # triangle as the whole tree, rays through vertices) against the oracle
+    monkeypatch.setenv("GWN_ORDER_QUERIES", "1")
+    rng = np.random.default_rng(700 + seed)
+    nt = [1, 2, 37, 500][seed]
+    V = (np.round(rng.uniform(-1, 1, size=(3 * nt, 3)) * 8) / 8).astype(np.float32)
+    F = rng.integers(0, V.shape[0], size=(nt, 3)).astype(np.int32)
+    Q = (np.round(rng.uniform(-1.2, 1.2, size=(4097, 3)) * 8) / 8).astype(np.float32)
+    Q[-3:] = [[9, 9, 0], [-9, 0, 1], [0, 0, 9]]
+    m = gwn.Mesh(_dev(V), _dev(F))
+    w, chi = gwn.query_batch(m, _dev(Q), want_chi=True)
+    up, dn = gwn.query_crossings(m, _dev(Q))
+    ou, od = O.chi(V, F, Q)
+    assert np.array_equal(up.cpu().numpy(), ou) and np.array_equal(dn.cpu().numpy(), od)
+    compare(w.cpu().numpy(), chi.cpu().numpy(), V, F, Q, TOL_FP32, f"wave{seed}")
