@@ -70,6 +70,10 @@ typedef struct {
     double qlo[3];           /* fixed-point origin: q = rint((x - qlo) * 2^qshift) */
     double build_ms;         /* wall time of the build */
     int64_t nunique;         /* distinct vertex positions after welding (nv without welding) */
+    int32_t axis;            /* ray axis the mesh was built for: 0 = z, 1 = x, 2 = y */
+    int32_t pad;
+    double proj_area[3];     /* twice the total |projected area| on the planes normal to x, y, z
+                                (filled when the axis was chosen automatically, else 0) */
 } gwn_mesh_info;
 
 typedef struct {
@@ -77,7 +81,14 @@ typedef struct {
                                 index before the boundary is extracted, so a soup whose triangles
                                 carry their own vertex copies (as in STL files) still cancels its
                                 interior edges (Sec. 4.1); w is unchanged, B shrinks */
-    int32_t reserved[3];     /* zero */
+    int32_t axis;            /* direction of the crossing ray x0 (Sec. 3.2; any direction gives the
+                                same w, Prop. 4.2): 0 = +z (default), 1 = +x, 2 = +y, -1 = the axis
+                                with the least total projected triangle area (fewest expected
+                                crossings).  The mesh is stored in the cyclically permuted frame
+                                whose third axis is the ray; every query call accepts and returns
+                                world coordinates, chi counts crossings along the chosen axis, and
+                                grids keep the world layout (z fastest). */
+    int32_t reserved[2];     /* zero */
 } gwn_build_opts;
 
 /*

@@ -79,13 +79,19 @@ gwn_status gwn_build_mesh_opts(const float* vx, const float* vy, const float* vz
         gwn::set_error("gwn_build_mesh: triangles given without vertices");
         return GWN_E_INVALID;
     }
+    const bool weld = opts && opts->weld_positions;
+    // public codes: 0 = z, 1 = x, 2 = y, -1 = choose; the same as the internal ones
+    const int axis = opts ? opts->axis : 0;
+    if (axis < -1 || axis > 2) {
+        gwn::set_error("gwn_build_mesh_opts: axis must be -1, 0 (z), 1 (x) or 2 (y), got %d", axis);
+        return GWN_E_INVALID;
+    }
     gwn_mesh_s* m = new (std::nothrow) gwn_mesh_s();
     if (!m) {
         gwn::set_error("gwn_build_mesh: host allocation failed");
         return GWN_E_OOM;
     }
-    const bool weld = opts && opts->weld_positions;
-    gwn_status s = gwn::build_mesh(vx, vy, vz, vstride, nv, tri, nf, weld, (hipStream_t)stream, m);
+    gwn_status s = gwn::build_mesh(vx, vy, vz, vstride, nv, tri, nf, weld, axis, (hipStream_t)stream, m);
     if (s == GWN_OK && m->depth > gwn::kLdsStack - 1) {
         gwn::set_error("gwn_build_mesh: BVH depth %d exceeds the traversal stack", m->depth);
         s = GWN_E_UNSUPPORTED;
@@ -111,10 +117,17 @@ gwn_status gwn_mesh_info_get(gwn_mesh m, gwn_mesh_info* out) {
     out->nnodes = m->nnodes;
     out->bvh_depth = m->depth;
     out->qshift = m->g.k;
-    for (int a = 0; a < 6; ++a) out->bbox[a] = m->bbox[a];
-    for (int a = 0; a < 3; ++a) out->qlo[a] = m->g.lo[a];
+    // the mesh keeps its data in its axis frame: frame component c is world (c + axis) % 3
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + m->axis) % 3;
+        out->bbox[a] = m->bbox[c];
+        out->bbox[3 + a] = m->bbox[3 + c];
+        out->qlo[a] = m->g.lo[c];
+    }
     out->build_ms = m->build_ms;
     out->nunique = m->nunique;
+    out->axis = m->axis;
+    for (int a = 0; a < 3; ++a) out->proj_area[a] = m->proj_area[a];
     return GWN_OK;
 }
 

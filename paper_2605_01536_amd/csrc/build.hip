@@ -359,6 +359,41 @@ __global__ void k_emit_loops(const int* __restrict__ efrom, const int* __restric
     if (r == (int)i) loop_off[lid[i]] = voff[i];
 }
 
+// ---------------------------------------------------------------- ray axis
+// Twice the triangles' total |projected area| on the planes normal to x, y, z:
+// the expected number of crossings of a random line along that axis scales
+// with it.  Per-block partial sums, written by one lane each.
+__global__ __launch_bounds__(kThreads) void k_proj_area(const float* __restrict__ vx, const float* __restrict__ vy,
+                                                         const float* __restrict__ vz, int64_t vs,
+                                                         const int32_t* __restrict__ tri, int64_t nf,
+                                                         double* __restrict__ part) {
+    __shared__ double sm[3][kThreads];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x; t < nf; t += (int64_t)gridDim.x * kThreads) {
+        double p[3][3];
+        for (int c = 0; c < 3; ++c) {
+            const int64_t v = tri[3 * t + c];
+            p[c][0] = vx[v * vs];
+            p[c][1] = vy[v * vs];
+            p[c][2] = vz[v * vs];
+        }
+        const double ux = p[1][0] - p[0][0], uy = p[1][1] - p[0][1], uz = p[1][2] - p[0][2];
+        const double wx = p[2][0] - p[0][0], wy = p[2][1] - p[0][1], wz = p[2][2] - p[0][2];
+        acc[0] += fabs(uy * wz - uz * wy);
+        acc[1] += fabs(uz * wx - ux * wz);
+        acc[2] += fabs(ux * wy - uy * wx);
+    }
+    for (int a = 0; a < 3; ++a) sm[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < 3; ++a) sm[a][threadIdx.x] += sm[a][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) part[blockIdx.x * 3 + a] = sm[a][0];
+}
+
 // ---------------------------------------------------------------- welding
 // Vertices with equal float coordinates (+0 and -0 equal) become one index, the
 // smallest: sort by (x, y, z) bit patterns (stable LSD passes), find runs, map.
@@ -450,7 +485,7 @@ QGrid make_qgrid(const double bbox[6]) {
 }
 
 gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t vs, int64_t nv, const int32_t* tri,
-                      int64_t nf, bool weld, hipStream_t st, gwn_mesh_s* m) {
+                      int64_t nf, bool weld, int axis, hipStream_t st, gwn_mesh_s* m) {
     auto t0 = std::chrono::steady_clock::now();
     Scratch S;
     m->nv = nv;
@@ -485,6 +520,32 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
         set_error("gwn_build_mesh: triangle index outside [0, %lld)", (long long)nv);
         return GWN_E_INVALID;
     }
+    // ---- ray axis: least total projected area (fewest expected crossings) when asked
+    if (axis < 0) {
+        axis = 0;
+        if (nf > 0) {
+            const int pb = 256;
+            double* pa = nullptr;
+            GWN_HIP_TRY(S.alloc(&pa, 3 * pb));
+            k_proj_area<<<pb, kThreads, 0, st>>>(vx, vy, vz, vs, tri, nf, pa);
+            GWN_HIP_TRY(hipGetLastError());
+            std::vector<double> h(3 * pb);
+            GWN_HIP_TRY(hipMemcpyAsync(h.data(), pa, sizeof(double) * 3 * pb, hipMemcpyDeviceToHost, st));
+            GWN_HIP_TRY(hipStreamSynchronize(st));
+            double A[3] = {0, 0, 0};
+            for (int b = 0; b < pb; ++b)
+                for (int a = 0; a < 3; ++a) A[a] += h[3 * b + a];
+            // world x, y, z -> axis codes 1, 2, 0; z wins ties
+            if (A[0] < A[2] && A[0] <= A[1]) axis = 1;
+            else if (A[1] < A[2] && A[1] < A[0]) axis = 2;
+            m->proj_area[0] = A[0];
+            m->proj_area[1] = A[1];
+            m->proj_area[2] = A[2];
+        }
+    }
+    m->axis = axis;
+    axis_ptrs(axis, vx, vy, vz);   // from here on every coordinate is in the mesh frame
+
     // ---- optional welding of equal positions (the boundary is extracted by index)
     m->nunique = nv;
     if (weld && nv > 1 && nf > 0) {
@@ -542,6 +603,13 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
             }
             bbox[a] = (double)mn;
             bbox[3 + a] = (double)mx;
+        }
+        // the statistics ran on the world axes: frame component c is world (c + axis) % 3
+        double bw[6];
+        std::memcpy(bw, bbox, sizeof(bw));
+        for (int c = 0; c < 3; ++c) {
+            bbox[c] = bw[(c + axis) % 3];
+            bbox[3 + c] = bw[3 + (c + axis) % 3];
         }
     }
     std::memcpy(m->bbox, bbox, sizeof(bbox));

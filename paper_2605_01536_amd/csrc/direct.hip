@@ -116,6 +116,7 @@ gwn_status launch_direct(const gwn_mesh_s* m, const float* qx, const float* qy, 
 
 gwn_status query_direct(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t nq,
                         int prec, void* w, hipStream_t st) {
+    axis_ptrs(m->axis, qx, qy, qz);
     const int64_t chunk = max_launch_queries();
     for (int64_t o = 0; o < nq; o += chunk) {
         const int64_t n = std::min<int64_t>(chunk, nq - o);

@@ -93,7 +93,7 @@ __device__ void grad_loops(const MeshView& mv, T pxs, T pys, T pzs, T f, double*
 template <class T>
 __global__ __launch_bounds__(256) void k_grad_batch(MeshView mv, const float* __restrict__ qx,
                                                     const float* __restrict__ qy, const float* __restrict__ qz,
-                                                    long long qs, long long nq, T* __restrict__ g) {
+                                                    long long qs, long long nq, int axis, T* __restrict__ g) {
     const long long i = blockIdx.x * 256ll + threadIdx.x;
     if (blockIdx.x * 256ll >= nq) return;
     const long long ii = i < nq ? i : nq - 1;
@@ -106,9 +106,8 @@ __global__ __launch_bounds__(256) void k_grad_batch(MeshView mv, const float* __
     if (i < nq) {
         // sum of 2 atan2 terms over 4 pi, and the chain rule through p * 2^(k-e)
         const double f = kInv2Pi * (double)fs.scf;
-        g[3 * i] = (T)(G[0] * f);
-        g[3 * i + 1] = (T)(G[1] * f);
-        g[3 * i + 2] = (T)(G[2] * f);
+        // frame component c is world component (c + axis) % 3
+        for (int c = 0; c < 3; ++c) g[3 * i + (c + axis) % 3] = (T)(G[c] * f);
     }
 }
 
@@ -117,13 +116,14 @@ __global__ __launch_bounds__(256) void k_grad_batch(MeshView mv, const float* __
 gwn_status query_gradient(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
                           int64_t nq, int prec, void* g, hipStream_t st) {
     const MeshView mv = m->view();
+    axis_ptrs(m->axis, qx, qy, qz);
     const int64_t chunk = max_launch_queries();
     for (int64_t o = 0; o < nq; o += chunk) {
         const int64_t n = std::min<int64_t>(chunk, nq - o);
         const unsigned blocks = (unsigned)((n + 255) / 256);
         const float *x = qx + o * qs, *y = qy + o * qs, *z = qz + o * qs;
-        if (prec == GWN_PREC_FP64) k_grad_batch<double><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, (double*)g + 3 * o);
-        else k_grad_batch<float><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, (float*)g + 3 * o);
+        if (prec == GWN_PREC_FP64) k_grad_batch<double><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, m->axis, (double*)g + 3 * o);
+        else k_grad_batch<float><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, m->axis, (float*)g + 3 * o);
         GWN_HIP_TRY(hipGetLastError());
     }
     return GWN_OK;

@@ -52,11 +52,28 @@ struct MeshView {
     int nloops;
     int nf;
     int root;              // >= 0 internal node, < 0 leaf ~t, INT_MIN when nf == 0
-    int pad;
+    int axis;              // ray axis of the mesh frame: 0 = z, 1 = x, 2 = y (see axis_ptrs)
     QGrid g;
 };
 
 constexpr int kNoRoot = (int)0x80000000;
+
+// A mesh built along axis a works in the frame (X, Y, Z) = (x, y, z), (y, z, x)
+// or (z, x, y) for a = 0 (z), 1 (x), 2 (y): a cyclic permutation, i.e. a
+// rotation, so orientations and w are unchanged and the ray +Z is the chosen
+// world axis.  Frame component c is world component (c + a) % 3.
+__host__ __device__ inline void axis_ptrs(int a, const float*& x, const float*& y, const float*& z) {
+    const float* t = x;
+    if (a == 1) {
+        x = y;
+        y = z;
+        z = t;
+    } else if (a == 2) {
+        x = z;
+        z = y;
+        y = t;
+    }
+}
 
 // Fixed-point coordinate of one input value, evaluated in FP64 exactly as the
 // rule states: rint((x - lo) * 2^k).  The multiply by a power of two is exact,

@@ -12,6 +12,8 @@ struct gwn_mesh_s {
     int device = 0;
     int64_t nv = 0, nf = 0, nb = 0, nloops = 0, nnodes = 0;
     int64_t nunique = 0;           // distinct positions after welding (nv without it)
+    int axis = 0;                  // ray axis (0 = z, 1 = x, 2 = y); all device data is in its frame
+    double proj_area[3] = {0, 0, 0};   // 2 x projected area on the planes normal to x, y, z (when chosen)
     int depth = 0;
     double build_ms = 0.0;
     double bbox[6] = {0, 0, 0, 0, 0, 0};
@@ -33,7 +35,7 @@ struct gwn_mesh_s {
         v.nloops = (int)nloops;
         v.nf = (int)nf;
         v.root = root;
-        v.pad = 0;
+        v.axis = axis;
         v.g = g;
         return v;
     }
@@ -45,8 +47,9 @@ namespace gwn {
 void set_error(const char* fmt, ...);
 void clear_error();
 
+// axis: 0 = z, 1 = x, 2 = y, -1 = the one with the least projected triangle area
 gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t vstride, int64_t nv,
-                      const int32_t* tri, int64_t nf, bool weld, hipStream_t stream, gwn_mesh_s* m);
+                      const int32_t* tri, int64_t nf, bool weld, int axis, hipStream_t stream, gwn_mesh_s* m);
 
 gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                        int64_t nq, int prec, void* w_out, int32_t* chi_out, hipStream_t stream);

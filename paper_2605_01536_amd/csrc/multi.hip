@@ -50,7 +50,9 @@ __global__ __launch_bounds__(kMultiChiBlock) void k_chi_multi(const MeshView* __
         else hi = mid - 1;
     }
     const MeshView mv = table[lo];
-    const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
+    const float *x = qx, *y = qy, *z = qz;
+    axis_ptrs(mv.axis, x, y, z);   // the mesh's frame
+    const QPoint q = quantize_point(x[i * qs], y[i * qs], z[i * qs], mv.g);
     chi[i] = q.inbox ? chi_up(mv, q, stk + threadIdx.x) : 0;
 }
 
@@ -70,10 +72,12 @@ __global__ __launch_bounds__(256) void k_bdry_persistent(const MeshView* __restr
         if (it >= nitems) break;
         const Item I = items[it];
         const MeshView mv = table[I.mesh];
+        const float *x = qx, *y = qy, *z = qz;
+        axis_ptrs(mv.axis, x, y, z);   // the mesh's frame
         for (int sub = 0; sub < I.nq; sub += 64) {
             const int k = sub + lane;
             const long long i = I.q0 + min(k, I.nq - 1);
-            const float px = qx[i * qs], py = qy[i * qs], pz = qz[i * qs];
+            const float px = x[i * qs], py = y[i * qs], pz = z[i * qs];
             const QPoint q = quantize_point(px, py, pz, mv.g);
             double S = 0.0;
             if (q.inbox) {

@@ -154,6 +154,7 @@ struct GridArgs {
     long long nchunks;   // z-chunks per column
     long long nwaves;    // columns * nchunks
     long long wave0;     // first wave of this launch (large grids take several)
+    long long st[3];     // output strides of the frame's x, y, z indices (world z fastest)
 };
 
 
@@ -255,13 +256,13 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs 
         boundary_loops<T, ZB, true>(mv, 0, 0, (T)px * fs.scf, (T)py * fs.scf, pzs, S, fs.f);
     }
 
-    const long long base = col * ga.nz;
+    const long long base = ci * ga.st[0] + cj * ga.st[1];
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {
         const long long k = k0 + r;
         if (k < ga.nz) {
-            w[base + k] = (T)((double)chi[r] + S[r] * kInv2Pi);
-            if (chi_out) chi_out[base + k] = chi[r];
+            w[base + k * ga.st[2]] = (T)((double)chi[r] + S[r] * kInv2Pi);
+            if (chi_out) chi_out[base + k * ga.st[2]] = chi[r];
         }
     }
 }
@@ -342,6 +343,7 @@ gwn_status launch_grid(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out,
 
 gwn_status query_crossings(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
                            int64_t nq, int32_t* up, int32_t* down, hipStream_t st) {
+    axis_ptrs(m->axis, qx, qy, qz);
     const MeshView mv = m->view();
     const int64_t chunk = max_launch_queries();
     for (int64_t o = 0; o < nq; o += chunk) {
@@ -378,6 +380,7 @@ int64_t max_launch_queries() {
 gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t nq,
                        int prec, void* w, int32_t* chi_out, hipStream_t st) {
     if (nq == 0) return GWN_OK;
+    axis_ptrs(m->axis, qx, qy, qz);
     if (prec == GWN_PREC_FP64) return launch_batch<double>(m, qx, qy, qz, qs, nq, (double*)w, chi_out, st);
     return launch_batch<float>(m, qx, qy, qz, qs, nq, (float*)w, chi_out, st);
 }
@@ -385,6 +388,7 @@ gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, co
 gwn_status query_batch_devcount(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
                                 int64_t nmax, const int* ndev, int* chi, float* w, hipStream_t st) {
     if (nmax == 0) return GWN_OK;
+    axis_ptrs(m->axis, qx, qy, qz);
     if (nmax > max_launch_queries()) {
         set_error("surrogate fallback: more than %lld points in one call", (long long)max_launch_queries());
         return GWN_E_INVALID;
@@ -400,14 +404,21 @@ gwn_status query_batch_devcount(const gwn_mesh_s* m, const float* qx, const floa
 
 gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims, int prec,
                       void* w, int32_t* chi_out, hipStream_t st) {
+    // the grid in the mesh frame: frame axis c is world axis (c + axis) % 3; the
+    // output keeps the world layout (x slowest, z fastest)
     GridArgs ga;
-    for (int a = 0; a < 3; ++a) {
-        ga.o[a] = origin[a];
-        ga.s[a] = spacing[a];
+    const long long wst[3] = {dims[1] * dims[2], dims[2], 1};
+    long long n[3];
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + m->axis) % 3;
+        ga.o[c] = origin[a];
+        ga.s[c] = spacing[a];
+        n[c] = dims[a];
+        ga.st[c] = wst[a];
     }
-    ga.nx = dims[0];
-    ga.ny = dims[1];
-    ga.nz = dims[2];
+    ga.nx = n[0];
+    ga.ny = n[1];
+    ga.nz = n[2];
     ga.nchunks = ga.nwaves = ga.wave0 = 0;
     if (ga.nx == 0 || ga.ny == 0 || ga.nz == 0) return GWN_OK;
     if (prec == GWN_PREC_FP64) return launch_grid<double>(m, ga, (double*)w, chi_out, st);

@@ -29,11 +29,15 @@ class MeshInfo(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("nf", ctypes.c_int64), ("nboundary", ctypes.c_int64),
                 ("nloops", ctypes.c_int64), ("nnodes", ctypes.c_int64), ("bvh_depth", ctypes.c_int32),
                 ("qshift", ctypes.c_int32), ("bbox", ctypes.c_double * 6), ("qlo", ctypes.c_double * 3),
-                ("build_ms", ctypes.c_double), ("nunique", ctypes.c_int64)]
+                ("build_ms", ctypes.c_double), ("nunique", ctypes.c_int64), ("axis", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("proj_area", ctypes.c_double * 3)]
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("weld_positions", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+    _fields_ = [("weld_positions", ctypes.c_int32), ("axis", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
+_AXIS = {"z": 0, "x": 1, "y": 2, "auto": -1}
 
 
 def load():
@@ -114,9 +118,10 @@ def _wdtype(p):
 
 class Mesh:
     """A soup built on the device: V (nv, 3) float32 and F (nf, 3) int32 CUDA tensors.
-    weld=True merges vertices with equal positions before the boundary is extracted."""
+    weld=True merges vertices with equal positions before the boundary is extracted;
+    axis ("z", "x", "y" or "auto") is the direction of the crossing ray."""
 
-    def __init__(self, V, F, stream=None, weld: bool = False):
+    def __init__(self, V, F, stream=None, weld: bool = False, axis: str = "z"):
         import torch
         L = load()
         if V.dim() != 2 or V.shape[1] != 3 or F.dim() != 2 or F.shape[1] != 3:
@@ -125,7 +130,7 @@ class Mesh:
         F = F.to(device="cuda", dtype=torch.int32).contiguous()
         self._h = ctypes.c_void_p()
         base = _ptr(V)
-        opts = BuildOpts(int(bool(weld)))
+        opts = BuildOpts(int(bool(weld)), _AXIS[axis])
         _check(L.gwn_build_mesh_opts(base, base + 4, base + 8, 3, V.shape[0], _ptr(F), F.shape[0],
                                      ctypes.byref(opts), _stream(stream), ctypes.byref(self._h)))
 
@@ -134,7 +139,8 @@ class Mesh:
         _check(load().gwn_mesh_info_get(self._h, ctypes.byref(inf)))
         return {"nv": inf.nv, "nf": inf.nf, "nboundary": inf.nboundary, "nloops": inf.nloops,
                 "nnodes": inf.nnodes, "bvh_depth": inf.bvh_depth, "qshift": inf.qshift,
-                "bbox": list(inf.bbox), "qlo": list(inf.qlo), "build_ms": inf.build_ms, "nunique": inf.nunique}
+                "bbox": list(inf.bbox), "qlo": list(inf.qlo), "build_ms": inf.build_ms, "nunique": inf.nunique,
+                "axis": "zxy"[inf.axis], "proj_area": list(inf.proj_area)}
 
     @property
     def handle(self):
@@ -152,8 +158,8 @@ class Mesh:
             pass
 
 
-def build_mesh(V, F, stream=None, weld: bool = False) -> Mesh:
-    return Mesh(V, F, stream, weld=weld)
+def build_mesh(V, F, stream=None, weld: bool = False, axis: str = "z") -> Mesh:
+    return Mesh(V, F, stream, weld=weld, axis=axis)
 
 
 def query_batch(mesh: Mesh, Q, prec="fp32", want_chi=False, out=None, chi_out=None, stream=None):

@@ -310,6 +310,24 @@ def ellipsoid_batch(seed: int = 3, n_mesh: int = 256, tri_range=(1_000, 200_000)
 # the five named configurations
 # ----------------------------------------------------------------------------
 
+def wavy_sheets(seed: int = 6, n_sheets: int = 6, n: int = 40) -> Soup:
+    """n_sheets open, gently waving sheets stacked along z over [-1, 1]^2, each an
+    n x n vertex grid: vertical rays cross every sheet, horizontal ones few (the
+    case the ray-axis choice is for)."""
+    rng = np.random.default_rng(seed)
+    u, v = np.meshgrid(np.linspace(-1, 1, n), np.linspace(-1, 1, n), indexing="ij")
+    idx = np.arange(n * n).reshape(n, n)
+    a, b, c, d = idx[:-1, :-1], idx[1:, :-1], idx[1:, 1:], idx[:-1, 1:]
+    quad = np.concatenate([np.stack([a, b, c], -1).reshape(-1, 3), np.stack([a, c, d], -1).reshape(-1, 3)])
+    Vs, Fs = [], []
+    for k in range(n_sheets):
+        ph = rng.uniform(0, 2 * np.pi, size=2)
+        z = (2.0 * (k + 0.5) / n_sheets - 1.0) * 0.9 + 0.04 * np.sin(3 * u + ph[0]) * np.cos(2 * v + ph[1])
+        Vs.append(np.stack([u, v, z], -1).reshape(-1, 3))
+        Fs.append(quad + k * n * n)
+    return Soup(np.concatenate(Vs).astype(np.float32), np.concatenate(Fs).astype(np.int32), {"seed": seed})
+
+
 def explode(soup: Soup, seed: int | None = None) -> Soup:
     """The same triangles with three private vertex copies each, as an STL file
     stores them (no shared indices); with a seed, the triangle order is shuffled."""

@@ -49,3 +49,9 @@ def test_status_strings_and_null_handle_errors():
     out = ctypes.c_void_p(1)
     assert L.gwn_build_mesh(None, None, None, 1, -1, None, 0, None, ctypes.byref(out)) == 1
     assert out.value is None
+    # build options are checked before any device work
+    from paper_2605_01536_amd.gwn import BuildOpts
+    opts = BuildOpts(0, 7)
+    out = ctypes.c_void_p(1)
+    assert L.gwn_build_mesh_opts(None, None, None, 1, 0, None, 0, ctypes.byref(opts), None, ctypes.byref(out)) == 1
+    assert b"axis" in L.gwn_last_error()
