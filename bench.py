@@ -46,6 +46,30 @@ TRANS_SLOTS = 3
 #                          7 polynomial FMAs, t*x (1), final FMA (1), accumulate (1)
 #                                                                  = 14 + 1 trans
 I_MIN_GRID = 6 + 14 + 3 * TRANS_SLOTS      # = 29
+
+# The all-FP64 grid path against the same issue ceiling, with FP64 add/mul/fma
+# and compares at 1.5 FP32 slots and v_rcp_f64 / v_rsq_f64 at 5.4 (measured by
+# the same probe).  The hardware reciprocal and reciprocal square root are only
+# ~26-bit approximations (csrc/probe/fp64_sqrt_probe.hip), so the refinement a
+# double result needs is part of the minimum:
+#   per sample and vertex: r_z, l^2 (2); sqrt = rsq + 7; l+|r_z| (1); rcp = rcp + 4;
+#                          rho^2*rcp (1); compare (1)          = 16 FP64 + 2 trans + select (2)
+#   per sample and edge:   D, fast-path test (2); rcp + 4; N*rcp, t^2 (2);
+#                          9 polynomial FMAs; t*x, final FMA, accumulate (3)
+#                                                              = 20 FP64 + 1 trans
+# Arbitrary points (one query per lane): the x/y quantities are no longer shared
+# by a column, adding per vertex dx, dy (2), their conversion (2), rho^2 (2) and
+# per edge N (2), x/y dot (2):
+I_MIN_BATCH = I_MIN_GRID + 10              # = 39
+# The gradient (Supp. Alg. 3) per pair: per vertex r (3), rho^2 (2), l^2 (1), sqrt,
+# 1/l, l+|r_z| (1), rcp, rho^2*rcp (1), compare + select (2) = 10 + 3 trans; per
+# edge l0 l1 (1), n (3), d (3), c0, c1 (2), grad D (6), n^2+d^2 (2), rcp, scale
+# (1), the three components (8), accumulate (3) = 29 + 1 trans
+I_MIN_GRAD = 10 + 29 + 4 * TRANS_SLOTS     # = 51
+# Dense bf16 MFMA peak of MI355X (no sparsity), for the surrogate network
+PEAK_BF16 = 2.5e15
+FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
+I_MIN_GRID_FP64 = (16 + 20) * FP64_OP_SLOTS + 3 * FP64_TRANS_SLOTS + 2   # = 72.2
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +240,12 @@ def _timed(fn, steps, warmup, stream):
     return a.elapsed_time(b) / steps, (time.perf_counter() - t0) * 1e3 / steps
 
 
+def _alu_roof(pairs, slots, ms, kernel):
+    a = pairs * slots / (ms / 1e3)
+    return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "T FP32-VALU-slots/s",
+            "frac": a / PEAK_SLOTS, "traffic": None, "kernel": kernel, "slots_per_pair": slots}
+
+
 def _emit(metric, value, unit, args, ms, config, extra=None, dtype="f32"):
     out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
@@ -243,7 +273,8 @@ def bench_batch(args):
     _emit("GWN queries/sec, arbitrary points", Q.shape[0] / (wall_ms / 1e3), "queries/s", args, wall_ms,
           {"workload": f"torus soup ({info['nf']} tris, {info['nboundary']} boundary edges), 1M uniform + 1M "
                        f"near-surface points", "precision": args.prec, "pairs_per_s": pairs / (ev_ms / 1e3)},
-          dtype="f32" if args.prec == "fp32" else "f64")
+          extra={"roofline": _alu_roof(pairs, I_MIN_BATCH, ev_ms, "k_chi_* + k_bdry_batch")}
+          if args.prec == "fp32" else None, dtype="f32" if args.prec == "fp32" else "f64")
 
 
 def bench_gradient(args):
@@ -269,6 +300,7 @@ def bench_gradient(args):
           {"workload": f"torus soup ({info['nf']} tris, {info['nboundary']} boundary edges), 1M uniform + 1M "
                        f"near-surface points", "precision": args.prec, "pairs_per_s": pairs / (ev_g / 1e3),
            "w_ms_same_points": wall_w},
+          extra={"roofline": _alu_roof(pairs, I_MIN_GRAD, ev_g, "k_grad_batch")} if args.prec == "fp32" else None,
           dtype="f32" if args.prec == "fp32" else "f64")
 
 
@@ -408,7 +440,8 @@ def bench_batched(args):
           wall_ms, {"workload": f"{len(meshes)} ellipsoid-union soups, {nq} queries, {pairs:.3e} pairs",
                     "pairs_per_s": pairs / (ev_ms / 1e3), "schedule": inf, "autotune_s": tune_s,
                     "per_mesh_launches_ms": wall2, "graph_speedup_vs_per_mesh": wall2 / wall_ms,
-                    "bitwise_equal_to_per_mesh": same})
+                    "bitwise_equal_to_per_mesh": same},
+          extra={"roofline": _alu_roof(pairs, I_MIN_BATCH, ev_ms, "graph: k_chi_multi + k_bdry_persistent")})
 
 
 def bench_surrogate(args):
@@ -472,7 +505,12 @@ def bench_surrogate(args):
     _emit("surrogate+fallback GWN queries/sec (band 0.3)", best["queries_per_s"], "queries/s", args, best["ms"],
           {"workload": f"opened-spheres soup ({info['nf']} tris, {info['nboundary']} boundary edges), "
                        f"train 10M / infer 16M uniform points", "exact_ms": ex_ms, "exact_queries_per_s": n / (ex_ms / 1e3),
-                       "network_only_ms": nn_ms, "network_max_abs_err": float(err_nn.max()),
+                       "network_only_ms": nn_ms,
+                       "network_roofline": {"bound": "mfma", "unit": "TFLOP/s", "flop_per_query": 114944,
+                                            "achieved": n * 114944 / (nn_ev / 1e3) / 1e12,
+                                            "peak": PEAK_BF16 / 1e12,
+                                            "frac": n * 114944 / (nn_ev / 1e3) / PEAK_BF16},
+                       "network_max_abs_err": float(err_nn.max()),
                        "network_rms_err": float(err_nn.pow(2).mean().sqrt()), "label_s": label_s, "train_s": train_s,
                        "train_loss": losses[-1][1], "sigma": args.sigma, "epochs": args.epochs, "bands": rows,
                        "identical_max_err": identical})
@@ -516,9 +554,14 @@ def bench_precision(args):
                                                chi_out=chi, stream=st), args.steps, args.warmup, st)
         e = np.abs(w[it].double().cpu().numpy() - w_o)[far]
         chi_ok = bool(np.array_equal(chi[it].cpu().numpy(), chi_o))
+        pairs = float(grid.n) * info["nboundary"]
+        slots = I_MIN_GRID_FP64 if prec == "fp64" else I_MIN_GRID
         res[prec] = {"ms": ms, "queries_per_s": grid.n / (ms / 1e3), "max_abs_err": float(e.max()),
                      "p99_abs_err": float(np.quantile(e, 0.99)), "rms_err": float(np.sqrt(np.mean(e * e))),
-                     "chi_bit_exact": chi_ok}
+                     "chi_bit_exact": chi_ok,
+                     "roofline": {"bound": "alu", "slots_per_pair": slots, "unit": "T FP32-VALU-slots/s",
+                                  "achieved": pairs * slots / (ev / 1e3) / 1e12, "peak": PEAK_SLOTS / 1e12,
+                                  "frac": pairs * slots / (ev / 1e3) / PEAK_SLOTS}}
         print(f"[bench] {prec}: {ms:.1f} ms, max|err| {e.max():.3e}, chi exact {chi_ok}", file=sys.stderr, flush=True)
         del w, chi
         torch.cuda.empty_cache()
