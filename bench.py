@@ -68,6 +68,12 @@ I_MIN_BATCH = I_MIN_GRID + 10              # = 39
 I_MIN_GRAD = 10 + 29 + 4 * TRANS_SLOTS     # = 51
 # Dense bf16 MFMA peak of MI355X (no sparsity), for the surrogate network
 PEAK_BF16 = 2.5e15
+# The network's VALU work per point, which bounds it before the MFMA work does:
+# 512 GELU activations at ~20.5 slots (bias add, |z|/sqrt2, 1 + p x and its rcp,
+# -x^2 and exp2, the degree-5 erf polynomial, sign, 0.5 + 0.5 erf, z Phi, half a
+# packed bf16 conversion; rcp and exp2 at 3 slots), 32 sincos of the Fourier
+# features at ~20, and the 128-term output dot product with bf16 widening (256)
+NET_VALU_SLOTS = 512 * 20.5 + 32 * 21 + 256     # = 11,424 per point
 FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
 I_MIN_GRID_FP64 = (16 + 20) * FP64_OP_SLOTS + 3 * FP64_TRANS_SLOTS + 2   # = 72.2
 def parse():
@@ -510,6 +516,11 @@ def bench_surrogate(args):
                                             "achieved": n * 114944 / (nn_ev / 1e3) / 1e12,
                                             "peak": PEAK_BF16 / 1e12,
                                             "frac": n * 114944 / (nn_ev / 1e3) / PEAK_BF16},
+                       "network_valu_roofline": {"bound": "alu", "unit": "T FP32-VALU-slots/s",
+                                                 "slots_per_query": NET_VALU_SLOTS,
+                                                 "achieved": n * NET_VALU_SLOTS / (nn_ev / 1e3) / 1e12,
+                                                 "peak": PEAK_SLOTS / 1e12,
+                                                 "frac": n * NET_VALU_SLOTS / (nn_ev / 1e3) / PEAK_SLOTS},
                        "network_max_abs_err": float(err_nn.max()),
                        "network_rms_err": float(err_nn.pow(2).mean().sqrt()), "label_s": label_s, "train_s": train_s,
                        "train_loss": losses[-1][1], "sigma": args.sigma, "epochs": args.epochs, "bands": rows,

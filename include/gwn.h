@@ -254,8 +254,9 @@ gwn_status gwn_multi_destroy(gwn_multi plan);
  *     0.999, eps 1e-8, bias-corrected).
  *   gwn_surrogate_query: w_out = network prediction, except for points with
  *     |prediction - 1/2| < band, which are re-evaluated by the exact FP32 path
- *     (gwn_query_batch arithmetic) on `mesh`; fallback_out (device, nullable)
- *     flags them and *nfallback_out (host, nullable; synchronises) counts them.
+ *     (gwn_query_batch) on `mesh`; fallback_out (device, nullable) flags them
+ *     and *nfallback_out (host, nullable) counts them.  The call synchronises
+ *     the stream once, to size the exact evaluation by that count.
  * The training scratch is owned by the handle and sized to the largest batch;
  * n must be < 2^31.
  */

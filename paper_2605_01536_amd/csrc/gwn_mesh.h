@@ -85,10 +85,6 @@ gwn_status multi_run(gwn_multi_s* p, hipStream_t stream);
 void multi_destroy(gwn_multi_s* p);
 void multi_info(const gwn_multi_s* p, gwn_multi_info* out);
 
-// exact FP32 batch path whose point count lives on the device (nmax bounds it)
-gwn_status query_batch_devcount(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
-                                int64_t nmax, const int* ndev, int* chi, float* w, hipStream_t st);
-
 gwn_status mlp_create(uint64_t seed, double sigma, gwn_mlp_s** out);
 void mlp_release(gwn_mlp_s* h);
 gwn_status mlp_get_state(gwn_mlp_s* h, float* theta, float* m, float* v, float* G, int64_t* step);

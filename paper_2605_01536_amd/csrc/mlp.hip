@@ -20,6 +20,7 @@
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 namespace gwn {
 namespace mlp {
@@ -35,6 +36,7 @@ constexpr int kChunk = 256;      // batch rows per weight-gradient workgroup
 constexpr int kLdC = kChunk + 4;
 constexpr int kWf = 128 * 64 + 3 * 128 * 128 + 128;   // forward bf16 copy: Wt0..Wt3 ([out][in]) + w4
 constexpr int kWb = 3 * 128 * 128;                    // backward bf16 copy: W1..W3 ([in][out])
+constexpr int kWi = 128 * 64 + 3 * 128 * 128;         // inference copy: W0..W3 as MFMA A fragments
 
 struct Dev {
     float* master;   // kNParams
@@ -43,6 +45,7 @@ struct Dev {
     float* G;        // 96
     unsigned short* wf;
     unsigned short* wb;
+    unsigned short* wi;
 };
 
 struct Train {
@@ -311,6 +314,135 @@ __global__ void k_reduce(const float* __restrict__ part, int nchunk, float* __re
     grad[p] = s;
 }
 
+// ---- inference: the activations never leave registers
+//
+// Each hidden layer is computed transposed, H_out^T = W^T H_in^T, with
+// v_mfma_f32_16x16x32_bf16: A = 16 output features x 32 input features of the
+// weights, B = 32 input features x 16 points of the activations, D = 16 output
+// features x 16 points (lane n + 16g holds features 4g..4g+3 of the tile for
+// point n).  Which input feature sits in fragment slot (g, j) is free as long as
+// A and B agree, so the input features of block b are numbered
+//   kappa(b, g, j) = 32 b + 4 g + j       (j < 4)   -- rows of output tile 2b
+//                  = 32 b + 16 + 4 g + j - 4 (j >= 4) -- rows of output tile 2b+1
+// and a lane's outputs of tiles 2b, 2b+1 ARE its B fragment of block b for the
+// next layer.  The Fourier features of the first layer use kappa0(b, g, j) =
+// 32 b + 8 g + j (block 0: sines, block 1: cosines of frequencies 8g..8g+7).
+// The weights are packed once per update into these A fragments, 16 bytes per
+// lane, in the order the kernel reads them.
+__host__ __device__ inline int infer_slot(int l, int k, int o) {
+    const int kb = l == 0 ? 2 : 4;
+    const int b = k / 32, r = k % 32;
+    int g, j;
+    if (l == 0) {
+        g = r / 8;
+        j = r % 8;
+    } else {
+        g = (r % 16) / 4;
+        j = 4 * (r / 16) + r % 4;
+    }
+    const int base = l == 0 ? 0 : 8192 + (l - 1) * 16384;
+    const int frag = (o / 16) * kb + b, lane = o % 16 + 16 * g;
+    return base + (frag * 64 + lane) * 8 + j;
+}
+
+// input feature held in slot j of block b by lane group g (hidden layers)
+__device__ __forceinline__ int kappa(int b, int g, int j) { return 32 * b + (j < 4 ? 4 * g + j : 12 + 4 * g + j); }
+
+constexpr int kInferWaves = 8;    // 512 threads: 2 waves per SIMD share one copy of the weights in LDS
+constexpr int kInferPts = 32;     // points per wave per step (two 16-point tiles reuse each A fragment)
+
+__global__ __launch_bounds__(64 * kInferWaves) void k_infer(Dev P, const float* __restrict__ qx,
+                                                           const float* __restrict__ qy,
+                                                           const float* __restrict__ qz, long long qs, long long n,
+                                                           float* __restrict__ y) {
+    __shared__ v8bf sWi[kWi / 8];
+    __shared__ float sB[4][128];
+    __shared__ float sW4[128];
+    __shared__ float sG[96];
+    {
+        const uint4* src = (const uint4*)P.wi;
+        uint4* dst = (uint4*)sWi;
+        for (int i = threadIdx.x; i < kWi / 8; i += 64 * kInferWaves) dst[i] = src[i];
+    }
+    for (int i = threadIdx.x; i < 128; i += 64 * kInferWaves) {
+        sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
+        for (int l = 0; l < 4; ++l) sB[l][i] = P.master[kOffB[l] + i];
+    }
+    if (threadIdx.x < 96) sG[threadIdx.x] = P.G[threadIdx.x];
+    const float b4 = P.master[kOffB[4]];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, ln = lane & 15, g = lane >> 4;
+    for (long long step = (long long)blockIdx.x * kInferWaves + wave; step * kInferPts < n;
+         step += (long long)gridDim.x * kInferWaves) {
+        v8bf X[2][4];
+        long long pt[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {   // Fourier features: frequencies 8g..8g+7 of point ln of tile p
+            pt[p] = step * kInferPts + 16 * p + ln;
+            const long long q = min(pt[p], n - 1);
+            const float px = qx[q * qs], py = qy[q * qs], pz = qz[q * qs];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int f = 8 * g + j;
+                const float arg = 6.283185307179586f * fmaf(sG[3 * f], px, fmaf(sG[3 * f + 1], py, sG[3 * f + 2] * pz));
+                float sn, cs;
+                sincosf(arg, &sn, &cs);
+                X[p][0][j] = (__bf16)sn;
+                X[p][1][j] = (__bf16)cs;
+            }
+        }
+#pragma unroll 1
+        for (int l = 0; l < 4; ++l) {
+            const int kb = l == 0 ? 2 : 4;
+            const v8bf* W = sWi + (l == 0 ? 0 : (8192 + (l - 1) * 16384) / 8);
+            v8bf Y[2][4];
+#pragma unroll
+            for (int bo = 0; bo < 4; ++bo) {   // output tiles 2bo, 2bo+1 = block bo of the next input
+                v4f acc[2][2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) acc[h][p] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (b >= kb) break;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const v8bf A = W[((2 * bo + h) * kb + b) * 64 + lane];
+#pragma unroll
+                        for (int p = 0; p < 2; ++p)
+                            acc[h][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, X[p][b], acc[h][p], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const float bias = sB[l][16 * (2 * bo + h) + 4 * g + c];
+#pragma unroll
+                        for (int p = 0; p < 2; ++p) Y[p][bo][4 * h + c] = (__bf16)gelu(acc[h][p][c] + bias);
+                    }
+            }
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) X[p][b] = Y[p][b];
+        }
+        // output layer: each lane's 32 activations, then the four lane groups of a point
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            float s = 0.f;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) s = fmaf((float)X[p][b][j], sW4[kappa(b, g, j)], s);
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            if (g == 0 && pt[p] < n) y[pt[p]] = s + b4;
+        }
+    }
+}
+
 // bf16 copies of one master parameter in the layouts the kernels read
 __device__ __forceinline__ void pack_one(const Dev& P, int p, float w) {
     for (int l = 0; l < 4; ++l) {
@@ -320,6 +452,7 @@ __device__ __forceinline__ void pack_one(const Dev& P, int p, float w) {
             const unsigned short b = f2bf(w);
             P.wf[(l == 0 ? 0 : 8192 + (l - 1) * 16384) + o * kin + k] = b;
             if (l >= 1) P.wb[(l - 1) * 16384 + k * 128 + o] = b;
+            P.wi[infer_slot(l, k, o)] = b;
             return;
         }
     }
@@ -478,6 +611,7 @@ void mlp_release(gwn_mlp_s* h) {
     (void)hipFree(h->d.G);
     (void)hipFree(h->d.wf);
     (void)hipFree(h->d.wb);
+    (void)hipFree(h->d.wi);
     free_train(h);
     (void)hipFree(h->scratch_w);
     (void)hipFree(h->scratch_q);
@@ -501,6 +635,7 @@ gwn_status mlp_create(uint64_t seed, double sigma, gwn_mlp_s** out) {
     GWN_HIP_TRY(hipMalloc((void**)&h->d.G, sizeof(float) * 96));
     GWN_HIP_TRY(hipMalloc((void**)&h->d.wf, sizeof(unsigned short) * kWf));
     GWN_HIP_TRY(hipMalloc((void**)&h->d.wb, sizeof(unsigned short) * kWb));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.wi, sizeof(unsigned short) * kWi));
     Rng r{seed};
     std::vector<float> G(96), theta(kNParams, 0.f);
     for (float& g : G) g = (float)(sigma * r.normal());
@@ -549,7 +684,10 @@ gwn_status mlp_set_state(gwn_mlp_s* h, const float* theta, const float* m, const
 gwn_status mlp_forward(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t n,
                        float* y, hipStream_t st) {
     if (n == 0) return GWN_OK;
-    k_fwd<false><<<fwd_grid(n), 256, 0, st>>>(h->d, qx, qy, qz, qs, n, y, Train{});
+    const long long steps = (n + kInferPts - 1) / kInferPts;
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((steps + kInferWaves - 1) / kInferWaves,
+                                                                                 256));
+    k_infer<<<blocks, 64 * kInferWaves, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
     GWN_HIP_TRY(hipGetLastError());
     return GWN_OK;
 }
@@ -614,18 +752,18 @@ gwn_status surrogate_query(gwn_mlp_s* h, const gwn_mesh_s* mesh, const float* qx
     k_band_select<<<nb, 256, 0, st>>>(w, n, band, h->scratch_cnt, h->scratch_idx, mask);
     k_gather<<<nb, 256, 0, st>>>(qx, qy, qz, qs, h->scratch_idx, h->scratch_cnt, h->scratch_q);
     GWN_HIP_TRY(hipGetLastError());
-    // exact crossing counts and boundary term on the compacted points (device count)
-    s = query_batch_devcount(mesh, h->scratch_q, h->scratch_q + 1, h->scratch_q + 2, 3, n, h->scratch_cnt,
-                             h->scratch_chi, h->scratch_w, st);
+    // the fallback count sizes the exact evaluation (one synchronisation), which
+    // then takes the ordinary batch path on the compacted points
+    int c = 0;
+    GWN_HIP_TRY(hipMemcpyAsync(&c, h->scratch_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+    GWN_HIP_TRY(hipStreamSynchronize(st));
+    if (nfallback) *nfallback = c;
+    if (c == 0) return GWN_OK;
+    s = query_batch(mesh, h->scratch_q, h->scratch_q + 1, h->scratch_q + 2, 3, c, GWN_PREC_FP32, h->scratch_w,
+                    h->scratch_chi, st);
     if (s != GWN_OK) return s;
-    k_scatter<<<nb, 256, 0, st>>>(h->scratch_w, h->scratch_idx, h->scratch_cnt, w);
+    k_scatter<<<(unsigned)((c + 255) / 256), 256, 0, st>>>(h->scratch_w, h->scratch_idx, h->scratch_cnt, w);
     GWN_HIP_TRY(hipGetLastError());
-    if (nfallback) {
-        int c = 0;
-        GWN_HIP_TRY(hipMemcpyAsync(&c, h->scratch_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
-        GWN_HIP_TRY(hipStreamSynchronize(st));
-        *nfallback = c;
-    }
     return GWN_OK;
 }
 

@@ -17,11 +17,10 @@ namespace {
 // perm (nullable): lane j handles point perm[j] (a traversal order)
 __global__ __launch_bounds__(kChiBlock) void k_chi_batch(MeshView mv, const float* __restrict__ qx,
                                                          const float* __restrict__ qy, const float* __restrict__ qz,
-                                                         long long qs, long long nq, const int* __restrict__ ndev,
-                                                         const int* __restrict__ perm, int* __restrict__ chi) {
+                                                         long long qs, long long nq, const int* __restrict__ perm,
+                                                         int* __restrict__ chi) {
     __shared__ int stk[kLdsStack * kChiBlock];
     const long long j = blockIdx.x * (long long)kChiBlock + threadIdx.x;
-    if (ndev) nq = min(nq, (long long)*ndev);   // count known only on the device
     if (j >= nq) return;
     const long long i = perm ? (long long)perm[j] : j;
     const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
@@ -125,10 +124,8 @@ __global__ __launch_bounds__(kChiBlock) void k_chi_line(MeshView mv, const float
 template <class T>
 __global__ __launch_bounds__(256) void k_bdry_batch(MeshView mv, const float* __restrict__ qx, const float* __restrict__ qy,
                                                     const float* __restrict__ qz, long long qs, long long nq,
-                                                    const int* __restrict__ ndev, const int* __restrict__ chi,
-                                                    T* __restrict__ w) {
+                                                    const int* __restrict__ chi, T* __restrict__ w) {
     const long long i = blockIdx.x * 256ll + threadIdx.x;
-    if (ndev) nq = min(nq, (long long)*ndev);   // count known only on the device
     if (nq <= 0 || blockIdx.x * 256ll >= nq) return;
     const long long ii = i < nq ? i : nq - 1;
     const float px = qx[ii * qs], py = qy[ii * qs], pz = qz[ii * qs];
@@ -289,12 +286,12 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
                 mv, x, y, z, qs, n, perm, chi + o, nullptr);
         } else {
             k_chi_batch<<<(unsigned)((n + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, x, y, z, qs, n,
-                                                                                           nullptr, nullptr, chi + o);
+                                                                                           nullptr, chi + o);
         }
         e = hipGetLastError();
         if (perm) (void)hipFreeAsync(perm, st);
         if (e == hipSuccess) {
-            k_bdry_batch<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(mv, x, y, z, qs, n, nullptr, chi + o, w + o);
+            k_bdry_batch<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(mv, x, y, z, qs, n, chi + o, w + o);
             e = hipGetLastError();
         }
     }
@@ -383,23 +380,6 @@ gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, co
     axis_ptrs(m->axis, qx, qy, qz);
     if (prec == GWN_PREC_FP64) return launch_batch<double>(m, qx, qy, qz, qs, nq, (double*)w, chi_out, st);
     return launch_batch<float>(m, qx, qy, qz, qs, nq, (float*)w, chi_out, st);
-}
-
-gwn_status query_batch_devcount(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
-                                int64_t nmax, const int* ndev, int* chi, float* w, hipStream_t st) {
-    if (nmax == 0) return GWN_OK;
-    axis_ptrs(m->axis, qx, qy, qz);
-    if (nmax > max_launch_queries()) {
-        set_error("surrogate fallback: more than %lld points in one call", (long long)max_launch_queries());
-        return GWN_E_INVALID;
-    }
-    const MeshView mv = m->view();
-    k_chi_batch<<<(unsigned)((nmax + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, qx, qy, qz, qs, nmax, ndev,
-                                                                                      nullptr, chi);
-    GWN_HIP_TRY(hipGetLastError());
-    k_bdry_batch<float><<<(unsigned)((nmax + 255) / 256), 256, 0, st>>>(mv, qx, qy, qz, qs, nmax, ndev, chi, w);
-    GWN_HIP_TRY(hipGetLastError());
-    return GWN_OK;
 }
 
 gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims, int prec,
