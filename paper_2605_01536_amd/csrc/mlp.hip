@@ -480,23 +480,67 @@ __global__ void k_adam(Dev P, const float* __restrict__ grad, float lr, float b1
 
 // ---- band fallback: compaction by ballot / mbcnt, gather, scatter
 
-__global__ void k_reset_int(int* c) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+// Stable two-pass compaction of the band points: per-block counts over
+// contiguous segments, an exclusive scan, then each block writes its indices in
+// order (one counter per block instead of one atomic per wave).
+constexpr int kBandBlocks = 1024;
+
+__device__ __forceinline__ bool in_band(const float* y, long long i, long long n, float band) {
+    return i < n && fabsf(y[i] - 0.5f) < band;
 }
 
-__global__ void k_band_select(const float* __restrict__ y, long long n, float band, int* __restrict__ count,
-                              long long* __restrict__ idx, unsigned char* __restrict__ mask) {
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const bool f = i < n && fabsf(y[i] - 0.5f) < band;
-    if (mask && i < n) mask[i] = f ? 1 : 0;
-    const unsigned long long b = __builtin_amdgcn_ballot_w64(f);
-    const int lane = threadIdx.x & 63;
-    int base = 0;
-    if (lane == 0 && b) base = atomicAdd(count, __popcll(b));
-    base = __shfl(base, 0);
-    if (f) {
-        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0));
-        idx[base + rank] = i;
+__global__ __launch_bounds__(256) void k_band_count(const float* __restrict__ y, long long n, long long seg,
+                                                    float band, int* __restrict__ bcnt) {
+    __shared__ int wc[4];
+    const long long a = blockIdx.x * seg, e = min(n, a + seg);
+    int c = 0;
+    for (long long i = a + threadIdx.x; i < e; i += 256) c += in_band(y, i, n, band) ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) bcnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+// exclusive scan of the kBandBlocks counts (one block of kBandBlocks threads);
+// the total goes to *count
+__global__ __launch_bounds__(kBandBlocks) void k_band_scan(const int* __restrict__ bcnt, int* __restrict__ boff,
+                                                          int* __restrict__ count) {
+    __shared__ int sh[kBandBlocks];
+    const int t = threadIdx.x;
+    sh[t] = bcnt[t];
+    __syncthreads();
+    for (int o = 1; o < kBandBlocks; o <<= 1) {
+        const int v = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    boff[t] = sh[t] - bcnt[t];
+    if (t == kBandBlocks - 1) *count = sh[t];
+}
+
+__global__ __launch_bounds__(256) void k_band_write(const float* __restrict__ y, long long n, long long seg,
+                                                    float band, const int* __restrict__ boff,
+                                                    long long* __restrict__ idx, unsigned char* __restrict__ mask) {
+    __shared__ int wc[4];
+    const long long a = blockIdx.x * seg, e = min(n, a + seg);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int base = boff[blockIdx.x];
+    for (long long c0 = a; c0 < e; c0 += 256) {
+        const long long i = c0 + threadIdx.x;
+        const bool f = i < e && in_band(y, i, n, band);
+        if (mask && i < e) mask[i] = f ? 1 : 0;
+        const unsigned long long b = __builtin_amdgcn_ballot_w64(f);
+        if (lane == 0) wc[wave] = __popcll(b);
+        __syncthreads();
+        int before = base;
+        for (int w = 0; w < wave; ++w) before += wc[w];
+        if (f) {
+            const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0));
+            idx[before + rank] = i;
+        }
+        base += wc[0] + wc[1] + wc[2] + wc[3];
+        __syncthreads();
     }
 }
 
@@ -544,6 +588,7 @@ struct gwn_mlp_s {
     long long* scratch_idx = nullptr;
     int* scratch_cnt = nullptr;
     int* scratch_chi = nullptr;
+    int* scratch_blk = nullptr;      // per-block band counts and offsets (2 x kBandBlocks)
     long long scratch_cap = 0;
 };
 
@@ -592,6 +637,7 @@ gwn_status ensure_scratch(gwn_mlp_s* h, long long n) {
     GWN_HIP_TRY(hipMalloc((void**)&h->scratch_idx, sizeof(long long) * cap));
     GWN_HIP_TRY(hipMalloc((void**)&h->scratch_chi, sizeof(int) * cap));
     if (!h->scratch_cnt) GWN_HIP_TRY(hipMalloc((void**)&h->scratch_cnt, sizeof(int)));
+    if (!h->scratch_blk) GWN_HIP_TRY(hipMalloc((void**)&h->scratch_blk, sizeof(int) * 2 * kBandBlocks));
     h->scratch_cap = cap;
     return GWN_OK;
 }
@@ -618,6 +664,7 @@ void mlp_release(gwn_mlp_s* h) {
     (void)hipFree(h->scratch_idx);
     (void)hipFree(h->scratch_chi);
     (void)hipFree(h->scratch_cnt);
+    (void)hipFree(h->scratch_blk);
     delete h;
 }
 
@@ -747,9 +794,11 @@ gwn_status surrogate_query(gwn_mlp_s* h, const gwn_mesh_s* mesh, const float* qx
     if (s != GWN_OK) return s;
     s = mlp_forward(h, qx, qy, qz, qs, n, w, st);
     if (s != GWN_OK) return s;
-    k_reset_int<<<1, 64, 0, st>>>(h->scratch_cnt);
     const unsigned nb = (unsigned)((n + 255) / 256);
-    k_band_select<<<nb, 256, 0, st>>>(w, n, band, h->scratch_cnt, h->scratch_idx, mask);
+    const long long seg = ((n + kBandBlocks - 1) / kBandBlocks + 255) / 256 * 256;
+    k_band_count<<<kBandBlocks, 256, 0, st>>>(w, n, seg, band, h->scratch_blk);
+    k_band_scan<<<1, kBandBlocks, 0, st>>>(h->scratch_blk, h->scratch_blk + kBandBlocks, h->scratch_cnt);
+    k_band_write<<<kBandBlocks, 256, 0, st>>>(w, n, seg, band, h->scratch_blk + kBandBlocks, h->scratch_idx, mask);
     k_gather<<<nb, 256, 0, st>>>(qx, qy, qz, qs, h->scratch_idx, h->scratch_cnt, h->scratch_q);
     GWN_HIP_TRY(hipGetLastError());
     // the fallback count sizes the exact evaluation (one synchronisation), which
