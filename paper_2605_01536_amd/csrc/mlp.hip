@@ -118,15 +118,18 @@ template <bool TRAIN>
 __global__ __launch_bounds__(256) void k_fwd(Dev P, const float* __restrict__ qx, const float* __restrict__ qy,
                                              const float* __restrict__ qz, long long qs, long long n,
                                              float* __restrict__ y, Train T) {
-    __shared__ unsigned short sW0[128 * kLd0];
-    __shared__ unsigned short sW[3][128 * kLd];
-    __shared__ unsigned short sA[kTile * kLd];
+    __shared__ __attribute__((aligned(16))) unsigned short sW0[128 * kLd0];
+    __shared__ __attribute__((aligned(16))) unsigned short sW[3][128 * kLd];
+    __shared__ __attribute__((aligned(16))) unsigned short sA[kTile * kLd];
     __shared__ float sW4[128];
     __shared__ float sB[4][128];
     __shared__ float sG[96];
-    for (int i = threadIdx.x; i < 128 * 64; i += 256) sW0[(i >> 6) * kLd0 + (i & 63)] = P.wf[i];
+    // weights staged 16 bytes (8 bf16) per load; padded rows stay 16-byte aligned
+    for (int i = threadIdx.x; i < 128 * 8; i += 256)
+        ((uint4*)(sW0 + (i >> 3) * kLd0))[i & 7] = ((const uint4*)P.wf)[i];
     for (int l = 0; l < 3; ++l)
-        for (int i = threadIdx.x; i < 128 * 128; i += 256) sW[l][(i >> 7) * kLd + (i & 127)] = P.wf[8192 + l * 16384 + i];
+        for (int i = threadIdx.x; i < 128 * 16; i += 256)
+            ((uint4*)(sW[l] + (i >> 4) * kLd))[i & 15] = ((const uint4*)(P.wf + 8192 + l * 16384))[i];
     for (int i = threadIdx.x; i < 128; i += 256) {
         sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
         for (int l = 0; l < 4; ++l) sB[l][i] = P.master[kOffB[l] + i];
@@ -199,11 +202,12 @@ __global__ __launch_bounds__(256) void k_fwd(Dev P, const float* __restrict__ qx
 
 // Backward pass through the activations: dy, then dz_3 .. dz_0 (bf16, row-major).
 __global__ __launch_bounds__(256) void k_bwd(Dev P, long long n, const float* __restrict__ tgt, float inv_n, Train T) {
-    __shared__ unsigned short sW[3][128 * kLd];   // W1..W3 as [in][out]
-    __shared__ unsigned short sA[kTile * kLd];
+    __shared__ __attribute__((aligned(16))) unsigned short sW[3][128 * kLd];   // W1..W3 as [in][out]
+    __shared__ __attribute__((aligned(16))) unsigned short sA[kTile * kLd];
     __shared__ float sW4[128];
     for (int l = 0; l < 3; ++l)
-        for (int i = threadIdx.x; i < 128 * 128; i += 256) sW[l][(i >> 7) * kLd + (i & 127)] = P.wb[l * 16384 + i];
+        for (int i = threadIdx.x; i < 128 * 16; i += 256)
+            ((uint4*)(sW[l] + (i >> 4) * kLd))[i & 15] = ((const uint4*)(P.wb + l * 16384))[i];
     for (int i = threadIdx.x; i < 128; i += 256) sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -258,35 +262,56 @@ __global__ __launch_bounds__(256) void k_wgrad(long long n, Train T) {
     const long long c0 = (long long)blockIdx.x * kChunk;
     float* part = T.part + (long long)blockIdx.x * (kNParams + 1);
     if (layer == 4) {
-        if (threadIdx.x < 129) {
-            float s = 0.f;
-            for (int m = 0; m < kChunk; ++m) {
-                const long long row = c0 + m;
-                if (row >= n) break;
-                const float dy = T.dy[row];
-                s += threadIdx.x < 128 ? bf2f(T.x[(4 * T.cap + row) * 128 + threadIdx.x]) * dy : dy;
+        // output layer: column j of x4 against dy, rows split between the two
+        // halves of the block; no early exit, so the loads of many rows are in
+        // flight at once
+        __shared__ float sh[3][128];
+        const int j = threadIdx.x & 127, half = threadIdx.x >> 7;
+        float s = 0.f, sb = 0.f, sl = 0.f;
+#pragma unroll 8
+        for (int m = half; m < kChunk; m += 2) {
+            const long long row = c0 + m;
+            const bool ok = row < n;
+            const float dy = ok ? T.dy[row] : 0.f;
+            const float x = ok ? bf2f(T.x[(4 * T.cap + row) * 128 + j]) : 0.f;
+            s = fmaf(x, dy, s);
+            sb += dy;
+            sl = fmaf(dy, dy, sl);
+        }
+        if (half == 1) {
+            sh[0][j] = s;
+            sh[1][j] = sb;
+            sh[2][j] = sl;
+        }
+        __syncthreads();
+        if (half == 0) {
+            part[kOffW[4] + j] = s + sh[0][j];
+            if (j == 0) {
+                part[kOffB[4]] = sb + sh[1][0];
+                part[kNParams] = sl + sh[2][0];   // sum of dy^2; the host turns it into the loss
             }
-            if (threadIdx.x < 128) part[kOffW[4] + threadIdx.x] = s;
-            else part[kOffB[4]] = s;
-        } else if (threadIdx.x == 129) {   // loss partial of this chunk
-            float s = 0.f;
-            for (int m = 0; m < kChunk; ++m) {
-                const long long row = c0 + m;
-                if (row >= n) break;
-                const float d = T.dy[row];
-                s += d * d;
-            }
-            part[kNParams] = s;   // sum of dy^2; the host turns it into the loss
         }
         return;
     }
     const int kin = layer == 0 ? 64 : 128;
-    for (int idx = threadIdx.x; idx < kChunk * 128; idx += 256) {
-        const int m = idx >> 7, j = idx & 127;
+    // rows arrive 8 bf16 at a time and are written transposed into LDS
+    for (int idx = threadIdx.x; idx < kChunk * 16; idx += 256) {
+        const int m = idx >> 4, j0 = (idx & 15) * 8;
         const long long row = c0 + m;
         const bool ok = row < n;
-        if (j < kin) sXt[j * kLdC + m] = ok ? T.x[((long long)layer * T.cap + row) * 128 + j] : (unsigned short)0;
-        sDt[j * kLdC + m] = ok ? T.dz[((long long)layer * T.cap + row) * 128 + j] : (unsigned short)0;
+        const uint4 z = {0u, 0u, 0u, 0u};
+        const uint4 xv = ok && j0 < kin ? *(const uint4*)(T.x + ((long long)layer * T.cap + row) * 128 + j0) : z;
+        const uint4 dv = ok ? *(const uint4*)(T.dz + ((long long)layer * T.cap + row) * 128 + j0) : z;
+        const unsigned xs[4] = {xv.x, xv.y, xv.z, xv.w}, ds[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (j0 < kin) {
+                sXt[(j0 + 2 * e) * kLdC + m] = (unsigned short)(xs[e] & 0xffffu);
+                sXt[(j0 + 2 * e + 1) * kLdC + m] = (unsigned short)(xs[e] >> 16);
+            }
+            sDt[(j0 + 2 * e) * kLdC + m] = (unsigned short)(ds[e] & 0xffffu);
+            sDt[(j0 + 2 * e + 1) * kLdC + m] = (unsigned short)(ds[e] >> 16);
+        }
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
