@@ -74,6 +74,14 @@ PEAK_BF16 = 2.5e15
 # packed bf16 conversion; rcp and exp2 at 3 slots), 32 sincos of the Fourier
 # features at ~20, and the 128-term output dot product with bf16 widening (256)
 NET_VALU_SLOTS = 512 * 20.5 + 32 * 21 + 256     # = 11,424 per point
+# HBM bytes moved per k_grid<float, 8> launch on the default workload (512^3 grid,
+# 1.05M-triangle soup), from two rocprofv3 --pmc passes over this command:
+# FETCH_SIZE 231,943.5 KiB and WRITE_SIZE 524,288 KiB per dispatch, scaled by
+# what the same counters read for a plain 1 GiB device copy (bench.py
+# --copy-probe: FETCH_SIZE shows 524,308.5 KiB -> x2.000, WRITE_SIZE
+# 1,048,576 KiB -> x1.000).  Measured on the kernel as it stands; re-take the
+# counters after any change to k_grid or the workload.
+K_GRID_TRAFFIC_BYTES = (231943.5 * 2.0 + 524288.0 * 1.0) * 1024
 FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
 I_MIN_GRID_FP64 = (16 + 20) * FP64_OP_SLOTS + 3 * FP64_TRANS_SLOTS + 2   # = 72.2
 def parse():
@@ -168,7 +176,9 @@ def main():
         "peak": PEAK_SLOTS / 1e12,
         "unit": "T FP32-VALU-slots/s",
         "frac": achieved / PEAK_SLOTS,
-        "traffic": None,
+        # HBM bytes per launch (rocprofv3 counters); only measured for the default workload
+        "traffic": K_GRID_TRAFFIC_BYTES if (args.n == 512 and args.prec == "fp32") else None,
+        "traffic_unit": "bytes per launch",
         "kernel": "k_grid",
         "slots_per_pair": I_MIN_GRID,
         "pairs_per_launch": pairs,

@@ -14,15 +14,12 @@ namespace gwn {
 namespace {
 
 // crossing counts of arbitrary points (per-lane LDS traversal stack)
-// perm (nullable): lane j handles point perm[j] (a traversal order)
 __global__ __launch_bounds__(kChiBlock) void k_chi_batch(MeshView mv, const float* __restrict__ qx,
                                                          const float* __restrict__ qy, const float* __restrict__ qz,
-                                                         long long qs, long long nq, const int* __restrict__ perm,
-                                                         int* __restrict__ chi) {
+                                                         long long qs, long long nq, int* __restrict__ chi) {
     __shared__ int stk[kLdsStack * kChiBlock];
-    const long long j = blockIdx.x * (long long)kChiBlock + threadIdx.x;
-    if (j >= nq) return;
-    const long long i = perm ? (long long)perm[j] : j;
+    const long long i = blockIdx.x * (long long)kChiBlock + threadIdx.x;
+    if (i >= nq) return;
     const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
     chi[i] = q.inbox ? chi_up(mv, q, stk + threadIdx.x) : 0;
 }
@@ -106,12 +103,11 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_chi_wave(MeshView mv, const
 // both crossing counts of arbitrary points (the whole vertical line)
 __global__ __launch_bounds__(kChiBlock) void k_chi_line(MeshView mv, const float* __restrict__ qx,
                                                         const float* __restrict__ qy, const float* __restrict__ qz,
-                                                        long long qs, long long nq, const int* __restrict__ perm,
-                                                        int* __restrict__ up, int* __restrict__ down) {
+                                                        long long qs, long long nq, int* __restrict__ up,
+                                                        int* __restrict__ down) {
     __shared__ int stk[kLdsStack * kChiBlock];
-    const long long j = blockIdx.x * (long long)kChiBlock + threadIdx.x;
-    if (j >= nq) return;
-    const long long i = perm ? (long long)perm[j] : j;
+    const long long i = blockIdx.x * (long long)kChiBlock + threadIdx.x;
+    if (i >= nq) return;
     const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
     int u = 0, d = 0;
     if (q.inbox) chi_line(mv, q, stk + threadIdx.x, u, d);
@@ -286,7 +282,7 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
                 mv, x, y, z, qs, n, perm, chi + o, nullptr);
         } else {
             k_chi_batch<<<(unsigned)((n + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(mv, x, y, z, qs, n,
-                                                                                           nullptr, chi + o);
+                                                                                           chi + o);
         }
         e = hipGetLastError();
         if (perm) (void)hipFreeAsync(perm, st);
@@ -356,7 +352,7 @@ gwn_status query_crossings(const gwn_mesh_s* m, const float* qx, const float* qy
                 mv, x, y, z, qs, n, perm, up ? up + o : nullptr, down ? down + o : nullptr);
         } else {
             k_chi_line<<<(unsigned)((n + kChiBlock - 1) / kChiBlock), kChiBlock, 0, st>>>(
-                mv, x, y, z, qs, n, nullptr, up ? up + o : nullptr, down ? down + o : nullptr);
+                mv, x, y, z, qs, n, up ? up + o : nullptr, down ? down + o : nullptr);
         }
         const hipError_t e = hipGetLastError();
         if (perm) (void)hipFreeAsync(perm, st);
