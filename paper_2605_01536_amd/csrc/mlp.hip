@@ -213,19 +213,26 @@ __global__ __launch_bounds__(256) void k_bwd(Dev P, long long n, const float* __
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     const int r0 = wave * 16;
     for (long long tile = blockIdx.x; tile * kTile < n; tile += gridDim.x) {
-        // dz_3 = (dy w4) * gelu'(z_3), in the accumulator layout
+        // dz_3 = (dy w4) * gelu'(z_3), in the accumulator layout.  Every load is
+        // issued before the first store (the stores could alias them, so the
+        // compiler would otherwise wait out one load latency per element).
+        float dyr[4], zr[8][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long long row = tile * kTile + r0 + 4 * lg + i;
+            dyr[i] = row < n ? 2.f * (T.y[row] - tgt[row]) * inv_n : 0.f;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) zr[t][i] = row < n ? T.z[(3 * T.cap + row) * 128 + 16 * t + lr] : 0.f;
+        }
+#pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int c = 16 * t + lr;
+#pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = r0 + 4 * lg + i;
                 const long long row = tile * kTile + r;
-                float dz = 0.f;
-                if (row < n) {
-                    const float dy = 2.f * (T.y[row] - tgt[row]) * inv_n;
-                    if (t == 0 && lr == 0) T.dy[row] = dy;
-                    dz = dy * sW4[c] * gelu_grad(T.z[(3 * T.cap + row) * 128 + c]);
-                }
-                const unsigned short b = f2bf(dz);
+                if (t == 0 && lr == 0 && row < n) T.dy[row] = dyr[i];
+                const unsigned short b = f2bf(row < n ? dyr[i] * sW4[c] * gelu_grad(zr[t][i]) : 0.f);
                 sA[r * kLd + c] = b;
                 if (row < n) T.dz[(3 * T.cap + row) * 128 + c] = b;
             }
@@ -234,16 +241,23 @@ __global__ __launch_bounds__(256) void k_bwd(Dev P, long long n, const float* __
         v4f acc[8];
         for (int l = 3; l >= 1; --l) {
             // dx_l = dz_l W_l^T: B[k][j] = W_l[j][k] is row j of W_l ([in][out])
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {   // z of the layer below, loaded before the stores
+                const long long row = tile * kTile + r0 + 4 * lg + i;
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    zr[t][i] = row < n ? T.z[((long long)(l - 1) * T.cap + row) * 128 + 16 * t + lr] : 0.f;
+            }
             mma_rows16<128>(sA, kLd, sW[l - 1], kLd, r0, acc);
             __syncthreads();
+#pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const int c = 16 * t + lr;
+#pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int r = r0 + 4 * lg + i;
                     const long long row = tile * kTile + r;
-                    float dz = 0.f;
-                    if (row < n) dz = acc[t][i] * gelu_grad(T.z[((long long)(l - 1) * T.cap + row) * 128 + c]);
-                    const unsigned short b = f2bf(dz);
+                    const unsigned short b = f2bf(row < n ? acc[t][i] * gelu_grad(zr[t][i]) : 0.f);
                     sA[r * kLd + c] = b;
                     if (row < n) T.dz[((long long)(l - 1) * T.cap + row) * 128 + c] = b;
                 }
