@@ -1,15 +1,19 @@
 // mlp.hip -- learned surrogate for far-field winding-number queries:
 // Fourier features gamma(p) = [sin 2piGp, cos 2piGp] (G: 32x3, fixed), four
 // GELU layers 64->128->128->128->128 and a linear output 128->1.  Matrix
-// products run on MFMA (v_mfma_f32_16x16x16bf16_1k: bf16 operands, fp32
-// accumulation); FP32 master weights are updated by Adam and re-packed into
-// bf16 copies in the two layouts the kernels read.  The band query evaluates
-// the network, re-evaluates every point whose prediction lies within `band`
-// of 1/2 with the exact kernels, and scatters those results back.
+// products run on MFMA with bf16 operands and fp32 accumulation: the training
+// kernels use v_mfma_f32_16x16x16bf16_1k on LDS tiles, inference
+// (k_infer) v_mfma_f32_16x16x32_bf16 with the activations kept in registers.
+// FP32 master weights are updated by Adam and re-packed into bf16 copies in
+// the three layouts the kernels read.  The band query evaluates the network,
+// re-evaluates every point whose prediction lies within `band` of 1/2 with the
+// exact kernels, and scatters those results back.
 //
 // MFMA 16x16x16 operand layout (wave64): lane l holds A[l%16][4(l/16)+i] and
 // B[4(l/16)+i][l%16] (i = 0..3); the result D[4(l/16)+i][l%16] lands in
-// component i of the lane's accumulator.
+// component i of the lane's accumulator.  The 16x16x32 form holds 8 k values
+// per lane (slot j of lane group l/16) with the same row, column and result
+// placement.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -111,13 +115,12 @@ __device__ __forceinline__ void mma_rows16(const unsigned short* sA, int lda, co
     }
 }
 
-// Forward pass.  Every workgroup stages all bf16 weights in LDS once, then
-// walks its tiles of 64 points; each wave owns 16 rows and only ever touches
-// its own rows of the activation tile.
-template <bool TRAIN>
+// Training forward pass: the layer inputs (bf16) and pre-activations (fp32)
+// are kept for the backward pass.  Every workgroup stages all bf16 weights in
+// LDS once, then walks its tiles of 64 points; each wave owns 16 rows and only
+// ever touches its own rows of the activation tile.
 __global__ __launch_bounds__(256) void k_fwd(Dev P, const float* __restrict__ qx, const float* __restrict__ qy,
-                                             const float* __restrict__ qz, long long qs, long long n,
-                                             float* __restrict__ y, Train T) {
+                                             const float* __restrict__ qz, long long qs, long long n, Train T) {
     __shared__ __attribute__((aligned(16))) unsigned short sW0[128 * kLd0];
     __shared__ __attribute__((aligned(16))) unsigned short sW[3][128 * kLd];
     __shared__ __attribute__((aligned(16))) unsigned short sA[kTile * kLd];
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(256) void k_fwd(Dev P, const float* __restrict__ qx
                 const unsigned short bs = f2bf(s), bc = f2bf(c);
                 sA[(r0 + lr) * kLd + f] = bs;
                 sA[(r0 + lr) * kLd + kFreq + f] = bc;
-                if (TRAIN && base + lr < n) {
+                if (base + lr < n) {
                     T.x[(base + lr) * 128 + f] = bs;
                     T.x[(base + lr) * 128 + kFreq + f] = bc;
                 }
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(256) void k_fwd(Dev P, const float* __restrict__ qx
                     const float zz = acc[t][i] + sB[l][c];
                     const unsigned short xb = f2bf(gelu(zz));
                     sA[r * kLd + c] = xb;
-                    if (TRAIN && tile * kTile + r < n) {
+                    if (tile * kTile + r < n) {
                         const long long row = tile * kTile + r;
                         T.z[((long long)l * T.cap + row) * 128 + c] = zz;
                         T.x[((long long)(l + 1) * T.cap + row) * 128 + c] = xb;
@@ -191,10 +194,7 @@ __global__ __launch_bounds__(256) void k_fwd(Dev P, const float* __restrict__ qx
             s += __shfl_xor(s, 1);
             s += __shfl_xor(s, 2);
             const long long row = tile * kTile + r;
-            if ((lane & 3) == 0 && row < n) {
-                y[row] = s + b4;
-                if (TRAIN) T.y[row] = s + b4;
-            }
+            if ((lane & 3) == 0 && row < n) T.y[row] = s + b4;
         }
         __syncthreads();
     }
@@ -782,7 +782,7 @@ gwn_status mlp_grad(gwn_mlp_s* h, const float* qx, const float* qy, const float*
                     int64_t n, hipStream_t st) {
     gwn_status s = ensure_train(h, n);
     if (s != GWN_OK) return s;
-    k_fwd<true><<<fwd_grid(n), 256, 0, st>>>(h->d, qx, qy, qz, qs, n, h->t.y, h->t);
+    k_fwd<<<fwd_grid(n), 256, 0, st>>>(h->d, qx, qy, qz, qs, n, h->t);
     GWN_HIP_TRY(hipGetLastError());
     k_bwd<<<fwd_grid(n), 256, 0, st>>>(h->d, n, tgt, 1.0f / (float)n, h->t);
     GWN_HIP_TRY(hipGetLastError());

@@ -342,3 +342,25 @@ def test_wave_traversal_small_meshes(gwn, monkeypatch, seed):
     ou, od = O.chi(V, F, Q)
     assert np.array_equal(up.cpu().numpy(), ou) and np.array_equal(dn.cpu().numpy(), od)
     compare(w.cpu().numpy(), chi.cpu().numpy(), V, F, Q, TOL_FP32, f"wave{seed}")
+
+
+def test_every_entry_point_on_empty_inputs(gwn):
+    # an empty mesh gives w = 0, chi = 0 and a zero gradient everywhere; zero
+    # points and zero grid sizes are no-ops
+    m0 = gwn.Mesh(torch.zeros((0, 3), device="cuda"), torch.zeros((0, 3), dtype=torch.int32, device="cuda"))
+    Q = torch.rand((300, 3), device="cuda")
+    for prec in ("fp32", "fp64"):
+        w, c = gwn.query_grid(m0, (-1, -1, -1), (0.1, 0.1, 0.1), (7, 5, 70), prec=prec, want_chi=True)
+        assert float(w.abs().max()) == 0.0 and int(c.abs().max()) == 0
+        assert float(gwn.query_gradient(m0, Q, prec=prec).abs().max()) == 0.0
+        assert float(gwn.query_direct(m0, Q, prec=prec).abs().max()) == 0.0
+    up, dn = gwn.query_crossings(m0, Q)
+    assert int(up.abs().max()) == 0 and int(dn.abs().max()) == 0
+    m = gwn.Mesh(_dev(OCT_V), _dev(OCT_F))
+    E = torch.zeros((0, 3), device="cuda")
+    assert gwn.query_batch(m, E).numel() == 0
+    assert gwn.query_gradient(m, E).numel() == 0
+    assert gwn.query_direct(m, E).numel() == 0
+    assert gwn.query_crossings(m, E)[0].numel() == 0
+    assert gwn.query_grid(m, (0, 0, 0), (1, 1, 1), (0, 4, 4)).numel() == 0
+    assert gwn.query_grid(m, (0, 0, 0), (1, 1, 1), (4, 4, 0)).numel() == 0
