@@ -312,10 +312,20 @@ def bench_gradient(args):
     pairs = Q.shape[0] * info["nboundary"]
     print(f"[bench] gradient {Q.shape[0]} pts B={info['nboundary']}: {wall_g:.1f} ms ({pairs / ev_g * 1e3:.3e} "
           f"edge terms/s); w at the same points {wall_w:.1f} ms", file=sys.stderr, flush=True)
+    # the 512^3 grid on the 1.05M-triangle soup: column-shared gradient kernel
+    soup4, grid = W.config4()
+    m4 = gwn.Mesh(torch.from_numpy(soup4.V).cuda(), torch.from_numpy(soup4.F).cuda())
+    g4 = torch.empty((grid.n, 3), device="cuda", dtype=dt)
+    ev_gg, _ = _timed(lambda: gwn.query_grid_gradient(m4, grid.origin, grid.spacing, grid.dims, prec=args.prec,
+                                                      out=g4, stream=st), max(1, args.steps // 5), 1, st)
+    pairs4 = float(grid.n) * m4.info()["nboundary"]
+    print(f"[bench] grid gradient 512^3: {ev_gg:.1f} ms ({pairs4 / ev_gg * 1e3:.3e} edge terms/s)",
+          file=sys.stderr, flush=True)
+    del g4, m4
     _emit("GWN gradients/sec, arbitrary points", Q.shape[0] / (wall_g / 1e3), "queries/s", args, wall_g,
           {"workload": f"torus soup ({info['nf']} tris, {info['nboundary']} boundary edges), 1M uniform + 1M "
                        f"near-surface points", "precision": args.prec, "pairs_per_s": pairs / (ev_g / 1e3),
-           "w_ms_same_points": wall_w},
+           "w_ms_same_points": wall_w, "grid_512_ms": ev_gg, "grid_512_pairs_per_s": pairs4 / (ev_gg / 1e3)},
           extra={"roofline": _alu_roof(pairs, I_MIN_GRAD, ev_g, "k_grad_batch")} if args.prec == "fp32" else None,
           dtype="f32" if args.prec == "fp32" else "f64")
 

@@ -174,6 +174,16 @@ gwn_status gwn_query_gradient(gwn_mesh m, const float* qx, const float* qy, cons
                               int64_t nq, int32_t prec, void* grad_out, void* stream);
 
 /*
+ * gwn_query_grid_gradient -- grad w (as gwn_query_gradient) at the points of the
+ * grid of gwn_query_grid, sharing each column's x/y work among its samples.
+ * grad_out: 3 * nx * ny * nz values, (dw/dx, dw/dy, dw/dz) for point (i, j, k)
+ * at 3 * ((i * ny + j) * nz + k); float or double by prec.  Errors as in
+ * gwn_query_grid.
+ */
+gwn_status gwn_query_grid_gradient(gwn_mesh m, const double* origin, const double* spacing, const int64_t* dims,
+                                   int32_t prec, void* grad_out, void* stream);
+
+/*
  * gwn_query_direct -- w as the direct sum of per-triangle signed solid angles
  * (Eq. 2, each triangle's area by Eq. 6), O(F) per query, from the float
  * vertex positions given to gwn_build_mesh.  The baseline the antipodal method

@@ -1,6 +1,7 @@
 // api.hip -- extern "C" entry points declared in include/gwn.h: argument
 // validation, handle lifetime and thread-local error reporting.  All compute
-// happens in the kernels of build.hip and query.hip.
+// happens in the kernels of the other sources (build, query, grad, direct,
+// order, multi, mlp).
 #include <cstdarg>
 #include <cstdio>
 #include <cmath>
@@ -159,27 +160,47 @@ gwn_status gwn_query_batch(gwn_mesh m, const float* qx, const float* qy, const f
     return gwn::query_batch(m, qx, qy, qz, qstride, nq, prec, w_out, chi_out, (hipStream_t)stream);
 }
 
+// shared checks of the grid entry points; *empty is set for a zero-size grid
+static gwn_status check_grid(const char* who, const double* origin, const double* spacing, const int64_t* dims,
+                             int32_t prec, const void* out, bool* empty) {
+    if (!origin || !spacing || !dims || (prec != GWN_PREC_FP32 && prec != GWN_PREC_FP64)) {
+        gwn::set_error("%s: null grid description or bad precision", who);
+        return GWN_E_INVALID;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (dims[a] < 0 || dims[a] > (1ll << 20) || !std::isfinite(origin[a]) || !std::isfinite(spacing[a])) {
+            gwn::set_error("%s: bad dims/origin/spacing on axis %d", who, a);
+            return GWN_E_INVALID;
+        }
+    }
+    *empty = dims[0] * dims[1] * dims[2] == 0;
+    if (!*empty && !out) {
+        gwn::set_error("%s: null output array", who);
+        return GWN_E_INVALID;
+    }
+    return GWN_OK;
+}
+
 gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacing, const int64_t* dims, int32_t prec,
                           void* w_out, int32_t* chi_out, void* stream) {
     gwn::clear_error();
     gwn_status s = check_mesh(m, "gwn_query_grid");
     if (s != GWN_OK) return s;
-    if (!origin || !spacing || !dims || (prec != GWN_PREC_FP32 && prec != GWN_PREC_FP64)) {
-        gwn::set_error("gwn_query_grid: null grid description or bad precision");
-        return GWN_E_INVALID;
-    }
-    for (int a = 0; a < 3; ++a) {
-        if (dims[a] < 0 || dims[a] > (1ll << 20) || !std::isfinite(origin[a]) || !std::isfinite(spacing[a])) {
-            gwn::set_error("gwn_query_grid: bad dims/origin/spacing on axis %d", a);
-            return GWN_E_INVALID;
-        }
-    }
-    if (dims[0] * dims[1] * dims[2] == 0) return GWN_OK;
-    if (!w_out) {
-        gwn::set_error("gwn_query_grid: null output array");
-        return GWN_E_INVALID;
-    }
+    bool empty = false;
+    s = check_grid("gwn_query_grid", origin, spacing, dims, prec, w_out, &empty);
+    if (s != GWN_OK || empty) return s;
     return gwn::query_grid(m, origin, spacing, dims, prec, w_out, chi_out, (hipStream_t)stream);
+}
+
+gwn_status gwn_query_grid_gradient(gwn_mesh m, const double* origin, const double* spacing, const int64_t* dims,
+                                   int32_t prec, void* grad_out, void* stream) {
+    gwn::clear_error();
+    gwn_status s = check_mesh(m, "gwn_query_grid_gradient");
+    if (s != GWN_OK) return s;
+    bool empty = false;
+    s = check_grid("gwn_query_grid_gradient", origin, spacing, dims, prec, grad_out, &empty);
+    if (s != GWN_OK || empty) return s;
+    return gwn::query_grid_gradient(m, origin, spacing, dims, prec, grad_out, (hipStream_t)stream);
 }
 
 gwn_status gwn_query_crossings(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,

@@ -15,7 +15,8 @@
 // its two edges; their divergent terms cancel in the sum but their values are
 // 0/0.  Such a query is summed again with the opposite axis (x0 = -z): the
 // gradient does not depend on the axis, and mirroring z maps that sum onto the
-// same code with r_z negated and the x, y components negated.
+// same code with r_z negated and the x, y components negated.  Grids share the
+// x/y quantities (N, grad N, the x/y dot) of a column among its samples.
 #include <algorithm>
 
 #include "gwn_kernels.h"
@@ -24,71 +25,120 @@
 namespace gwn {
 namespace {
 
+// x/y part of one boundary vertex relative to the query column, shared by all
+// samples of a grid column.  Offsets are in units of 2^e cells (f = 2^-e, see
+// far_scale): each edge term is homogeneous of degree -1 in the offsets, so the
+// sum is rescaled at the end.
 template <class T>
-struct GVtx {
-    T rx, ry, rz, l, u, s;   // offset from p, length, 1/length, l - r_z
+struct GCol {
+    T rx, ry, rho2;
 };
 
-// offsets in units of 2^e cells (f = 2^-e, see far_scale): each edge term is
-// homogeneous of degree -1 in the offsets, so the sum is rescaled at the end
-template <class T, bool FLIP>
-__device__ __forceinline__ GVtx<T> gvtx(const BVert& b, T pxs, T pys, T pzs, T f) {
-    GVtx<T> v;
-    v.rx = fma((T)b.x, f, -pxs);
-    v.ry = fma((T)b.y, f, -pys);
-    v.rz = FLIP ? -fma((T)b.z, f, -pzs) : fma((T)b.z, f, -pzs);
-    const T rho2 = v.rx * v.rx + v.ry * v.ry;
-    v.l = Arith<T>::sqrt(v.rz * v.rz + rho2);
-    v.u = Arith<T>::rcp(v.l);
-    const T t = v.l + fabs(v.rz);
-    v.s = v.rz > (T)0 ? rho2 * Arith<T>::rcp(t) : t;
-    return v;
+template <class T>
+__device__ __forceinline__ GCol<T> gcol(const BVert& b, T pxs, T pys, T f) {
+    GCol<T> c;
+    c.rx = fma((T)b.x, f, -pxs);
+    c.ry = fma((T)b.y, f, -pys);
+    c.rho2 = c.rx * c.rx + c.ry * c.ry;
+    return c;
 }
 
+// per-sample part of one vertex: u = 1/l and s = l - r_z (r_z negated for FLIP)
+template <class T, bool FLIP>
+__device__ __forceinline__ void gsamp(const BVert& b, const GCol<T>& c, T pzs, T f, T& u, T& s) {
+    const T rz0 = fma((T)b.z, f, -pzs);
+    const T rz = FLIP ? -rz0 : rz0;
+    const T l = Arith<T>::sqrt(rz * rz + c.rho2);
+    u = Arith<T>::rcp(l);
+    const T t = l + fabs(rz);
+    s = rz > (T)0 ? c.rho2 * Arith<T>::rcp(t) : t;
+}
+
+// one edge (a -> b) for one sample; N, dot and grad N come from x/y only
 template <class T>
-__device__ __forceinline__ void gedge(const GVtx<T>& a, const GVtx<T>& b, T& gx, T& gy, T& gz) {
-    const T k = a.u * b.u;
-    const T n = (a.ry * b.rx - a.rx * b.ry) * k;
-    const T d = (a.s * b.s + a.rx * b.rx + a.ry * b.ry) * k;
-    const T c0 = (T)1 + b.s * a.u, c1 = (T)1 + a.s * b.u;
+__device__ __forceinline__ void gedge(const GCol<T>& a, const GCol<T>& b, T N, T dot, T gNx, T gNy, T ua, T sa,
+                                      T ub, T sb, T* g) {
+    const T k = ua * ub;
+    const T n = N * k;
+    const T d = fma(sa, sb, dot) * k;
+    const T c0 = (T)1 + sb * ua, c1 = (T)1 + sa * ub;
     const T dDx = -(c0 * a.rx + c1 * b.rx);
     const T dDy = -(c0 * a.ry + c1 * b.ry);
-    const T dDz = a.s * b.s * (a.u + b.u);
-    const T f = k * Arith<T>::rcp(n * n + d * d);
-    gx += (d * (b.ry - a.ry) - n * dDx) * f;
-    gy += (d * (a.rx - b.rx) - n * dDy) * f;
-    gz += (-n * dDz) * f;
+    const T dDz = sa * sb * (ua + ub);
+    const T fr = k * Arith<T>::rcp(n * n + d * d);
+    g[0] += (d * gNx - n * dDx) * fr;
+    g[1] += (d * gNy - n * dDy) * fr;
+    g[2] += (-n * dDz) * fr;
 }
 
-// Sum over all loops of the edge terms, in cell units (FP32 partials flushed
-// into FP64 every 32 edges).  FLIP: the mirrored sum for the axis x0 = -z.
-template <class T, bool FLIP>
-__device__ void grad_loops(const MeshView& mv, T pxs, T pys, T pzs, T f, double* G) {
+// Sum over all loops of the edge terms for ZB samples on one vertical line, in
+// cell units (FP32 partials flushed into FP64 every 32 edges).  FLIP: the
+// mirrored sum for the axis x0 = -z.
+template <class T, int ZB, bool FLIP>
+__device__ void grad_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, double (*G)[3]) {
     const BVert* __restrict__ bv = mv.bverts;
-    G[0] = G[1] = G[2] = 0.0;
-    for (int l = 0; l < mv.nloops; ++l) {
-        const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
-        const GVtx<T> first = gvtx<T, FLIP>(bv[b0], pxs, pys, pzs, f);
-        GVtx<T> prev = first;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) G[r][0] = G[r][1] = G[r][2] = 0.0;
+    for (int lp = 0; lp < mv.nloops; ++lp) {
+        const int b0 = mv.loop_off[lp], b1 = mv.loop_off[lp + 1];
+        const GCol<T> cf = gcol<T>(bv[b0], pxs, pys, f);
+        T uf[ZB], sf[ZB];
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) gsamp<T, FLIP>(bv[b0], cf, pzs[r], f, uf[r], sf[r]);
+        GCol<T> cp = cf;
+        T up[ZB], sp[ZB];
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) {
+            up[r] = uf[r];
+            sp[r] = sf[r];
+        }
         for (int j = b0 + 1; j <= b1; j += 32) {
             const int je = min(b1 + 1, j + 32);
-            T gx = (T)0, gy = (T)0, gz = (T)0;
+            T acc[ZB][3];
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) acc[r][0] = acc[r][1] = acc[r][2] = (T)0;
             for (int jj = j; jj < je; ++jj) {
                 // index b1 closes the loop back to its first vertex
-                const GVtx<T> cur = jj < b1 ? gvtx<T, FLIP>(bv[jj], pxs, pys, pzs, f) : first;
-                gedge<T>(prev, cur, gx, gy, gz);
-                prev = cur;
+                GCol<T> cc = cf;
+                T uc[ZB], sc[ZB];
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) {
+                    uc[r] = uf[r];
+                    sc[r] = sf[r];
+                }
+                if (jj < b1) {
+                    cc = gcol<T>(bv[jj], pxs, pys, f);
+#pragma unroll
+                    for (int r = 0; r < ZB; ++r) gsamp<T, FLIP>(bv[jj], cc, pzs[r], f, uc[r], sc[r]);
+                }
+                const T N = cp.ry * cc.rx - cp.rx * cc.ry;
+                const T dot = cp.rx * cc.rx + cp.ry * cc.ry;
+                const T gNx = cc.ry - cp.ry, gNy = cp.rx - cc.rx;
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) gedge<T>(cp, cc, N, dot, gNx, gNy, up[r], sp[r], uc[r], sc[r], acc[r]);
+                cp = cc;
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) {
+                    up[r] = uc[r];
+                    sp[r] = sc[r];
+                }
             }
-            G[0] += (double)gx;
-            G[1] += (double)gy;
-            G[2] += (double)gz;
+#pragma unroll
+            for (int r = 0; r < ZB; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) G[r][c] += (double)acc[r][c];
         }
     }
     if (FLIP) {
-        G[0] = -G[0];
-        G[1] = -G[1];
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) {
+            G[r][0] = -G[r][0];
+            G[r][1] = -G[r][1];
+        }
     }
 }
+
+__device__ __forceinline__ bool finite3(const double* g) { return isfinite(g[0]) && isfinite(g[1]) && isfinite(g[2]); }
 
 template <class T>
 __global__ __launch_bounds__(256) void k_grad_batch(MeshView mv, const float* __restrict__ qx,
@@ -100,18 +150,92 @@ __global__ __launch_bounds__(256) void k_grad_batch(MeshView mv, const float* __
     const float px = qx[ii * qs], py = qy[ii * qs], pz = qz[ii * qs];
     const FarScale<T> fs = far_scale<T>(px, py, fabsf(pz), mv.g.scale);
     const T pxs = (T)px * fs.scf, pys = (T)py * fs.scf, pzs = (T)pz * fs.scf;
-    double G[3];
-    grad_loops<T, false>(mv, pxs, pys, pzs, fs.f, G);
-    if (!(isfinite(G[0]) && isfinite(G[1]) && isfinite(G[2]))) grad_loops<T, true>(mv, pxs, pys, pzs, fs.f, G);
+    double G[1][3];
+    grad_loops<T, 1, false>(mv, pxs, pys, &pzs, fs.f, G);
+    if (!finite3(G[0])) grad_loops<T, 1, true>(mv, pxs, pys, &pzs, fs.f, G);
     if (i < nq) {
         // sum of 2 atan2 terms over 4 pi, and the chain rule through p * 2^(k-e)
         const double f = kInv2Pi * (double)fs.scf;
         // frame component c is world component (c + axis) % 3
-        for (int c = 0; c < 3; ++c) g[3 * i + (c + axis) % 3] = (T)(G[c] * f);
+        for (int c = 0; c < 3; ++c) g[3 * i + (c + axis) % 3] = (T)(G[0][c] * f);
     }
 }
 
+// Gradient on a grid: one wave per (column, z-chunk) as for w, ZB samples per
+// lane sharing the column's x/y terms.  A column through a boundary vertex
+// makes the samples below it 0/0 on the +z axis; if any lane has such a sample,
+// the wave sums the mirrored axis too and those samples take that sum.
+template <class T, int ZB>
+__global__ __launch_bounds__(64 * kGridWaves) void k_grad_grid(MeshView mv, GridArgs ga, int axis,
+                                                               T* __restrict__ g) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const long long gw = ga.wave0 + (long long)blockIdx.x * kGridWaves + wave;
+    if (gw >= ga.nwaves) return;
+    const long long col = gw / ga.nchunks;
+    const long long chunk = gw - col * ga.nchunks;
+    const long long ci = col / ga.ny, cj = col - ci * ga.ny;
+    const float px = grid_coord(ga.o[0], ga.s[0], ci);
+    const float py = grid_coord(ga.o[1], ga.s[1], cj);
+    const long long k0 = chunk * 64 * ZB + (long long)lane * ZB;
+    float pz[ZB], pzm = 0.f;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        pz[r] = grid_coord(ga.o[2], ga.s[2], min(k0 + r, ga.nz - 1));
+        pzm = fmaxf(pzm, fabsf(pz[r]));
+    }
+    const FarScale<T> fs = far_scale<T>(px, py, pzm, mv.g.scale);
+    T pzs[ZB];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) pzs[r] = (T)pz[r] * fs.scf;
+    const T pxs = (T)px * fs.scf, pys = (T)py * fs.scf;
+    double G[ZB][3];
+    grad_loops<T, ZB, false>(mv, pxs, pys, pzs, fs.f, G);
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) bad |= !finite3(G[r]);
+    if (__builtin_amdgcn_ballot_w64(bad) != 0ull) {
+        double H[ZB][3];
+        grad_loops<T, ZB, true>(mv, pxs, pys, pzs, fs.f, H);
+#pragma unroll
+        for (int r = 0; r < ZB; ++r)
+            if (!finite3(G[r]))
+                for (int c = 0; c < 3; ++c) G[r][c] = H[r][c];
+    }
+    const double f = kInv2Pi * (double)fs.scf;
+    const long long base = ci * ga.st[0] + cj * ga.st[1];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        const long long k = k0 + r;
+        if (k < ga.nz)
+            for (int c = 0; c < 3; ++c) g[3 * (base + k * ga.st[2]) + (c + axis) % 3] = (T)(G[r][c] * f);
+    }
+}
+
+template <class T, int ZB>
+gwn_status launch_grad_grid(const gwn_mesh_s* m, GridArgs ga, T* g, hipStream_t st) {
+    ga.nchunks = (ga.nz + 64 * ZB - 1) / (64 * ZB);
+    ga.nwaves = ga.nx * ga.ny * ga.nchunks;
+    const long long kMaxWaves = max_launch_queries() / 64;   // 2^30 work-items per launch
+    for (long long w0 = 0; w0 < ga.nwaves; w0 += kMaxWaves) {
+        ga.wave0 = w0;
+        const long long blocks = (std::min(kMaxWaves, ga.nwaves - w0) + kGridWaves - 1) / kGridWaves;
+        k_grad_grid<T, ZB><<<(unsigned)blocks, 64 * kGridWaves, 0, st>>>(m->view(), ga, m->axis, g);
+        GWN_HIP_TRY(hipGetLastError());
+    }
+    return GWN_OK;
+}
+
 }  // namespace
+
+gwn_status query_grid_gradient(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims,
+                               int prec, void* g, hipStream_t st) {
+    GridArgs ga = frame_grid(m->axis, origin, spacing, dims);
+    if (ga.nx == 0 || ga.ny == 0 || ga.nz == 0) return GWN_OK;
+    // four samples per lane (two in FP64) share the column's x/y work
+    if (prec == GWN_PREC_FP64) return launch_grad_grid<double, 2>(m, ga, (double*)g, st);
+    return launch_grad_grid<float, 4>(m, ga, (float*)g, st);
+}
 
 gwn_status query_gradient(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
                           int64_t nq, int prec, void* g, hipStream_t st) {

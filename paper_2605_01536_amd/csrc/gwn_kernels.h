@@ -286,6 +286,45 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
     }
 }
 
+// ---------------------------------------------------------------- grids
+
+constexpr int kGridWaves = 4;  // waves per block in the wave-per-task kernels
+
+// A cell-centred grid in the mesh frame; one wave per (column, z-chunk).
+struct GridArgs {
+    double o[3], s[3];
+    long long nx, ny, nz;
+    long long nchunks;   // z-chunks per column
+    long long nwaves;    // columns * nchunks
+    long long wave0;     // first wave of this launch (large grids take several)
+    long long st[3];     // output strides of the frame's x, y, z indices (world z fastest)
+};
+
+// The grid in the frame of a mesh built along `axis`: frame axis c is world
+// axis (c + axis) % 3; the output keeps the world layout (x slowest, z fastest).
+inline GridArgs frame_grid(int axis, const double* origin, const double* spacing, const int64_t* dims) {
+    GridArgs ga;
+    const long long wst[3] = {dims[1] * dims[2], dims[2], 1};
+    long long n[3];
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + axis) % 3;
+        ga.o[c] = origin[a];
+        ga.s[c] = spacing[a];
+        n[c] = dims[a];
+        ga.st[c] = wst[a];
+    }
+    ga.nx = n[0];
+    ga.ny = n[1];
+    ga.nz = n[2];
+    ga.nchunks = ga.nwaves = ga.wave0 = 0;
+    return ga;
+}
+
+// grid coordinate origin + (i + 0.5) * spacing in FP64 without contraction
+__device__ __forceinline__ float grid_coord(double o, double s, long long i) {
+    return (float)__dadd_rn(o, __dmul_rn((double)i + 0.5, s));
+}
+
 // ---------------------------------------------------------------- chi, batch
 
 constexpr int kChiBlock = 64;

@@ -69,6 +69,9 @@ bool want_xy_order(const gwn_mesh_s* m, int64_t n);
 gwn_status xy_order(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride, int64_t n,
                     int** perm, hipStream_t stream);
 
+gwn_status query_grid_gradient(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims,
+                               int prec, void* g_out, hipStream_t stream);
+
 gwn_status query_crossings(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                            int64_t nq, int32_t* up, int32_t* down, hipStream_t stream);
 

@@ -24,7 +24,6 @@ __global__ __launch_bounds__(kChiBlock) void k_chi_batch(MeshView mv, const floa
     chi[i] = q.inbox ? chi_up(mv, q, stk + threadIdx.x) : 0;
 }
 
-constexpr int kGridWaves = 4;  // waves per block in the wave-per-task kernels
 
 // Crossing counts of Morton-ordered points, one wave-uniform traversal per wave:
 // the wave descends into a child when the line of ANY of its lanes meets the
@@ -141,20 +140,6 @@ __global__ __launch_bounds__(256) void k_bdry_batch(MeshView mv, const float* __
 
 // ---------------------------------------------------------------- grid (ray reuse)
 
-struct GridArgs {
-    double o[3], s[3];
-    long long nx, ny, nz;
-    long long nchunks;   // z-chunks per column
-    long long nwaves;    // columns * nchunks
-    long long wave0;     // first wave of this launch (large grids take several)
-    long long st[3];     // output strides of the frame's x, y, z indices (world z fastest)
-};
-
-
-// grid coordinate origin + (i + 0.5) * spacing in FP64 without contraction
-__device__ __forceinline__ float grid_coord(double o, double s, long long i) {
-    return (float)__dadd_rn(o, __dmul_rn((double)i + 0.5, s));
-}
 
 // One wave owns one (x, y) column and a chunk of 64*ZB consecutive z samples;
 // lane l holds samples l*ZB .. l*ZB+ZB-1 of the chunk.  The column's line is
@@ -380,22 +365,7 @@ gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, co
 
 gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims, int prec,
                       void* w, int32_t* chi_out, hipStream_t st) {
-    // the grid in the mesh frame: frame axis c is world axis (c + axis) % 3; the
-    // output keeps the world layout (x slowest, z fastest)
-    GridArgs ga;
-    const long long wst[3] = {dims[1] * dims[2], dims[2], 1};
-    long long n[3];
-    for (int c = 0; c < 3; ++c) {
-        const int a = (c + m->axis) % 3;
-        ga.o[c] = origin[a];
-        ga.s[c] = spacing[a];
-        n[c] = dims[a];
-        ga.st[c] = wst[a];
-    }
-    ga.nx = n[0];
-    ga.ny = n[1];
-    ga.nz = n[2];
-    ga.nchunks = ga.nwaves = ga.wave0 = 0;
+    GridArgs ga = frame_grid(m->axis, origin, spacing, dims);
     if (ga.nx == 0 || ga.ny == 0 || ga.nz == 0) return GWN_OK;
     if (prec == GWN_PREC_FP64) return launch_grid<double>(m, ga, (double*)w, chi_out, st);
     return launch_grid<float>(m, ga, (float*)w, chi_out, st);

@@ -63,6 +63,9 @@ def load():
     L.gwn_query_crossings.restype = ctypes.c_int
     L.gwn_query_gradient.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp]
     L.gwn_query_gradient.restype = ctypes.c_int
+    L.gwn_query_grid_gradient.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64), i32, vp, vp]
+    L.gwn_query_grid_gradient.restype = ctypes.c_int
     L.gwn_query_direct.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp]
     L.gwn_query_direct.restype = ctypes.c_int
     L.gwn_status_str.argtypes = [ctypes.c_int]
@@ -234,6 +237,21 @@ def query_grid(mesh: Mesh, origin, spacing, dims, prec="fp32", want_chi=False, o
     _check(L.gwn_query_grid(mesh.handle, o, s, d, p, _ptr(out), _ptr(chi_out) if chi_out is not None else None,
                             _stream(stream)))
     return (out, chi_out) if want_chi else out
+
+
+def query_grid_gradient(mesh: Mesh, origin, spacing, dims, prec="fp32", out=None, stream=None):
+    """grad w on the cell-centred grid of query_grid, (nx * ny * nz, 3), z fastest."""
+    L = load()
+    p = _PREC[prec]
+    if len(dims) != 3 or min(int(x) for x in dims) < 0:
+        raise ValueError("dims must be three non-negative sizes")
+    n = int(dims[0]) * int(dims[1]) * int(dims[2])
+    out = _out(out, (n, 3), _wdtype(p), "cuda", "out")
+    o = (ctypes.c_double * 3)(*[float(x) for x in origin])
+    s = (ctypes.c_double * 3)(*[float(x) for x in spacing])
+    d = (ctypes.c_int64 * 3)(*[int(x) for x in dims])
+    _check(L.gwn_query_grid_gradient(mesh.handle, o, s, d, p, _ptr(out), _stream(stream)))
+    return out
 
 
 class MultiOpts(ctypes.Structure):

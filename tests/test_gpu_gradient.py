@@ -98,3 +98,43 @@ def test_gradient_edge_cases(gwn):
     for prec in ("fp32", "fp64"):
         g, ref, mask = _check(gwn, V, F, Q, prec, f"octant-{prec}")
         assert np.isfinite(g).all()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("axis", ["z", "x"])
+def test_grid_gradient(gwn, prec, axis):
+    # the column-shared grid kernel against the oracle at every grid point (ragged
+    # z-chunks), and against the per-point kernel at the same points
+    s = W.opened_spheres(seed=61, n_surf=4, tris_per_surf=500)
+    m = gwn.Mesh(_dev(s.V), _dev(s.F), axis=axis)
+    g = W.GridSpec(origin=(-1.1, -1.0, -1.05), spacing=(0.2, 0.18, 0.009), dims=(11, 12, 233))
+    gg = gwn.query_grid_gradient(m, g.origin, g.spacing, g.dims, prec=prec)
+    P = W.grid_points(g)
+    gb = gwn.query_gradient(m, _dev(P), prec=prec)
+    # the rounding scale L1 belongs to the ray axis the kernel used
+    ref, l1 = O.gradient(s.V, s.F, P, axis=np.eye(3)[{"z": 2, "x": 0}[axis]], with_l1=True)
+    mask = off_surface_mask(s.V, s.F, P)
+    err = np.abs(gg.cpu().numpy().astype(np.float64) - ref).max(1)
+    assert (err[mask] <= REL[prec] * np.maximum(1.0, l1[mask])).all()
+    d = (gg.double() - gb.double()).abs().max(1).values.cpu().numpy()
+    assert (d[mask] <= REL[prec] * np.maximum(1.0, l1[mask])).all()
+
+
+def test_grid_gradient_columns_through_vertices(gwn):
+    # columns through boundary vertices: the samples below a vertex take the
+    # mirrored axis and stay finite
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0.5], [0.5, 0.5, 1]], np.float32)
+    F = np.array([[0, 1, 4], [1, 3, 4], [3, 2, 4]], np.int32)
+    m = gwn.Mesh(_dev(V), _dev(F))
+    g = W.GridSpec(origin=(-0.125, -0.125, -1.0), spacing=(0.25, 0.25, 0.0625), dims=(8, 8, 48))
+    gg = gwn.query_grid_gradient(m, g.origin, g.spacing, g.dims, prec="fp64").cpu().numpy()
+    assert np.isfinite(gg).all()
+    P = W.grid_points(g)
+    ref, l1 = O.gradient(V, F, P, with_l1=True)
+    sing = ~(np.isfinite(ref).all(1) & np.isfinite(l1))
+    assert sing.any()
+    r2, l2 = O.gradient(V, F, P[sing], axis=(0, 0, -1), with_l1=True)
+    ref[sing], l1[sing] = r2, l2
+    mask = off_surface_mask(V, F, P)
+    err = np.abs(gg - ref).max(1)
+    assert (err[mask] <= REL["fp64"] * np.maximum(1.0, l1[mask])).all()
