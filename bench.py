@@ -286,9 +286,22 @@ def bench_batch(args):
     pairs = Q.shape[0] * info["nboundary"]
     print(f"[bench] batch {Q.shape[0]} pts B={info['nboundary']}: {wall_ms:.1f} ms, {pairs / wall_ms * 1e3:.3e} pairs/s",
           file=sys.stderr, flush=True)
+    # a small batch (4,096 points): one workgroup per point with the edges split
+    # among its lanes (the default at this size) against one lane per point
+    small = {}
+    Qs = Qd[:4096].contiguous()
+    ws = torch.empty(4096, device="cuda", dtype=w.dtype)
+    for mode, flag in (("split", "1"), ("per_lane", "0")):
+        os.environ["GWN_SPLIT_BOUNDARY"] = flag
+        small[mode + "_ms"], _ = _timed(lambda: gwn.query_batch(mesh, Qs, prec=args.prec, out=ws, stream=st),
+                                        args.steps, args.warmup, st)
+    del os.environ["GWN_SPLIT_BOUNDARY"]
+    print(f"[bench] 4096 points: split {small['split_ms']:.2f} ms, per-lane {small['per_lane_ms']:.2f} ms",
+          file=sys.stderr, flush=True)
     _emit("GWN queries/sec, arbitrary points", Q.shape[0] / (wall_ms / 1e3), "queries/s", args, wall_ms,
           {"workload": f"torus soup ({info['nf']} tris, {info['nboundary']} boundary edges), 1M uniform + 1M "
-                       f"near-surface points", "precision": args.prec, "pairs_per_s": pairs / (ev_ms / 1e3)},
+                       f"near-surface points", "precision": args.prec, "pairs_per_s": pairs / (ev_ms / 1e3),
+           "small_batch_4096": small},
           extra={"roofline": _alu_roof(pairs, I_MIN_BATCH, ev_ms, "k_chi_* + k_bdry_batch")}
           if args.prec == "fp32" else None, dtype="f32" if args.prec == "fp32" else "f64")
 

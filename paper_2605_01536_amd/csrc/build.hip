@@ -354,7 +354,7 @@ __global__ void k_emit_loops(const int* __restrict__ efrom, const int* __restric
     b.qy = q.y;
     b.pad0 = v;
     b.pad1 = 0;
-    b.pad2 = 0;
+    b.loop = lid[r];   // lid is the loop index at each loop's representative only
     bv[slot] = b;
     if (r == (int)i) loop_off[lid[i]] = voff[i];
 }
@@ -488,6 +488,7 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
                       int64_t nf, bool weld, int axis, hipStream_t st, gwn_mesh_s* m) {
     auto t0 = std::chrono::steady_clock::now();
     Scratch S;
+    int loop_tail = 0;
     m->nv = nv;
     m->nf = nf;
     GWN_HIP_TRY(hipGetDevice(&m->device));
@@ -760,8 +761,8 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
             k_emit_loops<<<nblocks(nb), kThreads, 0, st>>>(efrom, repA, dA, voff, lid, nb, vx, vy, vz, vs, qv, g.scalef,
                                                           m->bverts, m->loop_off);
             GWN_HIP_TRY(hipGetLastError());
-            const int tail = (int)nb;
-            GWN_HIP_TRY(hipMemcpyAsync(m->loop_off + m->nloops, &tail, sizeof(int), hipMemcpyHostToDevice, st));
+            loop_tail = (int)nb;   // function scope: the copy reads it after this block
+            GWN_HIP_TRY(hipMemcpyAsync(m->loop_off + m->nloops, &loop_tail, sizeof(int), hipMemcpyHostToDevice, st));
         }
     }
     if (!m->loop_off) {

@@ -28,11 +28,13 @@ struct alignas(16) TriQ {
 
 // One boundary-loop vertex, 32 bytes so a wave can fetch it with one scalar load.
 // x, y, z: the input position times 2^k (an exact power-of-two scaling), i.e. in
-// fixed-point cell units; qx, qy: the quantised x and y.
+// fixed-point cell units; qx, qy: the quantised x and y; loop: the loop it
+// belongs to (its edge leads to the next vertex, or back to the loop's first).
 struct alignas(32) BVert {
     float x, y, z;
     int qx, qy;
-    int pad0, pad1, pad2;
+    int pad0, pad1;
+    int loop;
 };
 
 // Fixed-point grid parameters: q = rint((x - lo) * scale), scale = 2^k.

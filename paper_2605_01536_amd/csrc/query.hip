@@ -138,6 +138,87 @@ __global__ __launch_bounds__(256) void k_bdry_batch(MeshView mv, const float* __
     if (i < nq) w[i] = (T)((double)chi[i] + S * kInv2Pi);
 }
 
+// ---------------------------------------------------------------- boundary, split
+// Few points against many boundary edges: one workgroup per point, each lane
+// a contiguous run of boundary vertices (edge j leads from vertex j to the next
+// vertex of its loop), the partial sums reduced across the wave by shuffles and
+// across the workgroup in LDS, in a fixed order.  Fills the GPU where one lane
+// per point would leave most of it idle.
+
+constexpr int kSplitThreads = 256;
+
+template <class T, bool FAR>
+__device__ void split_run(const MeshView& mv, int a, int e, int qqx, int qqy, T pxs, T pys, T pzs, T f,
+                          double* S) {
+    if (a >= e) return;
+    const BVert* __restrict__ bv = mv.bverts;
+    ColV<T> cp;
+    T rzp, sp;
+    load_vertex<T, 1, FAR>(bv[a], qqx, qqy, pxs, pys, &pzs, f, cp, &rzp, &sp);
+    T acc = (T)0;
+    int cnt = 0;
+    for (int j = a; j < e; ++j) {
+        const int lp = min(max(bv[j].loop, 0), mv.nloops - 1);   // in range for any stored value
+        const int nx = j + 1 < mv.loop_off[lp + 1] ? j + 1 : mv.loop_off[lp];
+        ColV<T> cn;
+        T rzn, sn;
+        load_vertex<T, 1, FAR>(bv[nx], qqx, qqy, pxs, pys, &pzs, f, cn, &rzn, &sn);
+        edge_step<T, 1, FAR>(cp, cn, &sp, &sn, &rzp, &rzn, &acc);
+        if (++cnt == 32) {   // FP32 partials flushed into the FP64 sum every 32 edges
+            *S += (double)acc;
+            acc = (T)0;
+            cnt = 0;
+        }
+        if (j + 1 < e) {
+            if (nx == j + 1) {
+                cp = cn;
+                rzp = rzn;
+                sp = sn;
+            } else {   // the next edge starts a new loop
+                load_vertex<T, 1, FAR>(bv[j + 1], qqx, qqy, pxs, pys, &pzs, f, cp, &rzp, &sp);
+            }
+        }
+    }
+    *S += (double)acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(kSplitThreads) void k_bdry_split(MeshView mv, const float* __restrict__ qx,
+                                                             const float* __restrict__ qy,
+                                                             const float* __restrict__ qz, long long qs, long long nq,
+                                                             const int* __restrict__ chi, T* __restrict__ w) {
+    __shared__ double red[kSplitThreads / 64];
+    const long long i = blockIdx.x;   // one point per workgroup
+    if (i >= nq) return;
+    const float px = qx[i * qs], py = qy[i * qs], pz = qz[i * qs];
+    const QPoint q = quantize_point(px, py, pz, mv.g);
+    const int nb = mv.loop_off[mv.nloops];
+    const int per = (nb + kSplitThreads - 1) / kSplitThreads;
+    const int a = (int)threadIdx.x * per, e = min(nb, a + per);
+    double S = 0.0;
+    if (q.inbox) {
+        split_run<T, false>(mv, a, e, q.x, q.y, (T)0, (T)0, (T)pz * (T)mv.g.scale, (T)1, &S);
+    } else {
+        const FarScale<T> fs = far_scale<T>(px, py, fabsf(pz), mv.g.scale);
+        split_run<T, true>(mv, a, e, 0, 0, (T)px * fs.scf, (T)py * fs.scf, (T)pz * fs.scf, fs.f, &S);
+    }
+    for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = S;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kSplitThreads / 64; ++k) t += red[k];
+        w[i] = (T)((double)chi[i] + t * kInv2Pi);
+    }
+}
+
+// The split path serves batches of at most 8,192 points on meshes with at least
+// 16 boundary edges per lane (GWN_SPLIT_BOUNDARY=0/1 overrides).
+bool want_split(const gwn_mesh_s* m, int64_t n) {
+    if (const char* e = std::getenv("GWN_SPLIT_BOUNDARY")) return std::atoi(e) != 0 && m->nb > 0;
+    return n <= 8192 && m->nb >= 16 * kSplitThreads;
+}
+
 // ---------------------------------------------------------------- grid (ray reuse)
 
 
@@ -272,7 +353,10 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
         e = hipGetLastError();
         if (perm) (void)hipFreeAsync(perm, st);
         if (e == hipSuccess) {
-            k_bdry_batch<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(mv, x, y, z, qs, n, chi + o, w + o);
+            if (want_split(m, n))
+                k_bdry_split<T><<<(unsigned)n, kSplitThreads, 0, st>>>(mv, x, y, z, qs, n, chi + o, w + o);
+            else
+                k_bdry_batch<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(mv, x, y, z, qs, n, chi + o, w + o);
             e = hipGetLastError();
         }
     }

@@ -364,3 +364,26 @@ def test_every_entry_point_on_empty_inputs(gwn):
     assert gwn.query_crossings(m, E)[0].numel() == 0
     assert gwn.query_grid(m, (0, 0, 0), (1, 1, 1), (0, 4, 4)).numel() == 0
     assert gwn.query_grid(m, (0, 0, 0), (1, 1, 1), (4, 4, 0)).numel() == 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_split_boundary_path(gwn, monkeypatch, prec):
+    # few points, many boundary edges: one workgroup per point with the edges
+    # split among its lanes; forced on tiny soups (runs shorter than a lane's
+    # share, loops ending inside a run) and taken by default on the torus soup
+    tol = TOL_FP32 if prec == "fp32" else TOL_FP64
+    rng = np.random.default_rng(91)
+    V = (np.round(rng.uniform(-1, 1, size=(90, 3)) * 16) / 16).astype(np.float32)
+    F = rng.integers(0, 90, size=(30, 3)).astype(np.int32)
+    Q = (np.round(rng.uniform(-1.2, 1.2, size=(700, 3)) * 16) / 16).astype(np.float32)
+    Q[-3:] = [[5, 5, 0], [-4, 0, 0.1], [0.1, 0.2, -9]]
+    monkeypatch.setenv("GWN_SPLIT_BOUNDARY", "1")
+    _, w, chi = _run_batch(gwn, V, F, Q, prec)
+    compare(w, chi, V, F, Q, tol, f"split-tiny-{prec}")
+    monkeypatch.delenv("GWN_SPLIT_BOUNDARY")
+    s, Q = W.config2(n_uniform=1500, n_near=1500)
+    m, w, chi = _run_batch(gwn, s.V, s.F, Q, prec)      # 3,000 points, 63k edges: split by default
+    compare(w, chi, s.V, s.F, Q, tol, f"split-torus-{prec}")
+    monkeypatch.setenv("GWN_SPLIT_BOUNDARY", "0")
+    w1 = gwn.query_batch(m, _dev(Q), prec=prec).cpu().numpy()
+    assert np.abs(w1 - w).max() < (1e-5 if prec == "fp32" else 1e-11)
