@@ -325,6 +325,17 @@ def bench_gradient(args):
     pairs = Q.shape[0] * info["nboundary"]
     print(f"[bench] gradient {Q.shape[0]} pts B={info['nboundary']}: {wall_g:.1f} ms ({pairs / ev_g * 1e3:.3e} "
           f"edge terms/s); w at the same points {wall_w:.1f} ms", file=sys.stderr, flush=True)
+    # a small batch (4,096 points): workgroup per point against lane per point
+    small = {}
+    Qs = Qd[:4096].contiguous()
+    gs = torch.empty((4096, 3), device="cuda", dtype=dt)
+    for mode, flag in (("split", "1"), ("per_lane", "0")):
+        os.environ["GWN_SPLIT_BOUNDARY"] = flag
+        small[mode + "_ms"], _ = _timed(lambda: gwn.query_gradient(mesh, Qs, prec=args.prec, out=gs, stream=st),
+                                        args.steps, args.warmup, st)
+    del os.environ["GWN_SPLIT_BOUNDARY"]
+    print(f"[bench] gradient 4096 points: split {small['split_ms']:.2f} ms, per-lane {small['per_lane_ms']:.2f} ms",
+          file=sys.stderr, flush=True)
     # the 512^3 grid on the 1.05M-triangle soup: column-shared gradient kernel
     soup4, grid = W.config4()
     m4 = gwn.Mesh(torch.from_numpy(soup4.V).cuda(), torch.from_numpy(soup4.F).cuda())
@@ -338,7 +349,7 @@ def bench_gradient(args):
     _emit("GWN gradients/sec, arbitrary points", Q.shape[0] / (wall_g / 1e3), "queries/s", args, wall_g,
           {"workload": f"torus soup ({info['nf']} tris, {info['nboundary']} boundary edges), 1M uniform + 1M "
                        f"near-surface points", "precision": args.prec, "pairs_per_s": pairs / (ev_g / 1e3),
-           "w_ms_same_points": wall_w, "grid_512_ms": ev_gg, "grid_512_pairs_per_s": pairs4 / (ev_gg / 1e3)},
+           "w_ms_same_points": wall_w, "small_batch_4096": small, "grid_512_ms": ev_gg, "grid_512_pairs_per_s": pairs4 / (ev_gg / 1e3)},
           extra={"roofline": _alu_roof(pairs, I_MIN_GRAD, ev_g, "k_grad_batch")} if args.prec == "fp32" else None,
           dtype="f32" if args.prec == "fp32" else "f64")
 

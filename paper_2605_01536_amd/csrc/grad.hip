@@ -161,6 +161,97 @@ __global__ __launch_bounds__(256) void k_grad_batch(MeshView mv, const float* __
     }
 }
 
+// Few points against many boundary edges: one workgroup per point, each lane a
+// contiguous run of boundary vertices (edge j leads to the next vertex of its
+// loop), reduced by wave shuffles and LDS in a fixed order.  FLIP as above.
+constexpr int kSplitThreads = 256;
+
+template <class T, bool FLIP>
+__device__ void grad_run(const MeshView& mv, int a, int e, T pxs, T pys, T pzs, T f, double* G) {
+    G[0] = G[1] = G[2] = 0.0;
+    if (a >= e) return;
+    const BVert* __restrict__ bv = mv.bverts;
+    GCol<T> cp = gcol<T>(bv[a], pxs, pys, f);
+    T up, sp;
+    gsamp<T, FLIP>(bv[a], cp, pzs, f, up, sp);
+    T acc[3] = {(T)0, (T)0, (T)0};
+    int cnt = 0;
+    for (int j = a; j < e; ++j) {
+        const int lp = min(max(bv[j].loop, 0), mv.nloops - 1);   // in range for any stored value
+        const int nx = j + 1 < mv.loop_off[lp + 1] ? j + 1 : mv.loop_off[lp];
+        const GCol<T> cn = gcol<T>(bv[nx], pxs, pys, f);
+        T un, sn;
+        gsamp<T, FLIP>(bv[nx], cn, pzs, f, un, sn);
+        const T N = cp.ry * cn.rx - cp.rx * cn.ry;
+        const T dot = cp.rx * cn.rx + cp.ry * cn.ry;
+        gedge<T>(cp, cn, N, dot, cn.ry - cp.ry, cp.rx - cn.rx, up, sp, un, sn, acc);
+        if (++cnt == 32) {
+            for (int c = 0; c < 3; ++c) {
+                G[c] += (double)acc[c];
+                acc[c] = (T)0;
+            }
+            cnt = 0;
+        }
+        if (j + 1 < e) {
+            if (nx == j + 1) {
+                cp = cn;
+                up = un;
+                sp = sn;
+            } else {   // the next edge starts a new loop
+                cp = gcol<T>(bv[j + 1], pxs, pys, f);
+                gsamp<T, FLIP>(bv[j + 1], cp, pzs, f, up, sp);
+            }
+        }
+    }
+    for (int c = 0; c < 3; ++c) G[c] += (double)acc[c];
+    if (FLIP) {
+        G[0] = -G[0];
+        G[1] = -G[1];
+    }
+}
+
+// sum of the workgroup's per-lane vectors, the same in every lane afterwards
+__device__ void block_sum3(double* G, double (*red)[3]) {
+    for (int c = 0; c < 3; ++c)
+        for (int o = 32; o > 0; o >>= 1) G[c] += __shfl_xor(G[c], o);
+    __syncthreads();   // red may still be read from a previous call
+    if ((threadIdx.x & 63) == 0)
+        for (int c = 0; c < 3; ++c) red[threadIdx.x >> 6][c] = G[c];
+    __syncthreads();
+    for (int c = 0; c < 3; ++c) {
+        double t = 0.0;
+        for (int k = 0; k < kSplitThreads / 64; ++k) t += red[k][c];
+        G[c] = t;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kSplitThreads) void k_grad_split(MeshView mv, const float* __restrict__ qx,
+                                                             const float* __restrict__ qy,
+                                                             const float* __restrict__ qz, long long qs, long long nq,
+                                                             int axis, T* __restrict__ g) {
+    __shared__ double red[kSplitThreads / 64][3];
+    const long long i = blockIdx.x;   // one point per workgroup
+    if (i >= nq) return;
+    const float px = qx[i * qs], py = qy[i * qs], pz = qz[i * qs];
+    const FarScale<T> fs = far_scale<T>(px, py, fabsf(pz), mv.g.scale);
+    const T pxs = (T)px * fs.scf, pys = (T)py * fs.scf, pzs = (T)pz * fs.scf;
+    const int nb = mv.loop_off[mv.nloops];
+    const int per = (nb + kSplitThreads - 1) / kSplitThreads;
+    const int a = (int)threadIdx.x * per, e = min(nb, a + per);
+    double G[3];
+    grad_run<T, false>(mv, a, e, pxs, pys, pzs, fs.f, G);
+    block_sum3(G, red);
+    if (!finite3(G)) {   // uniform: every lane holds the same sum
+        grad_run<T, true>(mv, a, e, pxs, pys, pzs, fs.f, G);
+        block_sum3(G, red);
+    }
+    if (threadIdx.x == 0) {
+        const double f = kInv2Pi * (double)fs.scf;
+        for (int c = 0; c < 3; ++c) g[3 * i + (c + axis) % 3] = (T)(G[c] * f);
+    }
+}
+
 // Gradient on a grid: one wave per (column, z-chunk) as for w, ZB samples per
 // lane sharing the column's x/y terms.  A column through a boundary vertex
 // makes the samples below it 0/0 on the +z axis; if any lane has such a sample,
@@ -246,8 +337,18 @@ gwn_status query_gradient(const gwn_mesh_s* m, const float* qx, const float* qy,
         const int64_t n = std::min<int64_t>(chunk, nq - o);
         const unsigned blocks = (unsigned)((n + 255) / 256);
         const float *x = qx + o * qs, *y = qy + o * qs, *z = qz + o * qs;
-        if (prec == GWN_PREC_FP64) k_grad_batch<double><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, m->axis, (double*)g + 3 * o);
-        else k_grad_batch<float><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, m->axis, (float*)g + 3 * o);
+        if (want_split(m, n)) {   // few points, many edges: a workgroup per point
+            if (prec == GWN_PREC_FP64)
+                k_grad_split<double><<<(unsigned)n, kSplitThreads, 0, st>>>(mv, x, y, z, qs, n, m->axis,
+                                                                             (double*)g + 3 * o);
+            else
+                k_grad_split<float><<<(unsigned)n, kSplitThreads, 0, st>>>(mv, x, y, z, qs, n, m->axis,
+                                                                            (float*)g + 3 * o);
+        } else if (prec == GWN_PREC_FP64) {
+            k_grad_batch<double><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, m->axis, (double*)g + 3 * o);
+        } else {
+            k_grad_batch<float><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, m->axis, (float*)g + 3 * o);
+        }
         GWN_HIP_TRY(hipGetLastError());
     }
     return GWN_OK;

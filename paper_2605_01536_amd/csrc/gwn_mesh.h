@@ -62,6 +62,12 @@ gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* s
 // GWN_MAX_LAUNCH_QUERIES (a positive multiple of 256) lowers it, for tests.
 int64_t max_launch_queries();
 
+// Few points against many boundary edges take a workgroup per point with the
+// edges split among its lanes: batches of at most 8,192 points on meshes with at
+// least 16 boundary edges per lane of a 256-lane workgroup.
+// GWN_SPLIT_BOUNDARY=0/1 overrides.
+bool want_split(const gwn_mesh_s* m, int64_t n);
+
 // Morton order of the points' quantised x, y for the crossing traversal (perm is
 // stream-ordered device memory the caller frees with hipFreeAsync).
 // GWN_ORDER_QUERIES=0/1 overrides the size heuristic.

@@ -212,13 +212,6 @@ __global__ __launch_bounds__(kSplitThreads) void k_bdry_split(MeshView mv, const
     }
 }
 
-// The split path serves batches of at most 8,192 points on meshes with at least
-// 16 boundary edges per lane (GWN_SPLIT_BOUNDARY=0/1 overrides).
-bool want_split(const gwn_mesh_s* m, int64_t n) {
-    if (const char* e = std::getenv("GWN_SPLIT_BOUNDARY")) return std::atoi(e) != 0 && m->nb > 0;
-    return n <= 8192 && m->nb >= 16 * kSplitThreads;
-}
-
 // ---------------------------------------------------------------- grid (ray reuse)
 
 
@@ -428,6 +421,11 @@ gwn_status query_crossings(const gwn_mesh_s* m, const float* qx, const float* qy
         GWN_HIP_TRY(e);
     }
     return GWN_OK;
+}
+
+bool want_split(const gwn_mesh_s* m, int64_t n) {
+    if (const char* e = std::getenv("GWN_SPLIT_BOUNDARY")) return std::atoi(e) != 0 && m->nb > 0;
+    return n <= 8192 && m->nb >= 16 * 256;
 }
 
 int64_t max_launch_queries() {

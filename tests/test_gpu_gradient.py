@@ -138,3 +138,29 @@ def test_grid_gradient_columns_through_vertices(gwn):
     mask = off_surface_mask(V, F, P)
     err = np.abs(gg - ref).max(1)
     assert (err[mask] <= REL["fp64"] * np.maximum(1.0, l1[mask])).all()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_gradient_split_boundary(gwn, monkeypatch, prec):
+    # the workgroup-per-point path: forced on small soups (loops ending inside a
+    # lane's run, runs shorter than a lane's share, queries below a boundary
+    # vertex that take the mirrored axis), taken by default on the torus subset,
+    # and equal to the per-lane path within the same bound
+    monkeypatch.setenv("GWN_SPLIT_BOUNDARY", "1")
+    s = W.opened_spheres(seed=62, n_surf=3, tris_per_surf=300)
+    Q = np.random.default_rng(4).uniform(-1.3, 1.3, size=(900, 3)).astype(np.float32)
+    _check(gwn, s.V, s.F, Q, prec, f"split-spheres-{prec}")
+    V = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1]], np.float32)
+    F = np.array([[0, 1, 2]], np.int32)
+    Q = np.array([[0, 0, 0], [0.2, 0.2, 0.2], [3, -2, 1], [0, 0, -5], [1, 0, -0.5]], np.float32)
+    g, _, _ = _check(gwn, V, F, Q, prec, f"split-octant-{prec}")
+    assert np.isfinite(g).all()
+    monkeypatch.delenv("GWN_SPLIT_BOUNDARY")
+    s, Q = W.config2(n_uniform=1000, n_near=1000)
+    m = gwn.Mesh(_dev(s.V), _dev(s.F))
+    g, ref, mask = _check(gwn, s.V, s.F, Q, prec, f"split-torus-{prec}", m=m)
+    monkeypatch.setenv("GWN_SPLIT_BOUNDARY", "0")
+    g1 = gwn.query_gradient(m, _dev(Q), prec=prec).cpu().numpy().astype(np.float64)
+    _, l1 = O.gradient(s.V, s.F, Q, with_l1=True)
+    d = np.abs(g1 - g).max(1)
+    assert (d[mask] <= 2 * REL[prec] * np.maximum(1.0, l1[mask])).all()
