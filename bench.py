@@ -39,13 +39,18 @@ PEAK_SLOTS = N_CU * SIMD_PER_CU * LANES_PER_CLK * CLOCK_HZ
 TRANS_SLOTS = 3
 
 # Minimal VALU slots per (query, boundary edge) pair on the grid path, with x/y
-# work shared by the samples of a column (one boundary vertex per edge):
-#   per sample and vertex: r_z (1), l^2 (1), sqrt, l+|r_z| (1), rcp, rho^2*rcp (1),
-#                          compare + select (2)                    = 6 + 2 trans
-#   per sample and edge:   D (1), fast-path test (1), rcp, N*rcp (1), t^2 (1),
-#                          7 polynomial FMAs, t*x (1), final FMA (1), accumulate (1)
-#                                                                  = 14 + 1 trans
-I_MIN_GRID = 6 + 14 + 3 * TRANS_SLOTS      # = 29
+# work (N, N1 N2, the x/y dot) shared by the samples of a column and consecutive
+# edges summed in pairs by one arctangent (one boundary vertex per edge):
+#   per sample and vertex:    r_z (1), l^2 (1), sqrt, l+|r_z| (1), rcp, rho^2*rcp (1),
+#                             compare + select (2)                 = 6 + 2 trans
+#   per sample and edge:      D (1), fast-path test (1)            = 2
+#   per sample and edge pair: Re (1), Im (2), rcp, Im*rcp (1), t^2 (1), 3 polynomial
+#                             FMAs, t*x (1), final FMA (1), accumulate (1)
+#                                                                  = 11 + 1 trans
+I_MIN_GRID = 6 + 2 * TRANS_SLOTS + 2 + (11 + TRANS_SLOTS) / 2      # = 21
+# The single-edge form (reciprocal and degree-7 arctangent per edge) that the
+# per-lane kernels use: 6 + 14 + 3 transcendentals = 29.
+I_MIN_EDGE = 6 + 14 + 3 * TRANS_SLOTS      # = 29
 
 # The all-FP64 grid path against the same issue ceiling, with FP64 add/mul/fma
 # and compares at 1.5 FP32 slots and v_rcp_f64 / v_rsq_f64 at 5.4 (measured by
@@ -54,13 +59,13 @@ I_MIN_GRID = 6 + 14 + 3 * TRANS_SLOTS      # = 29
 # double result needs is part of the minimum:
 #   per sample and vertex: r_z, l^2 (2); sqrt = rsq + 7; l+|r_z| (1); rcp = rcp + 4;
 #                          rho^2*rcp (1); compare (1)          = 16 FP64 + 2 trans + select (2)
-#   per sample and edge:   D, fast-path test (2); rcp + 4; N*rcp, t^2 (2);
-#                          9 polynomial FMAs; t*x, final FMA, accumulate (3)
-#                                                              = 20 FP64 + 1 trans
+#   per sample and edge:   D, fast-path test (2)                       = 2 FP64
+#   per sample and pair:   Re, Im (3); rcp + 4; Im*rcp, t^2 (2); 9 polynomial
+#                          FMAs; t*x, final FMA, accumulate (3)         = 21 FP64 + 1 trans
 # Arbitrary points (one query per lane): the x/y quantities are no longer shared
 # by a column, adding per vertex dx, dy (2), their conversion (2), rho^2 (2) and
 # per edge N (2), x/y dot (2):
-I_MIN_BATCH = I_MIN_GRID + 10              # = 39
+I_MIN_BATCH = I_MIN_EDGE + 10              # = 39
 # The gradient (Supp. Alg. 3) per pair: per vertex r (3), rho^2 (2), l^2 (1), sqrt,
 # 1/l, l+|r_z| (1), rcp, rho^2*rcp (1), compare + select (2) = 10 + 3 trans; per
 # edge l0 l1 (1), n (3), d (3), c0, c1 (2), grad D (6), n^2+d^2 (2), rcp, scale
@@ -75,15 +80,15 @@ PEAK_BF16 = 2.5e15
 # features at ~20, and the 128-term output dot product with bf16 widening (256)
 NET_VALU_SLOTS = 512 * 20.5 + 32 * 21 + 256     # = 11,424 per point
 # HBM bytes moved per k_grid<float, 8> launch on the default workload (512^3 grid,
-# 1.05M-triangle soup), from two rocprofv3 --pmc passes over this command:
-# FETCH_SIZE 231,943.5 KiB and WRITE_SIZE 524,288 KiB per dispatch, scaled by
-# what the same counters read for a plain 1 GiB device copy (bench.py
-# --copy-probe: FETCH_SIZE shows 524,308.5 KiB -> x2.000, WRITE_SIZE
-# 1,048,576 KiB -> x1.000).  Measured on the kernel as it stands; re-take the
-# counters after any change to k_grid or the workload.
-K_GRID_TRAFFIC_BYTES = (231943.5 * 2.0 + 524288.0 * 1.0) * 1024
+# 1.05M-triangle soup), from two rocprofv3 --pmc passes over this command
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the same
+# counters read for a plain 1 GiB device copy (bench.py --copy-probe: FETCH_SIZE
+# shows half the bytes -> x2.000, WRITE_SIZE all of them -> x1.000).  None until
+# the counters are taken on the kernel as it stands; re-take them after any
+# change to k_grid or the workload.
+K_GRID_TRAFFIC_BYTES = None
 FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
-I_MIN_GRID_FP64 = (16 + 20) * FP64_OP_SLOTS + 3 * FP64_TRANS_SLOTS + 2   # = 72.2
+I_MIN_GRID_FP64 = (16 + 2 + 21 / 2) * FP64_OP_SLOTS + 2.5 * FP64_TRANS_SLOTS + 2   # = 58.25
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -12,6 +12,7 @@ i.e. a weighted minimax fit of h with weight x / g(x).  Usage:
 
     python gen_atan_poly.py [deg]            # float32 table, coefficients highest first
     python gen_atan_poly.py deg double       # float64 table for |t| <= tan(pi/8)
+    python gen_atan_poly.py deg pair         # float32 table for |t| <= tan(pi/8)
 
 The printed table is pasted into query.hip (kAtanQ); the script also reports
 the fitted error and the error of the same Horner evaluation in float32.
@@ -132,16 +133,18 @@ def main():
         print(f"// degree {deg} in x = t^2 on |t| <= tan(pi/8); max |Q - h| {emax:.3e}; float64 Horner: max rel {rel.max():.3e}")
         print(f"constexpr double kAtanQd[{deg + 1}] = {{" + ", ".join(repr(float(c)) for c in hi_first) + "};")
         return
-    coef, emax = remez(deg)
+    pair = len(sys.argv) > 2 and sys.argv[2] == "pair"
+    tmax = np.sqrt(3.0 - 2.0 * np.sqrt(2.0)) if pair else 1.0
+    coef, emax = remez(deg, xmax=tmax * tmax)
     hi_first = coef[::-1]
-    t = np.linspace(0.0, 1.0, 400001)[1:]
+    t = np.linspace(0.0, tmax, 400001)[1:]
     ref = np.arctan(t.astype(np.float32).astype(np.float64))
     f32 = horner_f32([np.float32(c) for c in hi_first], t.astype(np.float32)).astype(np.float64)
     rel = np.abs(f32 - ref) / ref
     print(f"// degree {deg} in x = t^2; minimax relative error {emax:.3e}; "
           f"float32 Horner: max rel {rel.max():.3e}, mean rel {np.mean(rel):.3e}, "
           f"mean signed rel {np.mean((f32 - ref) / ref):.3e}")
-    print("constexpr float kAtanQ[] = {" + ", ".join(f"{np.float32(c)!r}f".replace("np.float32(", "").replace(")", "")
+    print(f"constexpr float {'kAtanQp' if pair else 'kAtanQ'}[] = {{" + ", ".join(f"{np.float32(c)!r}f".replace("np.float32(", "").replace(")", "")
                                                  for c in hi_first) + "};")
 
 

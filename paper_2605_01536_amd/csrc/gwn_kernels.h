@@ -43,6 +43,10 @@ constexpr double kAtanQd[10] = {0.02277211404923737,  -0.044850509519182694, 0.0
                                 -0.06649717364503759, 0.0769106629901103,    -0.09090853283150221,
                                 0.11111109664858296,  -0.14285714266729652,  0.19999999999905727,
                                 -0.33333333333333276};
+// The same form for |t| <= tan(pi/8) (the edge-pair path): Q of degree 3 by the
+// Remez exchange (gen_atan_poly.py 3 pair: 2.1e-8 in exact arithmetic, 8.0e-8
+// max when evaluated in float32).
+constexpr float kAtanQp[4] = {0.08053723f, -0.1387768f, 0.1997771f, -0.3333295f};
 constexpr float kPi = 3.14159265358979f;
 constexpr float kPi2 = 1.57079632679490f;
 
@@ -51,6 +55,14 @@ __device__ __forceinline__ float atan_unit(float t) {
     float q = kAtanQ[0];
 #pragma unroll
     for (int k = 1; k < 8; ++k) q = fmaf(q, x, kAtanQ[k]);
+    return fmaf(t * x, q, t);
+}
+
+__device__ __forceinline__ float atan_pair(float t) {
+    const float x = t * t;
+    float q = kAtanQp[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) q = fmaf(q, x, kAtanQp[k]);
     return fmaf(t * x, q, t);
 }
 
@@ -141,7 +153,26 @@ __device__ __forceinline__ FarScale<T> far_scale(float px, float py, float pz_ab
     return s;
 }
 
-template <class T, bool FAR>
+// Edge pairs.  Where ZB samples share one column's x/y (the grid kernel, inside
+// the fixed-point box), two consecutive edges with |N| < tan(pi/16) D each are
+// summed by one arctangent: (D1 + i N1)(D2 + i N2) has argument
+// atan(N1/D1) + atan(N2/D2) in (-pi/8, pi/8), so its real part is positive and
+// atan(Im/Re) needs no branch fix-up and only the short-range polynomial.
+// N1 N2 is the column's, so the product costs three operations per sample
+// instead of a second reciprocal and arctangent.  FP32 offsets on that path are
+// in units of 2^16 cells (an exact scale that keeps products of two D below
+// 2^68), and D <= 2^-50 of those units takes the single-edge path (products
+// stay normal).
+template <class T, int ZB, bool FAR>
+struct EdgePairs {
+    static constexpr bool on = !FAR && ZB > 1;
+    static constexpr bool f32 = std::is_same<T, float>::value;
+    static constexpr float kUnit = on && f32 ? 0x1p-16f : 1.0f;   // cell units per offset unit
+    static constexpr float kInvTan = 5.02734f;                     // 1 / tan(pi/16), rounded up
+    static constexpr float kMinD = 0x1p-50f;
+};
+
+template <class T, int ZB, bool FAR>
 __device__ __forceinline__ ColV<T> col_vtx(const BVert& b, int qqx, int qqy, T pxs, T pys, T f) {
     ColV<T> c;
     c.dx = b.qx - qqx;
@@ -150,8 +181,8 @@ __device__ __forceinline__ ColV<T> col_vtx(const BVert& b, int qqx, int qqy, T p
         c.rx = fma((T)b.x, f, -pxs);
         c.ry = fma((T)b.y, f, -pys);
     } else {
-        c.rx = (T)c.dx;
-        c.ry = (T)c.dy;
+        c.rx = (T)c.dx * (T)EdgePairs<T, ZB, FAR>::kUnit;
+        c.ry = (T)c.dy * (T)EdgePairs<T, ZB, FAR>::kUnit;
     }
     c.rho2 = c.rx * c.rx + c.ry * c.ry;
     return c;
@@ -193,21 +224,16 @@ __device__ __forceinline__ T edge_slow(const ColV<T>& a, const ColV<T>& b, T rza
     return Arith<T>::atan2(N, D);
 }
 
-// One boundary edge for ZB samples.  Fast path (wave-uniform): every sample has
-// |N| < kFast D, so atan2(N, D) = atan(N/D) with no branch fix-up.
+// One boundary edge for ZB samples given N and D.  Fast path (wave-uniform):
+// every sample has |N| < kFast D, so atan2(N, D) = atan(N/D) with no branch
+// fix-up.
 template <class T, int ZB, bool FAR>
-__device__ __forceinline__ void edge_step(const ColV<T>& a, const ColV<T>& b, const T* sa, const T* sb, const T* rza,
-                                          const T* rzb, T* acc) {
-    const T N = a.ry * b.rx - a.rx * b.ry;
-    const T dot = a.rx * b.rx + a.ry * b.ry;
+__device__ __forceinline__ void edge_finish(const ColV<T>& a, const ColV<T>& b, const T* rza, const T* rzb, T N,
+                                            const T* D, T* acc) {
     const T aN = fabs(N);
-    T D[ZB];
     bool slow = false;
 #pragma unroll
-    for (int r = 0; r < ZB; ++r) {
-        D[r] = sa[r] * sb[r] + dot;
-        slow |= !(aN < Arith<T>::kFast * D[r]);
-    }
+    for (int r = 0; r < ZB; ++r) slow |= !(aN < Arith<T>::kFast * D[r]);
     if (__builtin_amdgcn_ballot_w64(slow) == 0ull) {
 #pragma unroll
         for (int r = 0; r < ZB; ++r) acc[r] += Arith<T>::atan_small(N * Arith<T>::rcp(D[r]));
@@ -218,27 +244,83 @@ __device__ __forceinline__ void edge_step(const ColV<T>& a, const ColV<T>& b, co
 }
 
 template <class T, int ZB, bool FAR>
+__device__ __forceinline__ void edge_step(const ColV<T>& a, const ColV<T>& b, const T* sa, const T* sb, const T* rza,
+                                          const T* rzb, T* acc) {
+    const T N = a.ry * b.rx - a.rx * b.ry;
+    const T dot = a.rx * b.rx + a.ry * b.ry;
+    T D[ZB];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) D[r] = sa[r] * sb[r] + dot;
+    edge_finish<T, ZB, FAR>(a, b, rza, rzb, N, D, acc);
+}
+
+// Edges a -> b -> c for ZB samples: as one pair when every sample allows it
+// (wave-uniform), else one by one.
+template <class T, int ZB, bool FAR>
+__device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, const ColV<T>& c, const T* sa,
+                                          const T* sb, const T* sc, const T* rza, const T* rzb, const T* rzc, T* acc) {
+    using P = EdgePairs<T, ZB, FAR>;
+    if constexpr (!P::on) {
+        edge_step<T, ZB, FAR>(a, b, sa, sb, rza, rzb, acc);
+        edge_step<T, ZB, FAR>(b, c, sb, sc, rzb, rzc, acc);
+    } else {
+        const T N1 = a.ry * b.rx - a.rx * b.ry, dot1 = a.rx * b.rx + a.ry * b.ry;
+        const T N2 = b.ry * c.rx - b.rx * c.ry, dot2 = b.rx * c.rx + b.ry * c.ry;
+        const T m1 = fmax(fabs(N1) * (T)P::kInvTan, (T)P::kMinD);
+        const T m2 = fmax(fabs(N2) * (T)P::kInvTan, (T)P::kMinD);
+        T D1[ZB], D2[ZB];
+        bool slow = false;
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) {
+            D1[r] = fma(sa[r], sb[r], dot1);
+            D2[r] = fma(sb[r], sc[r], dot2);
+            slow |= !(m1 < D1[r]) | !(m2 < D2[r]);
+        }
+        if (__builtin_amdgcn_ballot_w64(slow) == 0ull) {
+            const T N12 = N1 * N2;
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) {
+                const T re = fma(D1[r], D2[r], -N12);
+                const T im = fma(D1[r], N2, N1 * D2[r]);
+                const T t = im * Arith<T>::rcp(re);
+                if constexpr (P::f32) acc[r] += atan_pair(t);
+                else acc[r] += Arith<T>::atan_small(t);   // |t| < tan(pi/8)
+            }
+        } else {
+            edge_finish<T, ZB, FAR>(a, b, rza, rzb, N1, D1, acc);
+            edge_finish<T, ZB, FAR>(b, c, rzb, rzc, N2, D2, acc);
+        }
+    }
+}
+
+// pzs: the samples' z in offset units (cells times EdgePairs' kUnit inside the box)
+template <class T, int ZB, bool FAR>
 __device__ __forceinline__ void load_vertex(const BVert& b, int qqx, int qqy, T pxs, T pys, const T* pzs, T f,
                                             ColV<T>& c, T* rz, T* sv) {
-    c = col_vtx<T, FAR>(b, qqx, qqy, pxs, pys, f);
+    c = col_vtx<T, ZB, FAR>(b, qqx, qqy, pxs, pys, f);
+    constexpr T u = (T)EdgePairs<T, ZB, FAR>::kUnit;
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {
-        rz[r] = FAR ? fma((T)b.z, f, -pzs[r]) : (T)b.z - pzs[r];
+        rz[r] = FAR ? fma((T)b.z, f, -pzs[r]) : (u == (T)1 ? (T)b.z - pzs[r] : fma((T)b.z, u, -pzs[r]));
         sv[r] = samp_s<T>(c.rho2, rz[r]);
     }
 }
 
 // Boundary sum S = sum of atan2 over the chained loops for ZB samples sharing one
-// (x, y).  FP32 partials are flushed into the FP64 sum every 32 edges.
+// (x, y).  FP32 partials are flushed into the FP64 sum every 32 edges.  pzs in
+// cells inside the box (FAR: in units of 2^e cells).
 template <class T, int ZB, bool FAR>
 __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int qqy, T pxs, T pys, const T* pzs,
                                                double* S, T f = (T)1) {
     const BVert* __restrict__ bv = mv.bverts;
+    T pz[ZB];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) pz[r] = FAR ? pzs[r] : pzs[r] * (T)EdgePairs<T, ZB, FAR>::kUnit;
     for (int l = 0; l < mv.nloops; ++l) {
         const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
-        ColV<T> cf, cp;
-        T rzf[ZB], sf[ZB], rzp[ZB], sp[ZB];
-        load_vertex<T, ZB, FAR>(bv[b0], qqx, qqy, pxs, pys, pzs, f, cf, rzf, sf);
+        ColV<T> cf, cp, cq, cr;
+        T rzf[ZB], sf[ZB], rzp[ZB], sp[ZB], rzq[ZB], sq[ZB], rzr[ZB], sr[ZB];
+        load_vertex<T, ZB, FAR>(bv[b0], qqx, qqy, pxs, pys, pz, f, cf, rzf, sf);
         cp = cf;
 #pragma unroll
         for (int r = 0; r < ZB; ++r) {
@@ -251,26 +333,36 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
             T acc[ZB];
 #pragma unroll
             for (int r = 0; r < ZB; ++r) acc[r] = (T)0;
-            // two vertices per trip: the loop-carried vertex alternates between
-            // two register sets instead of being copied every edge
-            for (; j + 1 < je; j += 2) {
-                ColV<T> c1;
-                T rz1[ZB], s1[ZB];
-                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pzs, f, c1, rz1, s1);
-                edge_step<T, ZB, FAR>(cp, c1, sp, s1, rzp, rz1, acc);
-                load_vertex<T, ZB, FAR>(bv[j + 1], qqx, qqy, pxs, pys, pzs, f, cp, rzp, sp);
-                edge_step<T, ZB, FAR>(c1, cp, s1, sp, rz1, rzp, acc);
+            // four vertices (two edge pairs) per trip: p-q-r, then r-q-p with q and p
+            // reloaded, so the loop-carried vertex ends in the set it started in
+            for (; j + 3 < je; j += 4) {
+                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq);
+                load_vertex<T, ZB, FAR>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, rzr, sr);
+                edge_pair<T, ZB, FAR>(cp, cq, cr, sp, sq, sr, rzp, rzq, rzr, acc);
+                load_vertex<T, ZB, FAR>(bv[j + 2], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq);
+                load_vertex<T, ZB, FAR>(bv[j + 3], qqx, qqy, pxs, pys, pz, f, cp, rzp, sp);
+                edge_pair<T, ZB, FAR>(cr, cq, cp, sr, sq, sp, rzr, rzq, rzp, acc);
             }
-            if (j < je) {
-                ColV<T> cc;
-                T rzc[ZB], sc[ZB];
-                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pzs, f, cc, rzc, sc);
-                edge_step<T, ZB, FAR>(cp, cc, sp, sc, rzp, rzc, acc);
-                cp = cc;
+            if (j + 1 < je) {
+                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq);
+                load_vertex<T, ZB, FAR>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, rzr, sr);
+                edge_pair<T, ZB, FAR>(cp, cq, cr, sp, sq, sr, rzp, rzq, rzr, acc);
+                cp = cr;
 #pragma unroll
                 for (int r = 0; r < ZB; ++r) {
-                    rzp[r] = rzc[r];
-                    sp[r] = sc[r];
+                    rzp[r] = rzr[r];
+                    sp[r] = sr[r];
+                }
+                j += 2;
+            }
+            if (j < je) {
+                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq);
+                edge_step<T, ZB, FAR>(cp, cq, sp, sq, rzp, rzq, acc);
+                cp = cq;
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) {
+                    rzp[r] = rzq[r];
+                    sp[r] = sq[r];
                 }
                 ++j;
             }

@@ -144,6 +144,31 @@ def test_grid_far_columns_and_ray_hits_vertices(gwn):
     compare(w.cpu().numpy(), chi.cpu().numpy(), V, F, P, TOL_FP32, "grid-far")
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("zb", ["1", "2", "4", "8"])
+def test_grid_columns_through_boundary_vertices(gwn, monkeypatch, prec, zb):
+    # lattice soups on a grid whose columns pass exactly through boundary vertices
+    # and along edges (N = 0, the exact atan2 branch in the middle of an edge
+    # pair), loops of many lengths (every tail of the pair loop), for each number
+    # of samples per lane; against the oracle and against the per-point kernel
+    monkeypatch.setenv("GWN_GRID_SAMPLES_PER_LANE", zb)
+    g = W.GridSpec(origin=(-1.0625, -1.0625, -1.3), spacing=(0.125, 0.125, 2.6 / 130), dims=(18, 18, 130))
+    P = W.grid_points(g)
+    for seed in (17, 18):
+        rng = np.random.default_rng(seed)
+        V = (rng.integers(-8, 9, size=(120, 3)) / 8).astype(np.float32)
+        F = rng.integers(0, 120, size=(50 + 13 * (seed - 17), 3)).astype(np.int32)
+        m = gwn.Mesh(_dev(V), _dev(F))
+        assert m.info()["nloops"] >= 3
+        w, chi = gwn.query_grid(m, g.origin, g.spacing, g.dims, prec=prec, want_chi=True)
+        compare(w.cpu().numpy(), chi.cpu().numpy(), V, F, P, TOL_FP32 if prec == "fp32" else TOL_FP64,
+                f"lattice{seed}-zb{zb}-{prec}")
+        wb, cb = gwn.query_batch(m, _dev(P), prec=prec, want_chi=True)
+        assert torch.equal(cb, chi)
+        d = (wb.double() - w.double()).abs().cpu().numpy()
+        assert np.median(d) < (1e-7 if prec == "fp32" else 1e-14)
+
+
 def test_edge_cases(gwn):
     # nq = 0 is a no-op
     m = gwn.Mesh(_dev(OCT_V), _dev(OCT_F))
