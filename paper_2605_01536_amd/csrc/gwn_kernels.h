@@ -153,19 +153,32 @@ __device__ __forceinline__ FarScale<T> far_scale(float px, float py, float pz_ab
     return s;
 }
 
-// Edge pairs.  Where ZB samples share one column's x/y (the grid kernel, inside
-// the fixed-point box), two consecutive edges with |N| < tan(pi/16) D each are
-// summed by one arctangent: (D1 + i N1)(D2 + i N2) has argument
-// atan(N1/D1) + atan(N2/D2) in (-pi/8, pi/8), so its real part is positive and
-// atan(Im/Re) needs no branch fix-up and only the short-range polynomial.
-// N1 N2 is the column's, so the product costs three operations per sample
-// instead of a second reciprocal and arctangent.  FP32 offsets on that path are
-// in units of 2^16 cells (an exact scale that keeps products of two D below
-// 2^68), and D <= 2^-50 of those units takes the single-edge path (products
-// stay normal).
+// value of x in lane l (uniform result)
+template <class T>
+__device__ __forceinline__ T wave_lane(T x, int l) {
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+    } else {
+        const long long v = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+        const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    }
+}
+
+// Edge pairs.  Inside the fixed-point box two consecutive edges with
+// |N| < tan(pi/16) D each (a wave-uniform test) are summed by one arctangent:
+// (D1 + i N1)(D2 + i N2) has argument atan(N1/D1) + atan(N2/D2) in
+// (-pi/8, pi/8), so its real part is positive and atan(Im/Re) needs no branch
+// fix-up and only the short-range polynomial.  Where ZB samples share one
+// column's x/y (grids), N1 N2 is the column's and the product costs three
+// operations per sample instead of a second reciprocal and arctangent.  FP32
+// offsets are in units of 2^16 cells (an exact scale that keeps products of two
+// D below 2^68), and D <= 2^-50 of those units takes the single-edge path
+// (products stay normal).
 template <class T, int ZB, bool FAR>
 struct EdgePairs {
-    static constexpr bool on = !FAR && ZB > 1;
+    static constexpr bool on = !FAR;
     static constexpr bool f32 = std::is_same<T, float>::value;
     static constexpr float kUnit = on && f32 ? 0x1p-16f : 1.0f;   // cell units per offset unit
     static constexpr float kInvTan = 5.02734f;                     // 1 / tan(pi/16), rounded up
@@ -254,11 +267,24 @@ __device__ __forceinline__ void edge_step(const ColV<T>& a, const ColV<T>& b, co
     edge_finish<T, ZB, FAR>(a, b, rza, rzb, N, D, acc);
 }
 
-// Edges a -> b -> c for ZB samples: as one pair when every sample allows it
-// (wave-uniform), else one by one.
-template <class T, int ZB, bool FAR>
+// Inside the box x and y are within 2^31 cells of every boundary vertex but z
+// is not bounded: a sample more than 2^40 cells above or below the box takes
+// single edges (its offsets may even be infinite in FP32, which the single-edge
+// form turns into the right limit), so an edge pair's product stays below 2^101
+// in its units.
+__device__ __forceinline__ bool near_z(float pz, const QGrid& g) {
+    return fabs(((double)pz - g.lo[2]) * g.scale) <= 0x1p40;
+}
+
+// Edges a -> b -> c for ZB samples: as one pair where allowed, else one by one.
+// COL (a grid column): the choice is wave-uniform.  Otherwise each lane chooses
+// for its own point, so a point's result does not depend on which points share
+// its wave (the single-edge fast and exact forms agree bit for bit where
+// |N| < D, so their wave-uniform choice never mattered).
+template <class T, int ZB, bool FAR, bool COL>
 __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, const ColV<T>& c, const T* sa,
-                                          const T* sb, const T* sc, const T* rza, const T* rzb, const T* rzc, T* acc) {
+                                          const T* sb, const T* sc, const T* rza, const T* rzb, const T* rzc, T* acc,
+                                          bool pairs) {
     using P = EdgePairs<T, ZB, FAR>;
     if constexpr (!P::on) {
         edge_step<T, ZB, FAR>(a, b, sa, sb, rza, rzb, acc);
@@ -269,14 +295,15 @@ __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, co
         const T m1 = fmax(fabs(N1) * (T)P::kInvTan, (T)P::kMinD);
         const T m2 = fmax(fabs(N2) * (T)P::kInvTan, (T)P::kMinD);
         T D1[ZB], D2[ZB];
-        bool slow = false;
+        bool slow = !pairs;
 #pragma unroll
         for (int r = 0; r < ZB; ++r) {
             D1[r] = fma(sa[r], sb[r], dot1);
             D2[r] = fma(sb[r], sc[r], dot2);
             slow |= !(m1 < D1[r]) | !(m2 < D2[r]);
         }
-        if (__builtin_amdgcn_ballot_w64(slow) == 0ull) {
+        const bool pair = COL ? __builtin_amdgcn_ballot_w64(slow) == 0ull : !slow;
+        if (pair) {
             const T N12 = N1 * N2;
 #pragma unroll
             for (int r = 0; r < ZB; ++r) {
@@ -293,34 +320,98 @@ __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, co
     }
 }
 
+// s for blocks 0..R-1 by the two-sided form, for the others as l + |r_z|
+template <class T, int ZB, int R>
+__device__ __forceinline__ void s_blocks(const T* rz, const T* t, T rho2, T* sv) {
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) sv[r] = r < R ? (rz[r] > (T)0 ? rho2 * Arith<T>::rcp(t[r]) : t[r]) : t[r];
+}
+
+template <class T, int ZB>
+__device__ __forceinline__ void s_prefix(int R, const T* rz, const T* t, T rho2, T* sv) {
+    switch (R) {
+        case 0: s_blocks<T, ZB, 0>(rz, t, rho2, sv); break;
+        case 1: s_blocks<T, ZB, (1 < ZB ? 1 : ZB)>(rz, t, rho2, sv); break;
+        case 2: s_blocks<T, ZB, (2 < ZB ? 2 : ZB)>(rz, t, rho2, sv); break;
+        case 3: s_blocks<T, ZB, (3 < ZB ? 3 : ZB)>(rz, t, rho2, sv); break;
+        case 4: s_blocks<T, ZB, (4 < ZB ? 4 : ZB)>(rz, t, rho2, sv); break;
+        case 5: s_blocks<T, ZB, (5 < ZB ? 5 : ZB)>(rz, t, rho2, sv); break;
+        case 6: s_blocks<T, ZB, (6 < ZB ? 6 : ZB)>(rz, t, rho2, sv); break;
+        case 7: s_blocks<T, ZB, (7 < ZB ? 7 : ZB)>(rz, t, rho2, sv); break;
+        default: s_blocks<T, ZB, ZB>(rz, t, rho2, sv); break;
+    }
+}
+
+// Where the samples of a grid wave share a column, register r is a block of 64
+// consecutive samples and lane r of bmin holds the block's smallest z (+inf in
+// lanes >= ZB).  A vertex at or below every sample of a block (r_z <= 0 in all
+// its lanes) has s = l + |r_z| there with no reciprocal; fma(z, u, -bmin) > 0
+// in lane r is exactly "some lane of block r has r_z > 0" (r_z is the same fma
+// and falls as the sample's z rises).  When the blocks' smallest z ascend with
+// r (asc) the blocks needing the reciprocal are a prefix.
+template <class T>
+struct BlockMin {
+    T bmin;
+    bool asc;
+};
+
 // pzs: the samples' z in offset units (cells times EdgePairs' kUnit inside the box)
-template <class T, int ZB, bool FAR>
+template <class T, int ZB, bool FAR, bool COL = false>
 __device__ __forceinline__ void load_vertex(const BVert& b, int qqx, int qqy, T pxs, T pys, const T* pzs, T f,
-                                            ColV<T>& c, T* rz, T* sv) {
+                                            ColV<T>& c, T* rz, T* sv, const BlockMin<T>* bm = nullptr) {
     c = col_vtx<T, ZB, FAR>(b, qqx, qqy, pxs, pys, f);
     constexpr T u = (T)EdgePairs<T, ZB, FAR>::kUnit;
+    if constexpr (COL && !FAR) {
+        T t[ZB];
 #pragma unroll
-    for (int r = 0; r < ZB; ++r) {
-        rz[r] = FAR ? fma((T)b.z, f, -pzs[r]) : (u == (T)1 ? (T)b.z - pzs[r] : fma((T)b.z, u, -pzs[r]));
-        sv[r] = samp_s<T>(c.rho2, rz[r]);
+        for (int r = 0; r < ZB; ++r) {
+            rz[r] = u == (T)1 ? (T)b.z - pzs[r] : fma((T)b.z, u, -pzs[r]);
+            t[r] = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2) + fabs(rz[r]);
+        }
+        const T d = u == (T)1 ? (T)b.z - bm->bmin : fma((T)b.z, u, -bm->bmin);
+        const int R = bm->asc ? __builtin_popcountll(__builtin_amdgcn_ballot_w64(d > (T)0)) : ZB;
+        s_prefix<T, ZB>(R, rz, t, c.rho2, sv);
+    } else {
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) {
+            rz[r] = FAR ? fma((T)b.z, f, -pzs[r]) : (u == (T)1 ? (T)b.z - pzs[r] : fma((T)b.z, u, -pzs[r]));
+            sv[r] = samp_s<T>(c.rho2, rz[r]);
+        }
     }
 }
 
 // Boundary sum S = sum of atan2 over the chained loops for ZB samples sharing one
 // (x, y).  FP32 partials are flushed into the FP64 sum every 32 edges.  pzs in
-// cells inside the box (FAR: in units of 2^e cells).
-template <class T, int ZB, bool FAR>
+// cells inside the box (FAR: in units of 2^e cells).  COL: the wave is a grid
+// column whose register r holds 64 consecutive samples, z monotone in the lane.
+// pairs: this lane's samples may take edge pairs (see near_z).
+template <class T, int ZB, bool FAR, bool COL = false>
 __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int qqy, T pxs, T pys, const T* pzs,
-                                               double* S, T f = (T)1) {
+                                               double* S, T f = (T)1, bool pairs = true) {
     const BVert* __restrict__ bv = mv.bverts;
     T pz[ZB];
 #pragma unroll
     for (int r = 0; r < ZB; ++r) pz[r] = FAR ? pzs[r] : pzs[r] * (T)EdgePairs<T, ZB, FAR>::kUnit;
+    BlockMin<T> bmv{(T)INFINITY, true};
+    const BlockMin<T>* bm = &bmv;
+    if constexpr (COL && !FAR) {
+        // the samples of a block are monotone in the lane, so its smallest z is in
+        // lane 0 or lane 63
+        const int lane = (int)(threadIdx.x & 63);
+        T prev = -(T)INFINITY;
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) {
+            const T m = fmin(wave_lane<T>(pz[r], 0), wave_lane<T>(pz[r], 63));
+            if (lane == r) bmv.bmin = m;
+            bmv.asc &= !(m < prev);
+            prev = m;
+        }
+    }
     for (int l = 0; l < mv.nloops; ++l) {
         const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
         ColV<T> cf, cp, cq, cr;
         T rzf[ZB], sf[ZB], rzp[ZB], sp[ZB], rzq[ZB], sq[ZB], rzr[ZB], sr[ZB];
-        load_vertex<T, ZB, FAR>(bv[b0], qqx, qqy, pxs, pys, pz, f, cf, rzf, sf);
+        load_vertex<T, ZB, FAR, COL>(bv[b0], qqx, qqy, pxs, pys, pz, f, cf, rzf, sf, bm);
         cp = cf;
 #pragma unroll
         for (int r = 0; r < ZB; ++r) {
@@ -336,17 +427,17 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
             // four vertices (two edge pairs) per trip: p-q-r, then r-q-p with q and p
             // reloaded, so the loop-carried vertex ends in the set it started in
             for (; j + 3 < je; j += 4) {
-                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq);
-                load_vertex<T, ZB, FAR>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, rzr, sr);
-                edge_pair<T, ZB, FAR>(cp, cq, cr, sp, sq, sr, rzp, rzq, rzr, acc);
-                load_vertex<T, ZB, FAR>(bv[j + 2], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq);
-                load_vertex<T, ZB, FAR>(bv[j + 3], qqx, qqy, pxs, pys, pz, f, cp, rzp, sp);
-                edge_pair<T, ZB, FAR>(cr, cq, cp, sr, sq, sp, rzr, rzq, rzp, acc);
+                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq, bm);
+                load_vertex<T, ZB, FAR, COL>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, rzr, sr, bm);
+                edge_pair<T, ZB, FAR, COL>(cp, cq, cr, sp, sq, sr, rzp, rzq, rzr, acc, pairs);
+                load_vertex<T, ZB, FAR, COL>(bv[j + 2], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq, bm);
+                load_vertex<T, ZB, FAR, COL>(bv[j + 3], qqx, qqy, pxs, pys, pz, f, cp, rzp, sp, bm);
+                edge_pair<T, ZB, FAR, COL>(cr, cq, cp, sr, sq, sp, rzr, rzq, rzp, acc, pairs);
             }
             if (j + 1 < je) {
-                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq);
-                load_vertex<T, ZB, FAR>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, rzr, sr);
-                edge_pair<T, ZB, FAR>(cp, cq, cr, sp, sq, sr, rzp, rzq, rzr, acc);
+                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq, bm);
+                load_vertex<T, ZB, FAR, COL>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, rzr, sr, bm);
+                edge_pair<T, ZB, FAR, COL>(cp, cq, cr, sp, sq, sr, rzp, rzq, rzr, acc, pairs);
                 cp = cr;
 #pragma unroll
                 for (int r = 0; r < ZB; ++r) {
@@ -356,7 +447,7 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
                 j += 2;
             }
             if (j < je) {
-                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq);
+                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq, bm);
                 edge_step<T, ZB, FAR>(cp, cq, sp, sq, rzp, rzq, acc);
                 cp = cq;
 #pragma unroll

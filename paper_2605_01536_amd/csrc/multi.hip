@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_bdry_persistent(const MeshView* __restr
             double S = 0.0;
             if (q.inbox) {
                 const float pzs = pz * mv.g.scalef;
-                boundary_loops<float, 1, false>(mv, q.x, q.y, 0.f, 0.f, &pzs, &S);
+                boundary_loops<float, 1, false>(mv, q.x, q.y, 0.f, 0.f, &pzs, &S, 1.f, near_z(pz, mv.g));
             } else {
                 const FarScale<float> fs = far_scale<float>(px, py, fabsf(pz), mv.g.scale);
                 const float pzs = pz * fs.scf;

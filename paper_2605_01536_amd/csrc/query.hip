@@ -119,17 +119,22 @@ __global__ __launch_bounds__(kChiBlock) void k_chi_line(MeshView mv, const float
 template <class T>
 __global__ __launch_bounds__(256) void k_bdry_batch(MeshView mv, const float* __restrict__ qx, const float* __restrict__ qy,
                                                     const float* __restrict__ qz, long long qs, long long nq,
-                                                    const int* __restrict__ chi, T* __restrict__ w) {
-    const long long i = blockIdx.x * 256ll + threadIdx.x;
+                                                    const int* __restrict__ perm, const int* __restrict__ chi,
+                                                    T* __restrict__ w) {
+    const long long j = blockIdx.x * 256ll + threadIdx.x;
     if (nq <= 0 || blockIdx.x * 256ll >= nq) return;
-    const long long ii = i < nq ? i : nq - 1;
+    const long long jj = j < nq ? j : nq - 1;
+    // with a traversal order, lane j takes point perm[j]: the lanes of a wave are
+    // neighbours in x/y, so an edge's pair test passes or fails for all of them
+    const long long i = j < nq ? (perm ? (long long)perm[j] : j) : nq;
+    const long long ii = perm ? (long long)perm[jj] : jj;
     const float px = qx[ii * qs], py = qy[ii * qs], pz = qz[ii * qs];
     const QPoint q = quantize_point(px, py, pz, mv.g);
     // lanes outside the fixed-point grid (rare) take the raw-offset loop
     double S = 0.0;
     if (q.inbox) {
         const T pzs = (T)pz * (T)mv.g.scale;
-        boundary_loops<T, 1, false>(mv, q.x, q.y, (T)0, (T)0, &pzs, &S);
+        boundary_loops<T, 1, false>(mv, q.x, q.y, (T)0, (T)0, &pzs, &S, (T)1, near_z(pz, mv.g));
     } else {
         const FarScale<T> fs = far_scale<T>(px, py, fabsf(pz), mv.g.scale);
         const T pzs = (T)pz * fs.scf;
@@ -197,7 +202,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_bdry_split(MeshView mv, const
     const int a = (int)threadIdx.x * per, e = min(nb, a + per);
     double S = 0.0;
     if (q.inbox) {
-        split_run<T, false>(mv, a, e, q.x, q.y, (T)0, (T)0, (T)pz * (T)mv.g.scale, (T)1, &S);
+        split_run<T, false>(mv, a, e, q.x, q.y, (T)0, (T)0,
+                            (T)pz * (T)mv.g.scale * (T)EdgePairs<T, 1, false>::kUnit, (T)1, &S);
     } else {
         const FarScale<T> fs = far_scale<T>(px, py, fabsf(pz), mv.g.scale);
         split_run<T, true>(mv, a, e, 0, 0, (T)px * fs.scf, (T)py * fs.scf, (T)pz * fs.scf, fs.f, &S);
@@ -215,12 +221,18 @@ __global__ __launch_bounds__(kSplitThreads) void k_bdry_split(MeshView mv, const
 // ---------------------------------------------------------------- grid (ray reuse)
 
 
+// FP32 with 8 samples per lane and FP64 with 4 are held to 128 VGPRs (4 waves
+// per SIMD), a few spilled registers outside the edge loop cost less than the
+// fourth wave gains.
 // One wave owns one (x, y) column and a chunk of 64*ZB consecutive z samples;
-// lane l holds samples l*ZB .. l*ZB+ZB-1 of the chunk.  The column's line is
+// lane l holds samples l, l+64, ..., l+64(ZB-1) of the chunk, so each of its ZB
+// registers covers a block of 64 consecutive samples (most boundary vertices
+// lie wholly above or below a block, see load_vertex).  The column's line is
 // cast once (all lanes walk the same BVH path) and every crossing is classified
 // against each sample with the exact plane predicate (Sec. 4.3.1, ray reuse).
 template <class T, int ZB>
-__global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs ga, int* __restrict__ chi_out,
+__global__ __launch_bounds__(64 * kGridWaves)
+__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && ZB == 8) || (sizeof(T) == 8 && ZB == 4) ? 4 : 1))) void k_grid(MeshView mv, GridArgs ga, int* __restrict__ chi_out,
                                                           T* __restrict__ w) {
     __shared__ int wstack[kGridWaves][kLdsStack];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -232,7 +244,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs 
     const long long ci = col / ga.ny, cj = col - ci * ga.ny;
     const float px = grid_coord(ga.o[0], ga.s[0], ci);
     const float py = grid_coord(ga.o[1], ga.s[1], cj);
-    const long long k0 = chunk * 64 * ZB + (long long)lane * ZB;
+    const long long k0 = chunk * 64 * ZB + lane;   // sample r is k0 + 64 r
 
     float pz[ZB];
     int qzr[ZB];
@@ -240,7 +252,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs 
     const QPoint q0 = quantize_point(px, py, 0.0f, mv.g);
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {
-        pz[r] = grid_coord(ga.o[2], ga.s[2], min(k0 + r, ga.nz - 1));
+        pz[r] = grid_coord(ga.o[2], ga.s[2], min(k0 + 64 * r, ga.nz - 1));
         qzr[r] = quantize_point(px, py, pz[r], mv.g).z;
         chi[r] = 0;
     }
@@ -289,12 +301,14 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs 
     double S[ZB];
     if (q0.inbox) {
         const T sc = (T)mv.g.scale;
+        bool near = true;
 #pragma unroll
         for (int r = 0; r < ZB; ++r) {
             pzs[r] = (T)pz[r] * sc;
             S[r] = 0.0;
+            near &= near_z(pz[r], mv.g);
         }
-        boundary_loops<T, ZB, false>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S);
+        boundary_loops<T, ZB, false, true>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S, (T)1, near);
     } else {
         float pzm = 0.f;
 #pragma unroll
@@ -311,7 +325,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid(MeshView mv, GridArgs 
     const long long base = ci * ga.st[0] + cj * ga.st[1];
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {
-        const long long k = k0 + r;
+        const long long k = k0 + 64 * r;
         if (k < ga.nz) {
             w[base + k * ga.st[2]] = (T)((double)chi[r] + S[r] * kInv2Pi);
             if (chi_out) chi_out[base + k * ga.st[2]] = chi[r];
@@ -344,14 +358,15 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
                                                                                            chi + o);
         }
         e = hipGetLastError();
-        if (perm) (void)hipFreeAsync(perm, st);
         if (e == hipSuccess) {
             if (want_split(m, n))
                 k_bdry_split<T><<<(unsigned)n, kSplitThreads, 0, st>>>(mv, x, y, z, qs, n, chi + o, w + o);
             else
-                k_bdry_batch<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(mv, x, y, z, qs, n, chi + o, w + o);
+                k_bdry_batch<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(mv, x, y, z, qs, n, perm, chi + o,
+                                                                             w + o);
             e = hipGetLastError();
         }
+        if (perm) (void)hipFreeAsync(perm, st);
     }
     if (!chi_out) (void)hipFreeAsync(chi, st);
     GWN_HIP_TRY(e);

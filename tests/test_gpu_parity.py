@@ -314,6 +314,24 @@ def test_astronomically_far_queries(gwn, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_grid_columns_far_in_z(gwn, prec):
+    # columns inside the box whose samples lie far above and below it: every
+    # sample far (FP32 cell offsets overflow to infinity), and a column mixing
+    # near and far samples in one wave; finite, and against the oracle
+    s = W.opened_spheres(seed=40, n_surf=3, tris_per_surf=300)
+    m = gwn.Mesh(_dev(s.V), _dev(s.F))
+    tol = TOL_FP32 if prec == "fp32" else TOL_FP64
+    for g in (W.GridSpec(origin=(-0.5, -0.5, 1e30), spacing=(0.25, 0.25, 1e29), dims=(4, 4, 64)),
+              W.GridSpec(origin=(-0.5, -0.5, -3e4), spacing=(0.25, 0.25, 937.5), dims=(4, 4, 64)),
+              W.GridSpec(origin=(-0.5, -0.5, -3e4), spacing=(0.25, 0.25, 117.1875), dims=(4, 4, 512))):
+        w, chi = gwn.query_grid(m, g.origin, g.spacing, g.dims, prec=prec, want_chi=True)
+        w, chi = w.cpu().numpy(), chi.cpu().numpy()
+        assert np.isfinite(w).all()
+        P = W.grid_points(g)
+        compare(w, chi, s.V, s.F, P, tol, f"far-z-{prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_welded_exploded_soup(gwn, prec):
     # STL-style input: every triangle with its own vertices; welding on the
     # device recovers the indexed boundary, and w / chi match the oracle
