@@ -81,14 +81,13 @@ PEAK_BF16 = 2.5e15
 NET_VALU_SLOTS = 512 * 20.5 + 32 * 21 + 256     # = 11,424 per point
 # HBM bytes moved per k_grid<float, 8> launch on the default workload (512^3 grid,
 # 1.05M-triangle soup), from two rocprofv3 --pmc passes over this command:
-# FETCH_SIZE 513,634.2 KiB and WRITE_SIZE 1,581,048.9 KiB per dispatch, scaled by
+# FETCH_SIZE 232,881.6 KiB and WRITE_SIZE 524,288 KiB per dispatch, scaled by
 # what the same counters read for a plain 1 GiB device copy (bench.py
 # --copy-probe: FETCH_SIZE shows 524,309.4 KiB -> x2.000, WRITE_SIZE
-# 1,048,576 KiB -> x1.000).  Of the 2.67 GB, 0.54 GB is the w output and about
-# 1.2 GB the 72 bytes per lane the 128-register kernel spills once per wave
-# (stored before the boundary loops, reloaded after).  Measured on the kernel
-# as it stands; re-take the counters after any change to k_grid or the workload.
-K_GRID_TRAFFIC_BYTES = (513634.1875 * 2.0 + 1581048.875 * 1.0) * 1024
+# 1,048,576 KiB -> x1.000).  Writes are exactly the w output.  Measured on the
+# kernel as it stands; re-take the counters after any change to k_grid or the
+# workload.
+K_GRID_TRAFFIC_BYTES = (232881.625 * 2.0 + 524288.0 * 1.0) * 1024
 FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
 I_MIN_GRID_FP64 = (16 + 2 + 21 / 2) * FP64_OP_SLOTS + 2.5 * FP64_TRANS_SLOTS + 2   # = 58.25
 # Per sample and boundary vertex, the two-sided form of s (rcp, rho^2*rcp, the

@@ -211,12 +211,15 @@ __device__ __forceinline__ T samp_s(T rho2, T rz) {
 
 // Rare path of one (sample, edge): exact atan2 branch where D <= 0 (sign of N from
 // the perturbed predicate, or the perturbation limit for an endpoint on the ray),
-// then the full-range atan2.
+// then the full-range atan2.  An endpoint on the sample's vertical line
+// (dx = dy = 0, so rho = 0 exactly) lies on the ray above it exactly when its
+// s = rho^2 / (l + r_z) is 0 (below it s = 2 |r_z| > 0); s = 0 with r_z = 0 is a
+// vertex at the sample itself, on the surface, where w is undefined.
 template <class T>
-__device__ __forceinline__ T edge_slow(const ColV<T>& a, const ColV<T>& b, T rza, T rzb, T N, T D, bool exact) {
+__device__ __forceinline__ T edge_slow(const ColV<T>& a, const ColV<T>& b, T sa, T sb, T N, T D, bool exact) {
     if (exact && D <= (T)0) {
-        const bool aon = (a.dx == 0) & (a.dy == 0) & (rza > (T)0);
-        const bool bon = (b.dx == 0) & (b.dy == 0) & (rzb > (T)0);
+        const bool aon = (a.dx == 0) & (a.dy == 0) & (sa == (T)0);
+        const bool bon = (b.dx == 0) & (b.dy == 0) & (sb == (T)0);
         if (aon && bon) {
             N = (T)0;
             D = (T)1;
@@ -241,7 +244,7 @@ __device__ __forceinline__ T edge_slow(const ColV<T>& a, const ColV<T>& b, T rza
 // every sample has |N| < kFast D, so atan2(N, D) = atan(N/D) with no branch
 // fix-up.
 template <class T, int ZB, bool FAR>
-__device__ __forceinline__ void edge_finish(const ColV<T>& a, const ColV<T>& b, const T* rza, const T* rzb, T N,
+__device__ __forceinline__ void edge_finish(const ColV<T>& a, const ColV<T>& b, const T* sa, const T* sb, T N,
                                             const T* D, T* acc) {
     const T aN = fabs(N);
     bool slow = false;
@@ -252,19 +255,18 @@ __device__ __forceinline__ void edge_finish(const ColV<T>& a, const ColV<T>& b, 
         for (int r = 0; r < ZB; ++r) acc[r] += Arith<T>::atan_small(N * Arith<T>::rcp(D[r]));
     } else {
 #pragma unroll
-        for (int r = 0; r < ZB; ++r) acc[r] += edge_slow<T>(a, b, rza[r], rzb[r], N, D[r], !FAR);
+        for (int r = 0; r < ZB; ++r) acc[r] += edge_slow<T>(a, b, sa[r], sb[r], N, D[r], !FAR);
     }
 }
 
 template <class T, int ZB, bool FAR>
-__device__ __forceinline__ void edge_step(const ColV<T>& a, const ColV<T>& b, const T* sa, const T* sb, const T* rza,
-                                          const T* rzb, T* acc) {
+__device__ __forceinline__ void edge_step(const ColV<T>& a, const ColV<T>& b, const T* sa, const T* sb, T* acc) {
     const T N = a.ry * b.rx - a.rx * b.ry;
     const T dot = a.rx * b.rx + a.ry * b.ry;
     T D[ZB];
 #pragma unroll
     for (int r = 0; r < ZB; ++r) D[r] = sa[r] * sb[r] + dot;
-    edge_finish<T, ZB, FAR>(a, b, rza, rzb, N, D, acc);
+    edge_finish<T, ZB, FAR>(a, b, sa, sb, N, D, acc);
 }
 
 // Inside the box x and y are within 2^31 cells of every boundary vertex but z
@@ -283,12 +285,12 @@ __device__ __forceinline__ bool near_z(float pz, const QGrid& g) {
 // |N| < D, so their wave-uniform choice never mattered).
 template <class T, int ZB, bool FAR, bool COL>
 __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, const ColV<T>& c, const T* sa,
-                                          const T* sb, const T* sc, const T* rza, const T* rzb, const T* rzc, T* acc,
+                                          const T* sb, const T* sc, T* acc,
                                           bool pairs) {
     using P = EdgePairs<T, ZB, FAR>;
     if constexpr (!P::on) {
-        edge_step<T, ZB, FAR>(a, b, sa, sb, rza, rzb, acc);
-        edge_step<T, ZB, FAR>(b, c, sb, sc, rzb, rzc, acc);
+        edge_step<T, ZB, FAR>(a, b, sa, sb, acc);
+        edge_step<T, ZB, FAR>(b, c, sb, sc, acc);
     } else {
         const T N1 = a.ry * b.rx - a.rx * b.ry, dot1 = a.rx * b.rx + a.ry * b.ry;
         const T N2 = b.ry * c.rx - b.rx * c.ry, dot2 = b.rx * c.rx + b.ry * c.ry;
@@ -314,8 +316,8 @@ __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, co
                 else acc[r] += Arith<T>::atan_small(t);   // |t| < tan(pi/8)
             }
         } else {
-            edge_finish<T, ZB, FAR>(a, b, rza, rzb, N1, D1, acc);
-            edge_finish<T, ZB, FAR>(b, c, rzb, rzc, N2, D2, acc);
+            edge_finish<T, ZB, FAR>(a, b, sa, sb, N1, D1, acc);
+            edge_finish<T, ZB, FAR>(b, c, sb, sc, N2, D2, acc);
         }
     }
 }
@@ -358,9 +360,10 @@ struct BlockMin {
 // pzs: the samples' z in offset units (cells times EdgePairs' kUnit inside the box)
 template <class T, int ZB, bool FAR, bool COL = false>
 __device__ __forceinline__ void load_vertex(const BVert& b, int qqx, int qqy, T pxs, T pys, const T* pzs, T f,
-                                            ColV<T>& c, T* rz, T* sv, const BlockMin<T>* bm = nullptr) {
+                                            ColV<T>& c, T* sv, const BlockMin<T>* bm = nullptr) {
     c = col_vtx<T, ZB, FAR>(b, qqx, qqy, pxs, pys, f);
     constexpr T u = (T)EdgePairs<T, ZB, FAR>::kUnit;
+    T rz[ZB];
     if constexpr (COL && !FAR) {
         T t[ZB];
 #pragma unroll
@@ -410,12 +413,11 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
     for (int l = 0; l < mv.nloops; ++l) {
         const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
         ColV<T> cf, cp, cq, cr;
-        T rzf[ZB], sf[ZB], rzp[ZB], sp[ZB], rzq[ZB], sq[ZB], rzr[ZB], sr[ZB];
-        load_vertex<T, ZB, FAR, COL>(bv[b0], qqx, qqy, pxs, pys, pz, f, cf, rzf, sf, bm);
+        T sf[ZB], sp[ZB], sq[ZB], sr[ZB];
+        load_vertex<T, ZB, FAR, COL>(bv[b0], qqx, qqy, pxs, pys, pz, f, cf, sf, bm);
         cp = cf;
 #pragma unroll
         for (int r = 0; r < ZB; ++r) {
-            rzp[r] = rzf[r];
             sp[r] = sf[r];
         }
         int j = b0 + 1;
@@ -427,32 +429,30 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
             // four vertices (two edge pairs) per trip: p-q-r, then r-q-p with q and p
             // reloaded, so the loop-carried vertex ends in the set it started in
             for (; j + 3 < je; j += 4) {
-                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq, bm);
-                load_vertex<T, ZB, FAR, COL>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, rzr, sr, bm);
-                edge_pair<T, ZB, FAR, COL>(cp, cq, cr, sp, sq, sr, rzp, rzq, rzr, acc, pairs);
-                load_vertex<T, ZB, FAR, COL>(bv[j + 2], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq, bm);
-                load_vertex<T, ZB, FAR, COL>(bv[j + 3], qqx, qqy, pxs, pys, pz, f, cp, rzp, sp, bm);
-                edge_pair<T, ZB, FAR, COL>(cr, cq, cp, sr, sq, sp, rzr, rzq, rzp, acc, pairs);
+                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, sq, bm);
+                load_vertex<T, ZB, FAR, COL>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, sr, bm);
+                edge_pair<T, ZB, FAR, COL>(cp, cq, cr, sp, sq, sr, acc, pairs);
+                load_vertex<T, ZB, FAR, COL>(bv[j + 2], qqx, qqy, pxs, pys, pz, f, cq, sq, bm);
+                load_vertex<T, ZB, FAR, COL>(bv[j + 3], qqx, qqy, pxs, pys, pz, f, cp, sp, bm);
+                edge_pair<T, ZB, FAR, COL>(cr, cq, cp, sr, sq, sp, acc, pairs);
             }
             if (j + 1 < je) {
-                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq, bm);
-                load_vertex<T, ZB, FAR, COL>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, rzr, sr, bm);
-                edge_pair<T, ZB, FAR, COL>(cp, cq, cr, sp, sq, sr, rzp, rzq, rzr, acc, pairs);
+                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, sq, bm);
+                load_vertex<T, ZB, FAR, COL>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, sr, bm);
+                edge_pair<T, ZB, FAR, COL>(cp, cq, cr, sp, sq, sr, acc, pairs);
                 cp = cr;
 #pragma unroll
                 for (int r = 0; r < ZB; ++r) {
-                    rzp[r] = rzr[r];
                     sp[r] = sr[r];
                 }
                 j += 2;
             }
             if (j < je) {
-                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, rzq, sq, bm);
-                edge_step<T, ZB, FAR>(cp, cq, sp, sq, rzp, rzq, acc);
+                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, sq, bm);
+                edge_step<T, ZB, FAR>(cp, cq, sp, sq, acc);
                 cp = cq;
 #pragma unroll
                 for (int r = 0; r < ZB; ++r) {
-                    rzp[r] = rzq[r];
                     sp[r] = sq[r];
                 }
                 ++j;
@@ -463,7 +463,7 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
         T acc[ZB];
 #pragma unroll
         for (int r = 0; r < ZB; ++r) acc[r] = (T)0;
-        edge_step<T, ZB, FAR>(cp, cf, sp, sf, rzp, rzf, acc);
+        edge_step<T, ZB, FAR>(cp, cf, sp, sf, acc);
 #pragma unroll
         for (int r = 0; r < ZB; ++r) S[r] += (double)acc[r];
     }

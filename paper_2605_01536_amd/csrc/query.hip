@@ -158,17 +158,17 @@ __device__ void split_run(const MeshView& mv, int a, int e, int qqx, int qqy, T 
     if (a >= e) return;
     const BVert* __restrict__ bv = mv.bverts;
     ColV<T> cp;
-    T rzp, sp;
-    load_vertex<T, 1, FAR>(bv[a], qqx, qqy, pxs, pys, &pzs, f, cp, &rzp, &sp);
+    T sp;
+    load_vertex<T, 1, FAR>(bv[a], qqx, qqy, pxs, pys, &pzs, f, cp, &sp);
     T acc = (T)0;
     int cnt = 0;
     for (int j = a; j < e; ++j) {
         const int lp = min(max(bv[j].loop, 0), mv.nloops - 1);   // in range for any stored value
         const int nx = j + 1 < mv.loop_off[lp + 1] ? j + 1 : mv.loop_off[lp];
         ColV<T> cn;
-        T rzn, sn;
-        load_vertex<T, 1, FAR>(bv[nx], qqx, qqy, pxs, pys, &pzs, f, cn, &rzn, &sn);
-        edge_step<T, 1, FAR>(cp, cn, &sp, &sn, &rzp, &rzn, &acc);
+        T sn;
+        load_vertex<T, 1, FAR>(bv[nx], qqx, qqy, pxs, pys, &pzs, f, cn, &sn);
+        edge_step<T, 1, FAR>(cp, cn, &sp, &sn, &acc);
         if (++cnt == 32) {   // FP32 partials flushed into the FP64 sum every 32 edges
             *S += (double)acc;
             acc = (T)0;
@@ -177,10 +177,9 @@ __device__ void split_run(const MeshView& mv, int a, int e, int qqx, int qqy, T 
         if (j + 1 < e) {
             if (nx == j + 1) {
                 cp = cn;
-                rzp = rzn;
                 sp = sn;
             } else {   // the next edge starts a new loop
-                load_vertex<T, 1, FAR>(bv[j + 1], qqx, qqy, pxs, pys, &pzs, f, cp, &rzp, &sp);
+                load_vertex<T, 1, FAR>(bv[j + 1], qqx, qqy, pxs, pys, &pzs, f, cp, &sp);
             }
         }
     }
