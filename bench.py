@@ -62,10 +62,16 @@ I_MIN_EDGE = 6 + 14 + 3 * TRANS_SLOTS      # = 29
 #   per sample and edge:   D, fast-path test (2)                       = 2 FP64
 #   per sample and pair:   Re, Im (3); rcp + 4; Im*rcp, t^2 (2); 9 polynomial
 #                          FMAs; t*x, final FMA, accumulate (3)         = 21 FP64 + 1 trans
-# Arbitrary points (one query per lane): the x/y quantities are no longer shared
-# by a column, adding per vertex dx, dy (2), their conversion (2), rho^2 (2) and
-# per edge N (2), x/y dot (2):
-I_MIN_BATCH = I_MIN_EDGE + 10              # = 39
+# Arbitrary points (one query per lane, edge pairs chosen per lane): the x/y
+# quantities are no longer shared by a column.
+#   per vertex:      dx, dy (2), their conversion (2) and scale to offset units (2),
+#                    rho^2 (2), r_z (1), l^2 (1), sqrt, l+|r_z| (1), rcp,
+#                    rho^2*rcp (1), compare + select (2)      = 14 + 2 trans
+#   per edge:        N (2), x/y dot (2), pair bound (2), D (1), pair test (1) = 8
+#   per edge pair:   N1 N2 (1), Re (1), Im (2), rcp, Im*rcp (1), t^2 (1),
+#                    3 polynomial FMAs, t*x (1), final FMA (1), accumulate (1)
+#                                                             = 12 + 1 trans
+I_MIN_BATCH = 14 + 2 * TRANS_SLOTS + 8 + (12 + TRANS_SLOTS) / 2      # = 35.5
 # The gradient (Supp. Alg. 3) per pair: per vertex r (3), rho^2 (2), l^2 (1), sqrt,
 # 1/l, l+|r_z| (1), rcp, rho^2*rcp (1), compare + select (2) = 10 + 3 trans; per
 # edge l0 l1 (1), n (3), d (3), c0, c1 (2), grad D (6), n^2+d^2 (2), rcp, scale
