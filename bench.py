@@ -44,10 +44,10 @@ TRANS_SLOTS = 3
 #   per sample and vertex:    r_z (1), l^2 (1), sqrt, l+|r_z| (1), rcp, rho^2*rcp (1),
 #                             compare + select (2)                 = 6 + 2 trans
 #   per sample and edge:      D (1), fast-path test (1)            = 2
-#   per sample and edge pair: Re (1), Im (2), rcp, Im*rcp (1), t^2 (1), 3 polynomial
-#                             FMAs, t*x (1), final FMA (1), accumulate (1)
-#                                                                  = 11 + 1 trans
-I_MIN_GRID = 6 + 2 * TRANS_SLOTS + 2 + (11 + TRANS_SLOTS) / 2      # = 21
+#   per sample and edge pair: Re (1), Im (2), rcp, Im*rcp (1), t^2 (1), 4 FMAs for
+#                             P(t^2), accumulate as FMA(t, P, acc) (1)
+#                                                                  = 10 + 1 trans
+I_MIN_GRID = 6 + 2 * TRANS_SLOTS + 2 + (10 + TRANS_SLOTS) / 2      # = 20.5
 # The single-edge form (reciprocal and degree-7 arctangent per edge) that the
 # per-lane kernels use: 6 + 14 + 3 transcendentals = 29.
 I_MIN_EDGE = 6 + 14 + 3 * TRANS_SLOTS      # = 29
@@ -69,9 +69,8 @@ I_MIN_EDGE = 6 + 14 + 3 * TRANS_SLOTS      # = 29
 #                    rho^2*rcp (1), compare + select (2)      = 14 + 2 trans
 #   per edge:        N (2), x/y dot (2), pair bound (2), D (1), pair test (1) = 8
 #   per edge pair:   N1 N2 (1), Re (1), Im (2), rcp, Im*rcp (1), t^2 (1),
-#                    3 polynomial FMAs, t*x (1), final FMA (1), accumulate (1)
-#                                                             = 12 + 1 trans
-I_MIN_BATCH = 14 + 2 * TRANS_SLOTS + 8 + (12 + TRANS_SLOTS) / 2      # = 35.5
+#                    4 FMAs for P(t^2), FMA(t, P, acc) (1)    = 11 + 1 trans
+I_MIN_BATCH = 14 + 2 * TRANS_SLOTS + 8 + (11 + TRANS_SLOTS) / 2      # = 35
 # The gradient (Supp. Alg. 3) per pair: per vertex r (3), rho^2 (2), l^2 (1), sqrt,
 # 1/l, l+|r_z| (1), rcp, rho^2*rcp (1), compare + select (2) = 10 + 3 trans; per
 # edge l0 l1 (1), n (3), d (3), c0, c1 (2), grad D (6), n^2+d^2 (2), rcp, scale
@@ -87,13 +86,13 @@ PEAK_BF16 = 2.5e15
 NET_VALU_SLOTS = 512 * 20.5 + 32 * 21 + 256     # = 11,424 per point
 # HBM bytes moved per k_grid<float, 8> launch on the default workload (512^3 grid,
 # 1.05M-triangle soup), from two rocprofv3 --pmc passes over this command:
-# FETCH_SIZE 232,881.6 KiB and WRITE_SIZE 524,288 KiB per dispatch, scaled by
+# FETCH_SIZE 235,859.7 KiB and WRITE_SIZE 616,710.6 KiB per dispatch, scaled by
 # what the same counters read for a plain 1 GiB device copy (bench.py
 # --copy-probe: FETCH_SIZE shows 524,309.4 KiB -> x2.000, WRITE_SIZE
-# 1,048,576 KiB -> x1.000).  Writes are exactly the w output.  Measured on the
-# kernel as it stands; re-take the counters after any change to k_grid or the
-# workload.
-K_GRID_TRAFFIC_BYTES = (232881.625 * 2.0 + 524288.0 * 1.0) * 1024
+# 1,048,576 KiB -> x1.000).  Writes are the w output (0.54 GB) plus one 8-byte
+# register spill per lane and wave.  Measured on the kernel as it stands;
+# re-take the counters after any change to k_grid or the workload.
+K_GRID_TRAFFIC_BYTES = (235859.6875 * 2.0 + 616710.625 * 1.0) * 1024
 FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
 I_MIN_GRID_FP64 = (16 + 2 + 21 / 2) * FP64_OP_SLOTS + 2.5 * FP64_TRANS_SLOTS + 2   # = 58.25
 # Per sample and boundary vertex, the two-sided form of s (rcp, rho^2*rcp, the

@@ -13,9 +13,15 @@ i.e. a weighted minimax fit of h with weight x / g(x).  Usage:
     python gen_atan_poly.py [deg]            # float32 table, coefficients highest first
     python gen_atan_poly.py deg double       # float64 table for |t| <= tan(pi/8)
     python gen_atan_poly.py deg pair         # float32 table for |t| <= tan(pi/8)
+    python gen_atan_poly.py deg pform        # float32 table of P for |t| <= tan(pi/8)
 
-The printed table is pasted into query.hip (kAtanQ); the script also reports
-the fitted error and the error of the same Horner evaluation in float32.
+The "pform" table writes atan(t) = t * P(x) instead, P of degree `deg` fitted
+to g(x) = atan(sqrt x)/sqrt x by the Remez exchange for minimax relative error,
+so that a sum of arctangents accumulates as fma(t, P(x), acc).
+
+The printed table is pasted into gwn_kernels.h (kAtanQ, kAtanP); the script
+also reports the fitted error and the error of the same Horner evaluation in
+float32.
 """
 import sys
 
@@ -97,6 +103,45 @@ def remez(deg, iters=60, grid=200001, xmax=1.0, wfun=weight):
     return coef, float(np.max(np.abs(err)))
 
 
+def remez_g(deg, xmax, iters=80, grid=200001):
+    """Minimax relative fit of g on [0, xmax] by a polynomial of degree deg."""
+    n = deg + 1
+    k = np.arange(n + 1)
+    ref = xmax * (0.5 - 0.5 * np.cos(np.pi * k / n))
+    X = np.linspace(0.0, xmax, grid)
+    gx = g(X)
+    coef, err = None, None
+    for _ in range(iters):
+        A = np.zeros((n + 1, n + 1))
+        gr = g(ref)
+        for i, xi in enumerate(ref):
+            A[i, :n] = xi ** np.arange(n)
+            A[i, n] = (-1) ** i * gr[i]
+        coef = np.linalg.solve(A, gr)[:n]
+        err = (np.polyval(coef[::-1], X) - gx) / gx
+        sgn = np.sign(err)
+        idx = []
+        start = 0
+        for i in range(1, len(X) + 1):
+            if i == len(X) or sgn[i] != sgn[start]:
+                seg = np.arange(start, i)
+                idx.append(seg[np.argmax(np.abs(err[seg]))])
+                start = i
+        if len(idx) < n + 1:
+            break
+        while len(idx) > n + 1:
+            e = np.abs(err[idx])
+            if e[0] < e[-1]:
+                idx.pop(0)
+            else:
+                idx.pop()
+        new = X[idx]
+        if np.allclose(new, ref, rtol=0, atol=1e-13):
+            break
+        ref = new
+    return coef, float(np.max(np.abs(err)))
+
+
 def horner_f32(coef_hi_first, t):
     t = np.float32(t)
     x = (t * t).astype(np.float32)
@@ -132,6 +177,23 @@ def main():
         rel = np.abs(a - np.arctan(t)) / np.arctan(t)
         print(f"// degree {deg} in x = t^2 on |t| <= tan(pi/8); max |Q - h| {emax:.3e}; float64 Horner: max rel {rel.max():.3e}")
         print(f"constexpr double kAtanQd[{deg + 1}] = {{" + ", ".join(repr(float(c)) for c in hi_first) + "};")
+        return
+    if len(sys.argv) > 2 and sys.argv[2] == "pform":
+        xmax = 3.0 - 2.0 * np.sqrt(2.0)
+        coef, emax = remez_g(deg, xmax)
+        hi_first = [np.float32(c) for c in coef[::-1]]
+        t = np.linspace(0.0, np.sqrt(xmax), 400001)[1:].astype(np.float32)
+        x = (t * t).astype(np.float32)
+        q = np.full_like(x, hi_first[0])
+        for c in hi_first[1:]:
+            q = (q * x + c).astype(np.float32)
+        a = (t.astype(np.float64) * q.astype(np.float64)).astype(np.float32).astype(np.float64)
+        ref = np.arctan(t.astype(np.float64))
+        rel = np.abs(a - ref) / ref
+        print(f"// P of degree {deg} in x = t^2 on |t| <= tan(pi/8); minimax relative error {emax:.3e}; "
+              f"float32 Horner: max rel {rel.max():.3e}, mean signed rel {np.mean((a - ref) / ref):.3e}")
+        print("constexpr float kAtanP[] = {" + ", ".join(f"{c!r}f".replace("np.float32(", "").replace(")", "")
+                                                      for c in hi_first) + "};")
         return
     pair = len(sys.argv) > 2 and sys.argv[2] == "pair"
     tmax = np.sqrt(3.0 - 2.0 * np.sqrt(2.0)) if pair else 1.0

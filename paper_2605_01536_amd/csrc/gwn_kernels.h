@@ -43,10 +43,11 @@ constexpr double kAtanQd[10] = {0.02277211404923737,  -0.044850509519182694, 0.0
                                 -0.06649717364503759, 0.0769106629901103,    -0.09090853283150221,
                                 0.11111109664858296,  -0.14285714266729652,  0.19999999999905727,
                                 -0.33333333333333276};
-// The same form for |t| <= tan(pi/8) (the edge-pair path): Q of degree 3 by the
-// Remez exchange (gen_atan_poly.py 3 pair: 2.1e-8 in exact arithmetic, 8.0e-8
-// max when evaluated in float32).
-constexpr float kAtanQp[4] = {0.08053723f, -0.1387768f, 0.1997771f, -0.3333295f};
+// For |t| <= tan(pi/8) (the edge-pair path) atan(t) = t P(t^2), P of degree 4
+// fitted to atan(sqrt x)/sqrt x by the Remez exchange (gen_atan_poly.py 4 pform:
+// 1.8e-8 relative in exact arithmetic, 1.2e-7 max when evaluated in float32),
+// so that a pair's arctangent accumulates in its final FMA.
+constexpr float kAtanP[5] = {0.07986737f, -0.13852088f, 0.1997447f, -0.33332798f, 1.0f};
 constexpr float kPi = 3.14159265358979f;
 constexpr float kPi2 = 1.57079632679490f;
 
@@ -58,12 +59,13 @@ __device__ __forceinline__ float atan_unit(float t) {
     return fmaf(t * x, q, t);
 }
 
-__device__ __forceinline__ float atan_pair(float t) {
+// acc + atan(t) for |t| <= tan(pi/8) as fma(t, P(t^2), acc)
+__device__ __forceinline__ float atan_pair_acc(float t, float acc) {
     const float x = t * t;
-    float q = kAtanQp[0];
+    float p = kAtanP[0];
 #pragma unroll
-    for (int k = 1; k < 4; ++k) q = fmaf(q, x, kAtanQp[k]);
-    return fmaf(t * x, q, t);
+    for (int k = 1; k < 5; ++k) p = fmaf(p, x, kAtanP[k]);
+    return fmaf(t, p, acc);
 }
 
 // full-range atan2 built on atan_unit (octant reduction by min/max)
@@ -312,7 +314,7 @@ __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, co
                 const T re = fma(D1[r], D2[r], -N12);
                 const T im = fma(D1[r], N2, N1 * D2[r]);
                 const T t = im * Arith<T>::rcp(re);
-                if constexpr (P::f32) acc[r] += atan_pair(t);
+                if constexpr (P::f32) acc[r] = atan_pair_acc(t, acc[r]);
                 else acc[r] += Arith<T>::atan_small(t);   // |t| < tan(pi/8)
             }
         } else {

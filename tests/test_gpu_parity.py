@@ -314,6 +314,20 @@ def test_astronomically_far_queries(gwn, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_grid_descending_and_flat_z(gwn, prec):
+    # negative spacing (samples fall in z along a column, so the sample blocks'
+    # smallest z descend) and zero z spacing (every sample of a column equal)
+    s = W.opened_spheres(seed=41, n_surf=4, tris_per_surf=500)
+    m = gwn.Mesh(_dev(s.V), _dev(s.F))
+    tol = TOL_FP32 if prec == "fp32" else TOL_FP64
+    for g in (W.GridSpec(origin=(1.05, 1.0, 1.1), spacing=(-0.2, -0.18, -2.2 / 600), dims=(11, 12, 600)),
+              W.GridSpec(origin=(-1.0, -1.0, 0.37), spacing=(0.25, 0.25, 0.0), dims=(8, 8, 130))):
+        w, chi = gwn.query_grid(m, g.origin, g.spacing, g.dims, prec=prec, want_chi=True)
+        P = W.grid_points(g)
+        compare(w.cpu().numpy(), chi.cpu().numpy(), s.V, s.F, P, tol, f"grid-z{g.spacing[2]:+.3g}-{prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_grid_columns_far_in_z(gwn, prec):
     # columns inside the box whose samples lie far above and below it: every
     # sample far (FP32 cell offsets overflow to infinity), and a column mixing
