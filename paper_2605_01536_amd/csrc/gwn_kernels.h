@@ -299,14 +299,22 @@ __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, co
         const T m1 = fmax(fabs(N1) * (T)P::kInvTan, (T)P::kMinD);
         const T m2 = fmax(fabs(N2) * (T)P::kInvTan, (T)P::kMinD);
         T D1[ZB], D2[ZB];
-        bool slow = !pairs;
 #pragma unroll
         for (int r = 0; r < ZB; ++r) {
             D1[r] = fma(sa[r], sb[r], dot1);
             D2[r] = fma(sb[r], sc[r], dot2);
-            slow |= !(m1 < D1[r]) | !(m2 < D2[r]);
         }
-        const bool pair = COL ? __builtin_amdgcn_ballot_w64(slow) == 0ull : !slow;
+        bool pair;
+        // D = s_a s_b + dot >= dot (s >= 0, rounding is monotone), so in a column
+        // the x/y terms alone usually settle the test for every sample at once
+        if (COL && __builtin_amdgcn_ballot_w64(!((m1 < dot1) & (m2 < dot2) & pairs)) == 0ull) {
+            pair = true;
+        } else {
+            bool slow = !pairs;
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) slow |= !(m1 < D1[r]) | !(m2 < D2[r]);
+            pair = COL ? __builtin_amdgcn_ballot_w64(slow) == 0ull : !slow;
+        }
         if (pair) {
             const T N12 = N1 * N2;
 #pragma unroll

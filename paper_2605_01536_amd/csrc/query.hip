@@ -307,6 +307,7 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && ZB == 8) || (sizeof(T) == 
             S[r] = 0.0;
             near &= near_z(pz[r], mv.g);
         }
+        near = __builtin_amdgcn_ballot_w64(!near) == 0ull;   // one choice for the whole column
         boundary_loops<T, ZB, false, true>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S, (T)1, near);
     } else {
         float pzm = 0.f;
