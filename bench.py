@@ -94,10 +94,12 @@ NET_VALU_SLOTS = 512 * 20.5 + 32 * 21 + 256     # = 11,424 per point
 K_GRID_TRAFFIC_BYTES = None
 FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
 I_MIN_GRID_FP64 = (16 + 2 + 21 / 2) * FP64_OP_SLOTS + 2.5 * FP64_TRANS_SLOTS + 2   # = 58.25
-# Per sample and boundary vertex, the two-sided form of s (rcp, rho^2*rcp, the
-# sign compare and the select) is skipped where the vertex lies at or below all
-# 64 samples of a grid block: 6 FP32 slots, or 11.4 + 1.5 + 1.5 + 2 in FP64.
+# Per sample and boundary vertex the two-sided form of s (rcp, rho^2*rcp, the sign
+# compare and the select) is skipped where the vertex lies at or below all 64
+# samples of a grid block: 6 FP32 slots (11.4 + 1.5 + 1.5 + 2 in FP64); where it
+# lies above all of them only the compare and select are: 2 slots (1.5 + 2).
 SKIP_SLOTS = {"fp32": 6.0, "fp64": 16.4}
+SKIP_SEL_SLOTS = {"fp32": 2.0, "fp64": 3.5}
 
 
 def boundary_vertex_z(V, F):
@@ -117,18 +119,25 @@ def boundary_vertex_z(V, F):
 
 def grid_slots(soup, grid, prec):
     """Minimal VALU slots per (sample, edge) pair of the grid kernel on this
-    workload: the dense count less the reciprocals the sample blocks skip, and
-    the skipped fraction.  Blocks are 64 consecutive samples of a column."""
+    workload, and the fractions of (vertex, sample) pairs whose block skips the
+    reciprocal (the vertex at or below all its samples) and whose block skips
+    only the select (one of the R blocks with a sample below the vertex other
+    than the last).  Blocks are 64 consecutive samples of a column, z ascending."""
     zv = boundary_vertex_z(soup.V, soup.F)
     nz = int(grid.dims[2])
     kmin = np.arange(0, nz, 64)
     zmin = grid.origin[2] + (kmin + 0.5) * grid.spacing[2]
     sizes = np.minimum(64, nz - kmin)
-    # samples of blocks wholly at or above the vertex
-    skip = (zv[:, None] <= zmin[None, :]) * sizes[None, :]
-    frac = float(skip.sum(1).mean() / nz) if zv.size else 0.0
+    if zv.size == 0:
+        return (I_MIN_GRID_FP64 if prec == "fp64" else I_MIN_GRID), 0.0, 0.0
+    need = zv[:, None] > zmin[None, :]              # blocks with a sample below the vertex
+    above = ((~need) * sizes[None, :]).sum(1).mean() / nz
+    # of the R blocks that need the reciprocal, all but the last drop the select
+    R = need.sum(1)
+    first = np.arange(kmin.size)[None, :] < (R - 1)[:, None]
+    below = (first * sizes[None, :]).sum(1).mean() / nz
     dense = I_MIN_GRID_FP64 if prec == "fp64" else I_MIN_GRID
-    return dense - SKIP_SLOTS[prec] * frac, frac
+    return dense - SKIP_SLOTS[prec] * above - SKIP_SEL_SLOTS[prec] * below, float(above), float(below)
 
 
 def parse():
@@ -216,7 +225,7 @@ def main():
     qps = n / (ms_per_step / 1e3)
     avg_kernel_s = float(np.mean(kern_ms)) / 1e3
     pairs = float(n) * B
-    slots, skip_frac = grid_slots(soup, grid, args.prec)
+    slots, skip_frac, below_frac = grid_slots(soup, grid, args.prec)
     achieved = pairs * slots / avg_kernel_s
     roof = {
         "bound": "alu",
@@ -229,7 +238,8 @@ def main():
         "traffic_unit": "bytes per launch",
         "kernel": "k_grid",
         "slots_per_pair": slots,
-        "block_skip_fraction": skip_frac,
+        "block_above_fraction": skip_frac,
+        "block_below_fraction": below_frac,
         "pairs_per_launch": pairs,
         "avg_kernel_ms": avg_kernel_s * 1e3,
     }
@@ -659,7 +669,7 @@ def bench_precision(args):
         e = np.abs(w[it].double().cpu().numpy() - w_o)[far]
         chi_ok = bool(np.array_equal(chi[it].cpu().numpy(), chi_o))
         pairs = float(grid.n) * info["nboundary"]
-        slots, _ = grid_slots(soup, grid, prec)
+        slots, _, _ = grid_slots(soup, grid, prec)
         res[prec] = {"ms": ms, "queries_per_s": grid.n / (ms / 1e3), "max_abs_err": float(e.max()),
                      "p99_abs_err": float(np.quantile(e, 0.99)), "rms_err": float(np.sqrt(np.mean(e * e))),
                      "chi_bit_exact": chi_ok,

@@ -332,25 +332,34 @@ __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, co
     }
 }
 
-// s for blocks 0..R-1 by the two-sided form, for the others as l + |r_z|
+// s per block given R, the number of blocks with a sample below the vertex
+// (r_z > 0).  With z ascending in r (and in the lane) blocks 0..R-2 lie wholly
+// below the vertex (s = rho^2 / t, no select), block R-1 may straddle it (the
+// two-sided form) and blocks R.. lie wholly at or above it (s = t).  R > ZB:
+// no order known, the two-sided form everywhere.
 template <class T, int ZB, int R>
 __device__ __forceinline__ void s_blocks(const T* rz, const T* t, T rho2, T* sv) {
 #pragma unroll
-    for (int r = 0; r < ZB; ++r) sv[r] = r < R ? (rz[r] > (T)0 ? rho2 * Arith<T>::rcp(t[r]) : t[r]) : t[r];
+    for (int r = 0; r < ZB; ++r) {
+        if (R > ZB || r == R - 1) sv[r] = rz[r] > (T)0 ? rho2 * Arith<T>::rcp(t[r]) : t[r];
+        else if (r < R - 1) sv[r] = rho2 * Arith<T>::rcp(t[r]);
+        else sv[r] = t[r];
+    }
 }
 
 template <class T, int ZB>
 __device__ __forceinline__ void s_prefix(int R, const T* rz, const T* t, T rho2, T* sv) {
     switch (R) {
         case 0: s_blocks<T, ZB, 0>(rz, t, rho2, sv); break;
-        case 1: s_blocks<T, ZB, (1 < ZB ? 1 : ZB)>(rz, t, rho2, sv); break;
-        case 2: s_blocks<T, ZB, (2 < ZB ? 2 : ZB)>(rz, t, rho2, sv); break;
-        case 3: s_blocks<T, ZB, (3 < ZB ? 3 : ZB)>(rz, t, rho2, sv); break;
-        case 4: s_blocks<T, ZB, (4 < ZB ? 4 : ZB)>(rz, t, rho2, sv); break;
-        case 5: s_blocks<T, ZB, (5 < ZB ? 5 : ZB)>(rz, t, rho2, sv); break;
-        case 6: s_blocks<T, ZB, (6 < ZB ? 6 : ZB)>(rz, t, rho2, sv); break;
-        case 7: s_blocks<T, ZB, (7 < ZB ? 7 : ZB)>(rz, t, rho2, sv); break;
-        default: s_blocks<T, ZB, ZB>(rz, t, rho2, sv); break;
+        case 1: s_blocks<T, ZB, (1 <= ZB ? 1 : ZB + 1)>(rz, t, rho2, sv); break;
+        case 2: s_blocks<T, ZB, (2 <= ZB ? 2 : ZB + 1)>(rz, t, rho2, sv); break;
+        case 3: s_blocks<T, ZB, (3 <= ZB ? 3 : ZB + 1)>(rz, t, rho2, sv); break;
+        case 4: s_blocks<T, ZB, (4 <= ZB ? 4 : ZB + 1)>(rz, t, rho2, sv); break;
+        case 5: s_blocks<T, ZB, (5 <= ZB ? 5 : ZB + 1)>(rz, t, rho2, sv); break;
+        case 6: s_blocks<T, ZB, (6 <= ZB ? 6 : ZB + 1)>(rz, t, rho2, sv); break;
+        case 7: s_blocks<T, ZB, (7 <= ZB ? 7 : ZB + 1)>(rz, t, rho2, sv); break;
+        case 8: s_blocks<T, ZB, (8 <= ZB ? 8 : ZB + 1)>(rz, t, rho2, sv); break;
+        default: s_blocks<T, ZB, ZB + 1>(rz, t, rho2, sv); break;
     }
 }
 
@@ -360,7 +369,9 @@ __device__ __forceinline__ void s_prefix(int R, const T* rz, const T* t, T rho2,
 // its lanes) has s = l + |r_z| there with no reciprocal; fma(z, u, -bmin) > 0
 // in lane r is exactly "some lane of block r has r_z > 0" (r_z is the same fma
 // and falls as the sample's z rises).  When the blocks' smallest z ascend with
-// r (asc) the blocks needing the reciprocal are a prefix.
+// r (asc) the samples ascend through the whole column, so the blocks needing
+// the reciprocal are a prefix, all but its last wholly below the vertex (their
+// largest z is at most the next block's smallest).
 template <class T>
 struct BlockMin {
     T bmin;
@@ -382,7 +393,7 @@ __device__ __forceinline__ void load_vertex(const BVert& b, int qqx, int qqy, T 
             t[r] = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2) + fabs(rz[r]);
         }
         const T d = u == (T)1 ? (T)b.z - bm->bmin : fma((T)b.z, u, -bm->bmin);
-        const int R = bm->asc ? __builtin_popcountll(__builtin_amdgcn_ballot_w64(d > (T)0)) : ZB;
+        const int R = bm->asc ? __builtin_popcountll(__builtin_amdgcn_ballot_w64(d > (T)0)) : ZB + 1;
         s_prefix<T, ZB>(R, rz, t, c.rho2, sv);
     } else {
 #pragma unroll

@@ -24,10 +24,14 @@ def test_grid_slots_bounds():
     s = W.opened_spheres(seed=3, n_surf=2, tris_per_surf=200)
     g = W.GridSpec(origin=(-1, -1, -1), spacing=(2 / 8, 2 / 8, 2 / 200), dims=(8, 8, 200))
     for prec in ("fp32", "fp64"):
-        slots, frac = bench.grid_slots(s, g, prec)
+        slots, above, below = bench.grid_slots(s, g, prec)
         dense = bench.I_MIN_GRID_FP64 if prec == "fp64" else bench.I_MIN_GRID
-        assert 0.0 < frac < 1.0 and slots == dense - bench.SKIP_SLOTS[prec] * frac
-    # a grid wholly above every vertex skips every block; wholly below, none
+        assert 0.0 < above < 1.0 and 0.0 < below < 1.0 and above + below < 1.0
+        assert slots == dense - bench.SKIP_SLOTS[prec] * above - bench.SKIP_SEL_SLOTS[prec] * below
+    # a grid wholly above every vertex skips every block's reciprocal; wholly
+    # below, every block's select
     hi = W.GridSpec(origin=(-1, -1, 5), spacing=(0.1, 0.1, 0.1), dims=(2, 2, 100))
     lo = W.GridSpec(origin=(-1, -1, -50), spacing=(0.1, 0.1, 0.1), dims=(2, 2, 100))
-    assert bench.grid_slots(s, hi, "fp32")[1] == 1.0 and bench.grid_slots(s, lo, "fp32")[1] == 0.0
+    assert bench.grid_slots(s, hi, "fp32")[1:] == (1.0, 0.0)
+    # blocks of 64 and 36 samples: the first drops the select, the last keeps it
+    assert bench.grid_slots(s, lo, "fp32")[1:] == (0.0, 0.64)

@@ -152,9 +152,14 @@ def test_grid_columns_through_boundary_vertices(gwn, monkeypatch, prec, zb):
     # pair), loops of many lengths (every tail of the pair loop), for each number
     # of samples per lane; against the oracle and against the per-point kernel
     monkeypatch.setenv("GWN_GRID_SAMPLES_PER_LANE", zb)
-    g = W.GridSpec(origin=(-1.0625, -1.0625, -1.3), spacing=(0.125, 0.125, 2.6 / 130), dims=(18, 18, 130))
-    P = W.grid_points(g)
-    for seed in (17, 18):
+    # z samples off the lattice, then on it (samples at the vertices' heights)
+    for g, seed in ((W.GridSpec(origin=(-1.0625, -1.0625, -1.3), spacing=(0.125, 0.125, 2.6 / 130),
+                                dims=(18, 18, 130)), 17),
+                    (W.GridSpec(origin=(-1.0625, -1.0625, -1.3), spacing=(0.125, 0.125, 2.6 / 130),
+                                dims=(18, 18, 130)), 18),
+                    (W.GridSpec(origin=(-1.0625, -1.0625, -1.0625), spacing=(0.125, 0.125, 0.125),
+                                dims=(18, 18, 140)), 19)):
+        P = W.grid_points(g)
         rng = np.random.default_rng(seed)
         V = (rng.integers(-8, 9, size=(120, 3)) / 8).astype(np.float32)
         F = rng.integers(0, 120, size=(50 + 13 * (seed - 17), 3)).astype(np.int32)
