@@ -54,6 +54,27 @@ __device__ __forceinline__ void gsamp(const BVert& b, const GCol<T>& c, T pzs, T
     s = rz > (T)0 ? c.rho2 * Arith<T>::rcp(t) : t;
 }
 
+// u and s of one vertex for the ZB samples of a grid column whose register r is
+// a block of 64 consecutive samples (lane order, z ascending when bm->asc):
+// blocks wholly at or above the vertex take s = l + |r_z|, blocks wholly below
+// it s = rho^2 / (l + r_z), the block the vertex's height falls in the two-sided
+// form (the block counting is the w kernel's; r_z is the same fma in both).
+template <class T, int ZB>
+__device__ __forceinline__ void gsamp_blocks(const BVert& b, const GCol<T>& c, const T* pzs, T f,
+                                             const BlockMin<T>& bm, T* u, T* s) {
+    T rz[ZB], t[ZB];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        rz[r] = fma((T)b.z, f, -pzs[r]);
+        const T l = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2);
+        u[r] = Arith<T>::rcp(l);
+        t[r] = l + fabs(rz[r]);
+    }
+    const T d = fma((T)b.z, f, -bm.bmin);
+    const int R = bm.asc ? __builtin_popcountll(__builtin_amdgcn_ballot_w64(d > (T)0)) : ZB + 1;
+    s_prefix<T, ZB>(R, rz, t, c.rho2, s);
+}
+
 // one edge (a -> b) for one sample; N, dot and grad N come from x/y only
 template <class T>
 __device__ __forceinline__ void gedge(const GCol<T>& a, const GCol<T>& b, T N, T dot, T gNx, T gNy, T ua, T sa,
@@ -74,8 +95,9 @@ __device__ __forceinline__ void gedge(const GCol<T>& a, const GCol<T>& b, T N, T
 // Sum over all loops of the edge terms for ZB samples on one vertical line, in
 // cell units (FP32 partials flushed into FP64 every 32 edges).  FLIP: the
 // mirrored sum for the axis x0 = -z.
-template <class T, int ZB, bool FLIP>
-__device__ void grad_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, double (*G)[3]) {
+template <class T, int ZB, bool FLIP, bool COL = false>
+__device__ void grad_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, double (*G)[3],
+                           const BlockMin<T>* bm = nullptr) {
     const BVert* __restrict__ bv = mv.bverts;
 #pragma unroll
     for (int r = 0; r < ZB; ++r) G[r][0] = G[r][1] = G[r][2] = 0.0;
@@ -83,8 +105,12 @@ __device__ void grad_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, 
         const int b0 = mv.loop_off[lp], b1 = mv.loop_off[lp + 1];
         const GCol<T> cf = gcol<T>(bv[b0], pxs, pys, f);
         T uf[ZB], sf[ZB];
+        if constexpr (COL && !FLIP) {
+            gsamp_blocks<T, ZB>(bv[b0], cf, pzs, f, *bm, uf, sf);
+        } else {
 #pragma unroll
-        for (int r = 0; r < ZB; ++r) gsamp<T, FLIP>(bv[b0], cf, pzs[r], f, uf[r], sf[r]);
+            for (int r = 0; r < ZB; ++r) gsamp<T, FLIP>(bv[b0], cf, pzs[r], f, uf[r], sf[r]);
+        }
         GCol<T> cp = cf;
         T up[ZB], sp[ZB];
 #pragma unroll
@@ -108,8 +134,12 @@ __device__ void grad_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, 
                 }
                 if (jj < b1) {
                     cc = gcol<T>(bv[jj], pxs, pys, f);
+                    if constexpr (COL && !FLIP) {
+                        gsamp_blocks<T, ZB>(bv[jj], cc, pzs, f, *bm, uc, sc);
+                    } else {
 #pragma unroll
-                    for (int r = 0; r < ZB; ++r) gsamp<T, FLIP>(bv[jj], cc, pzs[r], f, uc[r], sc[r]);
+                        for (int r = 0; r < ZB; ++r) gsamp<T, FLIP>(bv[jj], cc, pzs[r], f, uc[r], sc[r]);
+                    }
                 }
                 const T N = cp.ry * cc.rx - cp.rx * cc.ry;
                 const T dot = cp.rx * cc.rx + cp.ry * cc.ry;
@@ -253,7 +283,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_grad_split(MeshView mv, const
 }
 
 // Gradient on a grid: one wave per (column, z-chunk) as for w, ZB samples per
-// lane sharing the column's x/y terms.  A column through a boundary vertex
+// lane (lane l holds samples l + 64 r of the chunk) sharing the column's x/y
+// terms.  A column through a boundary vertex
 // makes the samples below it 0/0 on the +z axis; if any lane has such a sample,
 // the wave sums the mirrored axis too and those samples take that sum.
 template <class T, int ZB>
@@ -268,11 +299,11 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grad_grid(MeshView mv, Grid
     const long long ci = col / ga.ny, cj = col - ci * ga.ny;
     const float px = grid_coord(ga.o[0], ga.s[0], ci);
     const float py = grid_coord(ga.o[1], ga.s[1], cj);
-    const long long k0 = chunk * 64 * ZB + (long long)lane * ZB;
+    const long long k0 = chunk * 64 * ZB + lane;   // sample r is k0 + 64 r
     float pz[ZB], pzm = 0.f;
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {
-        pz[r] = grid_coord(ga.o[2], ga.s[2], min(k0 + r, ga.nz - 1));
+        pz[r] = grid_coord(ga.o[2], ga.s[2], min(k0 + 64 * r, ga.nz - 1));
         pzm = fmaxf(pzm, fabsf(pz[r]));
     }
     const FarScale<T> fs = far_scale<T>(px, py, pzm, mv.g.scale);
@@ -280,8 +311,19 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grad_grid(MeshView mv, Grid
 #pragma unroll
     for (int r = 0; r < ZB; ++r) pzs[r] = (T)pz[r] * fs.scf;
     const T pxs = (T)px * fs.scf, pys = (T)py * fs.scf;
+    // lane r holds block r's smallest z (the samples of a block are monotone in
+    // the lane, so it is in lane 0 or lane 63)
+    BlockMin<T> bm{(T)INFINITY, true};
+    T prev = -(T)INFINITY;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        const T mz = fmin(wave_lane<T>(pzs[r], 0), wave_lane<T>(pzs[r], 63));
+        if (lane == r) bm.bmin = mz;
+        bm.asc &= !(mz < prev);
+        prev = mz;
+    }
     double G[ZB][3];
-    grad_loops<T, ZB, false>(mv, pxs, pys, pzs, fs.f, G);
+    grad_loops<T, ZB, false, true>(mv, pxs, pys, pzs, fs.f, G, &bm);
     bool bad = false;
 #pragma unroll
     for (int r = 0; r < ZB; ++r) bad |= !finite3(G[r]);
@@ -297,7 +339,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grad_grid(MeshView mv, Grid
     const long long base = ci * ga.st[0] + cj * ga.st[1];
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {
-        const long long k = k0 + r;
+        const long long k = k0 + 64 * r;
         if (k < ga.nz)
             for (int c = 0; c < 3; ++c) g[3 * (base + k * ga.st[2]) + (c + axis) % 3] = (T)(G[r][c] * f);
     }
