@@ -43,6 +43,30 @@ def test_multi_equals_single_mesh_path_and_oracle(gwn, monkeypatch):
                 soups[m].V, soups[m].F, queries[m][idx], TOL_FP32, f"multi mesh {m}")
 
 
+def test_multi_far_and_mixed_queries(gwn, monkeypatch):
+    # per-lane edge pairs: queries inside a mesh's box in x and y but far from it
+    # in z (single edges), far in x and y (far path) and ordinary ones, mixed in
+    # the same waves; bit for bit the single-mesh path, and against the oracle
+    monkeypatch.setenv("GWN_SPLIT_BOUNDARY", "0")
+    soups, queries, meshes, offs, Q = _batch_of(gwn, 6, seed=35, q_range=(300, 900))
+    Qh = Q.cpu().numpy()
+    rng = np.random.default_rng(9)
+    pick = rng.choice(Qh.shape[0], Qh.shape[0] // 3, replace=False)
+    Qh[pick[0::3], 2] = np.float32(1e6) * np.sign(rng.standard_normal(pick[0::3].size)).astype(np.float32)
+    Qh[pick[1::3], 2] = np.float32(3e35)
+    Qh[pick[2::3], 0] = np.float32(-4e7)
+    Q = torch.from_numpy(Qh).cuda()
+    plan = gwn.MultiPlan(meshes, Q, offs)
+    w = plan.run().clone()
+    torch.cuda.synchronize()
+    assert torch.isfinite(w).all()
+    for m, s in enumerate(soups):
+        a, b = int(offs[m]), int(offs[m + 1])
+        wb, cb = gwn.query_batch(meshes[m], Q[a:b], want_chi=True)
+        assert torch.equal(wb, w[a:b])
+        compare(wb.cpu().numpy(), cb.cpu().numpy(), s.V, s.F, Qh[a:b], TOL_FP32, f"far-mixed-{m}")
+
+
 @pytest.mark.parametrize("sched", [dict(item_queries=64, waves_per_simd=1, order=1),
                                    dict(item_queries=512, waves_per_simd=8, order=0),
                                    dict(item_queries=100, waves_per_simd=3, order=0)])
