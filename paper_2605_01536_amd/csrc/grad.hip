@@ -62,17 +62,17 @@ __device__ __forceinline__ void gsamp(const BVert& b, const GCol<T>& c, T pzs, T
 template <class T, int ZB>
 __device__ __forceinline__ void gsamp_blocks(const BVert& b, const GCol<T>& c, const T* pzs, T f,
                                              const BlockMin<T>& bm, T* u, T* s) {
-    T rz[ZB], t[ZB];
+    T rz[ZB];
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {
         rz[r] = fma((T)b.z, f, -pzs[r]);
         const T l = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2);
         u[r] = Arith<T>::rcp(l);
-        t[r] = l + fabs(rz[r]);
+        s[r] = l + fabs(rz[r]);   // t, made s in place
     }
     const T d = fma((T)b.z, f, -bm.bmin);
     const int R = bm.asc ? __builtin_popcountll(__builtin_amdgcn_ballot_w64(d > (T)0)) : ZB + 1;
-    s_prefix<T, ZB>(R, rz, t, c.rho2, s);
+    s_prefix<T, ZB>(R, rz, c.rho2, s);
 }
 
 // one edge (a -> b) for one sample; N, dot and grad N come from x/y only

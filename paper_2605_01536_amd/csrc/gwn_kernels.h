@@ -338,28 +338,27 @@ __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, co
 // two-sided form) and blocks R.. lie wholly at or above it (s = t).  R > ZB:
 // no order known, the two-sided form everywhere.
 template <class T, int ZB, int R>
-__device__ __forceinline__ void s_blocks(const T* rz, const T* t, T rho2, T* sv) {
+__device__ __forceinline__ void s_blocks(const T* rz, T rho2, T* sv) {
 #pragma unroll
-    for (int r = 0; r < ZB; ++r) {
-        if (R > ZB || r == R - 1) sv[r] = rz[r] > (T)0 ? rho2 * Arith<T>::rcp(t[r]) : t[r];
-        else if (r < R - 1) sv[r] = rho2 * Arith<T>::rcp(t[r]);
-        else sv[r] = t[r];
+    for (int r = 0; r < ZB; ++r) {   // sv holds t = l + |r_z| on entry
+        if (R > ZB || r == R - 1) sv[r] = rz[r] > (T)0 ? rho2 * Arith<T>::rcp(sv[r]) : sv[r];
+        else if (r < R - 1) sv[r] = rho2 * Arith<T>::rcp(sv[r]);
     }
 }
 
 template <class T, int ZB>
-__device__ __forceinline__ void s_prefix(int R, const T* rz, const T* t, T rho2, T* sv) {
+__device__ __forceinline__ void s_prefix(int R, const T* rz, T rho2, T* sv) {
     switch (R) {
-        case 0: s_blocks<T, ZB, 0>(rz, t, rho2, sv); break;
-        case 1: s_blocks<T, ZB, (1 <= ZB ? 1 : ZB + 1)>(rz, t, rho2, sv); break;
-        case 2: s_blocks<T, ZB, (2 <= ZB ? 2 : ZB + 1)>(rz, t, rho2, sv); break;
-        case 3: s_blocks<T, ZB, (3 <= ZB ? 3 : ZB + 1)>(rz, t, rho2, sv); break;
-        case 4: s_blocks<T, ZB, (4 <= ZB ? 4 : ZB + 1)>(rz, t, rho2, sv); break;
-        case 5: s_blocks<T, ZB, (5 <= ZB ? 5 : ZB + 1)>(rz, t, rho2, sv); break;
-        case 6: s_blocks<T, ZB, (6 <= ZB ? 6 : ZB + 1)>(rz, t, rho2, sv); break;
-        case 7: s_blocks<T, ZB, (7 <= ZB ? 7 : ZB + 1)>(rz, t, rho2, sv); break;
-        case 8: s_blocks<T, ZB, (8 <= ZB ? 8 : ZB + 1)>(rz, t, rho2, sv); break;
-        default: s_blocks<T, ZB, ZB + 1>(rz, t, rho2, sv); break;
+        case 0: break;
+        case 1: s_blocks<T, ZB, (1 <= ZB ? 1 : ZB + 1)>(rz, rho2, sv); break;
+        case 2: s_blocks<T, ZB, (2 <= ZB ? 2 : ZB + 1)>(rz, rho2, sv); break;
+        case 3: s_blocks<T, ZB, (3 <= ZB ? 3 : ZB + 1)>(rz, rho2, sv); break;
+        case 4: s_blocks<T, ZB, (4 <= ZB ? 4 : ZB + 1)>(rz, rho2, sv); break;
+        case 5: s_blocks<T, ZB, (5 <= ZB ? 5 : ZB + 1)>(rz, rho2, sv); break;
+        case 6: s_blocks<T, ZB, (6 <= ZB ? 6 : ZB + 1)>(rz, rho2, sv); break;
+        case 7: s_blocks<T, ZB, (7 <= ZB ? 7 : ZB + 1)>(rz, rho2, sv); break;
+        case 8: s_blocks<T, ZB, (8 <= ZB ? 8 : ZB + 1)>(rz, rho2, sv); break;
+        default: s_blocks<T, ZB, ZB + 1>(rz, rho2, sv); break;
     }
 }
 
@@ -386,15 +385,14 @@ __device__ __forceinline__ void load_vertex(const BVert& b, int qqx, int qqy, T 
     constexpr T u = (T)EdgePairs<T, ZB, FAR>::kUnit;
     T rz[ZB];
     if constexpr (COL && !FAR) {
-        T t[ZB];
 #pragma unroll
         for (int r = 0; r < ZB; ++r) {
             rz[r] = u == (T)1 ? (T)b.z - pzs[r] : fma((T)b.z, u, -pzs[r]);
-            t[r] = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2) + fabs(rz[r]);
+            sv[r] = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2) + fabs(rz[r]);   // t, made s in place
         }
         const T d = u == (T)1 ? (T)b.z - bm->bmin : fma((T)b.z, u, -bm->bmin);
         const int R = bm->asc ? __builtin_popcountll(__builtin_amdgcn_ballot_w64(d > (T)0)) : ZB + 1;
-        s_prefix<T, ZB>(R, rz, t, c.rho2, sv);
+        s_prefix<T, ZB>(R, rz, c.rho2, sv);
     } else {
 #pragma unroll
         for (int r = 0; r < ZB; ++r) {
