@@ -180,8 +180,9 @@ def copy_probe(nbytes: int):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only (queries shard without communication; "
-              "see the design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: queries and grid columns are independent, so more GPUs "
+              "would each take a contiguous share of them with no communication; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -42,7 +42,7 @@
  *       "Real-Time Collision Detection", Sec. 5.1.5).  Used only to mask
  *       queries that lie too close to the surface, where w is undefined.
  *
- * Readings taken where the paper is silent (each listed in the design notes):
+ * Readings taken where the paper is silent:
  *   - quantisation box: bbox expanded by 0.75 * max extent on every side,
  *     scale 2^k with k the largest integer such that 2.5 * extent * 2^k
  *     <= 2^30 - 1; q = rint((x - lo) * 2^k) in double.
