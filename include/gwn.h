@@ -132,7 +132,9 @@ gwn_status gwn_mesh_destroy(gwn_mesh m);
  *   w_out                   : nq results.
  *   chi_out                 : nullable; nq int32 crossing counts along +z.
  * nq == 0 is a no-op.  Queries on the surface get a well-defined chi; their w is
- * not meaningful (w is undefined on M).
+ * not meaningful (w is undefined on M).  A point's result depends only on the
+ * point and the mesh, not on the other points of the call or their order:
+ * repeated calls, any batching, and gwn_query_multi give the same bits.
  */
 gwn_status gwn_query_batch(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                            int64_t nq, int32_t prec, void* w_out, int32_t* chi_out, void* stream);
@@ -145,6 +147,9 @@ gwn_status gwn_query_batch(gwn_mesh m, const float* qx, const float* qy, const f
  *                           float(origin + (idx + 0.5) * spacing) per axis,
  *                           evaluated in FP64 then rounded once.
  *   w_out, chi_out        : dims[0]*dims[1]*dims[2] results at (i*ny + j)*nz + k.
+ * chi equals gwn_query_batch's at the same points bit for bit; w agrees with it
+ * to rounding (the boundary sum of a column is formed in a different order),
+ * and is itself deterministic for a given grid.
  */
 gwn_status gwn_query_grid(gwn_mesh m, const double* origin, const double* spacing, const int64_t* dims,
                           int32_t prec, void* w_out, int32_t* chi_out, void* stream);
