@@ -132,9 +132,13 @@ gwn_status gwn_mesh_destroy(gwn_mesh m);
  *   w_out                   : nq results.
  *   chi_out                 : nullable; nq int32 crossing counts along +z.
  * nq == 0 is a no-op.  Queries on the surface get a well-defined chi; their w is
- * not meaningful (w is undefined on M).  A point's result depends only on the
- * point and the mesh, not on the other points of the call or their order:
- * repeated calls, any batching, and gwn_query_multi give the same bits.
+ * not meaningful (w is undefined on M).  A point's w does not depend on the
+ * other points of the call or their order, and repeated calls give the same
+ * bits; gwn_query_multi gives the same bits too.  The one exception is the
+ * summation order: batches of at most 8,192 points on meshes with at least
+ * 4,096 boundary edges give each point a workgroup that splits its edges among
+ * lanes (GWN_SPLIT_BOUNDARY=0/1 overrides), which agrees with the other form
+ * to rounding.
  */
 gwn_status gwn_query_batch(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                            int64_t nq, int32_t prec, void* w_out, int32_t* chi_out, void* stream);
