@@ -123,7 +123,13 @@ struct Arith<double> {
         for (int k = 1; k < 10; ++k) q = fma(q, x, kAtanQd[k]);
         return fma(t * x, q, t);
     }
-    static __device__ __forceinline__ double atan2(double y, double x) { return ::atan2(y, x); }
+    // where the fast path would apply, its own expression, so that a lane gets
+    // the same bits whichever path its wave takes (the FP32 full-range atan2
+    // reduces to the same polynomial by construction)
+    static __device__ __forceinline__ double atan2(double y, double x) {
+        if (x > 0.0 && fabs(y) < kFast * x) return atan_small(y * rcp(x));
+        return ::atan2(y, x);
+    }
 };
 
 // ---------------------------------------------------------------- boundary loop

@@ -212,6 +212,22 @@ def test_deterministic(gwn):
     assert torch.equal(gwn.query_batch(m2, Qd), a)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_point_results_independent_of_the_batch(gwn, prec):
+    # per-lane edge pairs are chosen per point, so a point's w is the same bits
+    # in a large batch (traversal order by x, y), a smaller one (no reordering)
+    # and a shuffled one
+    s, Q = W.config2(n_uniform=150_000, n_near=150_000)
+    m = gwn.Mesh(_dev(s.V), _dev(s.F))
+    w_all = gwn.query_batch(m, _dev(Q), prec=prec)
+    sub = Q[::15][:20_000]
+    w_sub = gwn.query_batch(m, _dev(sub), prec=prec)
+    perm = np.random.default_rng(8).permutation(sub.shape[0])
+    w_shuf = gwn.query_batch(m, _dev(sub[perm]), prec=prec)
+    assert torch.equal(w_sub, w_all[::15][:20_000])
+    assert torch.equal(w_shuf, w_sub[torch.from_numpy(perm).cuda()])
+
+
 def test_launch_splitting_is_invisible(gwn, monkeypatch):
     # batches and grids larger than one launch are split; force tiny launches and
     # compare every output bit for bit with the single-launch result
