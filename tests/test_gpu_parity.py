@@ -174,6 +174,31 @@ def test_grid_columns_through_boundary_vertices(gwn, monkeypatch, prec, zb):
         assert np.median(d) < (1e-7 if prec == "fp32" else 1e-14)
 
 
+@pytest.mark.parametrize("seed", range(20))
+def test_random_lattice_soups(gwn, monkeypatch, seed):
+    # seeded lattice soups (shared, repeated and collinear vertices, zero-area and
+    # duplicated triangles) on grids whose columns and samples sit on the lattice,
+    # a random number of samples per lane, FP32 and FP64, against the oracle;
+    # batch points at the same places as a cross-check of the column form
+    rng = np.random.default_rng(1000 + seed)
+    nv = int(rng.integers(20, 200))
+    V = (rng.integers(-6, 7, size=(nv, 3)) / 6).astype(np.float32)
+    F = rng.integers(0, nv, size=(int(rng.integers(5, 120)), 3)).astype(np.int32)
+    F[::7] = F[::7][:, [0, 0, 1]]                      # some degenerate triangles
+    F = np.concatenate([F, F[: len(F) // 5]])          # some duplicates
+    monkeypatch.setenv("GWN_GRID_SAMPLES_PER_LANE", str(int(rng.choice([1, 2, 4, 8]))))
+    h = 1 / 6
+    g = W.GridSpec(origin=(-1 - h / 2 * rng.integers(0, 2), -1 - h / 2, -1.3 + h * rng.integers(0, 2)),
+                   spacing=(h, h, h / int(rng.integers(1, 4))), dims=(13, 13, int(rng.integers(60, 300))))
+    P = W.grid_points(g)
+    m = gwn.Mesh(_dev(V), _dev(F))
+    for prec, tol in (("fp32", TOL_FP32), ("fp64", TOL_FP64)):
+        w, chi = gwn.query_grid(m, g.origin, g.spacing, g.dims, prec=prec, want_chi=True)
+        compare(w.cpu().numpy(), chi.cpu().numpy(), V, F, P, tol, f"lattice-rand{seed}-{prec}")
+        wb, cb = gwn.query_batch(m, _dev(P), prec=prec, want_chi=True)
+        assert torch.equal(cb, chi)
+
+
 def test_edge_cases(gwn):
     # nq = 0 is a no-op
     m = gwn.Mesh(_dev(OCT_V), _dev(OCT_F))
