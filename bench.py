@@ -86,14 +86,15 @@ PEAK_BF16 = 2.5e15
 NET_VALU_SLOTS = 512 * 20.5 + 32 * 21 + 256     # = 11,424 per point
 # HBM bytes moved per k_grid<float, 8> launch on the default workload (512^3 grid,
 # 1.05M-triangle soup), from two rocprofv3 --pmc passes over this command:
-# FETCH_SIZE 242,521.6 KiB and WRITE_SIZE 733,179.3 KiB per dispatch, scaled by
+# FETCH_SIZE 505,386.0 KiB and WRITE_SIZE 1,686,997.5 KiB per dispatch, scaled by
 # what the same counters read for a plain 1 GiB device copy (bench.py
-# --copy-probe: FETCH_SIZE shows 524,309.4 KiB -> x2.000, WRITE_SIZE
+# --copy-probe: FETCH_SIZE shows 524,308 KiB -> x2.000, WRITE_SIZE
 # 1,048,576 KiB -> x1.000).  Writes are the w output (0.54 GB) plus the
-# register spill of the 128-VGPR bound, stored once per wave (~0.2 GB).
+# register spill of the 128-VGPR bound (84 bytes per lane), stored once per wave
+# before the boundary loops and read back at the end.
 # Measured on the kernel as it stands; re-take the counters after any change to
 # k_grid or the workload.
-K_GRID_TRAFFIC_BYTES = (242521.5625 * 2.0 + 733179.25 * 1.0) * 1024
+K_GRID_TRAFFIC_BYTES = (505386.0 * 2.0 + 1686997.5 * 1.0) * 1024
 FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
 I_MIN_GRID_FP64 = (16 + 2 + 21 / 2) * FP64_OP_SLOTS + 2.5 * FP64_TRANS_SLOTS + 2   # = 58.25
 # Per sample and boundary vertex the two-sided form of s (rcp, rho^2*rcp, the sign

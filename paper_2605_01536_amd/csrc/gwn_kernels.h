@@ -352,6 +352,17 @@ __device__ __forceinline__ void s_blocks(const T* rz, T rho2, T* sv) {
     }
 }
 
+// the same per block, as ZB uniform branches (each block's s stays in place)
+template <class T, int ZB>
+__device__ __forceinline__ void s_prefix_blocks(int R, const T* rz, T rho2, T* sv) {
+    const bool ord = R <= ZB;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        if (ord && r < R - 1) sv[r] = rho2 * Arith<T>::rcp(sv[r]);
+        else if (r < R) sv[r] = rz[r] > (T)0 ? rho2 * Arith<T>::rcp(sv[r]) : sv[r];
+    }
+}
+
 template <class T, int ZB>
 __device__ __forceinline__ void s_prefix(int R, const T* rz, T rho2, T* sv) {
     switch (R) {
@@ -489,6 +500,331 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
 #pragma unroll
         for (int r = 0; r < ZB; ++r) acc[r] = (T)0;
         edge_step<T, ZB, FAR>(cp, cf, sp, sf, acc);
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) S[r] += (double)acc[r];
+    }
+}
+
+// ---------------------------------------------------------------- grid columns
+// In a grid column every sample shares x and y, so a boundary vertex's x/y
+// terms (rho^2, and N, the x/y dot and the pair bound of its outgoing edge) are
+// the same for the whole wave.  They are computed for 64 boundary vertices at a
+// time, one vertex per lane, into a ring of records in LDS that every lane then
+// reads at the same address (a broadcast): a wave instruction's worth of x/y
+// work per vertex becomes one lane's.  The same pass counts each vertex's
+// blocks with a sample below it (R, see BlockMin), and whether its outgoing
+// edge pairs on its x/y terms alone becomes a bit of a wave mask.
+template <class T>
+struct alignas(4 * sizeof(T)) ColRec {
+    T zu;     // vertex z in offset units
+    T rho2;   // r_x^2 + r_y^2 from the column
+    T N;      // N of the outgoing edge (to the next vertex of the loop)
+    T dot;    // r_a,x r_b,x + r_a,y r_b,y of the outgoing edge
+};
+
+template <class T>
+struct ColAux {   // read on the rare paths only
+    T m;          // pair bound of the outgoing edge, max(|N| / tan(pi/16), kMinD)
+    T rx, ry;
+    int dx, dy;
+};
+
+constexpr int kColRing = 128;   // slots per wave; slot kColRing holds the loop's first vertex
+
+template <class T>
+struct ColRing {
+    ColRec<T> rec[kColRing + 1];
+    ColAux<T> aux[kColRing + 1];
+    int R[kColRing + 1];   // block count R of the vertex (see BlockMin)
+};
+
+// Records of vertices v0 .. v0 + n - 1 (n <= 64) of the loop [b0, b1), into the
+// ring slots (v0 - b0) mod kColRing; v0 - b0 is a multiple of 64, so they fill
+// one half.  The first call of a loop (v0 == b0) also keeps its first vertex in
+// slot kColRing.  bminr[r]: block r's smallest z in offset units (see BlockMin).
+// Bit k of mk: the edge leaving the half's slot k pairs on its x/y terms alone.
+template <class T, int ZB>
+__device__ __forceinline__ void col_fill(const MeshView& mv, int v0, int n, int b0, int b1, int qqx, int qqy,
+                                         const T* bminr, bool asc, bool pairs, ColRing<T>& ring,
+                                         unsigned long long& mk) {
+    using P = EdgePairs<T, ZB, false>;
+    constexpr T u = (T)P::kUnit;
+    const int lane = (int)(threadIdx.x & 63);
+    bool e = false;
+    int R = 0;
+    if (lane < n) {
+        const int v = v0 + lane;
+        const int vn = v + 1 < b1 ? v + 1 : b0;
+        const BVert a = mv.bverts[v], b = mv.bverts[vn];
+        const ColV<T> ca = col_vtx<T, ZB, false>(a, qqx, qqy, (T)0, (T)0, (T)1);
+        const ColV<T> cb = col_vtx<T, ZB, false>(b, qqx, qqy, (T)0, (T)0, (T)1);
+        ColRec<T> rc;
+        rc.zu = u == (T)1 ? (T)a.z : (T)a.z * u;   // exact (u is a power of two)
+        rc.rho2 = ca.rho2;
+        rc.N = ca.ry * cb.rx - ca.rx * cb.ry;
+        rc.dot = ca.rx * cb.rx + ca.ry * cb.ry;
+        ColAux<T> ax;
+        ax.m = fmax(fabs(rc.N) * (T)P::kInvTan, (T)P::kMinD);
+        ax.rx = ca.rx;
+        ax.ry = ca.ry;
+        ax.dx = ca.dx;
+        ax.dy = ca.dy;
+        if (asc) {
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) R += (u == (T)1 ? (T)a.z - bminr[r] : fma((T)a.z, u, -bminr[r])) > (T)0;
+        } else {
+            R = ZB + 1;
+        }
+        e = ax.m < rc.dot;
+        const int s = (v - b0) & (kColRing - 1);
+        ring.rec[s] = rc;
+        ring.aux[s] = ax;
+        ring.R[s] = R;
+        if (v == b0) {
+            ring.rec[kColRing] = rc;
+            ring.aux[kColRing] = ax;
+            ring.R[kColRing] = R;
+        }
+    }
+    mk = __builtin_amdgcn_ballot_w64(e && pairs);
+    // the wave reads what its own lanes wrote; LDS operations of a wave complete in order
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bool col_e(unsigned long long m0, unsigned long long m1, int k) {
+    return (((k & 64) ? m1 : m0) >> (k & 63)) & 1ull;
+}
+
+template <class T>
+__device__ __forceinline__ int ring_R(const ColRing<T>& ring, int k) {
+    return __builtin_amdgcn_readfirstlane(ring.R[k]);
+}
+
+// s of the vertex in slot k for the lane's ZB samples (pz in offset units),
+// and its outgoing edge's N and x/y dot
+template <class T, int ZB>
+__device__ __forceinline__ void col_vertex(const ColRec<T>& c, int R, const T* pz, T* sv, T& N, T& dot) {
+    T rz[ZB];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        rz[r] = c.zu - pz[r];
+        sv[r] = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2) + fabs(rz[r]);   // t, made s in place
+    }
+    s_prefix<T, ZB>(R, rz, c.rho2, sv);
+    N = c.N;
+    dot = c.dot;
+}
+
+template <class T>
+__device__ __forceinline__ ColV<T> col_aux(const ColRing<T>& ring, int k) {
+    const ColAux<T> a = ring.aux[k];
+    ColV<T> c;
+    c.dx = a.dx;
+    c.dy = a.dy;
+    c.rx = a.rx;
+    c.ry = a.ry;
+    c.rho2 = (T)0;   // not used by edge_slow
+    return c;
+}
+
+// One edge (slot ka to slot kb) given its D per sample: the fast form where
+// every sample allows it, else the exact and full-range forms (edge_slow).
+template <class T, int ZB>
+__device__ __forceinline__ void col_finish(const ColRing<T>& ring, int ka, int kb, const T* sa, const T* sb, T N,
+                                           const T* D, T* acc) {
+    const T aN = fabs(N);
+    bool slow = false;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) slow |= !(aN < Arith<T>::kFast * D[r]);
+    if (__builtin_amdgcn_ballot_w64(slow) == 0ull) {
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) acc[r] += Arith<T>::atan_small(N * Arith<T>::rcp(D[r]));
+    } else {
+        const ColV<T> a = col_aux<T>(ring, ka), b = col_aux<T>(ring, kb);
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) acc[r] += edge_slow<T>(a, b, sa[r], sb[r], N, D[r], true);
+    }
+}
+
+// Edges slot ka -> kb -> kc: one arctangent for the pair where every sample of
+// the wave allows it (decided by the x/y terms alone when ok, else per sample),
+// else one by one.
+template <class T, int ZB>
+__device__ __forceinline__ void col_pair(const ColRing<T>& ring, int ka, int kb, int kc, T N1, T dot1, T N2,
+                                         T dot2, bool ok, bool pairs, const T* sa, const T* sb, const T* sc,
+                                         T* acc) {
+    using P = EdgePairs<T, ZB, false>;
+    T D1[ZB], D2[ZB];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        D1[r] = fma(sa[r], sb[r], dot1);
+        D2[r] = fma(sb[r], sc[r], dot2);
+    }
+    bool pair = ok;
+    if (!ok && pairs) {
+        const T m1 = ring.aux[ka].m, m2 = ring.aux[kb].m;
+        bool slow = false;
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) slow |= !(m1 < D1[r]) | !(m2 < D2[r]);
+        pair = __builtin_amdgcn_ballot_w64(slow) == 0ull;
+    }
+    if (pair) {
+        const T N12 = N1 * N2;
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) {
+            const T re = fma(D1[r], D2[r], -N12);
+            const T im = fma(D1[r], N2, N1 * D2[r]);
+            const T t = im * Arith<T>::rcp(re);
+            if constexpr (P::f32) acc[r] = atan_pair_acc(t, acc[r]);
+            else acc[r] += Arith<T>::atan_small(t);   // |t| < tan(pi/8)
+        }
+    } else {
+        col_finish<T, ZB>(ring, ka, kb, sa, sb, N1, D1, acc);
+        col_finish<T, ZB>(ring, kb, kc, sb, sc, N2, D2, acc);
+    }
+}
+
+// Edges a -> b -> c known to pair on their x/y terms: one arctangent, no test.
+template <class T, int ZB>
+__device__ __forceinline__ void col_pair_xy(T N1, T dot1, T N2, T dot2, const T* sa, const T* sb, const T* sc,
+                                            T* acc) {
+    const T N12 = N1 * N2;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        const T D1 = fma(sa[r], sb[r], dot1), D2 = fma(sb[r], sc[r], dot2);
+        const T re = fma(D1, D2, -N12);
+        const T im = fma(D1, N2, N1 * D2);
+        const T t = im * Arith<T>::rcp(re);
+        if constexpr (EdgePairs<T, ZB, false>::f32) acc[r] = atan_pair_acc(t, acc[r]);
+        else acc[r] += Arith<T>::atan_small(t);
+    }
+}
+
+// single edge slot ka -> kb
+template <class T, int ZB>
+__device__ __forceinline__ void col_edge(const ColRing<T>& ring, int ka, int kb, T N, T dot, const T* sa,
+                                         const T* sb, T* acc) {
+    T D[ZB];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) D[r] = fma(sa[r], sb[r], dot);
+    col_finish<T, ZB>(ring, ka, kb, sa, sb, N, D, acc);
+}
+
+// Boundary sum S for the ZB samples of each lane of a grid column inside the
+// fixed-point box (qqx, qqy: the column's quantised x, y; pzs: the samples' z in
+// cells).  Register r of the wave is a block of 64 consecutive samples, z
+// monotone in the lane.  pairs: edge pairs allowed (see near_z).  Same sums as
+// boundary_loops, in the same order: FP32 partials flushed to FP64 every 32 edges.
+template <class T, int ZB>
+__device__ __forceinline__ void column_loops(const MeshView& mv, int qqx, int qqy, const T* pzs, double* S,
+                                             bool pairs, ColRing<T>& ring) {
+    constexpr T u = (T)EdgePairs<T, ZB, false>::kUnit;
+    T pz[ZB];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) pz[r] = pzs[r] * u;
+    // the samples of a block are monotone in the lane, so its smallest z is in
+    // lane 0 or lane 63
+    T bminr[ZB];
+    bool asc = true;
+    T prev = -(T)INFINITY;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        bminr[r] = fmin(wave_lane<T>(pz[r], 0), wave_lane<T>(pz[r], 63));
+        asc &= !(bminr[r] < prev);
+        prev = bminr[r];
+    }
+    for (int l = 0; l < mv.nloops; ++l) {
+        const int b0 = mv.loop_off[l], nv = mv.loop_off[l + 1] - b0;
+        unsigned long long m0, m1;   // pair bits of the ring's two halves
+        int done = min(64, nv);
+        col_fill<T, ZB>(mv, b0, done, b0, b0 + nv, qqx, qqy, bminr, asc, pairs, ring, m0);
+        m1 = m0;
+        T sp[ZB], sq[ZB], sr[ZB];
+        T Np, dotp, Nq, dotq, Nr, dotr;
+        // the first vertex's s is computed again for the closing edge (from its
+        // copy in slot kColRing) rather than held in registers through the loop
+        const int R0 = ring_R(ring, 0);
+        col_vertex<T, ZB>(ring.rec[0], R0, pz, sp, Np, dotp);
+        int j = 1;   // vertices are counted from b0; slot of vertex j is j mod kColRing
+        while (j < nv) {
+            const int je = min(nv, j + 32);
+            if (je > done) {   // one fill covers it: j <= done, je <= j + 32
+                const int n = min(64, nv - done);
+                if (done & 64) col_fill<T, ZB>(mv, b0 + done, n, b0, b0 + nv, qqx, qqy, bminr, asc, pairs, ring, m1);
+                else col_fill<T, ZB>(mv, b0 + done, n, b0, b0 + nv, qqx, qqy, bminr, asc, pairs, ring, m0);
+                done += n;
+            }
+            T acc[ZB];
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) acc[r] = (T)0;
+            // four vertices (two edge pairs) per trip: p-q-r, then r-q-p
+            while (j + 3 < je) {
+                // trips whose four edges all pair on their x/y terms alone
+                for (; j + 3 < je && col_e(m0, m1, (j - 1) & (kColRing - 1)) &&
+                       col_e(m0, m1, j & (kColRing - 1)) && col_e(m0, m1, (j + 1) & (kColRing - 1)) &&
+                       col_e(m0, m1, (j + 2) & (kColRing - 1));
+                     j += 4) {
+                    const int kq = j & (kColRing - 1), kr = (j + 1) & (kColRing - 1);
+                    const int kq2 = (j + 2) & (kColRing - 1), kp2 = (j + 3) & (kColRing - 1);
+                    const ColRec<T> cq = ring.rec[kq], cr = ring.rec[kr], cq2 = ring.rec[kq2], cp2 = ring.rec[kp2];
+                    col_vertex<T, ZB>(cq, ring_R(ring, kq), pz, sq, Nq, dotq);
+                    col_vertex<T, ZB>(cr, ring_R(ring, kr), pz, sr, Nr, dotr);
+                    col_pair_xy<T, ZB>(Np, dotp, Nq, dotq, sp, sq, sr, acc);
+                    col_vertex<T, ZB>(cq2, ring_R(ring, kq2), pz, sq, Nq, dotq);
+                    col_vertex<T, ZB>(cp2, ring_R(ring, kp2), pz, sp, Np, dotp);
+                    col_pair_xy<T, ZB>(Nr, dotr, Nq, dotq, sr, sq, sp, acc);
+                }
+                if (j + 3 >= je) break;
+                const int kp = (j - 1) & (kColRing - 1), kq = j & (kColRing - 1);
+                const int kr = (j + 1) & (kColRing - 1), kq2 = (j + 2) & (kColRing - 1);
+                const int kp2 = (j + 3) & (kColRing - 1);
+                // the trip's four records are read up front (LDS latency)
+                const ColRec<T> cq = ring.rec[kq], cr = ring.rec[kr], cq2 = ring.rec[kq2], cp2 = ring.rec[kp2];
+                col_vertex<T, ZB>(cq, ring_R(ring, kq), pz, sq, Nq, dotq);
+                col_vertex<T, ZB>(cr, ring_R(ring, kr), pz, sr, Nr, dotr);
+                col_pair<T, ZB>(ring, kp, kq, kr, Np, dotp, Nq, dotq, col_e(m0, m1, kp) & col_e(m0, m1, kq),
+                                pairs, sp, sq, sr, acc);
+                col_vertex<T, ZB>(cq2, ring_R(ring, kq2), pz, sq, Nq, dotq);
+                col_vertex<T, ZB>(cp2, ring_R(ring, kp2), pz, sp, Np, dotp);
+                col_pair<T, ZB>(ring, kr, kq2, kp2, Nr, dotr, Nq, dotq,
+                                col_e(m0, m1, kr) & col_e(m0, m1, kq2), pairs, sr, sq, sp, acc);
+                j += 4;
+            }
+            if (j + 1 < je) {
+                const int kp = (j - 1) & (kColRing - 1), kq = j & (kColRing - 1);
+                const int kr = (j + 1) & (kColRing - 1);
+                const ColRec<T> cq = ring.rec[kq], cr = ring.rec[kr];
+                col_vertex<T, ZB>(cq, ring_R(ring, kq), pz, sq, Nq, dotq);
+                col_vertex<T, ZB>(cr, ring_R(ring, kr), pz, sr, Nr, dotr);
+                col_pair<T, ZB>(ring, kp, kq, kr, Np, dotp, Nq, dotq, col_e(m0, m1, kp) & col_e(m0, m1, kq),
+                                pairs, sp, sq, sr, acc);
+                Np = Nr;
+                dotp = dotr;
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) sp[r] = sr[r];
+                j += 2;
+            }
+            if (j < je) {
+                const int kp = (j - 1) & (kColRing - 1), kq = j & (kColRing - 1);
+                col_vertex<T, ZB>(ring.rec[kq], ring_R(ring, kq), pz, sq, Nq, dotq);
+                col_edge<T, ZB>(ring, kp, kq, Np, dotp, sp, sq, acc);
+                Np = Nq;
+                dotp = dotq;
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) sp[r] = sq[r];
+                ++j;
+            }
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) S[r] += (double)acc[r];
+        }
+        // closing edge, last vertex -> first (kept in slot kColRing)
+        T acc[ZB], sf[ZB], Nf, dotf;
+        col_vertex<T, ZB>(ring.rec[kColRing], R0, pz, sf, Nf, dotf);
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) acc[r] = (T)0;
+        col_edge<T, ZB>(ring, (nv - 1) & (kColRing - 1), kColRing, Np, dotp, sp, sf, acc);
 #pragma unroll
         for (int r = 0; r < ZB; ++r) S[r] += (double)acc[r];
     }

@@ -234,6 +234,7 @@ __global__ __launch_bounds__(64 * kGridWaves)
 __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && ZB == 8) || (sizeof(T) == 8 && ZB == 4) ? 4 : 1))) void k_grid(MeshView mv, GridArgs ga, int* __restrict__ chi_out,
                                                           T* __restrict__ w) {
     __shared__ int wstack[kGridWaves][kLdsStack];
+    __shared__ ColRing<T> ring[kGridWaves];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const long long gw = ga.wave0 + (long long)blockIdx.x * kGridWaves + wave;
@@ -308,7 +309,7 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && ZB == 8) || (sizeof(T) == 
             near &= near_z(pz[r], mv.g);
         }
         near = __builtin_amdgcn_ballot_w64(!near) == 0ull;   // one choice for the whole column
-        boundary_loops<T, ZB, false, true>(mv, q0.x, q0.y, (T)0, (T)0, pzs, S, (T)1, near);
+        column_loops<T, ZB>(mv, q0.x, q0.y, pzs, S, near, ring[wave]);
     } else {
         float pzm = 0.f;
 #pragma unroll
