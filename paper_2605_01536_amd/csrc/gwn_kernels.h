@@ -287,11 +287,10 @@ __device__ __forceinline__ bool near_z(float pz, const QGrid& g) {
 }
 
 // Edges a -> b -> c for ZB samples: as one pair where allowed, else one by one.
-// COL (a grid column): the choice is wave-uniform.  Otherwise each lane chooses
-// for its own point, so a point's result does not depend on which points share
-// its wave (the single-edge fast and exact forms agree bit for bit where
-// |N| < D, so their wave-uniform choice never mattered).
-template <class T, int ZB, bool FAR, bool COL>
+// Each lane chooses for its own point, so a point's result does not depend on
+// which points share its wave (the single-edge fast and exact forms agree bit
+// for bit where |N| < D, so their wave-uniform choice never mattered).
+template <class T, int ZB, bool FAR>
 __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, const ColV<T>& c, const T* sa,
                                           const T* sb, const T* sc, T* acc,
                                           bool pairs) {
@@ -310,18 +309,10 @@ __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, co
             D1[r] = fma(sa[r], sb[r], dot1);
             D2[r] = fma(sb[r], sc[r], dot2);
         }
-        bool pair;
-        // D = s_a s_b + dot >= dot (s >= 0, rounding is monotone), so in a column
-        // the x/y terms alone usually settle the test for every sample at once
-        if (COL && __builtin_amdgcn_ballot_w64(!((m1 < dot1) & (m2 < dot2) & pairs)) == 0ull) {
-            pair = true;
-        } else {
-            bool slow = !pairs;
+        bool slow = !pairs;
 #pragma unroll
-            for (int r = 0; r < ZB; ++r) slow |= !(m1 < D1[r]) | !(m2 < D2[r]);
-            pair = COL ? __builtin_amdgcn_ballot_w64(slow) == 0ull : !slow;
-        }
-        if (pair) {
+        for (int r = 0; r < ZB; ++r) slow |= !(m1 < D1[r]) | !(m2 < D2[r]);
+        if (!slow) {
             const T N12 = N1 * N2;
 #pragma unroll
             for (int r = 0; r < ZB; ++r) {
@@ -395,62 +386,34 @@ struct BlockMin {
 };
 
 // pzs: the samples' z in offset units (cells times EdgePairs' kUnit inside the box)
-template <class T, int ZB, bool FAR, bool COL = false>
+template <class T, int ZB, bool FAR>
 __device__ __forceinline__ void load_vertex(const BVert& b, int qqx, int qqy, T pxs, T pys, const T* pzs, T f,
-                                            ColV<T>& c, T* sv, const BlockMin<T>* bm = nullptr) {
+                                            ColV<T>& c, T* sv) {
     c = col_vtx<T, ZB, FAR>(b, qqx, qqy, pxs, pys, f);
     constexpr T u = (T)EdgePairs<T, ZB, FAR>::kUnit;
-    T rz[ZB];
-    if constexpr (COL && !FAR) {
 #pragma unroll
-        for (int r = 0; r < ZB; ++r) {
-            rz[r] = u == (T)1 ? (T)b.z - pzs[r] : fma((T)b.z, u, -pzs[r]);
-            sv[r] = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2) + fabs(rz[r]);   // t, made s in place
-        }
-        const T d = u == (T)1 ? (T)b.z - bm->bmin : fma((T)b.z, u, -bm->bmin);
-        const int R = bm->asc ? __builtin_popcountll(__builtin_amdgcn_ballot_w64(d > (T)0)) : ZB + 1;
-        s_prefix<T, ZB>(R, rz, c.rho2, sv);
-    } else {
-#pragma unroll
-        for (int r = 0; r < ZB; ++r) {
-            rz[r] = FAR ? fma((T)b.z, f, -pzs[r]) : (u == (T)1 ? (T)b.z - pzs[r] : fma((T)b.z, u, -pzs[r]));
-            sv[r] = samp_s<T>(c.rho2, rz[r]);
-        }
+    for (int r = 0; r < ZB; ++r) {
+        const T rz = FAR ? fma((T)b.z, f, -pzs[r]) : (u == (T)1 ? (T)b.z - pzs[r] : fma((T)b.z, u, -pzs[r]));
+        sv[r] = samp_s<T>(c.rho2, rz);
     }
 }
 
 // Boundary sum S = sum of atan2 over the chained loops for ZB samples sharing one
 // (x, y).  FP32 partials are flushed into the FP64 sum every 32 edges.  pzs in
-// cells inside the box (FAR: in units of 2^e cells).  COL: the wave is a grid
-// column whose register r holds 64 consecutive samples, z monotone in the lane.
-// pairs: this lane's samples may take edge pairs (see near_z).
-template <class T, int ZB, bool FAR, bool COL = false>
+// cells inside the box (FAR: in units of 2^e cells).  pairs: this lane's
+// samples may take edge pairs (see near_z).  (Grid columns use column_loops.)
+template <class T, int ZB, bool FAR>
 __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int qqy, T pxs, T pys, const T* pzs,
                                                double* S, T f = (T)1, bool pairs = true) {
     const BVert* __restrict__ bv = mv.bverts;
     T pz[ZB];
 #pragma unroll
     for (int r = 0; r < ZB; ++r) pz[r] = FAR ? pzs[r] : pzs[r] * (T)EdgePairs<T, ZB, FAR>::kUnit;
-    BlockMin<T> bmv{(T)INFINITY, true};
-    const BlockMin<T>* bm = &bmv;
-    if constexpr (COL && !FAR) {
-        // the samples of a block are monotone in the lane, so its smallest z is in
-        // lane 0 or lane 63
-        const int lane = (int)(threadIdx.x & 63);
-        T prev = -(T)INFINITY;
-#pragma unroll
-        for (int r = 0; r < ZB; ++r) {
-            const T m = fmin(wave_lane<T>(pz[r], 0), wave_lane<T>(pz[r], 63));
-            if (lane == r) bmv.bmin = m;
-            bmv.asc &= !(m < prev);
-            prev = m;
-        }
-    }
     for (int l = 0; l < mv.nloops; ++l) {
         const int b0 = mv.loop_off[l], b1 = mv.loop_off[l + 1];
         ColV<T> cf, cp, cq, cr;
         T sf[ZB], sp[ZB], sq[ZB], sr[ZB];
-        load_vertex<T, ZB, FAR, COL>(bv[b0], qqx, qqy, pxs, pys, pz, f, cf, sf, bm);
+        load_vertex<T, ZB, FAR>(bv[b0], qqx, qqy, pxs, pys, pz, f, cf, sf);
         cp = cf;
 #pragma unroll
         for (int r = 0; r < ZB; ++r) {
@@ -465,17 +428,17 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
             // four vertices (two edge pairs) per trip: p-q-r, then r-q-p with q and p
             // reloaded, so the loop-carried vertex ends in the set it started in
             for (; j + 3 < je; j += 4) {
-                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, sq, bm);
-                load_vertex<T, ZB, FAR, COL>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, sr, bm);
-                edge_pair<T, ZB, FAR, COL>(cp, cq, cr, sp, sq, sr, acc, pairs);
-                load_vertex<T, ZB, FAR, COL>(bv[j + 2], qqx, qqy, pxs, pys, pz, f, cq, sq, bm);
-                load_vertex<T, ZB, FAR, COL>(bv[j + 3], qqx, qqy, pxs, pys, pz, f, cp, sp, bm);
-                edge_pair<T, ZB, FAR, COL>(cr, cq, cp, sr, sq, sp, acc, pairs);
+                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, sq);
+                load_vertex<T, ZB, FAR>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, sr);
+                edge_pair<T, ZB, FAR>(cp, cq, cr, sp, sq, sr, acc, pairs);
+                load_vertex<T, ZB, FAR>(bv[j + 2], qqx, qqy, pxs, pys, pz, f, cq, sq);
+                load_vertex<T, ZB, FAR>(bv[j + 3], qqx, qqy, pxs, pys, pz, f, cp, sp);
+                edge_pair<T, ZB, FAR>(cr, cq, cp, sr, sq, sp, acc, pairs);
             }
             if (j + 1 < je) {
-                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, sq, bm);
-                load_vertex<T, ZB, FAR, COL>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, sr, bm);
-                edge_pair<T, ZB, FAR, COL>(cp, cq, cr, sp, sq, sr, acc, pairs);
+                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, sq);
+                load_vertex<T, ZB, FAR>(bv[j + 1], qqx, qqy, pxs, pys, pz, f, cr, sr);
+                edge_pair<T, ZB, FAR>(cp, cq, cr, sp, sq, sr, acc, pairs);
                 cp = cr;
 #pragma unroll
                 for (int r = 0; r < ZB; ++r) {
@@ -484,7 +447,7 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
                 j += 2;
             }
             if (j < je) {
-                load_vertex<T, ZB, FAR, COL>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, sq, bm);
+                load_vertex<T, ZB, FAR>(bv[j], qqx, qqy, pxs, pys, pz, f, cq, sq);
                 edge_step<T, ZB, FAR>(cp, cq, sp, sq, acc);
                 cp = cq;
 #pragma unroll

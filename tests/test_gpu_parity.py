@@ -120,6 +120,51 @@ def test_grid_small_mesh_all_points(gwn, prec, dims):
     assert float((wb.double() - w.double()).abs().max()) < (1e-6 if prec == "fp32" else 1e-12)
 
 
+def _fans(lengths, seed):
+    """One triangle fan per entry: a wavy polygon of L boundary vertices around a
+    raised centre, the fans scattered over [-1, 1]^3 (boundary loops of exactly
+    those lengths)."""
+    rng = np.random.default_rng(seed)
+    Vs, Fs, nv = [], [], 0
+    for k, L in enumerate(lengths):
+        c = rng.uniform(-0.6, 0.6, size=3)
+        r = rng.uniform(0.15, 0.4)
+        a = np.sort(rng.uniform(0, 2 * np.pi, size=L)) if k % 2 else np.linspace(0, 2 * np.pi, L, endpoint=False)
+        ring = np.stack([c[0] + r * np.cos(a), c[1] + r * np.sin(a) * rng.uniform(0.5, 1.0),
+                         c[2] + 0.3 * r * np.sin(3 * a + k)], axis=1)
+        V = np.concatenate([ring, [c + [0, 0, rng.uniform(-0.2, 0.2)]]])
+        F = np.stack([np.arange(L), (np.arange(L) + 1) % L, np.full(L, L)], axis=1)
+        if k % 3 == 1:
+            F = F[:, [1, 0, 2]]                         # the other orientation
+        Vs.append(V)
+        Fs.append(F + nv)
+        nv += L + 1
+    return np.concatenate(Vs).astype(np.float32), np.concatenate(Fs).astype(np.int32)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("zb", ["1", "8"])
+def test_grid_long_boundary_loops(gwn, monkeypatch, prec, zb):
+    # boundary loops around the lengths where the grid kernel's vertex ring fills
+    # (64 vertices at a time), wraps (128 slots) and flushes (32 edges), and
+    # pairs its edges four at a time, plus single-edge and short loops
+    lengths = [3, 4, 5, 31, 32, 33, 34, 63, 64, 65, 66, 127, 128, 129, 130, 131, 191, 192, 193, 256, 257, 300]
+    V, F = _fans(lengths, seed=77)
+    monkeypatch.setenv("GWN_GRID_SAMPLES_PER_LANE", zb)
+    m = gwn.Mesh(_dev(V), _dev(F))
+    info = m.info()
+    assert info["nloops"] == len(lengths) and info["nboundary"] == sum(lengths)
+    g = W.GridSpec(origin=(-1.0, -0.93, -1.07), spacing=(2.0 / 15, 1.9 / 13, 2.1 / 200), dims=(15, 13, 200))
+    w, chi = gwn.query_grid(m, g.origin, g.spacing, g.dims, prec=prec, want_chi=True)
+    torch.cuda.synchronize()
+    P = W.grid_points(g)
+    compare(w.cpu().numpy(), chi.cpu().numpy(), V, F, P, TOL_FP32 if prec == "fp32" else TOL_FP64,
+            f"fans-zb{zb}-{prec}")
+    wb, cb = gwn.query_batch(m, _dev(P), prec=prec, want_chi=True)
+    assert torch.equal(cb, chi)
+    assert float((wb.double() - w.double()).abs().max()) < (1e-6 if prec == "fp32" else 1e-12)
+
+
 def test_grid_full_size_sampled(gwn):
     # the 1M-triangle soup on the 512^3 grid the benchmark times; sampled outputs
     s, g = W.config4()
