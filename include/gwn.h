@@ -213,7 +213,8 @@ gwn_status gwn_query_direct(gwn_mesh m, const float* qx, const float* qy, const 
  * captures one HIP graph: reset of a work counter, crossing counts for every
  * query, and a persistent kernel whose waves claim items from the counter.
  * With opts->autotune the candidate schedules (tile size, item order, resident
- * waves) are timed on the real inputs and the fastest is kept; with
+ * waves, and the best of those with each mesh's queries in Morton order) are
+ * timed on the real inputs and the fastest is kept; with
  * opts->tune_cache a previously stored choice for the same device and problem
  * size class is reused (and a new choice is appended).  Tuning runs the plan,
  * so it writes w_out / chi_out.
@@ -223,14 +224,17 @@ gwn_status gwn_query_direct(gwn_mesh m, const float* qx, const float* qy, const 
  * (float, FP32 path only) and chi_out (nullable; the plan then owns a scratch
  * buffer) alive and unchanged in size until gwn_multi_destroy.  The meshes must
  * outlive the plan.  Errors: GWN_E_INVALID for bad arguments or meshes from
- * another device, GWN_E_UNSUPPORTED for prec != GWN_PREC_FP32.
+ * another device or an order outside 0..3, GWN_E_UNSUPPORTED for
+ * prec != GWN_PREC_FP32.
  */
 typedef struct gwn_multi_s* gwn_multi;
 
 typedef struct {
     int32_t item_queries;     /* queries per work item, rounded up to a multiple of 64; 0 = default or tuned */
     int32_t waves_per_simd;   /* resident persistent waves per SIMD, 1..8; 0 = default or tuned */
-    int32_t order;            /* 0 = largest estimated cost first, 1 = mesh order */
+    int32_t order;            /* 0 = largest estimated cost first, 1 = mesh order; +2: each mesh's queries
+                                 taken in Morton order of their quantised x, y (a permutation made once at
+                                 creation from the query values then; results are the same bits either way) */
     int32_t autotune;         /* nonzero: time candidate schedules at creation and keep the fastest */
     const char* tune_cache;   /* nullable JSON-lines file read before tuning and appended after */
 } gwn_multi_opts;

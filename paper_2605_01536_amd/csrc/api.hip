@@ -283,6 +283,10 @@ gwn_status gwn_multi_create(const gwn_mesh* meshes, int32_t nmesh, const float* 
         gwn::set_error("gwn_multi_create: too many queries");
         return GWN_E_INVALID;
     }
+    if (opts && (opts->order < 0 || opts->order > 3)) {
+        gwn::set_error("gwn_multi_create: opts->order must be 0, 1, 2 or 3");
+        return GWN_E_INVALID;
+    }
     return gwn::multi_create(meshes, nmesh, qx, qy, qz, qstride, q_offsets, prec, w_out, chi_out, opts,
                              (hipStream_t)stream, out);
 }

@@ -5,7 +5,10 @@
 // counter, largest estimated cost first, so meshes whose cost spans orders of
 // magnitude share the GPU without a long tail.  The schedule (tile size, item
 // order, resident waves) is chosen by timing candidates (autotune) and can be
-// cached in a JSON-lines file keyed by device and problem size.
+// cached in a JSON-lines file keyed by device and problem size.  Optionally the
+// queries of each mesh are taken in Morton order of their quantised x, y (an
+// index permutation made once at creation), so that the 64 queries of a wave
+// lie close together and take the same branches of the boundary loop.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -56,14 +59,21 @@ __global__ __launch_bounds__(kMultiChiBlock) void k_chi_multi(const MeshView* __
     chi[i] = q.inbox ? chi_up(mv, q, stk + threadIdx.x) : 0;
 }
 
+// global query index i0 + perm_local[i - i0] for i in [i0, i0 + n)
+__global__ void k_perm_offset(const int* __restrict__ local, long long i0, int n, int* __restrict__ perm) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < n) perm[i0 + k] = (int)(i0 + (local ? local[k] : k));
+}
+
 // Persistent boundary-term kernel: every wave claims items until none are left
-// (the counter only grows, so every wave reaches the exit).
+// (the counter only grows, so every wave reaches the exit).  perm (nullable):
+// position i of the work list is query perm[i], a permutation within each mesh.
 __global__ __launch_bounds__(256) void k_bdry_persistent(const MeshView* __restrict__ table,
                                                          const Item* __restrict__ items, int nitems,
                                                          int* __restrict__ counter, const float* __restrict__ qx,
                                                          const float* __restrict__ qy, const float* __restrict__ qz,
-                                                         long long qs, const int* __restrict__ chi,
-                                                         float* __restrict__ w) {
+                                                         long long qs, const int* __restrict__ perm,
+                                                         const int* __restrict__ chi, float* __restrict__ w) {
     const int lane = threadIdx.x & 63;
     while (true) {
         int it = 0;
@@ -76,7 +86,8 @@ __global__ __launch_bounds__(256) void k_bdry_persistent(const MeshView* __restr
         axis_ptrs(mv.axis, x, y, z);   // the mesh's frame
         for (int sub = 0; sub < I.nq; sub += 64) {
             const int k = sub + lane;
-            const long long i = I.q0 + min(k, I.nq - 1);
+            const long long i0 = I.q0 + min(k, I.nq - 1);
+            const long long i = perm ? (long long)perm[i0] : i0;
             const float px = x[i * qs], py = y[i * qs], pz = z[i * qs];
             const QPoint q = quantize_point(px, py, pz, mv.g);
             double S = 0.0;
@@ -96,8 +107,10 @@ __global__ __launch_bounds__(256) void k_bdry_persistent(const MeshView* __restr
 struct Schedule {
     int item_queries = 128;   // multiple of 64
     int waves_per_simd = 8;   // resident persistent waves per SIMD
-    int order = 0;            // 0: largest cost first; 1: mesh order
+    int order = 0;            // bit 0: mesh order (else largest cost first); bit 1: queries in Morton order
 };
+
+constexpr int kOrderMesh = 1, kOrderSorted = 2;
 
 }  // namespace
 }  // namespace gwn
@@ -121,6 +134,7 @@ struct gwn_multi_s {
     long long* qoff = nullptr;
     gwn::Item* items = nullptr;
     int nitems = 0;
+    int* perm = nullptr;   // Morton order of each mesh's queries (made when a schedule asks for it)
     int* counter = nullptr;
     int grid = 0;
     hipStream_t cap = nullptr;
@@ -145,6 +159,7 @@ void release(gwn_multi_s* p) {
     (void)hipFree(p->table);
     (void)hipFree(p->qoff);
     (void)hipFree(p->items);
+    (void)hipFree(p->perm);
     (void)hipFree(p->counter);
     if (p->own_chi) (void)hipFree(p->chi);
     delete p;
@@ -167,7 +182,7 @@ gwn_status build_items(gwn_multi_s* p, const Schedule& s, hipStream_t st) {
             cost.push_back(per_q * it.nq);
         }
     }
-    if (s.order == 0) {
+    if (!(s.order & kOrderMesh)) {
         std::vector<size_t> idx(h.size());
         for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
         std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
@@ -185,6 +200,31 @@ gwn_status build_items(gwn_multi_s* p, const Schedule& s, hipStream_t st) {
     return GWN_OK;
 }
 
+// Each mesh's queries in Morton order of their quantised x, y in the mesh's
+// frame (the batch path's traversal order), as one permutation of all queries.
+gwn_status build_perm(gwn_multi_s* p, hipStream_t st) {
+    if (p->perm) return GWN_OK;
+    GWN_HIP_TRY(hipMalloc((void**)&p->perm, sizeof(int) * (size_t)std::max<long long>(1, p->nq)));
+    for (int m = 0; m < p->nmesh; ++m) {
+        const long long q0 = p->qoff_h[m], n = p->qoff_h[m + 1] - q0;
+        if (n <= 0) continue;
+        const float *x = p->qx, *y = p->qy, *z = p->qz;
+        axis_ptrs(p->meshes[m]->axis, x, y, z);
+        int* local = nullptr;
+        if (n > 1) {
+            const gwn_status r = xy_order(p->meshes[m], x + q0 * p->qs, y + q0 * p->qs, z + q0 * p->qs, p->qs, n,
+                                          &local, st);
+            if (r != GWN_OK) return r;
+        }
+        k_perm_offset<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(local, q0, (int)n, p->perm);
+        const hipError_t e = hipGetLastError();
+        if (local) (void)hipFreeAsync(local, st);
+        GWN_HIP_TRY(e);
+    }
+    GWN_HIP_TRY(hipStreamSynchronize(st));
+    return GWN_OK;
+}
+
 gwn_status capture(gwn_multi_s* p, const Schedule& s) {
     drop_graph(p);
     int ncu = 0;
@@ -198,7 +238,8 @@ gwn_status capture(gwn_multi_s* p, const Schedule& s) {
         k_chi_multi<<<(unsigned)((p->nq + kMultiChiBlock - 1) / kMultiChiBlock), kMultiChiBlock, 0, p->cap>>>(
             p->table, p->qoff, p->nmesh, p->qx, p->qy, p->qz, p->qs, p->chi);
         k_bdry_persistent<<<p->grid, 256, 0, p->cap>>>(p->table, p->items, p->nitems, p->counter, p->qx, p->qy,
-                                                       p->qz, p->qs, p->chi, p->w);
+                                                       p->qz, p->qs, (s.order & kOrderSorted) ? p->perm : nullptr,
+                                                       p->chi, p->w);
     }
     hipError_t e = hipStreamEndCapture(p->cap, &p->graph);
     GWN_HIP_TRY(e);
@@ -206,8 +247,11 @@ gwn_status capture(gwn_multi_s* p, const Schedule& s) {
     return GWN_OK;
 }
 
-gwn_status apply(gwn_multi_s* p, const Schedule& s, hipStream_t st) {
-    gwn_status r = build_items(p, s, st);
+gwn_status apply(gwn_multi_s* p, Schedule s, hipStream_t st) {
+    if (p->nq > 0x7fffffffll) s.order &= ~kOrderSorted;   // the permutation holds 32-bit indices
+    gwn_status r = (s.order & kOrderSorted) ? build_perm(p, st) : GWN_OK;
+    if (r != GWN_OK) return r;
+    r = build_items(p, s, st);
     if (r != GWN_OK) return r;
     r = capture(p, s);
     if (r != GWN_OK) return r;
@@ -257,7 +301,7 @@ bool cache_lookup(const char* path, const std::string& key, Schedule* s) {
         if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"item_queries\": %d, \"waves_per_simd\": %d, \"order\": %d",
                         k, &t.item_queries, &t.waves_per_simd, &t.order) == 4 &&
             key == k && t.item_queries >= 64 && t.item_queries % 64 == 0 && t.waves_per_simd >= 1 &&
-            t.waves_per_simd <= 8 && (t.order == 0 || t.order == 1)) {
+            t.waves_per_simd <= 8 && t.order >= 0 && t.order <= 3) {
             *s = t;
             found = true;   // the last matching line wins
         }
@@ -321,7 +365,7 @@ gwn_status multi_create(const gwn_mesh* meshes, int nmesh, const float* qx, cons
     const bool explicit_sched = opts && (opts->item_queries > 0 || opts->waves_per_simd > 0 || opts->order > 0);
     if (opts && opts->item_queries > 0) s.item_queries = ((opts->item_queries + 63) / 64) * 64;
     if (opts && opts->waves_per_simd > 0) s.waves_per_simd = std::min(8, opts->waves_per_simd);
-    if (opts && opts->order > 0) s.order = 1;
+    if (opts && opts->order > 0) s.order = opts->order & 3;
     const char* cache = opts ? opts->tune_cache : nullptr;
     const std::string key = cache_key(p);
     Schedule cached;
@@ -351,6 +395,18 @@ gwn_status multi_create(const gwn_mesh* meshes, int nmesh, const float* qx, cons
                         bs = c;
                     }
                 }
+        // the best schedule again with each mesh's queries in Morton order
+        Schedule c = bs;
+        c.order |= kOrderSorted;
+        gwn_status r = apply(p, c, st);
+        if (r != GWN_OK) return r;
+        double ms = 0.0;
+        r = time_replay(p, st, &ms);
+        if (r != GWN_OK) return r;
+        if (ms < best) {
+            best = ms;
+            bs = c;
+        }
         s = bs;
         p->tuned = true;
         p->tuned_ms = best;

@@ -69,13 +69,17 @@ def test_multi_far_and_mixed_queries(gwn, monkeypatch):
 
 @pytest.mark.parametrize("sched", [dict(item_queries=64, waves_per_simd=1, order=1),
                                    dict(item_queries=512, waves_per_simd=8, order=0),
-                                   dict(item_queries=100, waves_per_simd=3, order=0)])
+                                   dict(item_queries=100, waves_per_simd=3, order=0),
+                                   dict(item_queries=128, waves_per_simd=8, order=2),
+                                   dict(item_queries=64, waves_per_simd=4, order=3)])
 def test_schedules_agree(gwn, sched):
     soups, queries, meshes, offs, Q = _batch_of(gwn, 12, seed=34)
     ref = gwn.MultiPlan(meshes, Q, offs).run().clone()
     p = gwn.MultiPlan(meshes, Q, offs, **sched)
     inf = p.info()
-    assert inf["item_queries"] % 64 == 0 and inf["nitems"] > 0
+    assert inf["item_queries"] % 64 == 0 and inf["nitems"] > 0 and inf["order"] == sched["order"]
+    # the same bits whatever the schedule, Morton-ordered queries included
+    assert torch.equal(p.run(), ref)
     assert torch.equal(p.run(), ref)
 
 
@@ -114,3 +118,7 @@ def test_multi_rejects_bad_arguments(gwn):
         gwn.MultiPlan(meshes, Q, [1] + list(offs[1:]))
     with pytest.raises(gwn.GwnError):
         gwn.MultiPlan(meshes, Q, [0, 10, 5, int(offs[-1])])
+    for bad in (4, -1):
+        with pytest.raises(gwn.GwnError) as ei:
+            gwn.MultiPlan(meshes, Q, offs, order=bad)
+        assert ei.value.status == 1
