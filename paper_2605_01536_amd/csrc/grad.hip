@@ -54,27 +54,6 @@ __device__ __forceinline__ void gsamp(const BVert& b, const GCol<T>& c, T pzs, T
     s = rz > (T)0 ? c.rho2 * Arith<T>::rcp(t) : t;
 }
 
-// u and s of one vertex for the ZB samples of a grid column whose register r is
-// a block of 64 consecutive samples (lane order, z ascending when bm->asc):
-// blocks wholly at or above the vertex take s = l + |r_z|, blocks wholly below
-// it s = rho^2 / (l + r_z), the block the vertex's height falls in the two-sided
-// form (the block counting is the w kernel's; r_z is the same fma in both).
-template <class T, int ZB>
-__device__ __forceinline__ void gsamp_blocks(const BVert& b, const GCol<T>& c, const T* pzs, T f,
-                                             const BlockMin<T>& bm, T* u, T* s) {
-    T rz[ZB];
-#pragma unroll
-    for (int r = 0; r < ZB; ++r) {
-        rz[r] = fma((T)b.z, f, -pzs[r]);
-        const T l = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2);
-        u[r] = Arith<T>::rcp(l);
-        s[r] = l + fabs(rz[r]);   // t, made s in place
-    }
-    const T d = fma((T)b.z, f, -bm.bmin);
-    const int R = bm.asc ? __builtin_popcountll(__builtin_amdgcn_ballot_w64(d > (T)0)) : ZB + 1;
-    s_prefix<T, ZB>(R, rz, c.rho2, s);
-}
-
 // one edge (a -> b) for one sample; N, dot and grad N come from x/y only
 template <class T>
 __device__ __forceinline__ void gedge(const GCol<T>& a, const GCol<T>& b, T N, T dot, T gNx, T gNy, T ua, T sa,
@@ -95,9 +74,8 @@ __device__ __forceinline__ void gedge(const GCol<T>& a, const GCol<T>& b, T N, T
 // Sum over all loops of the edge terms for ZB samples on one vertical line, in
 // cell units (FP32 partials flushed into FP64 every 32 edges).  FLIP: the
 // mirrored sum for the axis x0 = -z.
-template <class T, int ZB, bool FLIP, bool COL = false>
-__device__ void grad_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, double (*G)[3],
-                           const BlockMin<T>* bm = nullptr) {
+template <class T, int ZB, bool FLIP>
+__device__ void grad_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, double (*G)[3]) {
     const BVert* __restrict__ bv = mv.bverts;
 #pragma unroll
     for (int r = 0; r < ZB; ++r) G[r][0] = G[r][1] = G[r][2] = 0.0;
@@ -105,12 +83,8 @@ __device__ void grad_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, 
         const int b0 = mv.loop_off[lp], b1 = mv.loop_off[lp + 1];
         const GCol<T> cf = gcol<T>(bv[b0], pxs, pys, f);
         T uf[ZB], sf[ZB];
-        if constexpr (COL && !FLIP) {
-            gsamp_blocks<T, ZB>(bv[b0], cf, pzs, f, *bm, uf, sf);
-        } else {
 #pragma unroll
-            for (int r = 0; r < ZB; ++r) gsamp<T, FLIP>(bv[b0], cf, pzs[r], f, uf[r], sf[r]);
-        }
+        for (int r = 0; r < ZB; ++r) gsamp<T, FLIP>(bv[b0], cf, pzs[r], f, uf[r], sf[r]);
         GCol<T> cp = cf;
         T up[ZB], sp[ZB];
 #pragma unroll
@@ -134,12 +108,8 @@ __device__ void grad_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, 
                 }
                 if (jj < b1) {
                     cc = gcol<T>(bv[jj], pxs, pys, f);
-                    if constexpr (COL && !FLIP) {
-                        gsamp_blocks<T, ZB>(bv[jj], cc, pzs, f, *bm, uc, sc);
-                    } else {
 #pragma unroll
-                        for (int r = 0; r < ZB; ++r) gsamp<T, FLIP>(bv[jj], cc, pzs[r], f, uc[r], sc[r]);
-                    }
+                    for (int r = 0; r < ZB; ++r) gsamp<T, FLIP>(bv[jj], cc, pzs[r], f, uc[r], sc[r]);
                 }
                 const T N = cp.ry * cc.rx - cp.rx * cc.ry;
                 const T dot = cp.rx * cc.rx + cp.ry * cc.ry;
@@ -164,6 +134,152 @@ __device__ void grad_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, 
         for (int r = 0; r < ZB; ++r) {
             G[r][0] = -G[r][0];
             G[r][1] = -G[r][1];
+        }
+    }
+}
+
+// Grid columns: a boundary vertex's x/y terms (its offsets, rho^2, and N, the
+// x/y dot and grad N of its outgoing edge) are the same for every sample of a
+// column's wave, so they are computed for 64 vertices at a time, one per lane,
+// into a ring of records in LDS that the whole wave reads back (as for w; the
+// ring's slots, fills and closing slot follow column_loops).
+template <class T>
+struct alignas(4 * sizeof(T)) GRec {
+    T z;      // vertex z as stored (offset units once times f)
+    T rho2;
+    T rx, ry;
+};
+
+template <class T>
+struct alignas(4 * sizeof(T)) GEdge {   // the vertex's outgoing edge
+    T N, dot, gNx, gNy;
+};
+
+template <class T>
+struct GRing {
+    GRec<T> v[kColRing + 1];
+    GEdge<T> e[kColRing + 1];
+    int R[kColRing + 1];   // blocks of the column with a sample below the vertex (see BlockMin)
+};
+
+template <class T, int ZB>
+__device__ __forceinline__ void grad_fill(const MeshView& mv, int v0, int n, int b0, int b1, T pxs, T pys, T f,
+                                          const T* bminr, bool asc, GRing<T>& ring) {
+    const int lane = (int)(threadIdx.x & 63);
+    if (lane < n) {
+        const int v = v0 + lane;
+        const int vn = v + 1 < b1 ? v + 1 : b0;
+        const BVert a = mv.bverts[v], b = mv.bverts[vn];
+        const GCol<T> ca = gcol<T>(a, pxs, pys, f), cb = gcol<T>(b, pxs, pys, f);
+        GRec<T> rv;
+        rv.z = (T)a.z;
+        rv.rho2 = ca.rho2;
+        rv.rx = ca.rx;
+        rv.ry = ca.ry;
+        GEdge<T> re;
+        re.N = ca.ry * cb.rx - ca.rx * cb.ry;
+        re.dot = ca.rx * cb.rx + ca.ry * cb.ry;
+        re.gNx = cb.ry - ca.ry;
+        re.gNy = ca.rx - cb.rx;
+        int R = ZB + 1;
+        if (asc) {
+            R = 0;
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) R += fma((T)a.z, f, -bminr[r]) > (T)0;
+        }
+        const int k = (v - b0) & (kColRing - 1);
+        ring.v[k] = rv;
+        ring.e[k] = re;
+        ring.R[k] = R;
+        if (v == b0) {
+            ring.v[kColRing] = rv;
+            ring.e[kColRing] = re;
+            ring.R[kColRing] = R;
+        }
+    }
+    // the wave reads what its own lanes wrote; LDS operations of a wave complete in order
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// u = 1/l and s of one ring vertex for the ZB samples: blocks wholly at or above
+// the vertex take s = l + |r_z|, blocks wholly below it s = rho^2 / (l + r_z),
+// the block the vertex's height falls in the two-sided form (the block count is
+// the w kernel's; r_z is the same fma in both)
+template <class T, int ZB>
+__device__ __forceinline__ void grad_vertex(const GRec<T>& c, int R, const T* pzs, T f, T* u, T* s) {
+    T rz[ZB];
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        rz[r] = fma(c.z, f, -pzs[r]);
+        const T l = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2);
+        u[r] = Arith<T>::rcp(l);
+        s[r] = l + fabs(rz[r]);   // t, made s in place
+    }
+    s_prefix<T, ZB>(R, rz, c.rho2, s);
+}
+
+// grad_loops for a grid column (x0 = +z), register r of the wave a block of 64
+// consecutive samples with z monotone in the lane; same sums in the same order.
+template <class T, int ZB>
+__device__ void grad_column_loops(const MeshView& mv, T pxs, T pys, const T* pzs, T f, double (*G)[3],
+                                  GRing<T>& ring) {
+    T bminr[ZB];
+    bool asc = true;
+    T prev = -(T)INFINITY;
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) {
+        bminr[r] = fmin(wave_lane<T>(pzs[r], 0), wave_lane<T>(pzs[r], 63));
+        asc &= !(bminr[r] < prev);
+        prev = bminr[r];
+    }
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) G[r][0] = G[r][1] = G[r][2] = 0.0;
+    for (int lp = 0; lp < mv.nloops; ++lp) {
+        const int b0 = mv.loop_off[lp], nv = mv.loop_off[lp + 1] - b0;
+        int done = min(64, nv);
+        grad_fill<T, ZB>(mv, b0, done, b0, b0 + nv, pxs, pys, f, bminr, asc, ring);
+        T up[ZB], sp[ZB];
+        grad_vertex<T, ZB>(ring.v[0], __builtin_amdgcn_readfirstlane(ring.R[0]), pzs, f, up, sp);
+        T prx = ring.v[0].rx, pry = ring.v[0].ry;
+        // edge j leads from vertex j - 1 to vertex j; j = nv closes the loop
+        for (int j = 1; j <= nv; j += 32) {
+            const int je = min(nv + 1, j + 32);
+            if (min(je, nv) > done) {   // one fill covers it: j <= done, je <= j + 32
+                const int n = min(64, nv - done);
+                grad_fill<T, ZB>(mv, b0 + done, n, b0, b0 + nv, pxs, pys, f, bminr, asc, ring);
+                done += n;
+            }
+            T acc[ZB][3];
+#pragma unroll
+            for (int r = 0; r < ZB; ++r) acc[r][0] = acc[r][1] = acc[r][2] = (T)0;
+            for (int jj = j; jj < je; ++jj) {
+                const int kp = (jj - 1) & (kColRing - 1), kc = jj < nv ? (jj & (kColRing - 1)) : kColRing;
+                const GRec<T> c = ring.v[kc];
+                const GEdge<T> e = ring.e[kp];
+                T uc[ZB], sc[ZB];
+                grad_vertex<T, ZB>(c, __builtin_amdgcn_readfirstlane(ring.R[kc]), pzs, f, uc, sc);
+                GCol<T> ga, gb;
+                ga.rx = prx;
+                ga.ry = pry;
+                gb.rx = c.rx;
+                gb.ry = c.ry;
+                ga.rho2 = gb.rho2 = (T)0;   // not used by gedge
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) gedge<T>(ga, gb, e.N, e.dot, e.gNx, e.gNy, up[r], sp[r], uc[r], sc[r], acc[r]);
+                prx = c.rx;
+                pry = c.ry;
+#pragma unroll
+                for (int r = 0; r < ZB; ++r) {
+                    up[r] = uc[r];
+                    sp[r] = sc[r];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < ZB; ++r)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) G[r][cc] += (double)acc[r][cc];
         }
     }
 }
@@ -290,6 +406,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_grad_split(MeshView mv, const
 template <class T, int ZB>
 __global__ __launch_bounds__(64 * kGridWaves) void k_grad_grid(MeshView mv, GridArgs ga, int axis,
                                                                T* __restrict__ g) {
+    __shared__ GRing<T> ring[kGridWaves];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const long long gw = ga.wave0 + (long long)blockIdx.x * kGridWaves + wave;
@@ -311,19 +428,8 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grad_grid(MeshView mv, Grid
 #pragma unroll
     for (int r = 0; r < ZB; ++r) pzs[r] = (T)pz[r] * fs.scf;
     const T pxs = (T)px * fs.scf, pys = (T)py * fs.scf;
-    // lane r holds block r's smallest z (the samples of a block are monotone in
-    // the lane, so it is in lane 0 or lane 63)
-    BlockMin<T> bm{(T)INFINITY, true};
-    T prev = -(T)INFINITY;
-#pragma unroll
-    for (int r = 0; r < ZB; ++r) {
-        const T mz = fmin(wave_lane<T>(pzs[r], 0), wave_lane<T>(pzs[r], 63));
-        if (lane == r) bm.bmin = mz;
-        bm.asc &= !(mz < prev);
-        prev = mz;
-    }
     double G[ZB][3];
-    grad_loops<T, ZB, false, true>(mv, pxs, pys, pzs, fs.f, G, &bm);
+    grad_column_loops<T, ZB>(mv, pxs, pys, pzs, fs.f, G, ring[wave]);
     bool bad = false;
 #pragma unroll
     for (int r = 0; r < ZB; ++r) bad |= !finite3(G[r]);
