@@ -28,3 +28,25 @@ def compare(w_gpu, chi_gpu, V, F, Q, tol, label=""):
     e = float(err[m].max()) if m.any() else 0.0
     assert e <= tol, f"{label}: max |w - oracle| = {e:.3e} > {tol:.1e} (n={m.sum()})"
     return e, int(m.sum())
+
+
+def fan_soup(lengths, seed):
+    """One triangle fan per entry: a wavy polygon of L boundary vertices around a
+    raised centre, the fans scattered over [-1, 1]^3 (boundary loops of exactly
+    those lengths)."""
+    rng = np.random.default_rng(seed)
+    Vs, Fs, nv = [], [], 0
+    for k, L in enumerate(lengths):
+        c = rng.uniform(-0.6, 0.6, size=3)
+        r = rng.uniform(0.15, 0.4)
+        a = np.sort(rng.uniform(0, 2 * np.pi, size=L)) if k % 2 else np.linspace(0, 2 * np.pi, L, endpoint=False)
+        ring = np.stack([c[0] + r * np.cos(a), c[1] + r * np.sin(a) * rng.uniform(0.5, 1.0),
+                         c[2] + 0.3 * r * np.sin(3 * a + k)], axis=1)
+        V = np.concatenate([ring, [c + [0, 0, rng.uniform(-0.2, 0.2)]]])
+        F = np.stack([np.arange(L), (np.arange(L) + 1) % L, np.full(L, L)], axis=1)
+        if k % 3 == 1:
+            F = F[:, [1, 0, 2]]                         # the other orientation
+        Vs.append(V)
+        Fs.append(F + nv)
+        nv += L + 1
+    return np.concatenate(Vs).astype(np.float32), np.concatenate(Fs).astype(np.int32)

@@ -13,7 +13,7 @@ import pytest
 
 import oracle as O
 from paper_2605_01536_amd import workloads as W
-from tests._util import off_surface_mask
+from tests._util import fan_soup, off_surface_mask
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -118,6 +118,27 @@ def test_grid_gradient(gwn, prec, axis):
     assert (err[mask] <= REL[prec] * np.maximum(1.0, l1[mask])).all()
     d = (gg.double() - gb.double()).abs().max(1).values.cpu().numpy()
     assert (d[mask] <= REL[prec] * np.maximum(1.0, l1[mask])).all()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_grid_gradient_long_boundary_loops(gwn, prec):
+    # boundary loops around the lengths where the grid kernel's vertex ring fills
+    # (64 vertices at a time), wraps (128 slots) and flushes (32 edges)
+    lengths = [3, 5, 32, 33, 63, 64, 65, 127, 128, 129, 130, 192, 193, 257]
+    V, F = fan_soup(lengths, seed=78)
+    m = gwn.Mesh(_dev(V), _dev(F))
+    assert m.info()["nboundary"] == sum(lengths)
+    g = W.GridSpec(origin=(-1.0, -0.93, -1.07), spacing=(2.0 / 11, 1.9 / 9, 2.1 / 150), dims=(11, 9, 150))
+    gg = gwn.query_grid_gradient(m, g.origin, g.spacing, g.dims, prec=prec).cpu().numpy().astype(np.float64)
+    P = W.grid_points(g)
+    ref, l1 = O.gradient(V, F, P, with_l1=True)
+    sing = ~(np.isfinite(ref).all(1) & np.isfinite(l1))
+    if sing.any():
+        r2, l2 = O.gradient(V, F, P[sing], axis=(0, 0, -1), with_l1=True)
+        ref[sing], l1[sing] = r2, l2
+    mask = off_surface_mask(V, F, P)
+    err = np.abs(gg - ref).max(1)
+    assert (err[mask] <= REL[prec] * np.maximum(1.0, l1[mask])).all(), float(err[mask].max())
 
 
 def test_grid_gradient_columns_through_vertices(gwn):

@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 from paper_2605_01536_amd import workloads as W
-from tests._util import TOL_FP32, TOL_FP64, compare, diag_of
+from tests._util import TOL_FP32, TOL_FP64, compare, diag_of, fan_soup
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -120,28 +120,6 @@ def test_grid_small_mesh_all_points(gwn, prec, dims):
     assert float((wb.double() - w.double()).abs().max()) < (1e-6 if prec == "fp32" else 1e-12)
 
 
-def _fans(lengths, seed):
-    """One triangle fan per entry: a wavy polygon of L boundary vertices around a
-    raised centre, the fans scattered over [-1, 1]^3 (boundary loops of exactly
-    those lengths)."""
-    rng = np.random.default_rng(seed)
-    Vs, Fs, nv = [], [], 0
-    for k, L in enumerate(lengths):
-        c = rng.uniform(-0.6, 0.6, size=3)
-        r = rng.uniform(0.15, 0.4)
-        a = np.sort(rng.uniform(0, 2 * np.pi, size=L)) if k % 2 else np.linspace(0, 2 * np.pi, L, endpoint=False)
-        ring = np.stack([c[0] + r * np.cos(a), c[1] + r * np.sin(a) * rng.uniform(0.5, 1.0),
-                         c[2] + 0.3 * r * np.sin(3 * a + k)], axis=1)
-        V = np.concatenate([ring, [c + [0, 0, rng.uniform(-0.2, 0.2)]]])
-        F = np.stack([np.arange(L), (np.arange(L) + 1) % L, np.full(L, L)], axis=1)
-        if k % 3 == 1:
-            F = F[:, [1, 0, 2]]                         # the other orientation
-        Vs.append(V)
-        Fs.append(F + nv)
-        nv += L + 1
-    return np.concatenate(Vs).astype(np.float32), np.concatenate(Fs).astype(np.int32)
-
-
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("zb", ["1", "8"])
 def test_grid_long_boundary_loops(gwn, monkeypatch, prec, zb):
@@ -149,7 +127,7 @@ def test_grid_long_boundary_loops(gwn, monkeypatch, prec, zb):
     # (64 vertices at a time), wraps (128 slots) and flushes (32 edges), and
     # pairs its edges four at a time, plus single-edge and short loops
     lengths = [3, 4, 5, 31, 32, 33, 34, 63, 64, 65, 66, 127, 128, 129, 130, 131, 191, 192, 193, 256, 257, 300]
-    V, F = _fans(lengths, seed=77)
+    V, F = fan_soup(lengths, seed=77)
     monkeypatch.setenv("GWN_GRID_SAMPLES_PER_LANE", zb)
     m = gwn.Mesh(_dev(V), _dev(F))
     info = m.info()
