@@ -15,9 +15,15 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
                     on or near the surface where w is undefined (Sec. 3.1).
 * ``boundary``   -- the cancelled directed boundary chain (Sec. 4.1).
 * ``weld``       -- merge vertices with equal coordinates onto one index.
+* ``parametric`` -- Alg. 2 for tensor-product cubic Bezier patches: chi by
+                    ray-driven subdivision to bilinear pieces, the boundary
+                    curves' integral of Alg. 2's f by adaptive GK15 (Sec. 4.4).
+* ``bezier_boundary`` -- the patches' boundary curves after equal curves
+                    traversed both ways cancel.
 
-The C source is ``gwn_oracle.c``; ``build()`` compiles it with gcc into
-``liboracle.so`` next to it (no FP contraction, OpenMP over queries).
+The C sources are ``gwn_oracle.c`` and ``param_oracle.c``; ``build()``
+compiles them with gcc into ``liboracle.so`` next to them (no FP contraction,
+OpenMP over queries).
 """
 from __future__ import annotations
 
@@ -29,6 +35,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gwn_oracle.c")
+_SRC_PARAM = os.path.join(_HERE, "param_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -44,10 +51,12 @@ _i32 = ctypes.c_int32
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (always when force=True)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                     os.path.getmtime(_SRC_PARAM))
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", _SRC, "-o", tmp, "-lquadmath", "-lm"]
+               "-fPIC", "-shared", _SRC, _SRC_PARAM, "-o", tmp, "-lquadmath", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -77,6 +86,10 @@ def lib():
         L.oracle_weld.argtypes = [_F32, _i64, _I32, _i64, _I32]
         L.oracle_weld.restype = _i64
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_param_boundary.argtypes = [_i64, _F64, _i64, _F64, _F64, ctypes.c_double, ctypes.c_int, _F64]
+        L.oracle_param_chi.argtypes = [_i64, _F64, _i64, _F64, _F64, ctypes.c_double, ctypes.c_double, _I32, _U8]
+        L.oracle_gk15_poly.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -196,3 +209,101 @@ def distance(V, F, Q, cutoff: float, use_bins: bool = True):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+# ---------------------------------------------------------------- parametric
+# Ray directions tried in turn (Sec. 4.4.1 shoots another ray when a hit is
+# ambiguous): +z, then three fixed unit vectors in general position.
+PARAM_DIRS = np.array([[0.0, 0.0, 1.0], [0.36, 0.48, 0.8], [-0.48, 0.6, 0.64], [0.6, -0.64, 0.48]])
+
+
+def bezier_curves(P):
+    """The four boundary curves of each patch, counter-clockwise in (u, v):
+    (n, 4 curves, 4 points, 3) from patches (n, 16, 3) (index 4 i + j, i along u)."""
+    P = np.asarray(P, dtype=np.float64).reshape(-1, 4, 4, 3)
+    c0 = P[:, :, 0]              # v = 0, u 0 -> 1
+    c1 = P[:, 3, :]              # u = 1, v 0 -> 1
+    c2 = P[:, ::-1, 3]           # v = 1, u 1 -> 0
+    c3 = P[:, 0, ::-1]           # u = 0, v 1 -> 0
+    return np.stack([c0, c1, c2, c3], axis=1)
+
+
+def bezier_boundary(P):
+    """Boundary curves (m, 4, 3) of the patch set: a curve and the same curve
+    traversed backwards (equal control points) cancel, as interior mesh edges do
+    (Sec. 4.1); what remains is kept with its net multiplicity."""
+    C = bezier_curves(P).reshape(-1, 4, 3)
+    net = {}
+    first = {}
+    for c in C:
+        key = c.tobytes()
+        rkey = c[::-1].copy().tobytes()
+        if rkey in net:
+            net[rkey] -= 1
+        else:
+            net[key] = net.get(key, 0) + 1
+            first.setdefault(key, c)
+    out = []
+    for key, m in net.items():
+        c = first[key]
+        for _ in range(abs(m)):
+            out.append(c if m > 0 else c[::-1])
+    return np.array(out, dtype=np.float64).reshape(-1, 4, 3)
+
+
+def param_chi(P, Q, d, tau, margin=1e-9):
+    """(chi, ambiguous) along unit direction d for patches P (n, 16, 3)."""
+    P = np.ascontiguousarray(P, dtype=np.float64).reshape(-1, 48)
+    Q = np.ascontiguousarray(Q, dtype=np.float64).reshape(-1, 3)
+    chi = np.zeros(Q.shape[0], dtype=np.int32)
+    amb = np.zeros(Q.shape[0], dtype=np.uint8)
+    lib().oracle_param_chi(P.shape[0], P, Q.shape[0], Q, np.ascontiguousarray(d, dtype=np.float64), float(tau),
+                           float(margin), chi, amb)
+    return chi, amb.astype(bool)
+
+
+def param_boundary(curves, Q, d, eps=1e-12, maxdepth=50):
+    """Sum over the curves of the adaptive-GK15 integral of Alg. 2's f with x0 = d."""
+    C = np.ascontiguousarray(curves, dtype=np.float64).reshape(-1, 12)
+    Q = np.ascontiguousarray(Q, dtype=np.float64).reshape(-1, 3)
+    S = np.zeros(Q.shape[0])
+    lib().oracle_param_boundary(C.shape[0], C, Q.shape[0], Q, np.ascontiguousarray(d, dtype=np.float64),
+                                float(eps), int(maxdepth), S)
+    return S
+
+
+def gk15_poly(k, a, b):
+    """(K15, G7) of t^k on [a, b] (test of the quadrature table)."""
+    K, G = ctypes.c_double(), ctypes.c_double()
+    lib().oracle_gk15_poly(int(k), float(a), float(b), ctypes.byref(K), ctypes.byref(G))
+    return K.value, G.value
+
+
+def parametric(P, Q, eps=1e-12, tau_rel=1e-9, margin=1e-9, dirs=None):
+    """Alg. 2: (w, chi, direction index) per query for cubic Bezier patches
+    P (n, 16, 3).  Each query takes the first direction of ``dirs`` whose ray
+    has no ambiguous hit; w = chi + boundary integral for that direction
+    (direction index -1 and NaN where every direction is ambiguous)."""
+    P = np.asarray(P, dtype=np.float64).reshape(-1, 16, 3)
+    Q = np.asarray(Q, dtype=np.float64).reshape(-1, 3)
+    dirs = PARAM_DIRS if dirs is None else np.asarray(dirs, dtype=np.float64)
+    diag = float(np.linalg.norm(P.reshape(-1, 3).max(0) - P.reshape(-1, 3).min(0))) if P.size else 1.0
+    curves = bezier_boundary(P)
+    n = Q.shape[0]
+    w = np.full(n, np.nan)
+    chi = np.zeros(n, dtype=np.int32)
+    di = np.full(n, -1, dtype=np.int32)
+    todo = np.arange(n)
+    for k, d in enumerate(dirs):
+        if todo.size == 0:
+            break
+        c, amb = param_chi(P, Q[todo], d, tau_rel * diag, margin)
+        ok = todo[~amb]
+        if ok.size:
+            S = param_boundary(curves, Q[ok], d, eps) if len(curves) else np.zeros(ok.size)
+            w[ok] = c[~amb] + S
+            chi[ok] = c[~amb]
+            di[ok] = k
+        todo = todo[amb]
+    return w, chi, di
+

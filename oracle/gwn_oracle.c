@@ -837,8 +837,20 @@ void oracle_distance2(const float* V, int64_t nv, const int32_t* F, int64_t nf, 
         for (int pass = 0; pass < 2; ++pass) {
             if (pass == 1) {
                 for (int64_t i = 0; i < G * G; ++i) start[i + 1] += start[i];
-                items = (int64_t*)malloc(sizeof(int64_t) * (size_t)(start[G * G] + 1));
-                fill = (int64_t*)calloc((size_t)(G * G), sizeof(int64_t));
+                /* a cutoff large against the triangles puts each in many buckets:
+                 * past a bound (or if memory runs out) every query scans all triangles */
+                if (start[G * G] <= 64 * nf + (1 << 20))
+                    items = (int64_t*)malloc(sizeof(int64_t) * (size_t)(start[G * G] + 1));
+                fill = items ? (int64_t*)calloc((size_t)(G * G), sizeof(int64_t)) : NULL;
+                if (!items || !fill) {
+                    free(items);
+                    free(fill);
+                    free(start);
+                    items = NULL;
+                    fill = NULL;
+                    start = NULL;
+                    break;
+                }
             }
             for (int64_t t = 0; t < nf; ++t) {
                 double lx = 1e300, hx = -1e300, ly = 1e300, hy = -1e300;

@@ -50,3 +50,43 @@ def fan_soup(lengths, seed):
         Fs.append(F + nv)
         nv += L + 1
     return np.concatenate(Vs).astype(np.float32), np.concatenate(Fs).astype(np.int32)
+
+
+def flat_bezier_patch(x0, x1, y0, y1, z=0.0):
+    """A planar bicubic patch over [x0, x1] x [y0, y1] at height z (normal +z), (16, 3)."""
+    P = np.zeros((4, 4, 3))
+    for i in range(4):
+        for j in range(4):
+            P[i, j] = [x0 + (x1 - x0) * i / 3, y0 + (y1 - y0) * j / 3, z]
+    return P.reshape(16, 3)
+
+
+def bezier_cube():
+    """The unit cube as six planar bicubic patches with outward normals, (6, 16, 3)."""
+    faces = [((0, 0, 0), (0, 1, 0), (1, 0, 0)), ((0, 0, 1), (1, 0, 0), (0, 1, 0)),
+             ((0, 0, 0), (1, 0, 0), (0, 0, 1)), ((0, 1, 0), (0, 0, 1), (1, 0, 0)),
+             ((0, 0, 0), (0, 0, 1), (0, 1, 0)), ((1, 0, 0), (0, 1, 0), (0, 0, 1))]
+    out = []
+    for o, U, V in faces:
+        o, U, V = (np.array(x, dtype=np.float64) for x in (o, U, V))
+        out.append(np.array([o + U * i / 3 + V * j / 3 for i in range(4) for j in range(4)]))
+    return np.array(out)
+
+
+def bezier_tessellate(P, n):
+    """(V float32, F int32): each cubic patch of P (m, 16, 3) sampled on an
+    (n + 1) x (n + 1) parameter grid, two triangles per cell, same orientation."""
+    P = np.asarray(P, dtype=np.float64).reshape(-1, 4, 4, 3)
+    t = np.linspace(0.0, 1.0, n + 1)
+    s = 1.0 - t
+    B = np.stack([s ** 3, 3 * s * s * t, 3 * s * t * t, t ** 3], axis=1)
+    Vs, Fs, off = [], [], 0
+    idx = np.arange((n + 1) * (n + 1)).reshape(n + 1, n + 1)
+    a, b, c, d = idx[:-1, :-1].ravel(), idx[1:, :-1].ravel(), idx[1:, 1:].ravel(), idx[:-1, 1:].ravel()
+    F = np.concatenate([np.stack([a, b, c], 1), np.stack([a, c, d], 1)])
+    for Pk in P:
+        S = np.einsum("ai,bj,ijc->abc", B, B, Pk)
+        Vs.append(S.reshape(-1, 3))
+        Fs.append(F + off)
+        off += S.shape[0] * S.shape[1]
+    return np.concatenate(Vs).astype(np.float32), np.concatenate(Fs).astype(np.int32)
