@@ -255,6 +255,63 @@ gwn_status gwn_multi_info_get(gwn_multi plan, gwn_multi_info* out);
 gwn_status gwn_multi_destroy(gwn_multi plan);
 
 /*
+ * Parametric surfaces (Sec. 4.4, Alg. 2): a surface made of tensor-product
+ * cubic Bezier patches, FP64 throughout.
+ *
+ * gwn_patches_build: cps is a DEVICE array of npatch * 16 * 3 doubles, patch k's
+ *   control point P[i][j] (i along u, j along v) at ((16 k + 4 i + j) * 3); it
+ *   is copied, the caller keeps ownership.  The patch's normal is S_u x S_v and
+ *   its boundary runs counter-clockwise in (u, v), so w = +1 inside a closed
+ *   surface whose normals point out.  The surface's boundary is the patches'
+ *   boundary curves after each curve cancels the same curve traversed
+ *   backwards (equal control points, +0 = -0), kept with net multiplicity.
+ *   opts (nullable; zero fields take the default): tau, the tolerance of the
+ *   "approximately bilinear" test of the ray-patch subdivision, relative to
+ *   the control points' bounding-box diagonal (default 1e-9); eps, the
+ *   absolute tolerance |K15 - G7| of each accepted quadrature interval
+ *   (default 1e-11); max_depth, the deepest interval bisection (default 30,
+ *   at most 50).  Synchronises `stream`.  Errors: GWN_E_INVALID for a null
+ *   argument, npatch outside [0, 2^24] or a non-finite control point.
+ * gwn_patches_query: w (double, nq) per query point (FP32 strided input, as for
+ *   meshes): w = chi(x0) + (1 / 4 pi) * sum over boundary curves of the
+ *   integral of the area rate of the geodesic triangle (-x0, Gamma(t),
+ *   Gamma(t + dt)) (Alg. 1's edge term in the limit of short edges), by
+ *   adaptive 15-point Gauss-Kronrod.  chi counts the signed crossings of the
+ *   ray p + t x0, t > 0 (+1 where the ray has positive dot product with the
+ *   normal).  x0 is the first of +z, (0.36, 0.48, 0.8), (-0.48, 0.6, 0.64),
+ *   (0.6, -0.64, 0.48) whose ray has no tangent hit, no hit at the query and
+ *   no hit within 1e-9 (in a leaf's parameters) of a subdivision leaf's edge
+ *   (Sec. 4.4.1 shoots another ray in such cases); dir_out (nullable) receives
+ *   its index, or -1 with w = NaN when all four are ambiguous; chi_out
+ *   (nullable) the crossing count along it.  w is independent of the choice
+ *   (Prop. 4.2); chi is not.  Asynchronous on `stream`; nq = 0 is a no-op.
+ *   Errors: GWN_E_INVALID for null arguments, nq < 0, qstride < 1 or another
+ *   current device than the build's.
+ */
+typedef struct gwn_patches_s* gwn_patches;
+
+typedef struct {
+    double tau;          /* bilinear tolerance, relative to the bounding-box diagonal; 0 = 1e-9 */
+    double eps;          /* |K15 - G7| per accepted interval; 0 = 1e-11 */
+    int32_t max_depth;   /* deepest interval bisection; 0 = 30 */
+} gwn_patch_opts;
+
+typedef struct {
+    int64_t npatch, ncurves;   /* patches; boundary curves left after cancellation */
+    double tau;                /* absolute bilinear tolerance */
+    double eps;
+    int32_t max_depth;
+    double diag;               /* bounding-box diagonal of the control points */
+} gwn_patches_info;
+
+gwn_status gwn_patches_build(const double* cps, int64_t npatch, const gwn_patch_opts* opts, void* stream,
+                             gwn_patches* out);
+gwn_status gwn_patches_info_get(gwn_patches h, gwn_patches_info* out);
+gwn_status gwn_patches_query(gwn_patches h, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                             int64_t nq, double* w_out, int32_t* chi_out, int32_t* dir_out, void* stream);
+gwn_status gwn_patches_destroy(gwn_patches h);
+
+/*
  * Learned surrogate (a Fourier-feature MLP standing in for far-field queries;
  * not part of the paper's method, whose nearest item is its future-work remark
  * on approximating the fractional part).

@@ -232,7 +232,7 @@ def bezier_boundary(P):
     """Boundary curves (m, 4, 3) of the patch set: a curve and the same curve
     traversed backwards (equal control points) cancel, as interior mesh edges do
     (Sec. 4.1); what remains is kept with its net multiplicity."""
-    C = bezier_curves(P).reshape(-1, 4, 3)
+    C = bezier_curves(P).reshape(-1, 4, 3) + 0.0   # -0 and +0 are the same point
     net = {}
     first = {}
     for c in C:

@@ -131,7 +131,7 @@ static double po_adapt(const double* C, const double* p, const double* x0, doubl
 {
     double K, G;
     po_gk15_rule(C, p, x0, a, b, &K, &G);
-    if (fabs(K - G) <= eps || depth >= maxdepth) return K;
+    if (!(fabs(K - G) > eps) || depth >= maxdepth) return K; /* a NaN integrand is accepted as it is */
     const double m = 0.5 * (a + b);
     return po_adapt(C, p, x0, a, m, eps, depth + 1, maxdepth) + po_adapt(C, p, x0, m, b, eps, depth + 1, maxdepth);
 }

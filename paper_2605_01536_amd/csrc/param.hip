@@ -1,0 +1,596 @@
+// param.hip -- generalized winding numbers of surfaces made of tensor-product
+// cubic Bezier patches (Sec. 4.4): w(p) = chi(x0) + boundary term, FP64.
+//
+// Patch: 16 control points P[i][j] (i along u, j along v) at (4 i + j) * 3;
+// normal S_u x S_v; its boundary runs counter-clockwise in (u, v).  A boundary
+// curve of one patch cancels the same curve traversed backwards by another
+// (equal control points), as interior mesh edges do (Sec. 4.1).
+//
+// chi(x0): one lane per query.  The ray p + t x0 (t > 0) is tested against
+// each patch by subdivision driven by the ray: a sub-patch is named by its
+// level and (u, v) cell, its control points are extracted from the patch by
+// de Casteljau on the cell's interval, the ray is tested against their
+// bounding box (convex hull property), and a sub-patch whose control net lies
+// within tau of the bilinear patch through its corners (Sec. 4.4.1's test for
+// "approximately bilinear") is intersected as that bilinear patch.  A hit that
+// is tangent, at the query, or near a leaf's edge makes the direction
+// ambiguous; the lane then shoots the next of four fixed directions (Sec. 4.4.1
+// shoots another ray in these cases).
+//
+// Boundary term, for the chosen x0 = d and x1 = -d: the area swept by the
+// geodesic triangle (x1, Gamma(t), Gamma(t + dt)) on the unit sphere around p,
+// i.e. Alg. 1's per-edge term of Eq. 10 in the limit of short edges.  In a
+// frame (e1, e2, d) with r = phi(t) - p, l = |r|, s = l - r_z (= rho^2 /
+// (l + r_z) for r_z > 0) it is
+//     (1 / 4 pi) * integral of (r_y r'_x - r_x r'_y) / (l s) dt,
+// the same N and s as the mesh kernels (Alg. 2 splits the same integral into
+// the spherical winding number at x1 and the field's rotation, Prop. 5.2).
+// Integrated by adaptive 15-point Gauss-Kronrod per curve (bisection while
+// |K15 - G7| > eps, to a maximum depth).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "gwn_mesh.h"
+
+struct gwn_patches_s {
+    int device = 0;
+    int64_t npatch = 0, ncurves = 0;
+    double tau = 0.0, eps = 0.0, diag = 0.0;
+    int max_depth = 25;
+    double* patches = nullptr;   // npatch * 48
+    double* boxes = nullptr;     // npatch * 6 (lo xyz, hi xyz of the control points)
+    double* curves = nullptr;    // ncurves * 12
+};
+
+namespace gwn {
+namespace {
+
+constexpr int kNDir = 4;
+// +z, then three unit vectors in general position
+__constant__ double c_dirs[kNDir][3] = {{0.0, 0.0, 1.0}, {0.36, 0.48, 0.8}, {-0.48, 0.6, 0.64}, {0.6, -0.64, 0.48}};
+
+// Kronrod nodes on [0, 1] of the 15-point rule (symmetric; the last is the
+// centre) and weights; the embedded 7-point Gauss rule uses nodes 1, 3, 5 and
+// the centre
+__constant__ double c_gk_x[8] = {0.991455371120812639206854697526329, 0.949107912342758524526189684047851,
+                                 0.864864423359769072789712788640926, 0.741531185599394439863864773280788,
+                                 0.586087235467691130294144845693013, 0.405845151377397166906606412076961,
+                                 0.207784955007898467600689403773245, 0.0};
+__constant__ double c_gk_w[8] = {0.022935322010529224963732008058970, 0.063092092629978553290700663189204,
+                                 0.104790010322250183839876322541518, 0.140653259715525918745189590510238,
+                                 0.169004726639267902826583426598550, 0.190350578064785409913256402421014,
+                                 0.204432940075298892414161999234649, 0.209482141084727828012999174891714};
+__constant__ double c_g7_w[4] = {0.129484966168869693270611432679082, 0.279705391489276667901467771423780,
+                                 0.381830050505118944950369775488975, 0.417959183673469387755102040816327};
+
+constexpr double kInv4Pi = 0.079577471545947667884441881686257;
+constexpr int kMaxLevel = 28;     // sub-patch cells of 2^-28
+constexpr int kRayStack = 3 * kMaxLevel + 4;
+constexpr int kQuadStack = 64;
+// Work bounds that keep every lane finite on degenerate input: a ray grazing a
+// patch meets about 2^level cells per level; past kMaxCells cells the direction
+// counts as ambiguous.  An integrand that is not finite is accepted as it is
+// (w becomes NaN), and past kMaxIntervals intervals on one curve the remaining
+// ones are accepted without bisection.
+constexpr int kMaxCells = 1 << 14;
+constexpr int kMaxIntervals = 1 << 15;
+
+struct Frame {
+    double e1[3], e2[3], d[3];   // right-handed: e1 x e2 = d
+};
+
+__device__ inline Frame make_frame(int k) {
+    Frame f;
+    for (int c = 0; c < 3; ++c) f.d[c] = c_dirs[k][c];
+    // e2: d x (the axis least aligned with d), normalised; e1 = e2 x d
+    const double ax = fabs(f.d[0]), ay = fabs(f.d[1]), az = fabs(f.d[2]);
+    double h[3] = {0.0, 0.0, 0.0};
+    if (ax <= ay && ax <= az) h[0] = 1.0;
+    else if (ay <= az) h[1] = 1.0;
+    else h[2] = 1.0;
+    double e[3] = {f.d[1] * h[2] - f.d[2] * h[1], f.d[2] * h[0] - f.d[0] * h[2], f.d[0] * h[1] - f.d[1] * h[0]};
+    const double n = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    for (int c = 0; c < 3; ++c) f.e2[c] = e[c] / n;   // d x h
+    // e1 = e2 x d so that e1 x e2 = d
+    f.e1[0] = f.e2[1] * f.d[2] - f.e2[2] * f.d[1];
+    f.e1[1] = f.e2[2] * f.d[0] - f.e2[0] * f.d[2];
+    f.e1[2] = f.e2[0] * f.d[1] - f.e2[1] * f.d[0];
+    return f;
+}
+
+// control points of the cubic c0..c3 restricted to [a, b] within [0, 1]
+__device__ inline void cubic_interval(double c0, double c1, double c2, double c3, double a, double b, double* o) {
+    // left part at b: control points of [0, b]
+    const double l01 = c0 + b * (c1 - c0), l12 = c1 + b * (c2 - c1), l23 = c2 + b * (c3 - c2);
+    const double l012 = l01 + b * (l12 - l01), l123 = l12 + b * (l23 - l12);
+    const double l0123 = l012 + b * (l123 - l012);
+    const double L0 = c0, L1 = l01, L2 = l012, L3 = l0123;
+    // right part of that at a / b: control points of [a, b]
+    const double s = b > 0.0 ? a / b : 0.0;
+    const double m01 = L0 + s * (L1 - L0), m12 = L1 + s * (L2 - L1), m23 = L2 + s * (L3 - L2);
+    const double m012 = m01 + s * (m12 - m01), m123 = m12 + s * (m23 - m12);
+    o[0] = m012 + s * (m123 - m012);
+    o[1] = m123;
+    o[2] = m23;
+    o[3] = L3;
+}
+
+// control points (48) of the cell [iu h, (iu + 1) h] x [iv h, (iv + 1) h], h = 2^-level
+__device__ inline void extract(const double* __restrict__ P, int level, unsigned iu, unsigned iv, double* S) {
+    const double h = ldexp(1.0, -level);
+    const double u0 = iu * h, u1 = (iu + 1) * h, v0 = iv * h, v1 = (iv + 1) * h;
+    double T[48];
+    for (int j = 0; j < 4; ++j)
+        for (int c = 0; c < 3; ++c) {
+            double o[4];
+            cubic_interval(P[(0 + j) * 3 + c], P[(4 + j) * 3 + c], P[(8 + j) * 3 + c], P[(12 + j) * 3 + c], u0, u1, o);
+            for (int i = 0; i < 4; ++i) T[(4 * i + j) * 3 + c] = o[i];
+        }
+    for (int i = 0; i < 4; ++i)
+        for (int c = 0; c < 3; ++c) {
+            double o[4];
+            cubic_interval(T[(4 * i) * 3 + c], T[(4 * i + 1) * 3 + c], T[(4 * i + 2) * 3 + c], T[(4 * i + 3) * 3 + c],
+                           v0, v1, o);
+            for (int j = 0; j < 4; ++j) S[(4 * i + j) * 3 + c] = o[j];
+        }
+}
+
+struct RayState {
+    double p[3], d[3], e1[3], e2[3];
+    double tau, margin;
+    int chi;
+    bool amb;
+};
+
+__device__ inline bool ray_box(const RayState& R, const double* lo, const double* hi) {
+    double t0 = 0.0, t1 = 1e300;
+    for (int c = 0; c < 3; ++c) {
+        const double pad = 1e-12 * (1.0 + fabs(lo[c]) + fabs(hi[c]));
+        const double l = lo[c] - pad, u = hi[c] + pad;
+        if (R.d[c] == 0.0) {
+            if (R.p[c] < l || R.p[c] > u) return false;
+        } else {
+            const double inv = 1.0 / R.d[c];
+            double a = (l - R.p[c]) * inv, b = (u - R.p[c]) * inv;
+            if (a > b) {
+                const double t = a;
+                a = b;
+                b = t;
+            }
+            t0 = fmax(t0, a);
+            t1 = fmin(t1, b);
+            if (t0 > t1) return false;
+        }
+    }
+    return true;
+}
+
+// distance of the control net from the bilinear patch through its corners
+__device__ inline double net_deviation(const double* S) {
+    double m = 0.0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            const double u = i * (1.0 / 3.0), v = j * (1.0 / 3.0);
+            double e2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double b = (1.0 - u) * ((1.0 - v) * S[c] + v * S[9 + c]) +
+                                 u * ((1.0 - v) * S[36 + c] + v * S[45 + c]);
+                const double e = S[(4 * i + j) * 3 + c] - b;
+                e2 += e * e;
+            }
+            m = fmax(m, e2);
+        }
+    return sqrt(m);
+}
+
+// the ray against the bilinear patch through the corners of S (00, 10, 11, 01
+// at control points 0, 12, 15, 3): two planes through the ray, e1.(x - p) = 0
+// and e2.(x - p) = 0, each bilinear in (u, v); eliminating u gives a quadratic
+// in v
+__device__ inline void bilinear_hits(RayState& R, const double* S) {
+    const double* q[4] = {S, S + 36, S + 45, S + 9};
+    double f1[4], f2[4];
+    for (int k = 0; k < 4; ++k) {
+        const double r0 = q[k][0] - R.p[0], r1 = q[k][1] - R.p[1], r2 = q[k][2] - R.p[2];
+        f1[k] = r0 * R.e1[0] + r1 * R.e1[1] + r2 * R.e1[2];
+        f2[k] = r0 * R.e2[0] + r1 * R.e2[1] + r2 * R.e2[2];
+    }
+    // f(u, v) = a + b u + c v + d u v
+    const double a1 = f1[0], b1 = f1[1] - f1[0], c1 = f1[3] - f1[0], d1 = f1[0] - f1[1] + f1[2] - f1[3];
+    const double a2 = f2[0], b2 = f2[1] - f2[0], c2 = f2[3] - f2[0], d2 = f2[0] - f2[1] + f2[2] - f2[3];
+    // (a2 + c2 v)(b1 + d1 v) - (a1 + c1 v)(b2 + d2 v) = 0
+    const double A = c2 * d1 - c1 * d2;
+    const double B = a2 * d1 + c2 * b1 - a1 * d2 - c1 * b2;
+    const double C = a2 * b1 - a1 * b2;
+    const double sc = fabs(A) + fabs(B) + fabs(C);
+    if (sc == 0.0) {
+        R.amb = true;
+        return;
+    }
+    double roots[2];
+    int nr = 0;
+    if (fabs(A) <= 1e-14 * sc) {
+        if (B != 0.0) roots[nr++] = -C / B;
+    } else {
+        const double disc = B * B - 4.0 * A * C;
+        if (disc < 0.0) return;
+        const double sq = sqrt(disc);
+        const double qq = -0.5 * (B + (B >= 0.0 ? sq : -sq));
+        roots[nr++] = qq / A;
+        if (qq != 0.0 && disc > 0.0) roots[nr++] = C / qq;
+    }
+    for (int k = 0; k < nr; ++k) {
+        const double v = roots[k];
+        const double den1 = b1 + d1 * v, den2 = b2 + d2 * v;
+        double u;
+        if (fabs(den1) >= fabs(den2)) {
+            if (den1 == 0.0) {
+                R.amb = true;
+                continue;
+            }
+            u = -(a1 + c1 * v) / den1;
+        } else {
+            u = -(a2 + c2 * v) / den2;
+        }
+        const double mg = R.margin;
+        if (u < -mg || u > 1.0 + mg || v < -mg || v > 1.0 + mg) continue;
+        if (u < mg || u > 1.0 - mg || v < mg || v > 1.0 - mg) {
+            R.amb = true;
+            continue;
+        }
+        double X[3], Su[3], Sv[3];
+        for (int c = 0; c < 3; ++c) {
+            X[c] = (1.0 - u) * ((1.0 - v) * q[0][c] + v * q[3][c]) + u * ((1.0 - v) * q[1][c] + v * q[2][c]);
+            Su[c] = (1.0 - v) * (q[1][c] - q[0][c]) + v * (q[2][c] - q[3][c]);
+            Sv[c] = (1.0 - u) * (q[3][c] - q[0][c]) + u * (q[2][c] - q[1][c]);
+        }
+        const double n0 = Su[1] * Sv[2] - Su[2] * Sv[1], n1 = Su[2] * Sv[0] - Su[0] * Sv[2],
+                     n2 = Su[0] * Sv[1] - Su[1] * Sv[0];
+        const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        const double nd = n0 * R.d[0] + n1 * R.d[1] + n2 * R.d[2];
+        const double r0 = X[0] - R.p[0], r1 = X[1] - R.p[1], r2 = X[2] - R.p[2];
+        const double t = r0 * R.d[0] + r1 * R.d[1] + r2 * R.d[2];
+        if (!(nn > 0.0) || fabs(nd) < 1e-9 * nn) {
+            R.amb = true;
+            continue;
+        }
+        if (fabs(t) <= 1e-12 * (1.0 + sqrt(r0 * r0 + r1 * r1 + r2 * r2))) {
+            R.amb = true;   // the query on the surface
+            continue;
+        }
+        if (t > 0.0) R.chi += nd > 0.0 ? 1 : -1;
+    }
+}
+
+// one patch: depth-first over sub-patch cells whose control-point box meets the ray
+__device__ void patch_ray(RayState& R, const double* __restrict__ P) {
+    unsigned long long stk[kRayStack];
+    int sp = 0;
+    stk[sp++] = 0ull;   // level 0, cell (0, 0)
+    int cells = 0;
+    while (sp > 0) {
+        if (++cells > kMaxCells) {
+            R.amb = true;
+            return;
+        }
+        const unsigned long long code = stk[--sp];
+        const int level = (int)(code >> 58);
+        const unsigned iu = (unsigned)((code >> 29) & 0x1fffffffu), iv = (unsigned)(code & 0x1fffffffu);
+        double S[48];
+        extract(P, level, iu, iv, S);
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int k = 0; k < 16; ++k)
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = fmin(lo[c], S[3 * k + c]);
+                hi[c] = fmax(hi[c], S[3 * k + c]);
+            }
+        if (!ray_box(R, lo, hi)) continue;
+        if (level >= kMaxLevel || net_deviation(S) <= R.tau) {
+            bilinear_hits(R, S);
+            continue;
+        }
+        if (sp + 4 > kRayStack) {   // cannot happen for depth-first with kRayStack >= 3 levels + 4
+            R.amb = true;
+            continue;
+        }
+        const unsigned long long nl = (unsigned long long)(level + 1) << 58;
+        for (int c = 0; c < 4; ++c) {
+            const unsigned long long cu = 2ull * iu + (c & 1), cv = 2ull * iv + (c >> 1);
+            stk[sp++] = nl | (cu << 29) | cv;
+        }
+    }
+}
+
+// the boundary integrand (without 1 / 4 pi) at t of curve C in frame F
+__device__ inline double area_rate(const double* __restrict__ C, double t, const double* p, const Frame& F) {
+    const double s1 = 1.0 - t;
+    const double b0 = s1 * s1 * s1, b1 = 3.0 * s1 * s1 * t, b2 = 3.0 * s1 * t * t, b3 = t * t * t;
+    const double d0 = -3.0 * s1 * s1, d1 = 3.0 * s1 * (s1 - 2.0 * t), d2 = 3.0 * t * (2.0 * s1 - t), d3 = 3.0 * t * t;
+    double r[3], dr[3];
+    for (int c = 0; c < 3; ++c) {
+        r[c] = b0 * C[c] + b1 * C[3 + c] + b2 * C[6 + c] + b3 * C[9 + c] - p[c];
+        dr[c] = d0 * C[c] + d1 * C[3 + c] + d2 * C[6 + c] + d3 * C[9 + c];
+    }
+    const double rx = r[0] * F.e1[0] + r[1] * F.e1[1] + r[2] * F.e1[2];
+    const double ry = r[0] * F.e2[0] + r[1] * F.e2[1] + r[2] * F.e2[2];
+    const double rz = r[0] * F.d[0] + r[1] * F.d[1] + r[2] * F.d[2];
+    const double dx = dr[0] * F.e1[0] + dr[1] * F.e1[1] + dr[2] * F.e1[2];
+    const double dy = dr[0] * F.e2[0] + dr[1] * F.e2[1] + dr[2] * F.e2[2];
+    const double rho2 = rx * rx + ry * ry;
+    const double l = sqrt(rho2 + rz * rz);
+    const double s = rz > 0.0 ? rho2 / (l + rz) : l - rz;
+    return (ry * dx - rx * dy) / (l * s);
+}
+
+// adaptive GK15 of area_rate over [0, 1]: depth-first over dyadic intervals
+__device__ double curve_integral(const double* __restrict__ C, const double* p, const Frame& F, double eps,
+                                 int max_depth) {
+    unsigned long long stk[kQuadStack];
+    int sp = 0;
+    stk[sp++] = 0ull;
+    double sum = 0.0;
+    int intervals = 0;
+    while (sp > 0) {
+        ++intervals;
+        const unsigned long long code = stk[--sp];
+        const int level = (int)(code >> 58);
+        const unsigned long long idx = code & ((1ull << 58) - 1);
+        const double h = ldexp(1.0, -level);
+        const double a = (double)idx * h;
+        const double c = a + 0.5 * h, hw = 0.5 * h;
+        const double fc = area_rate(C, c, p, F);
+        double K = c_gk_w[7] * fc, G = c_g7_w[3] * fc;
+        for (int i = 0; i < 7; ++i) {
+            const double f = area_rate(C, c - hw * c_gk_x[i], p, F) + area_rate(C, c + hw * c_gk_x[i], p, F);
+            K += c_gk_w[i] * f;
+            if (i & 1) G += c_g7_w[i >> 1] * f;
+        }
+        K *= hw;
+        G *= hw;
+        if (!(fabs(K - G) > eps) || level >= max_depth || sp + 2 > kQuadStack || intervals > kMaxIntervals) {
+            sum += K;
+        } else {
+            const unsigned long long nl = (unsigned long long)(level + 1) << 58;
+            stk[sp++] = nl | (2ull * idx + 1);   // right half, taken after the left
+            stk[sp++] = nl | (2ull * idx);
+        }
+    }
+    return sum;
+}
+
+__global__ __launch_bounds__(64) void k_param(const double* __restrict__ patches, const double* __restrict__ boxes,
+                                              long long npatch, const double* __restrict__ curves,
+                                              long long ncurves, const float* __restrict__ qx,
+                                              const float* __restrict__ qy, const float* __restrict__ qz,
+                                              long long qs, long long nq, double tau, double eps, int max_depth,
+                                              double* __restrict__ w, int* __restrict__ chi_out,
+                                              int* __restrict__ dir_out) {
+    const long long i = blockIdx.x * 64ll + threadIdx.x;
+    if (i >= nq) return;
+    RayState R;
+    R.p[0] = qx[i * qs];
+    R.p[1] = qy[i * qs];
+    R.p[2] = qz[i * qs];
+    R.tau = tau;
+    R.margin = 1e-9;
+    int dir = -1;
+    for (int k = 0; k < kNDir && dir < 0; ++k) {
+        const Frame F = make_frame(k);
+        for (int c = 0; c < 3; ++c) {
+            R.d[c] = F.d[c];
+            R.e1[c] = F.e1[c];
+            R.e2[c] = F.e2[c];
+        }
+        R.chi = 0;
+        R.amb = false;
+        for (long long pi = 0; pi < npatch && !R.amb; ++pi)
+            if (ray_box(R, boxes + 6 * pi, boxes + 6 * pi + 3)) patch_ray(R, patches + 48 * pi);
+        if (!R.amb) dir = k;
+    }
+    double wv = NAN;
+    if (dir >= 0) {
+        const Frame F = make_frame(dir);
+        double S = 0.0;
+        for (long long c = 0; c < ncurves; ++c) S += curve_integral(curves + 12 * c, R.p, F, eps, max_depth);
+        wv = (double)R.chi + S * kInv4Pi;
+    }
+    w[i] = wv;
+    if (chi_out) chi_out[i] = dir >= 0 ? R.chi : 0;
+    if (dir_out) dir_out[i] = dir;
+}
+
+// host: the four boundary curves of patch k, counter-clockwise in (u, v)
+void patch_curves(const double* P, double (*out)[12]) {
+    auto cp = [&](int i, int j, double* o) {
+        for (int c = 0; c < 3; ++c) o[c] = P[(4 * i + j) * 3 + c];
+    };
+    for (int k = 0; k < 4; ++k) {
+        cp(k, 0, out[0] + 3 * k);        // v = 0, u 0 -> 1
+        cp(3, k, out[1] + 3 * k);        // u = 1, v 0 -> 1
+        cp(3 - k, 3, out[2] + 3 * k);    // v = 1, u 1 -> 0
+        cp(0, 3 - k, out[3] + 3 * k);    // u = 0, v 1 -> 0
+    }
+}
+
+struct CurveKey {
+    uint64_t b[12];
+    bool operator<(const CurveKey& o) const { return std::memcmp(b, o.b, sizeof b) < 0; }
+};
+
+CurveKey key_of(const double* c, bool reversed) {
+    CurveKey k;
+    for (int i = 0; i < 4; ++i) {
+        const int src = reversed ? 3 - i : i;
+        for (int x = 0; x < 3; ++x) {
+            double v = c[3 * src + x];
+            if (v == 0.0) v = 0.0;   // +0 and -0 are the same point
+            std::memcpy(&k.b[3 * i + x], &v, 8);
+        }
+    }
+    return k;
+}
+
+}  // namespace
+}  // namespace gwn
+
+using gwn::set_error;
+
+extern "C" {
+
+gwn_status gwn_patches_build(const double* cps, int64_t npatch, const gwn_patch_opts* opts, void* stream,
+                             gwn_patches* out) {
+    gwn::clear_error();
+    if (!out || npatch < 0 || (npatch > 0 && !cps) || npatch > (1ll << 24)) {
+        set_error("gwn_patches_build: null argument or npatch outside [0, 2^24]");
+        return GWN_E_INVALID;
+    }
+    *out = nullptr;
+    const double tau_rel = opts && opts->tau > 0.0 ? opts->tau : 1e-9;
+    const double eps = opts && opts->eps > 0.0 ? opts->eps : 1e-11;
+    const int max_depth = opts && opts->max_depth > 0 ? std::min(opts->max_depth, 50) : 30;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> P((size_t)npatch * 48);
+    if (npatch > 0) {
+        GWN_HIP_TRY(hipMemcpyAsync(P.data(), cps, sizeof(double) * P.size(), hipMemcpyDeviceToHost, st));
+        GWN_HIP_TRY(hipStreamSynchronize(st));
+    }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    std::vector<double> boxes((size_t)npatch * 6);
+    for (int64_t k = 0; k < npatch; ++k) {
+        double* b = &boxes[6 * k];
+        for (int c = 0; c < 3; ++c) {
+            b[c] = 1e300;
+            b[3 + c] = -1e300;
+        }
+        for (int j = 0; j < 16; ++j)
+            for (int c = 0; c < 3; ++c) {
+                const double v = P[48 * k + 3 * j + c];
+                if (!std::isfinite(v)) {
+                    set_error("gwn_patches_build: non-finite control point in patch %lld", (long long)k);
+                    return GWN_E_INVALID;
+                }
+                b[c] = std::min(b[c], v);
+                b[3 + c] = std::max(b[3 + c], v);
+            }
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], b[c]);
+            hi[c] = std::max(hi[c], b[3 + c]);
+        }
+    }
+    // boundary: net multiplicity of each curve against its reverse
+    std::map<gwn::CurveKey, long long> net;
+    std::map<gwn::CurveKey, std::vector<double>> first;
+    for (int64_t k = 0; k < npatch; ++k) {
+        double cv[4][12];
+        gwn::patch_curves(&P[48 * k], cv);
+        for (int e = 0; e < 4; ++e) {
+            const gwn::CurveKey f = gwn::key_of(cv[e], false), r = gwn::key_of(cv[e], true);
+            auto it = net.find(r);
+            if (it != net.end()) {
+                it->second -= 1;
+            } else {
+                net[f] += 1;
+                if (!first.count(f)) first[f] = std::vector<double>(cv[e], cv[e] + 12);
+            }
+        }
+    }
+    std::vector<double> curves;
+    for (const auto& kv : net) {
+        const std::vector<double>& c = first[kv.first];
+        for (long long m = 0; m < std::llabs(kv.second); ++m)
+            for (int i = 0; i < 4; ++i) {
+                const int src = kv.second > 0 ? i : 3 - i;
+                for (int x = 0; x < 3; ++x) curves.push_back(c[3 * src + x]);
+            }
+    }
+    gwn_patches_s* h = new (std::nothrow) gwn_patches_s();
+    if (!h) return GWN_E_OOM;
+    GWN_HIP_TRY(hipGetDevice(&h->device));
+    h->npatch = npatch;
+    h->ncurves = (int64_t)(curves.size() / 12);
+    double diag = 0.0;
+    if (npatch > 0)
+        diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                         (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    h->diag = diag;
+    h->tau = tau_rel * std::max(diag, 1e-300);
+    h->eps = eps;
+    h->max_depth = max_depth;
+    auto up = [&](double** dst, const std::vector<double>& src) -> hipError_t {
+        hipError_t e = hipMalloc((void**)dst, sizeof(double) * std::max<size_t>(1, src.size()));
+        if (e == hipSuccess && !src.empty())
+            e = hipMemcpyAsync(*dst, src.data(), sizeof(double) * src.size(), hipMemcpyHostToDevice, st);
+        return e;
+    };
+    hipError_t e = up(&h->patches, P);
+    if (e == hipSuccess) e = up(&h->boxes, boxes);
+    if (e == hipSuccess) e = up(&h->curves, curves);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(h->patches);
+        (void)hipFree(h->boxes);
+        (void)hipFree(h->curves);
+        delete h;
+        set_error("gwn_patches_build: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? GWN_E_OOM : GWN_E_HIP;
+    }
+    *out = h;
+    return GWN_OK;
+}
+
+gwn_status gwn_patches_info_get(gwn_patches h, gwn_patches_info* out) {
+    gwn::clear_error();
+    if (!h || !out) {
+        set_error("gwn_patches_info_get: null argument");
+        return GWN_E_INVALID;
+    }
+    out->npatch = h->npatch;
+    out->ncurves = h->ncurves;
+    out->tau = h->tau;
+    out->eps = h->eps;
+    out->max_depth = h->max_depth;
+    out->diag = h->diag;
+    return GWN_OK;
+}
+
+gwn_status gwn_patches_query(gwn_patches h, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                             int64_t nq, double* w_out, int32_t* chi_out, int32_t* dir_out, void* stream) {
+    gwn::clear_error();
+    if (!h || nq < 0 || qstride < 1 || nq > (1ll << 40) || (nq > 0 && (!qx || !qy || !qz || !w_out))) {
+        set_error("gwn_patches_query: null argument, nq < 0 or qstride < 1");
+        return GWN_E_INVALID;
+    }
+    int dev = -1;
+    GWN_HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device) {
+        set_error("gwn_patches_query: the patches were built on device %d, the current device is %d", h->device, dev);
+        return GWN_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const long long chunk = 1ll << 30;
+    for (long long o = 0; o < nq; o += chunk) {
+        const long long n = std::min<long long>(chunk, nq - o);
+        gwn::k_param<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(
+            h->patches, h->boxes, h->npatch, h->curves, h->ncurves, qx + o * qstride, qy + o * qstride,
+            qz + o * qstride, qstride, n, h->tau, h->eps, h->max_depth, w_out + o, chi_out ? chi_out + o : nullptr,
+            dir_out ? dir_out + o : nullptr);
+        GWN_HIP_TRY(hipGetLastError());
+    }
+    return GWN_OK;
+}
+
+gwn_status gwn_patches_destroy(gwn_patches h) {
+    gwn::clear_error();
+    if (!h) return GWN_OK;
+    (void)hipFree(h->patches);
+    (void)hipFree(h->boxes);
+    (void)hipFree(h->curves);
+    delete h;
+    return GWN_OK;
+}
+
+}  // extern "C"

@@ -326,6 +326,78 @@ class MultiPlan:
             pass
 
 
+class PatchOpts(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("eps", ctypes.c_double), ("max_depth", ctypes.c_int32)]
+
+
+class PatchesInfo(ctypes.Structure):
+    _fields_ = [("npatch", ctypes.c_int64), ("ncurves", ctypes.c_int64), ("tau", ctypes.c_double),
+                ("eps", ctypes.c_double), ("max_depth", ctypes.c_int32), ("diag", ctypes.c_double)]
+
+
+def _load_patches(L):
+    if getattr(L, "_patches_ready", False):
+        return
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    L.gwn_patches_build.argtypes = [vp, i64, ctypes.POINTER(PatchOpts), vp, ctypes.POINTER(vp)]
+    L.gwn_patches_info_get.argtypes = [vp, ctypes.POINTER(PatchesInfo)]
+    L.gwn_patches_query.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp, vp]
+    L.gwn_patches_destroy.argtypes = [vp]
+    for f in ("gwn_patches_build", "gwn_patches_info_get", "gwn_patches_query", "gwn_patches_destroy"):
+        getattr(L, f).restype = ctypes.c_int
+    L._patches_ready = True
+
+
+class Patches:
+    """A surface of tensor-product cubic Bezier patches: P is a CUDA float64
+    tensor (npatch, 16, 3), control point P[k, 4 i + j] with i along u."""
+
+    def __init__(self, P, tau=0.0, eps=0.0, max_depth=0, stream=None):
+        import torch
+        L = load()
+        _load_patches(L)
+        if not (torch.is_tensor(P) and P.is_cuda and P.dtype == torch.float64 and P.dim() == 3
+                and P.shape[1:] == (16, 3)):
+            raise ValueError("P must be a CUDA float64 tensor of shape (npatch, 16, 3)")
+        self._P = P.contiguous()
+        opts = PatchOpts(float(tau), float(eps), int(max_depth))
+        self._h = ctypes.c_void_p()
+        _check(L.gwn_patches_build(_ptr(self._P), self._P.shape[0], ctypes.byref(opts), _stream(stream),
+                                   ctypes.byref(self._h)))
+
+    def info(self) -> dict:
+        inf = PatchesInfo()
+        _check(load().gwn_patches_info_get(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in PatchesInfo._fields_}
+
+    def query(self, Q, want_chi=False, out=None, stream=None):
+        """w (float64) per point of Q (n, 3) float32; with want_chi also the
+        crossing counts and the chosen direction index per point."""
+        import torch
+        L = load()
+        Q = _points(Q)
+        n = Q.shape[0]
+        out = _out(out, (n,), torch.float64, Q.device, "out")
+        chi = torch.empty(n, dtype=torch.int32, device=Q.device) if want_chi else None
+        dr = torch.empty(n, dtype=torch.int32, device=Q.device) if want_chi else None
+        base = _ptr(Q)
+        _check(L.gwn_patches_query(self._h, base, base + 4, base + 8, 3, n, _ptr(out),
+                                   _ptr(chi) if chi is not None else None, _ptr(dr) if dr is not None else None,
+                                   _stream(stream)))
+        return (out, chi, dr) if want_chi else out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().gwn_patches_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 MLP_NPARAMS = 57985
 
 
