@@ -97,6 +97,18 @@ NET_VALU_SLOTS = 512 * 20.5 + 32 * 21 + 256     # = 11,424 per point
 K_GRID_TRAFFIC_BYTES = (505386.0 * 2.0 + 1686997.5 * 1.0) * 1024
 FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
 I_MIN_GRID_FP64 = (16 + 2 + 21 / 2) * FP64_OP_SLOTS + 2.5 * FP64_TRANS_SLOTS + 2   # = 58.25
+# Parametric path (FP64), per unit of work the kernel reports, counted from its
+# arithmetic (a division = one reciprocal at the transcendental cost plus 4 ops):
+# one integrand evaluation: Bernstein weights and derivative weights 24, point
+# and derivative 27, projections onto the ray's frame 15, rho^2, l, s and the
+# numerator 8 ops, 1 square root, 2 divisions; a quadrature interval: 15
+# evaluations plus 30 ops of the two rules; a sub-patch cell: 24 cubic interval
+# extractions (24 ops and 1 division each), the control points' box (96), the
+# slab test (24, 3 divisions) and the control net's distance to the bilinear
+# patch (528, 1 square root).
+PARAM_EVAL_SLOTS = (74 + 2 * 4) * FP64_OP_SLOTS + 3 * FP64_TRANS_SLOTS
+PARAM_INTERVAL_SLOTS = 15 * PARAM_EVAL_SLOTS + 30 * FP64_OP_SLOTS
+PARAM_CELL_SLOTS = (24 * 24 + 96 + 24 + 528 + 27 * 4) * FP64_OP_SLOTS + 28 * FP64_TRANS_SLOTS
 # Per sample and boundary vertex the two-sided form of s (rcp, rho^2*rcp, the sign
 # compare and the select) is skipped where the vertex lies at or below all 64
 # samples of a grid block: 6 FP32 slots (11.4 + 1.5 + 1.5 + 2 in FP64); where it
@@ -153,9 +165,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["grid", "batch", "batched", "surrogate", "precision", "gradient",
-                                                 "direct", "weld", "axis"], default="grid",
+                                                 "direct", "weld", "axis", "parametric"], default="grid",
                     help="grid: the headline 512^3 grid on the 1M-triangle soup (default); batch: 2M points on the "
-                         "torus soup; batched: 256 soups in one persistent graph; surrogate: MLP + exact fallback")
+                         "torus soup; batched: 256 soups in one persistent graph; surrogate: MLP + exact fallback; "
+                         "parametric: 100 cubic Bezier patches on a 32^3 grid")
     ap.add_argument("--n-mesh", type=int, default=256, help="soups in the batched workload")
     ap.add_argument("--sample", type=int, default=20000, help="oracle sample size of the precision workload")
     ap.add_argument("--epochs", type=int, default=32, help="surrogate training epochs")
@@ -196,7 +209,7 @@ def main():
     if args.workload != "grid":
         {"batch": bench_batch, "batched": bench_batched, "surrogate": bench_surrogate,
          "precision": bench_precision, "gradient": bench_gradient, "direct": bench_direct,
-         "weld": bench_weld, "axis": bench_axis}[args.workload](args)
+         "weld": bench_weld, "axis": bench_axis, "parametric": bench_parametric}[args.workload](args)
         return
     t0 = time.time()
     soup, grid = W.config4(n=args.n)
@@ -450,6 +463,58 @@ def bench_direct(args):
           P4.shape[0] / rows[0]["direct_qps"] * 1e3,
           {"workload": "direct per-triangle sum vs antipodal on the same points", "precision": args.prec,
            "cases": rows}, dtype="f32" if args.prec == "fp32" else "f64")
+
+
+def bench_parametric(args):
+    """Surfaces of cubic Bezier patches (Sec. 4.4): 100 patches with control points uniform in
+    the unit cube on a 32^3 cell-centred grid over [-0.2, 1.2]^3 (the paper's synthetic
+    parametric benchmark in a voxelization setting), FP64."""
+    import torch
+    from paper_2605_01536_amd import gwn
+    n_patch, n = 100, 32
+    rng = np.random.default_rng(7)
+    P = rng.uniform(0.0, 1.0, size=(n_patch, 16, 3))
+    g = (np.arange(n) + 0.5) / n * 1.4 - 0.2
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    Q = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1).astype(np.float32)
+    pt = gwn.Patches(torch.from_numpy(P).cuda())
+    info = pt.info()
+    Qd = torch.from_numpy(Q).cuda()
+    w = torch.empty(Q.shape[0], device="cuda", dtype=torch.float64)
+    st = torch.cuda.current_stream()
+    _, nint, ncell = pt.query_stats(Qd, stream=st)
+    ev_ms, wall_ms = _timed(lambda: pt.query(Qd, out=w, stream=st), args.steps, args.warmup, st)
+    _, _, dirs = pt.query(Qd, want_chi=True, stream=st)
+    torch.cuda.synchronize()
+    dirs = dirs.cpu().numpy()
+    slots = nint * PARAM_INTERVAL_SLOTS + ncell * PARAM_CELL_SLOTS
+    achieved = slots / (ev_ms / 1e3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "T FP32-VALU-slots/s",
+            "frac": achieved / PEAK_SLOTS, "traffic": None, "kernel": "k_param",
+            "quadrature_intervals_per_query": nint / Q.shape[0], "subpatch_cells_per_query": ncell / Q.shape[0],
+            "slots_per_interval": PARAM_INTERVAL_SLOTS, "slots_per_cell": PARAM_CELL_SLOTS}
+    print(f"[bench] parametric: {ev_ms:.2f} ms per {Q.shape[0]} points, {nint / Q.shape[0]:.0f} intervals and "
+          f"{ncell / Q.shape[0]:.0f} cells per point, directions {np.bincount(dirs + 1).tolist()}",
+          file=sys.stderr, flush=True)
+    extra = {"roofline": roof}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        idx = np.sort(np.random.default_rng(1).choice(Q.shape[0], 16384, replace=False))
+        sample = Q[idx].astype(np.float64)
+        t0 = time.perf_counter()
+        wo, _, _ = O.parametric(P, sample)
+        dt = time.perf_counter() - t0
+        wg = w.cpu().numpy()
+        ok = np.isfinite(wo) & np.isfinite(wg[idx])
+        extra["cpu_baseline"] = {"value": sample.shape[0] / dt, "unit": "queries/s", "cores": O.num_threads(),
+                                 "kind": "oracle", "sample": f"{sample.shape[0]} points of the same grid, Alg. 2 "
+                                 f"oracle (GK15 at 1e-12, subdivision to 1e-9 of the diagonal), {dt:.1f} s",
+                                 "max_abs_err_vs_gpu": float(np.abs(wo - wg[idx])[ok].max())}
+    _emit("GWN queries/sec, cubic Bezier patches (Sec. 4.4)", Q.shape[0] / (ev_ms / 1e3), "queries/s", args, ev_ms,
+          {"workload": f"{n_patch} cubic Bezier patches, control points U[0,1]^3 (seed 7), {n}^3 cell-centred grid "
+                       "over [-0.2, 1.2]^3", "patches": n_patch, "boundary_curves": info["ncurves"],
+           "queries": int(Q.shape[0]), "tau": info["tau"], "eps": info["eps"], "max_depth": info["max_depth"]},
+          extra, dtype="f64")
 
 
 def bench_weld(args):

@@ -309,6 +309,12 @@ gwn_status gwn_patches_build(const double* cps, int64_t npatch, const gwn_patch_
 gwn_status gwn_patches_info_get(gwn_patches h, gwn_patches_info* out);
 gwn_status gwn_patches_query(gwn_patches h, const float* qx, const float* qy, const float* qz, int64_t qstride,
                              int64_t nq, double* w_out, int32_t* chi_out, int32_t* dir_out, void* stream);
+/* The same evaluation (w only) that also counts its work: counts[0] = quadrature
+ * intervals (15 integrand evaluations each), counts[1] = sub-patch cells
+ * extracted by the ray subdivision, summed over the queries (nq <= 2^30).
+ * counts is a HOST array of 2; synchronises `stream`; for measurement. */
+gwn_status gwn_patches_query_stats(gwn_patches h, const float* qx, const float* qy, const float* qz,
+                                   int64_t qstride, int64_t nq, double* w_out, int64_t* counts, void* stream);
 gwn_status gwn_patches_destroy(gwn_patches h);
 
 /*

@@ -6,8 +6,8 @@
 // curve of one patch cancels the same curve traversed backwards by another
 // (equal control points), as interior mesh edges do (Sec. 4.1).
 //
-// chi(x0): one lane per query.  The ray p + t x0 (t > 0) is tested against
-// each patch by subdivision driven by the ray: a sub-patch is named by its
+// chi(x0): one wave per query, its lanes sharing out the patches.  The ray
+// p + t x0 (t > 0) is tested against each patch by subdivision driven by the ray: a sub-patch is named by its
 // level and (u, v) cell, its control points are extracted from the patch by
 // de Casteljau on the cell's interval, the ray is tested against their
 // bounding box (convex hull property), and a sub-patch whose control net lies
@@ -267,7 +267,8 @@ __device__ inline void bilinear_hits(RayState& R, const double* S) {
 }
 
 // one patch: depth-first over sub-patch cells whose control-point box meets the ray
-__device__ void patch_ray(RayState& R, const double* __restrict__ P) {
+// (returns the number of cells extracted)
+__device__ int patch_ray(RayState& R, const double* __restrict__ P) {
     unsigned long long stk[kRayStack];
     int sp = 0;
     stk[sp++] = 0ull;   // level 0, cell (0, 0)
@@ -275,7 +276,7 @@ __device__ void patch_ray(RayState& R, const double* __restrict__ P) {
     while (sp > 0) {
         if (++cells > kMaxCells) {
             R.amb = true;
-            return;
+            return cells;
         }
         const unsigned long long code = stk[--sp];
         const int level = (int)(code >> 58);
@@ -303,6 +304,7 @@ __device__ void patch_ray(RayState& R, const double* __restrict__ P) {
             stk[sp++] = nl | (cu << 29) | cv;
         }
     }
+    return cells;
 }
 
 // the boundary integrand (without 1 / 4 pi) at t of curve C in frame F
@@ -328,7 +330,7 @@ __device__ inline double area_rate(const double* __restrict__ C, double t, const
 
 // adaptive GK15 of area_rate over [0, 1]: depth-first over dyadic intervals
 __device__ double curve_integral(const double* __restrict__ C, const double* p, const Frame& F, double eps,
-                                 int max_depth) {
+                                 int max_depth, int& nint) {
     unsigned long long stk[kQuadStack];
     int sp = 0;
     stk[sp++] = 0ull;
@@ -359,25 +361,40 @@ __device__ double curve_integral(const double* __restrict__ C, const double* p, 
             stk[sp++] = nl | (2ull * idx);
         }
     }
+    nint += intervals;
     return sum;
 }
 
-__global__ __launch_bounds__(64) void k_param(const double* __restrict__ patches, const double* __restrict__ boxes,
-                                              long long npatch, const double* __restrict__ curves,
-                                              long long ncurves, const float* __restrict__ qx,
-                                              const float* __restrict__ qy, const float* __restrict__ qz,
-                                              long long qs, long long nq, double tau, double eps, int max_depth,
-                                              double* __restrict__ w, int* __restrict__ chi_out,
-                                              int* __restrict__ dir_out) {
-    const long long i = blockIdx.x * 64ll + threadIdx.x;
-    if (i >= nq) return;
+// One wave per query: lane l takes patches l, l + 64, ... for the crossings and
+// curves l, l + 64, ... for the boundary term; the partial counts and sums are
+// combined across the wave in a fixed butterfly order.  A direction is ambiguous
+// for the query if it is for any lane.  STATS: also add the wave's quadrature
+// intervals and sub-patch cells to stats[0], stats[1].
+constexpr int kParamWaves = 4;   // waves (queries) per workgroup
+
+__device__ inline double wave_sum(double x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// crossings: chi and the chosen direction per query (-1: all ambiguous)
+template <bool STATS>
+__global__ __launch_bounds__(64 * kParamWaves) void k_param_chi(
+    const double* __restrict__ patches, const double* __restrict__ boxes, long long npatch,
+    const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz, long long qs,
+    long long nq, double tau, int* __restrict__ chi_out, int* __restrict__ dir_out,
+    unsigned long long* __restrict__ stats) {
+    const long long i = blockIdx.x * (long long)kParamWaves + (threadIdx.x >> 6);
+    if (i >= nq) return;   // whole waves leave together
+    const int lane = threadIdx.x & 63;
     RayState R;
     R.p[0] = qx[i * qs];
     R.p[1] = qy[i * qs];
     R.p[2] = qz[i * qs];
     R.tau = tau;
     R.margin = 1e-9;
-    int dir = -1;
+    int dir = -1, chi = 0;
+    long long ncell = 0;
     for (int k = 0; k < kNDir && dir < 0; ++k) {
         const Frame F = make_frame(k);
         for (int c = 0; c < 3; ++c) {
@@ -387,20 +404,57 @@ __global__ __launch_bounds__(64) void k_param(const double* __restrict__ patches
         }
         R.chi = 0;
         R.amb = false;
-        for (long long pi = 0; pi < npatch && !R.amb; ++pi)
-            if (ray_box(R, boxes + 6 * pi, boxes + 6 * pi + 3)) patch_ray(R, patches + 48 * pi);
-        if (!R.amb) dir = k;
+        for (long long pi = lane; pi < npatch && !R.amb; pi += 64)
+            if (ray_box(R, boxes + 6 * pi, boxes + 6 * pi + 3)) ncell += patch_ray(R, patches + 48 * pi);
+        if (__builtin_amdgcn_ballot_w64(R.amb) == 0ull) {
+            dir = k;
+            int c = R.chi;
+            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+            chi = c;
+        }
     }
-    double wv = NAN;
-    if (dir >= 0) {
-        const Frame F = make_frame(dir);
-        double S = 0.0;
-        for (long long c = 0; c < ncurves; ++c) S += curve_integral(curves + 12 * c, R.p, F, eps, max_depth);
-        wv = (double)R.chi + S * kInv4Pi;
+    if (lane == 0) {
+        chi_out[i] = dir >= 0 ? chi : 0;
+        dir_out[i] = dir;
     }
-    w[i] = wv;
-    if (chi_out) chi_out[i] = dir >= 0 ? R.chi : 0;
-    if (dir_out) dir_out[i] = dir;
+    if constexpr (STATS) atomicAdd(&stats[1], (unsigned long long)ncell);
+}
+
+// boundary term along the direction chosen for each query, and w
+template <bool STATS>
+__global__ __launch_bounds__(64 * kParamWaves) void k_param_bdry(
+    const double* __restrict__ curves, long long ncurves, const float* __restrict__ qx,
+    const float* __restrict__ qy, const float* __restrict__ qz, long long qs, long long nq, double eps, int max_depth,
+    const int* __restrict__ chi, const int* __restrict__ dir, double* __restrict__ w,
+    unsigned long long* __restrict__ stats) {
+    const long long i = blockIdx.x * (long long)kParamWaves + (threadIdx.x >> 6);
+    if (i >= nq) return;
+    const int lane = threadIdx.x & 63;
+    const int d = dir[i];
+    const double p[3] = {(double)qx[i * qs], (double)qy[i * qs], (double)qz[i * qs]};
+    double S = 0.0;
+    int nint = 0;
+    if (d >= 0) {
+        const Frame F = make_frame(d);
+        for (long long c = lane; c < ncurves; c += 64) S += curve_integral(curves + 12 * c, p, F, eps, max_depth, nint);
+    }
+    S = wave_sum(S);
+    if (lane == 0) w[i] = d >= 0 ? (double)chi[i] + S * kInv4Pi : NAN;
+    if constexpr (STATS) atomicAdd(&stats[0], (unsigned long long)nint);
+}
+
+// both kernels for queries [0, n): chi and dir are device buffers of n
+template <bool STATS>
+hipError_t launch_param(const gwn_patches_s* h, const float* qx, const float* qy, const float* qz, long long qs,
+                        long long n, double* w, int* chi, int* dir, unsigned long long* stats, hipStream_t st) {
+    const unsigned blocks = (unsigned)((n + kParamWaves - 1) / kParamWaves);
+    k_param_chi<STATS><<<blocks, 64 * kParamWaves, 0, st>>>(h->patches, h->boxes, h->npatch, qx, qy, qz, qs, n,
+                                                            h->tau, chi, dir, stats);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_param_bdry<STATS><<<blocks, 64 * kParamWaves, 0, st>>>(h->curves, h->ncurves, qx, qy, qz, qs, n, h->eps,
+                                                             h->max_depth, chi, dir, w, stats);
+    return hipGetLastError();
 }
 
 // host: the four boundary curves of patch k, counter-clockwise in (u, v)
@@ -571,15 +625,46 @@ gwn_status gwn_patches_query(gwn_patches h, const float* qx, const float* qy, co
         return GWN_E_INVALID;
     }
     hipStream_t st = (hipStream_t)stream;
-    const long long chunk = 1ll << 30;
-    for (long long o = 0; o < nq; o += chunk) {
+    const long long chunk = 1ll << 30;   // queries (workgroups of kParamWaves) per launch
+    int *chi = nullptr, *dir = nullptr;
+    hipError_t e = hipSuccess;
+    if (!chi_out) e = hipMallocAsync((void**)&chi, sizeof(int) * (size_t)std::min<long long>(std::max<long long>(nq, 1), chunk), st);
+    if (e == hipSuccess && !dir_out)
+        e = hipMallocAsync((void**)&dir, sizeof(int) * (size_t)std::min<long long>(std::max<long long>(nq, 1), chunk), st);
+    for (long long o = 0; o < nq && e == hipSuccess; o += chunk) {
         const long long n = std::min<long long>(chunk, nq - o);
-        gwn::k_param<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(
-            h->patches, h->boxes, h->npatch, h->curves, h->ncurves, qx + o * qstride, qy + o * qstride,
-            qz + o * qstride, qstride, n, h->tau, h->eps, h->max_depth, w_out + o, chi_out ? chi_out + o : nullptr,
-            dir_out ? dir_out + o : nullptr);
-        GWN_HIP_TRY(hipGetLastError());
+        e = gwn::launch_param<false>(h, qx + o * qstride, qy + o * qstride, qz + o * qstride, qstride, n, w_out + o,
+                                     chi_out ? chi_out + o : chi, dir_out ? dir_out + o : dir, nullptr, st);
     }
+    if (chi) (void)hipFreeAsync(chi, st);
+    if (dir) (void)hipFreeAsync(dir, st);
+    GWN_HIP_TRY(e);
+    return GWN_OK;
+}
+
+gwn_status gwn_patches_query_stats(gwn_patches h, const float* qx, const float* qy, const float* qz,
+                                   int64_t qstride, int64_t nq, double* w_out, int64_t* counts, void* stream) {
+    gwn::clear_error();
+    if (!h || !counts || nq < 0 || qstride < 1 || nq > (1ll << 30) || (nq > 0 && (!qx || !qy || !qz || !w_out))) {
+        set_error("gwn_patches_query_stats: null argument, nq outside [0, 2^30] or qstride < 1");
+        return GWN_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long* d = nullptr;
+    GWN_HIP_TRY(hipMalloc((void**)&d, 2 * sizeof(unsigned long long)));
+    unsigned long long hc[2] = {0, 0};
+    int* cd = nullptr;
+    hipError_t e = hipMemcpyAsync(d, hc, sizeof hc, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&cd, sizeof(int) * 2 * (size_t)std::max<long long>(nq, 1), st);
+    if (e == hipSuccess && nq > 0)
+        e = gwn::launch_param<true>(h, qx, qy, qz, qstride, nq, w_out, cd, cd + nq, d, st);
+    if (cd) (void)hipFreeAsync(cd, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hc, d, sizeof hc, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    GWN_HIP_TRY(e);
+    counts[0] = (int64_t)hc[0];
+    counts[1] = (int64_t)hc[1];
     return GWN_OK;
 }
 

@@ -343,7 +343,9 @@ def _load_patches(L):
     L.gwn_patches_info_get.argtypes = [vp, ctypes.POINTER(PatchesInfo)]
     L.gwn_patches_query.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp, vp]
     L.gwn_patches_destroy.argtypes = [vp]
-    for f in ("gwn_patches_build", "gwn_patches_info_get", "gwn_patches_query", "gwn_patches_destroy"):
+    L.gwn_patches_query_stats.argtypes = [vp, vp, vp, vp, i64, i64, vp, ctypes.POINTER(ctypes.c_int64), vp]
+    for f in ("gwn_patches_build", "gwn_patches_info_get", "gwn_patches_query", "gwn_patches_destroy",
+              "gwn_patches_query_stats"):
         getattr(L, f).restype = ctypes.c_int
     L._patches_ready = True
 
@@ -385,6 +387,18 @@ class Patches:
                                    _ptr(chi) if chi is not None else None, _ptr(dr) if dr is not None else None,
                                    _stream(stream)))
         return (out, chi, dr) if want_chi else out
+
+    def query_stats(self, Q, stream=None):
+        """(w, quadrature intervals, sub-patch cells) of one evaluation of Q."""
+        import torch
+        L = load()
+        Q = _points(Q)
+        out = torch.empty(Q.shape[0], dtype=torch.float64, device=Q.device)
+        counts = (ctypes.c_int64 * 2)()
+        base = _ptr(Q)
+        _check(L.gwn_patches_query_stats(self._h, base, base + 4, base + 8, 3, Q.shape[0], _ptr(out), counts,
+                                         _stream(stream)))
+        return out, int(counts[0]), int(counts[1])
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
