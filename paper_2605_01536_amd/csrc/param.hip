@@ -42,7 +42,8 @@ struct gwn_patches_s {
     double tau = 0.0, eps = 0.0, diag = 0.0;
     int max_depth = 25;
     double* patches = nullptr;   // npatch * 48
-    double* boxes = nullptr;     // npatch * 6 (lo xyz, hi xyz of the control points)
+    double* boxes = nullptr;     // npatch * 8: lo xyz, hi xyz of the control points, the first
+                                 // subdivision level worth testing for flatness, unused
     double* curves = nullptr;    // ncurves * 12
 };
 
@@ -140,7 +141,7 @@ __device__ inline void extract(const double* __restrict__ P, int level, unsigned
 }
 
 struct RayState {
-    double p[3], d[3], e1[3], e2[3];
+    double p[3], d[3], e1[3], e2[3], invd[3];
     double tau, margin;
     int chi;
     bool amb;
@@ -154,7 +155,7 @@ __device__ inline bool ray_box(const RayState& R, const double* lo, const double
         if (R.d[c] == 0.0) {
             if (R.p[c] < l || R.p[c] > u) return false;
         } else {
-            const double inv = 1.0 / R.d[c];
+            const double inv = R.invd[c];
             double a = (l - R.p[c]) * inv, b = (u - R.p[c]) * inv;
             if (a > b) {
                 const double t = a;
@@ -268,7 +269,7 @@ __device__ inline void bilinear_hits(RayState& R, const double* S) {
 
 // one patch: depth-first over sub-patch cells whose control-point box meets the ray
 // (returns the number of cells extracted)
-__device__ int patch_ray(RayState& R, const double* __restrict__ P) {
+__device__ int patch_ray(RayState& R, const double* __restrict__ P, int flat_level) {
     unsigned long long stk[kRayStack];
     int sp = 0;
     stk[sp++] = 0ull;   // level 0, cell (0, 0)
@@ -290,7 +291,9 @@ __device__ int patch_ray(RayState& R, const double* __restrict__ P) {
                 hi[c] = fmax(hi[c], S[3 * k + c]);
             }
         if (!ray_box(R, lo, hi)) continue;
-        if (level >= kMaxLevel || net_deviation(S) <= R.tau) {
+        // the net's distance from bilinear falls about 4x per level: cells above
+        // flat_level are subdivided without the test (a later leaf is as valid)
+        if (level >= kMaxLevel || (level >= flat_level && net_deviation(S) <= R.tau)) {
             bilinear_hits(R, S);
             continue;
         }
@@ -401,11 +404,13 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_chi(
             R.d[c] = F.d[c];
             R.e1[c] = F.e1[c];
             R.e2[c] = F.e2[c];
+            R.invd[c] = F.d[c] != 0.0 ? 1.0 / F.d[c] : 0.0;
         }
         R.chi = 0;
         R.amb = false;
         for (long long pi = lane; pi < npatch && !R.amb; pi += 64)
-            if (ray_box(R, boxes + 6 * pi, boxes + 6 * pi + 3)) ncell += patch_ray(R, patches + 48 * pi);
+            if (ray_box(R, boxes + 8 * pi, boxes + 8 * pi + 3))
+                ncell += patch_ray(R, patches + 48 * pi, (int)boxes[8 * pi + 6]);
         if (__builtin_amdgcn_ballot_w64(R.amb) == 0ull) {
             dir = k;
             int c = R.chi;
@@ -513,9 +518,9 @@ gwn_status gwn_patches_build(const double* cps, int64_t npatch, const gwn_patch_
         GWN_HIP_TRY(hipStreamSynchronize(st));
     }
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    std::vector<double> boxes((size_t)npatch * 6);
+    std::vector<double> boxes((size_t)npatch * 8);
     for (int64_t k = 0; k < npatch; ++k) {
-        double* b = &boxes[6 * k];
+        double* b = &boxes[8 * k];
         for (int c = 0; c < 3; ++c) {
             b[c] = 1e300;
             b[3 + c] = -1e300;
@@ -572,6 +577,27 @@ gwn_status gwn_patches_build(const double* cps, int64_t npatch, const gwn_patch_
                          (hi[2] - lo[2]) * (hi[2] - lo[2]));
     h->diag = diag;
     h->tau = tau_rel * std::max(diag, 1e-300);
+    // first level worth the flatness test: the control net's distance from the
+    // bilinear patch through its corners falls about 4x per subdivision level
+    for (int64_t k = 0; k < npatch; ++k) {
+        const double* Pk = &P[48 * k];
+        double dev = 0.0;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                const double u = i / 3.0, v = j / 3.0;
+                double e2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double b = (1.0 - u) * ((1.0 - v) * Pk[c] + v * Pk[9 + c]) +
+                                     u * ((1.0 - v) * Pk[36 + c] + v * Pk[45 + c]);
+                    e2 += (Pk[(4 * i + j) * 3 + c] - b) * (Pk[(4 * i + j) * 3 + c] - b);
+                }
+                dev = std::max(dev, std::sqrt(e2));
+            }
+        int lv = 0;
+        if (dev > h->tau) lv = std::max(0, (int)std::floor(std::log(dev / h->tau) / std::log(4.0)) - 1);
+        boxes[8 * k + 6] = (double)std::min(lv, 28);
+        boxes[8 * k + 7] = 0.0;
+    }
     h->eps = eps;
     h->max_depth = max_depth;
     auto up = [&](double** dst, const std::vector<double>& src) -> hipError_t {
