@@ -327,8 +327,10 @@ __device__ inline double area_rate(const double* __restrict__ C, double t, const
     const double dy = dr[0] * F.e2[0] + dr[1] * F.e2[1] + dr[2] * F.e2[2];
     const double rho2 = rx * rx + ry * ry;
     const double l = sqrt(rho2 + rz * rz);
-    const double s = rz > 0.0 ? rho2 / (l + rz) : l - rz;
-    return (ry * dx - rx * dy) / (l * s);
+    // (ry dx - rx dy) / (l s) with s = l - r_z, written for r_z > 0 through
+    // s = rho^2 / (l + r_z) without a second division
+    const double num = ry * dx - rx * dy;
+    return rz > 0.0 ? num * (l + rz) / (l * rho2) : num / (l * (l - rz));
 }
 
 // adaptive GK15 of area_rate over [0, 1]: depth-first over dyadic intervals
