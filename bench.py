@@ -474,7 +474,7 @@ def bench_parametric(args):
     n_patch, n = 100, 32
     rng = np.random.default_rng(7)
     P = rng.uniform(0.0, 1.0, size=(n_patch, 16, 3))
-    g = (np.arange(n) + 0.5) / n * 1.4 - 0.2
+    g = (-0.2 + (np.arange(n) + 0.5) * (1.4 / n)).astype(np.float32)   # the grid's own rounding
     X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
     Q = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1).astype(np.float32)
     pt = gwn.Patches(torch.from_numpy(P).cuda())
@@ -482,10 +482,18 @@ def bench_parametric(args):
     Qd = torch.from_numpy(Q).cuda()
     w = torch.empty(Q.shape[0], device="cuda", dtype=torch.float64)
     st = torch.cuda.current_stream()
-    _, nint, ncell = pt.query_stats(Qd, stream=st)
-    ev_ms, wall_ms = _timed(lambda: pt.query(Qd, out=w, stream=st), args.steps, args.warmup, st)
-    _, _, dirs = pt.query(Qd, want_chi=True, stream=st)
+    origin, spacing, dims = (-0.2, -0.2, -0.2), (1.4 / n, 1.4 / n, 1.4 / n), (n, n, n)
+    counts = []
+    pt.query_grid(origin, spacing, dims, out=w, stream=st, counts=counts)
+    nint, ncell = counts
+    # the grid with ray reuse (the timed path), then single rays at the same points for comparison
+    ev_ms, wall_ms = _timed(lambda: pt.query_grid(origin, spacing, dims, out=w, stream=st), args.steps,
+                            args.warmup, st)
+    _, _, dirs = pt.query_grid(origin, spacing, dims, want_chi=True, stream=st)
+    wb = torch.empty_like(w)
+    ev_b, _ = _timed(lambda: pt.query(Qd, out=wb, stream=st), max(1, args.steps // 2), 1, st)
     torch.cuda.synchronize()
+    same = float((w - wb).abs().max())
     dirs = dirs.cpu().numpy()
     slots = nint * PARAM_INTERVAL_SLOTS + ncell * PARAM_CELL_SLOTS
     achieved = slots / (ev_ms / 1e3)
@@ -493,9 +501,9 @@ def bench_parametric(args):
             "frac": achieved / PEAK_SLOTS, "traffic": None, "kernel": "k_param",
             "quadrature_intervals_per_query": nint / Q.shape[0], "subpatch_cells_per_query": ncell / Q.shape[0],
             "slots_per_interval": PARAM_INTERVAL_SLOTS, "slots_per_cell": PARAM_CELL_SLOTS}
-    print(f"[bench] parametric: {ev_ms:.2f} ms per {Q.shape[0]} points, {nint / Q.shape[0]:.0f} intervals and "
-          f"{ncell / Q.shape[0]:.0f} cells per point, directions {np.bincount(dirs + 1).tolist()}",
-          file=sys.stderr, flush=True)
+    print(f"[bench] parametric: {ev_ms:.2f} ms per {Q.shape[0]} points (single rays {ev_b:.2f} ms, max diff "
+          f"{same:.1e}), {nint / Q.shape[0]:.0f} intervals and {ncell / Q.shape[0]:.0f} cells per point, "
+          f"directions {np.bincount(dirs + 2).tolist()} (pending, none, 0..3)", file=sys.stderr, flush=True)
     extra = {"roofline": roof}
     if not args.no_cpu_baseline:
         import oracle as O
@@ -513,7 +521,9 @@ def bench_parametric(args):
     _emit("GWN queries/sec, cubic Bezier patches (Sec. 4.4)", Q.shape[0] / (ev_ms / 1e3), "queries/s", args, ev_ms,
           {"workload": f"{n_patch} cubic Bezier patches, control points U[0,1]^3 (seed 7), {n}^3 cell-centred grid "
                        "over [-0.2, 1.2]^3", "patches": n_patch, "boundary_curves": info["ncurves"],
-           "queries": int(Q.shape[0]), "tau": info["tau"], "eps": info["eps"], "max_depth": info["max_depth"]},
+           "queries": int(Q.shape[0]), "tau": info["tau"], "eps": info["eps"], "max_depth": info["max_depth"],
+           "path": "gwn_patches_query_grid (one line per column)", "single_rays_ms": ev_b,
+           "max_diff_vs_single_rays": same},
           extra, dtype="f64")
 
 

@@ -309,6 +309,20 @@ gwn_status gwn_patches_build(const double* cps, int64_t npatch, const gwn_patch_
 gwn_status gwn_patches_info_get(gwn_patches h, gwn_patches_info* out);
 gwn_status gwn_patches_query(gwn_patches h, const float* qx, const float* qy, const float* qz, int64_t qstride,
                              int64_t nq, double* w_out, int32_t* chi_out, int32_t* dir_out, void* stream);
+/* gwn_patches_query_grid: the same on the cell-centred grid point (i, j, k) =
+ * float(origin + (idx + 0.5) * spacing) (each coordinate rounded once from
+ * double), outputs at (i * ny + j) * nz + k.  Each (i, j) column's vertical line
+ * is intersected with the patches once and every sample counts the crossings
+ * above it (ray reuse, Sec. 4.3.1); a column with an ambiguous hit, and a
+ * sample within the on-surface margin of a crossing, take single rays as in
+ * gwn_patches_query.  Results equal gwn_patches_query's at the same points.
+ * counts (nullable HOST array of 2): when given, the work is also counted as
+ * for gwn_patches_query_stats and the call synchronises `stream`.  Errors:
+ * GWN_E_INVALID for null arguments, negative sizes, or more than 2^30 points
+ * or columns. */
+gwn_status gwn_patches_query_grid(gwn_patches h, const double* origin, const double* spacing, const int64_t* dims,
+                                  double* w_out, int32_t* chi_out, int32_t* dir_out, int64_t* counts,
+                                  void* stream);
 /* The same evaluation (w only) that also counts its work: counts[0] = quadrature
  * intervals (15 integrand evaluations each), counts[1] = sub-patch cells
  * extracted by the ray subdivision, summed over the queries (nq <= 2^30).

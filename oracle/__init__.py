@@ -298,12 +298,17 @@ def parametric(P, Q, eps=1e-12, tau_rel=1e-9, margin=1e-9, dirs=None):
         if todo.size == 0:
             break
         c, amb = param_chi(P, Q[todo], d, tau_rel * diag, margin)
-        ok = todo[~amb]
-        if ok.size:
-            S = param_boundary(curves, Q[ok], d, eps) if len(curves) else np.zeros(ok.size)
-            w[ok] = c[~amb] + S
-            chi[ok] = c[~amb]
-            di[ok] = k
+        sel = np.flatnonzero(~amb)
+        if sel.size:
+            S = param_boundary(curves, Q[todo[sel]], d, eps) if len(curves) else np.zeros(sel.size)
+            # Alg. 2's integrand is 0/0 where the boundary passes exactly through
+            # -x0 (v = 0 and X = 0): such a direction counts as ambiguous too
+            bad = ~np.isfinite(S)
+            amb[sel[bad]] = True
+            good = sel[~bad]
+            w[todo[good]] = c[good] + S[~bad]
+            chi[todo[good]] = c[good]
+            di[todo[good]] = k
         todo = todo[amb]
     return w, chi, di
 

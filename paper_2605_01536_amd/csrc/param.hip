@@ -145,10 +145,17 @@ struct RayState {
     double tau, margin;
     int chi;
     bool amb;
+    // line mode (a grid column): every hit along the whole line goes to an LDS
+    // list of (z, sign); a full list makes the line ambiguous
+    bool line = false;
+    double* hz = nullptr;
+    int* hs = nullptr;
+    int* hn = nullptr;
+    int hcap = 0;
 };
 
 __device__ inline bool ray_box(const RayState& R, const double* lo, const double* hi) {
-    double t0 = 0.0, t1 = 1e300;
+    double t0 = R.line ? -1e300 : 0.0, t1 = 1e300;
     for (int c = 0; c < 3; ++c) {
         const double pad = 1e-12 * (1.0 + fabs(lo[c]) + fabs(hi[c]));
         const double l = lo[c] - pad, u = hi[c] + pad;
@@ -257,6 +264,16 @@ __device__ inline void bilinear_hits(RayState& R, const double* S) {
         const double t = r0 * R.d[0] + r1 * R.d[1] + r2 * R.d[2];
         if (!(nn > 0.0) || fabs(nd) < 1e-9 * nn) {
             R.amb = true;
+            continue;
+        }
+        if (R.line) {   // the samples of the column classify the hit later
+            const int slot = atomicAdd(R.hn, 1);
+            if (slot < R.hcap) {
+                R.hz[slot] = X[2];
+                R.hs[slot] = nd > 0.0 ? 1 : -1;
+            } else {
+                R.amb = true;
+            }
             continue;
         }
         if (fabs(t) <= 1e-12 * (1.0 + sqrt(r0 * r0 + r1 * r1 + r2 * r2))) {
@@ -382,20 +399,48 @@ __device__ inline double wave_sum(double x) {
     return x;
 }
 
-// crossings: chi and the chosen direction per query (-1: all ambiguous)
-template <bool STATS>
+// query points: strided FP32 arrays, or the cell-centred grid
+// float(origin + (idx + 0.5) spacing) (each coordinate rounded once from FP64,
+// as for meshes), flattened (i ny + j) nz + k
+struct BatchPts {
+    const float *x, *y, *z;
+    long long qs;
+    __device__ inline void get(long long i, double* p) const {
+        p[0] = x[i * qs];
+        p[1] = y[i * qs];
+        p[2] = z[i * qs];
+    }
+};
+
+__device__ inline float cell_coord(double o, double s, long long i) {
+    return (float)__dadd_rn(o, __dmul_rn((double)i + 0.5, s));
+}
+
+struct GridPts {
+    double o[3], s[3];
+    long long ny, nz;
+    __device__ inline void get(long long i, double* p) const {
+        const long long k = i % nz, ij = i / nz;
+        p[0] = cell_coord(o[0], s[0], ij / ny);
+        p[1] = cell_coord(o[1], s[1], ij % ny);
+        p[2] = cell_coord(o[2], s[2], k);
+    }
+};
+
+constexpr int kPending = -2;   // direction not decided yet (a grid column that needs single rays)
+
+// crossings: chi and the chosen direction per query (-1: all ambiguous).
+// PENDING: only the queries whose direction is kPending.
+template <bool STATS, bool PENDING, class Pts>
 __global__ __launch_bounds__(64 * kParamWaves) void k_param_chi(
-    const double* __restrict__ patches, const double* __restrict__ boxes, long long npatch,
-    const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz, long long qs,
-    long long nq, double tau, int* __restrict__ chi_out, int* __restrict__ dir_out,
-    unsigned long long* __restrict__ stats) {
+    const double* __restrict__ patches, const double* __restrict__ boxes, long long npatch, Pts pts, long long nq,
+    double tau, int* __restrict__ chi_out, int* __restrict__ dir_out, unsigned long long* __restrict__ stats) {
     const long long i = blockIdx.x * (long long)kParamWaves + (threadIdx.x >> 6);
     if (i >= nq) return;   // whole waves leave together
+    if (PENDING && dir_out[i] != kPending) return;
     const int lane = threadIdx.x & 63;
     RayState R;
-    R.p[0] = qx[i * qs];
-    R.p[1] = qy[i * qs];
-    R.p[2] = qz[i * qs];
+    pts.get(i, R.p);
     R.tau = tau;
     R.margin = 1e-9;
     int dir = -1, chi = 0;
@@ -427,18 +472,87 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_chi(
     if constexpr (STATS) atomicAdd(&stats[1], (unsigned long long)ncell);
 }
 
-// boundary term along the direction chosen for each query, and w
+// Grid columns (Sec. 4.3.1's ray reuse): one wave per (i, j) column finds every
+// crossing of the column's vertical line (+z) once; each sample's chi is the
+// signed count of the crossings above it.  A column whose line has an
+// ambiguous hit, and a sample within the on-surface margin of a crossing, are
+// left kPending for single rays.
+constexpr int kMaxHits = 256;
+
 template <bool STATS>
+__global__ __launch_bounds__(64 * kParamWaves) void k_param_cols(
+    const double* __restrict__ patches, const double* __restrict__ boxes, long long npatch, GridPts g,
+    long long ncols, double tau, int* __restrict__ chi_out, int* __restrict__ dir_out,
+    unsigned long long* __restrict__ stats) {
+    __shared__ double hz[kParamWaves][kMaxHits];
+    __shared__ int hs[kParamWaves][kMaxHits];
+    __shared__ int hn[kParamWaves];
+    const int wave = threadIdx.x >> 6;
+    const long long col = blockIdx.x * (long long)kParamWaves + wave;
+    if (col >= ncols) return;   // whole waves leave together
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) hn[wave] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const long long ci = col / g.ny, cj = col - ci * g.ny;
+    RayState R;
+    R.p[0] = cell_coord(g.o[0], g.s[0], ci);
+    R.p[1] = cell_coord(g.o[1], g.s[1], cj);
+    R.p[2] = 0.0;
+    R.tau = tau;
+    R.margin = 1e-9;
+    const Frame F = make_frame(0);
+    for (int c = 0; c < 3; ++c) {
+        R.d[c] = F.d[c];
+        R.e1[c] = F.e1[c];
+        R.e2[c] = F.e2[c];
+        R.invd[c] = F.d[c] != 0.0 ? 1.0 / F.d[c] : 0.0;
+    }
+    R.chi = 0;
+    R.amb = false;
+    R.line = true;
+    R.hz = hz[wave];
+    R.hs = hs[wave];
+    R.hn = &hn[wave];
+    R.hcap = kMaxHits;
+    long long ncell = 0;
+    for (long long pi = lane; pi < npatch && !R.amb; pi += 64)
+        if (ray_box(R, boxes + 8 * pi, boxes + 8 * pi + 3))
+            ncell += patch_ray(R, patches + 48 * pi, (int)boxes[8 * pi + 6]);
+    const bool amb = __builtin_amdgcn_ballot_w64(R.amb) != 0ull;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nh = min(hn[wave], kMaxHits);
+    const long long base = col * g.nz;
+    for (long long k = lane; k < g.nz; k += 64) {
+        const double pz = cell_coord(g.o[2], g.s[2], k);
+        int chi = 0;
+        bool on = amb;
+        for (int h = 0; h < nh && !on; ++h) {
+            const double t = hz[wave][h] - pz;
+            if (fabs(t) <= 1e-12 * (1.0 + fabs(t))) on = true;
+            else if (t > 0.0) chi += hs[wave][h];
+        }
+        chi_out[base + k] = on ? 0 : chi;
+        dir_out[base + k] = on ? kPending : 0;
+    }
+    if constexpr (STATS) atomicAdd(&stats[1], (unsigned long long)ncell);
+}
+
+// boundary term along the direction chosen for each query, and w
+template <bool STATS, class Pts>
 __global__ __launch_bounds__(64 * kParamWaves) void k_param_bdry(
-    const double* __restrict__ curves, long long ncurves, const float* __restrict__ qx,
-    const float* __restrict__ qy, const float* __restrict__ qz, long long qs, long long nq, double eps, int max_depth,
+    const double* __restrict__ curves, long long ncurves, Pts pts, long long nq, double eps, int max_depth,
     const int* __restrict__ chi, const int* __restrict__ dir, double* __restrict__ w,
     unsigned long long* __restrict__ stats) {
     const long long i = blockIdx.x * (long long)kParamWaves + (threadIdx.x >> 6);
     if (i >= nq) return;
     const int lane = threadIdx.x & 63;
     const int d = dir[i];
-    const double p[3] = {(double)qx[i * qs], (double)qy[i * qs], (double)qz[i * qs]};
+    double p[3];
+    pts.get(i, p);
     double S = 0.0;
     int nint = 0;
     if (d >= 0) {
@@ -455,12 +569,32 @@ template <bool STATS>
 hipError_t launch_param(const gwn_patches_s* h, const float* qx, const float* qy, const float* qz, long long qs,
                         long long n, double* w, int* chi, int* dir, unsigned long long* stats, hipStream_t st) {
     const unsigned blocks = (unsigned)((n + kParamWaves - 1) / kParamWaves);
-    k_param_chi<STATS><<<blocks, 64 * kParamWaves, 0, st>>>(h->patches, h->boxes, h->npatch, qx, qy, qz, qs, n,
-                                                            h->tau, chi, dir, stats);
+    const BatchPts pts{qx, qy, qz, qs};
+    k_param_chi<STATS, false><<<blocks, 64 * kParamWaves, 0, st>>>(h->patches, h->boxes, h->npatch, pts, n, h->tau,
+                                                                   chi, dir, stats);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_param_bdry<STATS><<<blocks, 64 * kParamWaves, 0, st>>>(h->curves, h->ncurves, qx, qy, qz, qs, n, h->eps,
-                                                             h->max_depth, chi, dir, w, stats);
+    k_param_bdry<STATS><<<blocks, 64 * kParamWaves, 0, st>>>(h->curves, h->ncurves, pts, n, h->eps, h->max_depth,
+                                                             chi, dir, w, stats);
+    return hipGetLastError();
+}
+
+// a grid: columns once, single rays for what they leave pending, then the boundary term
+template <bool STATS>
+hipError_t launch_param_grid(const gwn_patches_s* h, const GridPts& g, long long nx, double* w, int* chi, int* dir,
+                             unsigned long long* stats, hipStream_t st) {
+    const long long ncols = nx * g.ny, n = ncols * g.nz;
+    k_param_cols<STATS><<<(unsigned)((ncols + kParamWaves - 1) / kParamWaves), 64 * kParamWaves, 0, st>>>(
+        h->patches, h->boxes, h->npatch, g, ncols, h->tau, chi, dir, stats);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)((n + kParamWaves - 1) / kParamWaves);
+    k_param_chi<STATS, true><<<blocks, 64 * kParamWaves, 0, st>>>(h->patches, h->boxes, h->npatch, g, n, h->tau, chi,
+                                                                  dir, stats);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_param_bdry<STATS><<<blocks, 64 * kParamWaves, 0, st>>>(h->curves, h->ncurves, g, n, h->eps, h->max_depth, chi,
+                                                             dir, w, stats);
     return hipGetLastError();
 }
 
@@ -667,6 +801,66 @@ gwn_status gwn_patches_query(gwn_patches h, const float* qx, const float* qy, co
     if (chi) (void)hipFreeAsync(chi, st);
     if (dir) (void)hipFreeAsync(dir, st);
     GWN_HIP_TRY(e);
+    return GWN_OK;
+}
+
+gwn_status gwn_patches_query_grid(gwn_patches h, const double* origin, const double* spacing, const int64_t* dims,
+                                  double* w_out, int32_t* chi_out, int32_t* dir_out, int64_t* counts,
+                                  void* stream) {
+    gwn::clear_error();
+    if (!h || !origin || !spacing || !dims || dims[0] < 0 || dims[1] < 0 || dims[2] < 0) {
+        set_error("gwn_patches_query_grid: null argument or negative size");
+        return GWN_E_INVALID;
+    }
+    const long long nx = dims[0], ny = dims[1], nz = dims[2];
+    if (nx == 0 || ny == 0 || nz == 0) return GWN_OK;
+    if (!w_out || nx > (1ll << 20) || ny > (1ll << 20) || nz > (1ll << 30) || nx * ny > (1ll << 30) ||
+        (double)nx * (double)ny * (double)nz > 0x1p36) {
+        set_error("gwn_patches_query_grid: null output or grid too large (at most 2^30 columns and 2^36 points)");
+        return GWN_E_INVALID;
+    }
+    int dev = -1;
+    GWN_HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device) {
+        set_error("gwn_patches_query_grid: the patches were built on device %d, the current device is %d", h->device,
+                  dev);
+        return GWN_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const long long n = nx * ny * nz;
+    if (n > (1ll << 30)) {
+        set_error("gwn_patches_query_grid: at most 2^30 points per call");
+        return GWN_E_INVALID;
+    }
+    int *chi = chi_out, *dir = dir_out;
+    unsigned long long* d = nullptr;
+    unsigned long long hc[2] = {0, 0};
+    hipError_t e = hipSuccess;
+    if (!chi) e = hipMallocAsync((void**)&chi, sizeof(int) * (size_t)n, st);
+    if (e == hipSuccess && !dir) e = hipMallocAsync((void**)&dir, sizeof(int) * (size_t)n, st);
+    if (e == hipSuccess && counts) e = hipMallocAsync((void**)&d, sizeof hc, st);
+    if (e == hipSuccess && counts) e = hipMemcpyAsync(d, hc, sizeof hc, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        gwn::GridPts g;
+        for (int c = 0; c < 3; ++c) {
+            g.o[c] = origin[c];
+            g.s[c] = spacing[c];
+        }
+        g.ny = ny;
+        g.nz = nz;
+        e = counts ? gwn::launch_param_grid<true>(h, g, nx, w_out, chi, dir, d, st)
+                   : gwn::launch_param_grid<false>(h, g, nx, w_out, chi, dir, nullptr, st);
+    }
+    if (e == hipSuccess && counts) e = hipMemcpyAsync(hc, d, sizeof hc, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && counts) e = hipStreamSynchronize(st);
+    if (!chi_out && chi) (void)hipFreeAsync(chi, st);
+    if (!dir_out && dir) (void)hipFreeAsync(dir, st);
+    if (d) (void)hipFreeAsync(d, st);
+    GWN_HIP_TRY(e);
+    if (counts) {
+        counts[0] = (int64_t)hc[0];
+        counts[1] = (int64_t)hc[1];
+    }
     return GWN_OK;
 }
 

@@ -344,8 +344,11 @@ def _load_patches(L):
     L.gwn_patches_query.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp, vp]
     L.gwn_patches_destroy.argtypes = [vp]
     L.gwn_patches_query_stats.argtypes = [vp, vp, vp, vp, i64, i64, vp, ctypes.POINTER(ctypes.c_int64), vp]
+    L.gwn_patches_query_grid.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64), vp, vp, vp,
+                                         ctypes.POINTER(ctypes.c_int64), vp]
     for f in ("gwn_patches_build", "gwn_patches_info_get", "gwn_patches_query", "gwn_patches_destroy",
-              "gwn_patches_query_stats"):
+              "gwn_patches_query_stats", "gwn_patches_query_grid"):
         getattr(L, f).restype = ctypes.c_int
     L._patches_ready = True
 
@@ -386,6 +389,28 @@ class Patches:
         _check(L.gwn_patches_query(self._h, base, base + 4, base + 8, 3, n, _ptr(out),
                                    _ptr(chi) if chi is not None else None, _ptr(dr) if dr is not None else None,
                                    _stream(stream)))
+        return (out, chi, dr) if want_chi else out
+
+    def query_grid(self, origin, spacing, dims, want_chi=False, out=None, stream=None, counts=None):
+        """w (float64) on the cell-centred grid origin + (idx + 0.5) * spacing, z fastest (columns
+        share their vertical ray); with want_chi also crossing counts and direction indices; with
+        counts (a list) the call also appends (quadrature intervals, sub-patch cells)."""
+        import torch
+        L = load()
+        if len(dims) != 3 or min(int(x) for x in dims) < 0:
+            raise ValueError("dims must be three non-negative sizes")
+        n = int(dims[0]) * int(dims[1]) * int(dims[2])
+        out = _out(out, (n,), torch.float64, "cuda", "out")
+        chi = torch.empty(n, dtype=torch.int32, device="cuda") if want_chi else None
+        dr = torch.empty(n, dtype=torch.int32, device="cuda") if want_chi else None
+        o = (ctypes.c_double * 3)(*[float(x) for x in origin])
+        s = (ctypes.c_double * 3)(*[float(x) for x in spacing])
+        d = (ctypes.c_int64 * 3)(*[int(x) for x in dims])
+        cnt = (ctypes.c_int64 * 2)() if counts is not None else None
+        _check(L.gwn_patches_query_grid(self._h, o, s, d, _ptr(out), _ptr(chi) if chi is not None else None,
+                                        _ptr(dr) if dr is not None else None, cnt, _stream(stream)))
+        if counts is not None:
+            counts.extend([int(cnt[0]), int(cnt[1])])
         return (out, chi, dr) if want_chi else out
 
     def query_stats(self, Q, stream=None):

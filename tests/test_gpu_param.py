@@ -120,3 +120,30 @@ def test_edge_cases(gwn):
     with pytest.raises(gwn.GwnError) as ei:
         gwn.Patches(_dev(Pn))
     assert ei.value.status == 1
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_grid_ray_reuse_equals_single_rays(gwn, seed):
+    # the column path (one line per column, samples count the crossings above
+    # them) against single rays at the same points and the oracle; the grid
+    # puts columns exactly through control points and patch corners (ambiguous
+    # lines fall back to single rays)
+    rng = np.random.default_rng(500 + seed)
+    P = np.round(rng.uniform(0, 1, size=(5, 16, 3)) * 8) / 8
+    dims = (9, 11, 70)
+    origin, spacing = (-0.0625, -0.0625, -0.3), (0.125, 0.125, 1.6 / 70)
+    pt = gwn.Patches(_dev(P))
+    wg, cg, dg = pt.query_grid(origin, spacing, dims, want_chi=True)
+    ii, jj, kk = np.meshgrid(*[np.arange(n) for n in dims], indexing="ij")
+    Q = np.stack([(np.float64(origin[c]) + ([ii, jj, kk][c].ravel() + 0.5) * spacing[c]) for c in range(3)],
+                 axis=1).astype(np.float32)
+    wb, cb, db = pt.query(_q(Q), want_chi=True)
+    wg, cg, dg = wg.cpu().numpy(), cg.cpu().numpy(), dg.cpu().numpy()
+    wb, cb, db = wb.cpu().numpy(), cb.cpu().numpy(), db.cpu().numpy()
+    same = (dg == db) & (dg >= 0)
+    assert same.mean() > 0.5
+    assert np.array_equal(cg[same], cb[same])
+    ok = np.isfinite(wg) & np.isfinite(wb)
+    assert np.abs(wg - wb)[ok].max() < 1e-9
+    _compare(gwn, P, Q[::7], f"grid{seed}")
+
