@@ -269,8 +269,8 @@ gwn_status gwn_multi_destroy(gwn_multi plan);
  *   "approximately bilinear" test of the ray-patch subdivision, relative to
  *   the control points' bounding-box diagonal (default 1e-9); eps, the
  *   absolute tolerance |K15 - G7| of each accepted quadrature interval
- *   (default 1e-11); max_depth, the deepest interval bisection (default 30,
- *   at most 50).  Synchronises `stream`.  Errors: GWN_E_INVALID for a null
+ *   (default 1e-11); max_depth, the deepest interval bisection (default and
+ *   at most 30).  Synchronises `stream`.  Errors: GWN_E_INVALID for a null
  *   argument, npatch outside [0, 2^24] or a non-finite control point.
  * gwn_patches_query: w (double, nq) per query point (FP32 strided input, as for
  *   meshes): w = chi(x0) + (1 / 4 pi) * sum over boundary curves of the

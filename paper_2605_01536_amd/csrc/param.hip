@@ -71,14 +71,13 @@ __constant__ double c_g7_w[4] = {0.129484966168869693270611432679082, 0.27970539
 constexpr double kInv4Pi = 0.079577471545947667884441881686257;
 constexpr int kMaxLevel = 28;     // sub-patch cells of 2^-28
 constexpr int kRayStack = 3 * kMaxLevel + 4;
-constexpr int kQuadStack = 64;
-// Work bounds that keep every lane finite on degenerate input: a ray grazing a
+// Work bounds that keep every wave finite on degenerate input: a ray grazing a
 // patch meets about 2^level cells per level; past kMaxCells cells the direction
 // counts as ambiguous.  An integrand that is not finite is accepted as it is
-// (w becomes NaN), and past kMaxIntervals intervals on one curve the remaining
+// (w becomes NaN), and past kMaxIntervals intervals for one query the remaining
 // ones are accepted without bisection.
 constexpr int kMaxCells = 1 << 14;
-constexpr int kMaxIntervals = 1 << 15;
+constexpr long long kMaxIntervals = 1 << 18;
 
 struct Frame {
     double e1[3], e2[3], d[3];   // right-handed: e1 x e2 = d
@@ -350,43 +349,6 @@ __device__ inline double area_rate(const double* __restrict__ C, double t, const
     return rz > 0.0 ? num * (l + rz) / (l * rho2) : num / (l * (l - rz));
 }
 
-// adaptive GK15 of area_rate over [0, 1]: depth-first over dyadic intervals
-__device__ double curve_integral(const double* __restrict__ C, const double* p, const Frame& F, double eps,
-                                 int max_depth, int& nint) {
-    unsigned long long stk[kQuadStack];
-    int sp = 0;
-    stk[sp++] = 0ull;
-    double sum = 0.0;
-    int intervals = 0;
-    while (sp > 0) {
-        ++intervals;
-        const unsigned long long code = stk[--sp];
-        const int level = (int)(code >> 58);
-        const unsigned long long idx = code & ((1ull << 58) - 1);
-        const double h = ldexp(1.0, -level);
-        const double a = (double)idx * h;
-        const double c = a + 0.5 * h, hw = 0.5 * h;
-        const double fc = area_rate(C, c, p, F);
-        double K = c_gk_w[7] * fc, G = c_g7_w[3] * fc;
-        for (int i = 0; i < 7; ++i) {
-            const double f = area_rate(C, c - hw * c_gk_x[i], p, F) + area_rate(C, c + hw * c_gk_x[i], p, F);
-            K += c_gk_w[i] * f;
-            if (i & 1) G += c_g7_w[i >> 1] * f;
-        }
-        K *= hw;
-        G *= hw;
-        if (!(fabs(K - G) > eps) || level >= max_depth || sp + 2 > kQuadStack || intervals > kMaxIntervals) {
-            sum += K;
-        } else {
-            const unsigned long long nl = (unsigned long long)(level + 1) << 58;
-            stk[sp++] = nl | (2ull * idx + 1);   // right half, taken after the left
-            stk[sp++] = nl | (2ull * idx);
-        }
-    }
-    nint += intervals;
-    return sum;
-}
-
 // One wave per query: lane l takes patches l, l + 64, ... for the crossings and
 // curves l, l + 64, ... for the boundary term; the partial counts and sums are
 // combined across the wave in a fixed butterfly order.  A direction is ambiguous
@@ -541,23 +503,130 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_cols(
     if constexpr (STATS) atomicAdd(&stats[1], (unsigned long long)ncell);
 }
 
-// boundary term along the direction chosen for each query, and w
+// GK15 of area_rate on the dyadic interval idx of 2^-level of curve C: K15 and G7
+__device__ inline void gk15_interval(const double* __restrict__ C, int level, unsigned long long idx,
+                                     const double* p, const Frame& F, double& K, double& G) {
+    const double h = ldexp(1.0, -level);
+    const double a = (double)idx * h;
+    const double c = a + 0.5 * h, hw = 0.5 * h;
+    const double fc = area_rate(C, c, p, F);
+    K = c_gk_w[7] * fc;
+    G = c_g7_w[3] * fc;
+    for (int i = 0; i < 7; ++i) {
+        const double f = area_rate(C, c - hw * c_gk_x[i], p, F) + area_rate(C, c + hw * c_gk_x[i], p, F);
+        K += c_gk_w[i] * f;
+        if (i & 1) G += c_g7_w[i >> 1] * f;
+    }
+    K *= hw;
+    G *= hw;
+}
+
+// The integral over interval idx of 2^-level of curve C by one lane alone:
+// depth-first bisection with a private stack (for intervals that do not fit
+// the wave's queue)
+__device__ double interval_local(const double* __restrict__ C, int level0, unsigned long long idx0, const double* p,
+                                 const Frame& F, double eps, int max_depth, long long& nint) {
+    unsigned long long stk[2 * 32];
+    int sp = 0;
+    stk[sp++] = ((unsigned long long)level0 << 30) | idx0;
+    double sum = 0.0;
+    while (sp > 0) {
+        const unsigned long long code = stk[--sp];
+        const int level = (int)(code >> 30);
+        const unsigned long long idx = code & ((1ull << 30) - 1);
+        double K, G;
+        gk15_interval(C, level, idx, p, F, K, G);
+        ++nint;
+        if (!(fabs(K - G) > eps) || level >= max_depth || sp + 2 > 2 * 32) {
+            sum += K;
+        } else {
+            const unsigned long long nl = (unsigned long long)(level + 1) << 30;
+            stk[sp++] = nl | (2ull * idx + 1);
+            stk[sp++] = nl | (2ull * idx);
+        }
+    }
+    return sum;
+}
+
+// Boundary term along the direction chosen for each query, and w.  The wave's
+// 64 lanes share one queue of intervals in LDS (curve, level, index): each round
+// the lanes take the 64 newest, accept those with |K15 - G7| <= eps (or at the
+// maximum depth) and push both halves of the others; new curves enter as the
+// queue drains.  Every lane stays busy whatever the curves' difficulty, and the
+// order is fixed (pushes are placed by lane rank), so w is deterministic.  A
+// lane whose halves find no room finishes that interval alone (interval_local).
+constexpr int kQueue = 512;   // intervals per wave
+constexpr int kQueueRefill = 192;   // new curves enter while fewer intervals wait
+
 template <bool STATS, class Pts>
 __global__ __launch_bounds__(64 * kParamWaves) void k_param_bdry(
     const double* __restrict__ curves, long long ncurves, Pts pts, long long nq, double eps, int max_depth,
     const int* __restrict__ chi, const int* __restrict__ dir, double* __restrict__ w,
     unsigned long long* __restrict__ stats) {
-    const long long i = blockIdx.x * (long long)kParamWaves + (threadIdx.x >> 6);
+    __shared__ unsigned long long queue[kParamWaves][kQueue];
+    const int wave = threadIdx.x >> 6;
+    const long long i = blockIdx.x * (long long)kParamWaves + wave;
     if (i >= nq) return;
     const int lane = threadIdx.x & 63;
+    unsigned long long* Qw = queue[wave];
     const int d = dir[i];
     double p[3];
     pts.get(i, p);
     double S = 0.0;
-    int nint = 0;
+    long long nint = 0;
     if (d >= 0) {
         const Frame F = make_frame(d);
-        for (long long c = lane; c < ncurves; c += 64) S += curve_integral(curves + 12 * c, p, F, eps, max_depth, nint);
+        int n = 0;                 // queue length (the same in every lane)
+        long long next = 0;        // next curve to enter
+        long long done = 0;        // intervals taken so far by the wave
+        while (true) {
+            // curves enter while room for a full round of pushes remains
+            while (next < ncurves && n < kQueueRefill) {
+                const int take = (int)min((long long)min(64, kQueueRefill - n), ncurves - next);
+                if (lane < take) Qw[n + lane] = (unsigned long long)(next + lane) << 36;   // level 0, index 0
+                n += take;
+                next += take;
+            }
+            if (n == 0) break;
+            const int take = min(n, 64);
+            n -= take;
+            const unsigned long long code = lane < take ? Qw[n + lane] : 0ull;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            bool split = false;
+            double K = 0.0;
+            const long long cv = (long long)(code >> 36);
+            const int level = (int)((code >> 30) & 63);
+            const unsigned long long idx = code & ((1ull << 30) - 1);
+            if (lane < take) {
+                double G;
+                gk15_interval(curves + 12 * cv, level, idx, p, F, K, G);
+                split = fabs(K - G) > eps && level < max_depth && done < kMaxIntervals;   // NaN: accepted
+                ++nint;
+            }
+            done += take;
+            // halves go where the lane's rank among splitting lanes puts them; past
+            // the queue's room the interval is accepted as it is
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(split);
+            const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            const int room = (kQueue - n) / 2;
+            if (split && rank >= room) {
+                split = false;
+                K = interval_local(curves + 12 * cv, level, idx, p, F, eps, max_depth, nint);
+                --nint;   // the interval itself was counted above
+            }
+            if (lane < take && !split) S += K;
+            if (split) {
+                const unsigned long long nl = ((unsigned long long)cv << 36) | ((unsigned long long)(level + 1) << 30);
+                Qw[n + 2 * rank] = nl | (2ull * idx + 1);
+                Qw[n + 2 * rank + 1] = nl | (2ull * idx);
+            }
+            n += 2 * min(__builtin_popcountll(m), room);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
     S = wave_sum(S);
     if (lane == 0) w[i] = d >= 0 ? (double)chi[i] + S * kInv4Pi : NAN;
@@ -646,7 +715,7 @@ gwn_status gwn_patches_build(const double* cps, int64_t npatch, const gwn_patch_
     *out = nullptr;
     const double tau_rel = opts && opts->tau > 0.0 ? opts->tau : 1e-9;
     const double eps = opts && opts->eps > 0.0 ? opts->eps : 1e-11;
-    const int max_depth = opts && opts->max_depth > 0 ? std::min(opts->max_depth, 50) : 30;
+    const int max_depth = opts && opts->max_depth > 0 ? std::min(opts->max_depth, 30) : 30;
     hipStream_t st = (hipStream_t)stream;
     std::vector<double> P((size_t)npatch * 48);
     if (npatch > 0) {

@@ -147,3 +147,12 @@ def test_grid_ray_reuse_equals_single_rays(gwn, seed):
     assert np.abs(wg - wb)[ok].max() < 1e-9
     _compare(gwn, P, Q[::7], f"grid{seed}")
 
+
+
+def test_many_curves_against_oracle(gwn):
+    # 100 random patches (400 boundary curves) as in the benchmark: the wave's
+    # interval queue refills and runs near its capacity
+    rng = np.random.default_rng(7)
+    P = rng.uniform(0, 1, size=(100, 16, 3))
+    Q = rng.uniform(-0.2, 1.2, size=(400, 3))
+    _compare(gwn, P, Q, "100 patches", cut=1e-3)
