@@ -434,29 +434,30 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_chi(
     if constexpr (STATS) atomicAdd(&stats[1], (unsigned long long)ncell);
 }
 
-// Grid columns (Sec. 4.3.1's ray reuse): one wave per (i, j) column finds every
-// crossing of the column's vertical line (+z) once; each sample's chi is the
-// signed count of the crossings above it.  A column whose line has an
-// ambiguous hit, and a sample within the on-surface margin of a crossing, are
-// left kPending for single rays.
+// Grid columns (Sec. 4.3.1's ray reuse): one workgroup per (i, j) column finds
+// every crossing of the column's vertical line (+z) once, its lanes sharing out
+// the patches; each sample's chi is the signed count of the crossings above it.
+// A column whose line has an ambiguous hit, and a sample within the on-surface
+// margin of a crossing, are left kPending for single rays.
 constexpr int kMaxHits = 256;
 
+constexpr int kColThreads = 256;   // one workgroup per column, a patch per lane
+
 template <bool STATS>
-__global__ __launch_bounds__(64 * kParamWaves) void k_param_cols(
+__global__ __launch_bounds__(kColThreads) void k_param_cols(
     const double* __restrict__ patches, const double* __restrict__ boxes, long long npatch, GridPts g,
     long long ncols, double tau, int* __restrict__ chi_out, int* __restrict__ dir_out,
     unsigned long long* __restrict__ stats) {
-    __shared__ double hz[kParamWaves][kMaxHits];
-    __shared__ int hs[kParamWaves][kMaxHits];
-    __shared__ int hn[kParamWaves];
-    const int wave = threadIdx.x >> 6;
-    const long long col = blockIdx.x * (long long)kParamWaves + wave;
-    if (col >= ncols) return;   // whole waves leave together
-    const int lane = threadIdx.x & 63;
-    if (lane == 0) hn[wave] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __shared__ double hz[kMaxHits];
+    __shared__ int hs[kMaxHits];
+    __shared__ int hn, amb_any;
+    const long long col = blockIdx.x;
+    if (col >= ncols) return;   // the whole workgroup
+    if (threadIdx.x == 0) {
+        hn = 0;
+        amb_any = 0;
+    }
+    __syncthreads();
     const long long ci = col / g.ny, cj = col - ci * g.ny;
     RayState R;
     R.p[0] = cell_coord(g.o[0], g.s[0], ci);
@@ -474,28 +475,27 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_cols(
     R.chi = 0;
     R.amb = false;
     R.line = true;
-    R.hz = hz[wave];
-    R.hs = hs[wave];
-    R.hn = &hn[wave];
+    R.hz = hz;
+    R.hs = hs;
+    R.hn = &hn;
     R.hcap = kMaxHits;
     long long ncell = 0;
-    for (long long pi = lane; pi < npatch && !R.amb; pi += 64)
+    for (long long pi = threadIdx.x; pi < npatch && !R.amb; pi += kColThreads)
         if (ray_box(R, boxes + 8 * pi, boxes + 8 * pi + 3))
             ncell += patch_ray(R, patches + 48 * pi, (int)boxes[8 * pi + 6]);
-    const bool amb = __builtin_amdgcn_ballot_w64(R.amb) != 0ull;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int nh = min(hn[wave], kMaxHits);
+    if (R.amb) amb_any = 1;
+    __syncthreads();
+    const bool amb = amb_any != 0;
+    const int nh = min(hn, kMaxHits);
     const long long base = col * g.nz;
-    for (long long k = lane; k < g.nz; k += 64) {
+    for (long long k = threadIdx.x; k < g.nz; k += kColThreads) {
         const double pz = cell_coord(g.o[2], g.s[2], k);
         int chi = 0;
         bool on = amb;
         for (int h = 0; h < nh && !on; ++h) {
-            const double t = hz[wave][h] - pz;
+            const double t = hz[h] - pz;
             if (fabs(t) <= 1e-12 * (1.0 + fabs(t))) on = true;
-            else if (t > 0.0) chi += hs[wave][h];
+            else if (t > 0.0) chi += hs[h];
         }
         chi_out[base + k] = on ? 0 : chi;
         dir_out[base + k] = on ? kPending : 0;
@@ -653,8 +653,8 @@ template <bool STATS>
 hipError_t launch_param_grid(const gwn_patches_s* h, const GridPts& g, long long nx, double* w, int* chi, int* dir,
                              unsigned long long* stats, hipStream_t st) {
     const long long ncols = nx * g.ny, n = ncols * g.nz;
-    k_param_cols<STATS><<<(unsigned)((ncols + kParamWaves - 1) / kParamWaves), 64 * kParamWaves, 0, st>>>(
-        h->patches, h->boxes, h->npatch, g, ncols, h->tau, chi, dir, stats);
+    k_param_cols<STATS><<<(unsigned)ncols, kColThreads, 0, st>>>(h->patches, h->boxes, h->npatch, g, ncols, h->tau,
+                                                                 chi, dir, stats);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned blocks = (unsigned)((n + kParamWaves - 1) / kParamWaves);
