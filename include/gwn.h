@@ -279,8 +279,9 @@ gwn_status gwn_multi_destroy(gwn_multi plan);
  *   adaptive 15-point Gauss-Kronrod.  chi counts the signed crossings of the
  *   ray p + t x0, t > 0 (+1 where the ray has positive dot product with the
  *   normal).  x0 is the first of +z, (0.36, 0.48, 0.8), (-0.48, 0.6, 0.64),
- *   (0.6, -0.64, 0.48) whose ray has no tangent hit, no hit at the query and
- *   no hit within 1e-9 (in a leaf's parameters) of a subdivision leaf's edge
+ *   (0.6, -0.64, 0.48) whose ray has no tangent hit, no hit at the query, no
+ *   hit within 1e-9 (in a leaf's parameters) of a subdivision leaf's edge and
+ *   no hit or near miss within 4 tau of a leaf edge on a patch's boundary
  *   (Sec. 4.4.1 shoots another ray in such cases); dir_out (nullable) receives
  *   its index, or -1 with w = NaN when all four are ambiguous; chi_out
  *   (nullable) the crossing count along it.  w is independent of the choice

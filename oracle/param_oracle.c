@@ -31,8 +31,10 @@
  * corners (the Hausdorff criterion of Sec. 4.4.1), then the ray meets that
  * bilinear patch: the problem projected along x0 onto a plane is the planar
  * inverse of a bilinear map, a quadratic in v.  A hit that is tangent or lies
- * within a small margin of a leaf's edge makes the query ambiguous for this
- * direction (Sec. 4.4.1 shoots another ray in such cases).
+ * within a small margin of a leaf's edge (at the patch's boundary: within 4 tau,
+ * the chord's distance from the exact curve, counting near misses) makes the
+ * query ambiguous for this direction (Sec. 4.4.1 shoots another ray in such
+ * cases).
  */
 #include <math.h>
 #include <stdint.h>
@@ -252,8 +254,11 @@ static int po_box_hit(const po_ray* R, const double* P)
 
 static inline double po_x2(double ax, double ay, double bx, double by) { return ax * by - ay * bx; }
 
-/* the ray against the bilinear patch through the corners of the leaf P */
-static void po_leaf_hits(po_ray* R, const double* P)
+/* the ray against the bilinear patch through the corners of the leaf P; bedge:
+ * bits 0..3 where the leaf's u = 0, u = 1, v = 0, v = 1 edge is on the patch
+ * boundary, whose margin also covers the chord's distance (up to tau) from the
+ * exact boundary curve */
+static void po_leaf_hits(po_ray* R, const double* P, int bedge)
 {
     const double* c3[4] = {P, P + 3 * 12, P + 3 * 15, P + 3 * 3}; /* (0,0) (1,0) (1,1) (0,1) */
     double q2[4][2];
@@ -295,9 +300,22 @@ static void po_leaf_hits(po_ray* R, const double* P)
         const double den = mx * mx + my * my;
         if (den == 0.0) { R->amb = 1; continue; }
         const double u = ((Hx - v * Fx) * mx + (Hy - v * Fy) * my) / den;
-        const double mg = R->margin;
-        if (u < -mg || u > 1.0 + mg || v < -mg || v > 1.0 + mg) continue;
-        if (u < mg || u > 1.0 - mg || v < mg || v > 1.0 - mg) { R->amb = 1; continue; }
+        double mu0 = R->margin, mu1 = R->margin, mv0 = R->margin, mv1 = R->margin;
+        if (bedge) {
+            double eu[3], ev[3];
+            for (int c = 0; c < 3; ++c) {
+                eu[c] = c3[1][c] - c3[0][c];
+                ev[c] = c3[3][c] - c3[0][c];
+            }
+            const double lu = sqrt(po_dot(eu, eu)), lv = sqrt(po_dot(ev, ev));
+            const double bu = lu > 0.0 ? 4.0 * R->tau / lu : 1.0, bv = lv > 0.0 ? 4.0 * R->tau / lv : 1.0;
+            if ((bedge & 1) && bu > mu0) mu0 = bu;
+            if ((bedge & 2) && bu > mu1) mu1 = bu;
+            if ((bedge & 4) && bv > mv0) mv0 = bv;
+            if ((bedge & 8) && bv > mv1) mv1 = bv;
+        }
+        if (u < -mu0 || u > 1.0 + mu1 || v < -mv0 || v > 1.0 + mv1) continue;
+        if (u < mu0 || u > 1.0 - mu1 || v < mv0 || v > 1.0 - mv1) { R->amb = 1; continue; }
         /* 3D point, ray parameter and normal of the bilinear patch */
         double X[3], Su[3], Sv[3], n[3];
         for (int c = 0; c < 3; ++c) {
@@ -317,16 +335,21 @@ static void po_leaf_hits(po_ray* R, const double* P)
     }
 }
 
-static void po_patch_ray(po_ray* R, const double* P, int depth)
+/* (i, j): the cell of this sub-patch among the 2^depth x 2^depth of its patch */
+static void po_patch_ray(po_ray* R, const double* P, int depth, int64_t i, int64_t j)
 {
     if (!po_box_hit(R, P)) return;
     if (depth >= 30 || po_bilinear_dev(P) <= R->tau) {
-        po_leaf_hits(R, P);
+        const int64_t last = ((int64_t)1 << depth) - 1;
+        po_leaf_hits(R, P, (i == 0 ? 1 : 0) | (i == last ? 2 : 0) | (j == 0 ? 4 : 0) | (j == last ? 8 : 0));
         return;
     }
     double q[4][48];
-    po_split_patch(P, q[0], q[1], q[2], q[3]);
-    for (int k = 0; k < 4; ++k) po_patch_ray(R, q[k], depth + 1);
+    po_split_patch(P, q[0], q[1], q[2], q[3]); /* (u, v) low-low, high-low, low-high, high-high */
+    po_patch_ray(R, q[0], depth + 1, 2 * i, 2 * j);
+    po_patch_ray(R, q[1], depth + 1, 2 * i + 1, 2 * j);
+    po_patch_ray(R, q[2], depth + 1, 2 * i, 2 * j + 1);
+    po_patch_ray(R, q[3], depth + 1, 2 * i + 1, 2 * j + 1);
 }
 
 /* chi along direction d for every query; amb_out[i] = 1 where a hit was tangent,
@@ -354,7 +377,7 @@ void oracle_param_chi(int64_t npatch, const double* P, int64_t nq, const double*
         R.margin = margin;
         R.chi = 0;
         R.amb = 0;
-        for (int64_t k = 0; k < npatch; ++k) po_patch_ray(&R, P + 48 * k, 0);
+        for (int64_t k = 0; k < npatch; ++k) po_patch_ray(&R, P + 48 * k, 0, 0, 0);
         chi_out[i] = R.chi;
         amb_out[i] = (uint8_t)R.amb;
     }

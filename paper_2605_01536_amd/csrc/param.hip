@@ -198,7 +198,11 @@ __device__ inline double net_deviation(const double* S) {
 // at control points 0, 12, 15, 3): two planes through the ray, e1.(x - p) = 0
 // and e2.(x - p) = 0, each bilinear in (u, v); eliminating u gives a quadratic
 // in v
-__device__ inline void bilinear_hits(RayState& R, const double* S) {
+// bedge: bits 0..3 set where the leaf's u = 0, u = 1, v = 0, v = 1 edge lies on
+// the patch's boundary; there the margin also covers the leaf chord's distance
+// from the exact boundary curve (up to tau), so a ray that passes between them
+// is ambiguous rather than counted against the wrong side
+__device__ inline void bilinear_hits(RayState& R, const double* S, int bedge) {
     const double* q[4] = {S, S + 36, S + 45, S + 9};
     double f1[4], f2[4];
     for (int k = 0; k < 4; ++k) {
@@ -243,9 +247,20 @@ __device__ inline void bilinear_hits(RayState& R, const double* S) {
         } else {
             u = -(a2 + c2 * v) / den2;
         }
-        const double mg = R.margin;
-        if (u < -mg || u > 1.0 + mg || v < -mg || v > 1.0 + mg) continue;
-        if (u < mg || u > 1.0 - mg || v < mg || v > 1.0 - mg) {
+        double mu0 = R.margin, mu1 = R.margin, mv0 = R.margin, mv1 = R.margin;
+        if (bedge) {
+            const double lu = sqrt((q[1][0] - q[0][0]) * (q[1][0] - q[0][0]) + (q[1][1] - q[0][1]) * (q[1][1] - q[0][1]) +
+                                   (q[1][2] - q[0][2]) * (q[1][2] - q[0][2]));
+            const double lv = sqrt((q[3][0] - q[0][0]) * (q[3][0] - q[0][0]) + (q[3][1] - q[0][1]) * (q[3][1] - q[0][1]) +
+                                   (q[3][2] - q[0][2]) * (q[3][2] - q[0][2]));
+            const double bu = lu > 0.0 ? 4.0 * R.tau / lu : 1.0, bv = lv > 0.0 ? 4.0 * R.tau / lv : 1.0;
+            if (bedge & 1) mu0 = fmax(mu0, bu);
+            if (bedge & 2) mu1 = fmax(mu1, bu);
+            if (bedge & 4) mv0 = fmax(mv0, bv);
+            if (bedge & 8) mv1 = fmax(mv1, bv);
+        }
+        if (u < -mu0 || u > 1.0 + mu1 || v < -mv0 || v > 1.0 + mv1) continue;
+        if (u < mu0 || u > 1.0 - mu1 || v < mv0 || v > 1.0 - mv1) {
             R.amb = true;
             continue;
         }
@@ -310,7 +325,8 @@ __device__ int patch_ray(RayState& R, const double* __restrict__ P, int flat_lev
         // the net's distance from bilinear falls about 4x per level: cells above
         // flat_level are subdivided without the test (a later leaf is as valid)
         if (level >= kMaxLevel || (level >= flat_level && net_deviation(S) <= R.tau)) {
-            bilinear_hits(R, S);
+            const unsigned last = (1u << level) - 1u;
+            bilinear_hits(R, S, (iu == 0 ? 1 : 0) | (iu == last ? 2 : 0) | (iv == 0 ? 4 : 0) | (iv == last ? 8 : 0));
             continue;
         }
         if (sp + 4 > kRayStack) {   // cannot happen for depth-first with kRayStack >= 3 levels + 4

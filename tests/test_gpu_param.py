@@ -156,3 +156,28 @@ def test_many_curves_against_oracle(gwn):
     P = rng.uniform(0, 1, size=(100, 16, 3))
     Q = rng.uniform(-0.2, 1.2, size=(400, 3))
     _compare(gwn, P, Q, "100 patches", cut=1e-3)
+
+
+def test_rays_grazing_boundary_curves(gwn):
+    # queries straight below and above points of curved boundary curves (and
+    # corners): their +z rays pass within the FP32 rounding of the curve, where
+    # the crossing count and the boundary integrand are both near their jumps;
+    # the GPU and the oracle re-shoot or resolve them alike
+    rng = np.random.default_rng(31)
+    P = rng.uniform(0, 1, size=(3, 16, 3))
+    C = O.bezier_boundary(P)
+    pts = []
+    for c in C[::2]:
+        for t in (0.0, 1.0 / 3.0, 0.5, 0.71):
+            b = np.array([(1 - t) ** 3, 3 * (1 - t) ** 2 * t, 3 * (1 - t) * t * t, t ** 3])
+            X = b @ c
+            pts += [X - [0, 0, 0.4], X + [0, 0, 0.3]]
+    Q = np.array(pts, dtype=np.float32)
+    pt = gwn.Patches(_dev(P))
+    w, chi, dr = pt.query(_q(Q), want_chi=True)
+    w, dr = w.cpu().numpy(), dr.cpu().numpy()
+    wo, co, do = O.parametric(P, Q.astype(np.float64))
+    ok = (dr >= 0) & (do >= 0) & _far(P, Q, 1e-3)
+    assert ok.sum() > 0.5 * len(Q)
+    assert np.isfinite(w[dr >= 0]).all()
+    assert np.abs(w - wo)[ok].max() < 1e-6
