@@ -300,10 +300,12 @@ __device__ inline void bilinear_hits(RayState& R, const double* S, int bedge) {
 
 // one patch: depth-first over sub-patch cells whose control-point box meets the ray
 // (returns the number of cells extracted)
-__device__ int patch_ray(RayState& R, const double* __restrict__ P, int flat_level) {
+// (start: the cell to begin with, level << 58 | iu << 29 | iv; 0 = the whole patch)
+__device__ int patch_ray(RayState& R, const double* __restrict__ P, int flat_level,
+                         unsigned long long start = 0ull) {
     unsigned long long stk[kRayStack];
     int sp = 0;
-    stk[sp++] = 0ull;   // level 0, cell (0, 0)
+    stk[sp++] = start;
     int cells = 0;
     while (sp > 0) {
         if (++cells > kMaxCells) {
@@ -457,7 +459,11 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_chi(
 // margin of a crossing, are left kPending for single rays.
 constexpr int kMaxHits = 256;
 
-constexpr int kColThreads = 256;   // one workgroup per column, a patch per lane
+constexpr int kColThreads = 256;   // one workgroup per column
+constexpr int kCellQueue = 1024;   // sub-patch cells waiting, per workgroup
+// a column whose line meets more cells than this in all patches together takes
+// the single-ray path (the per-patch limit kMaxCells plays this part there)
+constexpr long long kMaxColCells = 1ll << 20;
 
 template <bool STATS>
 __global__ __launch_bounds__(kColThreads) void k_param_cols(
@@ -466,12 +472,16 @@ __global__ __launch_bounds__(kColThreads) void k_param_cols(
     unsigned long long* __restrict__ stats) {
     __shared__ double hz[kMaxHits];
     __shared__ int hs[kMaxHits];
-    __shared__ int hn, amb_any;
+    __shared__ unsigned long long queue[kCellQueue];   // cell codes as patch_ray's
+    __shared__ int qpatch[kCellQueue];
+    __shared__ int hn, amb_any, qn, qpush;
     const long long col = blockIdx.x;
     if (col >= ncols) return;   // the whole workgroup
-    if (threadIdx.x == 0) {
+    const int tid = threadIdx.x;
+    if (tid == 0) {
         hn = 0;
         amb_any = 0;
+        qn = 0;
     }
     __syncthreads();
     const long long ci = col / g.ny, cj = col - ci * g.ny;
@@ -496,15 +506,92 @@ __global__ __launch_bounds__(kColThreads) void k_param_cols(
     R.hn = &hn;
     R.hcap = kMaxHits;
     long long ncell = 0;
-    for (long long pi = threadIdx.x; pi < npatch && !R.amb; pi += kColThreads)
-        if (ray_box(R, boxes + 8 * pi, boxes + 8 * pi + 3))
-            ncell += patch_ray(R, patches + 48 * pi, (int)boxes[8 * pi + 6]);
-    if (R.amb) amb_any = 1;
+    // The whole workgroup works through one queue of cells (patch, level, u
+    // cell, v cell) whose boxes the line may meet: each round every lane takes a
+    // cell, tests its box, intersects it if flat, or queues its four quarters.
+    // Patches whose box the line meets enter while the queue has room for a
+    // full round of them; a cell whose quarters find no room is followed by its
+    // lane alone.  Every cell is visited once in some order, and the crossings
+    // are an integer sum, so the result does not depend on the schedule.
+    long long next = 0, total = 0;
+    while (true) {
+        while (next < npatch && qn <= kCellQueue - kColThreads) {
+            const long long pi = next + tid;
+            const bool in = pi < npatch && ray_box(R, boxes + 8 * pi, boxes + 8 * pi + 3);
+            __syncthreads();   // every lane has read qn
+            if (in) {
+                const int slot = atomicAdd(&qn, 1);   // < kCellQueue by the loop's condition
+                queue[slot] = 0ull;
+                qpatch[slot] = (int)pi;
+            }
+            next += kColThreads;
+            __syncthreads();
+        }
+        const int n = qn;
+        // n == 0 here only once every patch has been offered
+        if (n == 0 || amb_any) break;   // an ambiguous line: its samples take single rays anyway
+        const int take = min(n, kColThreads), base = n - take;
+        total += take;
+        if (total > kMaxColCells) {
+            amb_any = 1;   // every lane writes the same value
+            break;
+        }
+        unsigned long long code = 0ull;
+        int pi = 0;
+        if (tid < take) {
+            code = queue[base + tid];
+            pi = qpatch[base + tid];
+        }
+        __syncthreads();   // the taken slots have been read
+        if (tid == 0) qpush = base;
+        __syncthreads();
+        if (tid < take) {
+            const int level = (int)(code >> 58);
+            const unsigned iu = (unsigned)((code >> 29) & 0x1fffffffu), iv = (unsigned)(code & 0x1fffffffu);
+            const double* P = patches + 48 * (long long)pi;
+            const int flat_level = (int)boxes[8 * (long long)pi + 6];
+            double S[48];
+            extract(P, level, iu, iv, S);
+            ++ncell;
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+            for (int k = 0; k < 16; ++k)
+                for (int c = 0; c < 3; ++c) {
+                    lo[c] = fmin(lo[c], S[3 * k + c]);
+                    hi[c] = fmax(hi[c], S[3 * k + c]);
+                }
+            if (ray_box(R, lo, hi)) {
+                if (level >= kMaxLevel || (level >= flat_level && net_deviation(S) <= R.tau)) {
+                    const unsigned last = (1u << level) - 1u;
+                    bilinear_hits(R, S, (iu == 0 ? 1 : 0) | (iu == last ? 2 : 0) | (iv == 0 ? 4 : 0) |
+                                            (iv == last ? 8 : 0));
+                } else {
+                    const unsigned long long nl = (unsigned long long)(level + 1) << 58;
+                    const int slot = atomicAdd(&qpush, 4);
+                    for (int c = 0; c < 4; ++c) {
+                        const unsigned long long cu = 2ull * iu + (c & 1), cv = 2ull * iv + (c >> 1);
+                        const unsigned long long child = nl | (cu << 29) | cv;
+                        if (slot + 4 <= kCellQueue) {
+                            queue[slot + c] = child;
+                            qpatch[slot + c] = pi;
+                        } else {   // no room: this lane alone
+                            ncell += patch_ray(R, P, flat_level, child);
+                        }
+                    }
+                }
+            }
+            if (R.amb) amb_any = 1;
+        }
+        __syncthreads();
+        // slots are handed out 4 at a time from base: those below the last
+        // multiple of 4 that fits were all written
+        if (tid == 0) qn = min(qpush, base + ((kCellQueue - base) & ~3));
+        __syncthreads();
+    }
     __syncthreads();
     const bool amb = amb_any != 0;
     const int nh = min(hn, kMaxHits);
     const long long base = col * g.nz;
-    for (long long k = threadIdx.x; k < g.nz; k += kColThreads) {
+    for (long long k = tid; k < g.nz; k += kColThreads) {
         const double pz = cell_coord(g.o[2], g.s[2], k);
         int chi = 0;
         bool on = amb;
