@@ -344,29 +344,6 @@ __device__ int patch_ray(RayState& R, const double* __restrict__ P, int flat_lev
     return cells;
 }
 
-// the boundary integrand (without 1 / 4 pi) at t of curve C in frame F
-__device__ inline double area_rate(const double* __restrict__ C, double t, const double* p, const Frame& F) {
-    const double s1 = 1.0 - t;
-    const double b0 = s1 * s1 * s1, b1 = 3.0 * s1 * s1 * t, b2 = 3.0 * s1 * t * t, b3 = t * t * t;
-    const double d0 = -3.0 * s1 * s1, d1 = 3.0 * s1 * (s1 - 2.0 * t), d2 = 3.0 * t * (2.0 * s1 - t), d3 = 3.0 * t * t;
-    double r[3], dr[3];
-    for (int c = 0; c < 3; ++c) {
-        r[c] = b0 * C[c] + b1 * C[3 + c] + b2 * C[6 + c] + b3 * C[9 + c] - p[c];
-        dr[c] = d0 * C[c] + d1 * C[3 + c] + d2 * C[6 + c] + d3 * C[9 + c];
-    }
-    const double rx = r[0] * F.e1[0] + r[1] * F.e1[1] + r[2] * F.e1[2];
-    const double ry = r[0] * F.e2[0] + r[1] * F.e2[1] + r[2] * F.e2[2];
-    const double rz = r[0] * F.d[0] + r[1] * F.d[1] + r[2] * F.d[2];
-    const double dx = dr[0] * F.e1[0] + dr[1] * F.e1[1] + dr[2] * F.e1[2];
-    const double dy = dr[0] * F.e2[0] + dr[1] * F.e2[1] + dr[2] * F.e2[2];
-    const double rho2 = rx * rx + ry * ry;
-    const double l = sqrt(rho2 + rz * rz);
-    // (ry dx - rx dy) / (l s) with s = l - r_z, written for r_z > 0 through
-    // s = rho^2 / (l + r_z) without a second division
-    const double num = ry * dx - rx * dy;
-    return rz > 0.0 ? num * (l + rz) / (l * rho2) : num / (l * (l - rz));
-}
-
 // One wave per query: lane l takes patches l, l + 64, ... for the crossings and
 // curves l, l + 64, ... for the boundary term; the partial counts and sums are
 // combined across the wave in a fixed butterfly order.  A direction is ambiguous
@@ -606,22 +583,63 @@ __global__ __launch_bounds__(kColThreads) void k_param_cols(
     if constexpr (STATS) atomicAdd(&stats[1], (unsigned long long)ncell);
 }
 
-// GK15 of area_rate on the dyadic interval idx of 2^-level of curve C: K15 and G7
+// The boundary integrand (without 1 / 4 pi) at one point of a curve, from the
+// point's coordinates relative to the query in the ray's frame (x, y along e1,
+// e2; z along the ray) and the derivatives dx, dy along the curve's parameter:
+// (y dx - x dy) / (l s), s = l - z, written for z > 0 through s = rho^2 / (l + z)
+// so that neither side cancels; one division either way
+__device__ inline double area_rate_xyz(double x, double y, double z, double dx, double dy) {
+    const double rho2 = x * x + y * y;
+    const double l = sqrt(rho2 + z * z);
+    const double num = y * dx - x * dy;
+    const bool up = z > 0.0;
+    return (up ? num * (l + z) : num) / (l * (up ? rho2 : l - z));
+}
+
+// GK15 of the integrand on the dyadic interval idx of 2^-level of curve C: K15
+// and G7.  The curve is taken relative to the query in the ray's frame and
+// expanded about the interval's centre in the local parameter s in [-1, 1]
+// (t = centre + s h / 2), a cubic a0 + a1 s + a2 s^2 + a3 s^3 per coordinate;
+// the nodes come in pairs +-x, whose points share the even and odd parts.  The
+// integrand is homogeneous of degree 1 in the derivative, so with derivatives
+// along s the rules' weights apply without the factor h / 2.
 __device__ inline void gk15_interval(const double* __restrict__ C, int level, unsigned long long idx,
                                      const double* p, const Frame& F, double& K, double& G) {
     const double h = ldexp(1.0, -level);
-    const double a = (double)idx * h;
-    const double c = a + 0.5 * h, hw = 0.5 * h;
-    const double fc = area_rate(C, c, p, F);
+    const double c = ((double)idx + 0.5) * h, hw = 0.5 * h;
+    double a[3][4];
+    for (int j = 0; j < 3; ++j) {
+        const double* ax = j == 0 ? F.e1 : (j == 1 ? F.e2 : F.d);
+        double q[4];
+        for (int k = 0; k < 4; ++k)
+            q[k] = (C[3 * k] - p[0]) * ax[0] + (C[3 * k + 1] - p[1]) * ax[1] + (C[3 * k + 2] - p[2]) * ax[2];
+        // power basis in t
+        const double b1 = 3.0 * (q[1] - q[0]), b2 = 3.0 * (q[0] - 2.0 * q[1] + q[2]);
+        const double b3 = q[3] - q[0] + 3.0 * (q[1] - q[2]);
+        // Taylor coefficients about c, scaled by powers of hw
+        a[j][0] = q[0] + c * (b1 + c * (b2 + c * b3));
+        a[j][1] = hw * (b1 + c * (2.0 * b2 + 3.0 * c * b3));
+        a[j][2] = hw * hw * (b2 + 3.0 * c * b3);
+        a[j][3] = hw * hw * hw * b3;
+    }
+    const double fc = area_rate_xyz(a[0][0], a[1][0], a[2][0], a[0][1], a[1][1]);
     K = c_gk_w[7] * fc;
     G = c_g7_w[3] * fc;
     for (int i = 0; i < 7; ++i) {
-        const double f = area_rate(C, c - hw * c_gk_x[i], p, F) + area_rate(C, c + hw * c_gk_x[i], p, F);
+        const double x = c_gk_x[i], x2 = x * x;
+        double ev[3], od[3];
+        for (int j = 0; j < 3; ++j) {
+            ev[j] = a[j][0] + a[j][2] * x2;
+            od[j] = x * (a[j][1] + a[j][3] * x2);
+        }
+        // derivative a1 + 2 a2 s + 3 a3 s^2: even part a1 + 3 a3 x^2, odd part 2 a2 x
+        const double dex = a[0][1] + 3.0 * a[0][3] * x2, dox = 2.0 * a[0][2] * x;
+        const double dey = a[1][1] + 3.0 * a[1][3] * x2, doy = 2.0 * a[1][2] * x;
+        const double f = area_rate_xyz(ev[0] - od[0], ev[1] - od[1], ev[2] - od[2], dex - dox, dey - doy) +
+                         area_rate_xyz(ev[0] + od[0], ev[1] + od[1], ev[2] + od[2], dex + dox, dey + doy);
         K += c_gk_w[i] * f;
         if (i & 1) G += c_g7_w[i >> 1] * f;
     }
-    K *= hw;
-    G *= hw;
 }
 
 // The integral over interval idx of 2^-level of curve C by one lane alone:
