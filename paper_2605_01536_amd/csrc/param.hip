@@ -387,7 +387,26 @@ struct GridPts {
 constexpr int kPending = -2;   // direction not decided yet (a grid column that needs single rays)
 
 // crossings: chi and the chosen direction per query (-1: all ambiguous).
-// PENDING: only the queries whose direction is kPending.
+// PENDING: only the queries whose direction is kPending.  The wave's lanes share
+// one LDS queue of sub-patch cells (patch, level, u cell, v cell): each round
+// they take up to 64, test their boxes and intersect them or queue their
+// quarters (placed by lane rank); patches enter while a round of them fits, and
+// a lane whose quarters find no room follows them alone.
+constexpr int kWaveCells = 256;   // sub-patch cells waiting, per wave
+// a ray (or a column's line) that meets more cells than this in all patches
+// together is taken as ambiguous, as one meeting kMaxCells in one patch is
+constexpr long long kMaxQueueCells = 1ll << 20;
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int lane_rank(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
 template <bool STATS, bool PENDING, class Pts>
 __global__ __launch_bounds__(64 * kParamWaves) void k_param_chi(
     const double* __restrict__ patches, const double* __restrict__ boxes, long long npatch, Pts pts, long long nq,
@@ -396,6 +415,10 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_chi(
     if (i >= nq) return;   // whole waves leave together
     if (PENDING && dir_out[i] != kPending) return;
     const int lane = threadIdx.x & 63;
+    __shared__ unsigned long long wq[kParamWaves][kWaveCells];   // cell codes as patch_ray's
+    __shared__ int wp[kParamWaves][kWaveCells];
+    unsigned long long* Q = wq[threadIdx.x >> 6];
+    int* QP = wp[threadIdx.x >> 6];
     RayState R;
     pts.get(i, R.p);
     R.tau = tau;
@@ -412,9 +435,82 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_chi(
         }
         R.chi = 0;
         R.amb = false;
-        for (long long pi = lane; pi < npatch && !R.amb; pi += 64)
-            if (ray_box(R, boxes + 8 * pi, boxes + 8 * pi + 3))
-                ncell += patch_ray(R, patches + 48 * pi, (int)boxes[8 * pi + 6]);
+        int n = 0;   // queue length (the same in every lane)
+        long long next = 0, total = 0;
+        while (true) {
+            while (next < npatch && n <= kWaveCells - 64) {
+                const long long pi = next + lane;
+                const bool in = pi < npatch && ray_box(R, boxes + 8 * pi, boxes + 8 * pi + 3);
+                const unsigned long long m = __builtin_amdgcn_ballot_w64(in);
+                if (in) {
+                    const int slot = n + lane_rank(m);
+                    Q[slot] = 0ull;
+                    QP[slot] = (int)pi;
+                }
+                n += __builtin_popcountll(m);
+                next += 64;
+            }
+            wave_lds_sync();
+            if (n == 0) break;   // every patch offered and every cell done
+            const int take = min(n, 64);
+            n -= take;
+            total += take;
+            if (total > kMaxQueueCells) {
+                R.amb = true;
+                break;
+            }
+            unsigned long long code = 0ull;
+            int pi = 0;
+            if (lane < take) {
+                code = Q[n + lane];
+                pi = QP[n + lane];
+            }
+            wave_lds_sync();
+            bool split = false;
+            const int level = (int)(code >> 58);
+            const unsigned iu = (unsigned)((code >> 29) & 0x1fffffffu), iv = (unsigned)(code & 0x1fffffffu);
+            const double* P = patches + 48 * (long long)pi;
+            const int flat_level = (int)boxes[8 * (long long)pi + 6];
+            if (lane < take) {
+                double S[48];
+                extract(P, level, iu, iv, S);
+                ++ncell;
+                double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+                for (int k2 = 0; k2 < 16; ++k2)
+                    for (int c = 0; c < 3; ++c) {
+                        lo[c] = fmin(lo[c], S[3 * k2 + c]);
+                        hi[c] = fmax(hi[c], S[3 * k2 + c]);
+                    }
+                if (ray_box(R, lo, hi)) {
+                    if (level >= kMaxLevel || (level >= flat_level && net_deviation(S) <= R.tau)) {
+                        const unsigned last = (1u << level) - 1u;
+                        bilinear_hits(R, S, (iu == 0 ? 1 : 0) | (iu == last ? 2 : 0) | (iv == 0 ? 4 : 0) |
+                                                (iv == last ? 8 : 0));
+                    } else {
+                        split = true;
+                    }
+                }
+            }
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(split);
+            const int room = (kWaveCells - n) / 4;
+            if (split) {
+                const int rank = lane_rank(m);
+                const unsigned long long nl = (unsigned long long)(level + 1) << 58;
+                for (int c = 0; c < 4; ++c) {
+                    const unsigned long long cu = 2ull * iu + (c & 1), cv = 2ull * iv + (c >> 1);
+                    const unsigned long long child = nl | (cu << 29) | cv;
+                    if (rank < room) {
+                        Q[n + 4 * rank + c] = child;
+                        QP[n + 4 * rank + c] = pi;
+                    } else {   // no room: this lane alone
+                        ncell += patch_ray(R, P, flat_level, child);
+                    }
+                }
+            }
+            n += 4 * min(__builtin_popcountll(m), room);
+            wave_lds_sync();
+            if (__builtin_amdgcn_ballot_w64(R.amb) != 0ull) break;
+        }
         if (__builtin_amdgcn_ballot_w64(R.amb) == 0ull) {
             dir = k;
             int c = R.chi;
@@ -438,9 +534,6 @@ constexpr int kMaxHits = 256;
 
 constexpr int kColThreads = 256;   // one workgroup per column
 constexpr int kCellQueue = 1024;   // sub-patch cells waiting, per workgroup
-// a column whose line meets more cells than this in all patches together takes
-// the single-ray path (the per-patch limit kMaxCells plays this part there)
-constexpr long long kMaxColCells = 1ll << 20;
 
 template <bool STATS>
 __global__ __launch_bounds__(kColThreads) void k_param_cols(
@@ -509,7 +602,7 @@ __global__ __launch_bounds__(kColThreads) void k_param_cols(
         if (n == 0 || amb_any) break;   // an ambiguous line: its samples take single rays anyway
         const int take = min(n, kColThreads), base = n - take;
         total += take;
-        if (total > kMaxColCells) {
+        if (total > kMaxQueueCells) {
             amb_any = 1;   // every lane writes the same value
             break;
         }
