@@ -181,3 +181,38 @@ def test_rays_grazing_boundary_curves(gwn):
     assert ok.sum() > 0.5 * len(Q)
     assert np.isfinite(w[dr >= 0]).all()
     assert np.abs(w - wo)[ok].max() < 1e-6
+
+
+def _stacked_bumps(n, rng):
+    # n copies of one curved patch (a bump over [-1, 1]^2) stacked 0.01 apart
+    # in z with small shifts in x and y: a vertical line meets all of them, so
+    # more cells wait than the shared queues hold and lanes follow the rest alone
+    B = flat_bezier_patch(-1, 1, -1, 1).reshape(4, 4, 3).copy()
+    B[1:3, 1:3, 2] += 0.3
+    P = np.stack([B.reshape(16, 3) + [rng.uniform(-0.05, 0.05), rng.uniform(-0.05, 0.05), 0.01 * k]
+                  for k in range(n)])
+    return P
+
+
+def test_stacked_patches_overflow_the_cell_queues(gwn):
+    rng = np.random.default_rng(41)
+    P = _stacked_bumps(256, rng)
+    Q = np.concatenate([rng.uniform([-0.6, -0.6, -0.5], [0.6, 0.6, 3.5], size=(60, 3)),
+                        rng.uniform([-0.6, -0.6, 0.0], [0.6, 0.6, 0.3], size=(20, 3))])
+    w, chi, dr = _compare(gwn, P, Q, "stacked", cut=1e-3)
+    # the grid path (a workgroup per column) against single rays at the same points
+    pt = gwn.Patches(_dev(P))
+    dims = (6, 5, 40)
+    origin, spacing = (-0.55, -0.5, -0.4), (0.2, 0.2, 0.1)
+    wg, cg, dg = pt.query_grid(origin, spacing, dims, want_chi=True)
+    ii, jj, kk = np.meshgrid(*[np.arange(m) for m in dims], indexing="ij")
+    G = np.stack([(np.float64(origin[c]) + ([ii, jj, kk][c].ravel() + 0.5) * spacing[c]) for c in range(3)],
+                 axis=1).astype(np.float32)
+    wb, cb, db = pt.query(_q(G), want_chi=True)
+    wg, cg, dg = wg.cpu().numpy(), cg.cpu().numpy(), dg.cpu().numpy()
+    wb, cb, db = wb.cpu().numpy(), cb.cpu().numpy(), db.cpu().numpy()
+    same = (dg == db) & (dg >= 0)
+    assert same.mean() > 0.5
+    assert np.array_equal(cg[same], cb[same])
+    ok = np.isfinite(wg) & np.isfinite(wb)
+    assert np.abs(wg - wb)[ok].max() < 1e-9
