@@ -343,17 +343,6 @@ __device__ __forceinline__ void s_blocks(const T* rz, T rho2, T* sv) {
     }
 }
 
-// the same per block, as ZB uniform branches (each block's s stays in place)
-template <class T, int ZB>
-__device__ __forceinline__ void s_prefix_blocks(int R, const T* rz, T rho2, T* sv) {
-    const bool ord = R <= ZB;
-#pragma unroll
-    for (int r = 0; r < ZB; ++r) {
-        if (ord && r < R - 1) sv[r] = rho2 * Arith<T>::rcp(sv[r]);
-        else if (r < R) sv[r] = rz[r] > (T)0 ? rho2 * Arith<T>::rcp(sv[r]) : sv[r];
-    }
-}
-
 template <class T, int ZB>
 __device__ __forceinline__ void s_prefix(int R, const T* rz, T rho2, T* sv) {
     switch (R) {
