@@ -316,11 +316,17 @@ gwn_status gwn_patches_query(gwn_patches h, const float* qx, const float* qy, co
  * is intersected with the patches once and every sample counts the crossings
  * above it (ray reuse, Sec. 4.3.1); a column with an ambiguous hit, and a
  * sample within the on-surface margin of a crossing, take single rays as in
- * gwn_patches_query.  Results equal gwn_patches_query's at the same points.
+ * gwn_patches_query.  Crossing counts and directions equal
+ * gwn_patches_query's at the same points; w agrees to the last bits of FP64
+ * (the two paths' kernels contract their products differently).
  * counts (nullable HOST array of 2): when given, the work is also counted as
- * for gwn_patches_query_stats and the call synchronises `stream`.  Errors:
- * GWN_E_INVALID for null arguments, negative sizes, or more than 2^30 points
- * or columns. */
+ * for gwn_patches_query_stats and the call synchronises `stream`.  Without
+ * counts the boundary term along the first direction runs on a stream the
+ * handle creates at its first grid call (released by gwn_patches_destroy),
+ * forked from and joined back into `stream` by events, beside the column
+ * kernel; calls on one handle from several host threads take turns enqueuing.
+ * Errors: GWN_E_INVALID for null arguments, negative sizes, or more than 2^30
+ * points or columns. */
 gwn_status gwn_patches_query_grid(gwn_patches h, const double* origin, const double* spacing, const int64_t* dims,
                                   double* w_out, int32_t* chi_out, int32_t* dir_out, int64_t* counts,
                                   void* stream);

@@ -31,6 +31,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -45,6 +46,12 @@ struct gwn_patches_s {
     double* boxes = nullptr;     // npatch * 8: lo xyz, hi xyz of the control points, the first
                                  // subdivision level worth testing for flatness, unused
     double* curves = nullptr;    // ncurves * 12
+    // grid calls run the boundary term along the first direction on a stream
+    // of their own, beside the column kernel; the mutex keeps each call's
+    // fork and join of the two streams together
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    std::mutex grid_mu;
 };
 
 namespace gwn {
@@ -783,7 +790,11 @@ __device__ double interval_local(const double* __restrict__ C, int level0, unsig
 constexpr int kQueue = 512;   // intervals per wave
 constexpr int kQueueRefill = 192;   // new curves enter while fewer intervals wait
 
-template <bool STATS, class Pts>
+// MODE 0: the direction in dir[i], w = chi + S / 4 pi (NaN without a
+// direction); MODE 1: the first direction for every query, w = S / 4 pi;
+// MODE 2: after MODE 1, queries with dir[i] == 0 add chi, the others are
+// computed as in MODE 0.
+template <bool STATS, class Pts, int MODE = 0>
 __global__ __launch_bounds__(64 * kParamWaves) void k_param_bdry(
     const double* __restrict__ curves, long long ncurves, Pts pts, long long nq, double eps, int max_depth,
     const int* __restrict__ chi, const int* __restrict__ dir, double* __restrict__ w,
@@ -794,7 +805,11 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_bdry(
     if (i >= nq) return;
     const int lane = threadIdx.x & 63;
     unsigned long long* Qw = queue[wave];
-    const int d = dir[i];
+    const int d = MODE == 1 ? 0 : dir[i];
+    if (MODE == 2 && d == 0) {
+        if (lane == 0) w[i] = (double)chi[i] + w[i];
+        return;   // the whole wave
+    }
     double p[3];
     pts.get(i, p);
     double S = 0.0;
@@ -854,7 +869,9 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_bdry(
         }
     }
     S = wave_sum(S);
-    if (lane == 0) w[i] = d >= 0 ? (double)chi[i] + S * kInv4Pi : NAN;
+    // the product rounded on its own in every mode, as MODE 1 + 2 split it
+    const double b = __dmul_rn(S, kInv4Pi);
+    if (lane == 0) w[i] = MODE == 1 ? b : (d >= 0 ? (double)chi[i] + b : NAN);
     if constexpr (STATS) atomicAdd(&stats[0], (unsigned long long)nint);
 }
 
@@ -875,20 +892,58 @@ hipError_t launch_param(const gwn_patches_s* h, const float* qx, const float* qy
 
 // a grid: columns once, single rays for what they leave pending, then the boundary term
 template <bool STATS>
-hipError_t launch_param_grid(const gwn_patches_s* h, const GridPts& g, long long nx, double* w, int* chi, int* dir,
+// Without STATS the boundary term along the first direction runs on the
+// handle's side stream while the columns are intersected (most queries take
+// that direction); the rest is fixed up after both.  With STATS the kernels run
+// in sequence, so each interval is counted once.
+hipError_t launch_param_grid(gwn_patches_s* h, const GridPts& g, long long nx, double* w, int* chi, int* dir,
                              unsigned long long* stats, hipStream_t st) {
     const long long ncols = nx * g.ny, n = ncols * g.nz;
+    const unsigned blocks = (unsigned)((n + kParamWaves - 1) / kParamWaves);
+    std::unique_lock<std::mutex> lock(h->grid_mu, std::defer_lock);
+    hipError_t e = hipSuccess;
+    if constexpr (!STATS) {
+        lock.lock();
+        if (!h->side) {
+            e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join, hipEventDisableTiming);
+            if (e != hipSuccess) {   // leave none of the three half made
+                if (h->side) (void)hipStreamDestroy(h->side);
+                if (h->fork) (void)hipEventDestroy(h->fork);
+                h->side = nullptr;
+                h->fork = nullptr;
+                return e;
+            }
+        }
+        e = hipEventRecord(h->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->fork, 0);
+        if (e != hipSuccess) return e;
+    }
     k_param_cols<STATS><<<(unsigned)ncols, kColThreads, 0, st>>>(h->patches, h->boxes, h->npatch, g, ncols, h->tau,
                                                                  chi, dir, stats);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned blocks = (unsigned)((n + kParamWaves - 1) / kParamWaves);
+    if constexpr (!STATS) {
+        k_param_bdry<false, GridPts, 1><<<blocks, 64 * kParamWaves, 0, h->side>>>(
+            h->curves, h->ncurves, g, n, h->eps, h->max_depth, chi, dir, w, nullptr);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(h->join, h->side);
+        if (e != hipSuccess) return e;
+    }
     k_param_chi<STATS, true><<<blocks, 64 * kParamWaves, 0, st>>>(h->patches, h->boxes, h->npatch, g, n, h->tau, chi,
                                                                   dir, stats);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_param_bdry<STATS><<<blocks, 64 * kParamWaves, 0, st>>>(h->curves, h->ncurves, g, n, h->eps, h->max_depth, chi,
-                                                             dir, w, stats);
+    if constexpr (STATS) {
+        k_param_bdry<true><<<blocks, 64 * kParamWaves, 0, st>>>(h->curves, h->ncurves, g, n, h->eps, h->max_depth,
+                                                                chi, dir, w, stats);
+    } else {
+        e = hipStreamWaitEvent(st, h->join, 0);
+        if (e != hipSuccess) return e;
+        k_param_bdry<false, GridPts, 2><<<blocks, 64 * kParamWaves, 0, st>>>(
+            h->curves, h->ncurves, g, n, h->eps, h->max_depth, chi, dir, w, nullptr);
+    }
     return hipGetLastError();
 }
 
@@ -1190,6 +1245,12 @@ gwn_status gwn_patches_destroy(gwn_patches h) {
     (void)hipFree(h->patches);
     (void)hipFree(h->boxes);
     (void)hipFree(h->curves);
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+        (void)hipEventDestroy(h->fork);
+        (void)hipEventDestroy(h->join);
+    }
     delete h;
     return GWN_OK;
 }
