@@ -216,3 +216,27 @@ def test_stacked_patches_overflow_the_cell_queues(gwn):
     assert np.array_equal(cg[same], cb[same])
     ok = np.isfinite(wg) & np.isfinite(wb)
     assert np.abs(wg - wb)[ok].max() < 1e-9
+
+
+def test_grid_calls_on_several_streams(gwn):
+    # a grid call forks its boundary term onto the handle's side stream and
+    # joins it back: calls on different streams, back to back without waiting
+    # in between, each give what one call alone gives
+    rng = np.random.default_rng(61)
+    P = rng.uniform(0, 1, size=(8, 16, 3))
+    pt = gwn.Patches(_dev(P))
+    dims = (7, 6, 50)
+    origin, spacing = (-0.2, -0.2, -0.2), (0.2, 0.24, 0.028)
+    ref = pt.query_grid(origin, spacing, dims)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    n = int(np.prod(dims))
+    outs = [torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(4)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.current_stream(), torch.cuda.Stream()]
+    for o, s in zip(outs, streams):
+        pt.query_grid(origin, spacing, dims, out=o, stream=s)
+    torch.cuda.synchronize()
+    for o in outs:
+        assert np.array_equal(o.cpu().numpy(), ref, equal_nan=True)
+    pt.close()
