@@ -100,8 +100,8 @@ I_MIN_GRID_FP64 = (16 + 2 + 21 / 2) * FP64_OP_SLOTS + 2.5 * FP64_TRANS_SLOTS + 2
 # Parametric path (FP64), per unit of work the kernel reports, counted from its
 # arithmetic (a division = one reciprocal at the transcendental cost plus 4 ops):
 # one integrand evaluation from frame coordinates: rho^2, l^2, the numerator,
-# the two-sided s and its selects, and two Newton steps on each of the hardware
-# estimates of 1 / l and of the other reciprocal, 24 ops and 2 estimates; a
+# the two-sided s and its selects, and one Newton step on each of the hardware
+# estimates of 1 / l and of the other reciprocal, 19 ops and 2 estimates; a
 # quadrature interval: the control points relative to the query projected onto
 # the ray's frame (48), their power basis and Taylor coefficients about the
 # interval's centre (66), the 7 node pairs' even and odd parts and their sums
@@ -109,7 +109,7 @@ I_MIN_GRID_FP64 = (16 + 2 + 21 / 2) * FP64_OP_SLOTS + 2.5 * FP64_TRANS_SLOTS + 2
 # interval extractions (24 ops and 1 division each), the control points' box
 # (96), the slab test (24, 3 divisions) and the control net's distance to the
 # bilinear patch (528, 1 square root).
-PARAM_EVAL_SLOTS = 24 * FP64_OP_SLOTS + 2 * FP64_TRANS_SLOTS
+PARAM_EVAL_SLOTS = 19 * FP64_OP_SLOTS + 2 * FP64_TRANS_SLOTS
 PARAM_INTERVAL_SLOTS = 15 * PARAM_EVAL_SLOTS + (48 + 66 + 196 + 30) * FP64_OP_SLOTS
 PARAM_CELL_SLOTS = (24 * 24 + 96 + 24 + 528 + 27 * 4) * FP64_OP_SLOTS + 28 * FP64_TRANS_SLOTS
 # Per sample and boundary vertex the two-sided form of s (rcp, rho^2*rcp, the sign

@@ -688,21 +688,21 @@ __global__ __launch_bounds__(kColThreads) void k_param_cols(
 // e2; z along the ray) and the derivatives dx, dy along the curve's parameter:
 // (y dx - x dy) / (l s), s = l - z, written for z > 0 through s = rho^2 / (l + z)
 // so that neither side cancels.  1 / l and the other reciprocal come from the
-// hardware estimates refined by two Newton steps each (quadratic convergence,
-// to the last bits of FP64); a zero length or denominator gives a non-finite
-// value as a division would.
+// hardware estimates refined by one Newton step each (the step squares the
+// estimate's relative error); against correctly rounded operations the
+// quadrature's intervals and results move only in the last digits, far below
+// its tolerance.  A zero length or denominator gives a non-finite value as a
+// division would.
 __device__ inline double area_rate_xyz(double x, double y, double z, double dx, double dy) {
     const double rho2 = x * x + y * y;
     const double l2 = rho2 + z * z, hl2 = 0.5 * l2;
     double ri = __builtin_amdgcn_rsq(l2);
-    ri = ri * (1.5 - hl2 * (ri * ri));
     ri = ri * (1.5 - hl2 * (ri * ri));
     const double l = l2 * ri;
     const double num = y * dx - x * dy;
     const bool up = z > 0.0;
     const double den = up ? rho2 : l - z;
     double qi = __builtin_amdgcn_rcp(den);
-    qi = qi * (2.0 - den * qi);
     qi = qi * (2.0 - den * qi);
     return (up ? num * (l + z) : num) * ri * qi;
 }
