@@ -351,11 +351,12 @@ __device__ int patch_ray(RayState& R, const double* __restrict__ P, int flat_lev
     return cells;
 }
 
-// One wave per query: lane l takes patches l, l + 64, ... for the crossings and
-// curves l, l + 64, ... for the boundary term; the partial counts and sums are
-// combined across the wave in a fixed butterfly order.  A direction is ambiguous
-// for the query if it is for any lane.  STATS: also add the wave's quadrature
-// intervals and sub-patch cells to stats[0], stats[1].
+// One wave per query: its lanes share the sub-patch cells of the crossings and
+// the quadrature intervals of the boundary term through queues in LDS; the
+// partial counts and sums are combined across the wave in a fixed butterfly
+// order.  A direction is ambiguous for the query if it is for any lane.  STATS:
+// also add the wave's quadrature intervals and sub-patch cells to stats[0],
+// stats[1].
 constexpr int kParamWaves = 4;   // waves (queries) per workgroup
 
 __device__ inline double wave_sum(double x) {
