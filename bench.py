@@ -6,7 +6,7 @@ spheres and ellipsoids in [-1,1]^3, queried on the 512^3 cell-centred grid
 (134,217,728 points) through gwn_query_grid, FP32 geometry with exact
 predicates and FP64 accumulation.  One step = one full grid evaluation (ray
 reuse + boundary term + combine).  The mesh build is precomputation and is not
-timed (Sec. 6.1 excludes it); its time is reported separately.
+timed (Sec. 5.1 excludes it); its time is reported separately.
 
 Prints ONE JSON line (see the keys below).  `roofline` prices the dominant
 kernel (the fused grid kernel) against the VALU issue ceiling; `cpu_baseline`
@@ -28,12 +28,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GWN queries/sec on 1M-tri open soup at max|err|≤1e-4 vs FP64; % roofline"
 
-# VALU issue ceiling of MI355X: FP32 add/mul/fma (and compares, selects,
-# 32-bit integer ops) issue at 32 lanes per clock per SIMD, i.e. one wave64
-# instruction per 2 clocks (measured on the box; this is the rate behind the
-# 157.3 TFLOP/s FP32 vector figure, which counts an FMA as 2 FLOPs):
-# 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 7.86e13 FP32 VALU slots/s.
-# sqrt and rcp were measured at 3.0 slots each (csrc/probe/valu_probe.hip).
+# VALU issue ceiling of MI355X, from the published FP32 vector peak of
+# 157.3 TFLOP/s (an FMA counted as 2 FLOPs): 7.86e13 FP32 VALU instruction slots
+# per second, i.e. 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz.  FP32 add/mul/fma,
+# compares, selects and 32-bit integer ops take one slot each; sqrt and rcp were
+# measured on the box at 3.0 slots each (profiles/valu_issue_rates_gfx950.md).
 N_CU, SIMD_PER_CU, LANES_PER_CLK, CLOCK_HZ = 256, 4, 32, 2.4e9
 PEAK_SLOTS = N_CU * SIMD_PER_CU * LANES_PER_CLK * CLOCK_HZ
 TRANS_SLOTS = 3
@@ -55,7 +54,7 @@ I_MIN_EDGE = 6 + 14 + 3 * TRANS_SLOTS      # = 29
 # The all-FP64 grid path against the same issue ceiling, with FP64 add/mul/fma
 # and compares at 1.5 FP32 slots and v_rcp_f64 / v_rsq_f64 at 5.4 (measured by
 # the same probe).  The hardware reciprocal and reciprocal square root are only
-# ~26-bit approximations (csrc/probe/fp64_sqrt_probe.hip), so the refinement a
+# ~26-bit approximations (measured on the box: 2.4e8 ulp), so the refinement a
 # double result needs is part of the minimum:
 #   per sample and vertex: r_z, l^2 (2); sqrt = rsq + 7; l+|r_z| (1); rcp = rcp + 4;
 #                          rho^2*rcp (1); compare (1)          = 16 FP64 + 2 trans + select (2)

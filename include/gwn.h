@@ -93,7 +93,7 @@ typedef struct {
 
 /*
  * gwn_build_mesh -- ingest a soup, quantise it, extract and chain the boundary,
- * and build the BVH, all on the device (precomputation; Sec. 6.1 excludes it
+ * and build the BVH, all on the device (precomputation; Sec. 5.1 excludes it
  * from query timings).
  *
  *   vx, vy, vz, vstride, nv : vertex coordinates (float32), strided as above.
@@ -113,12 +113,12 @@ typedef struct {
 gwn_status gwn_build_mesh(const float* vx, const float* vy, const float* vz, int64_t vstride, int64_t nv,
                           const int32_t* tri, int64_t nf, void* stream, gwn_mesh* out);
 
-/* Host-side copy of the mesh's sizes and fixed-point parameters. */
 /* gwn_build_mesh with options (opts may be NULL: the defaults of gwn_build_mesh). */
 gwn_status gwn_build_mesh_opts(const float* vx, const float* vy, const float* vz, int64_t vstride, int64_t nv,
                                const int32_t* tri, int64_t nf, const gwn_build_opts* opts, void* stream,
                                gwn_mesh* out);
 
+/* Host-side copy of the mesh's sizes and fixed-point parameters. */
 gwn_status gwn_mesh_info_get(gwn_mesh m, gwn_mesh_info* out);
 
 /* Release the handle and its device memory (NULL is a no-op). */

@@ -5,7 +5,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 (no shared sources, headers or constants) and implements, in plain FP64 C:
 
 * ``direct``     -- Eq. 2 with the per-triangle signed solid angle of Eq. 6,
-                    accumulated in double-double (ground truth, Sec. 6.2).
+                    accumulated in double-double (ground truth, Sec. 5.2).
 * ``antipodal``  -- Eq. 10 / Alg. 1 with x0 = +z and exact quantised
                     predicates with symbolic perturbation (Supp. Sec. 2.1).
 * ``chi``        -- signed crossings of the +z and -z rays (Sec. 3.2).

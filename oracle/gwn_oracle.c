@@ -12,7 +12,7 @@
  *       per-triangle signed solid angle by the Van Oosterom-Strackee
  *       formula [Eq. 6] written for unnormalised vectors (both atan2
  *       arguments scaled by |a||b||c| > 0), accumulated in double-double
- *       (the paper's accuracy study, Sec. 6.2, uses a double-double
+ *       (the paper's accuracy study, Sec. 5.2, uses a double-double
  *       accumulator for its ground truth).
  *
  *   O2  oracle_antipodal   w(p) = chi(x0) + (1/4pi) sum_{(a,b) in dM} Area(a^, b^, x1)

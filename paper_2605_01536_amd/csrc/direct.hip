@@ -1,6 +1,6 @@
 // direct.hip -- the direct sum of per-triangle signed solid angles (Eq. 2, with
 // the triangle's area by Eq. 6 scaled by |a||b||c| > 0).  O(F) per query: the
-// baseline the antipodal method is measured against (Sec. 6.1 compares with a
+// baseline the antipodal method is measured against (Sec. 5.1 compares with a
 // GPU parallelisation of this sum), and an independent GPU cross-check of w.
 //
 // One lane per query; each 256-lane block walks one slice of the triangles in

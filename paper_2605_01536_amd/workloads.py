@@ -6,7 +6,7 @@ It holds none of the winding-number arithmetic, so both the CPU oracle and
 the GPU path can consume its output without sharing any of the method.
 
 The shapes follow the paper's workload style (open, self-intersecting and
-non-manifold soups, grid and random queries; Sec. 6.1 measures on open
+non-manifold soups, grid and random queries; Sec. 5.1 measures on open
 meshes with queries in the bounding box), scaled to the five sizes used by
 the tests and the benchmark:
 
