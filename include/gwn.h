@@ -340,36 +340,36 @@ gwn_status gwn_patches_destroy(gwn_patches h);
 
 /*
  * Learned surrogate (a Fourier-feature MLP standing in for far-field queries;
- * not part of the paper's method, whose nearest item is its future-work remark
- * on approximating the fractional part).
+ * not part of the paper's method, whose nearest item is its closing remark on
+ * approximating the fractional part of w quickly, Sec. 6).
  *
  * Network: gamma(p) = [sin 2piGp, cos 2piGp] with G (32x3) ~ N(0, sigma^2)
  * fixed at creation; four GELU layers 64->128->128->128->128; linear output
  * 128->1.  Matrix products use bf16 MFMA with fp32 accumulation; Adam updates
  * fp32 master weights.  Parameters form one flat vector of GWN_MLP_NPARAMS
  * floats: W1 (64x128, row-major [in][out]), b1, W2, b2, W3, b3, W4, b4, W5
- * (128), b5.  Loss: mean squared error.
+ * (128), b5.  Loss: mean squared error.  A handle (gwn_mlp, also called
+ * gwn_surrogate) is bound to the device current at its creation.
  *
+ *   gwn_mlp_create: a new network; G and the weights are drawn from `seed`
+ *     (splitmix64 stream; Box-Muller normals for G, uniform +-sqrt(6/fan_in)
+ *     weights, zero biases).
  *   gwn_mlp_get_state / gwn_mlp_set_state copy the state between the device and
  *     HOST arrays (each nullable: theta and the Adam moments m, v of
  *     GWN_MLP_NPARAMS floats, G of 96 floats, the step counter; step < 0 keeps
- *     it).  They synchronise the device.  Used for checkpoints.
+ *     it).  They synchronise the device.
  *   gwn_mlp_forward: y_out[i] = network(q_i) for n device points.
  *   gwn_mlp_loss_grad: gradient of the loss over the n points with targets
  *     `target` into grad_out (device, nullable) and the loss (host, nullable).
  *   gwn_mlp_train_step: the same, then one Adam step (lr; beta1 0.9, beta2
- *     0.999, eps 1e-8, bias-corrected).
- *   gwn_surrogate_query: w_out = network prediction, except for points with
- *     |prediction - 1/2| < band, which are re-evaluated by the exact FP32 path
- *     (gwn_query_batch) on `mesh`; fallback_out (device, nullable) flags them
- *     and *nfallback_out (host, nullable) counts them.  The call synchronises
- *     the stream once, to size the exact evaluation by that count.
+ *     0.999, eps 1e-8, bias-corrected by the handle's step count).
  * The training scratch is owned by the handle and sized to the largest batch;
  * n must be < 2^31.
  */
 #define GWN_MLP_NPARAMS 57985
 
 typedef struct gwn_mlp_s* gwn_mlp;
+typedef gwn_mlp gwn_surrogate;
 
 gwn_status gwn_mlp_create(uint64_t seed, double fourier_sigma, gwn_mlp* out);
 gwn_status gwn_mlp_destroy(gwn_mlp h);
@@ -382,9 +382,102 @@ gwn_status gwn_mlp_loss_grad(gwn_mlp h, const float* qx, const float* qy, const 
                              const float* target, int64_t n, float* grad_out, float* loss_out, void* stream);
 gwn_status gwn_mlp_train_step(gwn_mlp h, const float* qx, const float* qy, const float* qz, int64_t qstride,
                               const float* target, int64_t n, float lr, float* loss_out, void* stream);
-gwn_status gwn_surrogate_query(gwn_mlp h, gwn_mesh mesh, const float* qx, const float* qy, const float* qz,
-                               int64_t qstride, int64_t n, float band, float* w_out, uint8_t* fallback_out,
-                               int64_t* nfallback_out, void* stream);
+
+/*
+ * gwn_surrogate_train -- fit the network to w on `mesh`, labels generated by the
+ * method itself (the exact FP32 path of gwn_query_batch).
+ *
+ * Data: with X == NULL the library draws cfg->n_train points uniformly in the
+ *   box [box_lo, box_hi] (both all zero: the mesh's bounding box) from
+ *   cfg->seed -- coordinate c of point i is lo_c + u (hi_c - lo_c), u the top 53
+ *   bits of splitmix64 at counter 3 i + c + 1 over 2^53, rounded once to float --
+ *   labels them, and keeps points and labels in the handle (16 bytes per
+ *   point).  Otherwise X is a DEVICE (n, 3) float array of the caller's points
+ *   (interleaved, stride 3) with labels T (device, n floats), or T == NULL to
+ *   have them labelled on `mesh` (kept in the handle).  `mesh` may be NULL only
+ *   when both X and T are given.
+ * Schedule: cfg->epochs passes over the data in mini-batches of cfg->batch
+ *   points (the last batch of a pass may be smaller); every pass visits the
+ *   points in a new random order, a keyed permutation that is a pure function
+ *   of (cfg->seed, pass number), evaluated on the device; the learning rate of
+ *   step k of the K-step schedule is lr_final + (lr - lr_final)(1 + cos(pi k /
+ *   (K - 1)))/2; one Adam step per batch.
+ * Resumption: the handle records the schedule and the data recipe it trains
+ *   under and how many passes are done; a call trains up to pass
+ *   cfg->stop_epoch (0 = cfg->epochs) and returns.  A later call -- on the same
+ *   handle, or on one made by gwn_surrogate_load -- with the same cfg and mesh
+ *   continues where it stopped, with the same bits as an uninterrupted run (the
+ *   shuffle and the learning rate depend only on the pass and step numbers, and
+ *   generated data are re-made identically).  A call with another schedule or
+ *   recipe on a handle that has trained passes returns GWN_E_INVALID.
+ * epoch_loss (HOST, nullable): one float per pass trained by this call, the
+ *   mean of its batches' losses; *epochs_run (HOST, nullable) receives the
+ *   number of passes trained.  Synchronises `stream` at the end.
+ * Errors: GWN_E_INVALID for a null handle, n_train or n outside [1, 2^31),
+ *   batch < 1, epochs < 1, lr or lr_final negative or not finite, an empty or
+ *   inverted box, or a mesh from another device.
+ */
+typedef struct {
+    uint64_t seed;           /* training points and the per-pass shuffles */
+    int64_t n_train;         /* generated points (when X is NULL) */
+    double box_lo[3];        /* box of the generated points; lo = hi = 0: the mesh's bounding box */
+    double box_hi[3];
+    int32_t epochs;          /* passes in the schedule */
+    int32_t batch;           /* points per Adam step */
+    float lr;                /* learning rate at the first step */
+    float lr_final;          /* ... at the last step of the schedule */
+    int32_t stop_epoch;      /* train until this many passes are done (0 = epochs) */
+    int32_t reserved;        /* zero */
+} gwn_surrogate_cfg;
+
+gwn_status gwn_surrogate_train(gwn_surrogate h, gwn_mesh mesh, const gwn_surrogate_cfg* cfg, const float* X,
+                               const float* T, int64_t n, float* epoch_loss, int64_t* epochs_run, void* stream);
+
+/*
+ * gwn_surrogate_save -- write the handle's complete state to `path` (a host
+ * file, replaced atomically): a fixed header (magic "GWNSURR1", format
+ * version 1, sizes, Adam step count, passes done, sigma, the seeds, the data
+ * recipe and the schedule of the run in progress, the labelling mesh's
+ * triangle and boundary-edge counts), then G, the fp32 master weights, the
+ * Adam moments m and v, the three bf16 copies the kernels read, and an FNV-1a
+ * 64-bit checksum of everything before it; little-endian.  Synchronises the
+ * device.  GWN_E_INVALID if the file cannot be written.
+ *
+ * gwn_surrogate_load -- a new handle on the current device from such a file.
+ * The bf16 copies are re-derived from the fp32 masters and must equal the
+ * stored ones.  GWN_E_INVALID for a missing, truncated, corrupted (checksum)
+ * or foreign file.  Training data are not stored: a resumed gwn_surrogate_train
+ * re-makes them from the recorded recipe.
+ *
+ * gwn_surrogate_destroy -- release the handle (NULL is a no-op); the same as
+ * gwn_mlp_destroy.
+ */
+gwn_status gwn_surrogate_save(gwn_surrogate h, const char* path);
+gwn_status gwn_surrogate_load(const char* path, gwn_surrogate* out);
+gwn_status gwn_surrogate_destroy(gwn_surrogate h);
+
+/*
+ * gwn_surrogate_query -- w_out = network prediction, except for points the
+ * fallback rule marks, which are re-evaluated by the exact FP32 path
+ * (gwn_query_batch) on `mesh`:
+ *   rule GWN_BAND_HALF (0): |prediction - 1/2| < band (uncertain between
+ *     outside, w = 0, and inside, w = 1);
+ *   rule GWN_BAND_FRAC (1): |frac(prediction) - 1/2| < band, i.e. the
+ *     prediction lies within band of a half-integer (uncertain between any two
+ *     consecutive winding levels, as where surfaces overlap).
+ * band > 1/2 under rule 1 re-evaluates every point (at 1/2 a prediction that is
+ * exactly an integer keeps its value).  fallback_out (device,
+ * nullable) flags the re-evaluated points and *nfallback_out (host, nullable)
+ * counts them.  The exact values are bit-identical to gwn_query_batch's at the
+ * same points.  The call synchronises the stream once, to size the exact
+ * evaluation by that count.  Errors: GWN_E_INVALID for band < 0, a rule other
+ * than 0 or 1, and as for gwn_query_batch.
+ */
+#define GWN_BAND_HALF 0
+#define GWN_BAND_FRAC 1
+gwn_status gwn_surrogate_query(gwn_surrogate h, gwn_mesh mesh, const float* qx, const float* qy, const float* qz,
+                               int64_t qstride, int64_t n, float band, int32_t rule, float* w_out,
+                               uint8_t* fallback_out, int64_t* nfallback_out, void* stream);
 
 const char* gwn_status_str(gwn_status s);
 const char* gwn_last_error(void);   /* thread-local; "" if none */

@@ -334,6 +334,11 @@ static gwn_status check_mlp(gwn_mlp h, const char* fn) {
         gwn::set_error("%s: null handle", fn);
         return GWN_E_INVALID;
     }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != gwn::mlp_device(h)) {
+        gwn::set_error("%s: the network was created on device %d, current device is %d", fn, gwn::mlp_device(h), dev);
+        return GWN_E_INVALID;
+    }
     return GWN_OK;
 }
 
@@ -399,19 +404,80 @@ gwn_status gwn_mlp_train_step(gwn_mlp h, const float* qx, const float* qy, const
 }
 
 gwn_status gwn_surrogate_query(gwn_mlp h, gwn_mesh mesh, const float* qx, const float* qy, const float* qz, int64_t qs,
-                               int64_t n, float band, float* w_out, uint8_t* fallback_out, int64_t* nfallback_out,
-                               void* stream) {
+                               int64_t n, float band, int32_t rule, float* w_out, uint8_t* fallback_out,
+                               int64_t* nfallback_out, void* stream) {
     gwn::clear_error();
     gwn_status s = check_mlp(h, "gwn_surrogate_query");
     if (s == GWN_OK) s = check_mesh(mesh, "gwn_surrogate_query");
     if (s == GWN_OK) s = check_points("gwn_surrogate_query", qx, qy, qz, qs, n, w_out);
-    if (s == GWN_OK && !(band >= 0.f)) {
-        gwn::set_error("gwn_surrogate_query: band must be >= 0");
+    if (s == GWN_OK && (!(band >= 0.f) || (rule != GWN_BAND_HALF && rule != GWN_BAND_FRAC))) {
+        gwn::set_error("gwn_surrogate_query: band must be >= 0 and rule 0 or 1 (got %g, %d)", (double)band, rule);
         s = GWN_E_INVALID;
     }
     return s != GWN_OK ? s
-                       : gwn::surrogate_query(h, mesh, qx, qy, qz, qs, n, band, w_out, fallback_out, nfallback_out,
-                                              (hipStream_t)stream);
+                       : gwn::surrogate_query(h, mesh, qx, qy, qz, qs, n, band, rule, w_out, fallback_out,
+                                              nfallback_out, (hipStream_t)stream);
+}
+
+gwn_status gwn_surrogate_train(gwn_surrogate h, gwn_mesh mesh, const gwn_surrogate_cfg* cfg, const float* X,
+                               const float* T, int64_t n, float* epoch_loss, int64_t* epochs_run, void* stream) {
+    gwn::clear_error();
+    if (epochs_run) *epochs_run = 0;
+    gwn_status s = check_mlp(h, "gwn_surrogate_train");
+    if (s != GWN_OK) return s;
+    if (!cfg) {
+        gwn::set_error("gwn_surrogate_train: null cfg");
+        return GWN_E_INVALID;
+    }
+    const gwn_surrogate_cfg& c = *cfg;
+    const int64_t npts = X ? n : c.n_train;
+    if (npts < 1 || npts >= (1ll << 31) || c.batch < 1 || c.epochs < 1 || c.stop_epoch < 0 ||
+        !(c.lr >= 0.f) || !std::isfinite(c.lr) || !(c.lr_final >= 0.f) || !std::isfinite(c.lr_final)) {
+        gwn::set_error("gwn_surrogate_train: bad configuration (points %lld, batch %d, epochs %d, stop %d, lr %g, "
+                       "lr_final %g)", (long long)npts, c.batch, c.epochs, c.stop_epoch, (double)c.lr,
+                       (double)c.lr_final);
+        return GWN_E_INVALID;
+    }
+    if (!X) {
+        const bool dflt = c.box_lo[0] == 0 && c.box_lo[1] == 0 && c.box_lo[2] == 0 && c.box_hi[0] == 0 &&
+                          c.box_hi[1] == 0 && c.box_hi[2] == 0;
+        for (int a = 0; a < 3 && !dflt; ++a)
+            if (!(c.box_hi[a] > c.box_lo[a]) || !std::isfinite(c.box_lo[a]) || !std::isfinite(c.box_hi[a])) {
+                gwn::set_error("gwn_surrogate_train: the box must have lo < hi on every axis");
+                return GWN_E_INVALID;
+            }
+    }
+    if (!X || !T) {
+        s = check_mesh(mesh, "gwn_surrogate_train");
+        if (s != GWN_OK) return s;
+    }
+    return gwn::surrogate_train(h, mesh, c, X, T, npts, epoch_loss, epochs_run, (hipStream_t)stream);
+}
+
+gwn_status gwn_surrogate_save(gwn_surrogate h, const char* path) {
+    gwn::clear_error();
+    gwn_status s = check_mlp(h, "gwn_surrogate_save");
+    if (s == GWN_OK && !path) {
+        gwn::set_error("gwn_surrogate_save: null path");
+        s = GWN_E_INVALID;
+    }
+    return s != GWN_OK ? s : gwn::surrogate_save(h, path);
+}
+
+gwn_status gwn_surrogate_load(const char* path, gwn_surrogate* out) {
+    gwn::clear_error();
+    if (!path || !out) {
+        gwn::set_error("gwn_surrogate_load: null argument");
+        return GWN_E_INVALID;
+    }
+    *out = nullptr;
+    return gwn::surrogate_load(path, out);
+}
+
+gwn_status gwn_surrogate_destroy(gwn_surrogate h) {
+    gwn::clear_error();
+    gwn::mlp_release(h);
+    return GWN_OK;
 }
 
 const char* gwn_status_str(gwn_status s) {

@@ -96,6 +96,7 @@ void multi_info(const gwn_multi_s* p, gwn_multi_info* out);
 
 gwn_status mlp_create(uint64_t seed, double sigma, gwn_mlp_s** out);
 void mlp_release(gwn_mlp_s* h);
+int mlp_device(const gwn_mlp_s* h);
 gwn_status mlp_get_state(gwn_mlp_s* h, float* theta, float* m, float* v, float* G, int64_t* step);
 gwn_status mlp_set_state(gwn_mlp_s* h, const float* theta, const float* m, const float* v, const float* G,
                          int64_t step);
@@ -106,8 +107,12 @@ gwn_status mlp_loss_grad(gwn_mlp_s* h, const float* qx, const float* qy, const f
 gwn_status mlp_train_step(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs,
                           const float* tgt, int64_t n, float lr, float* loss_out, hipStream_t st);
 gwn_status surrogate_query(gwn_mlp_s* h, const gwn_mesh_s* mesh, const float* qx, const float* qy, const float* qz,
-                           int64_t qs, int64_t n, float band, float* w, unsigned char* mask, int64_t* nfallback,
-                           hipStream_t st);
+                           int64_t qs, int64_t n, float band, int rule, float* w, unsigned char* mask,
+                           int64_t* nfallback, hipStream_t st);
+gwn_status surrogate_train(gwn_mlp_s* h, const gwn_mesh_s* mesh, const gwn_surrogate_cfg& cfg, const float* X,
+                           const float* T, int64_t n, float* epoch_loss, int64_t* epochs_run, hipStream_t st);
+gwn_status surrogate_save(gwn_mlp_s* h, const char* path);
+gwn_status surrogate_load(const char* path, gwn_mlp_s** out);
 
 // Fixed-point grid rule (host, FP64): origin = bbox_lo - 0.75 e, scale 2^k with
 // k the largest integer such that 2.5 e 2^k <= 2^30 - 1 (e = max extent, 1 if 0).

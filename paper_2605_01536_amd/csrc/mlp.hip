@@ -16,7 +16,9 @@
 // placement.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "gwn_kernels.h"
@@ -58,6 +60,7 @@ struct Train {
     unsigned short* dz;  // 4 x n x 128
     float* y;            // n
     float* dy;           // n
+    float* tb;           // n: the batch's targets, in batch order
     float* part;         // nchunk x (kNParams + 1)   (last entry: loss partial)
     float* grad;         // kNParams + 1
     long long cap;
@@ -69,6 +72,74 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
     return (unsigned short)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// splitmix64's output function (Steele, Lea and Flood 2014): a bijective 64-bit
+// mix.  Applied to a counter it is the splitmix64 generator; here it also
+// drives the shuffle's round function and the training points.
+__host__ __device__ inline unsigned long long smix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+constexpr unsigned long long kGolden = 0x9E3779B97F4A7C15ull;
+
+// Where the rows of a training batch come from: row r is source point
+// order(off + r), where order is the identity (half == 0) or a keyed random
+// permutation of [0, ntot): a 4-round Feistel network on 2*half bits with
+// cycle walking (re-apply until the value falls below ntot; the walk stays on
+// the cycle of a bijection, so it ends, after fewer than 4 rounds on average
+// since 2^(2 half) < 4 ntot).  Every epoch draws a new key.
+struct Src {
+    const float* qx;
+    const float* qy;
+    const float* qz;
+    long long qs;
+    const float* tgt;
+    long long off;
+    long long ntot;
+    unsigned long long key;
+    int half;
+};
+
+__host__ __device__ inline long long src_index(const Src& s, long long i) {
+    if (s.half == 0) return i;
+    const unsigned mask = (1u << s.half) - 1u;
+    unsigned long long x = (unsigned long long)i;
+    do {
+        unsigned L = (unsigned)(x >> s.half), R = (unsigned)x & mask;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const unsigned F = (unsigned)smix64(s.key + (unsigned long long)(r + 1) * kGolden + R) & mask;
+            const unsigned nr = L ^ F;
+            L = R;
+            R = nr;
+        }
+        x = ((unsigned long long)L << s.half) | R;
+    } while (x >= (unsigned long long)s.ntot);
+    return (long long)x;
+}
+
+// half-width of the shuffle's Feistel network for n points (2 half >= log2 n)
+inline int shuffle_half(long long n) {
+    int b = 1;
+    while (b < 62 && (1ll << b) < n) ++b;
+    return (b + 1) / 2;
+}
+
+// Training points: coordinate c of point i is lo_c + u (hi_c - lo_c) with
+// u = (top 53 bits of splitmix64 at counter 3 i + c + 1) / 2^53, in FP64, rounded once.
+__global__ void k_gen_points(unsigned long long seed, long long n, double lx, double ly, double lz, double ex,
+                             double ey, double ez, float* __restrict__ X) {
+    const long long i = blockIdx.x * 256ll + threadIdx.x;
+    if (i >= n) return;
+    const double lo[3] = {lx, ly, lz}, ext[3] = {ex, ey, ez};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const unsigned long long h = smix64(seed + (unsigned long long)(3 * i + c + 1) * kGolden);
+        const double u = (double)(h >> 11) * (1.0 / 9007199254740992.0);
+        X[3 * i + c] = (float)(lo[c] + u * ext[c]);
+    }
+}
 
 // erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7); returns Phi(z) and
 // exp(-z^2/2) so that gelu = z Phi and gelu' = Phi + z exp(-z^2/2)/sqrt(2 pi).
@@ -119,8 +190,7 @@ __device__ __forceinline__ void mma_rows16(const unsigned short* sA, int lda, co
 // are kept for the backward pass.  Every workgroup stages all bf16 weights in
 // LDS once, then walks its tiles of 64 points; each wave owns 16 rows and only
 // ever touches its own rows of the activation tile.
-__global__ __launch_bounds__(256) void k_fwd(Dev P, const float* __restrict__ qx, const float* __restrict__ qy,
-                                             const float* __restrict__ qz, long long qs, long long n, Train T) {
+__global__ __launch_bounds__(256) void k_fwd(Dev P, Src S, long long n, Train T) {
     __shared__ __attribute__((aligned(16))) unsigned short sW0[128 * kLd0];
     __shared__ __attribute__((aligned(16))) unsigned short sW[3][128 * kLd];
     __shared__ __attribute__((aligned(16))) unsigned short sA[kTile * kLd];
@@ -145,8 +215,9 @@ __global__ __launch_bounds__(256) void k_fwd(Dev P, const float* __restrict__ qx
     for (long long tile = blockIdx.x; tile * kTile < n; tile += gridDim.x) {
         const long long base = tile * kTile + r0;
         {   // Fourier features of this wave's 16 points; lane: point lr, frequencies 8lg..8lg+7
-            const long long pi = min(base + lr, n - 1);
-            const float px = qx[pi * qs], py = qy[pi * qs], pz = qz[pi * qs];
+            const long long pi = src_index(S, S.off + min(base + lr, n - 1));
+            const float px = S.qx[pi * S.qs], py = S.qy[pi * S.qs], pz = S.qz[pi * S.qs];
+            if (lg == 0 && base + lr < n) T.tb[base + lr] = S.tgt[pi];
 #pragma unroll
             for (int f = 8 * lg; f < 8 * lg + 8; ++f) {
                 const float arg = 6.283185307179586f * fmaf(sG[3 * f], px, fmaf(sG[3 * f + 1], py, sG[3 * f + 2] * pz));
@@ -201,7 +272,7 @@ __global__ __launch_bounds__(256) void k_fwd(Dev P, const float* __restrict__ qx
 }
 
 // Backward pass through the activations: dy, then dz_3 .. dz_0 (bf16, row-major).
-__global__ __launch_bounds__(256) void k_bwd(Dev P, long long n, const float* __restrict__ tgt, float inv_n, Train T) {
+__global__ __launch_bounds__(256) void k_bwd(Dev P, long long n, float inv_n, Train T) {
     __shared__ __attribute__((aligned(16))) unsigned short sW[3][128 * kLd];   // W1..W3 as [in][out]
     __shared__ __attribute__((aligned(16))) unsigned short sA[kTile * kLd];
     __shared__ float sW4[128];
@@ -220,7 +291,7 @@ __global__ __launch_bounds__(256) void k_bwd(Dev P, long long n, const float* __
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const long long row = tile * kTile + r0 + 4 * lg + i;
-            dyr[i] = row < n ? 2.f * (T.y[row] - tgt[row]) * inv_n : 0.f;
+            dyr[i] = row < n ? 2.f * (T.y[row] - T.tb[row]) * inv_n : 0.f;
 #pragma unroll
             for (int t = 0; t < 8; ++t) zr[t][i] = row < n ? T.z[(3 * T.cap + row) * 128 + 16 * t + lr] : 0.f;
         }
@@ -503,9 +574,12 @@ __global__ void k_pack(Dev P) {
     if (p < kNParams) pack_one(P, p, P.master[p]);
 }
 
+// loss_slot (nullable): receives the batch's mean squared error, sum(dy^2) nb / 4
+// with dy = 2 (y - t) / nb
 __global__ void k_adam(Dev P, const float* __restrict__ grad, float lr, float b1, float b2, float eps, float c1,
-                       float c2) {
+                       float c2, float* __restrict__ loss_slot, float nb) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0 && loss_slot) *loss_slot = grad[kNParams] * nb * 0.25f;
     if (p >= kNParams) return;
     const float g = grad[p];
     const float m = b1 * P.m[p] + (1.f - b1) * g;
@@ -524,16 +598,22 @@ __global__ void k_adam(Dev P, const float* __restrict__ grad, float lr, float b1
 // order (one counter per block instead of one atomic per wave).
 constexpr int kBandBlocks = 1024;
 
-__device__ __forceinline__ bool in_band(const float* y, long long i, long long n, float band) {
-    return i < n && fabsf(y[i] - 0.5f) < band;
+// rule 0: |y - 1/2| < band (the uncertain region between outside, w = 0, and
+// inside, w = 1); rule 1: |frac(y) - 1/2| < band, i.e. y within band of the
+// nearest half-integer (any jump between consecutive winding levels)
+__device__ __forceinline__ bool in_band(const float* y, long long i, long long n, float band, int rule) {
+    if (i >= n) return false;
+    const float v = y[i];
+    const float d = rule == 0 ? v - 0.5f : v - floorf(v) - 0.5f;
+    return fabsf(d) < band;
 }
 
 __global__ __launch_bounds__(256) void k_band_count(const float* __restrict__ y, long long n, long long seg,
-                                                    float band, int* __restrict__ bcnt) {
+                                                    float band, int rule, int* __restrict__ bcnt) {
     __shared__ int wc[4];
     const long long a = blockIdx.x * seg, e = min(n, a + seg);
     int c = 0;
-    for (long long i = a + threadIdx.x; i < e; i += 256) c += in_band(y, i, n, band) ? 1 : 0;
+    for (long long i = a + threadIdx.x; i < e; i += 256) c += in_band(y, i, n, band, rule) ? 1 : 0;
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
     if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = c;
     __syncthreads();
@@ -559,7 +639,7 @@ __global__ __launch_bounds__(kBandBlocks) void k_band_scan(const int* __restrict
 }
 
 __global__ __launch_bounds__(256) void k_band_write(const float* __restrict__ y, long long n, long long seg,
-                                                    float band, const int* __restrict__ boff,
+                                                    float band, int rule, const int* __restrict__ boff,
                                                     long long* __restrict__ idx, unsigned char* __restrict__ mask) {
     __shared__ int wc[4];
     const long long a = blockIdx.x * seg, e = min(n, a + seg);
@@ -567,7 +647,7 @@ __global__ __launch_bounds__(256) void k_band_write(const float* __restrict__ y,
     int base = boff[blockIdx.x];
     for (long long c0 = a; c0 < e; c0 += 256) {
         const long long i = c0 + threadIdx.x;
-        const bool f = i < e && in_band(y, i, n, band);
+        const bool f = i < e && in_band(y, i, n, band, rule);
         if (mask && i < e) mask[i] = f ? 1 : 0;
         const unsigned long long b = __builtin_amdgcn_ballot_w64(f);
         if (lane == 0) wc[wave] = __popcll(b);
@@ -604,14 +684,36 @@ __global__ void k_scatter(const float* __restrict__ wc, const long long* __restr
 // host-side parameter initialisation: a splitmix64 stream, Box-Muller normals
 struct Rng {
     unsigned long long s;
-    unsigned long long next() {
-        unsigned long long z = (s += 0x9E3779B97F4A7C15ull);
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        return z ^ (z >> 31);
-    }
+    unsigned long long next() { return smix64(s += kGolden); }
     double uni() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
     double normal() { return std::sqrt(-2.0 * std::log(uni())) * std::cos(6.283185307179586 * uni()); }
+};
+
+// The training data a handle generated for itself: n points uniform in the box,
+// drawn from `seed`, labelled by the exact FP32 path on the mesh.
+// The mesh's triangle and boundary-edge counts are kept as a fingerprint, so
+// that a resumed run cannot silently relabel its points on another mesh.
+struct Recipe {
+    unsigned long long seed = 0;
+    long long n = 0;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    long long mesh_nf = -1, mesh_nb = -1;
+    bool operator==(const Recipe& o) const {
+        return seed == o.seed && n == o.n && std::memcmp(lo, o.lo, sizeof(lo)) == 0 &&
+               std::memcmp(hi, o.hi, sizeof(hi)) == 0 && mesh_nf == o.mesh_nf && mesh_nb == o.mesh_nb;
+    }
+};
+
+// The schedule of a training run, recorded so that a resumed run (after
+// gwn_surrogate_load, or a later gwn_surrogate_train call) continues it exactly.
+struct Schedule {
+    int epochs = 0, batch = 0;
+    float lr = 0.f, lr_final = 0.f;
+    int external = 0;          // 1: the caller supplied the points
+    bool operator==(const Schedule& o) const {
+        return epochs == o.epochs && batch == o.batch && lr == o.lr && lr_final == o.lr_final &&
+               external == o.external;
+    }
 };
 
 }  // namespace mlp
@@ -621,7 +723,20 @@ struct gwn_mlp_s {
     int device = 0;
     gwn::mlp::Dev d{};
     gwn::mlp::Train t{};
-    long long step = 0;
+    long long step = 0;              // Adam steps taken
+    double sigma = 0.0;              // Fourier-feature scale the network was created with
+    unsigned long long init_seed = 0;
+    // training run in progress (gwn_surrogate_train)
+    gwn::mlp::Recipe recipe{};
+    gwn::mlp::Schedule sched{};
+    long long epochs_done = 0;
+    float* data_x = nullptr;         // recipe.n x 3 generated points
+    float* data_t = nullptr;         // their labels (or the labels of caller points, when only X is given)
+    long long data_cap = 0;
+    bool data_valid = false;         // data_x / data_t hold the recipe's points and labels
+    float* loss_dev = nullptr;       // per-step batch losses of one call
+    long long loss_cap = 0;
+    // band query scratch
     float* scratch_w = nullptr;      // compacted fallback outputs
     float* scratch_q = nullptr;      // compacted fallback coordinates
     long long* scratch_idx = nullptr;
@@ -643,6 +758,7 @@ void free_train(gwn_mlp_s* h) {
     (void)hipFree(h->t.dz);
     (void)hipFree(h->t.y);
     (void)hipFree(h->t.dy);
+    (void)hipFree(h->t.tb);
     (void)hipFree(h->t.part);
     (void)hipFree(h->t.grad);
     h->t = Train{};
@@ -658,6 +774,7 @@ gwn_status ensure_train(gwn_mlp_s* h, long long n) {
     GWN_HIP_TRY(hipMalloc((void**)&h->t.dz, sizeof(unsigned short) * 4 * cap * 128));
     GWN_HIP_TRY(hipMalloc((void**)&h->t.y, sizeof(float) * cap));
     GWN_HIP_TRY(hipMalloc((void**)&h->t.dy, sizeof(float) * cap));
+    GWN_HIP_TRY(hipMalloc((void**)&h->t.tb, sizeof(float) * cap));
     GWN_HIP_TRY(hipMalloc((void**)&h->t.part, sizeof(float) * nchunk * (kNParams + 1)));
     GWN_HIP_TRY(hipMalloc((void**)&h->t.grad, sizeof(float) * (kNParams + 1)));
     h->t.cap = cap;
@@ -670,6 +787,11 @@ gwn_status ensure_scratch(gwn_mlp_s* h, long long n) {
     (void)hipFree(h->scratch_q);
     (void)hipFree(h->scratch_idx);
     (void)hipFree(h->scratch_chi);
+    h->scratch_w = nullptr;
+    h->scratch_q = nullptr;
+    h->scratch_idx = nullptr;
+    h->scratch_chi = nullptr;
+    h->scratch_cap = 0;
     const long long cap = std::max<long long>(n, 1024);
     GWN_HIP_TRY(hipMalloc((void**)&h->scratch_w, sizeof(float) * cap));
     GWN_HIP_TRY(hipMalloc((void**)&h->scratch_q, sizeof(float) * 3 * cap));
@@ -681,15 +803,113 @@ gwn_status ensure_scratch(gwn_mlp_s* h, long long n) {
     return GWN_OK;
 }
 
+gwn_status ensure_data(gwn_mlp_s* h, long long n) {
+    if (h->data_cap >= n) return GWN_OK;
+    (void)hipFree(h->data_x);
+    (void)hipFree(h->data_t);
+    h->data_x = nullptr;
+    h->data_t = nullptr;
+    h->data_cap = 0;
+    h->data_valid = false;
+    GWN_HIP_TRY(hipMalloc((void**)&h->data_x, sizeof(float) * 3 * (size_t)std::max<long long>(n, 1)));
+    GWN_HIP_TRY(hipMalloc((void**)&h->data_t, sizeof(float) * (size_t)std::max<long long>(n, 1)));
+    h->data_cap = n;
+    return GWN_OK;
+}
+
 int fwd_grid(long long n) {
     const long long tiles = (n + kTile - 1) / kTile;
     return (int)std::max<long long>(1, std::min<long long>(tiles, 1024));
 }
 
+gwn_status alloc_params(gwn_mlp_s* h) {
+    GWN_HIP_TRY(hipGetDevice(&h->device));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.master, sizeof(float) * kNParams));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.m, sizeof(float) * kNParams));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.v, sizeof(float) * kNParams));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.G, sizeof(float) * 96));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.wf, sizeof(unsigned short) * kWf));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.wb, sizeof(unsigned short) * kWb));
+    GWN_HIP_TRY(hipMalloc((void**)&h->d.wi, sizeof(unsigned short) * kWi));
+    return GWN_OK;
+}
+
+// One optimisation step on the batch rows S.off .. S.off + n - 1: forward,
+// backward, weight gradients, their sum, then Adam at learning rate lr.
+gwn_status train_batch(gwn_mlp_s* h, const Src& S, long long n, float lr, float* loss_slot, hipStream_t st) {
+    k_fwd<<<fwd_grid(n), 256, 0, st>>>(h->d, S, n, h->t);
+    GWN_HIP_TRY(hipGetLastError());
+    k_bwd<<<fwd_grid(n), 256, 0, st>>>(h->d, n, 1.0f / (float)n, h->t);
+    GWN_HIP_TRY(hipGetLastError());
+    const int nchunk = (int)((n + kChunk - 1) / kChunk);
+    k_wgrad<<<dim3(nchunk, 5), 256, 0, st>>>(n, h->t);
+    GWN_HIP_TRY(hipGetLastError());
+    k_reduce<<<(kNParams + 1 + 255) / 256, 256, 0, st>>>(h->t.part, nchunk, h->t.grad);
+    GWN_HIP_TRY(hipGetLastError());
+    if (lr < 0.f) return GWN_OK;   // gradient only
+    h->step += 1;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)h->step));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)h->step));
+    k_adam<<<(kNParams + 255) / 256, 256, 0, st>>>(h->d, h->t.grad, lr, 0.9f, 0.999f, 1e-8f, c1, c2, loss_slot,
+                                                  (float)n);
+    GWN_HIP_TRY(hipGetLastError());
+    return GWN_OK;
+}
+
+Src plain_src(const float* qx, const float* qy, const float* qz, int64_t qs, const float* tgt, int64_t n) {
+    Src s{};
+    s.qx = qx;
+    s.qy = qy;
+    s.qz = qz;
+    s.qs = qs;
+    s.tgt = tgt;
+    s.off = 0;
+    s.ntot = n;
+    s.key = 0;
+    s.half = 0;
+    return s;
+}
+
+// ---- checkpoint file: a fixed little-endian header, the arrays, then an
+// FNV-1a 64-bit checksum of every byte before it
+constexpr char kMagic[8] = {'G', 'W', 'N', 'S', 'U', 'R', 'R', '1'};
+constexpr uint32_t kVersion = 1;
+
+struct FileHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t header_bytes;
+    int64_t nparams;
+    int64_t step;              // Adam steps taken (bias correction)
+    int64_t epochs_done;       // epochs of the recorded schedule completed
+    double sigma;
+    uint64_t init_seed;
+    uint64_t data_seed;        // the recipe of the generated training points
+    int64_t data_n;
+    double box_lo[3], box_hi[3];
+    int32_t sched_epochs, sched_batch;
+    float sched_lr, sched_lr_final;
+    int32_t sched_external;
+    int32_t data_generated;    // 1: the run trains on generated points (recipe above)
+    int64_t mesh_nf, mesh_nb;  // fingerprint of the labelling mesh (-1: labels from the caller)
+    int64_t n_wf, n_wb, n_wi;  // bf16 copies stored after the fp32 arrays
+};
+
+uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h) {
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+
 }  // namespace
+
+int mlp_device(const gwn_mlp_s* h) { return h->device; }
 
 void mlp_release(gwn_mlp_s* h) {
     if (!h) return;
+    (void)hipDeviceSynchronize();   // nothing may still use the buffers
     (void)hipFree(h->d.master);
     (void)hipFree(h->d.m);
     (void)hipFree(h->d.v);
@@ -698,6 +918,9 @@ void mlp_release(gwn_mlp_s* h) {
     (void)hipFree(h->d.wb);
     (void)hipFree(h->d.wi);
     free_train(h);
+    (void)hipFree(h->data_x);
+    (void)hipFree(h->data_t);
+    (void)hipFree(h->loss_dev);
     (void)hipFree(h->scratch_w);
     (void)hipFree(h->scratch_q);
     (void)hipFree(h->scratch_idx);
@@ -714,14 +937,10 @@ gwn_status mlp_create(uint64_t seed, double sigma, gwn_mlp_s** out) {
         gwn_mlp_s* h;
         ~Guard() { if (h) mlp_release(h); }
     } guard{h};
-    GWN_HIP_TRY(hipGetDevice(&h->device));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.master, sizeof(float) * kNParams));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.m, sizeof(float) * kNParams));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.v, sizeof(float) * kNParams));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.G, sizeof(float) * 96));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.wf, sizeof(unsigned short) * kWf));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.wb, sizeof(unsigned short) * kWb));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.wi, sizeof(unsigned short) * kWi));
+    gwn_status s = alloc_params(h);
+    if (s != GWN_OK) return s;
+    h->sigma = sigma;
+    h->init_seed = seed;
     Rng r{seed};
     std::vector<float> G(96), theta(kNParams, 0.f);
     for (float& g : G) g = (float)(sigma * r.normal());
@@ -778,25 +997,11 @@ gwn_status mlp_forward(gwn_mlp_s* h, const float* qx, const float* qy, const flo
     return GWN_OK;
 }
 
-gwn_status mlp_grad(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs, const float* tgt,
-                    int64_t n, hipStream_t st) {
-    gwn_status s = ensure_train(h, n);
-    if (s != GWN_OK) return s;
-    k_fwd<<<fwd_grid(n), 256, 0, st>>>(h->d, qx, qy, qz, qs, n, h->t);
-    GWN_HIP_TRY(hipGetLastError());
-    k_bwd<<<fwd_grid(n), 256, 0, st>>>(h->d, n, tgt, 1.0f / (float)n, h->t);
-    GWN_HIP_TRY(hipGetLastError());
-    const int nchunk = (int)((n + kChunk - 1) / kChunk);
-    k_wgrad<<<dim3(nchunk, 5), 256, 0, st>>>(n, h->t);
-    GWN_HIP_TRY(hipGetLastError());
-    k_reduce<<<(kNParams + 1 + 255) / 256, 256, 0, st>>>(h->t.part, nchunk, h->t.grad);
-    GWN_HIP_TRY(hipGetLastError());
-    return GWN_OK;
-}
-
 gwn_status mlp_loss_grad(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs,
                          const float* tgt, int64_t n, float* grad_out, float* loss_out, hipStream_t st) {
-    gwn_status s = mlp_grad(h, qx, qy, qz, qs, tgt, n, st);
+    gwn_status s = ensure_train(h, n);
+    if (s != GWN_OK) return s;
+    s = train_batch(h, plain_src(qx, qy, qz, qs, tgt, n), n, -1.f, nullptr, st);
     if (s != GWN_OK) return s;
     if (grad_out)
         GWN_HIP_TRY(hipMemcpyAsync(grad_out, h->t.grad, sizeof(float) * kNParams, hipMemcpyDeviceToDevice, st));
@@ -811,20 +1016,305 @@ gwn_status mlp_loss_grad(gwn_mlp_s* h, const float* qx, const float* qy, const f
 
 gwn_status mlp_train_step(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs,
                           const float* tgt, int64_t n, float lr, float* loss_out, hipStream_t st) {
-    gwn_status s = mlp_loss_grad(h, qx, qy, qz, qs, tgt, n, nullptr, loss_out, st);
+    gwn_status s = ensure_train(h, n);
     if (s != GWN_OK) return s;
-    h->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = (float)(1.0 - std::pow(0.9, (double)h->step));
-    const float c2 = (float)(1.0 - std::pow(0.999, (double)h->step));
-    k_adam<<<(kNParams + 255) / 256, 256, 0, st>>>(h->d, h->t.grad, lr, b1, b2, eps, c1, c2);
+    if (!h->loss_dev) {
+        GWN_HIP_TRY(hipMalloc((void**)&h->loss_dev, sizeof(float) * 1024));
+        h->loss_cap = 1024;
+    }
+    s = train_batch(h, plain_src(qx, qy, qz, qs, tgt, n), n, lr, h->loss_dev, st);
+    if (s != GWN_OK) return s;
+    if (loss_out) {
+        GWN_HIP_TRY(hipMemcpyAsync(loss_out, h->loss_dev, sizeof(float), hipMemcpyDeviceToHost, st));
+        GWN_HIP_TRY(hipStreamSynchronize(st));
+    }
+    return GWN_OK;
+}
+
+// World-frame bounding box of the mesh's vertices (the handle keeps it in the
+// frame of its ray axis: frame component c is world component (c + axis) % 3).
+static void world_bbox(const gwn_mesh_s* m, double lo[3], double hi[3]) {
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + m->axis) % 3;
+        lo[a] = m->bbox[c];
+        hi[a] = m->bbox[3 + c];
+    }
+}
+
+gwn_status surrogate_train(gwn_mlp_s* h, const gwn_mesh_s* mesh, const gwn_surrogate_cfg& c, const float* X,
+                           const float* T, int64_t n_given, float* epoch_loss, int64_t* epochs_run, hipStream_t st) {
+    if (epochs_run) *epochs_run = 0;
+    Schedule sc;
+    sc.epochs = c.epochs;
+    sc.batch = c.batch;
+    sc.lr = c.lr;
+    sc.lr_final = c.lr_final;
+    sc.external = X ? 1 : 0;
+    Recipe rc;
+    if (!X) {
+        rc.seed = c.seed;
+        rc.n = c.n_train;
+        const bool dflt = c.box_lo[0] == 0 && c.box_lo[1] == 0 && c.box_lo[2] == 0 && c.box_hi[0] == 0 &&
+                          c.box_hi[1] == 0 && c.box_hi[2] == 0;
+        if (dflt) world_bbox(mesh, rc.lo, rc.hi);
+        else
+            for (int a = 0; a < 3; ++a) {
+                rc.lo[a] = c.box_lo[a];
+                rc.hi[a] = c.box_hi[a];
+            }
+    } else {
+        rc.seed = c.seed;
+        rc.n = n_given;
+    }
+    if (!X || !T) {
+        rc.mesh_nf = mesh->nf;
+        rc.mesh_nb = mesh->nb;
+    }
+    // a run in progress continues only under the schedule and data it started with
+    if (h->epochs_done > 0 && !(h->sched == sc && h->recipe == rc)) {
+        set_error("gwn_surrogate_train: the handle has trained %lld epochs under another schedule or data recipe; "
+                  "resume with the same configuration or start from a new handle", h->epochs_done);
+        return GWN_E_INVALID;
+    }
+    const long long n = rc.n;
+    const int stop = c.stop_epoch > 0 ? std::min(c.stop_epoch, c.epochs) : c.epochs;
+    h->sched = sc;
+    const float* dx = X;
+    const float* dt = T;
+    gwn_status s = GWN_OK;
+    if (!X || !T) {
+        // generated points, or caller points without labels: the library keeps
+        // the points (when generated) and the labels
+        if (!X && !(h->data_valid && h->recipe == rc)) {
+            s = ensure_data(h, n);
+            if (s != GWN_OK) return s;
+            k_gen_points<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(rc.seed, n, rc.lo[0], rc.lo[1], rc.lo[2],
+                                                                     rc.hi[0] - rc.lo[0], rc.hi[1] - rc.lo[1],
+                                                                     rc.hi[2] - rc.lo[2], h->data_x);
+            GWN_HIP_TRY(hipGetLastError());
+            s = query_batch(mesh, h->data_x, h->data_x + 1, h->data_x + 2, 3, n, GWN_PREC_FP32, h->data_t, nullptr,
+                            st);
+            if (s != GWN_OK) return s;
+            h->data_valid = true;
+        } else if (X) {
+            s = ensure_data(h, n);
+            if (s != GWN_OK) return s;
+            h->data_valid = false;   // holds labels of caller points, not the recipe
+            s = query_batch(mesh, X, X + 1, X + 2, 3, n, GWN_PREC_FP32, h->data_t, nullptr, st);
+            if (s != GWN_OK) return s;
+        }
+        if (!X) dx = h->data_x;
+        dt = h->data_t;
+    }
+    h->recipe = rc;
+    if (h->epochs_done >= stop) return GWN_OK;
+    const long long batch = std::min<long long>(c.batch, n);
+    const long long spe = (n + batch - 1) / batch;
+    const long long total = (long long)c.epochs * spe;
+    const long long nsteps = (stop - h->epochs_done) * spe;
+    s = ensure_train(h, batch);
+    if (s != GWN_OK) return s;
+    if (h->loss_cap < nsteps) {
+        (void)hipFree(h->loss_dev);
+        h->loss_dev = nullptr;
+        h->loss_cap = 0;
+        GWN_HIP_TRY(hipMalloc((void**)&h->loss_dev, sizeof(float) * (size_t)nsteps));
+        h->loss_cap = nsteps;
+    }
+    Src S{};
+    S.qx = dx;
+    S.qy = dx + 1;
+    S.qz = dx + 2;
+    S.qs = 3;
+    S.tgt = dt;
+    S.ntot = n;
+    S.half = shuffle_half(n);
+    const int first = (int)h->epochs_done;
+    long long j = 0;
+    for (int e = first; e < stop; ++e) {
+        // the epoch's shuffle key: a pure function of the seed and the epoch
+        S.key = smix64(rc.seed ^ smix64(0x5348554646ull + (unsigned long long)e * kGolden));
+        for (long long b = 0; b < spe; ++b, ++j) {
+            S.off = b * batch;
+            const long long nb = std::min(batch, n - S.off);
+            const long long k = (long long)e * spe + b;   // position in the whole schedule
+            const double ph = 3.141592653589793 * (double)k / (double)std::max<long long>(1, total - 1);
+            const float lr = (float)(c.lr_final + 0.5 * ((double)c.lr - c.lr_final) * (1.0 + std::cos(ph)));
+            s = train_batch(h, S, nb, lr, h->loss_dev + j, st);
+            if (s != GWN_OK) return s;
+        }
+        h->epochs_done = e + 1;
+    }
+    std::vector<float> losses((size_t)nsteps);
+    GWN_HIP_TRY(hipMemcpyAsync(losses.data(), h->loss_dev, sizeof(float) * (size_t)nsteps, hipMemcpyDeviceToHost, st));
+    GWN_HIP_TRY(hipStreamSynchronize(st));
+    if (epoch_loss)
+        for (int e = first; e < stop; ++e) {
+            double acc = 0.0;
+            for (long long b = 0; b < spe; ++b) acc += losses[(size_t)((e - first) * spe + b)];
+            epoch_loss[e - first] = (float)(acc / (double)spe);
+        }
+    if (epochs_run) *epochs_run = stop - first;
+    return GWN_OK;
+}
+
+gwn_status surrogate_save(gwn_mlp_s* h, const char* path) {
+    FileHeader hd{};
+    std::memcpy(hd.magic, kMagic, 8);
+    hd.version = kVersion;
+    hd.header_bytes = sizeof(FileHeader);
+    hd.nparams = kNParams;
+    hd.step = h->step;
+    hd.epochs_done = h->epochs_done;
+    hd.sigma = h->sigma;
+    hd.init_seed = h->init_seed;
+    hd.data_seed = h->recipe.seed;
+    hd.data_n = h->recipe.n;
+    for (int a = 0; a < 3; ++a) {
+        hd.box_lo[a] = h->recipe.lo[a];
+        hd.box_hi[a] = h->recipe.hi[a];
+    }
+    hd.sched_epochs = h->sched.epochs;
+    hd.sched_batch = h->sched.batch;
+    hd.sched_lr = h->sched.lr;
+    hd.sched_lr_final = h->sched.lr_final;
+    hd.sched_external = h->sched.external;
+    hd.data_generated = h->sched.external ? 0 : 1;
+    hd.mesh_nf = h->recipe.mesh_nf;
+    hd.mesh_nb = h->recipe.mesh_nb;
+    hd.n_wf = kWf;
+    hd.n_wb = kWb;
+    hd.n_wi = kWi;
+    std::vector<float> G(96), th(kNParams), m(kNParams), v(kNParams);
+    std::vector<unsigned short> wf(kWf), wb(kWb), wi(kWi);
+    GWN_HIP_TRY(hipDeviceSynchronize());
+    GWN_HIP_TRY(hipMemcpy(G.data(), h->d.G, sizeof(float) * 96, hipMemcpyDeviceToHost));
+    GWN_HIP_TRY(hipMemcpy(th.data(), h->d.master, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    GWN_HIP_TRY(hipMemcpy(m.data(), h->d.m, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    GWN_HIP_TRY(hipMemcpy(v.data(), h->d.v, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    GWN_HIP_TRY(hipMemcpy(wf.data(), h->d.wf, sizeof(unsigned short) * kWf, hipMemcpyDeviceToHost));
+    GWN_HIP_TRY(hipMemcpy(wb.data(), h->d.wb, sizeof(unsigned short) * kWb, hipMemcpyDeviceToHost));
+    GWN_HIP_TRY(hipMemcpy(wi.data(), h->d.wi, sizeof(unsigned short) * kWi, hipMemcpyDeviceToHost));
+    std::vector<unsigned char> buf;
+    auto put = [&buf](const void* p, size_t n) {
+        const unsigned char* c = (const unsigned char*)p;
+        buf.insert(buf.end(), c, c + n);
+    };
+    put(&hd, sizeof(hd));
+    put(G.data(), sizeof(float) * 96);
+    put(th.data(), sizeof(float) * kNParams);
+    put(m.data(), sizeof(float) * kNParams);
+    put(v.data(), sizeof(float) * kNParams);
+    put(wf.data(), sizeof(unsigned short) * kWf);
+    put(wb.data(), sizeof(unsigned short) * kWb);
+    put(wi.data(), sizeof(unsigned short) * kWi);
+    const uint64_t sum = fnv1a(buf.data(), buf.size(), 0xCBF29CE484222325ull);
+    put(&sum, sizeof(sum));
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) {
+        set_error("gwn_surrogate_save: cannot open %s for writing", tmp.c_str());
+        return GWN_E_INVALID;
+    }
+    const size_t wrote = std::fwrite(buf.data(), 1, buf.size(), f);
+    const bool ok = wrote == buf.size() && std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        set_error("gwn_surrogate_save: writing %s failed", path);
+        return GWN_E_INVALID;
+    }
+    return GWN_OK;
+}
+
+gwn_status surrogate_load(const char* path, gwn_mlp_s** out) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) {
+        set_error("gwn_surrogate_load: cannot open %s", path);
+        return GWN_E_INVALID;
+    }
+    std::vector<unsigned char> buf;
+    unsigned char tmp[1 << 16];
+    size_t got;
+    while ((got = std::fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + got);
+    std::fclose(f);
+    const size_t arrays = sizeof(float) * (96 + 3 * (size_t)kNParams) + sizeof(unsigned short) * (kWf + kWb + kWi);
+    const size_t want = sizeof(FileHeader) + arrays + sizeof(uint64_t);
+    FileHeader hd;
+    if (buf.size() < sizeof(FileHeader)) {
+        set_error("gwn_surrogate_load: %s is too short for a checkpoint", path);
+        return GWN_E_INVALID;
+    }
+    std::memcpy(&hd, buf.data(), sizeof(hd));
+    if (std::memcmp(hd.magic, kMagic, 8) != 0 || hd.version != kVersion || hd.header_bytes != sizeof(FileHeader) ||
+        hd.nparams != kNParams || hd.n_wf != kWf || hd.n_wb != kWb || hd.n_wi != kWi || buf.size() != want) {
+        set_error("gwn_surrogate_load: %s is not a version-%u surrogate checkpoint of this network", path, kVersion);
+        return GWN_E_INVALID;
+    }
+    uint64_t sum;
+    std::memcpy(&sum, buf.data() + want - sizeof(uint64_t), sizeof(sum));
+    if (fnv1a(buf.data(), want - sizeof(uint64_t), 0xCBF29CE484222325ull) != sum) {
+        set_error("gwn_surrogate_load: checksum mismatch in %s", path);
+        return GWN_E_INVALID;
+    }
+    if (!(hd.sigma > 0.0) || hd.step < 0 || hd.epochs_done < 0 || hd.data_n < 0) {
+        set_error("gwn_surrogate_load: bad values in the header of %s", path);
+        return GWN_E_INVALID;
+    }
+    gwn_mlp_s* h = new (std::nothrow) gwn_mlp_s();
+    if (!h) return GWN_E_OOM;
+    struct Guard {
+        gwn_mlp_s* h;
+        ~Guard() { if (h) mlp_release(h); }
+    } guard{h};
+    gwn_status s = alloc_params(h);
+    if (s != GWN_OK) return s;
+    const unsigned char* p = buf.data() + sizeof(FileHeader);
+    auto dev = [&p](void* d, size_t n) -> hipError_t {
+        const hipError_t e = hipMemcpy(d, p, n, hipMemcpyHostToDevice);
+        p += n;
+        return e;
+    };
+    GWN_HIP_TRY(dev(h->d.G, sizeof(float) * 96));
+    GWN_HIP_TRY(dev(h->d.master, sizeof(float) * kNParams));
+    GWN_HIP_TRY(dev(h->d.m, sizeof(float) * kNParams));
+    GWN_HIP_TRY(dev(h->d.v, sizeof(float) * kNParams));
+    // the bf16 copies are a function of the masters: re-pack them and require
+    // the stored ones to agree, bit for bit
+    k_pack<<<(kNParams + 255) / 256, 256>>>(h->d);
     GWN_HIP_TRY(hipGetLastError());
+    std::vector<unsigned short> w((size_t)(kWf + kWb + kWi));
+    GWN_HIP_TRY(hipMemcpy(w.data(), h->d.wf, sizeof(unsigned short) * kWf, hipMemcpyDeviceToHost));
+    GWN_HIP_TRY(hipMemcpy(w.data() + kWf, h->d.wb, sizeof(unsigned short) * kWb, hipMemcpyDeviceToHost));
+    GWN_HIP_TRY(hipMemcpy(w.data() + kWf + kWb, h->d.wi, sizeof(unsigned short) * kWi, hipMemcpyDeviceToHost));
+    if (std::memcmp(w.data(), p, sizeof(unsigned short) * w.size()) != 0) {
+        set_error("gwn_surrogate_load: the bf16 weights in %s do not match its fp32 masters", path);
+        return GWN_E_INVALID;
+    }
+    h->step = hd.step;
+    h->epochs_done = hd.epochs_done;
+    h->sigma = hd.sigma;
+    h->init_seed = hd.init_seed;
+    h->recipe.seed = hd.data_seed;
+    h->recipe.n = hd.data_n;
+    h->recipe.mesh_nf = hd.mesh_nf;
+    h->recipe.mesh_nb = hd.mesh_nb;
+    for (int a = 0; a < 3; ++a) {
+        h->recipe.lo[a] = hd.box_lo[a];
+        h->recipe.hi[a] = hd.box_hi[a];
+    }
+    h->sched.epochs = hd.sched_epochs;
+    h->sched.batch = hd.sched_batch;
+    h->sched.lr = hd.sched_lr;
+    h->sched.lr_final = hd.sched_lr_final;
+    h->sched.external = hd.sched_external;
+    guard.h = nullptr;
+    *out = h;
     return GWN_OK;
 }
 
 gwn_status surrogate_query(gwn_mlp_s* h, const gwn_mesh_s* mesh, const float* qx, const float* qy, const float* qz,
-                           int64_t qs, int64_t n, float band, float* w, unsigned char* mask, int64_t* nfallback,
-                           hipStream_t st) {
+                           int64_t qs, int64_t n, float band, int rule, float* w, unsigned char* mask,
+                           int64_t* nfallback, hipStream_t st) {
     if (n == 0) {
         if (nfallback) *nfallback = 0;
         return GWN_OK;
@@ -835,9 +1325,10 @@ gwn_status surrogate_query(gwn_mlp_s* h, const gwn_mesh_s* mesh, const float* qx
     if (s != GWN_OK) return s;
     const unsigned nb = (unsigned)((n + 255) / 256);
     const long long seg = ((n + kBandBlocks - 1) / kBandBlocks + 255) / 256 * 256;
-    k_band_count<<<kBandBlocks, 256, 0, st>>>(w, n, seg, band, h->scratch_blk);
+    k_band_count<<<kBandBlocks, 256, 0, st>>>(w, n, seg, band, rule, h->scratch_blk);
     k_band_scan<<<1, kBandBlocks, 0, st>>>(h->scratch_blk, h->scratch_blk + kBandBlocks, h->scratch_cnt);
-    k_band_write<<<kBandBlocks, 256, 0, st>>>(w, n, seg, band, h->scratch_blk + kBandBlocks, h->scratch_idx, mask);
+    k_band_write<<<kBandBlocks, 256, 0, st>>>(w, n, seg, band, rule, h->scratch_blk + kBandBlocks, h->scratch_idx,
+                                              mask);
     k_gather<<<nb, 256, 0, st>>>(qx, qy, qz, qs, h->scratch_idx, h->scratch_cnt, h->scratch_q);
     GWN_HIP_TRY(hipGetLastError());
     // the fallback count sizes the exact evaluation (one synchronisation), which

@@ -447,10 +447,22 @@ def _target(T, Q):
     return T.to(torch.float32).contiguous()
 
 
+class SurrogateCfg(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_train", ctypes.c_int64), ("box_lo", ctypes.c_double * 3),
+                ("box_hi", ctypes.c_double * 3), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("lr_final", ctypes.c_float), ("stop_epoch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+BAND_HALF = 0   # |prediction - 1/2| < band
+BAND_FRAC = 1   # |frac(prediction) - 1/2| < band
+_RULE = {"half": BAND_HALF, "frac": BAND_FRAC, BAND_HALF: BAND_HALF, BAND_FRAC: BAND_FRAC}
+
+
 def _load_mlp(L):
     if getattr(L, "_mlp_ready", False):
         return
-    vp, i64, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float
+    vp, i64, i32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
     L.gwn_mlp_create.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(vp)]
     L.gwn_mlp_destroy.argtypes = [vp]
     L.gwn_mlp_get_state.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]
@@ -458,9 +470,16 @@ def _load_mlp(L):
     L.gwn_mlp_forward.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp]
     L.gwn_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, ctypes.POINTER(f32), vp]
     L.gwn_mlp_train_step.argtypes = [vp, vp, vp, vp, i64, vp, i64, f32, ctypes.POINTER(f32), vp]
-    L.gwn_surrogate_query.argtypes = [vp, vp, vp, vp, vp, i64, i64, f32, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
+    L.gwn_surrogate_query.argtypes = [vp, vp, vp, vp, vp, i64, i64, f32, i32, vp, vp, ctypes.POINTER(ctypes.c_int64),
+                                      vp]
+    L.gwn_surrogate_train.argtypes = [vp, vp, ctypes.POINTER(SurrogateCfg), vp, vp, i64, vp,
+                                      ctypes.POINTER(ctypes.c_int64), vp]
+    L.gwn_surrogate_save.argtypes = [vp, ctypes.c_char_p]
+    L.gwn_surrogate_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+    L.gwn_surrogate_destroy.argtypes = [vp]
     for f in ("gwn_mlp_create", "gwn_mlp_destroy", "gwn_mlp_get_state", "gwn_mlp_set_state", "gwn_mlp_forward",
-              "gwn_mlp_loss_grad", "gwn_mlp_train_step", "gwn_surrogate_query"):
+              "gwn_mlp_loss_grad", "gwn_mlp_train_step", "gwn_surrogate_query", "gwn_surrogate_train",
+              "gwn_surrogate_save", "gwn_surrogate_load", "gwn_surrogate_destroy"):
         getattr(L, f).restype = ctypes.c_int
     L._mlp_ready = True
 
@@ -468,11 +487,27 @@ def _load_mlp(L):
 class Surrogate:
     """Fourier-feature MLP trained and evaluated by the library's MFMA kernels."""
 
-    def __init__(self, seed: int = 0, sigma: float = 2.0):
+    def __init__(self, seed: int = 0, sigma: float = 2.0, _handle=None):
         L = load()
         _load_mlp(L)
+        if _handle is not None:
+            self._h = _handle
+            return
         self._h = ctypes.c_void_p()
         _check(L.gwn_mlp_create(int(seed), float(sigma), ctypes.byref(self._h)))
+
+    @classmethod
+    def load(cls, path: str) -> "Surrogate":
+        """A network restored from a checkpoint written by save() (gwn_surrogate_load)."""
+        L = load()
+        _load_mlp(L)
+        h = ctypes.c_void_p()
+        _check(L.gwn_surrogate_load(os.fsencode(path), ctypes.byref(h)))
+        return cls(_handle=h)
+
+    def save(self, path: str):
+        """The complete training state in the library's checkpoint format (gwn_surrogate_save)."""
+        _check(load().gwn_surrogate_save(self._h, os.fsencode(path)))
 
     def state(self) -> dict:
         import numpy as np
@@ -491,15 +526,37 @@ class Surrogate:
         p = {k: (arrs[k].ctypes.data if k in arrs else None) for k in ("theta", "m", "v", "G")}
         _check(load().gwn_mlp_set_state(self._h, p["theta"], p["m"], p["v"], p["G"], int(st.get("step", -1))))
 
-    def save(self, path: str):
+    def train(self, mesh, epochs: int, batch: int = 8192, lr: float = 2e-3, lr_final: float = 1e-4,
+              n_train: int = 0, seed: int = 0, box=None, X=None, T=None, stop_epoch: int = 0, stream=None):
+        """gwn_surrogate_train: mini-batch Adam with per-pass device shuffles and a cosine
+        learning rate, on n_train generated points labelled by the exact path (or on the
+        caller's points X (n, 3), with labels T or labelled on mesh).  Returns the mean
+        batch loss of each pass trained by this call."""
         import numpy as np
-        st = self.state()
-        np.savez(path, theta=st["theta"], m=st["m"], v=st["v"], G=st["G"], step=np.int64(st["step"]))
-
-    def load(self, path: str):
-        import numpy as np
-        with np.load(path, allow_pickle=False) as z:
-            self.load_state({"theta": z["theta"], "m": z["m"], "v": z["v"], "G": z["G"], "step": int(z["step"])})
+        L = load()
+        cfg = SurrogateCfg()
+        cfg.seed = int(seed)
+        cfg.n_train = int(n_train)
+        if box is not None:
+            for a in range(3):
+                cfg.box_lo[a] = float(box[0][a])
+                cfg.box_hi[a] = float(box[1][a])
+        cfg.epochs, cfg.batch, cfg.lr, cfg.lr_final = int(epochs), int(batch), float(lr), float(lr_final)
+        cfg.stop_epoch = int(stop_epoch)
+        n = 0
+        if X is not None:
+            X = _points(X, "X")
+            n = X.shape[0]
+            if T is not None:
+                T = _target(T, X)
+        elif T is not None:
+            raise ValueError("labels T need their points X")
+        losses = np.zeros(max(1, int(epochs)), np.float32)
+        ran = ctypes.c_int64(0)
+        _check(L.gwn_surrogate_train(self._h, mesh.handle if mesh is not None else None, ctypes.byref(cfg),
+                                     _ptr(X) if X is not None else None, _ptr(T) if T is not None else None, n,
+                                     losses.ctypes.data, ctypes.byref(ran), _stream(stream)))
+        return losses[:ran.value].tolist()
 
     def forward(self, Q, out=None, stream=None):
         import torch
@@ -530,8 +587,9 @@ class Surrogate:
                                          ctypes.byref(loss) if want_loss else None, _stream(stream)))
         return float(loss.value) if want_loss else None
 
-    def query(self, mesh: Mesh, Q, band: float, out=None, want_mask: bool = False, stream=None):
-        """Prediction, with exact re-evaluation where |prediction - 1/2| < band."""
+    def query(self, mesh: Mesh, Q, band: float, out=None, want_mask: bool = False, rule="half", stream=None):
+        """Prediction, with exact re-evaluation where the fallback rule holds: rule "half",
+        |prediction - 1/2| < band; rule "frac", |frac(prediction) - 1/2| < band."""
         import torch
         Q = _points(Q)
         n = Q.shape[0]
@@ -539,14 +597,14 @@ class Surrogate:
         mask = torch.empty(n, device=Q.device, dtype=torch.uint8) if want_mask else None
         nfb = ctypes.c_int64(0)
         b = _ptr(Q)
-        _check(load().gwn_surrogate_query(self._h, mesh.handle, b, b + 4, b + 8, 3, n, float(band), _ptr(out),
-                                          _ptr(mask) if mask is not None else None, ctypes.byref(nfb),
+        _check(load().gwn_surrogate_query(self._h, mesh.handle, b, b + 4, b + 8, 3, n, float(band), _RULE[rule],
+                                          _ptr(out), _ptr(mask) if mask is not None else None, ctypes.byref(nfb),
                                           _stream(stream)))
         return (out, mask, int(nfb.value)) if want_mask else (out, int(nfb.value))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
-            load().gwn_mlp_destroy(self._h)
+            load().gwn_surrogate_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):
@@ -554,31 +612,3 @@ class Surrogate:
             self.close()
         except Exception:
             pass
-
-
-def train_surrogate(sur: Surrogate, X, T, epochs: int = 4, batch: int = 8192, lr: float = 2e-3,
-                    lr_final: float = 1e-4, seed: int = 0, log=None):
-    """Mini-batch Adam over (X, T) with a cosine learning-rate decay; the
-    shuffling permutation comes from torch's seeded generator."""
-    import math
-
-    import torch
-    n = X.shape[0]
-    g = torch.Generator(device=X.device)
-    g.manual_seed(int(seed))
-    steps = epochs * ((n + batch - 1) // batch)
-    k = 0
-    losses = []
-    for ep in range(epochs):
-        perm = torch.randperm(n, device=X.device, generator=g)
-        for a in range(0, n, batch):
-            idx = perm[a:a + batch]
-            lr_k = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * k / max(1, steps - 1)))
-            want = (k % 200 == 0) or (k == steps - 1)
-            loss = sur.train_step(X[idx], T[idx], lr_k, want_loss=want)
-            if want:
-                losses.append((k, loss))
-                if log:
-                    log(f"step {k}/{steps} loss {loss:.4e} lr {lr_k:.2e}")
-            k += 1
-    return losses

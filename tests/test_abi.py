@@ -55,3 +55,20 @@ def test_status_strings_and_null_handle_errors():
     out = ctypes.c_void_p(1)
     assert L.gwn_build_mesh_opts(None, None, None, 1, 0, None, 0, ctypes.byref(opts), None, ctypes.byref(out)) == 1
     assert b"axis" in L.gwn_last_error()
+
+
+def test_surrogate_checkpoint_validation_on_the_host(tmp_path):
+    # gwn_surrogate_load checks the file before it touches the device
+    from paper_2605_01536_amd import gwn
+    L = gwn.load()
+    gwn._load_mlp(L)
+    h = ctypes.c_void_p(1)
+    assert L.gwn_surrogate_load(str(tmp_path / "missing").encode(), ctypes.byref(h)) == 1
+    assert h.value is None and b"cannot open" in L.gwn_last_error()
+    p = tmp_path / "junk.gwns"
+    p.write_bytes(b"GWNSURR1" + bytes(300))
+    assert L.gwn_surrogate_load(str(p).encode(), ctypes.byref(h)) == 1
+    assert b"not a version-1" in L.gwn_last_error()
+    assert L.gwn_surrogate_save(None, str(p).encode()) == 1
+    assert L.gwn_surrogate_train(None, None, None, None, None, 0, None, None, None) == 1
+    assert L.gwn_surrogate_destroy(None) == 0

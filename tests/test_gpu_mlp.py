@@ -65,30 +65,47 @@ def test_adam_step_matches_reference(gwn):
 
 
 def test_training_reduces_loss_on_winding_labels(gwn):
+    # caller points, labelled by the library on the mesh (gwn_surrogate_train)
     soup = W.opened_spheres(seed=41, n_surf=6, tris_per_surf=600)
     m = gwn.Mesh(torch.from_numpy(soup.V).cuda(), torch.from_numpy(soup.F).cuda())
     X = torch.rand((40000, 3), device="cuda") * 2 - 1
     T = gwn.query_batch(m, X)
     s = _sur(gwn, seed=7, sigma=1.5)
     l0, _ = s.loss_grad(X, T)
-    losses = gwn.train_surrogate(s, X, T, epochs=6, batch=4096, lr=3e-3, lr_final=3e-4)
+    losses = s.train(m, X=X, epochs=6, batch=4096, lr=3e-3, lr_final=3e-4)
+    assert len(losses) == 6
     l1, _ = s.loss_grad(X, T)
-    assert l1 < 0.2 * l0, (l0, l1, losses[-3:])
+    assert l1 < 0.2 * l0, (l0, l1, losses)
+    # the per-pass losses the library reports are the batch losses of that pass
+    assert losses[-1] < losses[0]
+
+
+def test_training_on_generated_points(gwn):
+    # the library draws the points in the mesh's box and labels them itself
+    soup = W.opened_spheres(seed=43, n_surf=4, tris_per_surf=600)
+    m = gwn.Mesh(torch.from_numpy(soup.V).cuda(), torch.from_numpy(soup.F).cuda())
+    s = _sur(gwn, seed=11, sigma=1.5)
+    losses = s.train(m, epochs=4, n_train=30000, batch=2048, lr=3e-3, lr_final=3e-4, seed=5)
+    assert len(losses) == 4 and losses[-1] < 0.5 * losses[0], losses
+    assert s.state()["step"] == 4 * ((30000 + 2047) // 2048)
+    # a handle that has trained passes under one recipe refuses another one
+    with pytest.raises(gwn.GwnError):
+        s.train(m, epochs=4, n_train=30000, batch=2048, lr=3e-3, lr_final=3e-4, seed=6)
 
 
 def test_checkpoint_resume_is_bit_identical(gwn, tmp_path):
+    # manual steps, saved and restored through gwn_surrogate_save / _load
     P = torch.from_numpy(_points(8192, 12)).cuda()
     t = torch.rand(8192, device="cuda")
     batches = [torch.arange(i * 1024, (i + 1) * 1024, device="cuda") for i in range(8)]
     a = _sur(gwn, seed=9)
     for i in range(4):
         a.train_step(P[batches[i]], t[batches[i]], 1e-3, want_loss=False)
-    path = str(tmp_path / "ckpt.npz")
+    path = str(tmp_path / "ckpt.gwns")
     a.save(path)
     for i in range(4, 8):
         a.train_step(P[batches[i]], t[batches[i]], 1e-3, want_loss=False)
-    b = _sur(gwn, seed=123)          # different init, overwritten by the checkpoint
-    b.load(path)
+    b = gwn.Surrogate.load(path)
     for i in range(4, 8):
         b.train_step(P[batches[i]], t[batches[i]], 1e-3, want_loss=False)
     sa, sb = a.state(), b.state()
@@ -98,21 +115,69 @@ def test_checkpoint_resume_is_bit_identical(gwn, tmp_path):
     assert torch.equal(a.forward(P), b.forward(P))
 
 
+def test_training_run_resumes_bit_identically(gwn, tmp_path):
+    # one uninterrupted gwn_surrogate_train run against the same run stopped after
+    # 3 of 6 passes, saved, loaded into a new handle and continued: the shuffles,
+    # learning rates, generated points and labels are re-made, so every bit agrees
+    soup = W.opened_spheres(seed=44, n_surf=3, tris_per_surf=500)
+    m = gwn.Mesh(torch.from_numpy(soup.V).cuda(), torch.from_numpy(soup.F).cuda())
+    cfg = dict(epochs=6, n_train=20000, batch=3000, lr=2e-3, lr_final=1e-4, seed=21)
+    a = _sur(gwn, seed=12)
+    la = a.train(m, **cfg)
+    b = _sur(gwn, seed=12)
+    lb1 = b.train(m, stop_epoch=3, **cfg)
+    path = str(tmp_path / "run.gwns")
+    b.save(path)
+    c = gwn.Surrogate.load(path)
+    del b
+    lc = c.train(m, **cfg)
+    assert len(lb1) == 3 and len(lc) == 3
+    assert la == lb1 + lc
+    sa, sc = a.state(), c.state()
+    for k in ("theta", "m", "v", "G"):
+        assert np.array_equal(sa[k], sc[k]), k
+    assert sa["step"] == sc["step"] == 6 * 7
+    assert c.train(m, **cfg) == []   # the schedule is complete
+
+
+def test_checkpoint_rejects_damaged_files(gwn, tmp_path):
+    a = _sur(gwn, seed=13)
+    path = tmp_path / "a.gwns"
+    a.save(str(path))
+    raw = bytearray(path.read_bytes())
+    bad = tmp_path / "bad.gwns"
+    raw[200] ^= 1                       # one bit inside the weights
+    bad.write_bytes(bytes(raw))
+    with pytest.raises(gwn.GwnError, match="checksum"):
+        gwn.Surrogate.load(str(bad))
+    bad.write_bytes(bytes(raw[:1000]))  # truncated
+    with pytest.raises(gwn.GwnError):
+        gwn.Surrogate.load(str(bad))
+    b = gwn.Surrogate.load(str(path))
+    P = torch.from_numpy(_points(999, 14)).cuda()
+    assert torch.equal(a.forward(P), b.forward(P))
+
+
 def test_band_query_matches_network_and_exact_path(gwn):
     soup = W.opened_spheres(seed=42, n_surf=5, tris_per_surf=800)
     m = gwn.Mesh(torch.from_numpy(soup.V).cuda(), torch.from_numpy(soup.F).cuda())
     X = torch.rand((20000, 3), device="cuda") * 2 - 1
-    T = gwn.query_batch(m, X)
     s = _sur(gwn, seed=8, sigma=1.5)
-    gwn.train_surrogate(s, X, T, epochs=3, batch=4096, lr=3e-3)
+    s.train(m, X=X, epochs=3, batch=4096, lr=3e-3)
     Q = torch.rand((30001, 3), device="cuda") * 2 - 1
     y = s.forward(Q)
     exact = gwn.query_batch(m, Q)
-    w0, mask0, n0 = s.query(m, Q, 0.0, want_mask=True)
-    assert n0 == 0 and torch.equal(w0, y) and int(mask0.sum()) == 0
-    wa, maska, na = s.query(m, Q, 1e9, want_mask=True)
-    assert na == Q.shape[0] and torch.equal(wa, exact)
-    w3, mask3, n3 = s.query(m, Q, 0.3, want_mask=True)
-    sel = (y - 0.5).abs() < 0.3
-    assert torch.equal(mask3.bool(), sel) and n3 == int(sel.sum())
-    assert torch.equal(w3[sel], exact[sel]) and torch.equal(w3[~sel], y[~sel])
+    for rule in ("half", "frac"):
+        w0, mask0, n0 = s.query(m, Q, 0.0, want_mask=True, rule=rule)
+        assert n0 == 0 and torch.equal(w0, y) and int(mask0.sum()) == 0
+        wa, maska, na = s.query(m, Q, 1e9, want_mask=True, rule=rule)
+        assert na == Q.shape[0] and torch.equal(wa, exact)
+        w3, mask3, n3 = s.query(m, Q, 0.3, want_mask=True, rule=rule)
+        d = (y - 0.5) if rule == "half" else (y - torch.floor(y) - 0.5)
+        sel = d.abs() < 0.3
+        assert torch.equal(mask3.bool(), sel) and n3 == int(sel.sum())
+        assert torch.equal(w3[sel], exact[sel]) and torch.equal(w3[~sel], y[~sel])
+    # the frac rule above 1/2 re-evaluates everything (at exactly 1/2 an integer
+    # prediction would keep its value)
+    wf, nf = s.query(m, Q, 0.5001, rule="frac")
+    assert nf == Q.shape[0] and torch.equal(wf, exact)
