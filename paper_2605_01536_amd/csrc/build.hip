@@ -3,8 +3,8 @@
 //   LBVH with integer boxes (Karras-style split search, bottom-up refit), and
 //   the directed boundary chain of the soup (Sec. 4.1: interior edges cancel),
 //   chained into closed loops so that the query kernels visit every boundary
-//   vertex once.  Sorting and scans use hipCUB; everything else is below.
-#include <hipcub/hipcub.hpp>
+//   vertex once.  Sorting and scans use the library's radix sort and scan
+//   (sort.hip); everything else is below.
 
 #include <algorithm>
 #include <chrono>
@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "gwn_mesh.h"
+#include "gwn_sort.h"
 
 namespace gwn {
 namespace {
@@ -445,15 +446,13 @@ __global__ void k_weld_tris(const int32_t* __restrict__ tri, int64_t n3, const i
     out[i] = remap[tri[i]];
 }
 
+// runs f(temp) with `bytes` of build scratch
 template <class F>
-hipError_t cub_call(Scratch& S, F&& f) {
-    size_t bytes = 0;
-    hipError_t e = f(nullptr, bytes);
+hipError_t with_temp(Scratch& S, size_t bytes, F&& f) {
+    char* tmp = nullptr;
+    hipError_t e = S.alloc(&tmp, (int64_t)bytes);
     if (e != hipSuccess) return e;
-    void* tmp = nullptr;
-    e = S.alloc((char**)&tmp, (int64_t)bytes);
-    if (e != hipSuccess) return e;
-    return f(tmp, bytes);
+    return f((void*)tmp);
 }
 
 int bits_for(int64_t n) {
@@ -570,18 +569,18 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
         GWN_HIP_TRY(hipMemsetAsync(nuq, 0, sizeof(int), st));
         k_weld_zkeys<<<nblocks(nv), kThreads, 0, st>>>(vz, vs, nv, kz, idx);
         GWN_HIP_TRY(hipGetLastError());
-        GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
-            return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kz, kz2, idx, idx2, (int)nv, 0, 32, st);
+        GWN_HIP_TRY(with_temp(S, sort_temp_bytes(nv, 4, true), [&](void* tmp) {
+            return radix_sort_u32(kz, kz2, idx, idx2, nv, 0, 32, tmp, st);
         }));
         k_weld_xykeys<<<nblocks(nv), kThreads, 0, st>>>(vx, vy, vs, nv, idx2, kxy);
         GWN_HIP_TRY(hipGetLastError());
-        GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
-            return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kxy, kxy2, idx2, idx3, (int)nv, 0, 64, st);
+        GWN_HIP_TRY(with_temp(S, sort_temp_bytes(nv, 8, true), [&](void* tmp) {
+            return radix_sort_u64(kxy, kxy2, idx2, idx3, nv, 0, 64, tmp, st);
         }));
         k_weld_heads<<<nblocks(nv), kThreads, 0, st>>>(vz, vs, nv, kxy2, idx3, head);
         GWN_HIP_TRY(hipGetLastError());
-        GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
-            return hipcub::DeviceScan::InclusiveScan(tmp, bytes, head, start, hipcub::Max(), (int)nv, st);
+        GWN_HIP_TRY(with_temp(S, scan_temp_bytes(nv), [&](void* tmp) {
+            return scan_inclusive_max(head, start, nv, tmp, st);
         }));
         k_weld_map<<<nblocks(nv), kThreads, 0, st>>>(idx3, start, nv, remap, nuq);
         GWN_HIP_TRY(hipGetLastError());
@@ -637,8 +636,11 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
         GWN_HIP_TRY(S.alloc(&keys2, nf));
         k_tri_setup<<<nblocks(nf), kThreads, 0, st>>>(tri, nf, qv, qlo, qspan, tq, keys);
         GWN_HIP_TRY(hipGetLastError());
-        GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
-            return hipcub::DeviceRadixSort::SortKeys(tmp, bytes, keys, keys2, (int)nf, 0, 62, st);
+        // the low 32 bits of a key are its triangle's index, i.e. its input
+        // position: a stable sort by the Morton code (bits 32..61) alone gives
+        // the order of a sort by the whole key
+        GWN_HIP_TRY(with_temp(S, sort_temp_bytes(nf, 8, false), [&](void* tmp) {
+            return radix_sort_u64(keys, keys2, nullptr, nullptr, nf, 32, 62, tmp, st);
         }));
         GWN_HIP_TRY(hipMalloc((void**)&m->tris, sizeof(TriQ) * (size_t)nf));
         GWN_HIP_TRY(hipMalloc((void**)&m->trif, sizeof(float4) * 3 * (size_t)nf));
@@ -690,13 +692,13 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
         GWN_HIP_TRY(S.alloc(&off, ne));
         k_edge_keys<<<nblocks(ne), kThreads, 0, st>>>(tri, nf, ek, es);
         GWN_HIP_TRY(hipGetLastError());
-        GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
-            return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, ek, ek2, es, es2, (int)ne, 0, 64, st);
+        GWN_HIP_TRY(with_temp(S, sort_temp_bytes(ne, 8, true), [&](void* tmp) {
+            return radix_sort_u64(ek, ek2, es, es2, ne, 0, 64, tmp, st);
         }));
         k_edge_runs<<<nblocks(ne), kThreads, 0, st>>>(ek2, es2, ne, net, cnt);
         GWN_HIP_TRY(hipGetLastError());
-        GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
-            return hipcub::DeviceScan::ExclusiveSum(tmp, bytes, cnt, off, (int)ne, st);
+        GWN_HIP_TRY(with_temp(S, scan_temp_bytes(ne), [&](void* tmp) {
+            return scan_exclusive_sum(cnt, off, ne, tmp, st);
         }));
         int last_off = 0, last_cnt = 0;
         GWN_HIP_TRY(hipMemcpyAsync(&last_off, off + ne - 1, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -716,13 +718,11 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
             GWN_HIP_TRY(hipGetLastError());
             k_iota<<<nblocks(nb), kThreads, 0, st>>>(ids, nb);
             const int vb = bits_for(nv);
-            GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
-                return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, (const unsigned*)eto, (unsigned*)kk, ids, in_by_to,
-                                                          (int)nb, 0, vb, st);
+            GWN_HIP_TRY(with_temp(S, sort_temp_bytes(nb, 4, true), [&](void* tmp) {
+                return radix_sort_u32((const uint32_t*)eto, (uint32_t*)kk, ids, in_by_to, nb, 0, vb, tmp, st);
             }));
-            GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
-                return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, (const unsigned*)efrom, (unsigned*)kk, ids,
-                                                          out_by_from, (int)nb, 0, vb, st);
+            GWN_HIP_TRY(with_temp(S, sort_temp_bytes(nb, 4, true), [&](void* tmp) {
+                return radix_sort_u32((const uint32_t*)efrom, (uint32_t*)kk, ids, out_by_from, nb, 0, vb, tmp, st);
             }));
             k_link<<<nblocks(nb), kThreads, 0, st>>>(in_by_to, out_by_from, nb, succ);
             GWN_HIP_TRY(hipGetLastError());
@@ -745,11 +745,11 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
             }
             GWN_HIP_TRY(hipGetLastError());
             k_loop_counts<<<nblocks(nb), kThreads, 0, st>>>(repA, dA, nb, len, head);
-            GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
-                return hipcub::DeviceScan::ExclusiveSum(tmp, bytes, len, voff, (int)nb, st);
+            GWN_HIP_TRY(with_temp(S, scan_temp_bytes(nb), [&](void* tmp) {
+                return scan_exclusive_sum(len, voff, nb, tmp, st);
             }));
-            GWN_HIP_TRY(cub_call(S, [&](void* tmp, size_t& bytes) {
-                return hipcub::DeviceScan::ExclusiveSum(tmp, bytes, head, lid, (int)nb, st);
+            GWN_HIP_TRY(with_temp(S, scan_temp_bytes(nb), [&](void* tmp) {
+                return scan_exclusive_sum(head, lid, nb, tmp, st);
             }));
             int last_lid = 0, last_head = 0;
             GWN_HIP_TRY(hipMemcpyAsync(&last_lid, lid + nb - 1, sizeof(int), hipMemcpyDeviceToHost, st));

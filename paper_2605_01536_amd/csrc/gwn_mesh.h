@@ -74,6 +74,10 @@ bool want_split(const gwn_mesh_s* m, int64_t n);
 bool want_xy_order(const gwn_mesh_s* m, int64_t n);
 gwn_status xy_order(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride, int64_t n,
                     int** perm, hipStream_t stream);
+// the same into caller memory: perm (n ints) and temp (xy_order_temp_bytes(n))
+size_t xy_order_temp_bytes(int64_t n);
+gwn_status xy_order_into(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                         int64_t n, int* perm, void* temp, hipStream_t stream);
 
 gwn_status query_grid_gradient(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims,
                                int prec, void* g_out, hipStream_t stream);

@@ -5,12 +5,11 @@
 // vertical: z does not matter) lets a wave walk the tree once, uniformly, for
 // all its lanes (k_chi_wave).  The order only permutes which lane handles which
 // point; every result is written to the point's own slot.
-#include <hipcub/hipcub.hpp>
-
 #include <cstdlib>
 
 #include "gwn_internal.h"
 #include "gwn_mesh.h"
+#include "gwn_sort.h"
 
 namespace gwn {
 namespace {
@@ -44,33 +43,45 @@ bool want_xy_order(const gwn_mesh_s* m, int64_t n) {
     return n >= (1 << 18) && m->nf >= (1 << 15);
 }
 
+size_t xy_order_temp_bytes(int64_t n) {
+    const size_t keys = (sizeof(uint32_t) * (size_t)n + 255) & ~(size_t)255;
+    const size_t idx = (sizeof(int) * (size_t)n + 255) & ~(size_t)255;
+    return 2 * keys + idx + sort_temp_bytes(n, 4, true);
+}
+
+gwn_status xy_order_into(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t n,
+                         int* perm, void* temp, hipStream_t st) {
+    const size_t keys = (sizeof(uint32_t) * (size_t)n + 255) & ~(size_t)255;
+    const size_t idx = (sizeof(int) * (size_t)n + 255) & ~(size_t)255;
+    char* p = (char*)temp;
+    uint32_t* k0 = (uint32_t*)p;
+    uint32_t* k1 = (uint32_t*)(p + keys);
+    int* i0 = (int*)(p + 2 * keys);
+    void* stmp = p + 2 * keys + idx;
+    k_xy_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(qx, qy, qz, qs, n, m->g, k0, i0);
+    GWN_HIP_TRY(hipGetLastError());
+    GWN_HIP_TRY(radix_sort_u32(k0, k1, i0, perm, n, 0, 32, stmp, st));
+    return GWN_OK;
+}
+
 gwn_status xy_order(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t n,
                     int** perm_out, hipStream_t st) {
     *perm_out = nullptr;
-    uint32_t *k0 = nullptr, *k1 = nullptr;
-    int *i0 = nullptr, *i1 = nullptr;
+    int* perm = nullptr;
     void* tmp = nullptr;
-    size_t bytes = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, k0, k1, i0, i1, (int)n, 0, 32, st);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&k0, sizeof(uint32_t) * (size_t)n, st);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&k1, sizeof(uint32_t) * (size_t)n, st);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&i0, sizeof(int) * (size_t)n, st);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&i1, sizeof(int) * (size_t)n, st);
-    if (e == hipSuccess) e = hipMallocAsync(&tmp, bytes, st);
-    if (e == hipSuccess) {
-        k_xy_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(qx, qy, qz, qs, n, m->g, k0, i0);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipcub::DeviceRadixSort::SortPairs(tmp, bytes, k0, k1, i0, i1, (int)n, 0, 32, st);
-    if (tmp) (void)hipFreeAsync(tmp, st);
-    if (k0) (void)hipFreeAsync(k0, st);
-    if (k1) (void)hipFreeAsync(k1, st);
-    if (i0) (void)hipFreeAsync(i0, st);
+    hipError_t e = hipMallocAsync((void**)&perm, sizeof(int) * (size_t)n, st);
+    if (e == hipSuccess) e = hipMallocAsync(&tmp, xy_order_temp_bytes(n), st);
     if (e != hipSuccess) {
-        if (i1) (void)hipFreeAsync(i1, st);
+        if (perm) (void)hipFreeAsync(perm, st);
         GWN_HIP_TRY(e);
     }
-    *perm_out = i1;
+    const gwn_status s = xy_order_into(m, qx, qy, qz, qs, n, perm, tmp, st);
+    (void)hipFreeAsync(tmp, st);
+    if (s != GWN_OK) {
+        (void)hipFreeAsync(perm, st);
+        return s;
+    }
+    *perm_out = perm;
     return GWN_OK;
 }
 

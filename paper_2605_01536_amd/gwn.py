@@ -612,3 +612,56 @@ class Surrogate:
             self.close()
         except Exception:
             pass
+
+
+def _load_prims(L):
+    if getattr(L, "_prims_ready", False):
+        return
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    for f in ("gwn_radix_sort_u32", "gwn_radix_sort_u64"):
+        getattr(L, f).argtypes = [vp, vp, vp, vp, i64, i32, i32, vp]
+        getattr(L, f).restype = ctypes.c_int
+    for f in ("gwn_scan_exclusive_sum_i32", "gwn_scan_inclusive_max_i32"):
+        getattr(L, f).argtypes = [vp, vp, i64, vp]
+        getattr(L, f).restype = ctypes.c_int
+    L._prims_ready = True
+
+
+def radix_sort(keys, vals=None, begin_bit: int = 0, end_bit: int | None = None, stream=None):
+    """Stable device sort of a 1-D CUDA tensor of uint32 or uint64 keys (given as int32 / int64
+    tensors, reinterpreted) by bits [begin_bit, end_bit); returns (sorted keys, payloads or None)."""
+    import torch
+    L = load()
+    _load_prims(L)
+    if not (isinstance(keys, torch.Tensor) and keys.is_cuda and keys.dim() == 1
+            and keys.dtype in (torch.int32, torch.int64)):
+        raise ValueError("keys must be a 1-D CUDA int32 or int64 tensor")
+    keys = keys.contiguous()
+    wide = keys.dtype == torch.int64
+    end_bit = (64 if wide else 32) if end_bit is None else end_bit
+    kout = torch.empty_like(keys)
+    vout = None
+    if vals is not None:
+        if not (isinstance(vals, torch.Tensor) and vals.is_cuda and vals.dtype == torch.int32
+                and vals.shape == keys.shape):
+            raise ValueError("vals must be a CUDA int32 tensor shaped like keys")
+        vals = vals.contiguous()
+        vout = torch.empty_like(vals)
+    f = L.gwn_radix_sort_u64 if wide else L.gwn_radix_sort_u32
+    _check(f(_ptr(keys), _ptr(kout), _ptr(vals) if vals is not None else None,
+             _ptr(vout) if vout is not None else None, keys.shape[0], int(begin_bit), int(end_bit), _stream(stream)))
+    return kout, vout
+
+
+def scan(x, op: str = "exclusive_sum", stream=None):
+    """Device prefix scan of a 1-D CUDA int32 tensor: "exclusive_sum" or "inclusive_max"."""
+    import torch
+    L = load()
+    _load_prims(L)
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dim() == 1 and x.dtype == torch.int32):
+        raise ValueError("x must be a 1-D CUDA int32 tensor")
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    f = {"exclusive_sum": L.gwn_scan_exclusive_sum_i32, "inclusive_max": L.gwn_scan_inclusive_max_i32}[op]
+    _check(f(_ptr(x), _ptr(out), x.shape[0], _stream(stream)))
+    return out
