@@ -144,6 +144,25 @@ gwn_status gwn_query_batch(gwn_mesh m, const float* qx, const float* qy, const f
                            int64_t nq, int32_t prec, void* w_out, int32_t* chi_out, void* stream);
 
 /*
+ * gwn_query_batch_noalloc -- gwn_query_batch for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The same kernels and the same results, bit for bit,
+ * as gwn_query_batch on the same points; no hipMalloc, hipFree or allocating
+ * call is made.  Its temporaries (a crossing-count buffer when chi_out is
+ * NULL, the traversal order of dense batches and that order's sort scratch)
+ * live in one fixed array of 29 MiB per GPU, held by the library on every GPU
+ * it runs on until the process ends.  That array is shared by every call on
+ * the GPU and keeps the last call's contents: calls that overlap on one GPU
+ * (other streams, other host threads) race and must be serialised by the
+ * caller.  At most GWN_NOALLOC_MAX_POINTS points per call; larger nq returns
+ * GWN_E_INVALID (split the batch).  Arguments and other errors as for
+ * gwn_query_batch.
+ */
+#define GWN_NOALLOC_MAX_POINTS 1048576
+gwn_status gwn_query_batch_noalloc(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                                   int64_t nq, int32_t prec, void* w_out, int32_t* chi_out, void* stream);
+
+/*
  * gwn_query_grid -- w on a cell-centred regular grid, reusing one ray per
  * (x, y) column for all its points (Sec. 4.3.1, ray reuse).
  *

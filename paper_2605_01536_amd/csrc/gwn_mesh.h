@@ -54,6 +54,19 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
 gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                        int64_t nq, int prec, void* w_out, int32_t* chi_out, hipStream_t stream);
 
+// Caller memory for the temporaries of one batch launch (see query_batch_ws).
+struct BatchWorkspace {
+    int* chi;           // nq ints: crossing counts when the caller passes no chi_out
+    int* perm;          // nq ints: the traversal order
+    void* order_temp;   // xy_order_temp_bytes(nq) bytes
+};
+
+// query_batch with its temporaries in ws (nullable: stream-ordered allocations);
+// with ws, nq must fit one launch (max_launch_queries()).
+gwn_status query_batch_ws(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qstride,
+                          int64_t nq, int prec, void* w_out, int32_t* chi_out, const BatchWorkspace* ws,
+                          hipStream_t stream);
+
 gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims,
                       int prec, void* w_out, int32_t* chi_out, hipStream_t stream);
 

@@ -334,11 +334,19 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && ZB == 8) || (sizeof(T) == 
     }
 }
 
+// ws (nullable): caller memory for the temporaries -- a crossing-count buffer
+// when chi_out is null, the traversal order and its sort's scratch -- for at
+// most one launch's worth of points; without it they are stream-ordered
+// allocations.
 template <class T>
 gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t nq,
-                        T* w, int32_t* chi_out, hipStream_t st) {
+                        T* w, int32_t* chi_out, const BatchWorkspace* ws, hipStream_t st) {
     int* chi = chi_out;
-    if (!chi) GWN_HIP_TRY(hipMallocAsync((void**)&chi, sizeof(int) * (size_t)nq, st));
+    if (!chi) {
+        if (ws) chi = ws->chi;
+        else GWN_HIP_TRY(hipMallocAsync((void**)&chi, sizeof(int) * (size_t)nq, st));
+    }
+    const bool own_chi = !chi_out && !ws;
     const MeshView mv = m->view();
     hipError_t e = hipSuccess;
     // one launch covers at most max_launch_queries() points (the 32-bit grid size)
@@ -347,9 +355,14 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
         const int64_t n = std::min<int64_t>(chunk, nq - o);
         const float *x = qx + o * qs, *y = qy + o * qs, *z = qz + o * qs;
         int* perm = nullptr;
-        if (want_xy_order(m, n) && xy_order(m, x, y, z, qs, n, &perm, st) != GWN_OK) {
-            if (!chi_out) (void)hipFreeAsync(chi, st);
-            return GWN_E_HIP;   // xy_order has set the message
+        if (want_xy_order(m, n)) {
+            const gwn_status so = ws ? xy_order_into(m, x, y, z, qs, n, ws->perm, ws->order_temp, st)
+                                     : xy_order(m, x, y, z, qs, n, &perm, st);
+            if (so != GWN_OK) {
+                if (own_chi) (void)hipFreeAsync(chi, st);
+                return so;   // the order has set the message
+            }
+            if (ws) perm = ws->perm;
         }
         if (perm) {
             k_chi_wave<true><<<(unsigned)((n + 64 * kGridWaves - 1) / (64 * kGridWaves)), 64 * kGridWaves, 0, st>>>(
@@ -367,9 +380,9 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
                                                                              w + o);
             e = hipGetLastError();
         }
-        if (perm) (void)hipFreeAsync(perm, st);
+        if (perm && !ws) (void)hipFreeAsync(perm, st);
     }
-    if (!chi_out) (void)hipFreeAsync(chi, st);
+    if (own_chi) (void)hipFreeAsync(chi, st);
     GWN_HIP_TRY(e);
     return GWN_OK;
 }
@@ -455,10 +468,19 @@ int64_t max_launch_queries() {
 
 gwn_status query_batch(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t nq,
                        int prec, void* w, int32_t* chi_out, hipStream_t st) {
+    return query_batch_ws(m, qx, qy, qz, qs, nq, prec, w, chi_out, nullptr, st);
+}
+
+gwn_status query_batch_ws(const gwn_mesh_s* m, const float* qx, const float* qy, const float* qz, int64_t qs,
+                          int64_t nq, int prec, void* w, int32_t* chi_out, const BatchWorkspace* ws, hipStream_t st) {
     if (nq == 0) return GWN_OK;
+    if (ws && nq > max_launch_queries()) {
+        set_error("query_batch: a workspace covers one launch of at most %lld points", (long long)max_launch_queries());
+        return GWN_E_INVALID;
+    }
     axis_ptrs(m->axis, qx, qy, qz);
-    if (prec == GWN_PREC_FP64) return launch_batch<double>(m, qx, qy, qz, qs, nq, (double*)w, chi_out, st);
-    return launch_batch<float>(m, qx, qy, qz, qs, nq, (float*)w, chi_out, st);
+    if (prec == GWN_PREC_FP64) return launch_batch<double>(m, qx, qy, qz, qs, nq, (double*)w, chi_out, ws, st);
+    return launch_batch<float>(m, qx, qy, qz, qs, nq, (float*)w, chi_out, ws, st);
 }
 
 gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims, int prec,

@@ -665,3 +665,28 @@ def scan(x, op: str = "exclusive_sum", stream=None):
     f = {"exclusive_sum": L.gwn_scan_exclusive_sum_i32, "inclusive_max": L.gwn_scan_inclusive_max_i32}[op]
     _check(f(_ptr(x), _ptr(out), x.shape[0], _stream(stream)))
     return out
+
+
+NOALLOC_MAX_POINTS = 1048576
+
+
+def query_batch_noalloc(mesh: Mesh, Q, prec="fp32", want_chi=False, out=None, chi_out=None, stream=None):
+    """gwn_query_batch_noalloc: query_batch with the library's fixed per-GPU scratch instead of
+    allocations (at most NOALLOC_MAX_POINTS points; calls overlapping on one GPU race)."""
+    import torch
+    L = load()
+    if not getattr(L, "_noalloc_ready", False):
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.gwn_query_batch_noalloc.argtypes = [vp, vp, vp, vp, i64, i64, i32, vp, vp, vp]
+        L.gwn_query_batch_noalloc.restype = ctypes.c_int
+        L._noalloc_ready = True
+    p = _PREC[prec]
+    Q = _points(Q)
+    n = Q.shape[0]
+    out = _out(out, (n,), _wdtype(p), Q.device, "out")
+    if want_chi or chi_out is not None:
+        chi_out = _out(chi_out, (n,), torch.int32, Q.device, "chi_out")
+    base = _ptr(Q)
+    _check(L.gwn_query_batch_noalloc(mesh.handle, base, base + 4, base + 8, 3, n, p, _ptr(out),
+                                     _ptr(chi_out) if chi_out is not None else None, _stream(stream)))
+    return (out, chi_out) if want_chi else out
