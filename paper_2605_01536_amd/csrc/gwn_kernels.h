@@ -30,6 +30,7 @@ namespace gwn {
 namespace {
 
 constexpr double kInv2Pi = 0.15915494309189533576888376337251;  // 1 / (2 pi)
+constexpr double k2Pi = 6.283185307179586476925286766559;         // 2 pi
 
 // atan(t) for |t| <= 1 as t + t x Q(x), x = t^2, Q of degree 7 fitted by the
 // Remez exchange for minimax relative error (gen_atan_poly.py: 1.7e-8 in exact
@@ -501,7 +502,11 @@ __device__ __forceinline__ void col_fill(const MeshView& mv, int v0, int n, int 
                                          unsigned long long& mk) {
     using P = EdgePairs<T, ZB, false>;
     constexpr T u = (T)P::kUnit;
-    const int lane = (int)(threadIdx.x & 63);
+    int lane = (int)(threadIdx.x & 63);
+    // Opaque to the optimiser (no instruction is emitted): the ring addresses
+    // derived from the lane are then formed here, once per fill, instead of
+    // being hoisted out of the boundary loops and held (or spilled) throughout.
+    asm volatile("" : "+v"(lane));
     bool e = false;
     int R = 0;
     if (lane < n) {

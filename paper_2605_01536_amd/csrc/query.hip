@@ -1,6 +1,6 @@
-// query.hip -- single-mesh query kernels: crossing counts for arbitrary
-// points, the boundary term per point, and the grid kernel with one ray per
-// column (the arithmetic lives in gwn_kernels.h).
+// query.hip -- single-mesh query kernels for arbitrary points: crossing counts
+// and the boundary term per point (the arithmetic lives in gwn_kernels.h; the
+// grid kernel with one ray per column is in grid.hip).
 #include <cmath>
 #include <cstdlib>
 #include <type_traits>
@@ -217,123 +217,6 @@ __global__ __launch_bounds__(kSplitThreads) void k_bdry_split(MeshView mv, const
     }
 }
 
-// ---------------------------------------------------------------- grid (ray reuse)
-
-
-// FP32 with 8 samples per lane and FP64 with 4 are held to 128 VGPRs (4 waves
-// per SIMD), a few spilled registers outside the edge loop cost less than the
-// fourth wave gains.
-// One wave owns one (x, y) column and a chunk of 64*ZB consecutive z samples;
-// lane l holds samples l, l+64, ..., l+64(ZB-1) of the chunk, so each of its ZB
-// registers covers a block of 64 consecutive samples (most boundary vertices
-// lie wholly above or below a block, see load_vertex).  The column's line is
-// cast once (all lanes walk the same BVH path) and every crossing is classified
-// against each sample with the exact plane predicate (Sec. 4.3.1, ray reuse).
-template <class T, int ZB>
-__global__ __launch_bounds__(64 * kGridWaves)
-__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && ZB == 8) || (sizeof(T) == 8 && ZB == 4) ? 4 : 1))) void k_grid(MeshView mv, GridArgs ga, int* __restrict__ chi_out,
-                                                          T* __restrict__ w) {
-    __shared__ int wstack[kGridWaves][kLdsStack];
-    __shared__ ColRing<T> ring[kGridWaves];
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const long long gw = ga.wave0 + (long long)blockIdx.x * kGridWaves + wave;
-    if (gw >= ga.nwaves) return;
-    const long long col = gw / ga.nchunks;
-    const long long chunk = gw - col * ga.nchunks;
-    const long long ci = col / ga.ny, cj = col - ci * ga.ny;
-    const float px = grid_coord(ga.o[0], ga.s[0], ci);
-    const float py = grid_coord(ga.o[1], ga.s[1], cj);
-    const long long k0 = chunk * 64 * ZB + lane;   // sample r is k0 + 64 r
-
-    float pz[ZB];
-    int qzr[ZB];
-    int chi[ZB];
-    const QPoint q0 = quantize_point(px, py, 0.0f, mv.g);
-#pragma unroll
-    for (int r = 0; r < ZB; ++r) {
-        pz[r] = grid_coord(ga.o[2], ga.s[2], min(k0 + 64 * r, ga.nz - 1));
-        qzr[r] = quantize_point(px, py, pz[r], mv.g).z;
-        chi[r] = 0;
-    }
-
-    // ---- crossings along the column's vertical line, classified per sample
-    if (q0.inbox && mv.root != kNoRoot) {
-        int* stk = wstack[wave];
-        int node = mv.root;
-        int sp = 0;
-        const bool leaf_only = node < 0;
-        while (true) {
-            int hits[2];
-            int nh = 0;
-            if (leaf_only) {
-                hits[nh++] = ~node;
-            } else {
-                const Node nd = mv.nodes[node];
-                bool hl = box_has_xy(nd.lxy.x, nd.lxy.y, nd.lxy.z, nd.lxy.w, q0.x, q0.y);
-                bool hr = box_has_xy(nd.rxy.x, nd.rxy.y, nd.rxy.z, nd.rxy.w, q0.x, q0.y);
-                const int L = nd.link.x, R = nd.link.y;
-                if (hl && L < 0) { hits[nh++] = ~L; hl = false; }
-                if (hr && R < 0) { hits[nh++] = ~R; hr = false; }
-                if (hl && hr) { stk[sp++] = R; node = L; }
-                else if (hl) node = L;
-                else if (hr) node = R;
-                else node = -1;
-            }
-            for (int h = 0; h < nh; ++h) {
-                const TriQ t = mv.tris[hits[h]];
-                const int s = tri_xy_sign(t, q0.x, q0.y);
-                if (s == 0) continue;
-                const PlaneQ pl = plane_of(t, q0.x, q0.y);
-#pragma unroll
-                for (int r = 0; r < ZB; ++r) chi[r] += plane_above(pl, qzr[r]) ? s : 0;
-            }
-            if (leaf_only) break;
-            if (node < 0) {
-                if (sp == 0) break;
-                node = stk[--sp];
-            }
-        }
-    }
-
-    // ---- boundary term
-    T pzs[ZB];
-    double S[ZB];
-    if (q0.inbox) {
-        const T sc = (T)mv.g.scale;
-        bool near = true;
-#pragma unroll
-        for (int r = 0; r < ZB; ++r) {
-            pzs[r] = (T)pz[r] * sc;
-            S[r] = 0.0;
-            near &= near_z(pz[r], mv.g);
-        }
-        near = __builtin_amdgcn_ballot_w64(!near) == 0ull;   // one choice for the whole column
-        column_loops<T, ZB>(mv, q0.x, q0.y, pzs, S, near, ring[wave]);
-    } else {
-        float pzm = 0.f;
-#pragma unroll
-        for (int r = 0; r < ZB; ++r) pzm = fmaxf(pzm, fabsf(pz[r]));
-        const FarScale<T> fs = far_scale<T>(px, py, pzm, mv.g.scale);
-#pragma unroll
-        for (int r = 0; r < ZB; ++r) {
-            pzs[r] = (T)pz[r] * fs.scf;
-            S[r] = 0.0;
-        }
-        boundary_loops<T, ZB, true>(mv, 0, 0, (T)px * fs.scf, (T)py * fs.scf, pzs, S, fs.f);
-    }
-
-    const long long base = ci * ga.st[0] + cj * ga.st[1];
-#pragma unroll
-    for (int r = 0; r < ZB; ++r) {
-        const long long k = k0 + 64 * r;
-        if (k < ga.nz) {
-            w[base + k * ga.st[2]] = (T)((double)chi[r] + S[r] * kInv2Pi);
-            if (chi_out) chi_out[base + k * ga.st[2]] = chi[r];
-        }
-    }
-}
-
 // ws (nullable): caller memory for the temporaries -- a crossing-count buffer
 // when chi_out is null, the traversal order and its sort's scratch -- for at
 // most one launch's worth of points; without it they are stream-ordered
@@ -385,42 +268,6 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
     if (own_chi) (void)hipFreeAsync(chi, st);
     GWN_HIP_TRY(e);
     return GWN_OK;
-}
-
-template <class T, int ZB>
-gwn_status launch_grid_zb(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out, hipStream_t st) {
-    ga.nchunks = (ga.nz + 64 * ZB - 1) / (64 * ZB);
-    ga.nwaves = ga.nx * ga.ny * ga.nchunks;
-    // at most 2^24 waves (2^30 work-items) per launch
-    const long long kMaxWaves = max_launch_queries() / 64;
-    for (long long w0 = 0; w0 < ga.nwaves; w0 += kMaxWaves) {
-        ga.wave0 = w0;
-        const long long blocks = (std::min(kMaxWaves, ga.nwaves - w0) + kGridWaves - 1) / kGridWaves;
-        k_grid<T, ZB><<<(unsigned)blocks, 64 * kGridWaves, 0, st>>>(m->view(), ga, chi_out, w);
-        GWN_HIP_TRY(hipGetLastError());
-    }
-    return GWN_OK;
-}
-
-// Samples per lane: more samples share more x/y work, fewer leave registers for
-// more resident waves.  GWN_GRID_SAMPLES_PER_LANE (1, 2, 4 or 8) overrides the
-// default choice, which is the largest value the column length fills.
-template <class T>
-gwn_status launch_grid(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out, hipStream_t st) {
-    if (const char* e = std::getenv("GWN_GRID_SAMPLES_PER_LANE")) {
-        switch (std::atoi(e)) {
-            case 1: return launch_grid_zb<T, 1>(m, ga, w, chi_out, st);
-            case 2: return launch_grid_zb<T, 2>(m, ga, w, chi_out, st);
-            case 4: return launch_grid_zb<T, 4>(m, ga, w, chi_out, st);
-            case 8: return launch_grid_zb<T, 8>(m, ga, w, chi_out, st);
-            default: break;
-        }
-    }
-    // FP64 keeps at most 4 samples per lane (8 would need ~200 VGPRs)
-    if (ga.nz >= 64 * 8 && sizeof(T) == 4) return launch_grid_zb<T, 8>(m, ga, w, chi_out, st);
-    if (ga.nz >= 64 * 4) return launch_grid_zb<T, 4>(m, ga, w, chi_out, st);
-    if (ga.nz >= 64 * 2) return launch_grid_zb<T, 2>(m, ga, w, chi_out, st);
-    return launch_grid_zb<T, 1>(m, ga, w, chi_out, st);
 }
 
 }  // namespace
@@ -481,14 +328,6 @@ gwn_status query_batch_ws(const gwn_mesh_s* m, const float* qx, const float* qy,
     axis_ptrs(m->axis, qx, qy, qz);
     if (prec == GWN_PREC_FP64) return launch_batch<double>(m, qx, qy, qz, qs, nq, (double*)w, chi_out, ws, st);
     return launch_batch<float>(m, qx, qy, qz, qs, nq, (float*)w, chi_out, ws, st);
-}
-
-gwn_status query_grid(const gwn_mesh_s* m, const double* origin, const double* spacing, const int64_t* dims, int prec,
-                      void* w, int32_t* chi_out, hipStream_t st) {
-    GridArgs ga = frame_grid(m->axis, origin, spacing, dims);
-    if (ga.nx == 0 || ga.ny == 0 || ga.nz == 0) return GWN_OK;
-    if (prec == GWN_PREC_FP64) return launch_grid<double>(m, ga, (double*)w, chi_out, st);
-    return launch_grid<float>(m, ga, (float*)w, chi_out, st);
 }
 
 }  // namespace gwn
