@@ -156,6 +156,18 @@ def grid_slots(soup, grid, prec):
     return dense - SKIP_SLOTS[prec] * above - SKIP_SEL_SLOTS[prec] * below, float(above), float(below)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,10 +300,26 @@ def main():
         far = oracle.distance(soup.V, soup.F, P[:mc], 2e-4 * diag) > 1e-4 * diag
         wg = w[torch.from_numpy(idx[:mc]).cuda()].double().cpu().numpy()
         err = float(np.abs(wg - w_o[:mc])[far].max())
+        # the direct sum (O1: Eq. 2 with Eq. 6, double-double) on a subsample sized to
+        # a few seconds, reported as triangle evaluations per second
+        t = time.perf_counter()
+        oracle.direct(soup.V, soup.F, W.grid_points(grid, idx[:64]))
+        per_pt = max((time.perf_counter() - t) / 64, 1e-9)
+        m1 = int(max(64, min(10_000, 0.5 * args.cpu_seconds / per_pt)))
+        t = time.perf_counter()
+        w_d = oracle.direct(soup.V, soup.F, P[:m1])
+        o1_s = time.perf_counter() - t
+        o1_far = far[:m1] if m1 <= mc else oracle.distance(soup.V, soup.F, P[:m1], 2e-4 * diag) > 1e-4 * diag
         cpu = {"value": m / cpu_s, "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"{m} random points of the same grid, FP64 antipodal oracle, {cpu_s:.1f} s",
-               "max_abs_err_vs_gpu": err, "n_compared": int(far.sum())}
-        print(f"[bench] oracle {m / cpu_s:.3e} q/s on {cpu['cores']} threads; max|err| {err:.2e}",
+               "max_abs_err_vs_gpu": err, "n_compared": int(far.sum()),
+               "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+               "direct_sum": {"kind": "oracle O1 (direct solid-angle sum, double-double)", "points": m1,
+                              "seconds": o1_s, "triangle_evals_per_s": m1 * float(soup.F.shape[0]) / o1_s,
+                              "queries_per_s": m1 / o1_s, "threads": oracle.num_threads(),
+                              "max_abs_diff_vs_antipodal_oracle": float(np.abs(w_d - w_o[:m1])[o1_far].max())}}
+        print(f"[bench] oracle {m / cpu_s:.3e} q/s on {cpu['cores']} threads of {cpu['nproc']} ({cpu['cpu_model']}); "
+              f"max|err| {err:.2e}; direct sum {cpu['direct_sum']['triangle_evals_per_s']:.3e} triangle evals/s",
               file=sys.stderr, flush=True)
 
     out = {

@@ -62,11 +62,26 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def build_sanitized(path: str) -> str:
+    """Compile the oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (any undefined behaviour aborts) into `path`; load it by setting
+    GWN_ORACLE_LIB=path in a process started with the sanitizer runtimes
+    preloaded (LD_PRELOAD)."""
+    cmd = ["gcc", "-O1", "-g", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+           _SRC, _SRC_PARAM, "-o", path, "-lquadmath", "-lm"]
+    subprocess.run(cmd, check=True)
+    return path
+
+
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        path = os.environ.get("GWN_ORACLE_LIB")
+        if not path:
+            build()
+            path = _LIB
+        L = ctypes.CDLL(path)
         L.oracle_quant_params.argtypes = [_F32, _i64, _F64, _F64, ctypes.POINTER(_i32)]
         L.oracle_quantize.argtypes = [_F32, _i64, _F64, _i32, _I64, _U8]
         L.oracle_orient2d_sos.argtypes = [_i64] * 6

@@ -60,5 +60,41 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+# AddressSanitizer and UndefinedBehaviorSanitizer on the host code only (every
+# flag behind -Xarch_host: the device code is built as usual); for running the
+# host-side checks (argument validation, handle lifetime, checkpoint parsing)
+# on the CPU with the clang sanitizer runtime preloaded.
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_host_sanitized(out: str, verbose: bool = False) -> str:
+    """The library with sanitized host code, linked against clang's shared
+    sanitizer runtime (which the loading process must preload), into `out`."""
+    obj = os.path.join(ROOT, "_build", "obj_hostsan")
+    os.makedirs(obj, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+    def one(src):
+        o = os.path.join(obj, os.path.basename(src) + ".o")
+        cmd = [HIPCC, *[f for f in CFLAGS if f != "-O3"], "-O1", "-g", *SAN_HOST,
+               *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", o]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        return o
+
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(one, srcs))
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out,
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host", "-shared-libsan"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    if verbose:
+        print(f"built {out} (host code sanitized)", file=sys.stderr)
+    return out
+
+
 if __name__ == "__main__":
     build()

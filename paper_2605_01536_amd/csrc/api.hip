@@ -2,11 +2,14 @@
 // validation, handle lifetime and thread-local error reporting.  All compute
 // happens in the kernels of the other sources (build, query, grad, direct,
 // order, multi, mlp).
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cmath>
 #include <new>
 
+#include "../../include/gwn_test.h"
+#include "gwn_alloc.h"
 #include "gwn_mesh.h"
 
 namespace gwn {
@@ -21,6 +24,38 @@ void set_error(const char* fmt, ...) {
 }
 
 void clear_error() { g_err[0] = 0; }
+
+// ---- device allocations and the allocation-failure hook (include/gwn_test.h)
+namespace {
+std::atomic<long long> g_alloc_budget{-1};   // < 0: no failures; else allocations left before they fail
+std::atomic<long long> g_alloc_count{0};
+
+bool take_alloc() {
+    g_alloc_count.fetch_add(1, std::memory_order_relaxed);
+    long long b = g_alloc_budget.load(std::memory_order_relaxed);
+    while (b >= 0) {
+        if (b == 0) return false;
+        if (g_alloc_budget.compare_exchange_weak(b, b - 1, std::memory_order_relaxed)) return true;
+    }
+    return true;
+}
+}  // namespace
+
+hipError_t dmalloc(void** p, size_t bytes) {
+    if (!take_alloc()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+hipError_t dmalloc_async(void** p, size_t bytes, hipStream_t st) {
+    if (!take_alloc()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMallocAsync(p, bytes, st);
+}
 
 }  // namespace gwn
 
@@ -52,6 +87,11 @@ gwn_status check_mesh(gwn_mesh m, const char* fn) {
 }  // namespace
 
 extern "C" {
+
+int64_t gwn_test_fail_alloc_after(int64_t n) {
+    gwn::g_alloc_budget.store(n < 0 ? -1 : n);
+    return gwn::g_alloc_count.exchange(0);
+}
 
 gwn_status gwn_build_mesh(const float* vx, const float* vy, const float* vz, int64_t vstride, int64_t nv,
                           const int32_t* tri, int64_t nf, void* stream, gwn_mesh* out) {

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <vector>
 
+#include "gwn_alloc.h"
 #include "gwn_mesh.h"
 #include "gwn_sort.h"
 
@@ -27,15 +28,20 @@ inline int nblocks(int64_t n, int t = kThreads) {
 
 // ------------------------------------------------------------------ helpers
 
+// Build temporaries, released when the build returns -- also on an error path,
+// where kernels enqueued before the failure may still be running: the stream is
+// drained first.
 struct Scratch {
     std::vector<void*> ptrs;
+    hipStream_t st = nullptr;
     ~Scratch() {
+        if (!ptrs.empty()) (void)hipStreamSynchronize(st);
         for (void* p : ptrs) (void)hipFree(p);
     }
     template <class T>
     hipError_t alloc(T** p, int64_t n) {
         *p = nullptr;
-        hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+        hipError_t e = gwn::dmalloc((void**)p, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
         if (e == hipSuccess) ptrs.push_back(*p);
         return e;
     }
@@ -487,6 +493,7 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
                       int64_t nf, bool weld, int axis, hipStream_t st, gwn_mesh_s* m) {
     auto t0 = std::chrono::steady_clock::now();
     Scratch S;
+    S.st = st;
     int loop_tail = 0;
     m->nv = nv;
     m->nf = nf;
@@ -642,13 +649,13 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
         GWN_HIP_TRY(with_temp(S, sort_temp_bytes(nf, 8, false), [&](void* tmp) {
             return radix_sort_u64(keys, keys2, nullptr, nullptr, nf, 32, 62, tmp, st);
         }));
-        GWN_HIP_TRY(hipMalloc((void**)&m->tris, sizeof(TriQ) * (size_t)nf));
-        GWN_HIP_TRY(hipMalloc((void**)&m->trif, sizeof(float4) * 3 * (size_t)nf));
+        GWN_HIP_TRY(gwn::dmalloc((void**)&m->tris, sizeof(TriQ) * (size_t)nf));
+        GWN_HIP_TRY(gwn::dmalloc((void**)&m->trif, sizeof(float4) * 3 * (size_t)nf));
         k_permute_tris<<<nblocks(nf), kThreads, 0, st>>>(keys2, nf, tq, m->tris, tri, vx, vy, vz, vs, m->trif);
         GWN_HIP_TRY(hipGetLastError());
         if (nf >= 2) {
             m->nnodes = nf - 1;
-            GWN_HIP_TRY(hipMalloc((void**)&m->nodes, sizeof(Node) * (size_t)(nf - 1)));
+            GWN_HIP_TRY(gwn::dmalloc((void**)&m->nodes, sizeof(Node) * (size_t)(nf - 1)));
             GWN_HIP_TRY(hipMemsetAsync(m->nodes, 0xff, sizeof(Node) * (size_t)(nf - 1), st));
             int *leaf_parent = nullptr, *rflags = nullptr, *depth = nullptr;
             GWN_HIP_TRY(S.alloc(&leaf_parent, nf));
@@ -756,8 +763,8 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
             GWN_HIP_TRY(hipMemcpyAsync(&last_head, head + nb - 1, sizeof(int), hipMemcpyDeviceToHost, st));
             GWN_HIP_TRY(hipStreamSynchronize(st));
             m->nloops = (int64_t)last_lid + last_head;
-            GWN_HIP_TRY(hipMalloc((void**)&m->bverts, sizeof(BVert) * (size_t)nb));
-            GWN_HIP_TRY(hipMalloc((void**)&m->loop_off, sizeof(int) * (size_t)(m->nloops + 1)));
+            GWN_HIP_TRY(gwn::dmalloc((void**)&m->bverts, sizeof(BVert) * (size_t)nb));
+            GWN_HIP_TRY(gwn::dmalloc((void**)&m->loop_off, sizeof(int) * (size_t)(m->nloops + 1)));
             k_emit_loops<<<nblocks(nb), kThreads, 0, st>>>(efrom, repA, dA, voff, lid, nb, vx, vy, vz, vs, qv, g.scalef,
                                                           m->bverts, m->loop_off);
             GWN_HIP_TRY(hipGetLastError());
@@ -766,7 +773,7 @@ gwn_status build_mesh(const float* vx, const float* vy, const float* vz, int64_t
         }
     }
     if (!m->loop_off) {
-        GWN_HIP_TRY(hipMalloc((void**)&m->loop_off, sizeof(int)));
+        GWN_HIP_TRY(gwn::dmalloc((void**)&m->loop_off, sizeof(int)));
         GWN_HIP_TRY(hipMemsetAsync(m->loop_off, 0, sizeof(int), st));
     }
     GWN_HIP_TRY(hipStreamSynchronize(st));

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "gwn_alloc.h"
 #include "gwn_kernels.h"
 #include "gwn_mesh.h"
 
@@ -99,7 +100,7 @@ gwn_status launch_direct(const gwn_mesh_s* m, const float* qx, const float* qy, 
     const int nslice = (int)std::min<long long>(std::min(want, maxs), 64);
     const long long per = ((m->nf + nslice - 1) / nslice + kDirBlock - 1) / kDirBlock * kDirBlock;
     double* part = nullptr;
-    if (nslice > 1) GWN_HIP_TRY(hipMallocAsync((void**)&part, sizeof(double) * (size_t)nslice * (size_t)nq, st));
+    if (nslice > 1) GWN_HIP_TRY(gwn::dmalloc_async((void**)&part, sizeof(double) * (size_t)nslice * (size_t)nq, st));
     dim3 grid((unsigned)qblocks, (unsigned)nslice);
     k_direct<T><<<grid, kDirBlock, 0, st>>>(m->trif, m->nf, per, qx, qy, qz, qs, nq, w, part);
     hipError_t e = hipGetLastError();

@@ -21,6 +21,7 @@
 #include <string>
 #include <vector>
 
+#include "gwn_alloc.h"
 #include "gwn_kernels.h"
 #include "gwn_mesh.h"
 
@@ -766,23 +767,25 @@ void free_train(gwn_mlp_s* h) {
 
 gwn_status ensure_train(gwn_mlp_s* h, long long n) {
     if (h->t.cap >= n) return GWN_OK;
+    if (h->t.x) (void)hipDeviceSynchronize();   // earlier steps may still use the buffers
     free_train(h);
     const long long cap = std::max<long long>(n, 1024);
     const long long nchunk = (cap + kChunk - 1) / kChunk;
-    GWN_HIP_TRY(hipMalloc((void**)&h->t.x, sizeof(unsigned short) * 5 * cap * 128));
-    GWN_HIP_TRY(hipMalloc((void**)&h->t.z, sizeof(float) * 4 * cap * 128));
-    GWN_HIP_TRY(hipMalloc((void**)&h->t.dz, sizeof(unsigned short) * 4 * cap * 128));
-    GWN_HIP_TRY(hipMalloc((void**)&h->t.y, sizeof(float) * cap));
-    GWN_HIP_TRY(hipMalloc((void**)&h->t.dy, sizeof(float) * cap));
-    GWN_HIP_TRY(hipMalloc((void**)&h->t.tb, sizeof(float) * cap));
-    GWN_HIP_TRY(hipMalloc((void**)&h->t.part, sizeof(float) * nchunk * (kNParams + 1)));
-    GWN_HIP_TRY(hipMalloc((void**)&h->t.grad, sizeof(float) * (kNParams + 1)));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.x, sizeof(unsigned short) * 5 * cap * 128));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.z, sizeof(float) * 4 * cap * 128));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.dz, sizeof(unsigned short) * 4 * cap * 128));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.y, sizeof(float) * cap));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.dy, sizeof(float) * cap));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.tb, sizeof(float) * cap));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.part, sizeof(float) * nchunk * (kNParams + 1)));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.grad, sizeof(float) * (kNParams + 1)));
     h->t.cap = cap;
     return GWN_OK;
 }
 
 gwn_status ensure_scratch(gwn_mlp_s* h, long long n) {
     if (h->scratch_cap >= n) return GWN_OK;
+    if (h->scratch_w) (void)hipDeviceSynchronize();   // an earlier query may still use the buffers
     (void)hipFree(h->scratch_w);
     (void)hipFree(h->scratch_q);
     (void)hipFree(h->scratch_idx);
@@ -793,26 +796,27 @@ gwn_status ensure_scratch(gwn_mlp_s* h, long long n) {
     h->scratch_chi = nullptr;
     h->scratch_cap = 0;
     const long long cap = std::max<long long>(n, 1024);
-    GWN_HIP_TRY(hipMalloc((void**)&h->scratch_w, sizeof(float) * cap));
-    GWN_HIP_TRY(hipMalloc((void**)&h->scratch_q, sizeof(float) * 3 * cap));
-    GWN_HIP_TRY(hipMalloc((void**)&h->scratch_idx, sizeof(long long) * cap));
-    GWN_HIP_TRY(hipMalloc((void**)&h->scratch_chi, sizeof(int) * cap));
-    if (!h->scratch_cnt) GWN_HIP_TRY(hipMalloc((void**)&h->scratch_cnt, sizeof(int)));
-    if (!h->scratch_blk) GWN_HIP_TRY(hipMalloc((void**)&h->scratch_blk, sizeof(int) * 2 * kBandBlocks));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->scratch_w, sizeof(float) * cap));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->scratch_q, sizeof(float) * 3 * cap));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->scratch_idx, sizeof(long long) * cap));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->scratch_chi, sizeof(int) * cap));
+    if (!h->scratch_cnt) GWN_HIP_TRY(gwn::dmalloc((void**)&h->scratch_cnt, sizeof(int)));
+    if (!h->scratch_blk) GWN_HIP_TRY(gwn::dmalloc((void**)&h->scratch_blk, sizeof(int) * 2 * kBandBlocks));
     h->scratch_cap = cap;
     return GWN_OK;
 }
 
 gwn_status ensure_data(gwn_mlp_s* h, long long n) {
     if (h->data_cap >= n) return GWN_OK;
+    if (h->data_x) (void)hipDeviceSynchronize();   // earlier training may still read the data
     (void)hipFree(h->data_x);
     (void)hipFree(h->data_t);
     h->data_x = nullptr;
     h->data_t = nullptr;
     h->data_cap = 0;
     h->data_valid = false;
-    GWN_HIP_TRY(hipMalloc((void**)&h->data_x, sizeof(float) * 3 * (size_t)std::max<long long>(n, 1)));
-    GWN_HIP_TRY(hipMalloc((void**)&h->data_t, sizeof(float) * (size_t)std::max<long long>(n, 1)));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->data_x, sizeof(float) * 3 * (size_t)std::max<long long>(n, 1)));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->data_t, sizeof(float) * (size_t)std::max<long long>(n, 1)));
     h->data_cap = n;
     return GWN_OK;
 }
@@ -824,13 +828,13 @@ int fwd_grid(long long n) {
 
 gwn_status alloc_params(gwn_mlp_s* h) {
     GWN_HIP_TRY(hipGetDevice(&h->device));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.master, sizeof(float) * kNParams));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.m, sizeof(float) * kNParams));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.v, sizeof(float) * kNParams));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.G, sizeof(float) * 96));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.wf, sizeof(unsigned short) * kWf));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.wb, sizeof(unsigned short) * kWb));
-    GWN_HIP_TRY(hipMalloc((void**)&h->d.wi, sizeof(unsigned short) * kWi));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.master, sizeof(float) * kNParams));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.m, sizeof(float) * kNParams));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.v, sizeof(float) * kNParams));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.G, sizeof(float) * 96));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.wf, sizeof(unsigned short) * kWf));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.wb, sizeof(unsigned short) * kWb));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.wi, sizeof(unsigned short) * kWi));
     return GWN_OK;
 }
 
@@ -1019,7 +1023,7 @@ gwn_status mlp_train_step(gwn_mlp_s* h, const float* qx, const float* qy, const 
     gwn_status s = ensure_train(h, n);
     if (s != GWN_OK) return s;
     if (!h->loss_dev) {
-        GWN_HIP_TRY(hipMalloc((void**)&h->loss_dev, sizeof(float) * 1024));
+        GWN_HIP_TRY(gwn::dmalloc((void**)&h->loss_dev, sizeof(float) * 1024));
         h->loss_cap = 1024;
     }
     s = train_batch(h, plain_src(qx, qy, qz, qs, tgt, n), n, lr, h->loss_dev, st);
@@ -1115,10 +1119,11 @@ gwn_status surrogate_train(gwn_mlp_s* h, const gwn_mesh_s* mesh, const gwn_surro
     s = ensure_train(h, batch);
     if (s != GWN_OK) return s;
     if (h->loss_cap < nsteps) {
+        if (h->loss_dev) (void)hipDeviceSynchronize();
         (void)hipFree(h->loss_dev);
         h->loss_dev = nullptr;
         h->loss_cap = 0;
-        GWN_HIP_TRY(hipMalloc((void**)&h->loss_dev, sizeof(float) * (size_t)nsteps));
+        GWN_HIP_TRY(gwn::dmalloc((void**)&h->loss_dev, sizeof(float) * (size_t)nsteps));
         h->loss_cap = nsteps;
     }
     Src S{};

@@ -17,6 +17,7 @@
 #include <string>
 #include <vector>
 
+#include "gwn_alloc.h"
 #include "gwn_kernels.h"
 #include "gwn_mesh.h"
 
@@ -193,7 +194,7 @@ gwn_status build_items(gwn_multi_s* p, const Schedule& s, hipStream_t st) {
     (void)hipFree(p->items);
     p->items = nullptr;
     p->nitems = (int)h.size();
-    GWN_HIP_TRY(hipMalloc((void**)&p->items, sizeof(Item) * std::max<size_t>(1, h.size())));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&p->items, sizeof(Item) * std::max<size_t>(1, h.size())));
     if (!h.empty())
         GWN_HIP_TRY(hipMemcpyAsync(p->items, h.data(), sizeof(Item) * h.size(), hipMemcpyHostToDevice, st));
     GWN_HIP_TRY(hipStreamSynchronize(st));
@@ -204,7 +205,7 @@ gwn_status build_items(gwn_multi_s* p, const Schedule& s, hipStream_t st) {
 // frame (the batch path's traversal order), as one permutation of all queries.
 gwn_status build_perm(gwn_multi_s* p, hipStream_t st) {
     if (p->perm) return GWN_OK;
-    GWN_HIP_TRY(hipMalloc((void**)&p->perm, sizeof(int) * (size_t)std::max<long long>(1, p->nq)));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&p->perm, sizeof(int) * (size_t)std::max<long long>(1, p->nq)));
     for (int m = 0; m < p->nmesh; ++m) {
         const long long q0 = p->qoff_h[m], n = p->qoff_h[m + 1] - q0;
         if (n <= 0) continue;
@@ -348,14 +349,14 @@ gwn_status multi_create(const gwn_mesh* meshes, int nmesh, const float* qx, cons
     p->w = (float*)w_out;
     p->chi = chi_out;
     if (!p->chi) {
-        GWN_HIP_TRY(hipMalloc((void**)&p->chi, sizeof(int) * (size_t)std::max<long long>(1, p->nq)));
+        GWN_HIP_TRY(gwn::dmalloc((void**)&p->chi, sizeof(int) * (size_t)std::max<long long>(1, p->nq)));
         p->own_chi = true;
     }
     std::vector<MeshView> tab(nmesh);
     for (int m = 0; m < nmesh; ++m) tab[m] = p->meshes[m]->view();
-    GWN_HIP_TRY(hipMalloc((void**)&p->table, sizeof(MeshView) * (size_t)nmesh));
-    GWN_HIP_TRY(hipMalloc((void**)&p->qoff, sizeof(long long) * (size_t)(nmesh + 1)));
-    GWN_HIP_TRY(hipMalloc((void**)&p->counter, sizeof(int)));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&p->table, sizeof(MeshView) * (size_t)nmesh));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&p->qoff, sizeof(long long) * (size_t)(nmesh + 1)));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&p->counter, sizeof(int)));
     GWN_HIP_TRY(hipMemcpyAsync(p->table, tab.data(), sizeof(MeshView) * nmesh, hipMemcpyHostToDevice, st));
     GWN_HIP_TRY(hipMemcpyAsync(p->qoff, p->qoff_h.data(), sizeof(long long) * (nmesh + 1), hipMemcpyHostToDevice, st));
     GWN_HIP_TRY(hipStreamSynchronize(st));

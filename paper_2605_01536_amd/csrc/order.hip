@@ -7,6 +7,7 @@
 // point; every result is written to the point's own slot.
 #include <cstdlib>
 
+#include "gwn_alloc.h"
 #include "gwn_internal.h"
 #include "gwn_mesh.h"
 #include "gwn_sort.h"
@@ -69,8 +70,8 @@ gwn_status xy_order(const gwn_mesh_s* m, const float* qx, const float* qy, const
     *perm_out = nullptr;
     int* perm = nullptr;
     void* tmp = nullptr;
-    hipError_t e = hipMallocAsync((void**)&perm, sizeof(int) * (size_t)n, st);
-    if (e == hipSuccess) e = hipMallocAsync(&tmp, xy_order_temp_bytes(n), st);
+    hipError_t e = gwn::dmalloc_async((void**)&perm, sizeof(int) * (size_t)n, st);
+    if (e == hipSuccess) e = gwn::dmalloc_async(&tmp, xy_order_temp_bytes(n), st);
     if (e != hipSuccess) {
         if (perm) (void)hipFreeAsync(perm, st);
         GWN_HIP_TRY(e);

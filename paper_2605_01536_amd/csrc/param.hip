@@ -35,6 +35,7 @@
 #include <new>
 #include <vector>
 
+#include "gwn_alloc.h"
 #include "gwn_mesh.h"
 
 struct gwn_patches_s {
@@ -1087,7 +1088,7 @@ gwn_status gwn_patches_build(const double* cps, int64_t npatch, const gwn_patch_
     h->eps = eps;
     h->max_depth = max_depth;
     auto up = [&](double** dst, const std::vector<double>& src) -> hipError_t {
-        hipError_t e = hipMalloc((void**)dst, sizeof(double) * std::max<size_t>(1, src.size()));
+        hipError_t e = gwn::dmalloc((void**)dst, sizeof(double) * std::max<size_t>(1, src.size()));
         if (e == hipSuccess && !src.empty())
             e = hipMemcpyAsync(*dst, src.data(), sizeof(double) * src.size(), hipMemcpyHostToDevice, st);
         return e;
@@ -1140,9 +1141,9 @@ gwn_status gwn_patches_query(gwn_patches h, const float* qx, const float* qy, co
     const long long chunk = 1ll << 30;   // queries (workgroups of kParamWaves) per launch
     int *chi = nullptr, *dir = nullptr;
     hipError_t e = hipSuccess;
-    if (!chi_out) e = hipMallocAsync((void**)&chi, sizeof(int) * (size_t)std::min<long long>(std::max<long long>(nq, 1), chunk), st);
+    if (!chi_out) e = gwn::dmalloc_async((void**)&chi, sizeof(int) * (size_t)std::min<long long>(std::max<long long>(nq, 1), chunk), st);
     if (e == hipSuccess && !dir_out)
-        e = hipMallocAsync((void**)&dir, sizeof(int) * (size_t)std::min<long long>(std::max<long long>(nq, 1), chunk), st);
+        e = gwn::dmalloc_async((void**)&dir, sizeof(int) * (size_t)std::min<long long>(std::max<long long>(nq, 1), chunk), st);
     for (long long o = 0; o < nq && e == hipSuccess; o += chunk) {
         const long long n = std::min<long long>(chunk, nq - o);
         e = gwn::launch_param<false>(h, qx + o * qstride, qy + o * qstride, qz + o * qstride, qstride, n, w_out + o,
@@ -1186,9 +1187,9 @@ gwn_status gwn_patches_query_grid(gwn_patches h, const double* origin, const dou
     unsigned long long* d = nullptr;
     unsigned long long hc[2] = {0, 0};
     hipError_t e = hipSuccess;
-    if (!chi) e = hipMallocAsync((void**)&chi, sizeof(int) * (size_t)n, st);
-    if (e == hipSuccess && !dir) e = hipMallocAsync((void**)&dir, sizeof(int) * (size_t)n, st);
-    if (e == hipSuccess && counts) e = hipMallocAsync((void**)&d, sizeof hc, st);
+    if (!chi) e = gwn::dmalloc_async((void**)&chi, sizeof(int) * (size_t)n, st);
+    if (e == hipSuccess && !dir) e = gwn::dmalloc_async((void**)&dir, sizeof(int) * (size_t)n, st);
+    if (e == hipSuccess && counts) e = gwn::dmalloc_async((void**)&d, sizeof hc, st);
     if (e == hipSuccess && counts) e = hipMemcpyAsync(d, hc, sizeof hc, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         gwn::GridPts g;
@@ -1223,11 +1224,11 @@ gwn_status gwn_patches_query_stats(gwn_patches h, const float* qx, const float* 
     }
     hipStream_t st = (hipStream_t)stream;
     unsigned long long* d = nullptr;
-    GWN_HIP_TRY(hipMalloc((void**)&d, 2 * sizeof(unsigned long long)));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&d, 2 * sizeof(unsigned long long)));
     unsigned long long hc[2] = {0, 0};
     int* cd = nullptr;
     hipError_t e = hipMemcpyAsync(d, hc, sizeof hc, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&cd, sizeof(int) * 2 * (size_t)std::max<long long>(nq, 1), st);
+    if (e == hipSuccess) e = gwn::dmalloc_async((void**)&cd, sizeof(int) * 2 * (size_t)std::max<long long>(nq, 1), st);
     if (e == hipSuccess && nq > 0)
         e = gwn::launch_param<true>(h, qx, qy, qz, qstride, nq, w_out, cd, cd + nq, d, st);
     if (cd) (void)hipFreeAsync(cd, st);

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 
+#include "gwn_alloc.h"
 #include "gwn_kernels.h"
 #include "gwn_mesh.h"
 
@@ -227,7 +228,7 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
     int* chi = chi_out;
     if (!chi) {
         if (ws) chi = ws->chi;
-        else GWN_HIP_TRY(hipMallocAsync((void**)&chi, sizeof(int) * (size_t)nq, st));
+        else GWN_HIP_TRY(gwn::dmalloc_async((void**)&chi, sizeof(int) * (size_t)nq, st));
     }
     const bool own_chi = !chi_out && !ws;
     const MeshView mv = m->view();

@@ -22,6 +22,7 @@
 // scan the tile totals recursively, and add the tile's prefix.
 #include <climits>
 
+#include "gwn_alloc.h"
 #include "gwn_sort.h"
 
 namespace gwn {
@@ -340,7 +341,7 @@ gwn_status prim_status(const char* fn, hipError_t e) {
 template <class F>
 gwn_status with_async_temp(const char* fn, size_t bytes, hipStream_t st, F&& f) {
     void* tmp = nullptr;
-    hipError_t e = hipMallocAsync(&tmp, bytes, st);
+    hipError_t e = gwn::dmalloc_async(&tmp, bytes, st);
     if (e != hipSuccess) return prim_status(fn, e);
     e = f(tmp);
     const hipError_t e2 = hipFreeAsync(tmp, st);

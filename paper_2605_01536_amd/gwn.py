@@ -10,7 +10,8 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libgwn.so")
+# GWN_LIB selects another build of the library (e.g. one with sanitized host code)
+LIB_PATH = os.environ.get("GWN_LIB") or os.path.join(_PKG, "libgwn.so")
 
 GWN_PREC_FP32 = 0
 GWN_PREC_FP64 = 1

@@ -35,3 +35,9 @@ def test_grid_slots_bounds():
     assert bench.grid_slots(s, hi, "fp32")[1:] == (1.0, 0.0)
     # blocks of 64 and 36 samples: the first drops the select, the last keeps it
     assert bench.grid_slots(s, lo, "fp32")[1:] == (0.0, 0.64)
+
+
+def test_cpu_model_is_reported():
+    import bench
+    s = bench.cpu_model()
+    assert isinstance(s, str) and s
