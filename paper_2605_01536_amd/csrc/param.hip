@@ -829,6 +829,10 @@ __global__ __launch_bounds__(64 * kParamWaves) void k_param_bdry(
                 n += take;
                 next += take;
             }
+            // the take below reads slots other lanes wrote in the refill
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (n == 0) break;
             const int take = min(n, 64);
             n -= take;
@@ -922,21 +926,35 @@ hipError_t launch_param_grid(gwn_patches_s* h, const GridPts& g, long long nx, d
         if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->fork, 0);
         if (e != hipSuccess) return e;
     }
+    // after the fork every return joins the side stream back into st first, so
+    // that work on st (and a caller synchronising st) also waits for the side
+    // kernel, which may still be writing w
+    bool joined = false;   // the join event has been recorded on the side stream
+    auto rejoin = [&](hipError_t err) {
+        if constexpr (!STATS) {
+            if (!joined) (void)hipEventRecord(h->join, h->side);
+            (void)hipStreamWaitEvent(st, h->join, 0);
+        }
+        return err;
+    };
     k_param_cols<STATS><<<(unsigned)ncols, kColThreads, 0, st>>>(h->patches, h->boxes, h->npatch, g, ncols, h->tau,
                                                                  chi, dir, stats);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) return rejoin(e);
     if constexpr (!STATS) {
         k_param_bdry<false, GridPts, 1><<<blocks, 64 * kParamWaves, 0, h->side>>>(
             h->curves, h->ncurves, g, n, h->eps, h->max_depth, chi, dir, w, nullptr);
         e = hipGetLastError();
-        if (e == hipSuccess) e = hipEventRecord(h->join, h->side);
-        if (e != hipSuccess) return e;
+        if (e == hipSuccess) {
+            e = hipEventRecord(h->join, h->side);
+            joined = e == hipSuccess;
+        }
+        if (e != hipSuccess) return rejoin(e);
     }
     k_param_chi<STATS, true><<<blocks, 64 * kParamWaves, 0, st>>>(h->patches, h->boxes, h->npatch, g, n, h->tau, chi,
                                                                   dir, stats);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) return rejoin(e);
     if constexpr (STATS) {
         k_param_bdry<true><<<blocks, 64 * kParamWaves, 0, st>>>(h->curves, h->ncurves, g, n, h->eps, h->max_depth,
                                                                 chi, dir, w, stats);
@@ -1222,6 +1240,13 @@ gwn_status gwn_patches_query_stats(gwn_patches h, const float* qx, const float* 
         set_error("gwn_patches_query_stats: null argument, nq outside [0, 2^30] or qstride < 1");
         return GWN_E_INVALID;
     }
+    int dev = -1;
+    GWN_HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device) {
+        set_error("gwn_patches_query_stats: the patches were built on device %d, the current device is %d", h->device,
+                  dev);
+        return GWN_E_INVALID;
+    }
     hipStream_t st = (hipStream_t)stream;
     unsigned long long* d = nullptr;
     GWN_HIP_TRY(gwn::dmalloc((void**)&d, 2 * sizeof(unsigned long long)));
@@ -1244,11 +1269,14 @@ gwn_status gwn_patches_query_stats(gwn_patches h, const float* qx, const float* 
 gwn_status gwn_patches_destroy(gwn_patches h) {
     gwn::clear_error();
     if (!h) return GWN_OK;
+    // the side stream's kernel reads the curves: drain it before they go, and
+    // let work on the caller's streams finish with the patches too
+    if (h->side) (void)hipStreamSynchronize(h->side);
+    (void)hipDeviceSynchronize();
     (void)hipFree(h->patches);
     (void)hipFree(h->boxes);
     (void)hipFree(h->curves);
     if (h->side) {
-        (void)hipStreamSynchronize(h->side);
         (void)hipStreamDestroy(h->side);
         (void)hipEventDestroy(h->fork);
         (void)hipEventDestroy(h->join);
