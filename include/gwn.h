@@ -125,6 +125,55 @@ gwn_status gwn_mesh_info_get(gwn_mesh m, gwn_mesh_info* out);
 gwn_status gwn_mesh_destroy(gwn_mesh m);
 
 /*
+ * Per-mesh query tuning.  Three choices of the query paths depend on the mesh
+ * and the device, not on the arithmetic: the largest batch that gives each
+ * point a workgroup with the boundary edges split among its lanes (per
+ * precision; this changes the summation order of w, i.e. its last bits), the
+ * smallest batch worth a Morton order of the points for the crossing walk (no
+ * result changes), and the grid kernel's samples per lane (per precision;
+ * w's last bits).  Crossing counts never change.  A field of 0 takes the
+ * built-in rule (split: at most 8,192 points on meshes with at least 4,096
+ * boundary edges; order: at least 2^18 points on meshes of at least 2^15
+ * triangles; samples: the largest of 8 (FP32) or 4 (FP64), 4, 2, 1 that the
+ * column length fills), -1 never (split, order).  The environment variables
+ * GWN_SPLIT_BOUNDARY, GWN_ORDER_QUERIES and GWN_GRID_SAMPLES_PER_LANE override
+ * any tuning.
+ *
+ * gwn_mesh_set_tuning / gwn_mesh_get_tuning: host-side, no device work.
+ *   Errors: GWN_E_INVALID for thresholds below -1 or samples per lane other
+ *   than 0, 1, 2, 4, 8 (FP64: at most 4).
+ * gwn_mesh_autotune: for opts->prec, times each candidate on the device with
+ *   points drawn uniformly in the mesh's bounding box -- split against one
+ *   lane per point for 256 .. 32,768 points, ordered against unordered for
+ *   2^20 down to 2^14 points, and, when opts->grid_nz > 0, samples per lane on
+ *   a 64 x 64 x grid_nz grid over the box -- keeping the fastest (the smallest
+ *   of opts->reps timings, default 3), and sets the mesh's tuning.  With
+ *   opts->cache (a JSON-lines file), a choice stored for the same device
+ *   architecture, triangle and boundary-edge counts (as powers of two),
+ *   precision and grid_nz is applied without timing, and a new one is
+ *   appended.  Allocates about 16 MB (more for large grid_nz) and synchronises
+ *   `stream`.  opts may be NULL (FP32, no grid, no cache).
+ */
+typedef struct {
+    int32_t split_max_points[2];       /* per precision (index GWN_PREC_FP32, GWN_PREC_FP64) */
+    int32_t order_min_points;
+    int32_t grid_samples_per_lane[2];  /* per precision */
+    int32_t tuned;                     /* get only: bit p set when precision p was tuned by gwn_mesh_autotune */
+} gwn_query_tuning;
+
+typedef struct {
+    int32_t prec;            /* GWN_PREC_FP32 or GWN_PREC_FP64 */
+    int32_t grid_nz;         /* column length of the grids to tune for; 0 = leave the grid choice */
+    int32_t reps;            /* timings per candidate; 0 = 3 */
+    int32_t reserved;        /* zero */
+    const char* cache;       /* nullable JSON-lines cache file */
+} gwn_autotune_opts;
+
+gwn_status gwn_mesh_set_tuning(gwn_mesh m, const gwn_query_tuning* t);
+gwn_status gwn_mesh_get_tuning(gwn_mesh m, gwn_query_tuning* out);
+gwn_status gwn_mesh_autotune(gwn_mesh m, const gwn_autotune_opts* opts, void* stream);
+
+/*
  * gwn_query_batch -- w for nq arbitrary points (Alg. 1 per point).
  *
  *   qx, qy, qz, qstride, nq : query coordinates (float32), strided.
@@ -135,10 +184,10 @@ gwn_status gwn_mesh_destroy(gwn_mesh m);
  * not meaningful (w is undefined on M).  A point's w does not depend on the
  * other points of the call or their order, and repeated calls give the same
  * bits; gwn_query_multi gives the same bits too.  The one exception is the
- * summation order: batches of at most 8,192 points on meshes with at least
- * 4,096 boundary edges give each point a workgroup that splits its edges among
- * lanes (GWN_SPLIT_BOUNDARY=0/1 overrides), which agrees with the other form
- * to rounding.
+ * summation order: small batches (at most 8,192 points on meshes with at least
+ * 4,096 boundary edges, or the mesh's tuning, see gwn_mesh_set_tuning) give
+ * each point a workgroup that splits its edges among lanes (GWN_SPLIT_BOUNDARY=
+ * 0/1 overrides), which agrees with the other form to rounding.
  */
 gwn_status gwn_query_batch(gwn_mesh m, const float* qx, const float* qy, const float* qz, int64_t qstride,
                            int64_t nq, int32_t prec, void* w_out, int32_t* chi_out, void* stream);

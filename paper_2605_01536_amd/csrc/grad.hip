@@ -485,7 +485,7 @@ gwn_status query_gradient(const gwn_mesh_s* m, const float* qx, const float* qy,
         const int64_t n = std::min<int64_t>(chunk, nq - o);
         const unsigned blocks = (unsigned)((n + 255) / 256);
         const float *x = qx + o * qs, *y = qy + o * qs, *z = qz + o * qs;
-        if (want_split(m, n)) {   // few points, many edges: a workgroup per point
+        if (want_split(m, n, -1)) {   // few points, many edges: a workgroup per point
             if (prec == GWN_PREC_FP64)
                 k_grad_split<double><<<(unsigned)n, kSplitThreads, 0, st>>>(mv, x, y, z, qs, n, m->axis,
                                                                              (double*)g + 3 * o);

@@ -170,18 +170,20 @@ gwn_status launch_grid_zb(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_o
 }
 
 // Samples per lane: more samples share more x/y work, fewer leave registers for
-// more resident waves.  GWN_GRID_SAMPLES_PER_LANE (1, 2, 4 or 8) overrides the
-// default choice, which is the largest value the column length fills.
+// more resident waves.  GWN_GRID_SAMPLES_PER_LANE (1, 2, 4 or 8) overrides
+// everything; then the mesh's tuning for the precision (gwn_mesh_set_tuning,
+// gwn_mesh_autotune); the built-in choice is the largest value the column fills.
 template <class T>
 gwn_status launch_grid(const gwn_mesh_s* m, GridArgs ga, T* w, int32_t* chi_out, hipStream_t st) {
-    if (const char* e = std::getenv("GWN_GRID_SAMPLES_PER_LANE")) {
-        switch (std::atoi(e)) {
-            case 1: return launch_grid_zb<T, 1>(m, ga, w, chi_out, st);
-            case 2: return launch_grid_zb<T, 2>(m, ga, w, chi_out, st);
-            case 4: return launch_grid_zb<T, 4>(m, ga, w, chi_out, st);
-            case 8: return launch_grid_zb<T, 8>(m, ga, w, chi_out, st);
-            default: break;
-        }
+    int zb = 0;
+    if (const char* e = std::getenv("GWN_GRID_SAMPLES_PER_LANE")) zb = std::atoi(e);
+    if (zb == 0) zb = m->grid_zb[sizeof(T) == 8 ? GWN_PREC_FP64 : GWN_PREC_FP32];
+    switch (zb) {
+        case 1: return launch_grid_zb<T, 1>(m, ga, w, chi_out, st);
+        case 2: return launch_grid_zb<T, 2>(m, ga, w, chi_out, st);
+        case 4: return launch_grid_zb<T, 4>(m, ga, w, chi_out, st);
+        case 8: return launch_grid_zb<T, 8>(m, ga, w, chi_out, st);
+        default: break;
     }
     // FP64 keeps at most 4 samples per lane (8 would need ~200 VGPRs)
     if (ga.nz >= 64 * 8 && sizeof(T) == 4) return launch_grid_zb<T, 8>(m, ga, w, chi_out, st);

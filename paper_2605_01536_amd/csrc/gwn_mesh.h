@@ -25,6 +25,11 @@ struct gwn_mesh_s {
     float4* trif = nullptr;        // float corners in Morton order (direct sum)
     gwn::BVert* bverts = nullptr;
     int* loop_off = nullptr;
+    // query tuning (gwn_mesh_set_tuning / gwn_mesh_autotune); 0 = the built-in rule
+    int split_max[2] = {0, 0};     // per precision: batches of at most this many points split their edges
+    int order_min = 0;             // batches of at least this many points are Morton-ordered
+    int grid_zb[2] = {0, 0};       // per precision: grid samples per lane
+    int tuned = 0;                 // bit p: precision p was tuned
 
     gwn::MeshView view() const {
         gwn::MeshView v;
@@ -79,7 +84,8 @@ int64_t max_launch_queries();
 // edges split among its lanes: batches of at most 8,192 points on meshes with at
 // least 16 boundary edges per lane of a 256-lane workgroup.
 // GWN_SPLIT_BOUNDARY=0/1 overrides.
-bool want_split(const gwn_mesh_s* m, int64_t n);
+// prec: the precision whose tuning applies (-1: the built-in rule only).
+bool want_split(const gwn_mesh_s* m, int64_t n, int prec);
 
 // Morton order of the points' quantised x, y for the crossing traversal (perm is
 // stream-ordered device memory the caller frees with hipFreeAsync).

@@ -41,6 +41,7 @@ __global__ void k_xy_keys(const float* __restrict__ qx, const float* __restrict_
 // 2^20 random grid points go 3.4x faster, 2^16 (16x sparser) 25% slower.
 bool want_xy_order(const gwn_mesh_s* m, int64_t n) {
     if (const char* e = std::getenv("GWN_ORDER_QUERIES")) return std::atoi(e) != 0 && n > 1;
+    if (m->order_min != 0) return m->order_min > 0 && n >= m->order_min && n > 1;
     return n >= (1 << 18) && m->nf >= (1 << 15);
 }
 

@@ -257,7 +257,7 @@ gwn_status launch_batch(const gwn_mesh_s* m, const float* qx, const float* qy, c
         }
         e = hipGetLastError();
         if (e == hipSuccess) {
-            if (want_split(m, n))
+            if (want_split(m, n, sizeof(T) == 8 ? GWN_PREC_FP64 : GWN_PREC_FP32))
                 k_bdry_split<T><<<(unsigned)n, kSplitThreads, 0, st>>>(mv, x, y, z, qs, n, chi + o, w + o);
             else
                 k_bdry_batch<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(mv, x, y, z, qs, n, perm, chi + o,
@@ -300,8 +300,9 @@ gwn_status query_crossings(const gwn_mesh_s* m, const float* qx, const float* qy
     return GWN_OK;
 }
 
-bool want_split(const gwn_mesh_s* m, int64_t n) {
+bool want_split(const gwn_mesh_s* m, int64_t n, int prec) {
     if (const char* e = std::getenv("GWN_SPLIT_BOUNDARY")) return std::atoi(e) != 0 && m->nb > 0;
+    if (prec >= 0 && prec < 2 && m->split_max[prec] != 0) return m->split_max[prec] > 0 && n <= m->split_max[prec] && m->nb > 0;
     return n <= 8192 && m->nb >= 16 * 256;
 }
 

@@ -34,6 +34,16 @@ class MeshInfo(ctypes.Structure):
                 ("pad", ctypes.c_int32), ("proj_area", ctypes.c_double * 3)]
 
 
+class QueryTuning(ctypes.Structure):
+    _fields_ = [("split_max_points", ctypes.c_int32 * 2), ("order_min_points", ctypes.c_int32),
+                ("grid_samples_per_lane", ctypes.c_int32 * 2), ("tuned", ctypes.c_int32)]
+
+
+class AutotuneOpts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("grid_nz", ctypes.c_int32), ("reps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("cache", ctypes.c_char_p)]
+
+
 class BuildOpts(ctypes.Structure):
     _fields_ = [("weld_positions", ctypes.c_int32), ("axis", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
@@ -149,6 +159,34 @@ class Mesh:
     @property
     def handle(self):
         return self._h
+
+    def tuning(self) -> dict:
+        """The mesh's query tuning (gwn_mesh_get_tuning); 0 = built-in rule, -1 = never."""
+        L = load()
+        L.gwn_mesh_get_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(QueryTuning)]
+        L.gwn_mesh_get_tuning.restype = ctypes.c_int
+        q = QueryTuning()
+        _check(L.gwn_mesh_get_tuning(self._h, ctypes.byref(q)))
+        return {"split_max_points": list(q.split_max_points), "order_min_points": q.order_min_points,
+                "grid_samples_per_lane": list(q.grid_samples_per_lane), "tuned": q.tuned}
+
+    def set_tuning(self, split_max_points=(0, 0), order_min_points=0, grid_samples_per_lane=(0, 0)):
+        """gwn_mesh_set_tuning; pairs are indexed by precision (fp32, fp64)."""
+        L = load()
+        L.gwn_mesh_set_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(QueryTuning)]
+        L.gwn_mesh_set_tuning.restype = ctypes.c_int
+        q = QueryTuning((ctypes.c_int32 * 2)(*split_max_points), int(order_min_points),
+                        (ctypes.c_int32 * 2)(*grid_samples_per_lane), 0)
+        _check(L.gwn_mesh_set_tuning(self._h, ctypes.byref(q)))
+
+    def autotune(self, prec="fp32", grid_nz: int = 0, reps: int = 0, cache: str | None = None, stream=None) -> dict:
+        """gwn_mesh_autotune for one precision; returns the tuning it set."""
+        L = load()
+        L.gwn_mesh_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(AutotuneOpts), ctypes.c_void_p]
+        L.gwn_mesh_autotune.restype = ctypes.c_int
+        o = AutotuneOpts(_PREC[prec], int(grid_nz), int(reps), 0, os.fsencode(cache) if cache else None)
+        _check(L.gwn_mesh_autotune(self._h, ctypes.byref(o), _stream(stream)))
+        return self.tuning()
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
