@@ -78,11 +78,11 @@ I_MIN_GRAD = 10 + 29 + 4 * TRANS_SLOTS     # = 51
 # Dense bf16 MFMA peak of MI355X (no sparsity), for the surrogate network
 PEAK_BF16 = 2.5e15
 # The network's VALU work per point, which bounds it before the MFMA work does:
-# 512 GELU activations at ~20.5 slots (bias add, |z|/sqrt2, 1 + p x and its rcp,
-# -x^2 and exp2, the degree-5 erf polynomial, sign, 0.5 + 0.5 erf, z Phi, half a
-# packed bf16 conversion; rcp and exp2 at 3 slots), 32 sincos of the Fourier
-# features at ~20, and the 128-term output dot product with bf16 widening (256)
-NET_VALU_SLOTS = 512 * 20.5 + 32 * 21 + 256     # = 11,424 per point
+# 512 GELU activations at 11 slots (bias add into the clamp, the square, 7 FMAs
+# of the polynomial, fma(zc, P, 1/2), the product; plus half a packed bf16
+# conversion counted with the bias add), 32 sincos of the Fourier features at
+# ~21, and the 128-term output dot product with bf16 widening (256)
+NET_VALU_SLOTS = 512 * 11 + 32 * 21 + 256     # = 6,560 per point
 # HBM bytes moved per k_grid<float, 8> launch on the default workload (512^3 grid,
 # 1.05M-triangle soup), from two rocprofv3 --pmc passes over this command:
 # FETCH_SIZE 231,887.25 KiB and WRITE_SIZE 524,288.0 KiB per dispatch, scaled by

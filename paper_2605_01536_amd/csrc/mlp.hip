@@ -1,10 +1,12 @@
 // mlp.hip -- learned surrogate for far-field winding-number queries:
 // Fourier features gamma(p) = [sin 2piGp, cos 2piGp] (G: 32x3, fixed), four
 // GELU layers 64->128->128->128->128 and a linear output 128->1.  Matrix
-// products run on MFMA with bf16 operands and fp32 accumulation: the training
-// kernels use v_mfma_f32_16x16x16bf16_1k on LDS tiles, inference
-// (k_infer) v_mfma_f32_16x16x32_bf16 with the activations kept in registers.
-// FP32 master weights are updated by Adam and re-packed into bf16 copies in
+// products run on MFMA (v_mfma_f32_16x16x32_bf16) with bf16 operands and fp32
+// accumulation: the training kernels on LDS tiles, inference (k_infer) with
+// the activations kept in registers.
+// Inference evaluates GELU by a minimax polynomial of Phi (gelu_fast, within
+// 5.3e-5 |z| of the erf form), training by the erf form (Abramowitz & Stegun
+// 7.1.26, 1.5e-7).  FP32 master weights are updated by Adam and re-packed into bf16 copies in
 // the three layouts the kernels read.  The band query evaluates the network,
 // re-evaluates every point whose prediction lies within `band` of 1/2 with the
 // exact kernels, and scatters those results back.
@@ -17,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -36,11 +39,21 @@ constexpr int kFreq = 32, kIn = 64, kHid = 128;
 constexpr int kNParams = 64 * 128 + 128 + 3 * (128 * 128 + 128) + 128 + 1;   // 57985
 constexpr int kOffW[5] = {0, 8320, 24832, 41344, 57856};
 constexpr int kOffB[5] = {8192, 24704, 41216, 57728, 57984};
+// the same offsets as arithmetic, for run-time layer indices (a constant table
+// indexed at run time would live in scratch memory)
+__host__ __device__ constexpr int off_w(int l) { return l == 0 ? 0 : 8320 + (l - 1) * 16512; }
+__host__ __device__ constexpr int off_b(int l) { return l == 4 ? 57984 : off_w(l) + (l == 0 ? 64 : 128) * 128; }
+static_assert(off_w(0) == kOffW[0] && off_w(1) == kOffW[1] && off_w(2) == kOffW[2] && off_w(3) == kOffW[3] &&
+              off_w(4) == kOffW[4], "weight offsets");
+static_assert(off_b(0) == kOffB[0] && off_b(1) == kOffB[1] && off_b(2) == kOffB[2] && off_b(3) == kOffB[3] &&
+              off_b(4) == kOffB[4], "bias offsets");
 constexpr int kTile = 64;        // points per workgroup tile (4 waves x 16 rows)
+constexpr int kInferShape = 0;   // k_infer shape: 0 = 2 tiles x 8 waves, 1 = 1 x 12, 2 = 1 x 16
+constexpr bool kInferPolyGelu = true;    // k_infer GELU: the polynomial form (gelu_fast) or the erf form
 constexpr int kLd = 136;         // padded LDS row (bf16) for 128-wide operands
 constexpr int kLd0 = 72;         // padded LDS row for the 64-wide first layer
 constexpr int kChunk = 256;      // batch rows per weight-gradient workgroup
-constexpr int kLdC = kChunk + 4;
+constexpr int kLdC = kChunk + 8;   // 16-byte aligned rows (528 bytes)
 constexpr int kWf = 128 * 64 + 3 * 128 * 128 + 128;   // forward bf16 copy: Wt0..Wt3 ([out][in]) + w4
 constexpr int kWb = 3 * 128 * 128;                    // backward bf16 copy: W1..W3 ([in][out])
 constexpr int kWi = 128 * 64 + 3 * 128 * 128;         // inference copy: W0..W3 as MFMA A fragments
@@ -161,6 +174,23 @@ __device__ __forceinline__ float gelu(float z) {
     gelu_parts(z, phi, e);
     return z * phi;
 }
+
+// Inference GELU: Phi(z) - 1/2 = z P(z^2) for |z| <= 4, P of degree 7 fitted by
+// the Remez exchange for minimax absolute error (gen_gelu_poly.py 7 4), and z
+// clamped to +-4 beyond (Phi off by at most 1 - Phi(4) = 3.2e-5); in float32
+// |Phi error| <= 5.3e-5, i.e. |GELU error| <= 5.3e-5 |z|, far below the bf16
+// rounding of the activation it feeds (2^-9 relative).  11 VALU slots: clamp,
+// square, 7 FMAs, fma(zc, P, 1/2), the product with z.
+constexpr float kGeluP[] = {-1.5807866e-09f, 1.2171112e-07f, -4.100867e-06f, 8.06674e-05f, -0.0010482044f,
+                            0.0096648745f, -0.06617538f, 0.39884752f};
+__device__ __forceinline__ float gelu_fast(float z) {
+    const float zc = __builtin_amdgcn_fmed3f(z, -4.0f, 4.0f);
+    const float x = zc * zc;
+    float p = kGeluP[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) p = fmaf(p, x, kGeluP[i]);
+    return z * fmaf(zc, p, 0.5f);
+}
 __device__ __forceinline__ float gelu_grad(float z) {
     float phi, e;
     gelu_parts(z, phi, e);
@@ -169,20 +199,23 @@ __device__ __forceinline__ float gelu_grad(float z) {
 
 // acc[t] += A(16 rows of this wave, K) x B(K, 16t..16t+15) for t = 0..7;
 // A rows come from sA (row-major, ld lda), B from sBt stored column-major as
-// [col][k] (ld ldb).
+// [col][k] (ld ldb).  v_mfma_f32_16x16x32_bf16: each lane reads 8 consecutive k
+// of its row (A) and of its column (B) as one 16-byte load, so K is a multiple
+// of 32 and both leading dimensions keep rows 16-byte aligned.
 template <int K>
 __device__ __forceinline__ void mma_rows16(const unsigned short* sA, int lda, const unsigned short* sBt, int ldb,
                                            int arow, v4f* acc) {
+    static_assert(K % 32 == 0, "K must be a multiple of 32");
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
 #pragma unroll
     for (int t = 0; t < 8; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        const v4s a = *(const v4s*)(sA + (arow + lr) * lda + k0 + 4 * lg);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const v8bf a = *(const v8bf*)(sA + (arow + lr) * lda + k0 + 8 * lg);
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const v4s b = *(const v4s*)(sBt + (16 * t + lr) * ldb + k0 + 4 * lg);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            const v8bf b = *(const v8bf*)(sBt + (16 * t + lr) * ldb + k0 + 8 * lg);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
         }
     }
 }
@@ -342,8 +375,8 @@ __global__ __launch_bounds__(256) void k_bwd(Dev P, long long n, float inv_n, Tr
 // Weight gradients of one layer for one chunk of rows: dW = x^T dz on MFMA,
 // db = column sums; blockIdx.y = layer (4 = output layer on the VALU).
 __global__ __launch_bounds__(256) void k_wgrad(long long n, Train T) {
-    __shared__ unsigned short sXt[128 * kLdC];
-    __shared__ unsigned short sDt[128 * kLdC];
+    __shared__ __attribute__((aligned(16))) unsigned short sXt[128 * kLdC];
+    __shared__ __attribute__((aligned(16))) unsigned short sDt[128 * kLdC];
     const int layer = blockIdx.y;
     const long long c0 = (long long)blockIdx.x * kChunk;
     float* part = T.part + (long long)blockIdx.x * (kNParams + 1);
@@ -385,9 +418,11 @@ __global__ __launch_bounds__(256) void k_wgrad(long long n, Train T) {
         const int m = idx >> 4, j0 = (idx & 15) * 8;
         const long long row = c0 + m;
         const bool ok = row < n;
-        const uint4 z = {0u, 0u, 0u, 0u};
-        const uint4 xv = ok && j0 < kin ? *(const uint4*)(T.x + ((long long)layer * T.cap + row) * 128 + j0) : z;
-        const uint4 dv = ok ? *(const uint4*)(T.dz + ((long long)layer * T.cap + row) * 128 + j0) : z;
+        // explicit branches: a select between the loaded vector and a zero one
+        // becomes a select between pointers, with the zero vector in scratch
+        uint4 xv = {0u, 0u, 0u, 0u}, dv = {0u, 0u, 0u, 0u};
+        if (ok && j0 < kin) xv = *(const uint4*)(T.x + ((long long)layer * T.cap + row) * 128 + j0);
+        if (ok) dv = *(const uint4*)(T.dz + ((long long)layer * T.cap + row) * 128 + j0);
         const unsigned xs[4] = {xv.x, xv.y, xv.z, xv.w}, ds[4] = {dv.x, dv.y, dv.z, dv.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -406,14 +441,16 @@ __global__ __launch_bounds__(256) void k_wgrad(long long n, Train T) {
         const int i0 = wave * rows_per_wave + 16 * rt;
         v4f acc[8];
         mma_rows16<kChunk>(sXt, kLdC, sDt, kLdC, i0, acc);
+#pragma unroll
         for (int t = 0; t < 8; ++t)
+#pragma unroll
             for (int v = 0; v < 4; ++v)
-                part[kOffW[layer] + (i0 + 4 * lg + v) * 128 + 16 * t + lr] = acc[t][v];
+                part[off_w(layer) + (i0 + 4 * lg + v) * 128 + 16 * t + lr] = acc[t][v];
     }
     if (threadIdx.x < 128) {
         float s = 0.f;
         for (int m = 0; m < kChunk; ++m) s += bf2f(sDt[threadIdx.x * kLdC + m]);
-        part[kOffB[layer] + threadIdx.x] = s;
+        part[off_b(layer) + threadIdx.x] = s;
     }
 }
 
@@ -459,13 +496,17 @@ __host__ __device__ inline int infer_slot(int l, int k, int o) {
 // input feature held in slot j of block b by lane group g (hidden layers)
 __device__ __forceinline__ int kappa(int b, int g, int j) { return 32 * b + (j < 4 ? 4 * g + j : 12 + 4 * g + j); }
 
-constexpr int kInferWaves = 8;    // 512 threads: 2 waves per SIMD share one copy of the weights in LDS
-constexpr int kInferPts = 32;     // points per wave per step (two 16-point tiles reuse each A fragment)
-
-__global__ __launch_bounds__(64 * kInferWaves) void k_infer(Dev P, const float* __restrict__ qx,
-                                                           const float* __restrict__ qy,
-                                                           const float* __restrict__ qz, long long qs, long long n,
-                                                           float* __restrict__ y) {
+// NT 16-point tiles per wave and step (NT = 2: each A fragment read from LDS
+// serves two tiles), NW waves per workgroup sharing one copy of the weights in
+// LDS (one workgroup per CU).  NT = 2, NW = 8 holds 206 VGPRs (2 waves per
+// SIMD); one tile per wave with 12 or 16 waves (3 or 4 per SIMD, 152 or 128
+// VGPRs) measured 2-5% slower.  POLY: the polynomial GELU (gelu_fast), else the
+// erf form of the training kernels.
+template <int NT, int NW, bool POLY>
+__global__ __launch_bounds__(64 * NW) void k_infer(Dev P, const float* __restrict__ qx, const float* __restrict__ qy,
+                                                   const float* __restrict__ qz, long long qs, long long n,
+                                                   float* __restrict__ y) {
+    constexpr int kPts = 16 * NT;   // points per wave per step
     __shared__ v8bf sWi[kWi / 8];
     __shared__ float sB[4][128];
     __shared__ float sW4[128];
@@ -473,9 +514,9 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_infer(Dev P, const float* 
     {
         const uint4* src = (const uint4*)P.wi;
         uint4* dst = (uint4*)sWi;
-        for (int i = threadIdx.x; i < kWi / 8; i += 64 * kInferWaves) dst[i] = src[i];
+        for (int i = threadIdx.x; i < kWi / 8; i += 64 * NW) dst[i] = src[i];
     }
-    for (int i = threadIdx.x; i < 128; i += 64 * kInferWaves) {
+    for (int i = threadIdx.x; i < 128; i += 64 * NW) {
         sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
         for (int l = 0; l < 4; ++l) sB[l][i] = P.master[kOffB[l] + i];
     }
@@ -483,13 +524,12 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_infer(Dev P, const float* 
     const float b4 = P.master[kOffB[4]];
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, ln = lane & 15, g = lane >> 4;
-    for (long long step = (long long)blockIdx.x * kInferWaves + wave; step * kInferPts < n;
-         step += (long long)gridDim.x * kInferWaves) {
-        v8bf X[2][4];
-        long long pt[2];
+    for (long long step = (long long)blockIdx.x * NW + wave; step * kPts < n; step += (long long)gridDim.x * NW) {
+        v8bf X[NT][4];
+        long long pt[NT];
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {   // Fourier features: frequencies 8g..8g+7 of point ln of tile p
-            pt[p] = step * kInferPts + 16 * p + ln;
+        for (int p = 0; p < NT; ++p) {   // Fourier features: frequencies 8g..8g+7 of point ln of tile p
+            pt[p] = step * kPts + 16 * p + ln;
             const long long q = min(pt[p], n - 1);
             const float px = qx[q * qs], py = qy[q * qs], pz = qz[q * qs];
 #pragma unroll
@@ -506,14 +546,14 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_infer(Dev P, const float* 
         for (int l = 0; l < 4; ++l) {
             const int kb = l == 0 ? 2 : 4;
             const v8bf* W = sWi + (l == 0 ? 0 : (8192 + (l - 1) * 16384) / 8);
-            v8bf Y[2][4];
+            v8bf Y[NT][4];
 #pragma unroll
             for (int bo = 0; bo < 4; ++bo) {   // output tiles 2bo, 2bo+1 = block bo of the next input
-                v4f acc[2][2];
+                v4f acc[2][NT];
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
-                    for (int p = 0; p < 2; ++p) acc[h][p] = v4f{0.f, 0.f, 0.f, 0.f};
+                    for (int p = 0; p < NT; ++p) acc[h][p] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     if (b >= kb) break;
@@ -521,7 +561,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_infer(Dev P, const float* 
                     for (int h = 0; h < 2; ++h) {
                         const v8bf A = W[((2 * bo + h) * kb + b) * 64 + lane];
 #pragma unroll
-                        for (int p = 0; p < 2; ++p)
+                        for (int p = 0; p < NT; ++p)
                             acc[h][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, X[p][b], acc[h][p], 0, 0, 0);
                     }
                 }
@@ -531,17 +571,20 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_infer(Dev P, const float* 
                     for (int c = 0; c < 4; ++c) {
                         const float bias = sB[l][16 * (2 * bo + h) + 4 * g + c];
 #pragma unroll
-                        for (int p = 0; p < 2; ++p) Y[p][bo][4 * h + c] = (__bf16)gelu(acc[h][p][c] + bias);
+                        for (int p = 0; p < NT; ++p) {
+                            const float zz = acc[h][p][c] + bias;
+                            Y[p][bo][4 * h + c] = (__bf16)(POLY ? gelu_fast(zz) : gelu(zz));
+                        }
                     }
             }
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
+            for (int p = 0; p < NT; ++p)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) X[p][b] = Y[p][b];
         }
         // output layer: each lane's 32 activations, then the four lane groups of a point
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
+        for (int p = 0; p < NT; ++p) {
             float s = 0.f;
 #pragma unroll
             for (int b = 0; b < 4; ++b)
@@ -993,10 +1036,14 @@ gwn_status mlp_set_state(gwn_mlp_s* h, const float* theta, const float* m, const
 gwn_status mlp_forward(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t n,
                        float* y, hipStream_t st) {
     if (n == 0) return GWN_OK;
-    const long long steps = (n + kInferPts - 1) / kInferPts;
-    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((steps + kInferWaves - 1) / kInferWaves,
-                                                                                 256));
-    k_infer<<<blocks, 64 * kInferWaves, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
+    constexpr long long pts = 32, nw = 8;   // k_infer<2, 8>: 2 tiles of 16 points per wave, 8 waves
+    const long long steps = (n + pts - 1) / pts;
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((steps + nw - 1) / nw, 256));
+    // GWN_INFER_GELU=erf selects the erf form of GELU (the training kernels' form)
+    bool poly = true;
+    if (const char* e = std::getenv("GWN_INFER_GELU")) poly = std::string(e) != "erf";
+    if (poly) k_infer<2, 8, true><<<blocks, 64 * 8, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
+    else k_infer<2, 8, false><<<blocks, 64 * 8, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
     GWN_HIP_TRY(hipGetLastError());
     return GWN_OK;
 }
