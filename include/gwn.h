@@ -289,11 +289,13 @@ gwn_status gwn_query_direct(gwn_mesh m, const float* qx, const float* qy, const 
  *
  * gwn_multi_run replays the graph on `stream` (asynchronous).  The plan keeps
  * the pointers it was created with: the caller keeps the query arrays, w_out
- * (float, FP32 path only) and chi_out (nullable; the plan then owns a scratch
- * buffer) alive and unchanged in size until gwn_multi_destroy.  The meshes must
- * outlive the plan.  Errors: GWN_E_INVALID for bad arguments or meshes from
- * another device or an order outside 0..3, GWN_E_UNSUPPORTED for
- * prec != GWN_PREC_FP32.
+ * (float for GWN_PREC_FP32, double for GWN_PREC_FP64) and chi_out (nullable;
+ * the plan then owns a scratch buffer) alive and unchanged in size until
+ * gwn_multi_destroy.  The meshes must outlive the plan.  Per query the result
+ * is the same bits as gwn_query_batch at the same precision on that mesh alone
+ * (one lane per query; see the split-path exception above).  Errors:
+ * GWN_E_INVALID for bad arguments, an unknown prec, meshes from another device
+ * or an order outside 0..3.
  */
 typedef struct gwn_multi_s* gwn_multi;
 

@@ -298,8 +298,9 @@ gwn_status gwn_multi_create(const gwn_mesh* meshes, int32_t nmesh, const float* 
                             const float* qz, int64_t qstride, const int64_t* q_offsets, int32_t prec, void* w_out,
                             int32_t* chi_out, const gwn_multi_opts* opts, void* stream, gwn_multi* out) {
     gwn::clear_error();
-    if (!out || !meshes || !q_offsets || nmesh < 1 || qstride < 1) {
-        gwn::set_error("gwn_multi_create: null argument, nmesh < 1 or qstride < 1");
+    if (!out || !meshes || !q_offsets || nmesh < 1 || qstride < 1 ||
+        (prec != GWN_PREC_FP32 && prec != GWN_PREC_FP64)) {
+        gwn::set_error("gwn_multi_create: null argument, nmesh < 1, qstride < 1 or unknown prec");
         return GWN_E_INVALID;
     }
     *out = nullptr;

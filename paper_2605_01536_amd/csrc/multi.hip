@@ -69,12 +69,15 @@ __global__ void k_perm_offset(const int* __restrict__ local, long long i0, int n
 // Persistent boundary-term kernel: every wave claims items until none are left
 // (the counter only grows, so every wave reaches the exit).  perm (nullable):
 // position i of the work list is query perm[i], a permutation within each mesh.
+// T is the geometry precision; per query it takes the same steps, in the same
+// order, as the one-lane-per-point batch kernel, so the results are the same bits.
+template <class T>
 __global__ __launch_bounds__(256) void k_bdry_persistent(const MeshView* __restrict__ table,
                                                          const Item* __restrict__ items, int nitems,
                                                          int* __restrict__ counter, const float* __restrict__ qx,
                                                          const float* __restrict__ qy, const float* __restrict__ qz,
                                                          long long qs, const int* __restrict__ perm,
-                                                         const int* __restrict__ chi, float* __restrict__ w) {
+                                                         const int* __restrict__ chi, T* __restrict__ w) {
     const int lane = threadIdx.x & 63;
     while (true) {
         int it = 0;
@@ -93,14 +96,14 @@ __global__ __launch_bounds__(256) void k_bdry_persistent(const MeshView* __restr
             const QPoint q = quantize_point(px, py, pz, mv.g);
             double S = 0.0;
             if (q.inbox) {
-                const float pzs = pz * mv.g.scalef;
-                boundary_loops<float, 1, false>(mv, q.x, q.y, 0.f, 0.f, &pzs, &S, 1.f, near_z(pz, mv.g));
+                const T pzs = (T)pz * (T)mv.g.scale;
+                boundary_loops<T, 1, false>(mv, q.x, q.y, (T)0, (T)0, &pzs, &S, (T)1, near_z(pz, mv.g));
             } else {
-                const FarScale<float> fs = far_scale<float>(px, py, fabsf(pz), mv.g.scale);
-                const float pzs = pz * fs.scf;
-                boundary_loops<float, 1, true>(mv, 0, 0, px * fs.scf, py * fs.scf, &pzs, &S, fs.f);
+                const FarScale<T> fs = far_scale<T>(px, py, fabsf(pz), mv.g.scale);
+                const T pzs = (T)pz * fs.scf;
+                boundary_loops<T, 1, true>(mv, 0, 0, (T)px * fs.scf, (T)py * fs.scf, &pzs, &S, fs.f);
             }
-            if (k < I.nq) w[i] = (float)((double)chi[i] + S * kInv2Pi);
+            if (k < I.nq) w[i] = (T)((double)chi[i] + S * kInv2Pi);
         }
     }
 }
@@ -128,7 +131,8 @@ struct gwn_multi_s {
     std::vector<long long> qoff_h;
     const float *qx = nullptr, *qy = nullptr, *qz = nullptr;
     long long qs = 1;
-    float* w = nullptr;
+    int prec = GWN_PREC_FP32;
+    void* w = nullptr;   // float (GWN_PREC_FP32) or double (GWN_PREC_FP64)
     int* chi = nullptr;
     bool own_chi = false;
     gwn::MeshView* table = nullptr;
@@ -238,9 +242,14 @@ gwn_status capture(gwn_multi_s* p, const Schedule& s) {
     if (p->nq > 0) {
         k_chi_multi<<<(unsigned)((p->nq + kMultiChiBlock - 1) / kMultiChiBlock), kMultiChiBlock, 0, p->cap>>>(
             p->table, p->qoff, p->nmesh, p->qx, p->qy, p->qz, p->qs, p->chi);
-        k_bdry_persistent<<<p->grid, 256, 0, p->cap>>>(p->table, p->items, p->nitems, p->counter, p->qx, p->qy,
-                                                       p->qz, p->qs, (s.order & kOrderSorted) ? p->perm : nullptr,
-                                                       p->chi, p->w);
+        const int* perm = (s.order & kOrderSorted) ? p->perm : nullptr;
+        if (p->prec == GWN_PREC_FP64)
+            k_bdry_persistent<double><<<p->grid, 256, 0, p->cap>>>(p->table, p->items, p->nitems, p->counter, p->qx,
+                                                                   p->qy, p->qz, p->qs, perm, p->chi,
+                                                                   (double*)p->w);
+        else
+            k_bdry_persistent<float><<<p->grid, 256, 0, p->cap>>>(p->table, p->items, p->nitems, p->counter, p->qx,
+                                                                  p->qy, p->qz, p->qs, perm, p->chi, (float*)p->w);
     }
     hipError_t e = hipStreamEndCapture(p->cap, &p->graph);
     GWN_HIP_TRY(e);
@@ -284,7 +293,8 @@ std::string cache_key(const gwn_multi_s* p) {
     const size_t colon = arch.find(':');
     if (colon != std::string::npos) arch = arch.substr(0, colon);
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%s|meshes=%d|q=2^%d|pairs=2^%d", arch.c_str(), p->nmesh,
+    std::snprintf(buf, sizeof(buf), "%s|%s|meshes=%d|q=2^%d|pairs=2^%d", arch.c_str(),
+                  p->prec == GWN_PREC_FP64 ? "fp64" : "fp32", p->nmesh,
                   (int)std::lround(std::log2(std::max(1.0, (double)p->nq))),
                   (int)std::lround(std::log2(std::max(1.0, p->est_pairs))));
     return buf;
@@ -325,10 +335,6 @@ void cache_store(const char* path, const std::string& key, const Schedule& s, do
 gwn_status multi_create(const gwn_mesh* meshes, int nmesh, const float* qx, const float* qy, const float* qz,
                         int64_t qs, const int64_t* q_offsets, int prec, void* w_out, int32_t* chi_out,
                         const gwn_multi_opts* opts, hipStream_t st, gwn_multi_s** out) {
-    if (prec != GWN_PREC_FP32) {
-        set_error("gwn_multi_create: only GWN_PREC_FP32 is implemented for the persistent kernel");
-        return GWN_E_UNSUPPORTED;
-    }
     gwn_multi_s* p = new (std::nothrow) gwn_multi_s();
     if (!p) return GWN_E_OOM;
     struct Guard {
@@ -346,7 +352,8 @@ gwn_status multi_create(const gwn_mesh* meshes, int nmesh, const float* qx, cons
     p->qy = qy;
     p->qz = qz;
     p->qs = qs;
-    p->w = (float*)w_out;
+    p->prec = prec;
+    p->w = w_out;
     p->chi = chi_out;
     if (!p->chi) {
         GWN_HIP_TRY(gwn::dmalloc((void**)&p->chi, sizeof(int) * (size_t)std::max<long long>(1, p->nq)));

@@ -323,16 +323,17 @@ class MultiPlan:
     """Captured multi-mesh evaluation: meshes[m] owns queries Q[offsets[m]:offsets[m+1]]."""
 
     def __init__(self, meshes, Q, offsets, w_out=None, chi_out=None, item_queries=0, waves_per_simd=0, order=0,
-                 autotune=False, tune_cache=None, stream=None):
+                 autotune=False, tune_cache=None, stream=None, prec="fp32"):
         import torch
         L = load()
         _load_multi(L)
+        prec = _PREC[prec]
         self._meshes = list(meshes)
         self._Q = _points(Q)
         n = int(offsets[-1])
         if len(offsets) != len(self._meshes) + 1 or self._Q.shape[0] < n:
             raise ValueError("offsets must have nmesh + 1 entries ending at most at len(Q)")
-        self.w = _out(w_out, (n,), torch.float32, Q.device, "w_out")
+        self.w = _out(w_out, (n,), torch.float64 if prec == GWN_PREC_FP64 else torch.float32, Q.device, "w_out")
         self.chi = _out(chi_out, (n,), torch.int32, Q.device, "chi_out") if chi_out is not None else None
         hs = (ctypes.c_void_p * len(self._meshes))(*[m.handle.value for m in self._meshes])
         offs = (ctypes.c_int64 * len(offsets))(*[int(o) for o in offsets])
@@ -340,7 +341,7 @@ class MultiPlan:
         opts = MultiOpts(int(item_queries), int(waves_per_simd), int(order), int(bool(autotune)), self._cache)
         base = _ptr(self._Q)
         self._h = ctypes.c_void_p()
-        _check(L.gwn_multi_create(hs, len(self._meshes), base, base + 4, base + 8, 3, offs, GWN_PREC_FP32,
+        _check(L.gwn_multi_create(hs, len(self._meshes), base, base + 4, base + 8, 3, offs, int(prec),
                                   _ptr(self.w), _ptr(self.chi) if self.chi is not None else None,
                                   ctypes.byref(opts), _stream(stream), ctypes.byref(self._h)))
 

@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 from paper_2605_01536_amd import workloads as W
-from tests._util import TOL_FP32, compare
+from tests._util import TOL_FP32, TOL_FP64, compare
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -122,3 +122,56 @@ def test_multi_rejects_bad_arguments(gwn):
         with pytest.raises(gwn.GwnError) as ei:
             gwn.MultiPlan(meshes, Q, offs, order=bad)
         assert ei.value.status == 1
+
+
+def test_multi_fp64_equals_single_mesh_path_and_oracle(gwn, monkeypatch):
+    # FP64 geometry in the persistent kernel: bit for bit the FP64 batch path
+    # (ordinary, far-in-z and far-in-x/y queries), and the oracle within TOL_FP64
+    monkeypatch.setenv("GWN_SPLIT_BOUNDARY", "0")
+    soups, queries, meshes, offs, Q = _batch_of(gwn, 10, seed=38, q_range=(300, 2000))
+    Qh = Q.cpu().numpy()
+    rng = np.random.default_rng(11)
+    pick = rng.choice(Qh.shape[0], Qh.shape[0] // 4, replace=False)
+    Qh[pick[0::2], 2] = np.float32(1e6)
+    Qh[pick[1::2], 0] = np.float32(-4e7)
+    Q = torch.from_numpy(Qh).cuda()
+    chi = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
+    plan = gwn.MultiPlan(meshes, Q, offs, chi_out=chi, prec="fp64")
+    w = plan.run().clone()
+    torch.cuda.synchronize()
+    assert w.dtype == torch.float64 and torch.isfinite(w).all()
+    w32 = gwn.MultiPlan(meshes, Q, offs).run()
+    for m, s in enumerate(soups):
+        a, b = int(offs[m]), int(offs[m + 1])
+        wb, cb = gwn.query_batch(meshes[m], Q[a:b], prec="fp64", want_chi=True)
+        assert torch.equal(cb, chi[a:b])
+        assert torch.equal(wb, w[a:b])
+        idx = rng.choice(b - a, min(200, b - a), replace=False)
+        ti = torch.from_numpy(idx).cuda()
+        compare(w[a:b][ti].cpu().numpy(), chi[a:b][ti].cpu().numpy(), s.V, s.F, Qh[a:b][idx], TOL_FP64,
+                f"multi fp64 mesh {m}")
+    # the two precisions agree to the FP32 bound
+    assert float((w32.double() - w).abs().max()) < TOL_FP32
+
+
+@pytest.mark.parametrize("sched", [dict(item_queries=64, waves_per_simd=2, order=1),
+                                   dict(item_queries=256, waves_per_simd=8, order=2)])
+def test_schedules_agree_fp64(gwn, sched):
+    soups, queries, meshes, offs, Q = _batch_of(gwn, 8, seed=39)
+    ref = gwn.MultiPlan(meshes, Q, offs, prec="fp64").run().clone()
+    assert torch.equal(gwn.MultiPlan(meshes, Q, offs, prec="fp64", **sched).run(), ref)
+
+
+def test_multi_rejects_unknown_precision(gwn):
+    import ctypes
+    soups, queries, meshes, offs, Q = _batch_of(gwn, 2, seed=40)
+    L = gwn.load()
+    gwn.MultiPlan(meshes, Q, offs).close()          # binds the multi entry points
+    hs = (ctypes.c_void_p * 2)(*[m.handle.value for m in meshes])
+    o = (ctypes.c_int64 * 3)(*[int(x) for x in offs])
+    w = torch.empty(int(offs[-1]), dtype=torch.float64, device="cuda")
+    h = ctypes.c_void_p()
+    base = Q.data_ptr()
+    st = L.gwn_multi_create(hs, 2, base, base + 4, base + 8, 3, o, 2, w.data_ptr(), None, None, None,
+                            ctypes.byref(h))
+    assert st == 1 and not h.value
