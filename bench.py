@@ -78,11 +78,13 @@ I_MIN_GRAD = 10 + 29 + 4 * TRANS_SLOTS     # = 51
 # Dense bf16 MFMA peak of MI355X (no sparsity), for the surrogate network
 PEAK_BF16 = 2.5e15
 # The network's VALU work per point, which bounds it before the MFMA work does:
-# 512 GELU activations at 11 slots (bias add into the clamp, the square, 7 FMAs
-# of the polynomial, fma(zc, P, 1/2), the product; plus half a packed bf16
-# conversion counted with the bias add), 32 sincos of the Fourier features at
-# ~21, and the 128-term output dot product with bf16 widening (256)
-NET_VALU_SLOTS = 512 * 11 + 32 * 21 + 256     # = 6,560 per point
+# 512 GELU activations at 11.5 slots (the clamp, the square, 7 FMAs of the
+# polynomial, fma(zc, P, 1/2), the product, half a packed bf16 conversion; the
+# bias enters through the matrix product's accumulator), 32 frequencies of the
+# Fourier features at 12 (the argument, 3; its fractional part, 1; the hardware
+# sine and cosine, 3 each; two halves of a bf16 conversion, 1) and the 128-term
+# output dot product with bf16 widening (256)
+NET_VALU_SLOTS = 512 * 11.5 + 32 * 12 + 256     # = 6,528 per point
 # HBM bytes moved per k_grid<float, 8> launch on the default workload (512^3 grid,
 # 1.05M-triangle soup), from two rocprofv3 --pmc passes over this command:
 # FETCH_SIZE 231,887.25 KiB and WRITE_SIZE 524,288.0 KiB per dispatch, scaled by

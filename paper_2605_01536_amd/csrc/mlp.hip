@@ -1,9 +1,9 @@
 // mlp.hip -- learned surrogate for far-field winding-number queries:
 // Fourier features gamma(p) = [sin 2piGp, cos 2piGp] (G: 32x3, fixed), four
 // GELU layers 64->128->128->128->128 and a linear output 128->1.  Matrix
-// products run on MFMA (v_mfma_f32_16x16x32_bf16) with bf16 operands and fp32
-// accumulation: the training kernels on LDS tiles, inference (k_infer) with
-// the activations kept in registers.
+// products run on MFMA with bf16 operands and fp32 accumulation: the training
+// kernels on LDS tiles (v_mfma_f32_16x16x32_bf16), inference (k_infer) with
+// the activations kept in registers (v_mfma_f32_32x32x16_bf16).
 // Inference evaluates GELU by a minimax polynomial of Phi (gelu_fast, within
 // 5.3e-5 |z| of the erf form), training by the erf form (Abramowitz & Stegun
 // 7.1.26, 1.5e-7).  FP32 master weights are updated by Adam and re-packed into bf16 copies in
@@ -11,11 +11,9 @@
 // re-evaluates every point whose prediction lies within `band` of 1/2 with the
 // exact kernels, and scatters those results back.
 //
-// MFMA 16x16x16 operand layout (wave64): lane l holds A[l%16][4(l/16)+i] and
-// B[4(l/16)+i][l%16] (i = 0..3); the result D[4(l/16)+i][l%16] lands in
-// component i of the lane's accumulator.  The 16x16x32 form holds 8 k values
-// per lane (slot j of lane group l/16) with the same row, column and result
-// placement.
+// MFMA 16x16x32 operand layout (wave64): lane l holds A[l%16][8(l/16)+j] and
+// B[8(l/16)+j][l%16] (j = 0..7); the result D[4(l/16)+i][l%16] lands in
+// component i of the lane's accumulator (i = 0..3).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -48,8 +46,6 @@ static_assert(off_w(0) == kOffW[0] && off_w(1) == kOffW[1] && off_w(2) == kOffW[
 static_assert(off_b(0) == kOffB[0] && off_b(1) == kOffB[1] && off_b(2) == kOffB[2] && off_b(3) == kOffB[3] &&
               off_b(4) == kOffB[4], "bias offsets");
 constexpr int kTile = 64;        // points per workgroup tile (4 waves x 16 rows)
-constexpr int kInferShape = 0;   // k_infer shape: 0 = 2 tiles x 8 waves, 1 = 1 x 12, 2 = 1 x 16
-constexpr bool kInferPolyGelu = true;    // k_infer GELU: the polynomial form (gelu_fast) or the erf form
 constexpr int kLd = 136;         // padded LDS row (bf16) for 128-wide operands
 constexpr int kLd0 = 72;         // padded LDS row for the 64-wide first layer
 constexpr int kChunk = 256;      // batch rows per weight-gradient workgroup
@@ -465,50 +461,110 @@ __global__ void k_reduce(const float* __restrict__ part, int nchunk, float* __re
 // ---- inference: the activations never leave registers
 //
 // Each hidden layer is computed transposed, H_out^T = W^T H_in^T, with
-// v_mfma_f32_16x16x32_bf16: A = 16 output features x 32 input features of the
-// weights, B = 32 input features x 16 points of the activations, D = 16 output
-// features x 16 points (lane n + 16g holds features 4g..4g+3 of the tile for
-// point n).  Which input feature sits in fragment slot (g, j) is free as long as
-// A and B agree, so the input features of block b are numbered
-//   kappa(b, g, j) = 32 b + 4 g + j       (j < 4)   -- rows of output tile 2b
-//                  = 32 b + 16 + 4 g + j - 4 (j >= 4) -- rows of output tile 2b+1
-// and a lane's outputs of tiles 2b, 2b+1 ARE its B fragment of block b for the
-// next layer.  The Fourier features of the first layer use kappa0(b, g, j) =
-// 32 b + 8 g + j (block 0: sines, block 1: cosines of frequencies 8g..8g+7).
-// The weights are packed once per update into these A fragments, 16 bytes per
-// lane, in the order the kernel reads them.
+// v_mfma_f32_32x32x16_bf16: A = 32 output features x 16 input features of the
+// weights, B = 16 input features x 32 points of the activations, D = 32 output
+// features x 32 points.  Operand layout (wave64): lane l holds A[l%32][8(l/32)+i]
+// and B[8(l/32)+i][l%32] (i = 0..7); D[8j + 4(l/32) + i][l%32] lands in
+// accumulator component 4j + i (j, i = 0..3).  Which input feature sits in B
+// slot (h = l/32, i) of K-block kb is free as long as A agrees, so the hidden
+// layers number them
+//   kappa(kb, h, i) = 16 kb + 8 (i / 4) + 4 h + i % 4,
+// which makes a lane's accumulator components 0..7 of output tile T its B
+// fragment of K-block 2T and components 8..15 that of K-block 2T+1: one layer's
+// output is the next layer's operand without any data movement.  The Fourier
+// features use kappa0(b, h, i) = 32 (b / 2) + 16 h + 8 (b % 2) + i (K-blocks 0
+// and 1: sines, 2 and 3: cosines; lane half h computes frequencies 16h..16h+15
+// of its point).  The weights are packed once per update into these A
+// fragments, 16 bytes per lane, in the order the kernel reads them; the bias
+// enters as the accumulator input of each output tile's first product.
 __host__ __device__ inline int infer_slot(int l, int k, int o) {
-    const int kb = l == 0 ? 2 : 4;
-    const int b = k / 32, r = k % 32;
-    int g, j;
+    int kb, h, i;
     if (l == 0) {
-        g = r / 8;
-        j = r % 8;
+        const int r = k % 32;
+        kb = 2 * (k / 32) + (r % 16) / 8;
+        h = r / 16;
+        i = r % 8;
     } else {
-        g = (r % 16) / 4;
-        j = 4 * (r / 16) + r % 4;
+        const int r = k % 16;
+        kb = k / 16;
+        h = (r % 8) / 4;
+        i = 4 * (r / 8) + r % 4;
     }
+    const int nkb = l == 0 ? 4 : 8;
     const int base = l == 0 ? 0 : 8192 + (l - 1) * 16384;
-    const int frag = (o / 16) * kb + b, lane = o % 16 + 16 * g;
-    return base + (frag * 64 + lane) * 8 + j;
+    const int frag = (o / 32) * nkb + kb, lane = o % 32 + 32 * h;
+    return base + (frag * 64 + lane) * 8 + i;
 }
 
-// input feature held in slot j of block b by lane group g (hidden layers)
-__device__ __forceinline__ int kappa(int b, int g, int j) { return 32 * b + (j < 4 ? 4 * g + j : 12 + 4 * g + j); }
+// input feature held in slot i of K-block kb by lane half h (hidden layers)
+__device__ __forceinline__ int kappa(int kb, int h, int i) { return 16 * kb + 8 * (i >> 2) + 4 * h + (i & 3); }
 
-// NT 16-point tiles per wave and step (NT = 2: each A fragment read from LDS
-// serves two tiles), NW waves per workgroup sharing one copy of the weights in
-// LDS (one workgroup per CU).  NT = 2, NW = 8 holds 206 VGPRs (2 waves per
-// SIMD); one tile per wave with 12 or 16 waves (3 or 4 per SIMD, 152 or 128
-// VGPRs) measured 2-5% slower.  POLY: the polynomial GELU (gelu_fast), else the
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// sin(2 pi t) and cos(2 pi t) from the hardware sine and cosine, which take
+// their argument in revolutions, after reducing t to its fractional part
+__device__ __forceinline__ void sincos_rev(float t, float& s, float& c) {
+    const float f = __builtin_amdgcn_fractf(t);
+    s = __builtin_amdgcn_sinf(f);
+    c = __builtin_amdgcn_cosf(f);
+}
+
+// One layer for NT tiles of 32 points: X (NKB K-blocks) -> Y (8 K-blocks).
+// The output tiles are software-pipelined: the products of tile T are issued
+// before the activations of tile T - 1 are evaluated, so the matrix core works
+// while the vector unit evaluates GELU.
+template <int NKB, int NT, bool POLY>
+__device__ __forceinline__ void infer_layer(const v8bf* __restrict__ W, const float* __restrict__ bias, int lane,
+                                            int h, const v8bf (&X)[NT][8], v8bf (&Y)[NT][8]) {
+    v16f acc[2][NT];
+#pragma unroll
+    for (int T = 0; T <= 4; ++T) {
+        // a scheduling fence per output tile: without it the scheduler hoists
+        // every weight fragment of the layer and runs out of registers
+        __builtin_amdgcn_sched_barrier(0);
+        if (T < 4) {
+            v16f b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float4 v = *(const float4*)(bias + 32 * T + 8 * j + 4 * h);
+                b[4 * j] = v.x;
+                b[4 * j + 1] = v.y;
+                b[4 * j + 2] = v.z;
+                b[4 * j + 3] = v.w;
+            }
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb) {
+                const v8bf A = W[(T * NKB + kb) * 64 + lane];
+#pragma unroll
+                for (int p = 0; p < NT; ++p)
+                    acc[T & 1][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, X[p][kb], kb == 0 ? b : acc[T & 1][p],
+                                                                            0, 0, 0);
+            }
+        }
+        if (T > 0) {
+            const int U = T - 1;
+#pragma unroll
+            for (int p = 0; p < NT; ++p)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const float z = acc[U & 1][p][e];
+                    Y[p][2 * U + (e >> 3)][e & 7] = (__bf16)(POLY ? gelu_fast(z) : gelu(z));
+                }
+        }
+    }
+}
+
+// NT tiles of 32 points per wave and step (each A fragment read from LDS
+// serves NT tiles), NW waves per workgroup sharing one copy of the weights in
+// LDS (one workgroup per CU).  POLY: the polynomial GELU (gelu_fast), else the
 // erf form of the training kernels.
 template <int NT, int NW, bool POLY>
 __global__ __launch_bounds__(64 * NW) void k_infer(Dev P, const float* __restrict__ qx, const float* __restrict__ qy,
                                                    const float* __restrict__ qz, long long qs, long long n,
                                                    float* __restrict__ y) {
-    constexpr int kPts = 16 * NT;   // points per wave per step
+    constexpr int kPts = 32 * NT;   // points per wave per step
     __shared__ v8bf sWi[kWi / 8];
-    __shared__ float sB[4][128];
+    __shared__ __attribute__((aligned(16))) float sB[4][128];
     __shared__ float sW4[128];
     __shared__ float sG[96];
     {
@@ -523,80 +579,43 @@ __global__ __launch_bounds__(64 * NW) void k_infer(Dev P, const float* __restric
     if (threadIdx.x < 96) sG[threadIdx.x] = P.G[threadIdx.x];
     const float b4 = P.master[kOffB[4]];
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, ln = lane & 15, g = lane >> 4;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, ln = lane & 31, h = lane >> 5;
     for (long long step = (long long)blockIdx.x * NW + wave; step * kPts < n; step += (long long)gridDim.x * NW) {
-        v8bf X[NT][4];
+        v8bf X[NT][8], Y[NT][8];
         long long pt[NT];
 #pragma unroll
-        for (int p = 0; p < NT; ++p) {   // Fourier features: frequencies 8g..8g+7 of point ln of tile p
-            pt[p] = step * kPts + 16 * p + ln;
+        for (int p = 0; p < NT; ++p) {   // Fourier features: frequencies 16h..16h+15 of point ln of tile p
+            pt[p] = step * kPts + 32 * p + ln;
             const long long q = min(pt[p], n - 1);
             const float px = qx[q * qs], py = qy[q * qs], pz = qz[q * qs];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int f = 8 * g + j;
-                const float arg = 6.283185307179586f * fmaf(sG[3 * f], px, fmaf(sG[3 * f + 1], py, sG[3 * f + 2] * pz));
-                float sn, cs;
-                sincosf(arg, &sn, &cs);
-                X[p][0][j] = (__bf16)sn;
-                X[p][1][j] = (__bf16)cs;
-            }
-        }
-#pragma unroll 1
-        for (int l = 0; l < 4; ++l) {
-            const int kb = l == 0 ? 2 : 4;
-            const v8bf* W = sWi + (l == 0 ? 0 : (8192 + (l - 1) * 16384) / 8);
-            v8bf Y[NT][4];
+            for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int bo = 0; bo < 4; ++bo) {   // output tiles 2bo, 2bo+1 = block bo of the next input
-                v4f acc[2][NT];
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int p = 0; p < NT; ++p) acc[h][p] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    if (b >= kb) break;
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const v8bf A = W[((2 * bo + h) * kb + b) * 64 + lane];
-#pragma unroll
-                        for (int p = 0; p < NT; ++p)
-                            acc[h][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, X[p][b], acc[h][p], 0, 0, 0);
-                    }
+                for (int i = 0; i < 8; ++i) {
+                    const int f = 16 * h + 8 * b + i;
+                    float sn, cs;
+                    sincos_rev(fmaf(sG[3 * f], px, fmaf(sG[3 * f + 1], py, sG[3 * f + 2] * pz)), sn, cs);
+                    X[p][b][i] = (__bf16)sn;
+                    X[p][2 + b][i] = (__bf16)cs;
                 }
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const float bias = sB[l][16 * (2 * bo + h) + 4 * g + c];
-#pragma unroll
-                        for (int p = 0; p < NT; ++p) {
-                            const float zz = acc[h][p][c] + bias;
-                            Y[p][bo][4 * h + c] = (__bf16)(POLY ? gelu_fast(zz) : gelu(zz));
-                        }
-                    }
-            }
-#pragma unroll
-            for (int p = 0; p < NT; ++p)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) X[p][b] = Y[p][b];
         }
-        // output layer: each lane's 32 activations, then the four lane groups of a point
+        infer_layer<4, NT, POLY>(sWi, sB[0], lane, h, X, Y);
+        infer_layer<8, NT, POLY>(sWi + 8192 / 8, sB[1], lane, h, Y, X);
+        infer_layer<8, NT, POLY>(sWi + (8192 + 16384) / 8, sB[2], lane, h, X, Y);
+        infer_layer<8, NT, POLY>(sWi + (8192 + 2 * 16384) / 8, sB[3], lane, h, Y, X);
+        // output layer: each lane's 64 activations, then the two lane halves of a point
 #pragma unroll
         for (int p = 0; p < NT; ++p) {
             float s = 0.f;
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+            for (int kb = 0; kb < 8; ++kb)
 #pragma unroll
-                for (int j = 0; j < 8; ++j) s = fmaf((float)X[p][b][j], sW4[kappa(b, g, j)], s);
-            s += __shfl_xor(s, 16);
+                for (int i = 0; i < 8; ++i) s = fmaf((float)X[p][kb][i], sW4[kappa(kb, h, i)], s);
             s += __shfl_xor(s, 32);
-            if (g == 0 && pt[p] < n) y[pt[p]] = s + b4;
+            if (h == 0 && pt[p] < n) y[pt[p]] = s + b4;
         }
     }
 }
-
 // bf16 copies of one master parameter in the layouts the kernels read
 __device__ __forceinline__ void pack_one(const Dev& P, int p, float w) {
     for (int l = 0; l < 4; ++l) {
@@ -1036,14 +1055,14 @@ gwn_status mlp_set_state(gwn_mlp_s* h, const float* theta, const float* m, const
 gwn_status mlp_forward(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t n,
                        float* y, hipStream_t st) {
     if (n == 0) return GWN_OK;
-    constexpr long long pts = 32, nw = 8;   // k_infer<2, 8>: 2 tiles of 16 points per wave, 8 waves
+    constexpr long long pts = 32, nw = 8;   // k_infer<1, 8>: one tile of 32 points per wave, 8 waves
     const long long steps = (n + pts - 1) / pts;
     const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((steps + nw - 1) / nw, 256));
     // GWN_INFER_GELU=erf selects the erf form of GELU (the training kernels' form)
     bool poly = true;
     if (const char* e = std::getenv("GWN_INFER_GELU")) poly = std::string(e) != "erf";
-    if (poly) k_infer<2, 8, true><<<blocks, 64 * 8, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
-    else k_infer<2, 8, false><<<blocks, 64 * 8, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
+    if (poly) k_infer<1, 8, true><<<blocks, 64 * 8, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
+    else k_infer<1, 8, false><<<blocks, 64 * 8, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
     GWN_HIP_TRY(hipGetLastError());
     return GWN_OK;
 }
