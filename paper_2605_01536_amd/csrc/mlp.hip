@@ -45,13 +45,8 @@ static_assert(off_w(0) == kOffW[0] && off_w(1) == kOffW[1] && off_w(2) == kOffW[
               off_w(4) == kOffW[4], "weight offsets");
 static_assert(off_b(0) == kOffB[0] && off_b(1) == kOffB[1] && off_b(2) == kOffB[2] && off_b(3) == kOffB[3] &&
               off_b(4) == kOffB[4], "bias offsets");
-constexpr int kTile = 64;        // points per workgroup tile (4 waves x 16 rows)
-constexpr int kLd = 136;         // padded LDS row (bf16) for 128-wide operands
-constexpr int kLd0 = 72;         // padded LDS row for the 64-wide first layer
-constexpr int kChunk = 256;      // batch rows per weight-gradient workgroup
-constexpr int kLdC = kChunk + 8;   // 16-byte aligned rows (528 bytes)
 constexpr int kWf = 128 * 64 + 3 * 128 * 128 + 128;   // forward bf16 copy: Wt0..Wt3 ([out][in]) + w4
-constexpr int kWb = 3 * 128 * 128;                    // backward bf16 copy: W1..W3 ([in][out])
+constexpr int kWb = 3 * 128 * 128;                    // backward copy: W1..W3 as MFMA A fragments
 constexpr int kWi = 128 * 64 + 3 * 128 * 128;         // inference copy: W0..W3 as MFMA A fragments
 
 struct Dev {
@@ -65,15 +60,15 @@ struct Dev {
 };
 
 struct Train {
-    unsigned short* x;   // 5 x n x 128 (x0 uses the first 64 columns)
-    float* z;            // 4 x n x 128
-    unsigned short* dz;  // 4 x n x 128
-    float* y;            // n
-    float* dy;           // n
-    float* tb;           // n: the batch's targets, in batch order
-    float* part;         // nchunk x (kNParams + 1)   (last entry: loss partial)
+    unsigned short* x;   // X: tiles x 36 K-blocks (fragment layout, bf16)
+    unsigned short* g;   // G: tiles x 32 K-blocks
+    unsigned short* dz;  // DZ: tiles x 32 K-blocks
+    float* y;            // tiles x 32
+    float* dy;           // tiles x 32: dL/dy, 0 beyond the batch
+    float* tb;           // tiles x 32: the batch's targets, in batch order
+    float* part;         // nchunk x (kNParams + 1)   (last entry: sum of (dL/dy)^2)
     float* grad;         // kNParams + 1
-    long long cap;
+    long long cap;       // points (a multiple of 32)
 };
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
@@ -187,275 +182,37 @@ __device__ __forceinline__ float gelu_fast(float z) {
     for (int i = 1; i < 8; ++i) p = fmaf(p, x, kGeluP[i]);
     return z * fmaf(zc, p, 0.5f);
 }
-__device__ __forceinline__ float gelu_grad(float z) {
-    float phi, e;
-    gelu_parts(z, phi, e);
-    return fmaf(z * 0.39894228040143268f, e, phi);
-}
 
-// acc[t] += A(16 rows of this wave, K) x B(K, 16t..16t+15) for t = 0..7;
-// A rows come from sA (row-major, ld lda), B from sBt stored column-major as
-// [col][k] (ld ldb).  v_mfma_f32_16x16x32_bf16: each lane reads 8 consecutive k
-// of its row (A) and of its column (B) as one 16-byte load, so K is a multiple
-// of 32 and both leading dimensions keep rows 16-byte aligned.
-template <int K>
-__device__ __forceinline__ void mma_rows16(const unsigned short* sA, int lda, const unsigned short* sBt, int ldb,
-                                           int arow, v4f* acc) {
-    static_assert(K % 32 == 0, "K must be a multiple of 32");
-    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+// Sum of the chunks' partial gradients of parameter p, four chunks in flight
+__device__ __forceinline__ float chunk_sum(const float* __restrict__ part, int nchunk, int p) {
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    int c = 0;
+    for (; c + 4 <= nchunk; c += 4)
 #pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        const v8bf a = *(const v8bf*)(sA + (arow + lr) * lda + k0 + 8 * lg);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const v8bf b = *(const v8bf*)(sBt + (16 * t + lr) * ldb + k0 + 8 * lg);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-        }
-    }
-}
-
-// Training forward pass: the layer inputs (bf16) and pre-activations (fp32)
-// are kept for the backward pass.  Every workgroup stages all bf16 weights in
-// LDS once, then walks its tiles of 64 points; each wave owns 16 rows and only
-// ever touches its own rows of the activation tile.
-__global__ __launch_bounds__(256) void k_fwd(Dev P, Src S, long long n, Train T) {
-    __shared__ __attribute__((aligned(16))) unsigned short sW0[128 * kLd0];
-    __shared__ __attribute__((aligned(16))) unsigned short sW[3][128 * kLd];
-    __shared__ __attribute__((aligned(16))) unsigned short sA[kTile * kLd];
-    __shared__ float sW4[128];
-    __shared__ float sB[4][128];
-    __shared__ float sG[96];
-    // weights staged 16 bytes (8 bf16) per load; padded rows stay 16-byte aligned
-    for (int i = threadIdx.x; i < 128 * 8; i += 256)
-        ((uint4*)(sW0 + (i >> 3) * kLd0))[i & 7] = ((const uint4*)P.wf)[i];
-    for (int l = 0; l < 3; ++l)
-        for (int i = threadIdx.x; i < 128 * 16; i += 256)
-            ((uint4*)(sW[l] + (i >> 4) * kLd))[i & 15] = ((const uint4*)(P.wf + 8192 + l * 16384))[i];
-    for (int i = threadIdx.x; i < 128; i += 256) {
-        sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
-        for (int l = 0; l < 4; ++l) sB[l][i] = P.master[kOffB[l] + i];
-    }
-    if (threadIdx.x < 96) sG[threadIdx.x] = P.G[threadIdx.x];
-    const float b4 = P.master[kOffB[4]];
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-    const int r0 = wave * 16;
-    for (long long tile = blockIdx.x; tile * kTile < n; tile += gridDim.x) {
-        const long long base = tile * kTile + r0;
-        {   // Fourier features of this wave's 16 points; lane: point lr, frequencies 8lg..8lg+7
-            const long long pi = src_index(S, S.off + min(base + lr, n - 1));
-            const float px = S.qx[pi * S.qs], py = S.qy[pi * S.qs], pz = S.qz[pi * S.qs];
-            if (lg == 0 && base + lr < n) T.tb[base + lr] = S.tgt[pi];
-#pragma unroll
-            for (int f = 8 * lg; f < 8 * lg + 8; ++f) {
-                const float arg = 6.283185307179586f * fmaf(sG[3 * f], px, fmaf(sG[3 * f + 1], py, sG[3 * f + 2] * pz));
-                float s, c;
-                sincosf(arg, &s, &c);
-                const unsigned short bs = f2bf(s), bc = f2bf(c);
-                sA[(r0 + lr) * kLd + f] = bs;
-                sA[(r0 + lr) * kLd + kFreq + f] = bc;
-                if (base + lr < n) {
-                    T.x[(base + lr) * 128 + f] = bs;
-                    T.x[(base + lr) * 128 + kFreq + f] = bc;
-                }
-            }
-        }
-        __syncthreads();
-        v4f acc[8];
-        for (int l = 0; l < 4; ++l) {
-            if (l == 0) mma_rows16<64>(sA, kLd, sW0, kLd0, r0, acc);
-            else mma_rows16<128>(sA, kLd, sW[l - 1], kLd, r0, acc);
-            __syncthreads();   // every lane's reads of this wave's rows are done before they are overwritten
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int c = 16 * t + lr;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = r0 + 4 * lg + i;
-                    const float zz = acc[t][i] + sB[l][c];
-                    const unsigned short xb = f2bf(gelu(zz));
-                    sA[r * kLd + c] = xb;
-                    if (tile * kTile + r < n) {
-                        const long long row = tile * kTile + r;
-                        T.z[((long long)l * T.cap + row) * 128 + c] = zz;
-                        T.x[((long long)(l + 1) * T.cap + row) * 128 + c] = xb;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        {   // output layer: 4 lanes per row, 32 columns each
-            const int r = r0 + (lane >> 2);
-            const int c0 = (lane & 3) * 32;
-            float s = 0.f;
-#pragma unroll 8
-            for (int c = c0; c < c0 + 32; ++c) s = fmaf(bf2f(sA[r * kLd + c]), sW4[c], s);
-            s += __shfl_xor(s, 1);
-            s += __shfl_xor(s, 2);
-            const long long row = tile * kTile + r;
-            if ((lane & 3) == 0 && row < n) T.y[row] = s + b4;
-        }
-        __syncthreads();
-    }
-}
-
-// Backward pass through the activations: dy, then dz_3 .. dz_0 (bf16, row-major).
-__global__ __launch_bounds__(256) void k_bwd(Dev P, long long n, float inv_n, Train T) {
-    __shared__ __attribute__((aligned(16))) unsigned short sW[3][128 * kLd];   // W1..W3 as [in][out]
-    __shared__ __attribute__((aligned(16))) unsigned short sA[kTile * kLd];
-    __shared__ float sW4[128];
-    for (int l = 0; l < 3; ++l)
-        for (int i = threadIdx.x; i < 128 * 16; i += 256)
-            ((uint4*)(sW[l] + (i >> 4) * kLd))[i & 15] = ((const uint4*)(P.wb + l * 16384))[i];
-    for (int i = threadIdx.x; i < 128; i += 256) sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-    const int r0 = wave * 16;
-    for (long long tile = blockIdx.x; tile * kTile < n; tile += gridDim.x) {
-        // dz_3 = (dy w4) * gelu'(z_3), in the accumulator layout.  Every load is
-        // issued before the first store (the stores could alias them, so the
-        // compiler would otherwise wait out one load latency per element).
-        float dyr[4], zr[8][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const long long row = tile * kTile + r0 + 4 * lg + i;
-            dyr[i] = row < n ? 2.f * (T.y[row] - T.tb[row]) * inv_n : 0.f;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) zr[t][i] = row < n ? T.z[(3 * T.cap + row) * 128 + 16 * t + lr] : 0.f;
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int c = 16 * t + lr;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = r0 + 4 * lg + i;
-                const long long row = tile * kTile + r;
-                if (t == 0 && lr == 0 && row < n) T.dy[row] = dyr[i];
-                const unsigned short b = f2bf(row < n ? dyr[i] * sW4[c] * gelu_grad(zr[t][i]) : 0.f);
-                sA[r * kLd + c] = b;
-                if (row < n) T.dz[(3 * T.cap + row) * 128 + c] = b;
-            }
-        }
-        __syncthreads();
-        v4f acc[8];
-        for (int l = 3; l >= 1; --l) {
-            // dx_l = dz_l W_l^T: B[k][j] = W_l[j][k] is row j of W_l ([in][out])
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {   // z of the layer below, loaded before the stores
-                const long long row = tile * kTile + r0 + 4 * lg + i;
-#pragma unroll
-                for (int t = 0; t < 8; ++t)
-                    zr[t][i] = row < n ? T.z[((long long)(l - 1) * T.cap + row) * 128 + 16 * t + lr] : 0.f;
-            }
-            mma_rows16<128>(sA, kLd, sW[l - 1], kLd, r0, acc);
-            __syncthreads();
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int c = 16 * t + lr;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = r0 + 4 * lg + i;
-                    const long long row = tile * kTile + r;
-                    const unsigned short b = f2bf(row < n ? acc[t][i] * gelu_grad(zr[t][i]) : 0.f);
-                    sA[r * kLd + c] = b;
-                    if (row < n) T.dz[((long long)(l - 1) * T.cap + row) * 128 + c] = b;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// Weight gradients of one layer for one chunk of rows: dW = x^T dz on MFMA,
-// db = column sums; blockIdx.y = layer (4 = output layer on the VALU).
-__global__ __launch_bounds__(256) void k_wgrad(long long n, Train T) {
-    __shared__ __attribute__((aligned(16))) unsigned short sXt[128 * kLdC];
-    __shared__ __attribute__((aligned(16))) unsigned short sDt[128 * kLdC];
-    const int layer = blockIdx.y;
-    const long long c0 = (long long)blockIdx.x * kChunk;
-    float* part = T.part + (long long)blockIdx.x * (kNParams + 1);
-    if (layer == 4) {
-        // output layer: column j of x4 against dy, rows split between the two
-        // halves of the block; no early exit, so the loads of many rows are in
-        // flight at once
-        __shared__ float sh[3][128];
-        const int j = threadIdx.x & 127, half = threadIdx.x >> 7;
-        float s = 0.f, sb = 0.f, sl = 0.f;
-#pragma unroll 8
-        for (int m = half; m < kChunk; m += 2) {
-            const long long row = c0 + m;
-            const bool ok = row < n;
-            const float dy = ok ? T.dy[row] : 0.f;
-            const float x = ok ? bf2f(T.x[(4 * T.cap + row) * 128 + j]) : 0.f;
-            s = fmaf(x, dy, s);
-            sb += dy;
-            sl = fmaf(dy, dy, sl);
-        }
-        if (half == 1) {
-            sh[0][j] = s;
-            sh[1][j] = sb;
-            sh[2][j] = sl;
-        }
-        __syncthreads();
-        if (half == 0) {
-            part[kOffW[4] + j] = s + sh[0][j];
-            if (j == 0) {
-                part[kOffB[4]] = sb + sh[1][0];
-                part[kNParams] = sl + sh[2][0];   // sum of dy^2; the host turns it into the loss
-            }
-        }
-        return;
-    }
-    const int kin = layer == 0 ? 64 : 128;
-    // rows arrive 8 bf16 at a time and are written transposed into LDS
-    for (int idx = threadIdx.x; idx < kChunk * 16; idx += 256) {
-        const int m = idx >> 4, j0 = (idx & 15) * 8;
-        const long long row = c0 + m;
-        const bool ok = row < n;
-        // explicit branches: a select between the loaded vector and a zero one
-        // becomes a select between pointers, with the zero vector in scratch
-        uint4 xv = {0u, 0u, 0u, 0u}, dv = {0u, 0u, 0u, 0u};
-        if (ok && j0 < kin) xv = *(const uint4*)(T.x + ((long long)layer * T.cap + row) * 128 + j0);
-        if (ok) dv = *(const uint4*)(T.dz + ((long long)layer * T.cap + row) * 128 + j0);
-        const unsigned xs[4] = {xv.x, xv.y, xv.z, xv.w}, ds[4] = {dv.x, dv.y, dv.z, dv.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            if (j0 < kin) {
-                sXt[(j0 + 2 * e) * kLdC + m] = (unsigned short)(xs[e] & 0xffffu);
-                sXt[(j0 + 2 * e + 1) * kLdC + m] = (unsigned short)(xs[e] >> 16);
-            }
-            sDt[(j0 + 2 * e) * kLdC + m] = (unsigned short)(ds[e] & 0xffffu);
-            sDt[(j0 + 2 * e + 1) * kLdC + m] = (unsigned short)(ds[e] >> 16);
-        }
-    }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-    const int rows_per_wave = kin / 4;   // 16 or 32
-    for (int rt = 0; rt < rows_per_wave / 16; ++rt) {
-        const int i0 = wave * rows_per_wave + 16 * rt;
-        v4f acc[8];
-        mma_rows16<kChunk>(sXt, kLdC, sDt, kLdC, i0, acc);
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                part[off_w(layer) + (i0 + 4 * lg + v) * 128 + 16 * t + lr] = acc[t][v];
-    }
-    if (threadIdx.x < 128) {
-        float s = 0.f;
-        for (int m = 0; m < kChunk; ++m) s += bf2f(sDt[threadIdx.x * kLdC + m]);
-        part[off_b(layer) + threadIdx.x] = s;
-    }
+        for (int k = 0; k < 4; ++k) s[k] += part[(long long)(c + k) * (kNParams + 1) + p];
+    for (; c < nchunk; ++c) s[0] += part[(long long)c * (kNParams + 1) + p];
+    return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 __global__ void k_reduce(const float* __restrict__ part, int nchunk, float* __restrict__ grad) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p > kNParams) return;
-    float s = 0.f;
-    for (int c = 0; c < nchunk; ++c) s += part[(long long)c * (kNParams + 1) + p];
-    grad[p] = s;
+    grad[p] = chunk_sum(part, nchunk, p);
+}
+
+// Copy n16 16-byte words from global memory to LDS with NT threads, eight
+// loads in flight per thread (a plain loop waits out every load in turn).
+template <int NT>
+__device__ __forceinline__ void stage_lds(uint4* __restrict__ dst, const uint4* __restrict__ src, int n16) {
+    for (int base = threadIdx.x; base < n16; base += NT * 8) {
+        uint4 r[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (base + k * NT < n16) r[k] = src[base + k * NT];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (base + k * NT < n16) dst[base + k * NT] = r[k];
+    }
 }
 
 // ---- inference: the activations never leave registers
@@ -567,11 +324,7 @@ __global__ __launch_bounds__(64 * NW) void k_infer(Dev P, const float* __restric
     __shared__ __attribute__((aligned(16))) float sB[4][128];
     __shared__ float sW4[128];
     __shared__ float sG[96];
-    {
-        const uint4* src = (const uint4*)P.wi;
-        uint4* dst = (uint4*)sWi;
-        for (int i = threadIdx.x; i < kWi / 8; i += 64 * NW) dst[i] = src[i];
-    }
+    stage_lds<64 * NW>((uint4*)sWi, (const uint4*)P.wi, kWi / 8);
     for (int i = threadIdx.x; i < 128; i += 64 * NW) {
         sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
         for (int l = 0; l < 4; ++l) sB[l][i] = P.master[kOffB[l] + i];
@@ -616,6 +369,345 @@ __global__ __launch_bounds__(64 * NW) void k_infer(Dev P, const float* __restric
         }
     }
 }
+// ---- training: tiles of 32 points on the inference kernel's MFMA form
+//
+// The forward and backward passes compute every product as the inference
+// kernel does (v_mfma_f32_32x32x16_bf16, transposed, operands in the fragment
+// layout), but four waves share a tile of 32 points: wave q computes output
+// tile q (32 features) of every layer and the waves exchange the layer's
+// activations through LDS, so a tile's latency is a quarter of one wave's.
+// What the weight gradients need goes to HBM in the fragment layout, 16 bytes
+// per lane and K-block (a contiguous kilobyte per wave and K-block):
+//   X   the inputs of the five layers, bf16: the features (4 K-blocks), then
+//       the four GELU outputs (8 K-blocks each)                    36 K-blocks
+//   G   GELU'(z) of the four GELU layers, bf16                      32 K-blocks
+//   DZ  dL/dz of the four GELU layers, bf16                         32 K-blocks
+// K-block kb of tile t of a tensor with nkb K-blocks per tile sits at element
+// ((t nkb + kb) 64 + lane) 8; lane (n, h) holds slots i = 0..7 of point 32 t + n
+// (features kappa0(kb, h, i) for the first layer's input, kappa(kb, h, i)
+// otherwise).  Rows beyond the batch carry dL/dy = 0, so their terms vanish.
+constexpr int kXkb = 36, kGkb = 32;
+__host__ __device__ constexpr int x_kb0(int l) { return l == 0 ? 0 : 4 + 8 * (l - 1); }
+
+__device__ __forceinline__ void st_frag(unsigned short* base, long long t, int nkb, int kb, int lane, v8bf v) {
+    *(v8bf*)(base + ((t * nkb + kb) * 64 + lane) * 8) = v;
+}
+__device__ __forceinline__ v8bf ld_frag(const unsigned short* base, long long t, int nkb, int kb, int lane) {
+    return *(const v8bf*)(base + ((t * nkb + kb) * 64 + lane) * 8);
+}
+
+// the kappa0 feature of slot i of K-block kb for lane half h (first layer)
+__host__ __device__ inline int kappa0(int kb, int h, int i) { return 32 * (kb >> 1) + 16 * h + 8 * (kb & 1) + i; }
+
+// Backward A fragments (layers 1..3): A'[i][k] = W_l[i][o] with i an input
+// feature of output tile i / 32 and o = kappa(kb, h, slot) the output feature
+// in K-block kb, so dx^T = A' dz^T chains like the forward pass.
+__host__ __device__ inline int bwd_slot(int l, int k, int o) {
+    const int kb = o / 16, r = o % 16;
+    const int h = (r % 8) / 4, i = 4 * (r / 8) + r % 4;
+    return (l - 1) * 16384 + (((k / 32) * 8 + kb) * 64 + k % 32 + 32 * h) * 8 + i;
+}
+
+// Training forward pass: G tiles in flight per workgroup of 4G waves.  Writes
+// X, G, y, dL/dy = 2 (y - t) / n (0 beyond the batch) and the batch targets.
+template <int G>
+__global__ __launch_bounds__(256 * G) void k_tfwd(Dev P, Src S, long long n, float inv_n, Train T) {
+    __shared__ v8bf sWi[kWi / 8];
+    __shared__ v8bf sX[G][2][8][64];   // the activations of the tile, ping-pong
+    __shared__ float sP[G][4][64];     // output-layer partial sums of the four waves
+    __shared__ __attribute__((aligned(16))) float sB[4][128];
+    __shared__ float sW4[128];
+    __shared__ float sG[96];
+    stage_lds<256 * G>((uint4*)sWi, (const uint4*)P.wi, kWi / 8);
+    for (int i = threadIdx.x; i < 128; i += 256 * G) {
+        sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
+        for (int l = 0; l < 4; ++l) sB[l][i] = P.master[kOffB[l] + i];
+    }
+    if (threadIdx.x < 96) sG[threadIdx.x] = P.G[threadIdx.x];
+    const float b4 = P.master[kOffB[4]];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, ln = lane & 31, h = lane >> 5;
+    const int g = wave >> 2, q = wave & 3;
+    const long long tiles = (n + 31) / 32;
+    // every wave runs the same number of rounds (the barriers are block-wide)
+    for (long long t0 = (long long)blockIdx.x * G; t0 < tiles; t0 += (long long)gridDim.x * G) {
+        const long long t = t0 + g;
+        const bool act = t < tiles;
+        const long long row = t * 32 + ln;
+        float tg = 0.f;
+        if (act) {   // features: wave q computes K-block q (sines for q < 2, cosines otherwise)
+            const long long pi = src_index(S, S.off + min(row, n - 1));
+            const float px = S.qx[pi * S.qs], py = S.qy[pi * S.qs], pz = S.qz[pi * S.qs];
+            tg = S.tgt[pi];
+            v8bf f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int fr = 16 * h + 8 * (q & 1) + i;
+                const float a = __builtin_amdgcn_fractf(
+                    fmaf(sG[3 * fr], px, fmaf(sG[3 * fr + 1], py, sG[3 * fr + 2] * pz)));
+                f[i] = (__bf16)(q < 2 ? __builtin_amdgcn_sinf(a) : __builtin_amdgcn_cosf(a));
+            }
+            sX[g][0][q][lane] = f;
+            st_frag(T.x, t, kXkb, q, lane, f);
+        }
+        __syncthreads();
+        float part = 0.f;
+#pragma unroll 1
+        for (int l = 0; l < 4; ++l) {
+            if (act) {
+                const int nkb = l == 0 ? 4 : 8;
+                const v8bf* W = sWi + (l == 0 ? 0 : (8192 + (l - 1) * 16384) / 8);
+                v16f acc;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float4 v = *(const float4*)(&sB[l][32 * q + 8 * j + 4 * h]);
+                    acc[4 * j] = v.x;
+                    acc[4 * j + 1] = v.y;
+                    acc[4 * j + 2] = v.z;
+                    acc[4 * j + 3] = v.w;
+                }
+#pragma unroll
+                for (int kb = 0; kb < 8; ++kb)
+                    if (kb < nkb)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(W[(q * nkb + kb) * 64 + lane], sX[g][l & 1][kb][lane],
+                                                                      acc, 0, 0, 0);
+                v8bf y[2], gd[2];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    float phi, ex;
+                    gelu_parts(acc[e], phi, ex);
+                    y[e >> 3][e & 7] = (__bf16)(acc[e] * phi);
+                    gd[e >> 3][e & 7] = (__bf16)fmaf(acc[e] * 0.39894228040143268f, ex, phi);
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    st_frag(T.x, t, kXkb, x_kb0(l + 1) + 2 * q + u, lane, y[u]);
+                    st_frag(T.g, t, kGkb, 8 * l + 2 * q + u, lane, gd[u]);
+                    if (l < 3) sX[g][(l + 1) & 1][2 * q + u][lane] = y[u];
+                }
+                if (l == 3) {   // this wave's share of the output layer
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) part = fmaf((float)y[u][i], sW4[kappa(2 * q + u, h, i)], part);
+                    sP[g][q][lane] = part;
+                }
+            }
+            __syncthreads();
+        }
+        if (act && q == 0) {
+            float s = sP[g][0][lane] + sP[g][1][lane] + sP[g][2][lane] + sP[g][3][lane];
+            s += __shfl_xor(s, 32);
+            const float yv = s + b4;
+            if (h == 0) {
+                T.y[row] = yv;
+                T.dy[row] = row < n ? 2.f * (yv - tg) * inv_n : 0.f;
+                T.tb[row] = tg;
+            }
+        }
+    }
+}
+
+// Training backward pass through the activations (dz of every GELU layer):
+// dz_3 = dL/dy w4 GELU'(z_3), then dx_l^T = A'_l dz_l^T and dz_{l-1} =
+// dx_l GELU'(z_{l-1}) for l = 3, 2, 1; wave q computes input tile q.
+template <int G>
+__global__ __launch_bounds__(256 * G) void k_tbwd(Dev P, long long n, Train T) {
+    __shared__ v8bf sWb[kWb / 8];
+    __shared__ v8bf sD[G][2][8][64];
+    __shared__ float sW4[128];
+    stage_lds<256 * G>((uint4*)sWb, (const uint4*)P.wb, kWb / 8);
+    for (int i = threadIdx.x; i < 128; i += 256 * G) sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, ln = lane & 31, h = lane >> 5;
+    const int g = wave >> 2, q = wave & 3;
+    const long long tiles = (n + 31) / 32;
+    for (long long t0 = (long long)blockIdx.x * G; t0 < tiles; t0 += (long long)gridDim.x * G) {
+        const long long t = t0 + g;
+        const bool act = t < tiles;
+        if (act) {   // dz_3, K-blocks 2q and 2q+1
+            const float dy = T.dy[t * 32 + ln];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int kb = 2 * q + u;
+                const v8bf gd = ld_frag(T.g, t, kGkb, 24 + kb, lane);
+                v8bf d;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) d[i] = (__bf16)(dy * sW4[kappa(kb, h, i)] * (float)gd[i]);
+                sD[g][0][kb][lane] = d;
+                st_frag(T.dz, t, kGkb, 24 + kb, lane, d);
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int l = 3; l >= 1; --l) {
+            if (act) {
+                const int src = (3 - l) & 1;
+                const v8bf* W = sWb + (l - 1) * 16384 / 8;
+                const v8bf g0 = ld_frag(T.g, t, kGkb, 8 * (l - 1) + 2 * q, lane);
+                const v8bf g1 = ld_frag(T.g, t, kGkb, 8 * (l - 1) + 2 * q + 1, lane);
+                v16f acc = {};
+#pragma unroll
+                for (int kb = 0; kb < 8; ++kb)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(W[(q * 8 + kb) * 64 + lane], sD[g][src][kb][lane], acc,
+                                                                  0, 0, 0);
+                v8bf d[2];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    d[0][e] = (__bf16)(acc[e] * (float)g0[e]);
+                    d[1][e] = (__bf16)(acc[8 + e] * (float)g1[e]);
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    st_frag(T.dz, t, kGkb, 8 * (l - 1) + 2 * q + u, lane, d[u]);
+                    if (l > 1) sD[g][src ^ 1][2 * q + u][lane] = d[u];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Weight gradients dW_l[i][o] = sum over points of x_l[i] dz_l[o] (and the
+// bias gradients as sums of dz) for the tiles of one chunk, on MFMA with the
+// points as the contraction index.  A tensor's fragments hold points in
+// lanes; one product with an identity operand transposes a pair of K-blocks
+// (D = X I puts 32 features in the columns and the points in the rows of the
+// result, which is the operand layout the point contraction needs).  Job
+// (blockIdx.y): 0-1 the first layer's input tiles, 2-13 input tile (job - 2) % 4
+// of layer (job - 2) / 4 + 1, 14 the output layer (and the loss).
+__device__ __forceinline__ int xt_feature(int l, int I, int c) {
+    const int kb = 2 * I + (c >> 4), r = c & 15;
+    return l == 0 ? kappa0(kb, r >> 3, r & 7) : kappa(kb, r >> 3, r & 7);
+}
+
+// Four waves per workgroup take the chunk's tiles in turn and add their sums
+// through LDS in a fixed order at the end.
+constexpr int kWgW = 4;
+__global__ __launch_bounds__(64 * kWgW) void k_twgrad(long long n, int chunk_tiles, Train T) {
+    __shared__ float sAcc[kWgW - 1][68][64];   // per lane: 64 accumulator values, 4 more sums
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 31, kg = lane >> 5;
+    const int job = blockIdx.y;
+    const long long tiles = (n + 31) / 32;
+    const long long ta = (long long)blockIdx.x * chunk_tiles, tb = min(tiles, ta + chunk_tiles);
+    float* part = T.part + (long long)blockIdx.x * (kNParams + 1);
+    v8bf ilo, ihi;   // B operands: ilo[k][n] = (k == n), ihi[k][n] = (k + 16 == n)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        ilo[s] = (__bf16)(8 * kg + s == c ? 1.f : 0.f);
+        ihi[s] = (__bf16)(8 * kg + s + 16 == c ? 1.f : 0.f);
+    }
+    const v16f zero = {};
+    // transposed pair of K-blocks (a, b): raw fp32 values and their bf16 operands
+    auto transpose = [&](const v8bf& a, const v8bf& b, v8bf (&out)[2], v16f& raw) {
+        raw = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, ilo, zero, 0, 0, 0);
+        raw = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b, ihi, raw, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) out[e >> 3][e & 7] = (__bf16)raw[e];
+    };
+    v16f acc[4] = {};
+    float sums[4] = {0.f, 0.f, 0.f, 0.f};   // bias gradients, or sum dL/dy and sum (dL/dy)^2
+    if (job < 14) {
+        const int l = job < 2 ? 0 : (job - 2) / 4 + 1, I = job < 2 ? job : (job - 2) % 4;
+        for (long long t = ta + wave; t < tb; t += kWgW) {
+            v8bf cx[2], cd[8];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) cx[u] = ld_frag(T.x, t, kXkb, x_kb0(l) + 2 * I + u, lane);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cd[k] = ld_frag(T.dz, t, kGkb, 8 * l + k, lane);
+            v8bf xt[2];
+            v16f raw;
+            transpose(cx[0], cx[1], xt, raw);
+#pragma unroll
+            for (int O = 0; O < 4; ++O) {
+                v8bf dt[2];
+                transpose(cd[2 * O], cd[2 * O + 1], dt, raw);
+                if (I == 0)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) sums[O] += raw[e];
+                acc[O] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xt[0], dt[0], acc[O], 0, 0, 0);
+                acc[O] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xt[1], dt[1], acc[O], 0, 0, 0);
+            }
+        }
+    } else {
+        // output layer: dw4 = X_4^T dL/dy on MFMA (dL/dy in column 0 of B)
+        for (long long t = ta + wave; t < tb; t += kWgW) {
+            v8bf cx[8], dyb[2];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cx[k] = ld_frag(T.x, t, kXkb, x_kb0(4) + k, lane);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+                    dyb[u][s] = (__bf16)(c == 0 ? T.dy[t * 32 + 16 * u + 8 * (s >> 2) + 4 * kg + (s & 3)] : 0.f);
+            const float d = lane < 32 ? T.dy[t * 32 + lane] : 0.f;
+            sums[0] += d;
+            sums[1] = fmaf(d, d, sums[1]);
+#pragma unroll
+            for (int I = 0; I < 4; ++I) {
+                v8bf xt[2];
+                v16f raw;
+                transpose(cx[2 * I], cx[2 * I + 1], xt, raw);
+                acc[I] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xt[0], dyb[0], acc[I], 0, 0, 0);
+                acc[I] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xt[1], dyb[1], acc[I], 0, 0, 0);
+            }
+        }
+    }
+    // waves 1..3 hand their sums to wave 0, which adds them in order
+    if (wave > 0) {
+#pragma unroll
+        for (int O = 0; O < 4; ++O) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) sAcc[wave - 1][16 * O + e][lane] = acc[O][e];
+            sAcc[wave - 1][64 + O][lane] = sums[O];
+        }
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < kWgW - 1; ++w)
+#pragma unroll
+        for (int O = 0; O < 4; ++O) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[O][e] += sAcc[w][16 * O + e][lane];
+            sums[O] += sAcc[w][64 + O][lane];
+        }
+    // result: lane (column c, half kg) holds rows 8j + 4kg + i in component 4j + i
+    if (job < 14) {
+        const int l = job < 2 ? 0 : (job - 2) / 4 + 1, I = job < 2 ? job : (job - 2) % 4;
+#pragma unroll
+        for (int O = 0; O < 4; ++O) {
+            const int fo = xt_feature(1, O, c);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int r = 8 * (e >> 2) + 4 * kg + (e & 3);
+                part[off_w(l) + xt_feature(l, I, r) * 128 + fo] = acc[O][e];
+            }
+            if (I == 0) {
+                const float s = sums[O] + __shfl_xor(sums[O], 32);
+                if (kg == 0) part[off_b(l) + fo] = s;
+            }
+        }
+    } else {
+        if (c == 0)
+#pragma unroll
+            for (int I = 0; I < 4; ++I)
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    part[kOffW[4] + xt_feature(4, I, 8 * (e >> 2) + 4 * kg + (e & 3))] = acc[I][e];
+        float sdy = sums[0], sdy2 = sums[1];
+#pragma unroll
+        for (int o = 16; o >= 1; o >>= 1) {
+            sdy += __shfl_xor(sdy, o);
+            sdy2 += __shfl_xor(sdy2, o);
+        }
+        if (lane == 0) {
+            part[kOffB[4]] = sdy;
+            part[kNParams] = sdy2;   // the host turns sum (dL/dy)^2 into the loss
+        }
+    }
+}
+
 // bf16 copies of one master parameter in the layouts the kernels read
 __device__ __forceinline__ void pack_one(const Dev& P, int p, float w) {
     for (int l = 0; l < 4; ++l) {
@@ -624,7 +716,7 @@ __device__ __forceinline__ void pack_one(const Dev& P, int p, float w) {
             const int k = (p - kOffW[l]) / 128, o = (p - kOffW[l]) % 128;
             const unsigned short b = f2bf(w);
             P.wf[(l == 0 ? 0 : 8192 + (l - 1) * 16384) + o * kin + k] = b;
-            if (l >= 1) P.wb[(l - 1) * 16384 + k * 128 + o] = b;
+            if (l >= 1) P.wb[bwd_slot(l, k, o)] = b;
             P.wi[infer_slot(l, k, o)] = b;
             return;
         }
@@ -637,14 +729,18 @@ __global__ void k_pack(Dev P) {
     if (p < kNParams) pack_one(P, p, P.master[p]);
 }
 
-// loss_slot (nullable): receives the batch's mean squared error, sum(dy^2) nb / 4
-// with dy = 2 (y - t) / nb
-__global__ void k_adam(Dev P, const float* __restrict__ grad, float lr, float b1, float b2, float eps, float c1,
-                       float c2, float* __restrict__ loss_slot, float nb) {
+// One Adam step: the chunks' partial gradients summed (as k_reduce does) and
+// applied at once.  loss_slot (nullable) receives the batch's mean squared
+// error, sum(dy^2) nb / 4 with dy = 2 (y - t) / nb.
+__global__ void k_reduce_adam(Dev P, const float* __restrict__ part, int nchunk, float lr, float b1, float b2,
+                              float eps, float c1, float c2, float* __restrict__ loss_slot, float nb) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0 && loss_slot) *loss_slot = grad[kNParams] * nb * 0.25f;
-    if (p >= kNParams) return;
-    const float g = grad[p];
+    if (p > kNParams) return;
+    const float g = chunk_sum(part, nchunk, p);
+    if (p == kNParams) {
+        if (loss_slot) *loss_slot = g * nb * 0.25f;
+        return;
+    }
     const float m = b1 * P.m[p] + (1.f - b1) * g;
     const float v = b2 * P.v[p] + (1.f - b2) * g * g;
     P.m[p] = m;
@@ -817,7 +913,7 @@ namespace {
 
 void free_train(gwn_mlp_s* h) {
     (void)hipFree(h->t.x);
-    (void)hipFree(h->t.z);
+    (void)hipFree(h->t.g);
     (void)hipFree(h->t.dz);
     (void)hipFree(h->t.y);
     (void)hipFree(h->t.dy);
@@ -827,15 +923,21 @@ void free_train(gwn_mlp_s* h) {
     h->t = Train{};
 }
 
+// tiles of 32 points per weight-gradient chunk: at least 8, and at most 64
+// chunks (so the partial sums stay small next to the activations)
+long long wgrad_chunk(long long tiles) { return std::max<long long>(8, (tiles + 63) / 64); }
+
 gwn_status ensure_train(gwn_mlp_s* h, long long n) {
     if (h->t.cap >= n) return GWN_OK;
     if (h->t.x) (void)hipDeviceSynchronize();   // earlier steps may still use the buffers
     free_train(h);
-    const long long cap = std::max<long long>(n, 1024);
-    const long long nchunk = (cap + kChunk - 1) / kChunk;
-    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.x, sizeof(unsigned short) * 5 * cap * 128));
-    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.z, sizeof(float) * 4 * cap * 128));
-    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.dz, sizeof(unsigned short) * 4 * cap * 128));
+    const long long tiles = (std::max<long long>(n, 1024) + 31) / 32, cap = tiles * 32;
+    // a batch of at most `tiles` tiles has at most this many chunks (every chunk
+    // but the last holds wgrad_chunk() >= 8 tiles, and there are at most 64)
+    const long long nchunk = std::min<long long>(64, (tiles + 7) / 8);
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.x, sizeof(unsigned short) * tiles * kXkb * 512));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.g, sizeof(unsigned short) * tiles * kGkb * 512));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.dz, sizeof(unsigned short) * tiles * kGkb * 512));
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.y, sizeof(float) * cap));
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.dy, sizeof(float) * cap));
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.tb, sizeof(float) * cap));
@@ -883,11 +985,6 @@ gwn_status ensure_data(gwn_mlp_s* h, long long n) {
     return GWN_OK;
 }
 
-int fwd_grid(long long n) {
-    const long long tiles = (n + kTile - 1) / kTile;
-    return (int)std::max<long long>(1, std::min<long long>(tiles, 1024));
-}
-
 gwn_status alloc_params(gwn_mlp_s* h) {
     GWN_HIP_TRY(hipGetDevice(&h->device));
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.master, sizeof(float) * kNParams));
@@ -903,21 +1000,35 @@ gwn_status alloc_params(gwn_mlp_s* h) {
 // One optimisation step on the batch rows S.off .. S.off + n - 1: forward,
 // backward, weight gradients, their sum, then Adam at learning rate lr.
 gwn_status train_batch(gwn_mlp_s* h, const Src& S, long long n, float lr, float* loss_slot, hipStream_t st) {
-    k_fwd<<<fwd_grid(n), 256, 0, st>>>(h->d, S, n, h->t);
+    const long long tiles = (n + 31) / 32;
+    // one workgroup per CU (the weights fill its LDS); two tiles in flight per
+    // workgroup once there are enough tiles for every CU to take two
+    if (tiles >= 512) {
+        const int blocks = (int)std::min<long long>((tiles + 1) / 2, 256);
+        k_tfwd<2><<<blocks, 512, 0, st>>>(h->d, S, n, 1.0f / (float)n, h->t);
+        GWN_HIP_TRY(hipGetLastError());
+        k_tbwd<2><<<blocks, 512, 0, st>>>(h->d, n, h->t);
+    } else {
+        const int blocks = (int)std::min<long long>(tiles, 256);
+        k_tfwd<1><<<blocks, 256, 0, st>>>(h->d, S, n, 1.0f / (float)n, h->t);
+        GWN_HIP_TRY(hipGetLastError());
+        k_tbwd<1><<<blocks, 256, 0, st>>>(h->d, n, h->t);
+    }
     GWN_HIP_TRY(hipGetLastError());
-    k_bwd<<<fwd_grid(n), 256, 0, st>>>(h->d, n, 1.0f / (float)n, h->t);
+    const long long ct = wgrad_chunk(tiles);
+    const int nchunk = (int)((tiles + ct - 1) / ct);
+    k_twgrad<<<dim3(nchunk, 15), 64 * kWgW, 0, st>>>(n, (int)ct, h->t);
     GWN_HIP_TRY(hipGetLastError());
-    const int nchunk = (int)((n + kChunk - 1) / kChunk);
-    k_wgrad<<<dim3(nchunk, 5), 256, 0, st>>>(n, h->t);
-    GWN_HIP_TRY(hipGetLastError());
-    k_reduce<<<(kNParams + 1 + 255) / 256, 256, 0, st>>>(h->t.part, nchunk, h->t.grad);
-    GWN_HIP_TRY(hipGetLastError());
-    if (lr < 0.f) return GWN_OK;   // gradient only
+    if (lr < 0.f) {   // gradient only
+        k_reduce<<<(kNParams + 1 + 255) / 256, 256, 0, st>>>(h->t.part, nchunk, h->t.grad);
+        GWN_HIP_TRY(hipGetLastError());
+        return GWN_OK;
+    }
     h->step += 1;
     const float c1 = (float)(1.0 - std::pow(0.9, (double)h->step));
     const float c2 = (float)(1.0 - std::pow(0.999, (double)h->step));
-    k_adam<<<(kNParams + 255) / 256, 256, 0, st>>>(h->d, h->t.grad, lr, 0.9f, 0.999f, 1e-8f, c1, c2, loss_slot,
-                                                  (float)n);
+    k_reduce_adam<<<(kNParams + 1 + 255) / 256, 256, 0, st>>>(h->d, h->t.part, nchunk, lr, 0.9f, 0.999f, 1e-8f, c1,
+                                                             c2, loss_slot, (float)n);
     GWN_HIP_TRY(hipGetLastError());
     return GWN_OK;
 }
@@ -939,7 +1050,7 @@ Src plain_src(const float* qx, const float* qy, const float* qz, int64_t qs, con
 // ---- checkpoint file: a fixed little-endian header, the arrays, then an
 // FNV-1a 64-bit checksum of every byte before it
 constexpr char kMagic[8] = {'G', 'W', 'N', 'S', 'U', 'R', 'R', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;   // 2: the 32x32x16 fragment layouts of the bf16 copies
 
 struct FileHeader {
     char magic[8];
