@@ -506,7 +506,7 @@ gwn_status gwn_surrogate_train(gwn_surrogate h, gwn_mesh mesh, const gwn_surroga
 /*
  * gwn_surrogate_save -- write the handle's complete state to `path` (a host
  * file, replaced atomically): a fixed header (magic "GWNSURR1", format
- * version 1, sizes, Adam step count, passes done, sigma, the seeds, the data
+ * version 2, sizes, Adam step count, passes done, sigma, the seeds, the data
  * recipe and the schedule of the run in progress, the labelling mesh's
  * triangle and boundary-edge counts), then G, the fp32 master weights, the
  * Adam moments m and v, the three bf16 copies the kernels read, and an FNV-1a

@@ -68,7 +68,7 @@ def test_surrogate_checkpoint_validation_on_the_host(tmp_path):
     p = tmp_path / "junk.gwns"
     p.write_bytes(b"GWNSURR1" + bytes(300))
     assert L.gwn_surrogate_load(str(p).encode(), ctypes.byref(h)) == 1
-    assert b"not a version-1" in L.gwn_last_error()
+    assert b"not a version-2" in L.gwn_last_error()
     assert L.gwn_surrogate_save(None, str(p).encode()) == 1
     assert L.gwn_surrogate_train(None, None, None, None, None, 0, None, None, None) == 1
     assert L.gwn_surrogate_destroy(None) == 0
