@@ -61,7 +61,6 @@ struct Dev {
 
 struct Train {
     unsigned short* x;   // X: tiles x 36 K-blocks (fragment layout, bf16)
-    unsigned short* g;   // G: tiles x 32 K-blocks
     unsigned short* dz;  // DZ: tiles x 32 K-blocks
     float* y;            // tiles x 32
     float* dy;           // tiles x 32: dL/dy, 0 beyond the batch
@@ -373,20 +372,17 @@ __global__ __launch_bounds__(64 * NW) void k_infer(Dev P, const float* __restric
 //
 // The forward and backward passes compute every product as the inference
 // kernel does (v_mfma_f32_32x32x16_bf16, transposed, operands in the fragment
-// layout), but four waves share a tile of 32 points: wave q computes output
-// tile q (32 features) of every layer and the waves exchange the layer's
-// activations through LDS, so a tile's latency is a quarter of one wave's.
-// What the weight gradients need goes to HBM in the fragment layout, 16 bytes
-// per lane and K-block (a contiguous kilobyte per wave and K-block):
+// layout), in one kernel (k_tfb).  What the weight gradients need goes to HBM
+// in the fragment layout, 16 bytes per lane and K-block (a contiguous
+// kilobyte per wave and K-block):
 //   X   the inputs of the five layers, bf16: the features (4 K-blocks), then
 //       the four GELU outputs (8 K-blocks each)                    36 K-blocks
-//   G   GELU'(z) of the four GELU layers, bf16                      32 K-blocks
 //   DZ  dL/dz of the four GELU layers, bf16                         32 K-blocks
 // K-block kb of tile t of a tensor with nkb K-blocks per tile sits at element
 // ((t nkb + kb) 64 + lane) 8; lane (n, h) holds slots i = 0..7 of point 32 t + n
 // (features kappa0(kb, h, i) for the first layer's input, kappa(kb, h, i)
 // otherwise).  Rows beyond the batch carry dL/dy = 0, so their terms vanish.
-constexpr int kXkb = 36, kGkb = 32;
+constexpr int kXkb = 36, kDzkb = 32;
 __host__ __device__ constexpr int x_kb0(int l) { return l == 0 ? 0 : 4 + 8 * (l - 1); }
 
 __device__ __forceinline__ void st_frag(unsigned short* base, long long t, int nkb, int kb, int lane, v8bf v) {
@@ -408,34 +404,48 @@ __host__ __device__ inline int bwd_slot(int l, int k, int o) {
     return (l - 1) * 16384 + (((k / 32) * 8 + kb) * 64 + k % 32 + 32 * h) * 8 + i;
 }
 
-// Training forward pass: G tiles in flight per workgroup of 4G waves.  Writes
-// X, G, y, dL/dy = 2 (y - t) / n (0 beyond the batch) and the batch targets.
-template <int G>
-__global__ __launch_bounds__(256 * G) void k_tfwd(Dev P, Src S, long long n, float inv_n, Train T) {
-    __shared__ v8bf sWi[kWi / 8];
-    __shared__ v8bf sX[G][2][8][64];   // the activations of the tile, ping-pong
-    __shared__ float sP[G][4][64];     // output-layer partial sums of the four waves
+// One training pass over the tiles of a batch, forward and backward through
+// the activations: wave q of a workgroup computes output tile q (32 features)
+// of every layer of the workgroup's current tile, holding its own forward and
+// backward weight fragments in registers (loaded once) and GELU'(z) of its
+// features from the forward pass to the backward one.  The four waves
+// exchange activations and dL/dz through LDS, one barrier per layer.  Writes
+// X, DZ, y, dL/dy = 2 (y - t) / n (0 beyond the batch) and the batch targets;
+// the backward pass ends at dz of the first layer (dx of the features is not
+// needed).
+__global__ __launch_bounds__(256) void k_tfb(Dev P, Src S, long long n, float inv_n, Train T) {
+    __shared__ v8bf sX[2][8][64];   // activations, then dL/dz, ping-pong
+    __shared__ float sP[4][64];     // output-layer partial sums of the four waves
+    __shared__ float sDy[32];
     __shared__ __attribute__((aligned(16))) float sB[4][128];
     __shared__ float sW4[128];
     __shared__ float sG[96];
-    stage_lds<256 * G>((uint4*)sWi, (const uint4*)P.wi, kWi / 8);
-    for (int i = threadIdx.x; i < 128; i += 256 * G) {
+    for (int i = threadIdx.x; i < 128; i += 256) {
         sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
         for (int l = 0; l < 4; ++l) sB[l][i] = P.master[kOffB[l] + i];
     }
     if (threadIdx.x < 96) sG[threadIdx.x] = P.G[threadIdx.x];
     const float b4 = P.master[kOffB[4]];
+    const int lane = threadIdx.x & 63, ln = lane & 31, h = lane >> 5, q = threadIdx.x >> 6;
+    // this wave's weight fragments: forward (4 + 3 x 8) and backward (3 x 8)
+    const v8bf* wi = (const v8bf*)P.wi;
+    const v8bf* wb = (const v8bf*)P.wb;
+    v8bf Af[28], Ab[24];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) Af[kb] = wi[(q * 4 + kb) * 64 + lane];
+#pragma unroll
+    for (int l = 1; l < 4; ++l)
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+            Af[4 + 8 * (l - 1) + kb] = wi[(8192 + (l - 1) * 16384) / 8 + (q * 8 + kb) * 64 + lane];
+            Ab[8 * (l - 1) + kb] = wb[(l - 1) * 16384 / 8 + (q * 8 + kb) * 64 + lane];
+        }
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, ln = lane & 31, h = lane >> 5;
-    const int g = wave >> 2, q = wave & 3;
     const long long tiles = (n + 31) / 32;
-    // every wave runs the same number of rounds (the barriers are block-wide)
-    for (long long t0 = (long long)blockIdx.x * G; t0 < tiles; t0 += (long long)gridDim.x * G) {
-        const long long t = t0 + g;
-        const bool act = t < tiles;
+    for (long long t = blockIdx.x; t < tiles; t += gridDim.x) {
         const long long row = t * 32 + ln;
-        float tg = 0.f;
-        if (act) {   // features: wave q computes K-block q (sines for q < 2, cosines otherwise)
+        float tg;
+        {   // features: wave q computes K-block q (sines for q < 2, cosines otherwise)
             const long long pi = src_index(S, S.off + min(row, n - 1));
             const float px = S.qx[pi * S.qs], py = S.qy[pi * S.qs], pz = S.qz[pi * S.qs];
             tg = S.tgt[pi];
@@ -447,121 +457,92 @@ __global__ __launch_bounds__(256 * G) void k_tfwd(Dev P, Src S, long long n, flo
                     fmaf(sG[3 * fr], px, fmaf(sG[3 * fr + 1], py, sG[3 * fr + 2] * pz)));
                 f[i] = (__bf16)(q < 2 ? __builtin_amdgcn_sinf(a) : __builtin_amdgcn_cosf(a));
             }
-            sX[g][0][q][lane] = f;
+            sX[0][q][lane] = f;
             st_frag(T.x, t, kXkb, q, lane, f);
         }
         __syncthreads();
+        v8bf gd[4][2];   // GELU'(z) of this wave's features, per layer
         float part = 0.f;
-#pragma unroll 1
+#pragma unroll
         for (int l = 0; l < 4; ++l) {
-            if (act) {
-                const int nkb = l == 0 ? 4 : 8;
-                const v8bf* W = sWi + (l == 0 ? 0 : (8192 + (l - 1) * 16384) / 8);
-                v16f acc;
+            const int nkb = l == 0 ? 4 : 8, a0 = l == 0 ? 0 : 4 + 8 * (l - 1);
+            v16f acc;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float4 v = *(const float4*)(&sB[l][32 * q + 8 * j + 4 * h]);
-                    acc[4 * j] = v.x;
-                    acc[4 * j + 1] = v.y;
-                    acc[4 * j + 2] = v.z;
-                    acc[4 * j + 3] = v.w;
-                }
+            for (int j = 0; j < 4; ++j) {
+                const float4 v = *(const float4*)(&sB[l][32 * q + 8 * j + 4 * h]);
+                acc[4 * j] = v.x;
+                acc[4 * j + 1] = v.y;
+                acc[4 * j + 2] = v.z;
+                acc[4 * j + 3] = v.w;
+            }
 #pragma unroll
-                for (int kb = 0; kb < 8; ++kb)
-                    if (kb < nkb)
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(W[(q * nkb + kb) * 64 + lane], sX[g][l & 1][kb][lane],
-                                                                      acc, 0, 0, 0);
-                v8bf y[2], gd[2];
+            for (int kb = 0; kb < nkb; ++kb)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Af[a0 + kb], sX[l & 1][kb][lane], acc, 0, 0, 0);
+            v8bf y[2];
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    float phi, ex;
-                    gelu_parts(acc[e], phi, ex);
-                    y[e >> 3][e & 7] = (__bf16)(acc[e] * phi);
-                    gd[e >> 3][e & 7] = (__bf16)fmaf(acc[e] * 0.39894228040143268f, ex, phi);
-                }
+            for (int e = 0; e < 16; ++e) {
+                float phi, ex;
+                gelu_parts(acc[e], phi, ex);
+                y[e >> 3][e & 7] = (__bf16)(acc[e] * phi);
+                gd[l][e >> 3][e & 7] = (__bf16)fmaf(acc[e] * 0.39894228040143268f, ex, phi);
+            }
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    st_frag(T.x, t, kXkb, x_kb0(l + 1) + 2 * q + u, lane, y[u]);
-                    st_frag(T.g, t, kGkb, 8 * l + 2 * q + u, lane, gd[u]);
-                    if (l < 3) sX[g][(l + 1) & 1][2 * q + u][lane] = y[u];
-                }
-                if (l == 3) {   // this wave's share of the output layer
+            for (int u = 0; u < 2; ++u) {
+                st_frag(T.x, t, kXkb, x_kb0(l + 1) + 2 * q + u, lane, y[u]);
+                if (l < 3) sX[(l + 1) & 1][2 * q + u][lane] = y[u];
+            }
+            if (l == 3) {   // this wave's share of the output layer
 #pragma unroll
-                    for (int u = 0; u < 2; ++u)
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) part = fmaf((float)y[u][i], sW4[kappa(2 * q + u, h, i)], part);
-                    sP[g][q][lane] = part;
-                }
+                    for (int i = 0; i < 8; ++i) part = fmaf((float)y[u][i], sW4[kappa(2 * q + u, h, i)], part);
+                sP[q][lane] = part;
             }
             __syncthreads();
         }
-        if (act && q == 0) {
-            float s = sP[g][0][lane] + sP[g][1][lane] + sP[g][2][lane] + sP[g][3][lane];
+        if (q == 0) {
+            float s = sP[0][lane] + sP[1][lane] + sP[2][lane] + sP[3][lane];
             s += __shfl_xor(s, 32);
-            const float yv = s + b4;
+            const float yv = s + b4, dy = row < n ? 2.f * (yv - tg) * inv_n : 0.f;
             if (h == 0) {
                 T.y[row] = yv;
-                T.dy[row] = row < n ? 2.f * (yv - tg) * inv_n : 0.f;
+                T.dy[row] = dy;
                 T.tb[row] = tg;
-            }
-        }
-    }
-}
-
-// Training backward pass through the activations (dz of every GELU layer):
-// dz_3 = dL/dy w4 GELU'(z_3), then dx_l^T = A'_l dz_l^T and dz_{l-1} =
-// dx_l GELU'(z_{l-1}) for l = 3, 2, 1; wave q computes input tile q.
-template <int G>
-__global__ __launch_bounds__(256 * G) void k_tbwd(Dev P, long long n, Train T) {
-    __shared__ v8bf sWb[kWb / 8];
-    __shared__ v8bf sD[G][2][8][64];
-    __shared__ float sW4[128];
-    stage_lds<256 * G>((uint4*)sWb, (const uint4*)P.wb, kWb / 8);
-    for (int i = threadIdx.x; i < 128; i += 256 * G) sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, ln = lane & 31, h = lane >> 5;
-    const int g = wave >> 2, q = wave & 3;
-    const long long tiles = (n + 31) / 32;
-    for (long long t0 = (long long)blockIdx.x * G; t0 < tiles; t0 += (long long)gridDim.x * G) {
-        const long long t = t0 + g;
-        const bool act = t < tiles;
-        if (act) {   // dz_3, K-blocks 2q and 2q+1
-            const float dy = T.dy[t * 32 + ln];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int kb = 2 * q + u;
-                const v8bf gd = ld_frag(T.g, t, kGkb, 24 + kb, lane);
-                v8bf d;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) d[i] = (__bf16)(dy * sW4[kappa(kb, h, i)] * (float)gd[i]);
-                sD[g][0][kb][lane] = d;
-                st_frag(T.dz, t, kGkb, 24 + kb, lane, d);
+                sDy[ln] = dy;
             }
         }
         __syncthreads();
-#pragma unroll 1
+        {   // dz of the last GELU layer, K-blocks 2q and 2q+1
+            const float dy = sDy[ln];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int kb = 2 * q + u;
+                v8bf d;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) d[i] = (__bf16)(dy * sW4[kappa(kb, h, i)] * (float)gd[3][u][i]);
+                sX[0][kb][lane] = d;
+                st_frag(T.dz, t, kDzkb, 24 + kb, lane, d);
+            }
+        }
+        __syncthreads();
+        // dx_l^T = A'_l dz_l^T, then dz_{l-1} = dx_l GELU'(z_{l-1}), for l = 3, 2, 1
+#pragma unroll
         for (int l = 3; l >= 1; --l) {
-            if (act) {
-                const int src = (3 - l) & 1;
-                const v8bf* W = sWb + (l - 1) * 16384 / 8;
-                const v8bf g0 = ld_frag(T.g, t, kGkb, 8 * (l - 1) + 2 * q, lane);
-                const v8bf g1 = ld_frag(T.g, t, kGkb, 8 * (l - 1) + 2 * q + 1, lane);
-                v16f acc = {};
+            const int src = (3 - l) & 1;
+            v16f acc = {};
 #pragma unroll
-                for (int kb = 0; kb < 8; ++kb)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(W[(q * 8 + kb) * 64 + lane], sD[g][src][kb][lane], acc,
-                                                                  0, 0, 0);
-                v8bf d[2];
+            for (int kb = 0; kb < 8; ++kb)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ab[8 * (l - 1) + kb], sX[src][kb][lane], acc, 0, 0, 0);
+            v8bf d[2];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    d[0][e] = (__bf16)(acc[e] * (float)g0[e]);
-                    d[1][e] = (__bf16)(acc[8 + e] * (float)g1[e]);
-                }
+            for (int e = 0; e < 8; ++e) {
+                d[0][e] = (__bf16)(acc[e] * (float)gd[l - 1][0][e]);
+                d[1][e] = (__bf16)(acc[8 + e] * (float)gd[l - 1][1][e]);
+            }
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    st_frag(T.dz, t, kGkb, 8 * (l - 1) + 2 * q + u, lane, d[u]);
-                    if (l > 1) sD[g][src ^ 1][2 * q + u][lane] = d[u];
-                }
+            for (int u = 0; u < 2; ++u) {
+                st_frag(T.dz, t, kDzkb, 8 * (l - 1) + 2 * q + u, lane, d[u]);
+                if (l > 1) sX[src ^ 1][2 * q + u][lane] = d[u];
             }
             __syncthreads();
         }
@@ -614,7 +595,7 @@ __global__ __launch_bounds__(64 * kWgW) void k_twgrad(long long n, int chunk_til
 #pragma unroll
             for (int u = 0; u < 2; ++u) cx[u] = ld_frag(T.x, t, kXkb, x_kb0(l) + 2 * I + u, lane);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) cd[k] = ld_frag(T.dz, t, kGkb, 8 * l + k, lane);
+            for (int k = 0; k < 8; ++k) cd[k] = ld_frag(T.dz, t, kDzkb, 8 * l + k, lane);
             v8bf xt[2];
             v16f raw;
             transpose(cx[0], cx[1], xt, raw);
@@ -913,7 +894,6 @@ namespace {
 
 void free_train(gwn_mlp_s* h) {
     (void)hipFree(h->t.x);
-    (void)hipFree(h->t.g);
     (void)hipFree(h->t.dz);
     (void)hipFree(h->t.y);
     (void)hipFree(h->t.dy);
@@ -936,8 +916,7 @@ gwn_status ensure_train(gwn_mlp_s* h, long long n) {
     // but the last holds wgrad_chunk() >= 8 tiles, and there are at most 64)
     const long long nchunk = std::min<long long>(64, (tiles + 7) / 8);
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.x, sizeof(unsigned short) * tiles * kXkb * 512));
-    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.g, sizeof(unsigned short) * tiles * kGkb * 512));
-    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.dz, sizeof(unsigned short) * tiles * kGkb * 512));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.dz, sizeof(unsigned short) * tiles * kDzkb * 512));
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.y, sizeof(float) * cap));
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.dy, sizeof(float) * cap));
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->t.tb, sizeof(float) * cap));
@@ -1001,19 +980,9 @@ gwn_status alloc_params(gwn_mlp_s* h) {
 // backward, weight gradients, their sum, then Adam at learning rate lr.
 gwn_status train_batch(gwn_mlp_s* h, const Src& S, long long n, float lr, float* loss_slot, hipStream_t st) {
     const long long tiles = (n + 31) / 32;
-    // one workgroup per CU (the weights fill its LDS); two tiles in flight per
-    // workgroup once there are enough tiles for every CU to take two
-    if (tiles >= 512) {
-        const int blocks = (int)std::min<long long>((tiles + 1) / 2, 256);
-        k_tfwd<2><<<blocks, 512, 0, st>>>(h->d, S, n, 1.0f / (float)n, h->t);
-        GWN_HIP_TRY(hipGetLastError());
-        k_tbwd<2><<<blocks, 512, 0, st>>>(h->d, n, h->t);
-    } else {
-        const int blocks = (int)std::min<long long>(tiles, 256);
-        k_tfwd<1><<<blocks, 256, 0, st>>>(h->d, S, n, 1.0f / (float)n, h->t);
-        GWN_HIP_TRY(hipGetLastError());
-        k_tbwd<1><<<blocks, 256, 0, st>>>(h->d, n, h->t);
-    }
+    // one workgroup of four waves per CU (each wave's weight fragments fill
+    // its registers), persistent over the tiles
+    k_tfb<<<(int)std::min<long long>(tiles, 256), 256, 0, st>>>(h->d, S, n, 1.0f / (float)n, h->t);
     GWN_HIP_TRY(hipGetLastError());
     const long long ct = wgrad_chunk(tiles);
     const int nchunk = (int)((tiles + ct - 1) / ct);
