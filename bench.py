@@ -749,6 +749,7 @@ def bench_surrogate(args):
                         "points_per_s": n_train * args.epochs / train_s,
                         "flop_per_point": 3 * 114944,
                         "tflop_per_s": 3 * 114944 * n_train * args.epochs / train_s / 1e12,
+                        "frac_of_bf16_peak": 3 * 114944 * n_train * args.epochs / train_s / PEAK_BF16,
                         "epoch_losses": losses},
            "network_max_abs_err": float(err_nn.max()),
            "network_rms_err": float(err_nn.pow(2).mean().sqrt()), "sigma": args.sigma,
