@@ -87,14 +87,14 @@ PEAK_BF16 = 2.5e15
 NET_VALU_SLOTS = 512 * 11.5 + 32 * 12 + 256     # = 6,528 per point
 # HBM bytes moved per k_grid<float, 8> launch on the default workload (512^3 grid,
 # 1.05M-triangle soup), from two rocprofv3 --pmc passes over this command:
-# FETCH_SIZE 231,887.25 KiB and WRITE_SIZE 524,288.0 KiB per dispatch, scaled by
+# FETCH_SIZE 231,971.81 KiB and WRITE_SIZE 524,288.0 KiB per dispatch, scaled by
 # what the same counters read for a plain 1 GiB device copy (bench.py
-# --copy-probe: FETCH_SIZE shows 524,308.6 KiB -> x2.000, WRITE_SIZE
+# --copy-probe: FETCH_SIZE shows 524,308.2 KiB -> x2.000, WRITE_SIZE
 # 1,048,576 KiB -> x1.000).  Writes are exactly the w output (134,217,728 x 4 B);
 # fetches are the BVH, triangles and boundary vertices read by the 8 XCD L2s.
 # Measured on the kernel as it stands; re-take the counters after any change to
 # k_grid or the workload.
-K_GRID_TRAFFIC_BYTES = (231887.25 * 2.0 + 524288.0 * 1.0) * 1024
+K_GRID_TRAFFIC_BYTES = (231971.8125 * 2.0 + 524288.0 * 1.0) * 1024
 FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
 I_MIN_GRID_FP64 = (16 + 2 + 21 / 2) * FP64_OP_SLOTS + 2.5 * FP64_TRANS_SLOTS + 2   # = 58.25
 # Parametric path (FP64), per unit of work the kernel reports, counted from its

@@ -335,29 +335,47 @@ __device__ __forceinline__ void edge_pair(const ColV<T>& a, const ColV<T>& b, co
 // below the vertex (s = rho^2 / t, no select), block R-1 may straddle it (the
 // two-sided form) and blocks R.. lie wholly at or above it (s = t).  R > ZB:
 // no order known, the two-sided form everywhere.
-template <class T, int ZB, int R>
+//
+// FARV: every sample below the vertex has r_z^2 <= 3 rho^2.  There
+// s = l - r_z = t - 2 max(r_z, 0) loses at most ~16 ulps to cancellation (its
+// rounding error is ~2 u l, and s = rho^2 / (l + r_z) >= l / 8 there), so the
+// blocks take it without the reciprocal.
+template <class T, int ZB, int R, bool FARV>
 __device__ __forceinline__ void s_blocks(const T* rz, T rho2, T* sv) {
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {   // sv holds t = l + |r_z| on entry
-        if (R > ZB || r == R - 1) sv[r] = rz[r] > (T)0 ? rho2 * Arith<T>::rcp(sv[r]) : sv[r];
-        else if (r < R - 1) sv[r] = rho2 * Arith<T>::rcp(sv[r]);
+        if (FARV && R <= ZB) {
+            if (r < R - 1) sv[r] = fma((T)-2, rz[r], sv[r]);
+            else if (r == R - 1) sv[r] = fma((T)-2, fmax(rz[r], (T)0), sv[r]);
+        } else if (R > ZB || r == R - 1) {
+            sv[r] = rz[r] > (T)0 ? rho2 * Arith<T>::rcp(sv[r]) : sv[r];
+        } else if (r < R - 1) {
+            sv[r] = rho2 * Arith<T>::rcp(sv[r]);
+        }
     }
 }
 
+// R as above; farv: the FARV case (wave-uniform)
 template <class T, int ZB>
-__device__ __forceinline__ void s_prefix(int R, const T* rz, T rho2, T* sv) {
+__device__ __forceinline__ void s_prefix(int R, const T* rz, T rho2, T* sv, bool farv = false) {
+#define GWN_S_CASE(K)                                                                          \
+    case K:                                                                                    \
+        if (farv) s_blocks<T, ZB, (K <= ZB ? K : ZB + 1), true>(rz, rho2, sv);                 \
+        else s_blocks<T, ZB, (K <= ZB ? K : ZB + 1), false>(rz, rho2, sv);                     \
+        break;
     switch (R) {
         case 0: break;
-        case 1: s_blocks<T, ZB, (1 <= ZB ? 1 : ZB + 1)>(rz, rho2, sv); break;
-        case 2: s_blocks<T, ZB, (2 <= ZB ? 2 : ZB + 1)>(rz, rho2, sv); break;
-        case 3: s_blocks<T, ZB, (3 <= ZB ? 3 : ZB + 1)>(rz, rho2, sv); break;
-        case 4: s_blocks<T, ZB, (4 <= ZB ? 4 : ZB + 1)>(rz, rho2, sv); break;
-        case 5: s_blocks<T, ZB, (5 <= ZB ? 5 : ZB + 1)>(rz, rho2, sv); break;
-        case 6: s_blocks<T, ZB, (6 <= ZB ? 6 : ZB + 1)>(rz, rho2, sv); break;
-        case 7: s_blocks<T, ZB, (7 <= ZB ? 7 : ZB + 1)>(rz, rho2, sv); break;
-        case 8: s_blocks<T, ZB, (8 <= ZB ? 8 : ZB + 1)>(rz, rho2, sv); break;
-        default: s_blocks<T, ZB, ZB + 1>(rz, rho2, sv); break;
+        GWN_S_CASE(1)
+        GWN_S_CASE(2)
+        GWN_S_CASE(3)
+        GWN_S_CASE(4)
+        GWN_S_CASE(5)
+        GWN_S_CASE(6)
+        GWN_S_CASE(7)
+        GWN_S_CASE(8)
+        default: s_blocks<T, ZB, ZB + 1, false>(rz, rho2, sv); break;
     }
+#undef GWN_S_CASE
 }
 
 // Where the samples of a grid wave share a column, register r is a block of 64
@@ -488,7 +506,7 @@ template <class T>
 struct ColRing {
     ColRec<T> rec[kColRing + 1];
     ColAux<T> aux[kColRing + 1];
-    int R[kColRing + 1];   // block count R of the vertex (see BlockMin)
+    int R[kColRing + 1];   // block count R of the vertex, plus 256 in the FARV case (see BlockMin, s_blocks)
 };
 
 // Records of vertices v0 .. v0 + n - 1 (n <= 64) of the loop [b0, b1), into the
@@ -527,8 +545,14 @@ __device__ __forceinline__ void col_fill(const MeshView& mv, int v0, int n, int 
         ax.dx = ca.dx;
         ax.dy = ca.dy;
         if (asc) {
+            bool farv = true;   // every sample below the vertex has r_z^2 <= 3 rho^2
 #pragma unroll
-            for (int r = 0; r < ZB; ++r) R += (u == (T)1 ? (T)a.z - bminr[r] : fma((T)a.z, u, -bminr[r])) > (T)0;
+            for (int r = 0; r < ZB; ++r) {
+                const T zr = u == (T)1 ? (T)a.z - bminr[r] : fma((T)a.z, u, -bminr[r]);
+                R += zr > (T)0;
+                farv &= !((zr > (T)0) & (zr * zr > (T)3 * rc.rho2));   // zr: the block's largest r_z
+            }
+            R |= farv ? 256 : 0;
         } else {
             R = ZB + 1;
         }
@@ -569,7 +593,7 @@ __device__ __forceinline__ void col_vertex(const ColRec<T>& c, int R, const T* p
         rz[r] = c.zu - pz[r];
         sv[r] = Arith<T>::sqrt(rz[r] * rz[r] + c.rho2) + fabs(rz[r]);   // t, made s in place
     }
-    s_prefix<T, ZB>(R, rz, c.rho2, sv);
+    s_prefix<T, ZB>(R & 0xff, rz, c.rho2, sv, R >= 256);
     N = c.N;
     dot = c.dot;
 }
