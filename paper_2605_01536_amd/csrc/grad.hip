@@ -159,7 +159,8 @@ template <class T>
 struct GRing {
     GRec<T> v[kColRing + 1];
     GEdge<T> e[kColRing + 1];
-    int R[kColRing + 1];   // blocks of the column with a sample below the vertex (see BlockMin)
+    int R[kColRing + 1];   // blocks of the column with a sample below the vertex (see BlockMin), plus 256
+                           // when the vertex is far (s_blocks)
 };
 
 template <class T, int ZB>
@@ -184,8 +185,14 @@ __device__ __forceinline__ void grad_fill(const MeshView& mv, int v0, int n, int
         int R = ZB + 1;
         if (asc) {
             R = 0;
+            bool farv = true;   // every sample below the vertex has r_z^2 <= 3 rho^2 (see s_blocks)
 #pragma unroll
-            for (int r = 0; r < ZB; ++r) R += fma((T)a.z, f, -bminr[r]) > (T)0;
+            for (int r = 0; r < ZB; ++r) {
+                const T zr = fma((T)a.z, f, -bminr[r]);   // the block's largest r_z
+                R += zr > (T)0;
+                farv &= !((zr > (T)0) & (zr * zr > (T)3 * rv.rho2));
+            }
+            R |= farv ? 256 : 0;
         }
         const int k = (v - b0) & (kColRing - 1);
         ring.v[k] = rv;
@@ -205,8 +212,9 @@ __device__ __forceinline__ void grad_fill(const MeshView& mv, int v0, int n, int
 
 // u = 1/l and s of one ring vertex for the ZB samples: blocks wholly at or above
 // the vertex take s = l + |r_z|, blocks wholly below it s = rho^2 / (l + r_z),
-// the block the vertex's height falls in the two-sided form (the block count is
-// the w kernel's; r_z is the same fma in both)
+// the block the vertex's height falls in the two-sided form, and a far vertex
+// l - r_z in every block (the block count and the far test are the w kernel's;
+// r_z is the same fma in both)
 template <class T, int ZB>
 __device__ __forceinline__ void grad_vertex(const GRec<T>& c, int R, const T* pzs, T f, T* u, T* s) {
     T rz[ZB];
@@ -217,7 +225,7 @@ __device__ __forceinline__ void grad_vertex(const GRec<T>& c, int R, const T* pz
         u[r] = Arith<T>::rcp(l);
         s[r] = l + fabs(rz[r]);   // t, made s in place
     }
-    s_prefix<T, ZB>(R, rz, c.rho2, s);
+    s_prefix<T, ZB>(R & 0xff, rz, c.rho2, s, R >= 256);
 }
 
 // grad_loops for a grid column (x0 = +z), register r of the wave a block of 64
