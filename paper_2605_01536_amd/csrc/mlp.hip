@@ -1,19 +1,18 @@
 // mlp.hip -- learned surrogate for far-field winding-number queries:
 // Fourier features gamma(p) = [sin 2piGp, cos 2piGp] (G: 32x3, fixed), four
-// GELU layers 64->128->128->128->128 and a linear output 128->1.  Matrix
-// products run on MFMA with bf16 operands and fp32 accumulation: the training
-// kernels on LDS tiles (v_mfma_f32_16x16x32_bf16), inference (k_infer) with
-// the activations kept in registers (v_mfma_f32_32x32x16_bf16).
+// GELU layers 64->128->128->128->128 and a linear output 128->1.  Every matrix
+// product runs on v_mfma_f32_32x32x16_bf16 (bf16 operands, fp32 accumulation)
+// in a transposed fragment layout where one layer's output registers are the
+// next layer's operand: inference (k_infer) keeps the activations in
+// registers; training runs the forward and backward passes in one kernel
+// (k_tfb) and the weight gradients in another (k_twgrad).
 // Inference evaluates GELU by a minimax polynomial of Phi (gelu_fast, within
 // 5.3e-5 |z| of the erf form), training by the erf form (Abramowitz & Stegun
-// 7.1.26, 1.5e-7).  FP32 master weights are updated by Adam and re-packed into bf16 copies in
-// the three layouts the kernels read.  The band query evaluates the network,
+// 7.1.26, 1.5e-7).  FP32 master weights are updated by Adam and re-packed into
+// the bf16 copies the kernels read.  The band query evaluates the network,
 // re-evaluates every point whose prediction lies within `band` of 1/2 with the
 // exact kernels, and scatters those results back.
-//
-// MFMA 16x16x32 operand layout (wave64): lane l holds A[l%16][8(l/16)+j] and
-// B[8(l/16)+j][l%16] (j = 0..7); the result D[4(l/16)+i][l%16] lands in
-// component i of the lane's accumulator (i = 0..3).
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -26,8 +25,6 @@
 #include "gwn_kernels.h"
 #include "gwn_mesh.h"
 
-typedef short v4s __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 namespace gwn {

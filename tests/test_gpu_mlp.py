@@ -74,6 +74,26 @@ def test_gradient_matches_reference(gwn):
     assert cos > 0.9995
 
 
+@pytest.mark.parametrize("n", [1, 31, 33, 257, 70_000])
+def test_gradient_ragged_batches(gwn, n):
+    # the training kernels work on tiles of 32 points (rows beyond the batch
+    # carry dL/dy = 0) and sum weight gradients over chunks of at least 8 tiles
+    # (at most 64 chunks, four waves per chunk): a single point, partial tiles,
+    # a partial chunk, and chunks of many tiles per wave
+    s = _sur(gwn, seed=9)
+    st = s.state()
+    P = _points(n, 100 + n)
+    t = np.random.default_rng(200 + n).uniform(-0.5, 1.5, n).astype(np.float32)
+    loss, g = s.loss_grad(torch.from_numpy(P).cuda(), torch.from_numpy(t).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    loss_ref, g_ref = R.loss_and_grad(st["theta"].astype(np.float64), st["G"].astype(np.float64), P, t, bf16=True)
+    assert loss == pytest.approx(loss_ref, rel=5e-3)
+    cos = g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref))
+    assert cos > 0.999, cos
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    assert rel < 4e-2, rel
+
+
 def test_adam_step_matches_reference(gwn):
     s = _sur(gwn, seed=6)
     P = torch.from_numpy(_points(2048, 11)).cuda()
