@@ -415,6 +415,33 @@ def test_grid_columns_far_in_z(gwn, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_grid_boundary_vertices_around_the_far_cone(gwn, prec):
+    # An open, slightly wavy disk (96 boundary vertices on a ring of radius 0.3
+    # at height ~0.3) over a grid whose columns lie 0 to ~0.6 (horizontally)
+    # from the ring's vertices and whose samples run from below the disk to
+    # above it.  The grid kernel takes s = l - r_z for a vertex whose every
+    # sample below it lies within 60 degrees of the vertical around the column
+    # (r_z^2 <= 3 rho^2), and the reciprocal form otherwise; here both occur in
+    # every column, along with blocks of samples straddling a vertex's height.
+    n = 96
+    ang = 2.0 * np.pi * np.arange(n) / n
+    ring = np.stack([0.3 * np.cos(ang), 0.3 * np.sin(ang), 0.3 + 0.02 * np.sin(3.0 * ang)], 1)
+    V = np.concatenate([[[0.01, -0.02, 0.36]], ring]).astype(np.float32)
+    F = np.array([[0, 1 + i, 1 + (i + 1) % n] for i in range(n)], np.int32)
+    m = gwn.Mesh(_dev(V), _dev(F))
+    assert m.info()["nboundary"] == n
+    g = W.GridSpec(origin=(-0.6, -0.6, -0.3), spacing=(0.075, 0.075, 0.8 / 512), dims=(16, 16, 512))
+    w, chi = gwn.query_grid(m, g.origin, g.spacing, g.dims, prec=prec, want_chi=True)
+    P = W.grid_points(g)
+    e, k = compare(w.cpu().numpy(), chi.cpu().numpy(), V, F, P, TOL_FP32 if prec == "fp32" else TOL_FP64,
+                   f"far-cone-{prec}")
+    assert k > 0.99 * P.shape[0]
+    # the same points through the batch path, which keeps the reciprocal form
+    wb = gwn.query_batch(m, _dev(P), prec=prec).cpu().numpy()
+    assert np.abs(wb.astype(np.float64) - w.cpu().numpy()).max() < (2e-6 if prec == "fp32" else 1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_welded_exploded_soup(gwn, prec):
     # STL-style input: every triangle with its own vertices; welding on the
     # device recovers the indexed boundary, and w / chi match the oracle
