@@ -189,6 +189,7 @@ def parse():
     ap.add_argument("--epochs", type=int, default=32, help="surrogate training epochs")
     ap.add_argument("--sigma", type=float, default=1.0, help="surrogate Fourier-feature scale")
     ap.add_argument("--lr", type=float, default=1e-3, help="surrogate peak learning rate")
+    ap.add_argument("--train-batch", type=int, default=8192, help="surrogate training batch (points per Adam step)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM counters) and exit")
     return ap.parse_args()
@@ -677,7 +678,7 @@ def bench_surrogate(args):
     Xi = torch.from_numpy(Xin).cuda()
     del Xin
     sur = gwn.Surrogate(seed=0, sigma=args.sigma)
-    n_train, batch = 10_000_000, 8192
+    n_train, batch = 10_000_000, args.train_batch
     t = time.time()
     losses = sur.train(mesh, epochs=args.epochs, n_train=n_train, batch=batch, lr=args.lr, lr_final=5e-5, seed=1,
                        box=((-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)))
