@@ -179,10 +179,18 @@ __device__ __forceinline__ float gelu_fast(float z) {
     return z * fmaf(zc, p, 0.5f);
 }
 
-// Sum of the chunks' partial gradients of parameter p, four chunks in flight
+// Sum of the chunks' partial gradients of parameter p: four running sums
+// (chunk c goes to sum c % 4), sixteen loads in flight per round
 __device__ __forceinline__ float chunk_sum(const float* __restrict__ part, int nchunk, int p) {
     float s[4] = {0.f, 0.f, 0.f, 0.f};
     int c = 0;
+    for (; c + 16 <= nchunk; c += 16) {
+        float r[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) r[k] = part[(long long)(c + k) * (kNParams + 1) + p];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s[k & 3] += r[k];
+    }
     for (; c + 4 <= nchunk; c += 4)
 #pragma unroll
         for (int k = 0; k < 4; ++k) s[k] += part[(long long)(c + k) * (kNParams + 1) + p];
