@@ -226,3 +226,29 @@ def test_band_query_matches_network_and_exact_path(gwn):
     # prediction would keep its value)
     wf, nf = s.query(m, Q, 0.5001, rule="frac")
     assert nf == Q.shape[0] and torch.equal(wf, exact)
+
+
+def test_surrogate_on_empty_inputs(gwn):
+    # zero points: the forward pass and the band query are no-ops; training on an
+    # empty batch is refused with an error and leaves the network as it was
+    soup = W.opened_spheres(seed=43, n_surf=2, tris_per_surf=200)
+    m = gwn.Mesh(torch.from_numpy(soup.V).cuda(), torch.from_numpy(soup.F).cuda())
+    s = _sur(gwn, seed=9)
+    theta0 = s.state()["theta"].copy()
+    E = torch.zeros((0, 3), device="cuda")
+    assert s.forward(E).numel() == 0
+    for rule in ("half", "frac"):
+        w, mask, nfb = s.query(m, E, 0.3, want_mask=True, rule=rule)
+        assert w.numel() == 0 and mask.numel() == 0 and nfb == 0
+    t0 = torch.zeros(0, device="cuda")
+    with pytest.raises(gwn.GwnError, match="empty batch"):
+        s.loss_grad(E, t0)
+    with pytest.raises(gwn.GwnError, match="empty batch"):
+        s.train_step(E, t0, 1e-3)
+    with pytest.raises(gwn.GwnError, match="bad configuration"):
+        s.train(m, epochs=1, X=E)
+    assert np.array_equal(s.state()["theta"], theta0)
+    P = torch.from_numpy(_points(257, 15)).cuda()
+    y = s.forward(P).cpu().numpy().astype(np.float64)
+    y_ref, _ = R.forward(theta0.astype(np.float64), s.state()["G"].astype(np.float64), _points(257, 15), bf16=True)
+    assert np.abs(y - y_ref).max() < 3e-2 * (1 + np.median(np.abs(y_ref)))
