@@ -661,7 +661,7 @@ def bench_batched(args):
                     "pairs_per_s": pairs / (ev_ms / 1e3), "schedule": inf, "autotune_s": tune_s,
                     "per_mesh_launches_ms": wall2, "graph_speedup_vs_per_mesh": wall2 / wall_ms,
                     "bitwise_equal_to_per_mesh": same},
-          extra={"roofline": _alu_roof(pairs, I_MIN_BATCH, ev_ms, "graph: k_chi_multi + k_bdry_persistent")})
+          extra={"roofline": _alu_roof(pairs, I_MIN_BATCH, ev_ms, "graph: k_chi_items + k_bdry_persistent")})
 
 
 def bench_surrogate(args):

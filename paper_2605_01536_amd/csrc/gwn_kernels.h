@@ -944,5 +944,63 @@ __device__ void chi_line(const MeshView& mv, const QPoint& q, int* stk, int& up,
     }
 }
 
+// Signed crossings of the lines of a wave's lanes, the wave walking the BVH
+// together: it descends into a child when the line of ANY active lane meets
+// the child's box (ballot), nodes and triangles arrive by scalar loads, and each
+// active lane applies its own exact leaf test (u: crossings above q, d: minus
+// those below).  UP: the +z ray only, the walk pruned by z (d then holds only
+// the leaves it visited); otherwise the whole line.  Every lane of the wave
+// calls it together; stk is the wave's LDS stack of kLdsStack entries (a
+// child is pushed only where both are taken, so it never holds more entries
+// than the tree is deep).
+template <bool UP>
+__device__ __forceinline__ void chi_wave_walk(const MeshView& mv, const QPoint& q, bool act, int* stk, int& u,
+                                              int& d) {
+    u = d = 0;
+    auto leaf = [&](int t) {
+        const TriQ tr = mv.tris[t];
+        const int s = tri_xy_sign(tr, q.x, q.y);
+        if (s == 0) return;
+        if (plane_above(plane_of(tr, q.x, q.y), q.z)) u += s;
+        else d -= s;
+    };
+    int node = mv.root;
+    if (__builtin_amdgcn_ballot_w64(act) == 0ull || node == kNoRoot) return;
+    if (node < 0) {
+        if (act) leaf(~node);
+        return;
+    }
+    int sp = 0;
+    while (true) {
+        const Node nd = mv.nodes[node];
+        const bool ml = act && box_has_xy(nd.lxy.x, nd.lxy.y, nd.lxy.z, nd.lxy.w, q.x, q.y) && (!UP || q.z <= nd.z.y);
+        const bool mr = act && box_has_xy(nd.rxy.x, nd.rxy.y, nd.rxy.z, nd.rxy.w, q.x, q.y) && (!UP || q.z <= nd.z.w);
+        bool hl = __builtin_amdgcn_ballot_w64(ml) != 0ull;
+        bool hr = __builtin_amdgcn_ballot_w64(mr) != 0ull;
+        const int L = nd.link.x, R = nd.link.y;
+        if (hl && L < 0) {
+            if (ml) leaf(~L);
+            hl = false;
+        }
+        if (hr && R < 0) {
+            if (mr) leaf(~R);
+            hr = false;
+        }
+        if (hl && hr) {
+            stk[sp++] = R;   // every lane stores the same value
+            node = L;
+        } else if (hl) {
+            node = L;
+        } else if (hr) {
+            node = R;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = stk[sp];
+        }
+        node = __builtin_amdgcn_readfirstlane(node);
+    }
+}
+
 }  // namespace
 }  // namespace gwn

@@ -34,30 +34,33 @@ __global__ void k_reset_counter(int* c) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
-constexpr int kMultiChiBlock = 64;
-
-// crossing counts of every query; each thread finds its mesh by binary search
-// over the query offsets
-__global__ __launch_bounds__(kMultiChiBlock) void k_chi_multi(const MeshView* __restrict__ table,
-                                                               const long long* __restrict__ qoff, int nmesh,
-                                                               const float* __restrict__ qx, const float* __restrict__ qy,
-                                                               const float* __restrict__ qz, long long qs,
-                                                               int* __restrict__ chi) {
-    __shared__ int stk[kLdsStack * kMultiChiBlock];
-    const long long i = blockIdx.x * (long long)kMultiChiBlock + threadIdx.x;
-    const long long nq = qoff[nmesh];
-    if (i >= nq) return;
-    int lo = 0, hi = nmesh - 1;   // last mesh with qoff[m] <= i
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (qoff[mid] <= i) lo = mid;
-        else hi = mid - 1;
-    }
-    const MeshView mv = table[lo];
+// Crossing counts along +z for every query, one wave per work item: the item's
+// queries (in Morton order within their mesh when perm is given, as the
+// boundary-term kernel takes them) walk the mesh's BVH together
+// (chi_wave_walk), so a wave follows about one path.  Out-of-box queries get 0.
+__global__ __launch_bounds__(64 * kGridWaves) void k_chi_items(const MeshView* __restrict__ table,
+                                                              const Item* __restrict__ items, int nitems,
+                                                              const float* __restrict__ qx,
+                                                              const float* __restrict__ qy,
+                                                              const float* __restrict__ qz, long long qs,
+                                                              const int* __restrict__ perm, int* __restrict__ chi) {
+    __shared__ int wstack[kGridWaves][kLdsStack];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const long long it = (long long)blockIdx.x * kGridWaves + wave;
+    if (it >= nitems) return;   // the whole wave
+    const Item I = items[it];
+    const MeshView mv = table[I.mesh];
     const float *x = qx, *y = qy, *z = qz;
     axis_ptrs(mv.axis, x, y, z);   // the mesh's frame
-    const QPoint q = quantize_point(x[i * qs], y[i * qs], z[i * qs], mv.g);
-    chi[i] = q.inbox ? chi_up(mv, q, stk + threadIdx.x) : 0;
+    for (int sub = 0; sub < I.nq; sub += 64) {
+        const int k = sub + lane;
+        const long long i0 = I.q0 + min(k, I.nq - 1);
+        const long long i = perm ? (long long)perm[i0] : i0;
+        const QPoint q = quantize_point(x[i * qs], y[i * qs], z[i * qs], mv.g);
+        int u, d;
+        chi_wave_walk<true>(mv, q, k < I.nq && q.inbox, wstack[wave], u, d);
+        if (k < I.nq) chi[i] = u;
+    }
 }
 
 // global query index i0 + perm_local[i - i0] for i in [i0, i0 + n)
@@ -136,7 +139,6 @@ struct gwn_multi_s {
     int* chi = nullptr;
     bool own_chi = false;
     gwn::MeshView* table = nullptr;
-    long long* qoff = nullptr;
     gwn::Item* items = nullptr;
     int nitems = 0;
     int* perm = nullptr;   // Morton order of each mesh's queries (made when a schedule asks for it)
@@ -162,7 +164,6 @@ void release(gwn_multi_s* p) {
     drop_graph(p);
     if (p->cap) (void)hipStreamDestroy(p->cap);
     (void)hipFree(p->table);
-    (void)hipFree(p->qoff);
     (void)hipFree(p->items);
     (void)hipFree(p->perm);
     (void)hipFree(p->counter);
@@ -240,9 +241,9 @@ gwn_status capture(gwn_multi_s* p, const Schedule& s) {
     GWN_HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
     k_reset_counter<<<1, 64, 0, p->cap>>>(p->counter);
     if (p->nq > 0) {
-        k_chi_multi<<<(unsigned)((p->nq + kMultiChiBlock - 1) / kMultiChiBlock), kMultiChiBlock, 0, p->cap>>>(
-            p->table, p->qoff, p->nmesh, p->qx, p->qy, p->qz, p->qs, p->chi);
         const int* perm = (s.order & kOrderSorted) ? p->perm : nullptr;
+        k_chi_items<<<(unsigned)((p->nitems + kGridWaves - 1) / kGridWaves), 64 * kGridWaves, 0, p->cap>>>(
+            p->table, p->items, p->nitems, p->qx, p->qy, p->qz, p->qs, perm, p->chi);
         if (p->prec == GWN_PREC_FP64)
             k_bdry_persistent<double><<<p->grid, 256, 0, p->cap>>>(p->table, p->items, p->nitems, p->counter, p->qx,
                                                                    p->qy, p->qz, p->qs, perm, p->chi,
@@ -362,10 +363,8 @@ gwn_status multi_create(const gwn_mesh* meshes, int nmesh, const float* qx, cons
     std::vector<MeshView> tab(nmesh);
     for (int m = 0; m < nmesh; ++m) tab[m] = p->meshes[m]->view();
     GWN_HIP_TRY(gwn::dmalloc((void**)&p->table, sizeof(MeshView) * (size_t)nmesh));
-    GWN_HIP_TRY(gwn::dmalloc((void**)&p->qoff, sizeof(long long) * (size_t)(nmesh + 1)));
     GWN_HIP_TRY(gwn::dmalloc((void**)&p->counter, sizeof(int)));
     GWN_HIP_TRY(hipMemcpyAsync(p->table, tab.data(), sizeof(MeshView) * nmesh, hipMemcpyHostToDevice, st));
-    GWN_HIP_TRY(hipMemcpyAsync(p->qoff, p->qoff_h.data(), sizeof(long long) * (nmesh + 1), hipMemcpyHostToDevice, st));
     GWN_HIP_TRY(hipStreamSynchronize(st));
     GWN_HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
 

@@ -26,12 +26,10 @@ __global__ __launch_bounds__(kChiBlock) void k_chi_batch(MeshView mv, const floa
 }
 
 
-// Crossing counts of Morton-ordered points, one wave-uniform traversal per wave:
-// the wave descends into a child when the line of ANY of its lanes meets the
-// child's box (ballot), nodes and triangles arrive by scalar loads, and each lane
-// applies its own exact leaf test.  Neighbouring lines share almost their whole
-// path, so the wave walks about one path instead of 64 divergent ones.  UP: the
-// +z ray only (z-pruned); otherwise both directions of the whole line.
+// Crossing counts of Morton-ordered points, one wave-uniform traversal per wave
+// (chi_wave_walk): neighbouring lines share almost their whole path, so the
+// wave walks about one path instead of 64 divergent ones.  UP: the +z ray only
+// (z-pruned); otherwise both directions of the whole line.
 template <bool UP>
 __global__ __launch_bounds__(64 * kGridWaves) void k_chi_wave(MeshView mv, const float* __restrict__ qx,
                                                              const float* __restrict__ qy,
@@ -46,54 +44,8 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_chi_wave(MeshView mv, const
     const long long i = perm[valid ? j : nq - 1];
     const QPoint q = quantize_point(qx[i * qs], qy[i * qs], qz[i * qs], mv.g);
     const bool act = valid && q.inbox;
-    int u = 0, d = 0;
-    auto leaf = [&](int t) {
-        const TriQ tr = mv.tris[t];
-        const int s = tri_xy_sign(tr, q.x, q.y);
-        if (s == 0) return;
-        if (plane_above(plane_of(tr, q.x, q.y), q.z)) u += s;
-        else d -= s;
-    };
-    int node = mv.root;
-    if (__builtin_amdgcn_ballot_w64(act) != 0ull && node != kNoRoot) {
-        if (node < 0) {
-            if (act) leaf(~node);
-        } else {
-            int* stk = wstack[wave];
-            int sp = 0;
-            while (true) {
-                const Node nd = mv.nodes[node];
-                const bool ml = act && box_has_xy(nd.lxy.x, nd.lxy.y, nd.lxy.z, nd.lxy.w, q.x, q.y) &&
-                                (!UP || q.z <= nd.z.y);
-                const bool mr = act && box_has_xy(nd.rxy.x, nd.rxy.y, nd.rxy.z, nd.rxy.w, q.x, q.y) &&
-                                (!UP || q.z <= nd.z.w);
-                bool hl = __builtin_amdgcn_ballot_w64(ml) != 0ull;
-                bool hr = __builtin_amdgcn_ballot_w64(mr) != 0ull;
-                const int L = nd.link.x, R = nd.link.y;
-                if (hl && L < 0) {
-                    if (ml) leaf(~L);
-                    hl = false;
-                }
-                if (hr && R < 0) {
-                    if (mr) leaf(~R);
-                    hr = false;
-                }
-                if (hl && hr) {
-                    stk[sp++] = R;   // every lane stores the same value
-                    node = L;
-                } else if (hl) {
-                    node = L;
-                } else if (hr) {
-                    node = R;
-                } else {
-                    if (sp == 0) break;
-                    --sp;
-                    node = stk[sp];
-                }
-                node = __builtin_amdgcn_readfirstlane(node);
-            }
-        }
-    }
+    int u, d;
+    chi_wave_walk<UP>(mv, q, act, wstack[wave], u, d);
     if (valid) {
         if (up) up[i] = u;
         if (down) down[i] = d;
