@@ -74,8 +74,10 @@ __global__ void k_perm_offset(const int* __restrict__ local, long long i0, int n
 // position i of the work list is query perm[i], a permutation within each mesh.
 // T is the geometry precision; per query it takes the same steps, in the same
 // order, as the one-lane-per-point batch kernel, so the results are the same bits.
+// FP32 is held to 64 VGPRs, so the 8 resident waves per SIMD the schedules ask
+// for all fit (68 unconstrained, i.e. 7).
 template <class T>
-__global__ __launch_bounds__(256) void k_bdry_persistent(const MeshView* __restrict__ table,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1))) void k_bdry_persistent(const MeshView* __restrict__ table,
                                                          const Item* __restrict__ items, int nitems,
                                                          int* __restrict__ counter, const float* __restrict__ qx,
                                                          const float* __restrict__ qy, const float* __restrict__ qz,
