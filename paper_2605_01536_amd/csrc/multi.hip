@@ -77,12 +77,11 @@ __global__ void k_perm_offset(const int* __restrict__ local, long long i0, int n
 // FP32 is held to 64 VGPRs, so the 8 resident waves per SIMD the schedules ask
 // for all fit (68 unconstrained, i.e. 7).
 template <class T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1))) void k_bdry_persistent(const MeshView* __restrict__ table,
-                                                         const Item* __restrict__ items, int nitems,
-                                                         int* __restrict__ counter, const float* __restrict__ qx,
-                                                         const float* __restrict__ qy, const float* __restrict__ qz,
-                                                         long long qs, const int* __restrict__ perm,
-                                                         const int* __restrict__ chi, T* __restrict__ w) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1)))
+void k_bdry_persistent(const MeshView* __restrict__ table, const Item* __restrict__ items, int nitems,
+                       int* __restrict__ counter, const float* __restrict__ qx, const float* __restrict__ qy,
+                       const float* __restrict__ qz, long long qs, const int* __restrict__ perm,
+                       const int* __restrict__ chi, T* __restrict__ w) {
     const int lane = threadIdx.x & 63;
     while (true) {
         int it = 0;
