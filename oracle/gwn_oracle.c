@@ -738,10 +738,40 @@ void oracle_gradient(const float* V, int64_t nv, const int32_t* F, int64_t nf, c
 /* O3: unsigned distance to the soup (Ericson 2005, Sec. 5.1.5)               */
 /* ------------------------------------------------------------------------ */
 
+/* squared distance from p to the nearest of the three segments of a zero-area
+ * triangle (collinear or coincident corners): as a point set it is those
+ * segments, and the region tests below would divide 0 by 0 on a zero-length
+ * edge */
+static double or_point_segs_dist2(const double* p, const double* a, const double* b, const double* c)
+{
+    double best = 1e300;
+    const double* P[3] = {a, b, c};
+    for (int e = 0; e < 3; ++e) {
+        const double* u = P[e];
+        const double* w = P[(e + 1) % 3];
+        double d[3] = {w[0] - u[0], w[1] - u[1], w[2] - u[2]};
+        double up[3] = {p[0] - u[0], p[1] - u[1], p[2] - u[2]};
+        double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double t = dd > 0.0 ? (up[0] * d[0] + up[1] * d[1] + up[2] * d[2]) / dd : 0.0;
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+        double r[3] = {up[0] - t * d[0], up[1] - t * d[1], up[2] - t * d[2]};
+        double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (r2 < best) best = r2;
+    }
+    return best;
+}
+
 static double or_point_tri_dist2(const double* p, const double* a, const double* b, const double* c)
 {
     double ab[3], ac[3], ap[3], q[3];
     for (int i = 0; i < 3; ++i) { ab[i] = b[i] - a[i]; ac[i] = c[i] - a[i]; ap[i] = p[i] - a[i]; }
+    /* corners from float32 inputs: their differences and the products below are
+     * exact in double, so the cross product is zero exactly when the corners
+     * are collinear */
+    if (ab[1] * ac[2] - ab[2] * ac[1] == 0.0 && ab[2] * ac[0] - ab[0] * ac[2] == 0.0 &&
+        ab[0] * ac[1] - ab[1] * ac[0] == 0.0)
+        return or_point_segs_dist2(p, a, b, c);
 #define DOT(u, v) ((u)[0] * (v)[0] + (u)[1] * (v)[1] + (u)[2] * (v)[2])
     double d1 = DOT(ab, ap), d2 = DOT(ac, ap);
     if (d1 <= 0.0 && d2 <= 0.0) { for (int i = 0; i < 3; ++i) q[i] = a[i]; goto done; }
@@ -773,24 +803,7 @@ static double or_point_tri_dist2(const double* p, const double* a, const double*
             goto done;
         }
         double den = va + vb + vc;
-        if (den == 0.0) { /* degenerate triangle: nearest of its vertices/edges */
-            double best = 1e300;
-            const double* P[3] = {a, b, c};
-            for (int e = 0; e < 3; ++e) {
-                const double* u = P[e];
-                const double* w = P[(e + 1) % 3];
-                double d[3] = {w[0] - u[0], w[1] - u[1], w[2] - u[2]};
-                double up[3] = {p[0] - u[0], p[1] - u[1], p[2] - u[2]};
-                double dd = DOT(d, d);
-                double t = dd > 0.0 ? DOT(up, d) / dd : 0.0;
-                if (t < 0.0) t = 0.0;
-                if (t > 1.0) t = 1.0;
-                double r[3] = {up[0] - t * d[0], up[1] - t * d[1], up[2] - t * d[2]};
-                double r2 = DOT(r, r);
-                if (r2 < best) best = r2;
-            }
-            return best;
-        }
+        if (den == 0.0) return or_point_segs_dist2(p, a, b, c); /* degenerate after rounding */
         double v = vb / den, w = vc / den;
         for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i] * v + ac[i] * w;
     }

@@ -490,3 +490,25 @@ def test_weld_restores_the_indexed_boundary():
     V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [-0.0, 0, -0.0]], np.float32)
     Fz, n = O.weld(V, np.array([[0, 1, 2], [3, 2, 1]], np.int32))
     assert n == 3 and Fz[1].tolist() == [0, 2, 1]
+
+
+def test_distance_to_zero_area_triangles():
+    # A zero-area triangle is still part of the soup: as a point set it is its
+    # segments, so the distance is the distance to them (closed forms below).
+    # Two coincident corners (a needle), collinear distinct corners, and all
+    # three at one point; the closest-point region tests would divide 0 by 0 on
+    # the zero-length edge of the needle.
+    needle_V = np.array([[0, 0, 1], [0, 0, 1], [0, 0, 0]], np.float32)
+    line_V = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], np.float32)
+    point_V = np.array([[0.5, 0.5, 0.5]] * 3, np.float32)
+    F = np.array([[0, 1, 2]], np.int32)
+    cases = [
+        (needle_V, [[0, 0, 0], [0, 0, 0.5], [0, 0, 1], [1, 0, 0.5], [0, 0, -2], [0, 3, 0.5]], [0, 0, 0, 1, 2, 3]),
+        (line_V, [[1, 1, 0], [3, 0, 0], [-1, 0, 0], [0.5, 0, 0], [2, 0, 2]], [1, 1, 1, 0, 2]),
+        (point_V, [[0.5, 0.5, 0.5], [0.5, 0.5, 1.5], [1.5, 0.5, 0.5]], [0, 1, 1]),
+    ]
+    for V, Q, want in cases:
+        Q = np.array(Q, np.float32)
+        for bins in (True, False):
+            d = O.distance(V, F, Q, 10.0, use_bins=bins)
+            assert np.allclose(d, want, rtol=0, atol=1e-12), (V.tolist(), d.tolist(), want)
