@@ -15,8 +15,10 @@
 // its two edges; their divergent terms cancel in the sum but their values are
 // 0/0.  Such a query is summed again with the opposite axis (x0 = -z): the
 // gradient does not depend on the axis, and mirroring z maps that sum onto the
-// same code with r_z negated and the x, y components negated.  Grids share the
-// x/y quantities (N, grad N, the x/y dot) of a column among its samples.
+// same code with r_z negated and the x, y components negated.  A query with
+// boundary vertices both above and below it takes a third pass with a general
+// axis (grad_run_axis, in kernels of its own).  Grids share the x/y quantities (N, grad N, the x/y
+// dot) of a column among its samples.
 #include <algorithm>
 
 #include "gwn_kernels.h"
@@ -292,6 +294,82 @@ __device__ void grad_column_loops(const MeshView& mv, T pxs, T pys, const T* pzs
     }
 }
 
+// Third pass, for samples whose lines along +z and -z both meet a boundary
+// vertex (vertical stacks of boundary vertices), where both folded forms above
+// are 0/0: the edge term of Alg. 3 for a general axis x0 = u, x1 = -u, in FP64
+// on the same offsets.  u is fixed and in no special relation to the grid or
+// the coordinate axes, so a sample whose line along u also meets a vertex is
+// left as 0/0, as with the paper's random choice of axis.  Per edge, with
+// r0 = a - p, r1 = b - p, l = |r|, v = r / l:
+//     n = x1.(r0 x r1),   d = l0 l1 + l1 x1.r0 + l0 x1.r1 + r0.r1,
+//     grad n = -(r1 x x1 + x1 x r0),
+//     grad d = -(l1 (x1 + v1 + (1 + x1.v1) v0) + l0 (x1 + v0 + (1 + x1.v0) v1)),
+// and the term (d grad n - n grad d) / (n^2 + d^2) is the gradient of
+// atan2(n, d), as the folded forms sum it.
+__device__ __forceinline__ void grad_axis_x1(double* x1) {
+    const double a = 0.5381966011250105, b = 0.4142135623730950, c = 0.7320508075688772;
+    const double k = -1.0 / sqrt(a * a + b * b + c * c);
+    x1[0] = a * k;
+    x1[1] = b * k;
+    x1[2] = c * k;
+}
+
+__device__ __forceinline__ void cross3(const double* u, const double* v, double* w) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+__device__ __forceinline__ double dot3(const double* u, const double* v) {
+    return u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+}
+
+__device__ __forceinline__ void grad_axis_edge(const double* r0, const double* r1, const double* x1, double* g) {
+    const double l0 = sqrt(dot3(r0, r0)), l1 = sqrt(dot3(r1, r1));
+    double v0[3], v1[3], c[3], c1[3], c0[3];
+    for (int k = 0; k < 3; ++k) {
+        v0[k] = r0[k] / l0;
+        v1[k] = r1[k] / l1;
+    }
+    cross3(r0, r1, c);
+    const double n = dot3(x1, c);
+    const double d = l0 * l1 + l1 * dot3(x1, r0) + l0 * dot3(x1, r1) + dot3(r0, r1);
+    cross3(r1, x1, c1);
+    cross3(x1, r0, c0);
+    const double e1 = 1.0 + dot3(x1, v1), e0 = 1.0 + dot3(x1, v0);
+    const double inv = 1.0 / (n * n + d * d);
+    for (int k = 0; k < 3; ++k) {
+        const double gn = -(c1[k] + c0[k]);
+        const double gd = -(l1 * (x1[k] + v1[k] + e1 * v0[k]) + l0 * (x1[k] + v0[k] + e0 * v1[k]));
+        g[k] += (d * gn - n * gd) * inv;
+    }
+}
+
+// the third pass over boundary vertices [a, e) (edge j leads to the next vertex
+// of its loop) for ZB samples on one vertical line
+template <int ZB>
+__device__ void grad_run_axis(const MeshView& mv, int a, int e, double pxs, double pys, const double* pzs, double f,
+                              double (*G)[3]) {
+    double x1[3];
+    grad_axis_x1(x1);
+#pragma unroll
+    for (int r = 0; r < ZB; ++r) G[r][0] = G[r][1] = G[r][2] = 0.0;
+    const BVert* __restrict__ bv = mv.bverts;
+    for (int j = a; j < e; ++j) {
+        const int lp = min(max(bv[j].loop, 0), mv.nloops - 1);   // in range for any stored value
+        const int nx = j + 1 < mv.loop_off[lp + 1] ? j + 1 : mv.loop_off[lp];
+        const BVert A = bv[j], B = bv[nx];
+        const double ax = fma((double)A.x, f, -pxs), ay = fma((double)A.y, f, -pys);
+        const double bx = fma((double)B.x, f, -pxs), by = fma((double)B.y, f, -pys);
+#pragma unroll
+        for (int r = 0; r < ZB; ++r) {
+            const double r0[3] = {ax, ay, fma((double)A.z, f, -pzs[r])};
+            const double r1[3] = {bx, by, fma((double)B.z, f, -pzs[r])};
+            grad_axis_edge(r0, r1, x1, G[r]);
+        }
+    }
+}
+
 __device__ __forceinline__ bool finite3(const double* g) { return isfinite(g[0]) && isfinite(g[1]) && isfinite(g[2]); }
 
 template <class T>
@@ -459,6 +537,49 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grad_grid(MeshView mv, Grid
     }
 }
 
+// The third pass (grad_run_axis) as kernels of its own, so that the main
+// kernels keep their register budgets: every output with a component that is
+// not finite (both folded forms 0/0; also a query on the boundary itself, which
+// stays 0/0) is summed again with the general axis.  Arbitrary points:
+template <class T>
+__global__ __launch_bounds__(256) void k_grad_fix_points(MeshView mv, const float* __restrict__ qx,
+                                                         const float* __restrict__ qy, const float* __restrict__ qz,
+                                                         long long qs, long long nq, int axis, T* __restrict__ g) {
+    const long long i = blockIdx.x * 256ll + threadIdx.x;
+    if (i >= nq) return;
+    T* gi = g + 3 * i;
+    if (isfinite(gi[0]) && isfinite(gi[1]) && isfinite(gi[2])) return;
+    const float px = qx[i * qs], py = qy[i * qs], pz = qz[i * qs];
+    const FarScale<T> fs = far_scale<T>(px, py, fabsf(pz), mv.g.scale);
+    const double pzd = (double)((T)pz * fs.scf);
+    double G[1][3];
+    grad_run_axis<1>(mv, 0, mv.loop_off[mv.nloops], (double)((T)px * fs.scf), (double)((T)py * fs.scf), &pzd,
+                     (double)fs.f, G);
+    const double f = kInv2Pi * (double)fs.scf;
+    for (int c = 0; c < 3; ++c) gi[(c + axis) % 3] = (T)(G[0][c] * f);
+}
+
+// ... and grid samples, t = n0 + thread in the frame's order (z fastest)
+template <class T>
+__global__ __launch_bounds__(256) void k_grad_fix_grid(MeshView mv, GridArgs ga, long long n0, long long n, int axis,
+                                                       T* __restrict__ g) {
+    const long long t = n0 + blockIdx.x * 256ll + threadIdx.x;
+    if (t >= n) return;
+    const long long k = t % ga.nz, col = t / ga.nz;
+    const long long ci = col / ga.ny, cj = col - ci * ga.ny;
+    T* gi = g + 3 * (ci * ga.st[0] + cj * ga.st[1] + k * ga.st[2]);
+    if (isfinite(gi[0]) && isfinite(gi[1]) && isfinite(gi[2])) return;
+    const float px = grid_coord(ga.o[0], ga.s[0], ci), py = grid_coord(ga.o[1], ga.s[1], cj);
+    const float pz = grid_coord(ga.o[2], ga.s[2], k);
+    const FarScale<T> fs = far_scale<T>(px, py, fabsf(pz), mv.g.scale);
+    const double pzd = (double)((T)pz * fs.scf);
+    double G[1][3];
+    grad_run_axis<1>(mv, 0, mv.loop_off[mv.nloops], (double)((T)px * fs.scf), (double)((T)py * fs.scf), &pzd,
+                     (double)fs.f, G);
+    const double f = kInv2Pi * (double)fs.scf;
+    for (int c = 0; c < 3; ++c) gi[(c + axis) % 3] = (T)(G[0][c] * f);
+}
+
 template <class T, int ZB>
 gwn_status launch_grad_grid(const gwn_mesh_s* m, GridArgs ga, T* g, hipStream_t st) {
     ga.nchunks = (ga.nz + 64 * ZB - 1) / (64 * ZB);
@@ -468,6 +589,12 @@ gwn_status launch_grad_grid(const gwn_mesh_s* m, GridArgs ga, T* g, hipStream_t 
         ga.wave0 = w0;
         const long long blocks = (std::min(kMaxWaves, ga.nwaves - w0) + kGridWaves - 1) / kGridWaves;
         k_grad_grid<T, ZB><<<(unsigned)blocks, 64 * kGridWaves, 0, st>>>(m->view(), ga, m->axis, g);
+        GWN_HIP_TRY(hipGetLastError());
+    }
+    const long long ns = ga.nx * ga.ny * ga.nz, chunk = max_launch_queries();
+    for (long long n0 = 0; n0 < ns; n0 += chunk) {
+        const long long n = std::min(chunk, ns - n0);
+        k_grad_fix_grid<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(m->view(), ga, n0, n0 + n, m->axis, g);
         GWN_HIP_TRY(hipGetLastError());
     }
     return GWN_OK;
@@ -505,6 +632,11 @@ gwn_status query_gradient(const gwn_mesh_s* m, const float* qx, const float* qy,
         } else {
             k_grad_batch<float><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, m->axis, (float*)g + 3 * o);
         }
+        GWN_HIP_TRY(hipGetLastError());
+        if (prec == GWN_PREC_FP64)
+            k_grad_fix_points<double><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, m->axis, (double*)g + 3 * o);
+        else
+            k_grad_fix_points<float><<<blocks, 256, 0, st>>>(mv, x, y, z, qs, n, m->axis, (float*)g + 3 * o);
         GWN_HIP_TRY(hipGetLastError());
     }
     return GWN_OK;

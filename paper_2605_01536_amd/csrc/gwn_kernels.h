@@ -845,9 +845,14 @@ inline GridArgs frame_grid(int axis, const double* origin, const double* spacing
     return ga;
 }
 
-// grid coordinate origin + (i + 0.5) * spacing in FP64 without contraction
+// grid coordinate origin + (i + 0.5) * spacing in FP64, the product and the
+// sum each rounded (no fused multiply-add: the pragma keeps the compiler from
+// contracting them, which near a float32 rounding tie moves the sample by an
+// ulp), then rounded to float32
 __device__ __forceinline__ float grid_coord(double o, double s, long long i) {
-    return (float)__dadd_rn(o, __dmul_rn((double)i + 0.5, s));
+#pragma clang fp contract(off)
+    const double t = ((double)i + 0.5) * s;
+    return (float)(o + t);
 }
 
 // ---------------------------------------------------------------- chi, batch

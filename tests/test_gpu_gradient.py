@@ -25,17 +25,30 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
+# the general axis of the kernels' third pass (any axis gives the same gradient;
+# this one is in no special relation to the lattices of the tests)
+AXIS3 = (0.5381966011250105, 0.4142135623730950, 0.7320508075688772)
+
+
+def _reference(V, F, Q):
+    # a boundary vertex exactly on the +z ray makes the +z-axis terms 0/0: the
+    # kernel (and this reference) then take the opposite axis, and where that
+    # line meets a vertex too, a general one
+    ref, l1 = O.gradient(V, F, Q, with_l1=True)
+    for axis in ((0, 0, -1), AXIS3):
+        sing = ~(np.isfinite(ref).all(1) & np.isfinite(l1))
+        if not sing.any():
+            break
+        r2, l2 = O.gradient(V, F, Q[sing], axis=axis, with_l1=True)
+        ref[sing], l1[sing] = r2, l2
+    return ref, l1
+
+
 def _check(G, V, F, Q, prec, label, m=None):
     if m is None:
         m = G.Mesh(_dev(V), _dev(F))
     g = G.query_gradient(m, _dev(Q), prec=prec).cpu().numpy().astype(np.float64)
-    ref, l1 = O.gradient(V, F, Q, with_l1=True)
-    # a boundary vertex exactly on the +z ray makes the +z-axis terms 0/0: the
-    # kernel (and this reference) then take the opposite axis
-    sing = ~(np.isfinite(ref).all(1) & np.isfinite(l1))
-    if sing.any():
-        r2, l2 = O.gradient(V, F, Q[sing], axis=(0, 0, -1), with_l1=True)
-        ref[sing], l1[sing] = r2, l2
+    ref, l1 = _reference(V, F, Q)
     assert np.isfinite(ref).all()
     mask = off_surface_mask(V, F, Q)
     err = np.abs(g - ref).max(1)
@@ -185,3 +198,70 @@ def test_gradient_split_boundary(gwn, monkeypatch, prec):
     _, l1 = O.gradient(s.V, s.F, Q, with_l1=True)
     d = np.abs(g1 - g).max(1)
     assert (d[mask] <= 2 * REL[prec] * np.maximum(1.0, l1[mask])).all()
+
+
+def _stacked_disks():
+    # two fan disks of radius 1/2 at heights 0 and 0.6 (opposite orientations):
+    # their boundary loops both pass through (1/2, 0), so the vertical line
+    # there meets a boundary vertex above and one below every point between them
+    a = np.arange(12) * (2 * np.pi / 12)
+    ring = np.stack([0.5 * np.cos(a), 0.5 * np.sin(a), np.zeros(12)], 1)
+    ring[0] = [0.5, 0.0, 0.0]
+    V = np.concatenate([ring, [[0, 0, 0]], ring + [0, 0, 0.6], [[0, 0, 0.6]]]).astype(np.float32)
+    F1 = np.stack([np.arange(12), (np.arange(12) + 1) % 12, np.full(12, 12)], 1)
+    F2 = np.stack([(np.arange(12) + 1) % 12, np.arange(12), np.full(12, 12)], 1) + 13
+    return V, np.concatenate([F1, F2]).astype(np.int32)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_gradient_between_stacked_boundary_vertices(gwn, monkeypatch, prec):
+    # queries whose lines along +z and -z both meet a boundary vertex: the third
+    # pass with a general axis gives a finite gradient, equal to the oracle's
+    # (per-lane, workgroup-per-point and grid paths)
+    V, F = _stacked_disks()
+    z = np.array([-0.5, -0.01, 0.05, 0.3, 0.55, 0.61, 1.0], np.float32)
+    Q = np.stack([np.full_like(z, 0.5), np.zeros_like(z), z], 1).astype(np.float32)
+    ref, l1 = _reference(V, F, Q)
+    both = ~np.isfinite(O.gradient(V, F, Q[2:5], axis=(0, 0, -1))).all(1)
+    assert both.all()   # the three points between the disks are singular on both z axes
+    for split in ("0", "1"):
+        monkeypatch.setenv("GWN_SPLIT_BOUNDARY", split)
+        g = gwn.query_gradient(gwn.Mesh(_dev(V), _dev(F)), _dev(Q), prec=prec).cpu().numpy().astype(np.float64)
+        assert np.isfinite(g).all(), (split, g)
+        assert (np.abs(g - ref).max(1) <= REL[prec] * np.maximum(1.0, l1)).all(), (split, np.abs(g - ref).max(1))
+    monkeypatch.delenv("GWN_SPLIT_BOUNDARY")
+    # a grid whose first column is that line (x = 0.375 + 0.125, y = -0.125 + 0.125)
+    m = gwn.Mesh(_dev(V), _dev(F))
+    dims = (2, 2, 30)
+    gg = gwn.query_grid_gradient(m, (0.375, -0.125, -1.0), (0.25, 0.25, 0.1), dims, prec=prec)
+    gg = gg.cpu().numpy().astype(np.float64)
+    ii, jj, kk = np.meshgrid(*[np.arange(d) for d in dims], indexing="ij")
+    P = np.stack([0.375 + (ii + 0.5) * 0.25, -0.125 + (jj + 0.5) * 0.25, -1.0 + (kk + 0.5) * 0.1], -1)
+    P = P.reshape(-1, 3).astype(np.float32)
+    assert P[0, 0] == 0.5 and P[0, 1] == 0.0
+    ref, l1 = _reference(V, F, P)
+    mask = off_surface_mask(V, F, P)
+    assert np.isfinite(gg[mask]).all()
+    assert (np.abs(gg - ref).max(1)[mask] <= REL[prec] * np.maximum(1.0, l1[mask])).all()
+
+
+def test_grid_samples_at_the_documented_positions(gwn):
+    # sample k of a grid sits at float32(o + (k + 1/2) s), the product and the
+    # sum each rounded in FP64 (no fused multiply-add).  In this column the
+    # double value at k = 47 lies within rounding of a float32 tie, where a
+    # fused form moved the sample by one ulp and the FP64 gradient there by
+    # 2e-8; now the grid's FP64 gradient equals the per-point one at the
+    # documented positions
+    from tests.test_gpu_random_soups import _soup
+    V, F, _ = _soup(184)
+    m = gwn.Mesh(_dev(V), _dev(F))
+    lo = V.min(0).astype(np.float64) - 0.1
+    sp = (V.max(0).astype(np.float64) + 0.1 - lo) / np.array([5, 4, 70])
+    k = np.arange(70)
+    P = np.stack([np.full(70, lo[0] + 0.5 * sp[0]), np.full(70, lo[1] + 0.5 * sp[1]), lo[2] + (k + 0.5) * sp[2]], -1)
+    P = P.astype(np.float32)
+    gg = gwn.query_grid_gradient(m, tuple(lo), tuple(sp), (1, 1, 70), prec="fp64").cpu().numpy()
+    gp = gwn.query_gradient(m, _dev(P), prec="fp64").cpu().numpy()
+    _, l1 = O.gradient(V, F, P, with_l1=True)
+    assert np.abs(gg[47] - gp[47]).max() <= 1e-12 * max(1.0, l1[47])
+    assert (np.abs(gg - gp).max(1) <= 1e-12 * np.maximum(1.0, l1)).all()
