@@ -265,3 +265,30 @@ def test_grid_samples_at_the_documented_positions(gwn):
     _, l1 = O.gradient(V, F, P, with_l1=True)
     assert np.abs(gg[47] - gp[47]).max() <= 1e-12 * max(1.0, l1[47])
     assert (np.abs(gg - gp).max(1) <= 1e-12 * np.maximum(1.0, l1)).all()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_grid_gradient_third_pass_in_chunks(gwn, monkeypatch, prec):
+    # the grid gradient launched in pieces of 256 samples (main kernel and third
+    # pass) equals the one-launch result bit for bit; the column through the
+    # stacked vertices is the grid's last, so its samples lie in later pieces
+    V, F = _stacked_disks()
+    m = gwn.Mesh(_dev(V), _dev(F))
+    origin, spacing, dims = (0.125, -0.375, -1.0), (0.25, 0.25, 0.01), (2, 2, 300)
+    g1 = gwn.query_grid_gradient(m, origin, spacing, dims, prec=prec).clone()
+    monkeypatch.setenv("GWN_MAX_LAUNCH_QUERIES", "256")
+    g2 = gwn.query_grid_gradient(m, origin, spacing, dims, prec=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    g = g1.cpu().numpy().astype(np.float64)
+    ii, jj, kk = np.meshgrid(*[np.arange(d) for d in dims], indexing="ij")
+    P = np.stack([origin[0] + (ii + 0.5) * spacing[0], origin[1] + (jj + 0.5) * spacing[1],
+                  origin[2] + (kk + 0.5) * spacing[2]], -1).reshape(-1, 3).astype(np.float32)
+    assert (P[900:, 0] == 0.5).all() and (P[900:, 1] == 0.0).all()
+    ref, l1 = _reference(V, F, P)
+    mask = off_surface_mask(V, F, P)
+    up = ~np.isfinite(O.gradient(V, F, P[900:])).all(1)
+    down = ~np.isfinite(O.gradient(V, F, P[900:], axis=(0, 0, -1))).all(1)
+    assert (up & down & mask[900:]).sum() > 20   # samples between the disks, singular on both z axes
+    assert np.isfinite(g[mask]).all()
+    assert (np.abs(g - ref).max(1)[mask] <= REL[prec] * np.maximum(1.0, l1[mask])).all()
