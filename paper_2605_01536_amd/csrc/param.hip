@@ -379,7 +379,9 @@ struct BatchPts {
 };
 
 __device__ inline float cell_coord(double o, double s, long long i) {
-    return (float)__dadd_rn(o, __dmul_rn((double)i + 0.5, s));
+#pragma clang fp contract(off)   // the product and the sum rounded separately (no fused multiply-add)
+    const double t = ((double)i + 0.5) * s;
+    return (float)(o + t);
 }
 
 struct GridPts {
