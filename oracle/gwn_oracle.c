@@ -26,6 +26,11 @@
  *       the query, q_eps = q + (e1, e2, e3), 0 < e3 << e2 << e1
  *       (Supp. Sec. 2.1).  The boundary term is the literal Alg. 1
  *       expression on unit vectors, summed with Neumaier compensation.
+ *       Domain: its d = 1 + x1.a^ + x1.b^ + a^.b^ cancels in double when a
+ *       boundary vertex lies far above the query compared with its x/y
+ *       offset (relative offsets below ~1e-8, e.g. queries ~1e8 soup sizes
+ *       below the soup); there O1 is the reference.  The same holds for the
+ *       d of O4.
  *
  *   O4  oracle_gradient    grad w(p) = (1/4pi) sum_{(a,b) in dM} grad Area(a^, b^, x1)
  *       [Supp. Sec. 4, Alg. 3]: the integer part is locally constant, so
