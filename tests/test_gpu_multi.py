@@ -175,3 +175,33 @@ def test_multi_rejects_unknown_precision(gwn):
     st = L.gwn_multi_create(hs, 2, base, base + 4, base + 8, 3, o, 2, w.data_ptr(), None, None, None,
                             ctypes.byref(h))
     assert st == 1 and not h.value
+
+
+def test_multi_empty_meshes_and_queryless_meshes(gwn, monkeypatch):
+    # empty meshes, meshes without queries and meshes with one query in one
+    # plan, in both precisions, input or Morton order, tuned or not: every
+    # replay equal to the single-mesh calls bit for bit
+    from tests.test_gpu_random_soups import _soup
+    monkeypatch.setenv("GWN_SPLIT_BOUNDARY", "0")
+    rng = np.random.default_rng(5)
+    meshes, qs = [], []
+    for k in range(40):
+        if k % 7 == 3:
+            V, F = np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32)
+        else:
+            V, F, _ = _soup(1000 + k)
+        meshes.append(gwn.Mesh(torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()))
+        nq = 0 if k % 5 == 2 else (1 if k % 11 == 4 else int(rng.integers(1, 400)))
+        qs.append(rng.uniform(-1.2, 1.2, (nq, 3)).astype(np.float32))
+    offs = np.concatenate([[0], np.cumsum([q.shape[0] for q in qs])]).astype(np.int64)
+    Q = torch.from_numpy(np.concatenate(qs)).cuda()
+    for prec, order, iq, tune in (("fp32", 0, 0, False), ("fp32", 2, 64, False), ("fp64", 3, 128, False),
+                                  ("fp32", 0, 0, True)):
+        chi = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
+        plan = gwn.MultiPlan(meshes, Q, offs, chi_out=chi, prec=prec, order=order, item_queries=iq, autotune=tune)
+        w = plan.run().clone()
+        assert torch.equal(plan.run(), w)
+        for i, m in enumerate(meshes):
+            a, b = int(offs[i]), int(offs[i + 1])
+            wb, cb = gwn.query_batch(m, Q[a:b], prec=prec, want_chi=True)
+            assert torch.equal(wb, w[a:b]) and torch.equal(cb, chi[a:b]), (prec, order, i)
