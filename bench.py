@@ -94,7 +94,7 @@ NET_VALU_SLOTS = 512 * 11.5 + 32 * 12 + 256     # = 6,528 per point
 # fetches are the BVH, triangles and boundary vertices read by the 8 XCD L2s.
 # Measured on the kernel as it stands; re-take the counters after any change to
 # k_grid or the workload.
-K_GRID_TRAFFIC_BYTES = (231980.25 * 2.0 + 524288.0 * 1.0) * 1024
+K_GRID_TRAFFIC_BYTES = (231964.5 * 2.0 + 524288.0 * 1.0) * 1024
 FP64_OP_SLOTS, FP64_TRANS_SLOTS = 1.5, 5.4
 I_MIN_GRID_FP64 = (16 + 2 + 21 / 2) * FP64_OP_SLOTS + 2.5 * FP64_TRANS_SLOTS + 2   # = 58.25
 # Parametric path (FP64), per unit of work the kernel reports, counted from its

@@ -239,9 +239,10 @@ __device__ void grad_column_loops(const MeshView& mv, T pxs, T pys, const T* pzs
     bool asc = true;
     T prev = -(T)INFINITY;
 #pragma unroll
-    for (int r = 0; r < ZB; ++r) {
-        bminr[r] = fmin(wave_lane<T>(pzs[r], 0), wave_lane<T>(pzs[r], 63));
-        asc &= !(bminr[r] < prev);
+    for (int r = 0; r < ZB; ++r) {   // ascending blocks with non-falling minima, as for w (column_loops)
+        const T z0 = wave_lane<T>(pzs[r], 0), z63 = wave_lane<T>(pzs[r], 63);
+        bminr[r] = fmin(z0, z63);
+        asc &= !(bminr[r] < prev) & !(z63 < z0);
         prev = bminr[r];
     }
 #pragma unroll

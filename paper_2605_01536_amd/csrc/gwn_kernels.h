@@ -383,8 +383,9 @@ __device__ __forceinline__ void s_prefix(int R, const T* rz, T rho2, T* sv, bool
 // lanes >= ZB).  A vertex at or below every sample of a block (r_z <= 0 in all
 // its lanes) has s = l + |r_z| there with no reciprocal; fma(z, u, -bmin) > 0
 // in lane r is exactly "some lane of block r has r_z > 0" (r_z is the same fma
-// and falls as the sample's z rises).  When the blocks' smallest z ascend with
-// r (asc) the samples ascend through the whole column, so the blocks needing
+// and falls as the sample's z rises).  When every block ascends in the lane and
+// the blocks' smallest z do not fall with r (asc) the samples ascend through the
+// whole column, so the blocks needing
 // the reciprocal are a prefix, all but its last wholly below the vertex (their
 // largest z is at most the next block's smallest).
 template <class T>
@@ -706,14 +707,18 @@ __device__ __forceinline__ void column_loops(const MeshView& mv, int qqx, int qq
 #pragma unroll
     for (int r = 0; r < ZB; ++r) pz[r] = pzs[r] * u;
     // the samples of a block are monotone in the lane, so its smallest z is in
-    // lane 0 or lane 63
+    // lane 0 or lane 63.  The column ascends (asc) when every block ascends and
+    // the blocks' smallest z do not fall: the minima alone do not show it, as a
+    // descending column's last block and the blocks of clamped copies of its
+    // last sample after it share their smallest z.
     T bminr[ZB];
     bool asc = true;
     T prev = -(T)INFINITY;
 #pragma unroll
     for (int r = 0; r < ZB; ++r) {
-        bminr[r] = fmin(wave_lane<T>(pz[r], 0), wave_lane<T>(pz[r], 63));
-        asc &= !(bminr[r] < prev);
+        const T z0 = wave_lane<T>(pz[r], 0), z63 = wave_lane<T>(pz[r], 63);
+        bminr[r] = fmin(z0, z63);
+        asc &= !(bminr[r] < prev) & !(z63 < z0);
         prev = bminr[r];
     }
     for (int l = 0; l < mv.nloops; ++l) {

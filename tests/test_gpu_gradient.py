@@ -154,6 +154,29 @@ def test_grid_gradient_long_boundary_loops(gwn, prec):
     assert (err[mask] <= REL[prec] * np.maximum(1.0, l1[mask])).all(), float(err[mask].max())
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_grid_gradient_descending_axes(gwn, prec):
+    # negative spacing on each axis, with column lengths whose last chunk fills
+    # only its first block of 64 samples (the blocks after it hold clamped copies
+    # of the column's last sample): against the oracle and the per-point kernel
+    s = W.opened_spheres(seed=62, n_surf=3, tris_per_surf=300)
+    m = gwn.Mesh(_dev(s.V), _dev(s.F))
+    for nz in (7, 70, 130, 257):
+        for sx, sy, sz in ((0.31, 0.29, -1.0), (-0.31, 0.29, 1.0), (0.31, -0.29, -1.0)):
+            o = (-0.93 if sx > 0 else 0.93, -0.87 if sy > 0 else 0.87, -1.1 * sz)
+            g = W.GridSpec(origin=o, spacing=(sx, sy, 2.2 * sz / nz), dims=(6, 5, nz))
+            gg = gwn.query_grid_gradient(m, g.origin, g.spacing, g.dims, prec=prec)
+            P = W.grid_points(g)
+            gb = gwn.query_gradient(m, _dev(P), prec=prec)
+            ref, l1 = _reference(s.V, s.F, P)
+            mask = off_surface_mask(s.V, s.F, P)
+            bound = REL[prec] * np.maximum(1.0, l1[mask])
+            err = np.abs(gg.cpu().numpy().astype(np.float64) - ref).max(1)
+            assert (err[mask] <= bound).all(), (nz, sx, sy, sz, float(err[mask].max()))
+            d = (gg.double() - gb.double()).abs().max(1).values.cpu().numpy()
+            assert (d[mask] <= bound).all(), (nz, sx, sy, sz, float(d[mask].max()))
+
+
 def test_grid_gradient_columns_through_vertices(gwn):
     # columns through boundary vertices: the samples below a vertex take the
     # mirrored axis and stay finite

@@ -397,6 +397,27 @@ def test_grid_descending_and_flat_z(gwn, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("zb", ["", "1", "2", "4", "8"])
+def test_grid_descending_z_with_clamped_blocks(gwn, monkeypatch, prec, zb):
+    # negative z spacing with column lengths whose last chunk fills only its
+    # first block of 64 samples (the later blocks hold clamped copies of the
+    # column's last sample, with the same smallest z): the blocks' order must not
+    # be taken for ascending there; the chosen and each forced samples per lane
+    if zb:
+        monkeypatch.setenv("GWN_GRID_SAMPLES_PER_LANE", zb)
+    s = W.opened_spheres(seed=43, n_surf=3, tris_per_surf=400)
+    m = gwn.Mesh(_dev(s.V), _dev(s.F))
+    tol = TOL_FP32 if prec == "fp32" else TOL_FP64
+    for nz in (7, 70, 130, 150, 257, 520):
+        g = W.GridSpec(origin=(-0.93, -0.87, 1.1), spacing=(0.31, 0.29, -2.2 / nz), dims=(6, 5, nz))
+        w, chi = gwn.query_grid(m, g.origin, g.spacing, g.dims, prec=prec, want_chi=True)
+        P = W.grid_points(g)
+        compare(w.cpu().numpy(), chi.cpu().numpy(), s.V, s.F, P, tol, f"desc-nz{nz}-zb{zb}-{prec}")
+        wb, cb = gwn.query_batch(m, _dev(P), prec=prec, want_chi=True)
+        assert torch.equal(cb, chi)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_grid_columns_far_in_z(gwn, prec):
     # columns inside the box whose samples lie far above and below it: every
     # sample far (FP32 cell offsets overflow to infinity), and a column mixing
