@@ -75,21 +75,25 @@ I_MIN_BATCH = 14 + 2 * TRANS_SLOTS + 8 + (11 + TRANS_SLOTS) / 2      # = 35
 # edge l0 l1 (1), n (3), d (3), c0, c1 (2), grad D (6), n^2+d^2 (2), rcp, scale
 # (1), the three components (8), accumulate (3) = 29 + 1 trans
 I_MIN_GRAD = 10 + 29 + 4 * TRANS_SLOTS     # = 51
-# Dense bf16 MFMA peak of MI355X (no sparsity), for the surrogate network
+# Dense MFMA peak of MI355X (no sparsity), the same for bf16 (training) and
+# fp16 (inference) operands
 PEAK_BF16 = 2.5e15
-# The network's VALU work per point, which bounds it before the MFMA work does:
-# 512 GELU activations at 11.5 slots (the clamp, the square, 7 FMAs of the
-# polynomial, fma(zc, P, 1/2), the product, half a packed bf16 conversion; the
-# bias enters through the matrix product's accumulator), 32 frequencies of the
-# Fourier features at 12 (the argument, 3; its fractional part, 1; the hardware
-# sine and cosine, 3 each; two halves of a bf16 conversion, 1) and the 128-term
-# output dot product with bf16 widening (256)
-NET_VALU_SLOTS = 512 * 11.5 + 32 * 12 + 256     # = 6,528 per point
+PEAK_F16 = 2.5e15
+# The network's VALU work per point at inference, in lane slots (a packed half
+# instruction on two values is one slot, taken to issue at the FP32 rate): 512
+# GELU activations at 5 slots (10 packed half instructions per pair: the
+# conversion from the float32 accumulator, the clamp, 2t - 1, the square, 4 FMAs
+# of the polynomial, the 1/2 term, the product; the bias enters through the
+# matrix product's accumulator), 32 frequencies of the Fourier features at 12
+# (the argument, 3; its fractional part, 1; the hardware sine and cosine, 3
+# each; half a packed conversion per value, 1) and the 128-term output dot
+# product on mixed-precision FMAs (128)
+NET_VALU_SLOTS = 512 * 5 + 32 * 12 + 128     # = 3,072 per point
 # HBM bytes moved per k_grid<float, 8> launch on the default workload (512^3 grid,
 # 1.05M-triangle soup), from two rocprofv3 --pmc passes over this command:
-# FETCH_SIZE 231,971.81 KiB and WRITE_SIZE 524,288.0 KiB per dispatch, scaled by
+# FETCH_SIZE 231,964.50 KiB and WRITE_SIZE 524,288.0 KiB per dispatch, scaled by
 # what the same counters read for a plain 1 GiB device copy (bench.py
-# --copy-probe: FETCH_SIZE shows 524,308.2 KiB -> x2.000, WRITE_SIZE
+# --copy-probe: FETCH_SIZE shows 524,308.25 KiB -> x2.000, WRITE_SIZE
 # 1,048,576 KiB -> x1.000).  Writes are exactly the w output (134,217,728 x 4 B);
 # fetches are the BVH, triangles and boundary vertices read by the 8 XCD L2s.
 # Measured on the kernel as it stands; re-take the counters after any change to
@@ -738,10 +742,11 @@ def bench_surrogate(args):
                        f"train {n_train} generated points / infer {n} uniform points", "exact_ms": ex_ms,
            "exact_queries_per_s": n / (ex_ms / 1e3), "network_only_ms": nn_ms,
            "network_roofline": {"bound": "mfma", "unit": "TFLOP/s", "flop_per_query": 114944,
+                                "operands": "f16, f32 accumulation",
                                 "achieved": n * 114944 / (nn_ev / 1e3) / 1e12,
-                                "peak": PEAK_BF16 / 1e12,
-                                "frac": n * 114944 / (nn_ev / 1e3) / PEAK_BF16},
-           "network_valu_roofline": {"bound": "alu", "unit": "T FP32-VALU-slots/s",
+                                "peak": PEAK_F16 / 1e12,
+                                "frac": n * 114944 / (nn_ev / 1e3) / PEAK_F16},
+           "network_valu_roofline": {"bound": "alu", "unit": "T VALU-slots/s",
                                      "slots_per_query": NET_VALU_SLOTS,
                                      "achieved": n * NET_VALU_SLOTS / (nn_ev / 1e3) / 1e12,
                                      "peak": PEAK_SLOTS / 1e12,

@@ -415,8 +415,12 @@ gwn_status gwn_patches_destroy(gwn_patches h);
  *
  * Network: gamma(p) = [sin 2piGp, cos 2piGp] with G (32x3) ~ N(0, sigma^2)
  * fixed at creation; four GELU layers 64->128->128->128->128; linear output
- * 128->1.  Matrix products use bf16 MFMA with fp32 accumulation; Adam updates
- * fp32 master weights.  Parameters form one flat vector of GWN_MLP_NPARAMS
+ * 128->1.  Training's matrix products use bf16 MFMA with fp32 accumulation
+ * and the erf form of GELU; gwn_mlp_forward uses half-precision operands (the
+ * bf16 weights carried over exactly, activations rounded to half, fp32
+ * accumulation) and a polynomial GELU in packed half arithmetic (within
+ * 2.9e-3 |z|), or the training arithmetic when the environment variable
+ * GWN_INFER_GELU is "erf".  Adam updates fp32 master weights.  Parameters form one flat vector of GWN_MLP_NPARAMS
  * floats: W1 (64x128, row-major [in][out]), b1, W2, b2, W3, b3, W4, b4, W5
  * (128), b5.  Loss: mean squared error.  A handle (gwn_mlp, also called
  * gwn_surrogate) is bound to the device current at its creation.
@@ -428,7 +432,8 @@ gwn_status gwn_patches_destroy(gwn_patches h);
  *     HOST arrays (each nullable: theta and the Adam moments m, v of
  *     GWN_MLP_NPARAMS floats, G of 96 floats, the step counter; step < 0 keeps
  *     it).  They synchronise the device.
- *   gwn_mlp_forward: y_out[i] = network(q_i) for n device points.
+ *   gwn_mlp_forward: y_out[i] = network(q_i) for n device points (pre-
+ *     activations beyond the half range, |z| > 65504, overflow there).
  *   gwn_mlp_loss_grad: gradient of the loss over the n points with targets
  *     `target` into grad_out (device, nullable) and the loss (host, nullable).
  *   gwn_mlp_train_step: the same, then one Adam step (lr; beta1 0.9, beta2
@@ -509,7 +514,8 @@ gwn_status gwn_surrogate_train(gwn_surrogate h, gwn_mesh mesh, const gwn_surroga
  * version 2, sizes, Adam step count, passes done, sigma, the seeds, the data
  * recipe and the schedule of the run in progress, the labelling mesh's
  * triangle and boundary-edge counts), then G, the fp32 master weights, the
- * Adam moments m and v, the three bf16 copies the kernels read, and an FNV-1a
+ * Adam moments m and v, the three bf16 copies the kernels read (the half copy
+ * of inference is not stored: loading re-derives it), and an FNV-1a
  * 64-bit checksum of everything before it; little-endian.  Synchronises the
  * device.  GWN_E_INVALID if the file cannot be written.
  *

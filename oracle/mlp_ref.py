@@ -15,6 +15,10 @@ Parameters are one flat vector in this order: W1 (64x128, row-major
 [in][out]), b1, W2, b2, W3, b3, W4, b4, W5 (128), b5 -- 57,985 values.
 `bf16=True` rounds the weights and the input of every layer to bfloat16
 (round to nearest even), as the GPU kernels do before their matrix products.
+`half=True` takes the inference kernel's operands instead: the bf16 weights of
+the four hidden products carried into IEEE half precision (exact for |w| in
+[2^-14, 65504]), the output layer's weights in bf16, and the input of every
+layer rounded to half precision (round to nearest even).  GELU stays exact.
 """
 from __future__ import annotations
 
@@ -53,6 +57,11 @@ def round_bf16(a):
     return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
 
 
+def round_half(a):
+    """float -> IEEE half (round to nearest even, saturated at 65504) -> float64."""
+    return np.clip(np.asarray(a, np.float64), -65504.0, 65504.0).astype(np.float16).astype(np.float64)
+
+
 def features(P, G):
     z = 2.0 * math.pi * (np.asarray(P, np.float64) @ np.asarray(G, np.float64).T)
     return np.concatenate([np.sin(z), np.cos(z)], axis=1)
@@ -66,20 +75,25 @@ def gelu_grad(z):
     return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
 
 
-def forward(theta, G, P, bf16=False):
+def forward(theta, G, P, bf16=False, half=False):
     Ws, bs = unpack(theta)
-    r = round_bf16 if bf16 else (lambda a: np.asarray(a, np.float64))
+    if half:
+        r = round_half
+        rw = [lambda a: round_half(round_bf16(a))] * 4 + [round_bf16]
+    else:
+        r = round_bf16 if bf16 else (lambda a: np.asarray(a, np.float64))
+        rw = [r] * 5
     x = features(P, G)
     xs, zs = [], []
     for l in range(4):
         xi = r(x)
         xs.append(xi)
-        z = xi @ r(Ws[l]) + bs[l]
+        z = xi @ rw[l](Ws[l]) + bs[l]
         zs.append(z)
         x = gelu(z)
     xi = r(x)
     xs.append(xi)
-    y = xi @ r(Ws[4])[:, 0] + bs[4][0]
+    y = xi @ rw[4](Ws[4])[:, 0] + bs[4][0]
     return y, (xs, zs)
 
 

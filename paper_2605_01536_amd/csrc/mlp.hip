@@ -1,14 +1,16 @@
 // mlp.hip -- learned surrogate for far-field winding-number queries:
 // Fourier features gamma(p) = [sin 2piGp, cos 2piGp] (G: 32x3, fixed), four
 // GELU layers 64->128->128->128->128 and a linear output 128->1.  Every matrix
-// product runs on v_mfma_f32_32x32x16_bf16 (bf16 operands, fp32 accumulation)
-// in a transposed fragment layout where one layer's output registers are the
+// product of training runs on v_mfma_f32_32x32x16_bf16 (bf16 operands, fp32
+// accumulation) in a transposed fragment layout where one layer's output registers are the
 // next layer's operand: inference (k_infer) keeps the activations in
 // registers; training runs the forward and backward passes in one kernel
 // (k_tfb) and the weight gradients in another (k_twgrad).
-// Inference evaluates GELU by a minimax polynomial of Phi (gelu_fast, within
-// 5.3e-5 |z| of the erf form), training by the erf form (Abramowitz & Stegun
-// 7.1.26, 1.5e-7).  FP32 master weights are updated by Adam and re-packed into
+// Inference runs its products on v_mfma_f32_32x32x16_f16 with half-precision
+// activations and evaluates GELU by a minimax polynomial of Phi in packed half
+// arithmetic (gelu_half2, within 2.4e-3 |z| of the erf form); training uses the
+// erf form (Abramowitz & Stegun 7.1.26, 1.5e-7) on bf16 operands, which the
+// inference kernel keeps as an option (GWN_INFER_GELU=erf).  FP32 master weights are updated by Adam and re-packed into
 // the bf16 copies the kernels read.  The band query evaluates the network,
 // re-evaluates every point whose prediction lies within `band` of 1/2 with the
 // exact kernels, and scatters those results back.
@@ -19,6 +21,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "gwn_alloc.h"
@@ -26,6 +29,8 @@
 #include "gwn_mesh.h"
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
 namespace gwn {
 namespace mlp {
@@ -54,6 +59,7 @@ struct Dev {
     unsigned short* wf;
     unsigned short* wb;
     unsigned short* wi;
+    unsigned short* wh;   // the inference copy in half precision (same layout as wi)
 };
 
 struct Train {
@@ -73,6 +79,11 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
     return (unsigned short)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+// half-precision bits of a bf16 weight: exact for |w| in [2^-14, 65504] (8
+// significant bits into 11), rounded into the subnormals below, saturated above
+__device__ __forceinline__ unsigned short w2h(float w) {
+    return __builtin_bit_cast(unsigned short, (_Float16)fminf(fmaxf(w, -65504.0f), 65504.0f));
+}
 
 // splitmix64's output function (Steele, Lea and Flood 2014): a bijective 64-bit
 // mix.  Applied to a counter it is the splitmix64 generator; here it also
@@ -162,21 +173,30 @@ __device__ __forceinline__ float gelu(float z) {
     return z * phi;
 }
 
-// Inference GELU: Phi(z) - 1/2 = z P(z^2) for |z| <= 4, P of degree 7 fitted by
-// the Remez exchange for minimax absolute error (gen_gelu_poly.py 7 4), and z
-// clamped to +-4 beyond (Phi off by at most 1 - Phi(4) = 3.2e-5); in float32
-// |Phi error| <= 5.3e-5, i.e. |GELU error| <= 5.3e-5 |z|, far below the bf16
-// rounding of the activation it feeds (2^-9 relative).  11 VALU slots: clamp,
-// square, 7 FMAs, fma(zc, P, 1/2), the product with z.
-constexpr float kGeluP[] = {-1.5807866e-09f, 1.2171112e-07f, -4.100867e-06f, 8.06674e-05f, -0.0010482044f,
-                            0.0096648745f, -0.06617538f, 0.39884752f};
-__device__ __forceinline__ float gelu_fast(float z) {
-    const float zc = __builtin_amdgcn_fmed3f(z, -4.0f, 4.0f);
-    const float x = zc * zc;
-    float p = kGeluP[0];
+// Inference GELU in packed half precision, two activations per instruction:
+// t = z / (2c) + 1/2 clamped to [0, 1] (the FMA's output clamp), u = 2t - 1 =
+// clamp(z / c, -1, 1), Phi(z) - 1/2 = u Q(u^2), GELU = z (u Q(u^2) + 1/2).  Q of
+// degree 4 for c = 3.5 (kGeluHC), a minimax fit rounded to half-precision
+// coefficients one at a time with the rest re-fitted (gen_gelu_poly.py 4 3.5):
+// |Phi error| <= 1.2e-3 in exact arithmetic, 2.4e-3 as evaluated here, plus the
+// clamp's 2.3e-4 beyond c -- the size of the bf16 rounding of an activation
+// (2^-9 to 2^-8 relative).  10 VALU instructions per pair of activations (conversion,
+// clamp, 2t - 1, square, four FMAs, the 1/2 term, the product) against 11.5 per
+// activation for a degree-7 polynomial in float32.
+constexpr float kGeluHC = 3.5f;
+constexpr float kGeluH[] = {0.900390625f, -2.86328125f, 3.705078125f, -2.62890625f, 1.3876953125f};
+__device__ __forceinline__ h2 hsplat(float a) { return (h2){(_Float16)a, (_Float16)a}; }
+__device__ __forceinline__ h2 gelu_half2(float a, float b) {
+    const h2 z = (h2){(_Float16)a, (_Float16)b};   // one v_cvt_pk_f16_f32 (round to nearest even)
+    const h2 t = __builtin_elementwise_min(
+        __builtin_elementwise_max(__builtin_elementwise_fma(z, hsplat(0.5f / kGeluHC), hsplat(0.5f)), hsplat(0.0f)),
+        hsplat(1.0f));
+    const h2 u = __builtin_elementwise_fma(t, hsplat(2.0f), hsplat(-1.0f));
+    const h2 v = u * u;
+    h2 q = hsplat(kGeluH[0]);
 #pragma unroll
-    for (int i = 1; i < 8; ++i) p = fmaf(p, x, kGeluP[i]);
-    return z * fmaf(zc, p, 0.5f);
+    for (int i = 1; i < 5; ++i) q = __builtin_elementwise_fma(q, v, hsplat(kGeluH[i]));
+    return z * __builtin_elementwise_fma(u, q, hsplat(0.5f));
 }
 
 // Sum of the chunks' partial gradients of parameter p: four running sums
@@ -222,7 +242,8 @@ __device__ __forceinline__ void stage_lds(uint4* __restrict__ dst, const uint4* 
 // ---- inference: the activations never leave registers
 //
 // Each hidden layer is computed transposed, H_out^T = W^T H_in^T, with
-// v_mfma_f32_32x32x16_bf16: A = 32 output features x 16 input features of the
+// v_mfma_f32_32x32x16_f16 (or its bf16 twin, which has the same operand
+// layout): A = 32 output features x 16 input features of the
 // weights, B = 16 input features x 32 points of the activations, D = 32 output
 // features x 32 points.  Operand layout (wave64): lane l holds A[l%32][8(l/32)+i]
 // and B[8(l/32)+i][l%32] (i = 0..7); D[8j + 4(l/32) + i][l%32] lands in
@@ -270,13 +291,23 @@ __device__ __forceinline__ void sincos_rev(float t, float& s, float& c) {
     c = __builtin_amdgcn_cosf(f);
 }
 
+__device__ __forceinline__ v16f mfma32(const v8bf& a, const v8bf& b, const v16f& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v16f mfma32(const v8h& a, const v8h& b, const v16f& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
 // One layer for NT tiles of 32 points: X (NKB K-blocks) -> Y (8 K-blocks).
 // The output tiles are software-pipelined: the products of tile T are issued
 // before the activations of tile T - 1 are evaluated, so the matrix core works
 // while the vector unit evaluates GELU.
-template <int NKB, int NT, bool POLY>
-__device__ __forceinline__ void infer_layer(const v8bf* __restrict__ W, const float* __restrict__ bias, int lane,
-                                            int h, const v8bf (&X)[NT][8], v8bf (&Y)[NT][8]) {
+// V = v8h: half-precision operands and the packed half GELU; V = v8bf: bf16
+// operands and the erf form of GELU (the training kernels' arithmetic).
+template <int NKB, int NT, class V>
+__device__ __forceinline__ void infer_layer(const V* __restrict__ W, const float* __restrict__ bias, int lane, int h,
+                                            const V (&X)[NT][8], V (&Y)[NT][8]) {
+    constexpr bool HALF = __is_same(V, v8h);
     v16f acc[2][NT];
 #pragma unroll
     for (int T = 0; T <= 4; ++T) {
@@ -295,11 +326,9 @@ __device__ __forceinline__ void infer_layer(const v8bf* __restrict__ W, const fl
             }
 #pragma unroll
             for (int kb = 0; kb < NKB; ++kb) {
-                const v8bf A = W[(T * NKB + kb) * 64 + lane];
+                const V A = W[(T * NKB + kb) * 64 + lane];
 #pragma unroll
-                for (int p = 0; p < NT; ++p)
-                    acc[T & 1][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, X[p][kb], kb == 0 ? b : acc[T & 1][p],
-                                                                            0, 0, 0);
+                for (int p = 0; p < NT; ++p) acc[T & 1][p] = mfma32(A, X[p][kb], kb == 0 ? b : acc[T & 1][p]);
             }
         }
         if (T > 0) {
@@ -307,9 +336,15 @@ __device__ __forceinline__ void infer_layer(const v8bf* __restrict__ W, const fl
 #pragma unroll
             for (int p = 0; p < NT; ++p)
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const float z = acc[U & 1][p][e];
-                    Y[p][2 * U + (e >> 3)][e & 7] = (__bf16)(POLY ? gelu_fast(z) : gelu(z));
+                for (int e = 0; e < 16; e += 2) {
+                    if constexpr (HALF) {
+                        const h2 g = gelu_half2(acc[U & 1][p][e], acc[U & 1][p][e + 1]);
+                        Y[p][2 * U + (e >> 3)][e & 7] = g[0];
+                        Y[p][2 * U + (e >> 3)][(e & 7) + 1] = g[1];
+                    } else {
+                        Y[p][2 * U + (e >> 3)][e & 7] = (__bf16)gelu(acc[U & 1][p][e]);
+                        Y[p][2 * U + (e >> 3)][(e & 7) + 1] = (__bf16)gelu(acc[U & 1][p][e + 1]);
+                    }
                 }
         }
     }
@@ -317,18 +352,21 @@ __device__ __forceinline__ void infer_layer(const v8bf* __restrict__ W, const fl
 
 // NT tiles of 32 points per wave and step (each A fragment read from LDS
 // serves NT tiles), NW waves per workgroup sharing one copy of the weights in
-// LDS (one workgroup per CU).  POLY: the polynomial GELU (gelu_fast), else the
-// erf form of the training kernels.
+// LDS (one workgroup per CU).  POLY: half-precision operands (the wh copy of
+// the weights) and the packed half GELU (gelu_half2); else bf16 operands (wi)
+// and the erf form of the training kernels.
 template <int NT, int NW, bool POLY>
 __global__ __launch_bounds__(64 * NW) void k_infer(Dev P, const float* __restrict__ qx, const float* __restrict__ qy,
                                                    const float* __restrict__ qz, long long qs, long long n,
                                                    float* __restrict__ y) {
     constexpr int kPts = 32 * NT;   // points per wave per step
-    __shared__ v8bf sWi[kWi / 8];
+    using V = typename std::conditional<POLY, v8h, v8bf>::type;
+    using E = typename std::conditional<POLY, _Float16, __bf16>::type;
+    __shared__ V sWi[kWi / 8];
     __shared__ __attribute__((aligned(16))) float sB[4][128];
     __shared__ float sW4[128];
     __shared__ float sG[96];
-    stage_lds<64 * NW>((uint4*)sWi, (const uint4*)P.wi, kWi / 8);
+    stage_lds<64 * NW>((uint4*)sWi, (const uint4*)(POLY ? P.wh : P.wi), kWi / 8);
     for (int i = threadIdx.x; i < 128; i += 64 * NW) {
         sW4[i] = bf2f(P.wf[8192 + 3 * 16384 + i]);
         for (int l = 0; l < 4; ++l) sB[l][i] = P.master[kOffB[l] + i];
@@ -338,7 +376,7 @@ __global__ __launch_bounds__(64 * NW) void k_infer(Dev P, const float* __restric
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, ln = lane & 31, h = lane >> 5;
     for (long long step = (long long)blockIdx.x * NW + wave; step * kPts < n; step += (long long)gridDim.x * NW) {
-        v8bf X[NT][8], Y[NT][8];
+        V X[NT][8], Y[NT][8];
         long long pt[NT];
 #pragma unroll
         for (int p = 0; p < NT; ++p) {   // Fourier features: frequencies 16h..16h+15 of point ln of tile p
@@ -352,14 +390,14 @@ __global__ __launch_bounds__(64 * NW) void k_infer(Dev P, const float* __restric
                     const int f = 16 * h + 8 * b + i;
                     float sn, cs;
                     sincos_rev(fmaf(sG[3 * f], px, fmaf(sG[3 * f + 1], py, sG[3 * f + 2] * pz)), sn, cs);
-                    X[p][b][i] = (__bf16)sn;
-                    X[p][2 + b][i] = (__bf16)cs;
+                    X[p][b][i] = (E)sn;
+                    X[p][2 + b][i] = (E)cs;
                 }
         }
-        infer_layer<4, NT, POLY>(sWi, sB[0], lane, h, X, Y);
-        infer_layer<8, NT, POLY>(sWi + 8192 / 8, sB[1], lane, h, Y, X);
-        infer_layer<8, NT, POLY>(sWi + (8192 + 16384) / 8, sB[2], lane, h, X, Y);
-        infer_layer<8, NT, POLY>(sWi + (8192 + 2 * 16384) / 8, sB[3], lane, h, Y, X);
+        infer_layer<4, NT, V>(sWi, sB[0], lane, h, X, Y);
+        infer_layer<8, NT, V>(sWi + 8192 / 8, sB[1], lane, h, Y, X);
+        infer_layer<8, NT, V>(sWi + (8192 + 16384) / 8, sB[2], lane, h, X, Y);
+        infer_layer<8, NT, V>(sWi + (8192 + 2 * 16384) / 8, sB[3], lane, h, Y, X);
         // output layer: each lane's 64 activations, then the two lane halves of a point
 #pragma unroll
         for (int p = 0; p < NT; ++p) {
@@ -704,6 +742,7 @@ __device__ __forceinline__ void pack_one(const Dev& P, int p, float w) {
             P.wf[(l == 0 ? 0 : 8192 + (l - 1) * 16384) + o * kin + k] = b;
             if (l >= 1) P.wb[bwd_slot(l, k, o)] = b;
             P.wi[infer_slot(l, k, o)] = b;
+            P.wh[infer_slot(l, k, o)] = w2h(bf2f(b));
             return;
         }
     }
@@ -978,6 +1017,7 @@ gwn_status alloc_params(gwn_mlp_s* h) {
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.wf, sizeof(unsigned short) * kWf));
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.wb, sizeof(unsigned short) * kWb));
     GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.wi, sizeof(unsigned short) * kWi));
+    GWN_HIP_TRY(gwn::dmalloc((void**)&h->d.wh, sizeof(unsigned short) * kWi));
     return GWN_OK;
 }
 
@@ -1068,6 +1108,7 @@ void mlp_release(gwn_mlp_s* h) {
     (void)hipFree(h->d.wf);
     (void)hipFree(h->d.wb);
     (void)hipFree(h->d.wi);
+    (void)hipFree(h->d.wh);
     free_train(h);
     (void)hipFree(h->data_x);
     (void)hipFree(h->data_t);
@@ -1140,14 +1181,19 @@ gwn_status mlp_set_state(gwn_mlp_s* h, const float* theta, const float* m, const
 gwn_status mlp_forward(gwn_mlp_s* h, const float* qx, const float* qy, const float* qz, int64_t qs, int64_t n,
                        float* y, hipStream_t st) {
     if (n == 0) return GWN_OK;
-    constexpr long long pts = 32, nw = 8;   // k_infer<1, 8>: one tile of 32 points per wave, 8 waves
-    const long long steps = (n + pts - 1) / pts;
-    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((steps + nw - 1) / nw, 256));
-    // GWN_INFER_GELU=erf selects the erf form of GELU (the training kernels' form)
+    // half path: k_infer<2, 8>, two tiles of 32 points per wave (each weight
+    // fragment read from LDS serves both), 8 waves; erf path: one tile per wave
+    // (its 150 VGPRs leave no room for a second)
+    const long long nw = 8;
+    auto blocks = [&](long long pts) {
+        const long long steps = (n + pts - 1) / pts;
+        return (unsigned)std::max<long long>(1, std::min<long long>((steps + nw - 1) / nw, 256));
+    };
+    // GWN_INFER_GELU=erf selects the erf form of GELU on bf16 operands (the training kernels' arithmetic)
     bool poly = true;
     if (const char* e = std::getenv("GWN_INFER_GELU")) poly = std::string(e) != "erf";
-    if (poly) k_infer<1, 8, true><<<blocks, 64 * 8, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
-    else k_infer<1, 8, false><<<blocks, 64 * 8, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
+    if (poly) k_infer<2, 8, true><<<blocks(64), 64 * 8, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
+    else k_infer<1, 8, false><<<blocks(32), 64 * 8, 0, st>>>(h->d, qx, qy, qz, qs, n, y);
     GWN_HIP_TRY(hipGetLastError());
     return GWN_OK;
 }

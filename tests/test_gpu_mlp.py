@@ -35,25 +35,28 @@ def test_forward_matches_reference(gwn, n, monkeypatch):
 
 
 @pytest.mark.parametrize("n", [1, 1000, 100_000])
-def test_default_forward_with_polynomial_gelu(gwn, n, monkeypatch):
-    # the default inference GELU is a polynomial within 5.3e-5 |z| of the erf
-    # form (tests/test_gelu_poly.py): about 1 in 80 activations then rounds to a
-    # neighbouring bf16 value (one ulp, 2^-8 relative), a few per point, each
-    # moving the output by ~0.2 x 2^-8 of an activation.  Measured against the
-    # FP64 reference on 100k points: median 6.7e-4, p99 5.3e-3, max 1.4e-2 at an
-    # output scale of 0.47; the bars are about three times that.
+def test_default_forward_in_half_precision(gwn, n, monkeypatch):
+    # the default inference: half-precision operands and the packed half GELU,
+    # within 2.9e-3 |z| of the erf form (tests/test_gelu_poly.py), against the
+    # FP64 reference with the kernel's operands (half=True), so what remains is
+    # the GELU polynomial's error, whose small mean (1.5e-4 over z ~ N(0, 1))
+    # adds up over each layer's 128 inputs.  Measured on 100k points: median
+    # 1.3e-3, p99 5.8e-3, max 1.3e-2 at an output scale of 0.47 (against the
+    # unrounded network 2.1e-3 / 9.6e-3 / 1.8e-2; the bf16 erf form there:
+    # 2.3e-3 / 1.0e-2 / 2.6e-2); the bars are about three times that.
     monkeypatch.delenv("GWN_INFER_GELU", raising=False)
     s = _sur(gwn)
     st = s.state()
     P = _points(n, 20 + n)
     y = s.forward(torch.from_numpy(P).cuda()).cpu().numpy().astype(np.float64)
-    y_ref, _ = R.forward(st["theta"].astype(np.float64), st["G"].astype(np.float64), P, bf16=True)
+    y_ref, _ = R.forward(st["theta"].astype(np.float64), st["G"].astype(np.float64), P, half=True)
     err = np.abs(y - y_ref)
     print(f"n={n}: median {np.median(err):.3e} p99 {np.quantile(err, 0.99):.3e} max {err.max():.3e}, "
           f"median |y| {np.median(np.abs(y_ref)):.3e}")
-    assert np.median(err) < 1.5e-3 * (1 + np.median(np.abs(y_ref)))
-    assert np.quantile(err, 0.99) < 1e-2 * (1 + np.median(np.abs(y_ref)))
-    assert err.max() < 3e-2 * (1 + np.median(np.abs(y_ref)))
+    scale = 1 + np.median(np.abs(y_ref))
+    assert np.median(err) < 2.5e-3 * scale
+    assert np.quantile(err, 0.99) < 1.2e-2 * scale
+    assert err.max() < 3e-2 * scale
 
 
 def test_gradient_matches_reference(gwn):
@@ -250,5 +253,5 @@ def test_surrogate_on_empty_inputs(gwn):
     assert np.array_equal(s.state()["theta"], theta0)
     P = torch.from_numpy(_points(257, 15)).cuda()
     y = s.forward(P).cpu().numpy().astype(np.float64)
-    y_ref, _ = R.forward(theta0.astype(np.float64), s.state()["G"].astype(np.float64), _points(257, 15), bf16=True)
+    y_ref, _ = R.forward(theta0.astype(np.float64), s.state()["G"].astype(np.float64), _points(257, 15), half=True)
     assert np.abs(y - y_ref).max() < 3e-2 * (1 + np.median(np.abs(y_ref)))

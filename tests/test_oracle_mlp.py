@@ -42,6 +42,37 @@ def test_bf16_rounding():
     assert abs(r[4] - 3e-3) / 3e-3 < 2 ** -8
 
 
+def test_half_rounding():
+    x = np.array([1.0, 1.0 + 2 ** -11, 1.0 + 3 * 2 ** -12, 70000.0, -70000.0, 2.0 ** -20, 1e-9, 65504.0])
+    r = R.round_half(x)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                      # tie -> even
+    assert r[2] == 1.0 + 2 ** -10           # above the tie -> up
+    assert r[3] == 65504.0 and r[4] == -65504.0   # saturated, not infinite
+    assert r[5] == 2.0 ** -20               # a subnormal, exact
+    assert r[6] == 0.0                      # below half of the smallest subnormal (2^-25)
+    assert r[7] == 65504.0
+
+
+def test_half_operands_of_bf16_weights_are_exact():
+    # bf16 keeps 8 significant bits and half 11, so a bf16 weight in the half
+    # normal range converts exactly; the half forward then differs from the bf16
+    # forward only by the layer inputs' rounding (half: 2^-11 relative, bf16:
+    # 2^-8), so it lies closer to the unrounded network (both keep bf16 weights)
+    rng = np.random.default_rng(4)
+    w = R.round_bf16(rng.choice([-1, 1], 4000) * rng.uniform(1, 2, 4000) * 2.0 ** rng.integers(-14, 15, 4000))
+    assert np.array_equal(R.round_half(w), w)
+    theta = rng.normal(0, 0.1, R.N_PARAMS)
+    G = rng.normal(0, 1.0, (32, 3))
+    P = rng.uniform(-1, 1, (300, 3))
+    y, _ = R.forward(theta, G, P)
+    yh, (xs, _) = R.forward(theta, G, P, half=True)
+    yb, _ = R.forward(theta, G, P, bf16=True)
+    assert all(np.array_equal(R.round_half(x), x) for x in xs)
+    eh, eb = np.abs(yh - y).max(), np.abs(yb - y).max()
+    assert eh < eb, (eh, eb)
+
+
 @pytest.mark.parametrize("bf16", [False])
 def test_gradient_matches_central_differences(bf16):
     rng = np.random.default_rng(0)
