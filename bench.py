@@ -80,7 +80,9 @@ I_MIN_GRAD = 10 + 29 + 4 * TRANS_SLOTS     # = 51
 PEAK_BF16 = 2.5e15
 PEAK_F16 = 2.5e15
 # The network's VALU work per point at inference, in lane slots (a packed half
-# instruction on two values is one slot, taken to issue at the FP32 rate): 512
+# instruction on two values is one slot, counted at the 2-clock FP32 rate,
+# which it does not reach: rocprofv3 shows packed half instructions never
+# dual-issued, so each takes the unpaired ~4 clocks): 512
 # GELU activations at 5 slots (10 packed half instructions per pair: the
 # conversion from the float32 accumulator, the clamp, 2t - 1, the square, 4 FMAs
 # of the polynomial, the 1/2 term, the product; the bias enters through the

@@ -161,7 +161,7 @@ template <class T>
 struct GRing {
     GRec<T> v[kColRing + 1];
     GEdge<T> e[kColRing + 1];
-    int R[kColRing + 1];   // blocks of the column with a sample below the vertex (see BlockMin), plus 256
+    int R[kColRing + 1];   // blocks of the column with a sample below the vertex (see the sample blocks note in gwn_kernels.h), plus 256
                            // when the vertex is far (s_blocks)
 };
 

@@ -378,21 +378,16 @@ __device__ __forceinline__ void s_prefix(int R, const T* rz, T rho2, T* sv, bool
 #undef GWN_S_CASE
 }
 
-// Where the samples of a grid wave share a column, register r is a block of 64
-// consecutive samples and lane r of bmin holds the block's smallest z (+inf in
-// lanes >= ZB).  A vertex at or below every sample of a block (r_z <= 0 in all
-// its lanes) has s = l + |r_z| there with no reciprocal; fma(z, u, -bmin) > 0
-// in lane r is exactly "some lane of block r has r_z > 0" (r_z is the same fma
-// and falls as the sample's z rises).  When every block ascends in the lane and
-// the blocks' smallest z do not fall with r (asc) the samples ascend through the
-// whole column, so the blocks needing
-// the reciprocal are a prefix, all but its last wholly below the vertex (their
+// Sample blocks.  Where the samples of a grid wave share a column, register r
+// is a block of 64 consecutive samples and bminr[r] (the same in every lane)
+// holds the block's smallest z.  A vertex at or below every sample of a block
+// (r_z <= 0 in all its lanes) has s = l + |r_z| there with no reciprocal;
+// fma(z, u, -bminr[r]) > 0 is exactly "some lane of block r has r_z > 0" (r_z
+// is the same fma and falls as the sample's z rises).  When every block
+// ascends in the lane and the blocks' smallest z do not fall with r (asc) the
+// samples ascend through the whole column, so the blocks needing the
+// reciprocal are a prefix, all but its last wholly below the vertex (their
 // largest z is at most the next block's smallest).
-template <class T>
-struct BlockMin {
-    T bmin;
-    bool asc;
-};
 
 // pzs: the samples' z in offset units (cells times EdgePairs' kUnit inside the box)
 template <class T, int ZB, bool FAR>
@@ -484,7 +479,7 @@ __device__ __forceinline__ void boundary_loops(const MeshView& mv, int qqx, int 
 // time, one vertex per lane, into a ring of records in LDS that every lane then
 // reads at the same address (a broadcast): a wave instruction's worth of x/y
 // work per vertex becomes one lane's.  The same pass counts each vertex's
-// blocks with a sample below it (R, see BlockMin), and whether its outgoing
+// blocks with a sample below it (R, see the sample blocks note), and whether its outgoing
 // edge pairs on its x/y terms alone becomes a bit of a wave mask.
 template <class T>
 struct alignas(4 * sizeof(T)) ColRec {
@@ -507,13 +502,13 @@ template <class T>
 struct ColRing {
     ColRec<T> rec[kColRing + 1];
     ColAux<T> aux[kColRing + 1];
-    int R[kColRing + 1];   // block count R of the vertex, plus 256 in the FARV case (see BlockMin, s_blocks)
+    int R[kColRing + 1];   // block count R of the vertex, plus 256 in the FARV case (see the sample blocks note, s_blocks)
 };
 
 // Records of vertices v0 .. v0 + n - 1 (n <= 64) of the loop [b0, b1), into the
 // ring slots (v0 - b0) mod kColRing; v0 - b0 is a multiple of 64, so they fill
 // one half.  The first call of a loop (v0 == b0) also keeps its first vertex in
-// slot kColRing.  bminr[r]: block r's smallest z in offset units (see BlockMin).
+// slot kColRing.  bminr[r]: block r's smallest z in offset units (see the sample blocks note).
 // Bit k of mk: the edge leaving the half's slot k pairs on its x/y terms alone.
 template <class T, int ZB>
 __device__ __forceinline__ void col_fill(const MeshView& mv, int v0, int n, int b0, int b1, int qqx, int qqy,
