@@ -80,9 +80,11 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 // half-precision bits of a bf16 weight: exact for |w| in [2^-14, 65504] (8
-// significant bits into 11), rounded into the subnormals below, saturated above
+// significant bits into 11), rounded into the subnormals below, saturated above;
+// a NaN stays NaN (so a diverged network reads NaN on both inference paths)
 __device__ __forceinline__ unsigned short w2h(float w) {
-    return __builtin_bit_cast(unsigned short, (_Float16)fminf(fmaxf(w, -65504.0f), 65504.0f));
+    const float c = fabsf(w) > 65504.0f ? copysignf(65504.0f, w) : w;
+    return __builtin_bit_cast(unsigned short, (_Float16)c);
 }
 
 // splitmix64's output function (Steele, Lea and Flood 2014): a bijective 64-bit

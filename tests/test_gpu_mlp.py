@@ -231,6 +231,28 @@ def test_band_query_matches_network_and_exact_path(gwn):
     assert nf == Q.shape[0] and torch.equal(wf, exact)
 
 
+def test_nan_weight_reaches_the_output_on_both_inference_paths(gwn, monkeypatch):
+    # a NaN master weight (a diverged run) stays NaN in the bf16 and the half
+    # copies, so both inference paths return NaN rather than finite values;
+    # restoring the weights restores the outputs bit for bit
+    s = _sur(gwn, seed=11)
+    theta = s.state()["theta"].copy()
+    P = torch.from_numpy(_points(300, 31)).cuda()
+    y0 = s.forward(P).clone()
+    bad = theta.copy()
+    bad[R.offsets()[1][0] + 5 * 128 + 17] = np.nan      # W2[5][17]: hidden feature 17 of layer 2
+    s.load_state({"theta": bad})
+    for mode in (None, "erf"):
+        if mode:
+            monkeypatch.setenv("GWN_INFER_GELU", mode)
+        else:
+            monkeypatch.delenv("GWN_INFER_GELU", raising=False)
+        assert torch.isnan(s.forward(P)).all(), mode
+    monkeypatch.delenv("GWN_INFER_GELU", raising=False)
+    s.load_state({"theta": theta})
+    assert torch.equal(s.forward(P), y0)
+
+
 def test_surrogate_on_empty_inputs(gwn):
     # zero points: the forward pass and the band query are no-ops; training on an
     # empty batch is refused with an error and leaves the network as it was
