@@ -59,6 +59,34 @@ def test_default_forward_in_half_precision(gwn, n, monkeypatch):
     assert err.max() < 3e-2 * scale
 
 
+@pytest.mark.parametrize("seed,sigma", [(1, 0.5), (2, 1.0), (4, 3.0), (6, 6.0)])
+def test_half_forward_across_networks(gwn, seed, sigma, monkeypatch):
+    # the half-precision bars of the default forward test hold for other
+    # initial networks and Fourier scales (wider pre-activation ranges reach
+    # the polynomial's clamp), and after training steps move the weights
+    monkeypatch.delenv("GWN_INFER_GELU", raising=False)
+    s = _sur(gwn, seed=seed, sigma=sigma)
+    P = _points(20000, 50 + seed)
+    Pt = torch.from_numpy(P).cuda()
+    for stage in range(2):
+        st = s.state()
+        y = s.forward(Pt).cpu().numpy().astype(np.float64)
+        y_ref, (_, zs) = R.forward(st["theta"].astype(np.float64), st["G"].astype(np.float64), P, half=True)
+        err = np.abs(y - y_ref)
+        scale = 1 + np.median(np.abs(y_ref))
+        zmax = max(float(np.abs(z).max()) for z in zs)
+        print(f"seed {seed} sigma {sigma} stage {stage}: median {np.median(err):.3e} p99 "
+              f"{np.quantile(err, 0.99):.3e} max {err.max():.3e}, median |y| {np.median(np.abs(y_ref)):.3e}, "
+              f"max |z| {zmax:.2f}")
+        assert np.median(err) < 2.5e-3 * scale
+        assert np.quantile(err, 0.99) < 1.2e-2 * scale
+        assert err.max() < 3e-2 * scale
+        if stage == 0:   # a few Adam steps towards a smooth target
+            t = torch.from_numpy(np.sin(3 * P[:, 0]) * np.cos(2 * P[:, 1]) + P[:, 2]).float().cuda()
+            for _ in range(20):
+                s.train_step(Pt[:4096], t[:4096], 3e-3)
+
+
 def test_gradient_matches_reference(gwn):
     s = _sur(gwn, seed=5)
     st = s.state()
