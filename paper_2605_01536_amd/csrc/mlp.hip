@@ -180,11 +180,13 @@ __device__ __forceinline__ float gelu(float z) {
 // clamp(z / c, -1, 1), Phi(z) - 1/2 = u Q(u^2), GELU = z (u Q(u^2) + 1/2).  Q of
 // degree 4 for c = 3.5 (kGeluHC), a minimax fit rounded to half-precision
 // coefficients one at a time with the rest re-fitted (gen_gelu_poly.py 4 3.5):
-// |Phi error| <= 1.2e-3 in exact arithmetic, 2.4e-3 as evaluated here, plus the
-// clamp's 2.3e-4 beyond c -- the size of the bf16 rounding of an activation
-// (2^-9 to 2^-8 relative).  10 VALU instructions per pair of activations (conversion,
-// clamp, 2t - 1, square, four FMAs, the 1/2 term, the product) against 11.5 per
-// activation for a degree-7 polynomial in float32.
+// |Phi error| <= 1.2e-3 in exact arithmetic, 2.4e-3 as evaluated here, plus
+// the clamp's 2.3e-4 beyond c -- the size of the bf16 rounding of an
+// activation (2^-9 to 2^-8 relative).  10 VALU instructions per pair of
+// activations (conversion, clamp, 2t - 1, square, four FMAs, the 1/2 term, the
+// product) against 11.5 per activation for a degree-7 polynomial in float32.
+// NaN stays NaN (the product with z); pre-activations beyond the half range
+// (|z| > 65504) become infinite.
 constexpr float kGeluHC = 3.5f;
 constexpr float kGeluH[] = {0.900390625f, -2.86328125f, 3.705078125f, -2.62890625f, 1.3876953125f};
 __device__ __forceinline__ h2 hsplat(float a) { return (h2){(_Float16)a, (_Float16)a}; }
